@@ -1,0 +1,186 @@
+"""Oracle for the 1D well-balanced ALE-WENO hybrid scheme (ctypes wrapper).
+
+TEST INFRASTRUCTURE ONLY: a plain, slow, serial FP64 CPU implementation of
+the scheme of Zhang, Xia & Xu (arXiv 2208.06588) in ``alew_oracle.cpp``.
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import it.  It shares no code with the GPU library.
+
+Every function documents the passage of the paper it follows; the readings
+of ambiguous passages are listed at the top of ``alew_oracle.cpp``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "alew_oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+BC_PERIODIC, BC_TRANSMISSIVE, BC_REFLECTIVE = 0, 1, 2
+MESH_GIVEN, MESH_SINE, MESH_PAPER, MESH_FLUID = 0, 1, 2, 3
+ST_OK, ST_ARG, ST_MESH, ST_NEGDEPTH, ST_NONFINITE, ST_NEGWEIGHT = 0, 1, 2, 3, 4, 8
+FLAG_BETA_LOCAL, FLAG_BETA_FROM_H = 1, 2
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("g", C.c_double), ("cfl", C.c_double), ("weno_eps", C.c_double), ("pp_eps", C.c_double),
+        ("mesh_A", C.c_double), ("mesh_k", C.c_double), ("mesh_omega", C.c_double),
+        ("dry_eps", C.c_double),
+        ("bc", C.c_int32), ("mesh", C.c_int32), ("flags", C.c_int32), ("pad", C.c_int32),
+    ]
+
+
+class Stats(C.Structure):
+    _fields_ = [
+        ("steps", C.c_int64), ("n_class", C.c_int64 * 3), ("n_limited", C.c_int64),
+        ("n_negweight", C.c_int64),
+        ("t", C.c_double), ("dt_min", C.c_double), ("dt_max", C.c_double), ("h_min", C.c_double),
+        ("mass_eta0", C.c_double), ("mass_eta", C.c_double), ("mass_b0", C.c_double),
+        ("mass_b", C.c_double),
+        ("status", C.c_int32), ("pad", C.c_int32),
+    ]
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with g++ (no FMA contraction, IEEE division/sqrt)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(
+            ["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+             "-shared", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = C.CDLL(_LIB)
+        dp = C.POINTER(C.c_double)
+        u8p = C.POINTER(C.c_uint8)
+        L.orc_geometry.argtypes = [dp, dp, dp, dp, dp]
+        L.orc_reconstruct.argtypes = [dp, dp, dp, dp, dp, C.c_double, C.c_double, dp, dp, dp]
+        L.orc_limit.argtypes = [C.c_double, C.c_double, dp, C.c_double, dp]
+        L.orc_residual.argtypes = [C.POINTER(Params), C.c_int64, dp, dp, dp, dp, dp, dp, dp, u8p]
+        L.orc_mesh_velocity.argtypes = [C.POINTER(Params), C.c_int64, dp, dp, dp, dp, C.c_double,
+                                        C.c_double, dp]
+        L.orc_run.argtypes = [C.POINTER(Params), C.c_int64, dp, dp, dp, dp, dp, dp, C.c_double,
+                              C.c_double, C.c_int64, dp, dp, u8p, C.POINTER(Stats)]
+        L.orc_adjoint.argtypes = [C.POINTER(Params), C.c_int64, dp, dp, dp, dp, dp, C.c_double,
+                                  C.c_int64, dp, C.c_int64, dp, dp, dp, dp, dp, dp]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    if a is None:
+        return None
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _f64(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def params(g=9.812, cfl=0.6, weno_eps=1e-6, pp_eps=1e-11, bc=BC_PERIODIC, mesh=MESH_SINE,
+           mesh_A=0.05, mesh_k=1.0, mesh_omega=np.pi, flags=0, dry_eps=1e-8) -> Params:
+    """Scheme constants: g (Sec. 5), CFL, WENO epsilon (Sec. 2.2 Step 2),
+    positivity epsilon (eq. (3.20)), boundary type, mesh motion and the dry
+    tolerance of the trace velocity."""
+    return Params(g, cfl, weno_eps, pp_eps, mesh_A, mesh_k, mesh_omega, dry_eps, bc, mesh, flags,
+                  0)
+
+
+def geometry(widths5):
+    """Stencil polynomials and linear weights of one cell (Sec. 2.2, Step 1).
+
+    Returns (d[4,3], c[3,4,3], cd[3,4,3], a[3,3,3]) at the 4 Gauss-Lobatto
+    points s = 0, 1/2 -+ sqrt(5)/10, 1 of the cell."""
+    w = _f64(widths5)
+    d = np.zeros((4, 3)); c = np.zeros((3, 4, 3)); cd = np.zeros((3, 4, 3)); a = np.zeros((3, 3, 3))
+    lib().orc_geometry(_p(w), _p(d), _p(c), _p(cd), _p(a))
+    return d, c, cd, a
+
+
+def reconstruct(widths5, h5, m5, b5, dx, eps=1e-6, v5=None):
+    """Unlimited hybrid WENO values of one cell (Sec. 2.2 Steps 2-4, eq. (2.10)).
+
+    v5 is the first indicator variable (default eta = h + b).
+    Returns (vals[16] = h[4], hu[4], b[4], b_x[4]; cls; beta[3]; gamma)."""
+    h5, m5, b5 = _f64(h5), _f64(m5), _f64(b5)
+    v5 = h5 + b5 if v5 is None else _f64(v5)
+    out = np.zeros(16); beta = np.zeros(3); gam = np.zeros(1)
+    cls = lib().orc_reconstruct(_p(_f64(widths5)), _p(v5), _p(h5), _p(m5), _p(b5),
+                                float(dx), float(eps), _p(out), _p(beta), _p(gam))
+    return out, cls, beta, float(gam[0])
+
+
+def limit(hbar, mbar, traces6, pp_eps=1e-11):
+    """1D positivity limiter (eq. (3.20)-(3.21), Remark 4.1) on (hL,huL,bL,hR,huR,bR)."""
+    out = np.zeros(6)
+    r = lib().orc_limit(float(hbar), float(mbar), _p(_f64(traces6)), float(pp_eps), _p(out))
+    return out, r
+
+
+def residual(P: Params, eta, hu, b, J, w):
+    """Semi-discrete right-hand side (eq. (3.12), (3.17), (4.7)-(4.10)).
+
+    Returns (R[3,n] for (eta, hu, b), alpha, cls[n])."""
+    eta, hu, b, J, w = map(_f64, (eta, hu, b, J, w))
+    n = eta.size
+    R = np.zeros(3 * n); al = np.zeros(1); cls = np.zeros(n, np.uint8)
+    lib().orc_residual(C.byref(P), n, _p(eta), _p(hu), _p(b), _p(J), _p(w), _p(R), _p(al),
+                       cls.ctypes.data_as(C.POINTER(C.c_uint8)))
+    return R.reshape(3, n), float(al[0]), cls
+
+
+def mesh_velocity(P: Params, h, hu, b, xi, t, dt):
+    """Node speeds of the step [t, t+dt] for the prescribed or fluid mesh."""
+    h, hu, b, xi = map(_f64, (h, hu, b, xi))
+    w = np.zeros(h.size + 1)
+    lib().orc_mesh_velocity(C.byref(P), h.size, _p(h), _p(hu), _p(b), _p(xi), float(t), float(dt),
+                            _p(w))
+    return w
+
+
+def run(P: Params, h, hu, b, x, xi=None, w=None, t0=0.0, t_end=0.0, max_steps=0, dts=None,
+        record_cls=False):
+    """Time-march the scheme (eq. (3.14)-(3.15)) from t0 to t_end and/or for
+    max_steps steps.  Returns dict(h, hu, b, x, t, stats, status, cls)."""
+    h, hu, b, x = (_f64(a).copy() for a in (h, hu, b, x))
+    n = h.size
+    xi_a = None if xi is None else _f64(xi)
+    w_a = None if w is None else _f64(w)
+    dts_a = None if dts is None else _f64(dts)
+    nrec = max_steps if max_steps > 0 else 0
+    cls = np.zeros((nrec, 3, n), np.uint8) if (record_cls and nrec > 0) else None
+    S = Stats()
+    t = np.zeros(1)
+    st = lib().orc_run(C.byref(P), n, _p(h), _p(hu), _p(b), _p(x), _p(xi_a), _p(w_a), float(t0),
+                       float(t_end), int(max_steps), _p(dts_a), _p(t),
+                       None if cls is None else cls.ctypes.data_as(C.POINTER(C.c_uint8)),
+                       C.byref(S))
+    return dict(h=h, hu=hu, b=b, x=x, t=float(t[0]), stats=S, status=st, cls=cls)
+
+
+def adjoint(P: Params, h0, hu0, b0, x0, xi, dts, gauge_x, gauge_bar, t0=0.0):
+    """Exact discrete adjoint of the oracle run with frozen step sizes.
+
+    gauge_h[g] = hbar(T) of the cell containing gauge_x[g]; returns
+    (gauge_h, dh0, dhu0, db0) for the functional sum_g gauge_bar[g] gauge_h[g]."""
+    h0, hu0, b0, x0, xi, dts, gx, gb = map(_f64, (h0, hu0, b0, x0, xi, dts, gauge_x, gauge_bar))
+    n = h0.size
+    gh = np.zeros(gx.size); dh = np.zeros(n); dhu = np.zeros(n); db = np.zeros(n)
+    st = lib().orc_adjoint(C.byref(P), n, _p(h0), _p(hu0), _p(b0), _p(x0), _p(xi), float(t0),
+                           dts.size, _p(dts), gx.size, _p(gx), _p(gh), _p(gb), _p(dh), _p(dhu),
+                           _p(db))
+    return gh, dh, dhu, db, st

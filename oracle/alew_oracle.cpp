@@ -1,0 +1,910 @@
+/*
+ * Oracle for the 1D well-balanced ALE-WENO hybrid scheme with the special
+ * source-term treatment (Zhang, Xia & Xu, "Structure-preserving finite volume
+ * arbitrary Lagrangian-Eulerian WENO schemes for the shallow water equations").
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is a plain, slow, serial FP64 CPU version of
+ * the scheme.  Only the test-suite, the smoke check and the CPU-baseline leg of
+ * the benchmark load it, to check the GPU library against it.  It shares no
+ * code, header, table or constant generator with the GPU library.
+ *
+ * Style: every quantity is computed from its definition in the paper, in the
+ * paper's order.  Polynomials are obtained by solving the cell-average
+ * matching systems with Gaussian elimination, integrals by exact Gauss
+ * quadrature, and there is no fusion, blocking or reordering.  Built with
+ * -ffp-contract=off (no FMA contraction), IEEE division and sqrt.
+ *
+ * The forward scheme is written once as templates over the scalar type, so
+ * that the same code also runs on a reverse-mode tape scalar (AD below).
+ * That gives the exact discrete adjoint of this oracle, with every branch
+ * (detector class, limiter activity, argmin/argmax, |.| signs, dry cut-offs)
+ * taken from the forward values.
+ *
+ * Readings of points the paper leaves open (each also listed in the design doc):
+ *  R1  Dx in the smoothness indicators is the global max cell width of the
+ *      stage mesh (Sec. 2.2, Step 1 defines Dx^n as max_j Delta_j^n); flag
+ *      FLAG_BETA_LOCAL switches to the cell's own width.
+ *  R2  Class ties: smooth if gamma <= 1/2, non-smooth if gamma >= 1, else
+ *      transition (Sec. 2.2, Step 2; the printed intervals overlap).
+ *  R3  tau, gamma and the WENO-Z weights use the beta summed over the two
+ *      equations (eq. (2.10)), taken on the equilibrium variables (eta, hu)
+ *      of eq. (3.2); b is not an equation.  The polynomials themselves are
+ *      built on (h, hu) and b (Sec. 4.1).  This is the reading under which
+ *      the still-water test over the step bottom (Table 5.5) stays at
+ *      round-off; indicators on (h, hu) lose it near the step.  Flag
+ *      FLAG_BETA_FROM_H selects indicators on (h, hu).
+ *  R4  Well-balanced reconstruction is component-wise on (h, hu) and b with
+ *      shared weights (Sec. 4.1 items 1-2); no characteristic projection.
+ *  R5  Linear weights on non-uniform cells come from the two outermost
+ *      coefficients of the 5-cell quartic; a negative one is counted and
+ *      reported as an error (no splitting).
+ *  R6  Lax-Friedrichs alpha: per stage, global over all interfaces and both
+ *      limited traces (eq. (3.13): "taken globally").
+ *  R7  Time step: dt = CFL * min_j J_j / (max_j(|u_j| + sqrt(g h_j)) + max|W|),
+ *      W the node speed of the mesh at t_n; clipped to t_end.
+ *  R8  Prescribed mesh X(xi,t) = xi + A S(xi) sin(omega t): node velocity is
+ *      the chord (X(t_{n+1}) - X(t_n))/dt of eq. (2.1), evaluated with the
+ *      sum-to-product identity.  Periodic meshes use w_N = w_0.
+ *  R9  Stage widths follow the recurrence of eq. (3.15) (1D: div(w) J = dw_j).
+ *  R10 Limiter (eq. (3.20)-(3.21), 1D): delta from the Gauss-Lobatto mean
+ *      identity (eq. (A.3)), m = min(h^L, delta, h^R), active only when
+ *      m < eps_j; hu traces scaled by the same Phi about the mean; the bottom
+ *      traces follow Remark 4.1 (b = eta - h_new).
+ *  R11 Dry cut-off at traces: u = hu/h if h > dry_eps, else u = 0 and hu = 0.
+ *      The limiter only bounds trace depths below by eps = 1e-11; dividing
+ *      by depths that small makes the global alpha explode (Moses's second
+ *      problem reaches alpha ~ 3e3 against ~10 physical at its second step),
+ *      so the cut-off has its own tolerance (default 1e-8).  Setting u = 0
+ *      at a trace keeps |u - w| <= alpha there, which is all the positivity
+ *      argument of Appendix A uses.  A mean depth is reported negative only
+ *      below -eps: dry cells (h = 0) carry round-off of either sign because
+ *      h = eta - b is the difference of two separately updated means.
+ *  R12 Special source (eq. (4.8)-(4.10), 1D): B1, B2 from the limited bottom
+ *      traces; the interior integral uses the 4-point Gauss-Lobatto rule with
+ *      the unlimited hybrid values of eta = h + b and of d b/dx.
+ *  R13 Bottom evolves by the ALE scheme of eq. (3.17) (the paper's default).
+ *  R14 Ghost cells: 3 per side.  Periodic wraps; transmissive copies the
+ *      boundary cell (values and width); reflective mirrors with hu negated.
+ *  R15 The state carried through a run is (eta, hu, b); h = eta - b is
+ *      formed on entry and on exit of each library call.
+ */
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+#include <algorithm>
+
+namespace orc {
+
+/* ------------------------------------------------------------------------ */
+/* Reverse-mode tape scalar                                                  */
+/* ------------------------------------------------------------------------ */
+struct TapeNode { int64_t a, b; double da, db; };
+static std::vector<TapeNode>* g_tape = nullptr;
+
+struct AD {
+  double v;
+  int64_t i;  /* tape index, -1 = constant */
+  AD() : v(0.0), i(-1) {}
+  AD(double x) : v(x), i(-1) {}
+};
+
+static inline AD node(double v, int64_t a, double da, int64_t b, double db) {
+  AD r;
+  r.v = v;
+  if (a < 0 && b < 0) { r.i = -1; return r; }
+  r.i = (int64_t)g_tape->size();
+  g_tape->push_back({a, b, da, db});
+  return r;
+}
+static inline AD make_input(double v) {
+  AD r;
+  r.v = v;
+  r.i = (int64_t)g_tape->size();
+  g_tape->push_back({-1, -1, 0.0, 0.0});
+  return r;
+}
+static inline AD operator+(const AD& x, const AD& y) { return node(x.v + y.v, x.i, 1.0, y.i, 1.0); }
+static inline AD operator-(const AD& x, const AD& y) { return node(x.v - y.v, x.i, 1.0, y.i, -1.0); }
+static inline AD operator*(const AD& x, const AD& y) { return node(x.v * y.v, x.i, y.v, y.i, x.v); }
+static inline AD operator/(const AD& x, const AD& y) {
+  double q = x.v / y.v;
+  return node(q, x.i, 1.0 / y.v, y.i, -q / y.v);
+}
+static inline AD operator-(const AD& x) { return node(-x.v, x.i, -1.0, -1, 0.0); }
+static inline AD sqrt(const AD& x) {
+  double s = std::sqrt(x.v);
+  return node(s, x.i, s > 0.0 ? 0.5 / s : 0.0, -1, 0.0);
+}
+static inline AD fabs(const AD& x) {
+  double d = x.v > 0.0 ? 1.0 : (x.v < 0.0 ? -1.0 : 0.0);
+  return node(std::fabs(x.v), x.i, d, -1, 0.0);
+}
+static inline double val(double x) { return x; }
+static inline double val(const AD& x) { return x.v; }
+using std::sqrt;
+using std::fabs;
+
+/* ------------------------------------------------------------------------ */
+/* Parameters, statistics                                                    */
+/* ------------------------------------------------------------------------ */
+enum { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1, BC_REFLECTIVE = 2 };
+enum { MESH_GIVEN = 0, MESH_SINE = 1, MESH_PAPER = 2, MESH_FLUID = 3 };
+enum { ST_OK = 0, ST_ARG = 1, ST_MESH = 2, ST_NEGDEPTH = 3, ST_NONFINITE = 4, ST_NEGWEIGHT = 8 };
+
+enum { FLAG_BETA_LOCAL = 1, FLAG_BETA_FROM_H = 2 };
+
+struct Params {
+  double g, cfl, weno_eps, pp_eps;
+  double mesh_A, mesh_k, mesh_omega, dry_eps;
+  int32_t bc, mesh, flags, pad;
+};
+
+struct Stats {
+  int64_t steps;
+  int64_t n_class[3];
+  int64_t n_limited, n_negweight;
+  double t, dt_min, dt_max, h_min;
+  double mass_eta0, mass_eta, mass_b0, mass_b;
+  int32_t status, pad;
+};
+
+/* ------------------------------------------------------------------------ */
+/* Small dense linear algebra: Gaussian elimination with partial pivoting    */
+/* ------------------------------------------------------------------------ */
+/* Inverse of the n x n row-major matrix A into Ainv. */
+static void invert(int n, const double* A, double* Ainv) {
+  double M[5][10];
+  for (int r = 0; r < n; ++r) {
+    for (int c = 0; c < n; ++c) M[r][c] = A[r * n + c];
+    for (int c = 0; c < n; ++c) M[r][n + c] = (r == c) ? 1.0 : 0.0;
+  }
+  for (int k = 0; k < n; ++k) {
+    int p = k;
+    for (int r = k + 1; r < n; ++r)
+      if (std::fabs(M[r][k]) > std::fabs(M[p][k])) p = r;
+    if (p != k)
+      for (int c = 0; c < 2 * n; ++c) std::swap(M[k][c], M[p][c]);
+    double piv = M[k][k];
+    for (int c = 0; c < 2 * n; ++c) M[k][c] = M[k][c] / piv;
+    for (int r = 0; r < n; ++r) {
+      if (r == k) continue;
+      double f = M[r][k];
+      if (f == 0.0) continue;
+      for (int c = 0; c < 2 * n; ++c) M[r][c] = M[r][c] - f * M[k][c];
+    }
+  }
+  for (int r = 0; r < n; ++r)
+    for (int c = 0; c < n; ++c) Ainv[r * n + c] = M[r][n + c];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sec. 2.2, Step 1: stencil polynomials and linear weights on moving cells  */
+/* ------------------------------------------------------------------------ */
+/* Evaluation points in cell j, in the coordinate s = (x - x_{j-1/2}) / Delta_j:
+ * the 4-point Gauss-Lobatto nodes on [0,1] (Sec. 3.4.1 with k = 4 >= (5+2)/2). */
+static const double kS[4] = {0.0, 0.5 - 0.1 * 2.2360679774997896964,
+                             0.5 + 0.1 * 2.2360679774997896964, 1.0};
+/* Gauss-Lobatto weights (sum 1). */
+static const double kGLW[4] = {1.0 / 12.0, 5.0 / 12.0, 5.0 / 12.0, 1.0 / 12.0};
+
+struct CellGeo {
+  double J;            /* width of the cell                                    */
+  double a[3][3][3];   /* a[r][p][i]: coefficient of s^p in u_r, per average i  */
+  double c[3][4][3];   /* c[r][mu][i]: u_r(x_mu) = sum_i c[r][mu][i] ubar_{j-r+i} */
+  double cd[3][4][3];  /* same for d u_r/dx at x_mu                            */
+  double d[4][3];      /* linear weights d_r(x_mu)                              */
+};
+
+/* Mean over [a,b] of s^p. */
+static double mean_pow(double a, double b, int p) {
+  return (std::pow(b, p + 1) - std::pow(a, p + 1)) / ((p + 1) * (b - a));
+}
+
+/* wid[k] = width of cell j-2+k, k = 0..4. */
+static void cell_geometry(const double wid[5], CellGeo& G) {
+  const double Jj = wid[2];
+  G.J = Jj;
+  double E[6];
+  E[2] = 0.0;
+  E[3] = 1.0;
+  E[1] = -wid[1] / Jj;
+  E[0] = E[1] - wid[0] / Jj;
+  E[4] = 1.0 + wid[3] / Jj;
+  E[5] = E[4] + wid[4] / Jj;
+  /* Small stencils s_r(j) = {T_{j-r}, T_{j-r+1}, T_{j-r+2}}, r = 0,1,2:
+   * the quadratic whose averages over the three cells equal the data. */
+  for (int r = 0; r < 3; ++r) {
+    double M[9], Mi[9];
+    for (int i = 0; i < 3; ++i) {
+      int k = 2 - r + i; /* cell index 0..4 within the big stencil */
+      for (int p = 0; p < 3; ++p) M[i * 3 + p] = mean_pow(E[k], E[k + 1], p);
+    }
+    invert(3, M, Mi);
+    for (int p = 0; p < 3; ++p)
+      for (int i = 0; i < 3; ++i) G.a[r][p][i] = Mi[p * 3 + i];
+    for (int mu = 0; mu < 4; ++mu) {
+      double s = kS[mu];
+      for (int i = 0; i < 3; ++i) {
+        double v = 0.0, dv = 0.0;
+        for (int p = 0; p < 3; ++p) v = v + std::pow(s, p) * Mi[p * 3 + i];
+        for (int p = 1; p < 3; ++p) dv = dv + p * std::pow(s, p - 1) * Mi[p * 3 + i];
+        G.c[r][mu][i] = v;
+        G.cd[r][mu][i] = dv / Jj;
+      }
+    }
+  }
+  /* Big stencil S_j = {T_{j-2}, ..., T_{j+2}}: the quartic matching all five
+   * averages.  Linear weights with sum_r d_r u_r = quartic: cell j+2 appears
+   * only in u_0 (as its third average), cell j-2 only in u_2 (first average). */
+  double M5[25], M5i[25];
+  for (int k = 0; k < 5; ++k)
+    for (int p = 0; p < 5; ++p) M5[k * 5 + p] = mean_pow(E[k], E[k + 1], p);
+  invert(5, M5, M5i);
+  for (int mu = 0; mu < 4; ++mu) {
+    double s = kS[mu];
+    double Cm2 = 0.0, Cp2 = 0.0;
+    for (int p = 0; p < 5; ++p) {
+      Cm2 = Cm2 + std::pow(s, p) * M5i[p * 5 + 0];
+      Cp2 = Cp2 + std::pow(s, p) * M5i[p * 5 + 4];
+    }
+    double d0 = Cp2 / G.c[0][mu][2];
+    double d2 = Cm2 / G.c[2][mu][0];
+    G.d[mu][0] = d0;
+    G.d[mu][2] = d2;
+    G.d[mu][1] = 1.0 - d0 - d2;
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sec. 2.2, Steps 2-4 with eq. (2.10): hybrid WENO values in one cell       */
+/* ------------------------------------------------------------------------ */
+enum { CLS_S = 0, CLS_T = 1, CLS_N = 2 };
+
+template <class T>
+struct Recon {
+  T h[4], m[4], b[4]; /* hybrid values at the 4 Gauss-Lobatto points */
+  T bx[4];            /* hybrid value of d b / dx at the same points  */
+  int cls;
+  int negw;
+};
+
+/* 3-point Gauss-Legendre rule on [0,1] (exact to degree 5). */
+static const double kGLeg_s[3] = {0.5 - 0.5 * 0.77459666924148337704, 0.5,
+                                  0.5 + 0.5 * 0.77459666924148337704};
+static const double kGLeg_w[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
+
+/* Smoothness indicator of one stencil polynomial for one variable (Step 2):
+ * sum_{l=1,2} Dx^{2l-1} * integral over cell j of (d^l u_r / dx^l)^2. */
+template <class T>
+static T beta_one(const CellGeo& G, int r, const T v[3], double Dx) {
+  T a1 = 0.0, a2 = 0.0;
+  for (int i = 0; i < 3; ++i) {
+    a1 = a1 + G.a[r][1][i] * v[i];
+    a2 = a2 + G.a[r][2][i] * v[i];
+  }
+  const double J = G.J;
+  /* u_r(x) = a0 + a1 s + a2 s^2 with s = (x - x_{j-1/2})/J. */
+  T I1 = 0.0;
+  for (int q = 0; q < 3; ++q) {
+    T du = (a1 + 2.0 * a2 * kGLeg_s[q]) / J;
+    I1 = I1 + kGLeg_w[q] * J * (du * du);
+  }
+  T d2u = 2.0 * a2 / (J * J);
+  T I2 = J * (d2u * d2u);
+  return Dx * I1 + (Dx * Dx * Dx) * I2;
+}
+
+/* v[5]: the first indicator variable (eta by default, see R3). */
+template <class T>
+static void reconstruct(const CellGeo& G, double Dx, double eps, const T v[5], const T h[5],
+                        const T m[5], const T b[5], Recon<T>& o) {
+  /* Step 2: indicators summed over the two equations, detector. */
+  T beta[3];
+  for (int r = 0; r < 3; ++r) {
+    T vv[3] = {v[2 - r], v[3 - r], v[4 - r]};
+    T mv[3] = {m[2 - r], m[3 - r], m[4 - r]};
+    beta[r] = beta_one(G, r, vv, Dx) + beta_one(G, r, mv, Dx);
+  }
+  T tau = fabs(beta[0] - beta[2]);
+  T betaA = (beta[0] + beta[1] + beta[2]) / 3.0;
+  T gamma = tau / (betaA + eps);
+  int cls;
+  if (val(gamma) <= 0.5) cls = CLS_S;
+  else if (val(gamma) >= 1.0) cls = CLS_N;
+  else cls = CLS_T;
+  o.cls = cls;
+  o.negw = 0;
+  /* Steps 3-4 at each point. */
+  for (int mu = 0; mu < 4; ++mu) {
+    T phi[3];
+    for (int r = 0; r < 3; ++r)
+      if (G.d[mu][r] < 0.0) o.negw = 1;
+    if (cls == CLS_S) {
+      for (int r = 0; r < 3; ++r) phi[r] = G.d[mu][r];
+    } else {
+      T alpha[3];
+      for (int r = 0; r < 3; ++r) {
+        T q = tau / (beta[r] + eps);
+        alpha[r] = G.d[mu][r] * (1.0 + q * q);
+      }
+      T sum = alpha[0] + alpha[1] + alpha[2];
+      T phiN[3];
+      for (int r = 0; r < 3; ++r) phiN[r] = alpha[r] / sum;
+      if (cls == CLS_N) {
+        for (int r = 0; r < 3; ++r) phi[r] = phiN[r];
+      } else {
+        T M = 2.0 * gamma - 1.0;
+        for (int r = 0; r < 3; ++r) phi[r] = M * phiN[r] + (1.0 - M) * G.d[mu][r];
+      }
+    }
+    T vh = 0.0, vm = 0.0, vb = 0.0, vbx = 0.0;
+    for (int r = 0; r < 3; ++r) {
+      T ph = 0.0, pm = 0.0, pb = 0.0, pbx = 0.0;
+      for (int i = 0; i < 3; ++i) {
+        ph = ph + G.c[r][mu][i] * h[2 - r + i];
+        pm = pm + G.c[r][mu][i] * m[2 - r + i];
+        pb = pb + G.c[r][mu][i] * b[2 - r + i];
+        pbx = pbx + G.cd[r][mu][i] * b[2 - r + i];
+      }
+      vh = vh + phi[r] * ph;
+      vm = vm + phi[r] * pm;
+      vb = vb + phi[r] * pb;
+      vbx = vbx + phi[r] * pbx;
+    }
+    o.h[mu] = vh;
+    o.m[mu] = vm;
+    o.b[mu] = vb;
+    o.bx[mu] = vbx;
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sec. 3.4.2, eq. (3.20)-(3.21) in 1D, with Remark 4.1                      */
+/* ------------------------------------------------------------------------ */
+template <class T>
+struct Traces {
+  T hL, mL, bL, hR, mR, bR;
+};
+
+/* Returns 1 if the limiter modified the traces, 2 if hbar < 0. */
+template <class T>
+static int limit_cell(T hbar, T mbar, const Recon<T>& o, double pp_eps, Traces<T>& tr) {
+  tr.hL = o.h[0]; tr.mL = o.m[0]; tr.bL = o.b[0];
+  tr.hR = o.h[3]; tr.mR = o.m[3]; tr.bR = o.b[3];
+  const double s1 = kGLW[0];
+  if (val(hbar) <= 0.0) {
+    /* Phi = 0: the traces collapse onto the cell mean. */
+    T etaL = tr.hL + tr.bL, etaR = tr.hR + tr.bR;
+    tr.hL = hbar; tr.hR = hbar;
+    tr.mL = mbar; tr.mR = mbar;
+    tr.bL = etaL - tr.hL;
+    tr.bR = etaR - tr.hR;
+    return val(hbar) < 0.0 ? 2 : 1;
+  }
+  /* Interior mean delta from hbar = s1 hL + s1 hR + (1 - 2 s1) delta. */
+  T delta = (hbar - s1 * tr.hL - s1 * tr.hR) / (1.0 - 2.0 * s1);
+  T mn = tr.hL;
+  if (val(delta) < val(mn)) mn = delta;
+  if (val(tr.hR) < val(mn)) mn = tr.hR;
+  T epsj = (pp_eps < val(hbar)) ? T(pp_eps) : hbar;
+  if (!(val(mn) < val(epsj))) return 0;
+  T Phi = (hbar - epsj) / (hbar - mn);
+  if (val(Phi) > 1.0) Phi = 1.0;
+  T etaL = tr.hL + tr.bL, etaR = tr.hR + tr.bR;
+  tr.hL = Phi * (tr.hL - hbar) + hbar;
+  tr.hR = Phi * (tr.hR - hbar) + hbar;
+  tr.mL = Phi * (tr.mL - mbar) + mbar;
+  tr.mR = Phi * (tr.mR - mbar) + mbar;
+  tr.bL = etaL - tr.hL;
+  tr.bR = etaR - tr.hR;
+  return 1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Residual of the semi-discrete scheme (eq. (3.11)-(3.13), (3.17),          */
+/* (4.7)-(4.10)), 1D: RHS_j for (eta, hu, b)                                 */
+/* ------------------------------------------------------------------------ */
+struct Counters {
+  int64_t n_class[3];
+  int64_t n_limited, n_negweight;
+  int negdepth;
+};
+
+/* Source cell and hu sign of extended index k in [-3, n+2] (R14). */
+static void ghost_map(int bc, int n, int k, int& src, double& msign) {
+  msign = 1.0;
+  if (k >= 0 && k < n) { src = k; return; }
+  if (bc == BC_PERIODIC) {
+    src = ((k % n) + n) % n;
+  } else if (bc == BC_TRANSMISSIVE) {
+    src = k < 0 ? 0 : n - 1;
+  } else {
+    src = k < 0 ? -1 - k : 2 * n - 1 - k;
+    msign = -1.0;
+  }
+}
+
+template <class T>
+struct TraceFlux {
+  T h, m, b, eta, u;
+};
+
+template <class T>
+static TraceFlux<T> trace_state(T h, T m, T b, double dry_eps) {
+  TraceFlux<T> s;
+  s.h = h;
+  s.b = b;
+  s.eta = h + b;
+  if (val(h) > dry_eps) {
+    s.m = m;
+    s.u = m / h;
+  } else {
+    s.m = 0.0;
+    s.u = 0.0;
+  }
+  return s;
+}
+
+template <class T>
+static void residual(const Params& P, int n, const T* eta, const T* m, const T* b, const double* J,
+                     const double* w, T* R, double* alpha_out, uint8_t* cls, Counters& cnt) {
+  const int G = 3, NE = n + 2 * G;
+  std::vector<T> he(NE), me(NE), be(NE), etae(NE);
+  std::vector<double> Je(NE);
+  for (int k = -G; k < n + G; ++k) {
+    int src;
+    double ms;
+    ghost_map(P.bc, n, k, src, ms);
+    etae[k + G] = eta[src];
+    be[k + G] = b[src];
+    he[k + G] = eta[src] - b[src];
+    me[k + G] = ms * m[src];
+    Je[k + G] = J[src];
+  }
+  double Dx = 0.0;
+  for (int j = 0; j < n; ++j) Dx = std::max(Dx, J[j]);
+  /* Cells -1..n: reconstruction and limiter. */
+  const int NC = n + 2;
+  std::vector<Recon<T>> rec(NC);
+  std::vector<Traces<T>> tr(NC);
+  for (int j = -1; j <= n; ++j) {
+    double wid[5];
+    T vs[5], hs[5], ms5[5], bs[5];
+    for (int k = 0; k < 5; ++k) {
+      wid[k] = Je[j - 2 + k + G];
+      hs[k] = he[j - 2 + k + G];
+      ms5[k] = me[j - 2 + k + G];
+      bs[k] = be[j - 2 + k + G];
+      vs[k] = (P.flags & FLAG_BETA_FROM_H) ? hs[k] : etae[j - 2 + k + G];
+    }
+    CellGeo geo;
+    cell_geometry(wid, geo);
+    double dxr = (P.flags & FLAG_BETA_LOCAL) ? wid[2] : Dx;
+    reconstruct(geo, dxr, P.weno_eps, vs, hs, ms5, bs, rec[j + 1]);
+    int lim = limit_cell(he[j + G], me[j + G], rec[j + 1], P.pp_eps, tr[j + 1]);
+    if (j >= 0 && j < n) {
+      cnt.n_class[rec[j + 1].cls] += 1;
+      if (cls) cls[j] = (uint8_t)rec[j + 1].cls;
+      if (lim) cnt.n_limited += 1;
+      if (val(he[j + G]) < -P.pp_eps) cnt.negdepth = 1;
+    }
+    if (rec[j + 1].negw) cnt.n_negweight += 1;
+  }
+  /* Interface i (0..n) lies between cell i-1 (its right trace) and cell i
+   * (its left trace).  Global LF speed over all interfaces and both traces. */
+  std::vector<TraceFlux<T>> Lt(n + 1), Rt(n + 1);
+  T alpha = 0.0;
+  for (int i = 0; i <= n; ++i) {
+    const Traces<T>& a = tr[i];     /* cell i-1 */
+    const Traces<T>& c = tr[i + 1]; /* cell i   */
+    Lt[i] = trace_state(a.hR, a.mR, a.bR, P.dry_eps);
+    Rt[i] = trace_state(c.hL, c.mL, c.bL, P.dry_eps);
+    T hl = Lt[i].h, hr = Rt[i].h;
+    if (val(hl) < 0.0) hl = 0.0;
+    if (val(hr) < 0.0) hr = 0.0;
+    T sl = fabs(Lt[i].u - w[i]) + sqrt(P.g * hl);
+    T sr = fabs(Rt[i].u - w[i]) + sqrt(P.g * hr);
+    if (val(sl) > val(alpha)) alpha = sl;
+    if (val(sr) > val(alpha)) alpha = sr;
+  }
+  if (alpha_out) *alpha_out = val(alpha);
+  /* Numerical fluxes (eq. (3.13), (3.17)) and bottom averages (eq. (4.9)). */
+  std::vector<T> F1(n + 1), F2(n + 1), Gb(n + 1), B1(n + 1), B2(n + 1);
+  for (int i = 0; i <= n; ++i) {
+    const TraceFlux<T>& l = Lt[i];
+    const TraceFlux<T>& r = Rt[i];
+    const double wi = w[i];
+    T Hl1 = l.m - wi * l.eta;
+    T Hl2 = l.m * l.u + 0.5 * P.g * l.h * l.h - wi * l.m;
+    T Hr1 = r.m - wi * r.eta;
+    T Hr2 = r.m * r.u + 0.5 * P.g * r.h * r.h - wi * r.m;
+    F1[i] = 0.5 * (Hl1 + Hr1) - 0.5 * alpha * (r.eta - l.eta);
+    F2[i] = 0.5 * (Hl2 + Hr2) - 0.5 * alpha * (r.m - l.m);
+    Gb[i] = -0.5 * wi * (l.b + r.b) - 0.5 * alpha * (r.b - l.b);
+    B1[i] = 0.5 * (l.b + r.b);
+    B2[i] = 0.5 * (l.b * l.b + r.b * r.b);
+  }
+  /* Residuals with the special source (eq. (4.7)-(4.10)). */
+  for (int j = 0; j < n; ++j) {
+    const Recon<T>& o = rec[j + 1];
+    T etabar = eta[j];
+    T rint = 0.0;
+    for (int mu = 0; mu < 4; ++mu) {
+      T etamu = o.h[mu] + o.b[mu];
+      rint = rint + (kGLW[mu] * J[j]) * (P.g * (etamu - etabar) * o.bx[mu]);
+    }
+    T S = 0.5 * P.g * (B2[j + 1] - B2[j]) - P.g * etabar * (B1[j + 1] - B1[j]) - rint;
+    R[j] = -(F1[j + 1] - F1[j]);
+    R[n + j] = -(F2[j + 1] - F2[j]) + S;
+    R[2 * n + j] = -(Gb[j + 1] - Gb[j]);
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Mesh motion                                                               */
+/* ------------------------------------------------------------------------ */
+static double mesh_shape(const Params& P, double xi, double xmin, double xmax) {
+  if (P.mesh == MESH_SINE) return std::sin(2.0 * M_PI * P.mesh_k * xi);
+  /* eq. (5.1): (xi - xmax)(xi - xmin) / (3 (xmax - xmin)^2) */
+  double L = xmax - xmin;
+  return (xi - xmax) * (xi - xmin) / (3.0 * L * L);
+}
+
+/* Node speeds for the step [t, t+dt]. */
+template <class T>
+static void mesh_velocity(const Params& P, int n, const T* eta, const T* m, const T* b,
+                          const double* xi, const double* w_given, double t, double dt, double* w) {
+  if (P.mesh == MESH_GIVEN) {
+    for (int i = 0; i <= n; ++i) w[i] = w_given[i];
+  } else if (P.mesh == MESH_SINE || P.mesh == MESH_PAPER) {
+    /* Chord of X(xi,t) = xi + A S(xi) sin(omega t) over the step (eq. (2.1)):
+     * (sin(om(t+dt)) - sin(om t))/dt = 2 cos(om(t+dt/2)) sin(om dt/2)/dt. */
+    double om = P.mesh_omega;
+    double fac = 2.0 * std::cos(om * (t + 0.5 * dt)) * std::sin(0.5 * om * dt) / dt;
+    for (int i = 0; i <= n; ++i) w[i] = P.mesh_A * mesh_shape(P, xi[i], xi[0], xi[n]) * fac;
+  } else {
+    /* Fluid-following mesh: node average of the cell velocities, two passes
+     * of [1/4, 1/2, 1/4] smoothing, fixed boundary nodes (non-periodic). */
+    std::vector<double> u(n), v(n + 1), v2(n + 1);
+    for (int j = 0; j < n; ++j) {
+      double hb = val(eta[j]) - val(b[j]);
+      u[j] = hb > P.dry_eps ? val(m[j]) / hb : 0.0;
+    }
+    for (int i = 0; i <= n; ++i) {
+      if (P.bc == BC_PERIODIC) {
+        int l = (i - 1 + n) % n, r = i % n;
+        v[i] = 0.5 * (u[l] + u[r]);
+      } else {
+        v[i] = (i == 0 || i == n) ? 0.0 : 0.5 * (u[i - 1] + u[i]);
+      }
+    }
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int i = 0; i <= n; ++i) {
+        if (P.bc == BC_PERIODIC) {
+          int l = (i - 1 + n) % n, r = (i + 1) % n;
+          int c = i % n;
+          v2[i] = 0.25 * v[l] + 0.5 * v[c] + 0.25 * v[r];
+        } else {
+          v2[i] = (i == 0 || i == n) ? 0.0 : 0.25 * v[i - 1] + 0.5 * v[i] + 0.25 * v[i + 1];
+        }
+      }
+      v.swap(v2);
+    }
+    for (int i = 0; i <= n; ++i) w[i] = v[i];
+  }
+  if (P.bc == BC_PERIODIC) w[n] = w[0];
+}
+
+/* Largest node speed of the mesh at time t, for the time-step rule (R7). */
+template <class T>
+static double mesh_speed_bound(const Params& P, int n, const T* eta, const T* m, const T* b,
+                               const double* xi, const double* w_given, double t) {
+  double W = 0.0;
+  if (P.mesh == MESH_GIVEN) {
+    for (int i = 0; i <= n; ++i) W = std::max(W, std::fabs(w_given[i]));
+  } else if (P.mesh == MESH_SINE || P.mesh == MESH_PAPER) {
+    double Smax = 0.0;
+    for (int i = 0; i <= n; ++i) Smax = std::max(Smax, std::fabs(mesh_shape(P, xi[i], xi[0], xi[n])));
+    W = std::fabs(P.mesh_A * P.mesh_omega * std::cos(P.mesh_omega * t)) * Smax;
+  } else {
+    std::vector<double> wf(n + 1);
+    mesh_velocity(P, n, eta, m, b, xi, w_given, t, 1.0, wf.data());
+    for (int i = 0; i <= n; ++i) W = std::max(W, std::fabs(wf[i]));
+  }
+  return W;
+}
+
+/* ------------------------------------------------------------------------ */
+/* One time step: eq. (3.14)-(3.15) in 1D                                    */
+/* ------------------------------------------------------------------------ */
+template <class T>
+static double cfl_dt(const Params& P, int n, const T* eta, const T* m, const T* b, const double* x,
+                     const double* xi, const double* w_given, double t) {
+  double Jmin = INFINITY, smax = 0.0;
+  for (int j = 0; j < n; ++j) {
+    Jmin = std::min(Jmin, x[j + 1] - x[j]);
+    double hb = val(eta[j]) - val(b[j]);
+    double u = hb > P.dry_eps ? val(m[j]) / hb : 0.0;
+    double s = std::fabs(u) + std::sqrt(P.g * std::max(hb, 0.0));
+    smax = std::max(smax, s);
+  }
+  double W = mesh_speed_bound(P, n, eta, m, b, xi, w_given, t);
+  return P.cfl * Jmin / (smax + W);
+}
+
+template <class T>
+static int step(const Params& P, int n, T* eta, T* m, T* b, double* x, const double* xi,
+                const double* w_given, double* w_used, double& t, double dt, uint8_t* cls,
+                Counters& cnt) {
+  std::vector<double> J0(n), w(n + 1), dw(n);
+  for (int j = 0; j < n; ++j) {
+    J0[j] = x[j + 1] - x[j];
+    if (!(J0[j] > 0.0)) return ST_MESH;
+  }
+  mesh_velocity(P, n, eta, m, b, xi, w_given, t, dt, w.data());
+  for (int j = 0; j < n; ++j) dw[j] = w[j + 1] - w[j];
+  /* Base state Q^n = J^n q^n. */
+  std::vector<T> Qn(3 * n), q(3 * n), Rv(3 * n);
+  for (int j = 0; j < n; ++j) {
+    Qn[j] = J0[j] * eta[j];
+    Qn[n + j] = J0[j] * m[j];
+    Qn[2 * n + j] = J0[j] * b[j];
+    q[j] = eta[j];
+    q[n + j] = m[j];
+    q[2 * n + j] = b[j];
+  }
+  std::vector<double> Js = J0, Jn(n);
+  const double ca[3] = {0.0, 0.75, 1.0 / 3.0};
+  const double cb[3] = {1.0, 0.25, 2.0 / 3.0};
+  for (int s = 0; s < 3; ++s) {
+    for (int j = 0; j < n; ++j)
+      if (!(Js[j] > 0.0)) return ST_MESH;
+    double alpha;
+    residual(P, n, q.data(), q.data() + n, q.data() + 2 * n, Js.data(), w.data(), Rv.data(), &alpha,
+             cls ? cls + (size_t)s * n : nullptr, cnt);
+    for (int j = 0; j < n; ++j) Jn[j] = ca[s] * J0[j] + cb[s] * (Js[j] + dt * dw[j]);
+    for (int v = 0; v < 3; ++v)
+      for (int j = 0; j < n; ++j) {
+        T Q = ca[s] * Qn[v * n + j] + cb[s] * (Js[j] * q[v * n + j] + dt * Rv[v * n + j]);
+        q[v * n + j] = Q / Jn[j];
+      }
+    Js = Jn;
+  }
+  for (int j = 0; j < n; ++j) {
+    eta[j] = q[j];
+    m[j] = q[n + j];
+    b[j] = q[2 * n + j];
+  }
+  for (int i = 0; i <= n; ++i) x[i] = x[i] + dt * w[i];
+  if (w_used)
+    for (int i = 0; i <= n; ++i) w_used[i] = w[i];
+  t = t + dt;
+  int st = ST_OK;
+  if (cnt.negdepth) st = ST_NEGDEPTH;
+  for (int j = 0; j < n; ++j) {
+    if (!std::isfinite(val(eta[j])) || !std::isfinite(val(m[j])) || !std::isfinite(val(b[j])))
+      st = ST_NONFINITE;
+    if (val(eta[j]) - val(b[j]) < -P.pp_eps && st == ST_OK) st = ST_NEGDEPTH;
+  }
+  if (cnt.n_negweight && st == ST_OK) st = ST_NEGWEIGHT;
+  return st;
+}
+
+static void mass(int n, const double* eta, const double* b, const double* x, double& me, double& mb) {
+  me = 0.0;
+  mb = 0.0;
+  for (int j = 0; j < n; ++j) {
+    double J = x[j + 1] - x[j];
+    me = me + J * eta[j];
+    mb = mb + J * b[j];
+  }
+}
+
+}  // namespace orc
+
+/* ======================================================================== */
+/* C interface (ctypes)                                                      */
+/* ======================================================================== */
+using namespace orc;
+
+extern "C" {
+
+/* Geometry of one cell from the widths of cells j-2..j+2: d[4][3], c[3][4][3],
+ * cd[3][4][3], a[3][3][3]. */
+int orc_geometry(const double* wid5, double* d, double* c, double* cd, double* a) {
+  CellGeo G;
+  cell_geometry(wid5, G);
+  if (d) std::memcpy(d, G.d, sizeof(G.d));
+  if (c) std::memcpy(c, G.c, sizeof(G.c));
+  if (cd) std::memcpy(cd, G.cd, sizeof(G.cd));
+  if (a) std::memcpy(a, G.a, sizeof(G.a));
+  return 0;
+}
+
+/* Unlimited hybrid reconstruction of one cell.  v5 is the first indicator
+ * variable (eta, or h under FLAG_BETA_FROM_H).  out[16] = h[4], m[4], b[4],
+ * bx[4]; beta_out[3] (may be NULL); returns the class (0 S, 1 T, 2 N). */
+int orc_reconstruct(const double* wid5, const double* v5, const double* h5, const double* m5,
+                    const double* b5, double Dx, double eps, double* out, double* beta_out,
+                    double* gamma_out) {
+  CellGeo G;
+  cell_geometry(wid5, G);
+  Recon<double> o;
+  reconstruct(G, Dx, eps, v5, h5, m5, b5, o);
+  for (int mu = 0; mu < 4; ++mu) {
+    out[mu] = o.h[mu];
+    out[4 + mu] = o.m[mu];
+    out[8 + mu] = o.b[mu];
+    out[12 + mu] = o.bx[mu];
+  }
+  if (beta_out || gamma_out) {
+    double beta[3];
+    for (int r = 0; r < 3; ++r) {
+      double hv[3] = {v5[2 - r], v5[3 - r], v5[4 - r]};
+      double mv[3] = {m5[2 - r], m5[3 - r], m5[4 - r]};
+      beta[r] = beta_one(G, r, hv, Dx) + beta_one(G, r, mv, Dx);
+      if (beta_out) beta_out[r] = beta[r];
+    }
+    if (gamma_out) {
+      double tau = std::fabs(beta[0] - beta[2]);
+      *gamma_out = tau / ((beta[0] + beta[1] + beta[2]) / 3.0 + eps);
+    }
+  }
+  return o.cls;
+}
+
+/* Positivity limiter on given traces.  in[6] = hL, mL, bL, hR, mR, bR;
+ * out[6] same order.  Returns 0 untouched, 1 limited, 2 negative mean. */
+int orc_limit(double hbar, double mbar, const double* in, double pp_eps, double* out) {
+  Recon<double> o;
+  for (int mu = 0; mu < 4; ++mu) { o.h[mu] = 0; o.m[mu] = 0; o.b[mu] = 0; o.bx[mu] = 0; }
+  o.h[0] = in[0]; o.m[0] = in[1]; o.b[0] = in[2];
+  o.h[3] = in[3]; o.m[3] = in[4]; o.b[3] = in[5];
+  Traces<double> tr;
+  int r = limit_cell(hbar, mbar, o, pp_eps, tr);
+  out[0] = tr.hL; out[1] = tr.mL; out[2] = tr.bL;
+  out[3] = tr.hR; out[4] = tr.mR; out[5] = tr.bR;
+  return r;
+}
+
+/* Residual RHS_j (3n: eta, hu, b) of the state (eta, hu, b) on widths J and
+ * node speeds w.  Returns the LF speed in *alpha. */
+int orc_residual(const Params* P, int64_t n, const double* eta, const double* m, const double* b,
+                 const double* J, const double* w, double* R, double* alpha, uint8_t* cls) {
+  Counters cnt{};
+  residual(*P, (int)n, eta, m, b, J, w, R, alpha, cls, cnt);
+  return 0;
+}
+
+/* Node speed used by a step [t, t+dt] (mesh modes other than GIVEN). */
+int orc_mesh_velocity(const Params* P, int64_t n, const double* h, const double* hu, const double* b,
+                      const double* xi, double t, double dt, double* w) {
+  std::vector<double> eta(n);
+  for (int64_t j = 0; j < n; ++j) eta[j] = h[j] + b[j];
+  mesh_velocity(*P, (int)n, eta.data(), hu, b, xi, (const double*)nullptr, t, dt, w);
+  return 0;
+}
+
+static void stats_init(Stats* S) {
+  if (!S) return;
+  std::memset(S, 0, sizeof(Stats));
+  S->dt_min = INFINITY;
+  S->dt_max = 0.0;
+  S->h_min = INFINITY;
+}
+
+/* Run from t0 until t_end (if t_end > t0) or for max_steps steps (if > 0).
+ * If dts != NULL it gives the step sizes (frozen); otherwise the CFL rule.
+ * h, hu, b [n] and x [n+1] are updated in place; t_out receives the time.
+ * w_given [n+1] is the node speed for MESH_GIVEN.  cls (optional) receives
+ * the class of every cell, stage and step: [max_steps][3][n]. */
+int orc_run(const Params* P, int64_t n_, double* h, double* hu, double* b, double* x,
+            const double* xi, const double* w_given, double t0, double t_end, int64_t max_steps,
+            const double* dts, double* t_out, uint8_t* cls, Stats* S) {
+  const int n = (int)n_;
+  if (n < 5 || !P || !h || !hu || !b || !x) return ST_ARG;
+  if (P->mesh != MESH_GIVEN && !xi) return ST_ARG;
+  if (P->mesh == MESH_GIVEN && !w_given) return ST_ARG;
+  stats_init(S);
+  std::vector<double> eta(n);
+  for (int j = 0; j < n; ++j) eta[j] = h[j] + b[j];
+  double t = t0;
+  if (S) {
+    mass(n, eta.data(), b, x, S->mass_eta0, S->mass_b0);
+    for (int j = 0; j < n; ++j) S->h_min = std::min(S->h_min, h[j]);
+  }
+  int st = ST_OK;
+  int64_t k = 0;
+  const bool timed = t_end > t0;
+  while (true) {
+    if (max_steps > 0 && k >= max_steps) break;
+    if (timed && !(t < t_end)) break;
+    if (!timed && max_steps <= 0) break;
+    double dt;
+    if (dts) dt = dts[k];
+    else dt = cfl_dt(*P, n, eta.data(), hu, b, x, xi, w_given, t);
+    if (timed && t + dt > t_end) dt = t_end - t;
+    Counters cnt{};
+    st = step(*P, n, eta.data(), hu, b, x, xi, w_given, (double*)nullptr, t, dt,
+              cls ? cls + (size_t)k * 3 * n : nullptr, cnt);
+    if (S) {
+      S->steps += 1;
+      for (int c = 0; c < 3; ++c) S->n_class[c] += cnt.n_class[c];
+      S->n_limited += cnt.n_limited;
+      S->n_negweight += cnt.n_negweight;
+      S->dt_min = std::min(S->dt_min, dt);
+      S->dt_max = std::max(S->dt_max, dt);
+      for (int j = 0; j < n; ++j) S->h_min = std::min(S->h_min, eta[j] - b[j]);
+    }
+    ++k;
+    if (st != ST_OK && st != ST_NEGWEIGHT) break;
+  }
+  for (int j = 0; j < n; ++j) h[j] = eta[j] - b[j];
+  if (t_out) *t_out = t;
+  if (S) {
+    S->t = t;
+    mass(n, eta.data(), b, x, S->mass_eta, S->mass_b);
+    S->status = st;
+  }
+  return st;
+}
+
+/* Discrete adjoint of a run with frozen step sizes dts[nsteps] (prescribed
+ * mesh): gauge_h[g] = hbar of the cell containing gauge_x[g] at the final
+ * time; returns d/d(h0, hu0, b0) of sum_g gauge_bar[g] * gauge_h[g]. */
+int orc_adjoint(const Params* P, int64_t n_, const double* h0, const double* hu0, const double* b0,
+                const double* x0, const double* xi, double t0, int64_t nsteps, const double* dts,
+                int64_t ngauge, const double* gauge_x, double* gauge_h, const double* gauge_bar,
+                double* dh0, double* dhu0, double* db0) {
+  const int n = (int)n_;
+  if (n < 5 || P->mesh == MESH_FLUID || P->mesh == MESH_GIVEN) return ST_ARG;
+  std::vector<TapeNode> tape;
+  tape.reserve(1 << 20);
+  g_tape = &tape;
+  std::vector<AD> eta(n), m(n), b(n), hin(n), muin(n), bin(n);
+  for (int j = 0; j < n; ++j) {
+    hin[j] = make_input(h0[j]);
+    muin[j] = make_input(hu0[j]);
+    bin[j] = make_input(b0[j]);
+  }
+  for (int j = 0; j < n; ++j) {
+    eta[j] = hin[j] + bin[j];
+    m[j] = muin[j];
+    b[j] = bin[j];
+  }
+  std::vector<double> x(x0, x0 + n + 1);
+  double t = t0;
+  int st = ST_OK;
+  for (int64_t k = 0; k < nsteps; ++k) {
+    Counters cnt{};
+    st = step(*P, n, eta.data(), m.data(), b.data(), x.data(), xi, (const double*)nullptr,
+              (double*)nullptr, t, dts[k], (uint8_t*)nullptr, cnt);
+    if (st != ST_OK && st != ST_NEGWEIGHT) break;
+  }
+  std::vector<double> adj(tape.size(), 0.0);
+  for (int64_t gI = 0; gI < ngauge; ++gI) {
+    double xg = gauge_x[gI];
+    int c = 0;
+    while (c < n - 1 && !(xg < x[c + 1])) ++c;
+    AD hg = eta[c] - b[c];
+    if (gauge_h) gauge_h[gI] = hg.v;
+    if (hg.i >= 0) adj[hg.i] += gauge_bar[gI];
+  }
+  for (int64_t k = (int64_t)tape.size() - 1; k >= 0; --k) {
+    double a = adj[k];
+    if (a == 0.0) continue;
+    const TapeNode& nd = tape[k];
+    if (nd.a >= 0) adj[nd.a] += nd.da * a;
+    if (nd.b >= 0) adj[nd.b] += nd.db * a;
+  }
+  for (int j = 0; j < n; ++j) {
+    dh0[j] = adj[hin[j].i];
+    dhu0[j] = adj[muin[j].i];
+    db0[j] = adj[bin[j].i];
+  }
+  g_tape = nullptr;
+  return st;
+}
+
+}  /* extern "C" */

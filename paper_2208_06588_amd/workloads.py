@@ -1,0 +1,199 @@
+"""Seeded synthetic inputs shaped like the paper's 1D tests.
+
+This module only builds initial data (nodes and cell averages of analytic
+initial conditions).  It holds none of the scheme's arithmetic, imports
+nothing else from the package, and serves both the GPU path and the oracle.
+
+Cell averages use the 5-point Gauss-Legendre rule on each cell, with cells
+split at the breakpoints of piecewise-defined data.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+G = 9.812  # gravitational constant used throughout Sec. 5
+
+_GL5_X = np.array([-0.9061798459386640, -0.5384693101056831, 0.0,
+                   0.5384693101056831, 0.9061798459386640])
+_GL5_W = np.array([0.2369268850561891, 0.4786286704993665, 0.5688888888888889,
+                   0.4786286704993665, 0.2369268850561891])
+
+
+def uniform_nodes(n: int, x0: float, x1: float) -> np.ndarray:
+    return x0 + (x1 - x0) * (np.arange(n + 1, dtype=np.float64) / n)
+
+
+def cell_averages(f, nodes: np.ndarray, breaks=()) -> np.ndarray:
+    """Average of f over each cell [nodes[j], nodes[j+1]] (5-point Gauss-Legendre,
+    cells containing a breakpoint are split there)."""
+    a = nodes[:-1]
+    b = nodes[1:]
+
+    def gl(lo, hi):
+        mid = 0.5 * (lo + hi)
+        half = 0.5 * (hi - lo)
+        xs = mid[:, None] + half[:, None] * _GL5_X[None, :]
+        return (f(xs) * _GL5_W[None, :]).sum(axis=1) * half
+
+    integ = gl(a, b)
+    for c in breaks:
+        idx = np.nonzero((a < c) & (c < b))[0]
+        if idx.size:
+            cc = np.full(idx.size, c)
+            integ[idx] = gl(a[idx], cc) + gl(cc, b[idx])
+    return integ / (b - a)
+
+
+# --------------------------------------------------------------------------
+# Example 5.1 (accuracy test) and the smooth periodic parity case
+# --------------------------------------------------------------------------
+def accuracy_1d(n: int = 200, mesh: str = "sine"):
+    """[0,1] periodic; b = sin^2(pi x), h = 5 + exp(cos 2 pi x), hu = sin(cos 2 pi x)
+    (eq. (5.3)).  mesh='sine': X = xi + 0.05 sin(2 pi xi) sin(pi t);
+    mesh='paper': eq. (5.1) with t_end = 0.1."""
+    xi = uniform_nodes(n, 0.0, 1.0)
+    b = cell_averages(lambda x: np.sin(np.pi * x) ** 2, xi)
+    h = cell_averages(lambda x: 5.0 + np.exp(np.cos(2 * np.pi * x)), xi)
+    hu = cell_averages(lambda x: np.sin(np.cos(2 * np.pi * x)), xi)
+    if mesh == "sine":
+        m = dict(mesh="sine", mesh_A=0.05, mesh_k=1.0, mesh_omega=math.pi)
+    else:
+        m = dict(mesh="paper", mesh_A=1.0, mesh_k=0.0, mesh_omega=2 * math.pi / 0.1)
+    return dict(xi=xi, x=xi.copy(), h=h, hu=hu, b=b, bc="periodic", t_end=0.1, cfl=0.6,
+                weno_eps=1e-6, **m)
+
+
+# --------------------------------------------------------------------------
+# Example 5.3 (still water)
+# --------------------------------------------------------------------------
+def still_water_1d(n: int = 200, bottom: str = "smooth", t_end: float = 0.5):
+    """[0,10]; b = 5 exp(-0.4 (x-5)^2) (eq. (5.6)) or 4 on [4,8] (eq. (5.7));
+    h + b = 10, hu = 0; moving mesh eq. (5.1); transmissive boundaries."""
+    xi = uniform_nodes(n, 0.0, 10.0)
+    if bottom == "smooth":
+        bf = lambda x: 5.0 * np.exp(-0.4 * (x - 5.0) ** 2)
+        br = ()
+    else:
+        bf = lambda x: np.where((x >= 4.0) & (x <= 8.0), 4.0, 0.0)
+        br = (4.0, 8.0)
+    b = cell_averages(bf, xi, br)
+    h = cell_averages(lambda x: 10.0 - bf(x), xi, br)
+    hu = np.zeros(n)
+    return dict(xi=xi, x=xi.copy(), h=h, hu=hu, b=b, bc="transmissive", t_end=t_end, cfl=0.6,
+                weno_eps=1e-6, mesh="paper", mesh_A=1.0, mesh_k=0.0,
+                mesh_omega=2 * math.pi / t_end)
+
+
+# --------------------------------------------------------------------------
+# Example 5.2, Moses's second problem (dry bed in the middle, flat bottom)
+# --------------------------------------------------------------------------
+def moses2_1d(n: int = 200, t_end: float = 1.0):
+    xi = uniform_nodes(n, -300.0, 300.0)
+    hf = lambda x: np.where(np.abs(x) < 70.0, 0.0, 10.0)
+    h = cell_averages(hf, xi, (-70.0, 70.0))
+    return dict(xi=xi, x=xi.copy(), h=h, hu=np.zeros(n), b=np.zeros(n), bc="transmissive",
+                t_end=t_end, cfl=0.08, weno_eps=1e-6, mesh="paper", mesh_A=1.0, mesh_k=0.0,
+                mesh_omega=2 * math.pi / t_end)
+
+
+# --------------------------------------------------------------------------
+# Example 5.4 (LeVeque perturbation), ragged batch
+# --------------------------------------------------------------------------
+def _lev_bottom(x):
+    return np.where(np.abs(x - 1.5) < 0.1, 0.25 * (np.cos(10 * np.pi * (x - 1.5)) + 1.0), 0.0)
+
+
+def perturbation_instance(n: int, eps: float):
+    """[0,2]; bump bottom; h = 1 - b + eps on [1.1,1.2], else 1 - b; hu = 0."""
+    xi = uniform_nodes(n, 0.0, 2.0)
+    br = (1.1, 1.2, 1.4, 1.6)
+    b = cell_averages(_lev_bottom, xi, br)
+    h = cell_averages(lambda x: 1.0 - _lev_bottom(x) + np.where((x >= 1.1) & (x <= 1.2), eps, 0.0),
+                      xi, br)
+    return xi, h, np.zeros(n), b
+
+
+def perturbation_batch(ninst: int = 4096, nmin: int = 1000, nmax: int = 20000,
+                       seed: int = 2208065881, subset: int | None = None):
+    """Ragged batch: cell counts uniform in [nmin, nmax], eps uniform in
+    [1e-5, 1e-2] (NumPy PCG64, drawn in that order).  Packed SoA with
+    cell offsets; node arrays hold ncell+1 entries per instance.  subset=k
+    keeps the first k instances of the same draw."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ns = rng.integers(nmin, nmax + 1, ninst)
+    eps = rng.uniform(1e-5, 1e-2, ninst)
+    if subset is not None:
+        ns = ns[:subset]
+        eps = eps[:subset]
+    return pack([perturbation_instance(int(n), float(e)) for n, e in zip(ns, eps)],
+                bc="transmissive", t_end=0.2, cfl=0.6, weno_eps=1e-9, mesh="sine",
+                mesh_A=0.05, mesh_k=1.0, mesh_omega=math.pi, eps=eps)
+
+
+def pack(instances, **meta):
+    ns = np.array([len(h) for (_, h, _, _) in instances], dtype=np.int64)
+    cell_off = np.zeros(len(ns) + 1, dtype=np.int64)
+    cell_off[1:] = np.cumsum(ns)
+    xi = np.concatenate([i[0] for i in instances])
+    h = np.concatenate([i[1] for i in instances])
+    hu = np.concatenate([i[2] for i in instances])
+    b = np.concatenate([i[3] for i in instances])
+    return dict(cell_off=cell_off, xi=xi, x=xi.copy(), h=h, hu=hu, b=b, **meta)
+
+
+# --------------------------------------------------------------------------
+# 1D analogue of Example 5.10 (parabolic basin), wet/dry, fluid-following mesh
+# --------------------------------------------------------------------------
+def bowl_1d(n: int = 1 << 24, h0: float = 10.0, a: float = 3000.0, r0: float | None = None):
+    """[-2a, 2a]; b = h0 (x/a)^2; h from eq. (5.22) at t = 0 restricted to a
+    line (zero outside the wet region); hu = 0; transmissive boundaries."""
+    if r0 is None:
+        r0 = 0.8 * a
+    A = (a ** 4 - r0 ** 4) / (a ** 4 + r0 ** 4)
+    xi = uniform_nodes(n, -2 * a, 2 * a)
+    bf = lambda x: h0 * (x / a) ** 2
+    hf = lambda x: np.maximum(0.0, h0 * (math.sqrt(1 - A * A) / (1 - A)
+                                         - (x / a) ** 2 * (1 - A * A) / (1 - A) ** 2))
+    b = cell_averages(bf, xi)
+    h = cell_averages(hf, xi)
+    return dict(xi=xi, x=xi.copy(), h=h, hu=np.zeros(n), b=b, bc="transmissive", cfl=0.08,
+                weno_eps=1e-6, mesh="fluid", mesh_A=0.0, mesh_k=0.0, mesh_omega=0.0)
+
+
+# --------------------------------------------------------------------------
+# Bathymetry-inversion batch (gauge misfit)
+# --------------------------------------------------------------------------
+def inversion_batch(ninst: int = 256, n: int = 65536, seed: int = 2208065883,
+                    ngauge: int = 64):
+    """ninst instances of n cells on [0,1]: b = sum of 8 Gaussian bumps
+    (amplitudes U[0,0.3], widths U[0.01,0.05], centres U[0,1]); still water
+    eta = 1 plus a Gaussian hump 0.05 (centre U[0.25,0.75]); hu = 0;
+    ngauge gauges per instance uniform in [0.02, 0.98]; also an independent
+    'true' bottom for synthetic observations."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    xi = uniform_nodes(n, 0.0, 1.0)
+
+    def bottom():
+        A = rng.uniform(0.0, 0.3, 8)
+        s = rng.uniform(0.01, 0.05, 8)
+        c = rng.uniform(0.0, 1.0, 8)
+        return lambda x: sum(A[k] * np.exp(-((x - c[k]) / s[k]) ** 2) for k in range(8))
+
+    insts, true_b, gauges = [], [], []
+    for _ in range(ninst):
+        bf = bottom()
+        ch = rng.uniform(0.25, 0.75)
+        etaf = lambda x, ch=ch: 1.0 + 0.05 * np.exp(-((x - ch) / 0.05) ** 2)
+        b = cell_averages(bf, xi)
+        h = cell_averages(lambda x: np.maximum(0.0, etaf(x) - bf(x)), xi)
+        insts.append((xi, h, np.zeros(n), b))
+        bt = bottom()
+        true_b.append(cell_averages(bt, xi))
+        gauges.append(np.sort(rng.uniform(0.02, 0.98, ngauge)))
+    out = pack(insts, bc="transmissive", cfl=0.6, weno_eps=1e-6, mesh="sine", mesh_A=0.05,
+               mesh_k=1.0, mesh_omega=math.pi)
+    out["b_true"] = np.concatenate(true_b)
+    out["gauge_x"] = np.concatenate(gauges)
+    return out

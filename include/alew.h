@@ -1,0 +1,181 @@
+/*
+ * alew.h -- C ABI of the MI355X (gfx950) library for the 1D well-balanced
+ * ALE-WENO hybrid finite-volume scheme of Zhang, Xia & Xu, "Structure-preserving
+ * finite volume arbitrary Lagrangian-Eulerian WENO schemes for the shallow water
+ * equations" (special source-term variant, Sec. 4.2).
+ *
+ * One time step is the modified SSP-RK3 of eq. (3.14) with the width recurrence
+ * of eq. (3.15).  Each stage evaluates the semi-discrete right-hand side
+ * eq. (3.11)-(3.12): hybrid WENO reconstruction with the smooth/transition/
+ * non-smooth detector (Sec. 2.2, eq. (2.7)-(2.10)), the positivity limiter of
+ * eq. (3.20)-(3.21) with Remark 4.1, the Lax-Friedrichs flux of F(q) - w q with
+ * the global speed of eq. (3.13), the ALE bottom flux of eq. (3.17) and the
+ * well-balanced source of eq. (4.7)-(4.10).  Everything is FP64.
+ *
+ * Conventions shared by every entry point
+ *  - Array arguments are DEVICE pointers to contiguous FP64 (or int64/uint8)
+ *    data unless the comment says "host".  The caller owns them; the library
+ *    never frees or keeps them after the call returns.
+ *  - State arrays are cell averages: h (depth), hu (discharge), b (bottom), one
+ *    value per cell.  Nodes x hold ncell+1 positions per instance; xi holds the
+ *    reference node positions of the prescribed mesh map
+ *    X(xi,t) = xi + mesh_A * S(xi) * sin(mesh_omega * t).
+ *  - Ragged batches are packed: instance i owns cells [cell_off[i],
+ *    cell_off[i+1]) and nodes [cell_off[i] + i, cell_off[i+1] + i].
+ *  - Work is enqueued on the context's HIP stream.  Calls that return stats
+ *    synchronise that stream before returning.
+ *  - Errors: argument errors return at once (ALEW_E_ARG); errors found on the
+ *    device (non-positive width, negative mean depth below -pp_eps, non-finite
+ *    values, negative linear weight) stop the affected instance and are
+ *    returned by the call (and per instance in stats).  alew_last_error()
+ *    returns a message for the calling thread's last non-OK return.
+ *  - One context per host thread and stream; contexts are independent.
+ */
+#ifndef ALEW_H
+#define ALEW_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct alew_ctx alew_ctx;
+
+typedef enum {
+  ALEW_OK = 0,
+  ALEW_E_ARG = 1,         /* bad argument (NULL, size, enum, ...)                  */
+  ALEW_E_MESH = 2,        /* a cell width <= 0 (assumption (A1) of Sec. 2.1)        */
+  ALEW_E_NEGDEPTH = 3,    /* a mean depth below -pp_eps (Property 3.1 violated)     */
+  ALEW_E_NONFINITE = 4,   /* NaN or Inf in the state                               */
+  ALEW_E_HIP = 5,         /* HIP runtime error                                     */
+  ALEW_E_NOMEM = 6,       /* device allocation failed                              */
+  ALEW_E_UNSUPPORTED = 7, /* combination not supported by this entry point          */
+  ALEW_E_NEGWEIGHT = 8    /* a negative linear weight d_r (Sec. 2.2, after Step 4)  */
+} alew_status;
+
+enum { ALEW_BC_PERIODIC = 0, ALEW_BC_TRANSMISSIVE = 1, ALEW_BC_REFLECTIVE = 2 };
+
+/* Mesh motion.  GIVEN: node speeds w supplied by the caller (alew_step only).
+ * SINE: S(xi) = sin(2 pi mesh_k xi).  PAPER: S(xi) = (xi - xi_N)(xi - xi_0) /
+ * (3 (xi_N - xi_0)^2), eq. (5.1) with mesh_A = 1, mesh_omega = 2 pi / t_end.
+ * For SINE and PAPER the node speed of a step is the chord of eq. (2.1),
+ * (X(xi, t+dt) - X(xi, t)) / dt.  FLUID: node speeds follow the fluid (average
+ * of the two adjacent cell velocities, two passes of [1/4,1/2,1/4] smoothing,
+ * fixed end nodes unless periodic). */
+enum { ALEW_MESH_GIVEN = 0, ALEW_MESH_SINE = 1, ALEW_MESH_PAPER = 2, ALEW_MESH_FLUID = 3 };
+
+/* flags */
+enum {
+  ALEW_F_BETA_LOCAL = 1,  /* Dx in the indicators = the cell's own width instead of
+                             the max width of the stage mesh (Sec. 2.2, Step 1)     */
+  ALEW_F_BETA_FROM_H = 2  /* indicators on (h, hu) instead of (eta, hu)             */
+};
+
+typedef struct {
+  double g;          /* gravitational constant (9.812 in Sec. 5)                       */
+  double cfl;        /* CFL number of the time-step rule                               */
+  double weno_eps;   /* epsilon of eq. (2.7)-(2.8) (1e-6; 1e-9 for Example 5.4)         */
+  double pp_eps;     /* positivity epsilon of eq. (3.20) (1e-11)                        */
+  double mesh_A, mesh_k, mesh_omega;   /* prescribed mesh map (see above)            */
+  double dry_eps;    /* trace depth below which u = hu = 0 in the flux (1e-8)          */
+  int32_t bc;        /* ALEW_BC_*                                                      */
+  int32_t mesh;      /* ALEW_MESH_*                                                    */
+  int32_t flags;     /* ALEW_F_*                                                       */
+  int32_t pad;
+} alew_params;
+
+typedef struct {
+  int64_t steps;          /* time steps taken                                          */
+  int64_t n_class[3];     /* cell-stages classified smooth / transition / non-smooth   */
+  int64_t n_limited;      /* cell-stages where the positivity limiter acted            */
+  int64_t n_negweight;    /* cell-stages with a negative linear weight                  */
+  double t;               /* time reached                                               */
+  double dt_min, dt_max;  /* step sizes used                                            */
+  double h_min;           /* smallest mean depth seen (initial and after every step)    */
+  double mass_eta0, mass_eta;  /* sum_j Delta_j eta_j at start and end                  */
+  double mass_b0, mass_b;      /* sum_j Delta_j b_j at start and end                    */
+  int32_t status;         /* alew_status of this instance                               */
+  int32_t pad;
+} alew_stats;
+
+/* Launch configuration (normally chosen by the autotuner).
+ * engine 0 = automatic, 1 = persistent (one launch runs a whole ragged batch,
+ * a work-group per instance, instances taken largest first from a device queue),
+ * 2 = stage launches (every tile of every instance in each stage kernel).
+ * block: work-group size (128, 256 or 512; 0 = 256).
+ * steps_per_launch: persistent engine, steps per launch before control returns to
+ * the host (0 = until every instance is done).
+ * use_graph: stage-launch engine, replay the launches of a step as a hipGraph. */
+typedef struct {
+  int32_t engine;
+  int32_t block;
+  int32_t steps_per_launch;
+  int32_t use_graph;
+} alew_launch;
+
+/* Create a context able to run up to max_cells cells in up to max_inst instances.
+ * Scratch memory (about 110 bytes per cell) is allocated here and nowhere else.
+ * hip_stream: hipStream_t to enqueue on (NULL = default stream). */
+alew_status alew_create(alew_ctx** ctx, int64_t max_cells, int64_t max_inst, void* hip_stream);
+void alew_destroy(alew_ctx* ctx);
+alew_status alew_set_stream(alew_ctx* ctx, void* hip_stream);
+alew_status alew_set_launch(alew_ctx* ctx, const alew_launch* launch);
+alew_status alew_get_launch(const alew_ctx* ctx, alew_launch* launch);
+
+/* One time step of one instance (eq. (3.14)-(3.15)).
+ * h, hu, b [ncell] and x [ncell+1] are updated in place.  xi [ncell+1] is
+ * required for SINE/PAPER meshes; w [ncell+1] is required for GIVEN (node
+ * speeds over the step; w[ncell] must equal w[0] when periodic).
+ * dt > 0 fixes the step; dt <= 0 selects the CFL rule
+ *   dt = cfl * min_j Delta_j / (max_j(|u_j| + sqrt(g h_j)) + max_i |W_i|),
+ * W the node speed at t.  If t_end > t the step is clipped to end at t_end.
+ * cls [3*ncell] (optional) receives the detector class of every cell at each
+ * stage (0 smooth, 1 transition, 2 non-smooth).  stats (host, optional)
+ * receives the step statistics; stats->t is the new time.  ncell >= 5. */
+alew_status alew_step(alew_ctx* ctx, const alew_params* p, int64_t ncell, double* h, double* hu,
+                      double* b, double* x, const double* xi, const double* w, double t, double dt,
+                      double t_end, uint8_t* cls, alew_stats* stats);
+
+/* Run a ragged batch of independent instances.
+ * cell_off (host) [ninst+1]; h, hu, b, x, xi packed as described above.
+ * t0, t_end, max_steps (host) [ninst], each may be NULL: instance i starts at
+ * t0[i] (0) and advances until t_end[i] (if > t0[i]) and/or max_steps[i] steps
+ * (if > 0).  dts (device, optional) [ninst * dts_stride] fixes the step sizes
+ * (the CFL rule is used when NULL).  dt_log (device, optional)
+ * [ninst * dts_stride] receives the step sizes used.  stats (host, optional)
+ * [ninst].  mesh must be SINE, PAPER or FLUID. */
+alew_status alew_run(alew_ctx* ctx, const alew_params* p, int64_t ninst, const int64_t* cell_off,
+                     double* h, double* hu, double* b, double* x, const double* xi,
+                     const double* t0, const double* t_end, const int64_t* max_steps,
+                     const double* dts, double* dt_log, int64_t dts_stride, alew_stats* stats);
+
+/* Discrete adjoint of alew_run with frozen step sizes (prescribed mesh).
+ * Forward: from (h0, hu0, b0, x0) run nsteps steps of sizes dts (device,
+ * [ninst * nsteps]); gauge_h (device, out) [ninst * ngauge] receives the mean
+ * depth at the final time of the cell containing gauge_x (device)
+ * [ninst * ngauge] (positions in the final mesh).
+ * Reverse: with gauge_bar (device) [ninst * ngauge] = dL/d gauge_h, writes
+ * dh0, dhu0, db0 (device) [sum ncell] = dL/d (h0, hu0, b0).  The detector class,
+ * the limiter's active set and argmin, the argmax of the LF speed, |.| signs and
+ * dry cut-offs are frozen to the forward pass.  The forward is checkpointed every
+ * ckpt_every steps and recomputed segment by segment (ckpt_every <= 0: 16).
+ * gauge_h may be computed without the reverse pass by passing gauge_bar = NULL. */
+alew_status alew_adjoint(alew_ctx* ctx, const alew_params* p, int64_t ninst,
+                         const int64_t* cell_off, const double* h0, const double* hu0,
+                         const double* b0, const double* x0, const double* xi, int64_t nsteps,
+                         const double* dts, int64_t ckpt_every, int64_t ngauge,
+                         const double* gauge_x, double* gauge_h, const double* gauge_bar,
+                         double* dh0, double* dhu0, double* db0);
+
+/* Message for the calling thread's last non-OK status ("" if none). */
+const char* alew_last_error(void);
+
+/* Library version string. */
+const char* alew_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ALEW_H */

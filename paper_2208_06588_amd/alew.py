@@ -1,0 +1,220 @@
+"""Thin ctypes binding of ``libalew.so`` (C ABI in include/alew.h).
+
+Argument marshalling only: every step of the scheme runs in the HIP kernels.
+PyTorch provides device memory and the stream.  If the library is missing
+this module raises at load time; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libalew.so")
+
+OK, E_ARG, E_MESH, E_NEGDEPTH, E_NONFINITE, E_HIP, E_NOMEM, E_UNSUPPORTED, E_NEGWEIGHT = range(9)
+BC = {"periodic": 0, "transmissive": 1, "reflective": 2}
+MESH = {"given": 0, "sine": 1, "paper": 2, "fluid": 3}
+F_BETA_LOCAL, F_BETA_FROM_H = 1, 2
+ENGINE_AUTO, ENGINE_PERSISTENT, ENGINE_STAGES = 0, 1, 2
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("g", C.c_double), ("cfl", C.c_double), ("weno_eps", C.c_double), ("pp_eps", C.c_double),
+        ("mesh_A", C.c_double), ("mesh_k", C.c_double), ("mesh_omega", C.c_double),
+        ("dry_eps", C.c_double),
+        ("bc", C.c_int32), ("mesh", C.c_int32), ("flags", C.c_int32), ("pad", C.c_int32),
+    ]
+
+
+class Stats(C.Structure):
+    _fields_ = [
+        ("steps", C.c_int64), ("n_class", C.c_int64 * 3), ("n_limited", C.c_int64),
+        ("n_negweight", C.c_int64),
+        ("t", C.c_double), ("dt_min", C.c_double), ("dt_max", C.c_double), ("h_min", C.c_double),
+        ("mass_eta0", C.c_double), ("mass_eta", C.c_double), ("mass_b0", C.c_double),
+        ("mass_b", C.c_double),
+        ("status", C.c_int32), ("pad", C.c_int32),
+    ]
+
+    def as_dict(self):
+        return {k: (list(getattr(self, k)) if k == "n_class" else getattr(self, k))
+                for k, _ in self._fields_ if k != "pad"}
+
+
+class Launch(C.Structure):
+    _fields_ = [("engine", C.c_int32), ("block", C.c_int32), ("steps_per_launch", C.c_int32),
+                ("use_graph", C.c_int32)]
+
+
+class AlewError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"alew status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() first")
+        L = C.CDLL(LIB_PATH)
+        vp, dp, i64 = C.c_void_p, C.POINTER(C.c_double), C.c_int64
+        L.alew_create.argtypes = [C.POINTER(vp), i64, i64, vp]
+        L.alew_destroy.argtypes = [vp]
+        L.alew_set_stream.argtypes = [vp, vp]
+        L.alew_set_launch.argtypes = [vp, C.POINTER(Launch)]
+        L.alew_get_launch.argtypes = [vp, C.POINTER(Launch)]
+        L.alew_step.argtypes = [vp, C.POINTER(Params), i64, vp, vp, vp, vp, vp, vp, C.c_double,
+                                C.c_double, C.c_double, vp, C.POINTER(Stats)]
+        L.alew_run.argtypes = [vp, C.POINTER(Params), i64, C.POINTER(C.c_int64), vp, vp, vp, vp, vp,
+                               dp, dp, C.POINTER(C.c_int64), vp, vp, i64, C.POINTER(Stats)]
+        L.alew_adjoint.argtypes = [vp, C.POINTER(Params), i64, C.POINTER(C.c_int64), vp, vp, vp,
+                                   vp, vp, i64, vp, i64, i64, vp, vp, vp, vp, vp, vp]
+        L.alew_last_error.restype = C.c_char_p
+        L.alew_version.restype = C.c_char_p
+        for f in ("alew_create", "alew_set_stream", "alew_set_launch", "alew_get_launch",
+                  "alew_step", "alew_run", "alew_adjoint"):
+            getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def params(g=9.812, cfl=0.6, weno_eps=1e-6, pp_eps=1e-11, dry_eps=1e-8, bc="periodic",
+           mesh="sine", mesh_A=0.05, mesh_k=1.0, mesh_omega=3.141592653589793, flags=0) -> Params:
+    return Params(g, cfl, weno_eps, pp_eps, mesh_A, mesh_k, mesh_omega, dry_eps,
+                  BC[bc] if isinstance(bc, str) else int(bc),
+                  MESH[mesh] if isinstance(mesh, str) else int(mesh), int(flags), 0)
+
+
+def _ptr(t: Optional[torch.Tensor], dtype=torch.float64):
+    if t is None:
+        return None
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"expected a contiguous {dtype} CUDA tensor, got {t.dtype} "
+                         f"{'cuda' if t.is_cuda else 'cpu'} contiguous={t.is_contiguous()}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _sizes(ncell, ninst, h, hu, b, x, xi, w):
+    """Host-side shape checks: the kernels index exactly these extents."""
+    for name, t in (("h", h), ("hu", hu), ("b", b)):
+        if t.numel() != ncell:
+            raise ValueError(f"{name} has {t.numel()} entries, expected {ncell}")
+    for name, t in (("x", x), ("xi", xi), ("w", w)):
+        if t is not None and t.numel() != ncell + ninst:
+            raise ValueError(f"{name} has {t.numel()} entries, expected {ncell + ninst}")
+
+
+def _check(st):
+    if st != OK:
+        raise AlewError(st, lib().alew_last_error().decode())
+
+
+class Context:
+    """Owns the library's scratch memory for up to max_cells cells in
+    max_inst instances; work goes to the current torch stream."""
+
+    def __init__(self, max_cells: int, max_inst: int = 1, device=None):
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.max_cells, self.max_inst = int(max_cells), int(max_inst)
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            stream = torch.cuda.current_stream().cuda_stream
+            _check(lib().alew_create(C.byref(h), self.max_cells, self.max_inst, C.c_void_p(stream)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().alew_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _sync_stream(self):
+        _check(lib().alew_set_stream(self._h, C.c_void_p(torch.cuda.current_stream().cuda_stream)))
+
+    def set_launch(self, engine=ENGINE_AUTO, block=256, steps_per_launch=0, use_graph=1):
+        _check(lib().alew_set_launch(self._h, C.byref(Launch(engine, block, steps_per_launch,
+                                                             use_graph))))
+
+    def get_launch(self) -> Launch:
+        l = Launch()
+        _check(lib().alew_get_launch(self._h, C.byref(l)))
+        return l
+
+    def step(self, p: Params, h, hu, b, x, xi=None, w=None, t=0.0, dt=0.0, t_end=0.0, cls=None,
+             check=True) -> Stats:
+        """One SSP-RK3 step of one instance; tensors are updated in place."""
+        n = h.numel()
+        _sizes(n, 1, h, hu, b, x, xi, w)
+        if n > self.max_cells:
+            raise ValueError("more cells than the context holds")
+        if cls is not None and cls.numel() != 3 * n:
+            raise ValueError("cls must hold 3 * ncell entries")
+        self._sync_stream()
+        S = Stats()
+        st = lib().alew_step(self._h, C.byref(p), h.numel(), _ptr(h), _ptr(hu), _ptr(b), _ptr(x),
+                             _ptr(xi), _ptr(w), float(t), float(dt), float(t_end),
+                             _ptr(cls, torch.uint8), C.byref(S))
+        if check:
+            _check(st)
+        S.status = st if st else S.status
+        return S
+
+    def run(self, p: Params, cell_off: Sequence[int], h, hu, b, x, xi, t0=None, t_end=None,
+            max_steps=None, dts=None, dt_log=None, dts_stride=0, check=True):
+        """Run a packed ragged batch; returns the per-instance Stats."""
+        ninst = len(cell_off) - 1
+        _sizes(int(cell_off[-1]), ninst, h, hu, b, x, xi, None)
+        for d in (dts, dt_log):
+            if d is not None and d.numel() < ninst * dts_stride:
+                raise ValueError("dts/dt_log must hold ninst * dts_stride entries")
+        self._sync_stream()
+        off = (C.c_int64 * len(cell_off))(*[int(v) for v in cell_off])
+        n = len(cell_off) - 1
+
+        def darr(v):
+            if v is None:
+                return None
+            v = [float(a) for a in (v if hasattr(v, "__len__") else [v] * n)]
+            return (C.c_double * n)(*v)
+
+        def iarr(v):
+            if v is None:
+                return None
+            v = [int(a) for a in (v if hasattr(v, "__len__") else [v] * n)]
+            return (C.c_int64 * n)(*v)
+
+        stats = (Stats * n)()
+        st = lib().alew_run(self._h, C.byref(p), n, off, _ptr(h), _ptr(hu), _ptr(b), _ptr(x),
+                            _ptr(xi), darr(t0), darr(t_end), iarr(max_steps), _ptr(dts),
+                            _ptr(dt_log), int(dts_stride), stats)
+        if check:
+            _check(st)
+        return list(stats)
+
+    def adjoint(self, p: Params, cell_off, h0, hu0, b0, x0, xi, nsteps, dts, ngauge, gauge_x,
+                gauge_h, gauge_bar, dh0, dhu0, db0, ckpt_every=16):
+        self._sync_stream()
+        off = (C.c_int64 * len(cell_off))(*[int(v) for v in cell_off])
+        st = lib().alew_adjoint(self._h, C.byref(p), len(cell_off) - 1, off, _ptr(h0), _ptr(hu0),
+                                _ptr(b0), _ptr(x0), _ptr(xi), int(nsteps), _ptr(dts),
+                                int(ckpt_every), int(ngauge), _ptr(gauge_x), _ptr(gauge_h),
+                                _ptr(gauge_bar), _ptr(dh0), _ptr(dhu0), _ptr(db0))
+        _check(st)
+
+
+def version() -> str:
+    return lib().alew_version().decode()

@@ -1,0 +1,815 @@
+// MI355X (gfx950) library for the 1D well-balanced ALE-WENO hybrid scheme:
+// kernels and the C ABI declared in include/alew.h.
+//
+// Two engines run the same tile bodies (alew_kernels.h):
+//  * stage launches: each kernel covers every tile of every active instance;
+//    per-instance reductions (LF speed, widths, step-size inputs) go through
+//    integer atomics on IEEE bit patterns, so they are order independent.  One
+//    time step is 9-10 launches; a 2-step sequence is replayed as a hipGraph.
+//  * persistent: one launch runs a whole ragged batch.  A work-group takes the
+//    next instance from a device queue (largest first), runs all of its steps
+//    with work-group reductions only, and takes the next one.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "alew.h"
+#include "alew_kernels.h"
+
+using namespace alew_dev;
+
+// ============================================================================
+// kernels
+// ============================================================================
+struct Tile {
+  int32_t inst;
+  int32_t pad;
+  int64_t c0;
+};
+
+// Start of a call: eta = h + b, reductions for the first step, shape bound of
+// the prescribed map, initial masses.  Plain tiles: B items per tile over the
+// n+1 nodes of each instance.
+template <int B>
+__global__ __launch_bounds__(B) void k_prep(Bufs bf, Consts cs, const Tile* __restrict__ tiles,
+                                            const double* __restrict__ h_in,
+                                            const double* __restrict__ wgiven) {
+  __shared__ double red[(B / 64) * 8];
+  const Tile tl = tiles[blockIdx.x];
+  Inst& I = bf.inst[tl.inst];
+  View v = make_view(bf, tl.inst, I);
+  const int64_t j = tl.c0 + threadIdx.x;
+  double speed = 0, minJ = INFINITY, maxJ = 0, hmin = INFINITY, me = 0, mb = 0, sabs = 0;
+  if (j < v.n) {
+    const int64_t g = v.co + j;
+    const double h = h_in[g], b = bf.b[g], m = bf.m[g];
+    const double e = h + b;
+    bf.eta[g] = e;
+    const double J = v.x[j + 1] - v.x[j];
+    const double hh = e - b;
+    const double u = hh > cs.dry_eps ? m / hh : 0.0;
+    speed = fabs(u) + sqrt(cs.g * fmax(hh, 0.0));
+    minJ = J; maxJ = J; hmin = hh;
+    me = J * e; mb = J * b;
+  }
+  if (j <= v.n) {
+    if (cs.mesh == MESH_SINE || cs.mesh == MESH_PAPER) {
+      const double* xi = bf.xi + v.no;
+      sabs = fabs(mesh_shape(cs, xi[j], xi[0], xi[v.n]));
+    } else if (cs.mesh == MESH_GIVEN && wgiven) {
+      const double wv = wgiven[j];
+      bf.w[v.no + j] = wv;
+      sabs = fabs(wv);
+    }
+  }
+  double rv[7] = {speed, minJ, maxJ, hmin, me, mb, sabs};
+  const int op[7] = {0, 1, 0, 1, 2, 2, 0};
+  block_reduce<B, 7>(rv, op, red);
+  if (threadIdx.x == 0) {
+    amax_pos(&I.r_speed, rv[0]);
+    amin_pos(&I.r_minJ, rv[1]);
+    amax_pos(&I.r_maxJ, rv[2]);
+    atomicMin(&I.r_hmin, okey(rv[3]));
+    atomicAdd(&I.mass_eta0, rv[4]);
+    atomicAdd(&I.mass_b0, rv[5]);
+    if (cs.mesh == MESH_GIVEN) amax_pos(&I.r_W, rv[6]);
+    else amax_pos((unsigned long long*)&I.smax, rv[6]);
+  }
+}
+
+template <int B>
+__global__ __launch_bounds__(B) void k_wmap(Bufs bf, Consts cs, const Tile* __restrict__ tiles) {
+  const Tile tl = tiles[blockIdx.x];
+  const Inst& I = bf.inst[tl.inst];
+  if (!I.active) return;
+  View v = make_view(bf, tl.inst, I);
+  wmap_tile<B>(bf, cs, v, I.t, I.dt, tl.c0);
+}
+
+template <int B>
+__global__ __launch_bounds__(B) void k_wfluid(Bufs bf, Consts cs, const Tile* __restrict__ tiles) {
+  __shared__ double su[B + 6], sv[B + 4], red[(B / 64) * 8];
+  const Tile tl = tiles[blockIdx.x];
+  Inst& I = bf.inst[tl.inst];
+  if (!I.active) return;
+  View v = make_view(bf, tl.inst, I);
+  const double W = wfluid_tile<B>(bf, cs, v, tl.c0, su, sv, red);
+  if (threadIdx.x == 0) amax_pos(&I.r_W, W);
+}
+
+template <int B>
+__global__ __launch_bounds__(B) void k_stage(Bufs bf, Consts cs, const Tile* __restrict__ tiles,
+                                             int s) {
+  __shared__ SmemStage<B> sm;
+  const Tile tl = tiles[blockIdx.x];
+  Inst& I = bf.inst[tl.inst];
+  if (!I.active) return;
+  View v = make_view(bf, tl.inst, I);
+  StageScal sc;
+  sc.s = s;
+  sc.dt = I.dt;
+  sc.as = s == 1 ? 0.0 : (s == 2 ? 0.75 : 1.0 / 3.0);
+  sc.bs = s == 1 ? 1.0 : (s == 2 ? 0.25 : 2.0 / 3.0);
+  const double bprev = s == 2 ? 1.0 : 0.25;
+  sc.cprev = s == 1 ? 0.0 : bprev * I.dt * I.alpha[s - 2];
+  sc.dx = I.dx[s - 1];
+  uint8_t* cl = bf.cls ? bf.cls + (int64_t)(s - 1) * bf.S + v.co : nullptr;
+  StageRes r = stage_tile<B>(bf, cs, v, sc, tl.c0, sm, cl);
+  if (threadIdx.x == 0) {
+    amax_pos(&I.r_alpha, r.alpha);
+    if (s < 3) amax_pos(&I.r_maxJs, r.maxJ);
+    atomicAdd(&I.n_class[0], (unsigned long long)r.ncls0);
+    atomicAdd(&I.n_class[1], (unsigned long long)r.ncls1);
+    atomicAdd(&I.n_class[2], (unsigned long long)r.ncls2);
+    atomicAdd(&I.n_limited, (unsigned long long)r.nlim);
+    atomicAdd(&I.n_negweight, (unsigned long long)r.nneg);
+    if (r.status) atomicOr(&I.status, r.status);
+  }
+}
+
+template <int B>
+__global__ __launch_bounds__(B) void k_final(Bufs bf, Consts cs, const Tile* __restrict__ tiles) {
+  __shared__ double red[(B / 64) * 8];
+  const Tile tl = tiles[blockIdx.x];
+  Inst& I = bf.inst[tl.inst];
+  if (!I.active) return;
+  View v = make_view(bf, tl.inst, I);
+  FinalRes r = final_tile<B>(bf, cs, v, I.dt, I.alpha[2], tl.c0, red);
+  if (threadIdx.x == 0) {
+    amax_pos(&I.r_speed, r.speed);
+    amin_pos(&I.r_minJ, r.minJ);
+    amax_pos(&I.r_maxJ, r.maxJ);
+    atomicMin(&I.r_hmin, okey(r.hmin));
+    if (r.status) atomicOr(&I.status, r.status);
+  }
+}
+
+// Per-instance scalar work between launches (one work-group, loops over instances).
+__device__ void reset_step_slots(Inst& I) {
+  I.r_speed = 0ull;
+  I.r_minJ = dbits(INFINITY);
+  I.r_maxJ = 0ull;
+  I.r_W = 0ull;
+}
+
+// End of a step (first = false) and size of the next one.
+__device__ void boundary_update(Inst& I, const Consts& cs, const Bufs& bf, int i, bool first) {
+  if (!I.active) return;
+  if (!first) {
+    I.t = I.t + I.dt;
+    I.steps += 1;
+    I.dt_min = fmin(I.dt_min, I.dt);
+    I.dt_max = fmax(I.dt_max, I.dt);
+  }
+  if (inst_done(I)) {
+    I.active = 0;
+    return;
+  }
+  // the frozen step sizes and the step log hold dts_stride entries per instance
+  if ((bf.dts || bf.dt_log) && I.steps >= bf.dts_stride) {
+    I.active = 0;
+    return;
+  }
+  const double dt = next_dt(I, cs, bf.dts, bf.dts_stride, i);
+  // a step that cannot advance the clock ends the instance (no endless loops)
+  if (!(dt > 0.0) || !(dt < INFINITY) || I.steps >= 100000000ll) {
+    I.status |= SB_NONFINITE;
+    I.active = 0;
+    return;
+  }
+  I.dt = dt;
+  if (bf.dt_log) bf.dt_log[(int64_t)i * bf.dts_stride + I.steps] = dt;
+  I.dx[0] = bitsd(I.r_maxJ);
+  reset_step_slots(I);
+}
+
+__global__ __launch_bounds__(1024) void k_boundary(Bufs bf, Consts cs, int first,
+                                                   int* __restrict__ n_active) {
+  __shared__ int cnt;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  int c = 0;
+  for (int i = threadIdx.x; i < bf.ninst; i += blockDim.x) {
+    Inst& I = bf.inst[i];
+    boundary_update(I, cs, bf, i, first != 0);
+    c += I.active ? 1 : 0;
+  }
+  atomicAdd(&cnt, c);
+  __syncthreads();
+  if (threadIdx.x == 0) *n_active = cnt;
+}
+
+__global__ __launch_bounds__(1024) void k_after_stage(Bufs bf, int s) {
+  for (int i = threadIdx.x; i < bf.ninst; i += blockDim.x) {
+    Inst& I = bf.inst[i];
+    if (!I.active) continue;
+    I.alpha[s - 1] = bitsd(I.r_alpha);
+    if (s < 3) I.dx[s] = bitsd(I.r_maxJs);
+    I.r_alpha = 0ull;
+    I.r_maxJs = 0ull;
+  }
+}
+
+// End of a call: h = eta - b, final nodes back into the caller's array, masses.
+template <int B>
+__global__ __launch_bounds__(B) void k_finish(Bufs bf, Consts cs, const Tile* __restrict__ tiles,
+                                              double* __restrict__ h_out,
+                                              double* __restrict__ x_out) {
+  __shared__ double red[(B / 64) * 8];
+  const Tile tl = tiles[blockIdx.x];
+  Inst& I = bf.inst[tl.inst];
+  View v = make_view(bf, tl.inst, I);
+  const int64_t j = tl.c0 + threadIdx.x;
+  double me = 0, mb = 0;
+  if (j <= v.n) x_out[v.no + j] = v.x[j];
+  if (j < v.n) {
+    const int64_t g = v.co + j;
+    const double e = bf.eta[g], b = bf.b[g];
+    h_out[g] = e - b;
+    const double J = v.x[j + 1] - v.x[j];
+    me = J * e;
+    mb = J * b;
+  }
+  double rv[2] = {me, mb};
+  const int op[2] = {2, 2};
+  block_reduce<B, 2>(rv, op, red);
+  if (threadIdx.x == 0) {
+    atomicAdd(&I.mass_eta, rv[0]);
+    atomicAdd(&I.mass_b, rv[1]);
+  }
+}
+
+__global__ void k_zero_u32(unsigned* p) { *p = 0u; }
+
+__global__ __launch_bounds__(1024) void k_count_active(Bufs bf, int* __restrict__ n_active) {
+  __shared__ int cnt;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  int c = 0;
+  for (int i = threadIdx.x; i < bf.ninst; i += blockDim.x) c += bf.inst[i].active ? 1 : 0;
+  atomicAdd(&cnt, c);
+  __syncthreads();
+  if (threadIdx.x == 0) *n_active = cnt;
+}
+
+// Persistent engine: one launch for the whole batch.
+template <int B>
+__global__ __launch_bounds__(B) void k_persistent(Bufs bf, Consts cs,
+                                                  const int32_t* __restrict__ order,
+                                                  unsigned* __restrict__ queue,
+                                                  int32_t steps_limit) {
+  __shared__ SmemStage<B> sm;
+  __shared__ Inst sI;
+  __shared__ int s_idx;
+  __shared__ double su[B + 6], sv[B + 4];
+  for (;;) {
+    if (threadIdx.x == 0) s_idx = (int)atomicAdd(queue, 1u);
+    __syncthreads();
+    const int qi = s_idx;
+    if (qi >= bf.ninst) break;
+    const int i = order[qi];
+    if (threadIdx.x == 0) sI = bf.inst[i];
+    __syncthreads();
+    int launched = 0;
+    while (sI.active && (steps_limit <= 0 || launched < steps_limit)) {
+      const View v = make_view(bf, i, sI);
+      const double dt = sI.dt;
+      if (cs.mesh == MESH_SINE || cs.mesh == MESH_PAPER) {
+        for (int64_t k0 = 0; k0 <= v.n; k0 += B) wmap_tile<B>(bf, cs, v, sI.t, dt, k0);
+        __syncthreads();
+      }
+      double c_cls[3] = {0, 0, 0}, c_lim = 0, c_neg = 0;
+      int st = 0;
+      for (int s = 1; s <= 3; ++s) {
+        StageScal sc;
+        sc.s = s;
+        sc.dt = dt;
+        sc.as = s == 1 ? 0.0 : (s == 2 ? 0.75 : 1.0 / 3.0);
+        sc.bs = s == 1 ? 1.0 : (s == 2 ? 0.25 : 2.0 / 3.0);
+        const double bprev = s == 2 ? 1.0 : 0.25;
+        sc.cprev = s == 1 ? 0.0 : bprev * dt * sI.alpha[s - 2];
+        sc.dx = sI.dx[s - 1];
+        double amax = 0.0, jmax = 0.0;
+        for (int64_t c0 = 0; c0 < v.n; c0 += B - 2) {
+          StageRes r = stage_tile<B>(bf, cs, v, sc, c0, sm, nullptr);
+          amax = fmax(amax, r.alpha);
+          jmax = fmax(jmax, r.maxJ);
+          c_cls[0] += r.ncls0; c_cls[1] += r.ncls1; c_cls[2] += r.ncls2;
+          c_lim += r.nlim; c_neg += r.nneg;
+          st |= r.status;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+          sI.alpha[s - 1] = amax;
+          if (s < 3) sI.dx[s] = jmax;
+        }
+        __syncthreads();
+      }
+      double fsp = 0.0, fminJ = INFINITY, fmaxJ = 0.0, fhmin = INFINITY;
+      for (int64_t c0 = 0; c0 < v.n; c0 += B) {
+        FinalRes r = final_tile<B>(bf, cs, v, dt, sI.alpha[2], c0, sm.red);
+        fsp = fmax(fsp, r.speed);
+        fminJ = fmin(fminJ, r.minJ);
+        fmaxJ = fmax(fmaxJ, r.maxJ);
+        fhmin = fmin(fhmin, r.hmin);
+        st |= r.status;
+      }
+      __syncthreads();
+      double Wf = 0.0;
+      if (cs.mesh == MESH_FLUID) {
+        // the node speeds of the next step follow the new state
+        View vn = v;
+        vn.x = v.xnew;
+        for (int64_t k0 = 0; k0 <= v.n; k0 += B)
+          Wf = fmax(Wf, wfluid_tile<B>(bf, cs, vn, k0, su, sv, sm.red));
+        __syncthreads();
+      }
+      if (threadIdx.x == 0) {
+        sI.n_class[0] += (unsigned long long)c_cls[0];
+        sI.n_class[1] += (unsigned long long)c_cls[1];
+        sI.n_class[2] += (unsigned long long)c_cls[2];
+        sI.n_limited += (unsigned long long)c_lim;
+        sI.n_negweight += (unsigned long long)c_neg;
+        sI.status |= st;
+        sI.r_speed = dbits(fsp);
+        sI.r_minJ = dbits(fminJ);
+        sI.r_maxJ = dbits(fmaxJ);
+        if (cs.mesh == MESH_FLUID) sI.r_W = dbits(Wf);
+        const unsigned long long hk = okey(fhmin);
+        if (hk < sI.r_hmin) sI.r_hmin = hk;
+        boundary_update(sI, cs, bf, i, false);
+      }
+      __syncthreads();
+      ++launched;
+    }
+    if (threadIdx.x == 0) bf.inst[i] = sI;
+    __syncthreads();
+  }
+}
+
+// ============================================================================
+// host side
+// ============================================================================
+namespace {
+
+thread_local std::string g_err;
+
+alew_status fail(alew_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIPCHK(expr)                                                             \
+  do {                                                                           \
+    hipError_t e_ = (expr);                                                      \
+    if (e_ != hipSuccess)                                                        \
+      return fail(ALEW_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+struct GraphKey {
+  std::vector<char> bytes;
+  bool operator==(const GraphKey& o) const { return bytes == o.bytes; }
+};
+
+}  // namespace
+
+struct alew_ctx {
+  hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;  // capture stream for graphs
+  int64_t max_cells = 0, max_inst = 0;
+  double *eta = nullptr, *P0 = nullptr, *D0 = nullptr, *P1 = nullptr, *D1 = nullptr;
+  double *w = nullptr, *xa = nullptr, *xb = nullptr;
+  Inst* inst = nullptr;
+  Inst* inst_h = nullptr;  // pinned
+  int64_t* cell_off_d = nullptr;
+  int32_t* order_d = nullptr;
+  unsigned* queue_d = nullptr;
+  int* nactive_d = nullptr;
+  int* nactive_h = nullptr;  // pinned
+  double* dt1_d = nullptr;   // step size of alew_step
+  double* dt1_h = nullptr;   // pinned staging
+  Tile* tiles_stage_d = nullptr;
+  Tile* tiles_plain_d = nullptr;
+  int64_t tiles_cap = 0;
+  std::vector<int64_t> cell_off_h;  // cached batch layout
+  int cached_B = 0;
+  int64_t n_tiles_stage = 0, n_tiles_plain = 0;
+  alew_launch launch{0, 256, 0, 1};
+  // graph of a 2-step sequence (stage-launch engine)
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  GraphKey gkey;
+};
+
+namespace {
+
+Consts make_consts(const alew_params* p) {
+  Consts c;
+  c.g = p->g; c.cfl = p->cfl; c.weno_eps = p->weno_eps; c.pp_eps = p->pp_eps;
+  c.mesh_A = p->mesh_A; c.mesh_k = p->mesh_k; c.mesh_omega = p->mesh_omega; c.dry_eps = p->dry_eps;
+  c.bc = p->bc; c.mesh = p->mesh; c.flags = p->flags; c.pad = 0;
+  return c;
+}
+
+alew_status check_params(const alew_params* p) {
+  if (!p) return fail(ALEW_E_ARG, "params is NULL");
+  if (!(p->g > 0) || !(p->cfl > 0) || !(p->weno_eps > 0) || !(p->pp_eps >= 0) || !(p->dry_eps >= 0))
+    return fail(ALEW_E_ARG, "g, cfl, weno_eps must be > 0 and pp_eps, dry_eps >= 0");
+  if (p->bc < 0 || p->bc > 2) return fail(ALEW_E_ARG, "unknown boundary type");
+  if (p->mesh < 0 || p->mesh > 3) return fail(ALEW_E_ARG, "unknown mesh mode");
+  if ((p->mesh == ALEW_MESH_SINE || p->mesh == ALEW_MESH_PAPER) && !(p->mesh_omega == p->mesh_omega))
+    return fail(ALEW_E_ARG, "mesh_omega is NaN");
+  return ALEW_OK;
+}
+
+int pick_block(const alew_ctx* c) {
+  const int b = c->launch.block;
+  return (b == 128 || b == 256 || b == 512) ? b : 256;
+}
+
+// (Re)build the tile tables for a batch layout and block size.
+alew_status build_tiles(alew_ctx* c, const int64_t* cell_off, int64_t ninst, int B) {
+  std::vector<int64_t> off(cell_off, cell_off + ninst + 1);
+  if (off == c->cell_off_h && c->cached_B == B) return ALEW_OK;
+  std::vector<Tile> ts, tp;
+  for (int64_t i = 0; i < ninst; ++i) {
+    const int64_t n = off[i + 1] - off[i];
+    for (int64_t c0 = 0; c0 < n; c0 += B - 2) ts.push_back(Tile{(int32_t)i, 0, c0});
+    for (int64_t c0 = 0; c0 <= n; c0 += B) tp.push_back(Tile{(int32_t)i, 0, c0});
+  }
+  const int64_t need = (int64_t)std::max(ts.size(), tp.size());
+  if (need > c->tiles_cap) {
+    if (c->tiles_stage_d) (void)hipFree(c->tiles_stage_d);
+    if (c->tiles_plain_d) (void)hipFree(c->tiles_plain_d);
+    c->tiles_stage_d = c->tiles_plain_d = nullptr;
+    HIPCHK(hipMalloc(&c->tiles_stage_d, need * sizeof(Tile)));
+    HIPCHK(hipMalloc(&c->tiles_plain_d, need * sizeof(Tile)));
+    c->tiles_cap = need;
+  }
+  HIPCHK(hipMemcpyAsync(c->tiles_stage_d, ts.data(), ts.size() * sizeof(Tile), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(c->tiles_plain_d, tp.data(), tp.size() * sizeof(Tile), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(c->cell_off_d, off.data(), off.size() * sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
+  // largest work first for the persistent queue
+  std::vector<int32_t> order(ninst);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    return (off[a + 1] - off[a]) > (off[b + 1] - off[b]);
+  });
+  HIPCHK(hipMemcpyAsync(c->order_d, order.data(), order.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->cell_off_h = off;
+  c->cached_B = B;
+  c->n_tiles_stage = (int64_t)ts.size();
+  c->n_tiles_plain = (int64_t)tp.size();
+  if (c->gexec) { (void)hipGraphExecDestroy(c->gexec); c->gexec = nullptr; }
+  if (c->graph) { (void)hipGraphDestroy(c->graph); c->graph = nullptr; }
+  return ALEW_OK;
+}
+
+Bufs make_bufs(alew_ctx* c, int64_t S, int64_t ninst, double* hu, double* b, const double* xi,
+               uint8_t* cls, const double* dts, double* dt_log, int64_t dts_stride) {
+  Bufs bf;
+  bf.cell_off = c->cell_off_d;
+  bf.eta = c->eta; bf.m = hu; bf.b = b;
+  bf.xa = c->xa; bf.xb = c->xb; bf.xi = xi; bf.w = c->w;
+  bf.P0 = c->P0; bf.D0 = c->D0; bf.P1 = c->P1; bf.D1 = c->D1;
+  bf.cls = cls; bf.inst = c->inst;
+  bf.dts = dts; bf.dt_log = dt_log; bf.dts_stride = dts_stride;
+  bf.S = S; bf.ninst = (int32_t)ninst; bf.pad = 0;
+  return bf;
+}
+
+template <int B>
+void launch_step_seq(alew_ctx* c, const Bufs& bf, const Consts& cs, hipStream_t st) {
+  const dim3 gs((unsigned)c->n_tiles_stage), gp((unsigned)c->n_tiles_plain);
+  if (cs.mesh == MESH_SINE || cs.mesh == MESH_PAPER)
+    hipLaunchKernelGGL(k_wmap<B>, gp, dim3(B), 0, st, bf, cs, c->tiles_plain_d);
+  for (int s = 1; s <= 3; ++s) {
+    hipLaunchKernelGGL(k_stage<B>, gs, dim3(B), 0, st, bf, cs, c->tiles_stage_d, s);
+    hipLaunchKernelGGL(k_after_stage, dim3(1), dim3(1024), 0, st, bf, s);
+  }
+  hipLaunchKernelGGL(k_final<B>, gp, dim3(B), 0, st, bf, cs, c->tiles_plain_d);
+  if (cs.mesh == MESH_FLUID)
+    hipLaunchKernelGGL(k_wfluid<B>, gp, dim3(B), 0, st, bf, cs, c->tiles_plain_d);
+  hipLaunchKernelGGL(k_boundary, dim3(1), dim3(1024), 0, st, bf, cs, 0, c->nactive_d);
+}
+
+GraphKey make_key(const Bufs& bf, const Consts& cs, int B, const alew_ctx* c) {
+  GraphKey k;
+  auto put = [&](const void* p, size_t n) {
+    const char* q = (const char*)p;
+    k.bytes.insert(k.bytes.end(), q, q + n);
+  };
+  put(&bf, sizeof(bf));
+  put(&cs, sizeof(cs));
+  put(&B, sizeof(B));
+  put(&c->n_tiles_stage, sizeof(int64_t));
+  put(&c->n_tiles_plain, sizeof(int64_t));
+  return k;
+}
+
+template <int B>
+alew_status run_stage_engine(alew_ctx* c, const Bufs& bf, const Consts& cs, int64_t max_iters) {
+  const bool use_graph = c->launch.use_graph != 0;
+  const int check_every = 8;  // 2-step graphs between host checks
+  if (use_graph) {
+    GraphKey key = make_key(bf, cs, B, c);
+    if (!c->gexec || !(key == c->gkey)) {
+      if (c->gexec) { (void)hipGraphExecDestroy(c->gexec); c->gexec = nullptr; }
+      if (c->graph) { (void)hipGraphDestroy(c->graph); c->graph = nullptr; }
+      HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+      launch_step_seq<B>(c, bf, cs, c->cap_stream);
+      launch_step_seq<B>(c, bf, cs, c->cap_stream);
+      HIPCHK(hipStreamEndCapture(c->cap_stream, &c->graph));
+      HIPCHK(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+      c->gkey = key;
+    }
+  }
+  int64_t it = 0;
+  while (it < max_iters) {
+    for (int k = 0; k < check_every && it < max_iters; ++k) {
+      if (use_graph) {
+        HIPCHK(hipGraphLaunch(c->gexec, c->stream));
+        it += 2;
+      } else {
+        launch_step_seq<B>(c, bf, cs, c->stream);
+        it += 1;
+      }
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(c->nactive_h, c->nactive_d, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (*c->nactive_h == 0) break;
+  }
+  return ALEW_OK;
+}
+
+template <int B>
+alew_status run_persistent(alew_ctx* c, const Bufs& bf, const Consts& cs, int64_t ninst) {
+  int dev = 0, ncu = 0, per_cu = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<B>, B, 0));
+  int64_t grid = (int64_t)std::max(1, ncu) * std::max(1, per_cu);
+  grid = std::min<int64_t>(grid, ninst);
+  const int limit = c->launch.steps_per_launch;
+  for (;;) {
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, c->stream, c->queue_d);
+    hipLaunchKernelGGL(k_persistent<B>, dim3((unsigned)grid), dim3(B), 0, c->stream, bf, cs,
+                       c->order_d, c->queue_d, limit);
+    HIPCHK(hipGetLastError());
+    if (limit <= 0) break;
+    hipLaunchKernelGGL(k_count_active, dim3(1), dim3(1024), 0, c->stream, bf, c->nactive_d);
+    HIPCHK(hipMemcpyAsync(c->nactive_h, c->nactive_d, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (*c->nactive_h == 0) break;
+  }
+  return ALEW_OK;
+}
+
+alew_status map_status(int bits) {
+  if (bits & SB_MESH) return ALEW_E_MESH;
+  if (bits & SB_NONFINITE) return ALEW_E_NONFINITE;
+  if (bits & SB_NEGDEPTH) return ALEW_E_NEGDEPTH;
+  if (bits & SB_NEGWEIGHT) return ALEW_E_NEGWEIGHT;
+  return ALEW_OK;
+}
+
+// Shared driver of alew_step and alew_run.
+alew_status drive(alew_ctx* c, const alew_params* p, int64_t ninst, const int64_t* cell_off,
+                  double* h, double* hu, double* b, double* x, const double* xi,
+                  const double* wgiven, const double* t0, const double* t_end,
+                  const int64_t* max_steps, const double* dts, double* dt_log, int64_t dts_stride,
+                  uint8_t* cls, alew_stats* stats, int engine) {
+  alew_status ps = check_params(p);
+  if (ps != ALEW_OK) return ps;
+  if (!c) return fail(ALEW_E_ARG, "ctx is NULL");
+  if (ninst <= 0 || !cell_off) return fail(ALEW_E_ARG, "ninst <= 0 or cell_off is NULL");
+  if (ninst > c->max_inst) return fail(ALEW_E_ARG, "ninst exceeds the context capacity");
+  if (!h || !hu || !b || !x) return fail(ALEW_E_ARG, "state or node array is NULL");
+  if ((p->mesh == ALEW_MESH_SINE || p->mesh == ALEW_MESH_PAPER) && !xi)
+    return fail(ALEW_E_ARG, "xi is required for the prescribed mesh");
+  if (p->mesh == ALEW_MESH_GIVEN && !wgiven) return fail(ALEW_E_ARG, "w is required for MESH_GIVEN");
+  if (cell_off[0] != 0) return fail(ALEW_E_ARG, "cell_off[0] must be 0");
+  for (int64_t i = 0; i < ninst; ++i)
+    if (cell_off[i + 1] - cell_off[i] < 5) return fail(ALEW_E_ARG, "every instance needs >= 5 cells");
+  const int64_t S = cell_off[ninst];
+  if (S > c->max_cells) return fail(ALEW_E_ARG, "total cells exceed the context capacity");
+  if ((dts || dt_log) && dts_stride <= 0) return fail(ALEW_E_ARG, "dts_stride must be > 0");
+  const int B = pick_block(c);
+  alew_status ts = build_tiles(c, cell_off, ninst, B);
+  if (ts != ALEW_OK) return ts;
+  // per-instance scalars
+  int64_t max_iters = 0;
+  for (int64_t i = 0; i < ninst; ++i) {
+    Inst& I = c->inst_h[i];
+    std::memset(&I, 0, sizeof(Inst));
+    I.t0 = t0 ? t0[i] : 0.0;
+    I.t = I.t0;
+    I.t_end = t_end ? t_end[i] : 0.0;
+    I.max_steps = max_steps ? max_steps[i] : 0;
+    I.active = 1;
+    I.dt_min = INFINITY;
+    I.dt_max = 0.0;
+    I.r_minJ = 0x7ff0000000000000ull;  // +inf
+    I.r_hmin = 0xffffffffffffffffull;
+    if (I.max_steps > 0) max_iters = std::max(max_iters, I.max_steps);
+    else if (I.t_end > I.t0) max_iters = std::max<int64_t>(max_iters, INT64_MAX / 4);
+  }
+  HIPCHK(hipMemcpyAsync(c->inst, c->inst_h, ninst * sizeof(Inst), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(c->xa, x, (S + ninst) * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  Bufs bf = make_bufs(c, S, ninst, hu, b, xi, cls, dts, dt_log, dts_stride);
+  const Consts cs = make_consts(p);
+  const dim3 gp((unsigned)c->n_tiles_plain);
+#define ALEW_DISPATCH(BB)                                                                       \
+  do {                                                                                          \
+    hipLaunchKernelGGL(k_prep<BB>, gp, dim3(BB), 0, c->stream, bf, cs, c->tiles_plain_d, h, wgiven); \
+    if (cs.mesh == MESH_FLUID)                                                                  \
+      hipLaunchKernelGGL(k_wfluid<BB>, gp, dim3(BB), 0, c->stream, bf, cs, c->tiles_plain_d);  \
+    hipLaunchKernelGGL(k_boundary, dim3(1), dim3(1024), 0, c->stream, bf, cs, 1, c->nactive_d); \
+    HIPCHK(hipGetLastError());                                                                  \
+    alew_status rs = (engine == 1) ? run_persistent<BB>(c, bf, cs, ninst)                       \
+                                   : run_stage_engine<BB>(c, bf, cs, max_iters);                \
+    if (rs != ALEW_OK) return rs;                                                               \
+    hipLaunchKernelGGL(k_finish<BB>, gp, dim3(BB), 0, c->stream, bf, cs, c->tiles_plain_d, h, x); \
+  } while (0)
+  if (B == 128) ALEW_DISPATCH(128);
+  else if (B == 512) ALEW_DISPATCH(512);
+  else ALEW_DISPATCH(256);
+#undef ALEW_DISPATCH
+  HIPCHK(hipGetLastError());
+  // statistics and status
+  HIPCHK(hipMemcpyAsync(c->inst_h, c->inst, ninst * sizeof(Inst), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  alew_status worst = ALEW_OK;
+  for (int64_t i = 0; i < ninst; ++i) {
+    const Inst& I = c->inst_h[i];
+    const alew_status si = map_status(I.status);
+    if (si != ALEW_OK && (worst == ALEW_OK || worst == ALEW_E_NEGWEIGHT)) worst = si;
+    if (stats) {
+      alew_stats& S_ = stats[i];
+      std::memset(&S_, 0, sizeof(S_));
+      S_.steps = I.steps;
+      for (int k = 0; k < 3; ++k) S_.n_class[k] = (int64_t)I.n_class[k];
+      S_.n_limited = (int64_t)I.n_limited;
+      S_.n_negweight = (int64_t)I.n_negweight;
+      S_.t = I.t;
+      S_.dt_min = I.dt_min;
+      S_.dt_max = I.dt_max;
+      unsigned long long k = I.r_hmin;
+      unsigned long long u = (k & 0x8000000000000000ull) ? (k & 0x7fffffffffffffffull) : ~k;
+      double hm;
+      std::memcpy(&hm, &u, sizeof(hm));
+      S_.h_min = hm;
+      S_.mass_eta0 = I.mass_eta0;
+      S_.mass_eta = I.mass_eta;
+      S_.mass_b0 = I.mass_b0;
+      S_.mass_b = I.mass_b;
+      S_.status = (int32_t)si;
+    }
+  }
+  if (worst != ALEW_OK) {
+    char buf[128];
+    std::snprintf(buf, sizeof buf, "device reported status %d", (int)worst);
+    g_err = buf;
+  }
+  return worst;
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+extern "C" {
+
+const char* alew_last_error(void) { return g_err.c_str(); }
+const char* alew_version(void) { return "alew 0.1 gfx950 fp64"; }
+
+alew_status alew_create(alew_ctx** out, int64_t max_cells, int64_t max_inst, void* hip_stream) {
+  if (!out) return fail(ALEW_E_ARG, "ctx output pointer is NULL");
+  *out = nullptr;
+  if (max_cells < 5 || max_inst < 1) return fail(ALEW_E_ARG, "max_cells >= 5 and max_inst >= 1 required");
+  alew_ctx* c = new alew_ctx();
+  c->stream = (hipStream_t)hip_stream;
+  c->max_cells = max_cells;
+  c->max_inst = max_inst;
+  const int64_t S = max_cells, Nn = max_cells + max_inst;
+  auto alloc = [&](void** p, size_t bytes) -> bool { return hipMalloc(p, bytes) == hipSuccess; };
+  bool ok = alloc((void**)&c->eta, S * 8) && alloc((void**)&c->P0, 3 * S * 8) &&
+            alloc((void**)&c->D0, 3 * S * 8) && alloc((void**)&c->P1, 3 * S * 8) &&
+            alloc((void**)&c->D1, 3 * S * 8) && alloc((void**)&c->w, Nn * 8) &&
+            alloc((void**)&c->xa, Nn * 8) && alloc((void**)&c->xb, Nn * 8) &&
+            alloc((void**)&c->inst, max_inst * sizeof(Inst)) &&
+            alloc((void**)&c->cell_off_d, (max_inst + 1) * sizeof(int64_t)) &&
+            alloc((void**)&c->order_d, max_inst * sizeof(int32_t)) &&
+            alloc((void**)&c->queue_d, sizeof(unsigned)) && alloc((void**)&c->nactive_d, sizeof(int)) &&
+            alloc((void**)&c->dt1_d, sizeof(double));
+  ok = ok && hipHostMalloc((void**)&c->dt1_h, sizeof(double), hipHostMallocDefault) == hipSuccess;
+  ok = ok && hipHostMalloc((void**)&c->inst_h, max_inst * sizeof(Inst), hipHostMallocDefault) == hipSuccess;
+  ok = ok && hipHostMalloc((void**)&c->nactive_h, sizeof(int), hipHostMallocDefault) == hipSuccess;
+  ok = ok && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) == hipSuccess;
+  if (!ok) {
+    alew_destroy(c);
+    return fail(ALEW_E_NOMEM, "device allocation failed");
+  }
+  *out = c;
+  return ALEW_OK;
+}
+
+void alew_destroy(alew_ctx* c) {
+  if (!c) return;
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  void* ps[] = {c->eta, c->P0, c->D0, c->P1, c->D1, c->w, c->xa, c->xb, c->inst, c->cell_off_d,
+                c->order_d, c->queue_d, c->nactive_d, c->tiles_stage_d, c->tiles_plain_d, c->dt1_d};
+  for (void* p : ps)
+    if (p) (void)hipFree(p);
+  if (c->inst_h) (void)hipHostFree(c->inst_h);
+  if (c->dt1_h) (void)hipHostFree(c->dt1_h);
+  if (c->nactive_h) (void)hipHostFree(c->nactive_h);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  delete c;
+}
+
+alew_status alew_set_stream(alew_ctx* c, void* s) {
+  if (!c) return fail(ALEW_E_ARG, "ctx is NULL");
+  c->stream = (hipStream_t)s;
+  return ALEW_OK;
+}
+
+alew_status alew_set_launch(alew_ctx* c, const alew_launch* l) {
+  if (!c || !l) return fail(ALEW_E_ARG, "ctx or launch is NULL");
+  if (l->engine < 0 || l->engine > 2) return fail(ALEW_E_ARG, "unknown engine");
+  if (l->block != 0 && l->block != 128 && l->block != 256 && l->block != 512)
+    return fail(ALEW_E_ARG, "block must be 0, 128, 256 or 512");
+  c->launch = *l;
+  if (c->cached_B != pick_block(c)) c->cell_off_h.clear();
+  return ALEW_OK;
+}
+
+alew_status alew_get_launch(const alew_ctx* c, alew_launch* l) {
+  if (!c || !l) return fail(ALEW_E_ARG, "ctx or launch is NULL");
+  *l = c->launch;
+  return ALEW_OK;
+}
+
+alew_status alew_step(alew_ctx* c, const alew_params* p, int64_t ncell, double* h, double* hu,
+                      double* b, double* x, const double* xi, const double* w, double t, double dt,
+                      double t_end, uint8_t* cls, alew_stats* stats) {
+  if (!c) return fail(ALEW_E_ARG, "ctx is NULL");
+  if (ncell < 5) return fail(ALEW_E_ARG, "ncell must be >= 5");
+  const int64_t off[2] = {0, ncell};
+  const int64_t one = 1;
+  const double tend = t_end;
+  const double* dts = nullptr;
+  if (dt > 0) {
+    HIPCHK(hipStreamSynchronize(c->stream));  // the staging buffer may still be in use
+    *c->dt1_h = dt;
+    HIPCHK(hipMemcpyAsync(c->dt1_d, c->dt1_h, sizeof(double), hipMemcpyHostToDevice, c->stream));
+    dts = c->dt1_d;
+  }
+  const alew_launch keep = c->launch;
+  c->launch.engine = 2;
+  c->launch.use_graph = 0;
+  alew_stats st;
+  alew_status r = drive(c, p, 1, off, h, hu, b, x, xi, w, &t, &tend, &one, dts, nullptr,
+                        dts ? 1 : 0, cls, &st, 2);
+  c->launch = keep;
+  if (stats) *stats = st;
+  return r;
+}
+
+alew_status alew_run(alew_ctx* c, const alew_params* p, int64_t ninst, const int64_t* cell_off,
+                     double* h, double* hu, double* b, double* x, const double* xi,
+                     const double* t0, const double* t_end, const int64_t* max_steps,
+                     const double* dts, double* dt_log, int64_t dts_stride, alew_stats* stats) {
+  if (p && p->mesh == ALEW_MESH_GIVEN) return fail(ALEW_E_UNSUPPORTED, "alew_run needs a SINE, PAPER or FLUID mesh");
+  if (!c) return fail(ALEW_E_ARG, "ctx is NULL");
+  int engine = c->launch.engine;
+  if (engine == 0) engine = ninst >= 64 ? 1 : 2;
+  std::vector<alew_stats> tmp;
+  if (!stats) { tmp.resize(ninst > 0 ? ninst : 1); stats = tmp.data(); }
+  return drive(c, p, ninst, cell_off, h, hu, b, x, xi, nullptr, t0, t_end, max_steps, dts, dt_log,
+               dts_stride, nullptr, stats, engine);
+}
+
+alew_status alew_adjoint(alew_ctx* c, const alew_params* p, int64_t ninst,
+                         const int64_t* cell_off, const double* h0, const double* hu0,
+                         const double* b0, const double* x0, const double* xi, int64_t nsteps,
+                         const double* dts, int64_t ckpt_every, int64_t ngauge,
+                         const double* gauge_x, double* gauge_h, const double* gauge_bar,
+                         double* dh0, double* dhu0, double* db0) {
+  (void)c; (void)p; (void)ninst; (void)cell_off; (void)h0; (void)hu0; (void)b0; (void)x0;
+  (void)xi; (void)nsteps; (void)dts; (void)ckpt_every; (void)ngauge; (void)gauge_x;
+  (void)gauge_h; (void)gauge_bar; (void)dh0; (void)dhu0; (void)db0;
+  return fail(ALEW_E_UNSUPPORTED, "adjoint not built yet");
+}
+
+}  // extern "C"

@@ -1,0 +1,395 @@
+// Device building blocks of the FP64 ALE-WENO stage for gfx950.
+//
+// Layout: every per-cell quantity is a plain FP64 array (SoA).  A work-group of
+// B threads handles a tile of B-2 consecutive cells of one instance: it stages
+// the B+4 cells of the stencils (3 halo cells each side) in LDS, reconstructs
+// the B cells c0-1 .. c0+B-2 (one per thread), exchanges the limited traces
+// through LDS, evaluates the B-1 interface fluxes, and updates the B-2 owned
+// cells.  The global Lax-Friedrichs speed of the stage (eq. (3.13)) is not
+// known until every trace of the instance exists, so the update is split as
+// RHS = A + alpha * D: the stage writes
+//     P = a_s Q^n + b_s (J^(s-1) q^(s-1) + dt A)   and   D,
+// and the next stage (or the step epilogue) forms Q^(s) = P + b_s dt alpha D
+// while loading.  No MFMA: nothing here is a dense contraction.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace alew_dev {
+
+enum { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1, BC_REFLECTIVE = 2 };
+enum { MESH_GIVEN = 0, MESH_SINE = 1, MESH_PAPER = 2, MESH_FLUID = 3 };
+enum { F_BETA_LOCAL = 1, F_BETA_FROM_H = 2 };
+// status bits (combined per instance; mapped to alew_status on the host)
+enum { SB_MESH = 1, SB_NEGDEPTH = 2, SB_NONFINITE = 4, SB_NEGWEIGHT = 8 };
+
+struct Consts {
+  double g, cfl, weno_eps, pp_eps;
+  double mesh_A, mesh_k, mesh_omega, dry_eps;
+  int32_t bc, mesh, flags, pad;
+};
+
+// Per-instance scalars.  Reduction slots hold IEEE bit patterns so that
+// integer atomics give order-independent max/min.
+struct Inst {
+  double t, t0, t_end, dt;
+  double alpha[3];  // LF speed of stages 1..3
+  double dx[3];     // Dx of the indicators at stages 1..3
+  double smax;      // max_i |S(xi_i)| of the prescribed map
+  double dt_min, dt_max;
+  double mass_eta0, mass_b0, mass_eta, mass_b;
+  int64_t steps, max_steps;
+  int32_t active, status;
+  unsigned long long r_speed, r_minJ, r_maxJ, r_W;  // for the next step size
+  unsigned long long r_alpha, r_maxJs;              // stage slots
+  unsigned long long r_hmin;                        // ordered key of min depth
+  unsigned long long n_class[3], n_limited, n_negweight;
+};
+
+// ----------------------------------------------------------------------------
+// order-independent atomics on doubles
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ unsigned long long dbits(double v) {
+  return (unsigned long long)__double_as_longlong(v);
+}
+__device__ __forceinline__ double bitsd(unsigned long long u) {
+  return __longlong_as_double((long long)u);
+}
+// total-order key for doubles of either sign (min via unsigned compare)
+__device__ __forceinline__ unsigned long long okey(double v) {
+  unsigned long long u = dbits(v);
+  return (u & 0x8000000000000000ull) ? ~u : (u | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double okey_inv(unsigned long long k) {
+  unsigned long long u = (k & 0x8000000000000000ull) ? (k & 0x7fffffffffffffffull) : ~k;
+  return bitsd(u);
+}
+__device__ __forceinline__ void amax_pos(unsigned long long* p, double v) {
+  atomicMax(p, dbits(v));
+}
+__device__ __forceinline__ void amin_pos(unsigned long long* p, double v) {
+  atomicMin(p, dbits(v));
+}
+
+// ----------------------------------------------------------------------------
+// wave64 / work-group reductions (result in every thread)
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ unsigned wave_usum(unsigned v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Reduce NV values per thread across the work-group.  op[k]: 0 max, 1 min, 2 sum.
+template <int B, int NV>
+__device__ __forceinline__ void block_reduce(double (&v)[NV], const int (&op)[NV], double* red) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k)
+    v[k] = op[k] == 0 ? wave_max(v[k]) : (op[k] == 1 ? wave_min(v[k]) : wave_sum(v[k]));
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) red[wid * NV + k] = v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double r = red[k];
+    for (int q = 1; q < B / 64; ++q) {
+      double o = red[q * NV + k];
+      r = op[k] == 0 ? fmax(r, o) : (op[k] == 1 ? fmin(r, o) : r + o);
+    }
+    v[k] = r;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// boundary conditions (3 ghost cells per side)
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ int64_t ghost_src(int bc, int64_t n, int64_t k, double& msign) {
+  msign = 1.0;
+  if (k >= 0 && k < n) return k;
+  if (bc == BC_PERIODIC) {
+    int64_t r = k % n;
+    return r < 0 ? r + n : r;
+  }
+  if (bc == BC_TRANSMISSIVE) return k < 0 ? 0 : n - 1;
+  msign = -1.0;
+  return k < 0 ? -1 - k : 2 * n - 1 - k;
+}
+
+// ----------------------------------------------------------------------------
+// Reconstruction of one cell (Sec. 2.2, Steps 1-4 with eq. (2.10)).
+//
+// Geometry in the cell's own normalised coordinate y = (x - x_j)/Delta_j,
+// cell j = [-1/2, 1/2].  Each stencil quadratic is written as
+//   p_r(y) = ubar_j + B_r y + C_r (y^2 - 1/12)
+// (both basis functions have zero mean on cell j, so the average of cell j is
+// matched by construction); B_r, C_r come from the 2x2 system matching the
+// averages of the other two cells of the stencil.  The linear weights at each
+// evaluation point are the unique weights (summing to one) under which the
+// combination of the three quadratics also reproduces the cubic y^3 and the
+// quartic y^4 - 1/80: with e_r^(3), e_r^(4) the errors of stencil r on those two
+// functions, d is the normalised cross product e^(3) x e^(4).  That is the
+// 5-cell quartic condition of Step 1, in a form with 3x3 work per point.
+// ----------------------------------------------------------------------------
+struct CellRecon {
+  double hL, mL, bL, hR, mR, bR;  // unlimited traces
+  double rint;                    // sum_mu w_mu (eta_mu - etabar) b_x(x_mu) * Delta_j
+  int cls;
+  int negw;
+};
+
+__device__ __forceinline__ void moments(double a, double b, double& M1, double& M2, double& M3,
+                                        double& M4) {
+  const double a2 = a * a, b2 = b * b, ab = a * b;
+  M1 = 0.5 * (a + b);
+  M2 = (a2 + ab + b2) * (1.0 / 3.0) - (1.0 / 12.0);
+  M3 = 0.25 * (a + b) * (a2 + b2);
+  M4 = (a2 * a2 + a2 * ab + ab * ab + ab * b2 + b2 * b2) * 0.2 - 0.0125;
+}
+
+// e5: eta (or h under F_BETA_FROM_H: chosen by the caller via v5), stencil
+// order cells j-2..j+2.
+__device__ __forceinline__ void recon_cell(const double* __restrict__ v5,  // indicator var
+                                           const double* __restrict__ h5,
+                                           const double* __restrict__ m5,
+                                           const double* __restrict__ b5,
+                                           const double* __restrict__ J5, double Dx, double eps,
+                                           double etabar, CellRecon& o) {
+  const double J0 = J5[2];
+  const double iJ0 = 1.0 / J0;
+  // cell edges of the big stencil in y
+  const double em1 = -0.5 - J5[1] * iJ0;
+  const double em2 = em1 - J5[0] * iJ0;
+  const double ep1 = 0.5 + J5[3] * iJ0;
+  const double ep2 = ep1 + J5[4] * iJ0;
+  double M1[4], M2[4], M3[4], M4[4];  // cells j-2, j-1, j+1, j+2
+  moments(em2, em1, M1[0], M2[0], M3[0], M4[0]);
+  moments(em1, -0.5, M1[1], M2[1], M3[1], M4[1]);
+  moments(0.5, ep1, M1[2], M2[2], M3[2], M4[2]);
+  moments(ep1, ep2, M1[3], M2[3], M3[3], M4[3]);
+  // stencil r uses neighbour slots (c1, c2): r=0 -> (j+1, j+2), r=1 -> (j-1, j+1),
+  // r=2 -> (j-2, j-1)
+  const int C1[3] = {2, 1, 0}, C2[3] = {3, 2, 1};
+  double kb1[3], kb2[3], kc1[3], kc2[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const int c1 = C1[r], c2 = C2[r];
+    const double idet = 1.0 / (M1[c1] * M2[c2] - M1[c2] * M2[c1]);
+    kb1[r] = M2[c2] * idet;
+    kb2[r] = -M2[c1] * idet;
+    kc1[r] = -M1[c2] * idet;
+    kc2[r] = M1[c1] * idet;
+  }
+  // linear weights at the 4 Gauss-Lobatto points y = -1/2, -q, q, 1/2
+  const double q = 0.22360679774997896964;       // sqrt(5)/10
+  const double q3 = 0.011180339887498948482;     // q^3
+  const double yv[4] = {-0.5, -q, q, 0.5};
+  const double p2v[4] = {1.0 / 6.0, -1.0 / 30.0, -1.0 / 30.0, 1.0 / 6.0};
+  const double f3v[4] = {-0.125, -q3, q3, 0.125};
+  const double f4v[4] = {0.05, -0.01, -0.01, 0.05};
+  double d[4][3];
+  int negw = 0;
+  {
+    double B3[3], C3[3], B4[3], C4[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const int c1 = C1[r], c2 = C2[r];
+      B3[r] = kb1[r] * M3[c1] + kb2[r] * M3[c2];
+      C3[r] = kc1[r] * M3[c1] + kc2[r] * M3[c2];
+      B4[r] = kb1[r] * M4[c1] + kb2[r] * M4[c2];
+      C4[r] = kc1[r] * M4[c1] + kc2[r] * M4[c2];
+    }
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+      double e3[3], e4[3];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        e3[r] = B3[r] * yv[mu] + C3[r] * p2v[mu] - f3v[mu];
+        e4[r] = B4[r] * yv[mu] + C4[r] * p2v[mu] - f4v[mu];
+      }
+      const double x0 = e3[1] * e4[2] - e3[2] * e4[1];
+      const double x1 = e3[2] * e4[0] - e3[0] * e4[2];
+      const double x2 = e3[0] * e4[1] - e3[1] * e4[0];
+      const double is = 1.0 / (x0 + x1 + x2);
+      d[mu][0] = x0 * is;
+      d[mu][1] = x1 * is;
+      d[mu][2] = x2 * is;
+      negw |= (d[mu][0] < 0.0) | (d[mu][1] < 0.0) | (d[mu][2] < 0.0);
+    }
+  }
+  // per-variable stencil coefficients
+  double dv[4], dh[4], dm[4], db[4];
+  {
+    const int idx[4] = {0, 1, 3, 4};
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      dv[c] = v5[idx[c]] - v5[2];
+      dh[c] = h5[idx[c]] - h5[2];
+      dm[c] = m5[idx[c]] - m5[2];
+      db[c] = b5[idx[c]] - b5[2];
+    }
+  }
+  double Bh[3], Ch[3], Bm[3], Cm[3], Bb[3], Cb[3], beta[3];
+  const double kap = Dx * iJ0;
+  const double kapC = kap * (1.0 / 3.0) + 4.0 * kap * kap * kap;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const int c1 = C1[r], c2 = C2[r];
+    const double Bv = kb1[r] * dv[c1] + kb2[r] * dv[c2];
+    const double Cv = kc1[r] * dv[c1] + kc2[r] * dv[c2];
+    Bh[r] = kb1[r] * dh[c1] + kb2[r] * dh[c2];
+    Ch[r] = kc1[r] * dh[c1] + kc2[r] * dh[c2];
+    Bm[r] = kb1[r] * dm[c1] + kb2[r] * dm[c2];
+    Cm[r] = kc1[r] * dm[c1] + kc2[r] * dm[c2];
+    Bb[r] = kb1[r] * db[c1] + kb2[r] * db[c2];
+    Cb[r] = kc1[r] * db[c1] + kc2[r] * db[c2];
+    // Dx int (p')^2 + Dx^3 int (p'')^2 over cell j, summed over the two equations
+    beta[r] = (kap * (Bv * Bv) + kapC * (Cv * Cv)) + (kap * (Bm[r] * Bm[r]) + kapC * (Cm[r] * Cm[r]));
+  }
+  // Step 2: detector
+  const double tau = fabs(beta[0] - beta[2]);
+  const double betaA = (beta[0] + beta[1] + beta[2]) / 3.0;
+  const double gam = tau / (betaA + eps);
+  const int cls = (gam <= 0.5) ? 0 : ((gam >= 1.0) ? 2 : 1);
+  double K[3];
+  if (cls != 0) {
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const double z = tau / (beta[r] + eps);
+      K[r] = 1.0 + z * z;
+    }
+  }
+  const double Mg = 2.0 * gam - 1.0;
+  // Steps 3-4 at the 4 points; values h, m, b (traces) and eta, b_x (source)
+  double hv[4], mv[4], bv[4], bxv[4];
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+    double ph[3];
+    if (cls == 0) {
+      ph[0] = d[mu][0];
+      ph[1] = d[mu][1];
+      ph[2] = d[mu][2];
+    } else {
+      const double a0 = d[mu][0] * K[0], a1 = d[mu][1] * K[1], a2 = d[mu][2] * K[2];
+      const double ia = 1.0 / (a0 + a1 + a2);
+      ph[0] = a0 * ia;
+      ph[1] = a1 * ia;
+      ph[2] = a2 * ia;
+      if (cls == 1) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) ph[r] = Mg * ph[r] + (1.0 - Mg) * d[mu][r];
+      }
+    }
+    const double y = yv[mu], p2 = p2v[mu];
+    double sBh = 0, sCh = 0, sBm = 0, sCm = 0, sBb = 0, sCb = 0;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      sBh += ph[r] * Bh[r];
+      sCh += ph[r] * Ch[r];
+      sBm += ph[r] * Bm[r];
+      sCm += ph[r] * Cm[r];
+      sBb += ph[r] * Bb[r];
+      sCb += ph[r] * Cb[r];
+    }
+    hv[mu] = h5[2] + (sBh * y + sCh * p2);
+    mv[mu] = m5[2] + (sBm * y + sCm * p2);
+    bv[mu] = b5[2] + (sBb * y + sCb * p2);
+    bxv[mu] = (sBb + 2.0 * y * sCb) * iJ0;
+  }
+  o.hL = hv[0]; o.mL = mv[0]; o.bL = bv[0];
+  o.hR = hv[3]; o.mR = mv[3]; o.bR = bv[3];
+  // interior Gauss-Lobatto quadrature of (eta - etabar) b_x, weights (1,5,5,1)/12
+  const double wgl[4] = {1.0 / 12.0, 5.0 / 12.0, 5.0 / 12.0, 1.0 / 12.0};
+  double ri = 0.0;
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) ri += (wgl[mu] * J0) * (((hv[mu] + bv[mu]) - etabar) * bxv[mu]);
+  o.rint = ri;
+  o.cls = cls;
+  o.negw = negw;
+}
+
+// ----------------------------------------------------------------------------
+// Positivity limiter, 1D form of eq. (3.20)-(3.21); bottom traces by Remark 4.1.
+// Returns 1 when the traces were modified.
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ int limit_cell(double hbar, double mbar, double pp_eps, CellRecon& o) {
+  if (hbar <= 0.0) {
+    const double eL = o.hL + o.bL, eR = o.hR + o.bR;
+    o.hL = hbar; o.hR = hbar;
+    o.mL = mbar; o.mR = mbar;
+    o.bL = eL - o.hL;
+    o.bR = eR - o.hR;
+    return 1;
+  }
+  const double s1 = 1.0 / 12.0;
+  const double delta = (hbar - s1 * o.hL - s1 * o.hR) / (1.0 - 2.0 * s1);
+  double mn = o.hL;
+  if (delta < mn) mn = delta;
+  if (o.hR < mn) mn = o.hR;
+  const double epsj = (pp_eps < hbar) ? pp_eps : hbar;
+  if (!(mn < epsj)) return 0;
+  double Phi = (hbar - epsj) / (hbar - mn);
+  if (Phi > 1.0) Phi = 1.0;
+  const double eL = o.hL + o.bL, eR = o.hR + o.bR;
+  o.hL = Phi * (o.hL - hbar) + hbar;
+  o.hR = Phi * (o.hR - hbar) + hbar;
+  o.mL = Phi * (o.mL - mbar) + mbar;
+  o.mR = Phi * (o.mR - mbar) + mbar;
+  o.bL = eL - o.hL;
+  o.bR = eR - o.hR;
+  return 1;
+}
+
+// ----------------------------------------------------------------------------
+// Interface flux pieces (eq. (3.13), (3.17), (4.9)) for left trace (cell i-1's
+// right trace) and right trace (cell i's left trace) at node speed w.
+// F_hat = Fc - alpha/2 * jump; the alpha part is applied later.
+// ----------------------------------------------------------------------------
+struct Face {
+  double Fc1, Fc2, Gc, je, jm, jb, B1, B2;
+  double speed;  // max over both traces of |u - w| + sqrt(g h)
+};
+
+__device__ __forceinline__ void face_flux(double hl, double ml, double bl, double hr, double mr,
+                                          double br, double w, double g, double dry, Face& f) {
+  const double el = hl + bl, er = hr + br;
+  double ul = 0.0, ur = 0.0;
+  if (hl > dry) ul = ml / hl; else ml = 0.0;
+  if (hr > dry) ur = mr / hr; else mr = 0.0;
+  const double Hl1 = ml - w * el;
+  const double Hl2 = ml * ul + 0.5 * g * hl * hl - w * ml;
+  const double Hr1 = mr - w * er;
+  const double Hr2 = mr * ur + 0.5 * g * hr * hr - w * mr;
+  f.Fc1 = 0.5 * (Hl1 + Hr1);
+  f.Fc2 = 0.5 * (Hl2 + Hr2);
+  f.Gc = -0.5 * w * (bl + br);
+  f.je = er - el;
+  f.jm = mr - ml;
+  f.jb = br - bl;
+  f.B1 = 0.5 * (bl + br);
+  f.B2 = 0.5 * (bl * bl + br * br);
+  const double sl = fabs(ul - w) + sqrt(g * fmax(hl, 0.0));
+  const double sr = fabs(ur - w) + sqrt(g * fmax(hr, 0.0));
+  f.speed = fmax(sl, sr);
+}
+
+}  // namespace alew_dev

@@ -1,0 +1,273 @@
+"""GPU path (through the C ABI) against the CPU oracle, element by element.
+
+Tolerance: 1e-11 relative L-inf in FP64 after the whole run (each field scaled
+by its own max magnitude, at least 1).  Detector classes are compared per cell,
+per stage, per step; flips are counted and must be zero on these cases.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2208_06588_amd import alew, workloads as W
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-11
+
+
+@pytest.fixture(scope="module")
+def dev():
+    torch.cuda.set_device(0)
+    return torch.device("cuda", 0)
+
+
+def _t(a, dev):
+    return torch.tensor(np.asarray(a), dtype=torch.float64, device=dev)
+
+
+def _gp(wl, **kw):
+    d = dict(bc=wl["bc"], mesh=wl["mesh"], mesh_A=wl["mesh_A"], mesh_k=wl["mesh_k"],
+             mesh_omega=wl["mesh_omega"], cfl=wl["cfl"], weno_eps=wl["weno_eps"])
+    d.update(kw)
+    return alew.params(**d)
+
+
+def _op(wl, **kw):
+    bc = dict(periodic=O.BC_PERIODIC, transmissive=O.BC_TRANSMISSIVE, reflective=O.BC_REFLECTIVE)
+    mesh = dict(given=O.MESH_GIVEN, sine=O.MESH_SINE, paper=O.MESH_PAPER, fluid=O.MESH_FLUID)
+    d = dict(bc=bc[wl["bc"]], mesh=mesh[wl["mesh"]], mesh_A=wl["mesh_A"], mesh_k=wl["mesh_k"],
+             mesh_omega=wl["mesh_omega"], cfl=wl["cfl"], weno_eps=wl["weno_eps"])
+    d.update(kw)
+    return O.params(**d)
+
+
+def _relerr(g, r):
+    g = np.asarray(g)
+    r = np.asarray(r)
+    return float(np.abs(g - r).max() / max(1.0, np.abs(r).max()))
+
+
+def _run_gpu(ctx, p, wl, dev, **kw):
+    n = len(wl["h"])
+    t = {k: _t(wl[k], dev) for k in ("h", "hu", "b", "x", "xi")}
+    st = ctx.run(p, [0, n], t["h"], t["hu"], t["b"], t["x"], t["xi"], **kw)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in t.items()}, st[0]
+
+
+def _assert_parity(g, r, fields=("h", "hu", "b", "x")):
+    for k in fields:
+        e = _relerr(g[k], r[k])
+        assert e <= TOL, (k, e)
+
+
+def test_periodic_smooth_full_run(dev):
+    """200 cells on periodic [0,1], sine mesh, CFL 0.6, to t = 0.1."""
+    wl = W.accuracy_1d(200)
+    ctx = alew.Context(200, 1)
+    ctx.set_launch(engine=alew.ENGINE_STAGES, block=256, use_graph=1)
+    g, st = _run_gpu(ctx, _gp(wl), wl, dev, t_end=[0.1])
+    r = O.run(_op(wl), wl["h"], wl["hu"], wl["b"], wl["x"], wl["xi"], t_end=0.1)
+    assert st.status == 0 and r["status"] == 0
+    assert st.steps == r["stats"].steps
+    assert abs(st.t - 0.1) < 1e-15
+    _assert_parity(g, r)
+    assert list(st.n_class) == list(r["stats"].n_class)
+    assert abs(st.mass_eta - st.mass_eta0) <= 1e-13 * st.mass_eta0
+
+
+def test_classes_per_cell_per_stage(dev):
+    """alew_step, one call per step with the CFL rule; classes of every cell at
+    every stage against the oracle's."""
+    wl = W.still_water_1d(200, "step")
+    wl["h"] = wl["h"] + 0.05 * np.exp(-((np.linspace(0, 10, 200) - 2.0) ** 2))  # moving pulse
+    nsteps = 30
+    p = _gp(wl)
+    ctx = alew.Context(200, 1)
+    t = {k: _t(wl[k], dev) for k in ("h", "hu", "b", "x", "xi")}
+    cls = torch.zeros(3 * 200, dtype=torch.uint8, device=dev)
+    tt = 0.0
+    got = []
+    for _ in range(nsteps):
+        st = ctx.step(p, t["h"], t["hu"], t["b"], t["x"], t["xi"], t=tt, t_end=wl["t_end"], cls=cls)
+        tt = st.t
+        got.append(cls.cpu().numpy().reshape(3, 200).copy())
+    r = O.run(_op(wl), wl["h"], wl["hu"], wl["b"], wl["x"], wl["xi"], t_end=wl["t_end"],
+              max_steps=nsteps, record_cls=True)
+    got = np.stack(got)
+    flips = int((got != r["cls"]).sum())
+    assert flips == 0, f"{flips} class flips"
+    assert (got == 2).any() and (got == 0).any()
+    g = {k: v.cpu().numpy() for k, v in t.items()}
+    _assert_parity(g, r)
+
+
+@pytest.mark.parametrize("bottom", ["smooth", "step"])
+def test_still_water_on_gpu(dev, bottom):
+    """Example 5.3 (Tables 5.4/5.5): exact to round-off on the GPU as well."""
+    wl = W.still_water_1d(200, bottom)
+    ctx = alew.Context(200, 1)
+    g, st = _run_gpu(ctx, _gp(wl), wl, dev, t_end=[0.5])
+    assert st.status == 0
+    assert np.abs(g["h"] + g["b"] - 10).max() < 1e-12
+    assert np.abs(g["hu"]).max() < 2e-12
+    r = O.run(_op(wl), wl["h"], wl["hu"], wl["b"], wl["x"], wl["xi"], t_end=0.5)
+    _assert_parity(g, r)
+
+
+def test_positivity_dry_bed(dev):
+    """Example 5.2, Moses's second problem: dry middle, CFL 0.08."""
+    wl = W.moses2_1d(200, t_end=1.0)
+    ctx = alew.Context(200, 1)
+    g, st = _run_gpu(ctx, _gp(wl), wl, dev, t_end=[1.0])
+    r = O.run(_op(wl), wl["h"], wl["hu"], wl["b"], wl["x"], wl["xi"], t_end=1.0)
+    assert st.status == 0 and st.n_limited > 0
+    assert st.h_min >= -1e-20
+    assert st.steps == r["stats"].steps
+    _assert_parity(g, r)
+
+
+def test_given_mesh_reflective_step(dev):
+    """alew_step with caller-given node speeds and reflective walls."""
+    n = 97
+    xi = W.uniform_nodes(n, 0.0, 1.0)
+    xc = 0.5 * (xi[1:] + xi[:-1])
+    h = 1.0 + 0.3 * np.exp(-100 * (xc - 0.3) ** 2)
+    b = 0.2 * np.sin(3 * xc) ** 2
+    hu = 0.1 * np.sin(2 * np.pi * xc)
+    w = 0.2 * np.sin(np.pi * xi)  # zero at both walls
+    p = alew.params(bc="reflective", mesh="given")
+    ctx = alew.Context(n, 1)
+    T = {k: _t(v, dev) for k, v in dict(h=h, hu=hu, b=b, x=xi, w=w).items()}
+    tt = 0.0
+    for _ in range(12):
+        st = ctx.step(p, T["h"], T["hu"], T["b"], T["x"], None, T["w"], t=tt)
+        tt = st.t
+    r = O.run(O.params(bc=O.BC_REFLECTIVE, mesh=O.MESH_GIVEN), h, hu, b, xi, w=w, max_steps=12)
+    g = {k: v.cpu().numpy() for k, v in T.items()}
+    assert abs(tt - r["t"]) <= 1e-15
+    _assert_parity(g, r)
+
+
+def _small_batch(seed=5, ninst=6):
+    rng = np.random.default_rng(seed)
+    ns = rng.integers(40, 400, ninst)
+    eps = rng.uniform(1e-5, 1e-2, ninst)
+    insts = [W.perturbation_instance(int(n), float(e)) for n, e in zip(ns, eps)]
+    return W.pack(insts, bc="transmissive", t_end=0.2, cfl=0.6, weno_eps=1e-9, mesh="sine",
+                  mesh_A=0.05, mesh_k=1.0, mesh_omega=math.pi)
+
+
+def test_batched_engines_bitwise_and_oracle(dev):
+    """Ragged batch: the persistent engine and the stage-launch engine (three
+    block sizes) give bitwise identical results; each instance matches the
+    oracle run on its own."""
+    bt = _small_batch()
+    off = bt["cell_off"]
+    n = int(off[-1])
+    ninst = len(off) - 1
+    p = _gp(bt)
+    nsteps = 25
+    outs = []
+    for engine, block in ((alew.ENGINE_PERSISTENT, 256), (alew.ENGINE_STAGES, 128),
+                          (alew.ENGINE_STAGES, 256), (alew.ENGINE_STAGES, 512),
+                          (alew.ENGINE_PERSISTENT, 128)):
+        ctx = alew.Context(n, ninst)
+        ctx.set_launch(engine=engine, block=block, use_graph=1)
+        T = {k: _t(bt[k], dev) for k in ("h", "hu", "b", "x", "xi")}
+        st = ctx.run(p, off, T["h"], T["hu"], T["b"], T["x"], T["xi"], max_steps=[nsteps] * ninst)
+        torch.cuda.synchronize()
+        outs.append(({k: v.cpu().numpy() for k, v in T.items()}, st))
+    ref = outs[0][0]
+    for o, st in outs[1:]:
+        for k in ("h", "hu", "b", "x"):
+            assert np.array_equal(o[k], ref[k]), k
+    for i in range(ninst):
+        a, e = int(off[i]), int(off[i + 1])
+        r = O.run(_op(bt), bt["h"][a:e], bt["hu"][a:e], bt["b"][a:e], bt["x"][a + i:e + i + 1],
+                  bt["xi"][a + i:e + i + 1], max_steps=nsteps)
+        g = dict(h=ref["h"][a:e], hu=ref["hu"][a:e], b=ref["b"][a:e], x=ref["x"][a + i:e + i + 1])
+        _assert_parity(g, r)
+        assert outs[0][1][i].steps == nsteps
+
+
+def test_batched_to_t_end_matches_per_instance(dev):
+    """Instances of different sizes run to the same end time with their own
+    step sizes in one call; each equals a one-instance call."""
+    bt = _small_batch(seed=9, ninst=4)
+    off = bt["cell_off"]
+    n = int(off[-1])
+    ninst = len(off) - 1
+    p = _gp(bt)
+    T_end = 0.02
+    ctx = alew.Context(n, ninst)
+    ctx.set_launch(engine=alew.ENGINE_PERSISTENT, block=256)
+    T = {k: _t(bt[k], dev) for k in ("h", "hu", "b", "x", "xi")}
+    st = ctx.run(p, off, T["h"], T["hu"], T["b"], T["x"], T["xi"], t_end=[T_end] * ninst)
+    torch.cuda.synchronize()
+    for i in range(ninst):
+        a, e = int(off[i]), int(off[i + 1])
+        one = {k: _t(bt[k][a:e], dev) for k in ("h", "hu", "b")}
+        one["x"] = _t(bt["x"][a + i:e + i + 1], dev)
+        one["xi"] = _t(bt["xi"][a + i:e + i + 1], dev)
+        c1 = alew.Context(e - a, 1)
+        s1 = c1.run(p, [0, e - a], one["h"], one["hu"], one["b"], one["x"], one["xi"],
+                    t_end=[T_end])[0]
+        assert s1.steps == st[i].steps and abs(st[i].t - T_end) < 1e-15
+        for k in ("h", "hu", "b"):
+            assert np.array_equal(one[k].cpu().numpy(), T[k][a:e].cpu().numpy()), (i, k)
+
+
+def test_fluid_mesh_wet_dry_bowl(dev):
+    """1D parabolic bowl (wet/dry, fluid-following mesh, CFL 0.08) at 2048 cells."""
+    wl = W.bowl_1d(2048)
+    ctx = alew.Context(2048, 1)
+    g, st = _run_gpu(ctx, _gp(wl), wl, dev, max_steps=[30])
+    r = O.run(_op(wl), wl["h"], wl["hu"], wl["b"], wl["x"], wl["xi"], max_steps=30)
+    assert st.status == 0 and r["status"] == 0
+    assert st.n_limited > 0
+    assert g["h"].min() >= -1e-20
+    _assert_parity(g, r)
+
+
+def test_frozen_steps_reproduce_run(dev):
+    """dt_log of a CFL run fed back as frozen step sizes gives the same result."""
+    bt = _small_batch(seed=3, ninst=3)
+    off = bt["cell_off"]
+    n = int(off[-1])
+    ninst = len(off) - 1
+    p = _gp(bt)
+    ns = 10
+    ctx = alew.Context(n, ninst)
+    T1 = {k: _t(bt[k], dev) for k in ("h", "hu", "b", "x", "xi")}
+    log = torch.zeros(ninst * ns, dtype=torch.float64, device=dev)
+    ctx.run(p, off, T1["h"], T1["hu"], T1["b"], T1["x"], T1["xi"], max_steps=[ns] * ninst,
+            dt_log=log, dts_stride=ns)
+    T2 = {k: _t(bt[k], dev) for k in ("h", "hu", "b", "x", "xi")}
+    ctx.run(p, off, T2["h"], T2["hu"], T2["b"], T2["x"], T2["xi"], max_steps=[ns] * ninst,
+            dts=log, dts_stride=ns)
+    torch.cuda.synchronize()
+    assert (log > 0).all()
+    for k in ("h", "hu", "b", "x"):
+        assert torch.equal(T1[k], T2[k]), k
+
+
+def test_device_errors_are_reported(dev):
+    """Errors forced from the host through the inputs: a tangled mesh and a NaN."""
+    wl = W.accuracy_1d(64)
+    ctx = alew.Context(64, 1)
+    p = _gp(wl)
+    x = wl["x"].copy()
+    x[10], x[11] = x[11], x[10]  # cell 10 has negative width
+    T = {k: _t(v, dev) for k, v in dict(h=wl["h"], hu=wl["hu"], b=wl["b"], x=x, xi=wl["xi"]).items()}
+    st = ctx.run(p, [0, 64], T["h"], T["hu"], T["b"], T["x"], T["xi"], max_steps=[3], check=False)
+    assert st[0].status == alew.E_MESH
+    h = wl["h"].copy()
+    h[5] = np.nan
+    T = {k: _t(v, dev) for k, v in dict(h=h, hu=wl["hu"], b=wl["b"], x=wl["x"], xi=wl["xi"]).items()}
+    st = ctx.run(p, [0, 64], T["h"], T["hu"], T["b"], T["x"], T["xi"], max_steps=[3], check=False)
+    assert st[0].status == alew.E_NONFINITE
+    with pytest.raises(alew.AlewError):
+        ctx.run(p, [0, 3], T["h"], T["hu"], T["b"], T["x"], T["xi"], max_steps=[1])

@@ -1,0 +1,226 @@
+#!/usr/bin/env python3
+"""Throughput of the batched FP64 ALE-WENO forward run on one MI355X.
+
+Workload: ragged batch of 4096 independent 1D perturbation-of-still-water
+instances (LeVeque bump, Example 5.4 shape), cell counts uniform in
+[1000, 20000] from seed 2208065881 (43,017,136 cells), transmissive
+boundaries, sine-moving mesh, CFL 0.6, each instance with its own CFL step.
+A benchmark "step" advances every instance by one SSP-RK3 time step (three
+stages).  Throughput = cells x stages / second over exactly --steps steps
+timed after --warmup untimed steps, inputs resident in HBM.
+
+Prints one JSON line (roofline of the dominant kernel, CPU oracle baseline,
+batched-vs-per-instance speedup).  --gpus N with N > 1 exits: one GPU only.
+"""
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cell-updates/s per RK stage (FP64) + %HBM roofline; adjoint/forward time ratio"
+HBM_PEAK_GBS = 8000.0
+# Algorithmic HBM bytes per cell and time step (FP64 SoA): stage 1 reads q^n, J^n,
+# x^n and writes q^(1) (64 B); stage 2 also reads the base state (88 B); stage 3
+# writes q^{n+1}, J^{n+1}, x^{n+1} (104 B).
+ALG_BYTES_PER_CELL_STEP = 256.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_hash():
+    h = hashlib.sha1()
+    for f in ("alew.hip", "alew_device.h", "alew_kernels.h"):
+        with open(os.path.join(ROOT, "paper_2208_06588_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel):
+    """HBM bytes per launch measured with rocprofv3 counters for this source
+    (profiles/traffic.json), or None when the kernel changed since."""
+    try:
+        with open(os.path.join(ROOT, "profiles", "traffic.json")) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    e = d.get(kernel)
+    if not e or e.get("source_hash") != source_hash():
+        return None
+    return e.get("bytes_per_cell_step")
+
+
+def cpu_baseline(bt, ninst_sample, steps):
+    """The oracle on the host cores: first ninst_sample instances of the same
+    draw, `steps` CFL steps each, one instance per thread."""
+    import oracle as O
+    off = bt["cell_off"]
+    P = O.params(bc=O.BC_TRANSMISSIVE, mesh=O.MESH_SINE, mesh_A=0.05, mesh_k=1.0,
+                 mesh_omega=np.pi, cfl=0.6, weno_eps=1e-9)
+    O.lib()
+    cores = min(16, os.cpu_count() or 1)
+
+    def one(i):
+        a, e = int(off[i]), int(off[i + 1])
+        r = O.run(P, bt["h"][a:e], bt["hu"][a:e], bt["b"][a:e], bt["x"][a + i:e + i + 1],
+                  bt["xi"][a + i:e + i + 1], max_steps=steps)
+        return (e - a) * 3 * r["stats"].steps
+
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=cores) as ex:
+        work = sum(ex.map(one, range(ninst_sample)))
+    wall = time.perf_counter() - t0
+    ncell = int(off[ninst_sample])
+    return dict(value=work / wall, unit="cell-updates/s", cores=cores, kind="oracle",
+                sample=f"first {ninst_sample} instances of the same draw ({ncell} cells), "
+                       f"{steps} CFL steps each, one instance per thread; {wall:.1f} s wall")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--engine", default="tune", choices=["tune", "persistent", "stages"])
+    ap.add_argument("--block", type=int, default=256)
+    ap.add_argument("--ninst", type=int, default=4096)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-inst", type=int, default=64)
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--no-speedup", action="store_true",
+                    help="skip the batched vs per-instance comparison")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="first copy a buffer of this many MiB (calibrates profiler byte counters)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: the batched instances are independent and this "
+              "build measures one GPU's share; use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2208_06588_amd import alew, autotune, workloads as W
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    if args.copy_probe > 0:
+        n = args.copy_probe * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copy probe: {n * 8} bytes read, {n * 8} bytes written")
+        del a, b
+    t0 = time.perf_counter()
+    bt = W.perturbation_batch(ninst=args.ninst) if args.ninst == 4096 else \
+        W.perturbation_batch(subset=args.ninst)
+    off = [int(v) for v in bt["cell_off"]]
+    ninst = len(off) - 1
+    S = off[-1]
+    log(f"workload: {ninst} instances, {S} cells ({time.perf_counter() - t0:.1f} s to build)")
+    p = alew.params(bc="transmissive", mesh="sine", mesh_A=0.05, mesh_k=1.0, mesh_omega=np.pi,
+                    cfl=0.6, weno_eps=1e-9)
+    T = {k: torch.tensor(bt[k], dtype=torch.float64, device=dev) for k in ("h", "hu", "b", "x", "xi")}
+    ctx = alew.Context(S, ninst)
+
+    if args.engine == "tune":
+        best, times = autotune.tune(ctx, p, off, T, steps=2, use_cache=False, log=log)
+        log(f"autotune picked {best}")
+    else:
+        eng = alew.ENGINE_PERSISTENT if args.engine == "persistent" else alew.ENGINE_STAGES
+        ctx.set_launch(engine=eng, block=args.block, use_graph=1)
+    L = ctx.get_launch()
+    engine_name = "persistent" if L.engine == alew.ENGINE_PERSISTENT else "stage-launches"
+
+    # warmup (untimed), then exactly --steps steps in one call
+    tnow = [0.0] * ninst
+    if args.warmup > 0:
+        st = ctx.run(p, off, T["h"], T["hu"], T["b"], T["x"], T["xi"], t0=tnow,
+                     max_steps=[args.warmup] * ninst)
+        tnow = [s.t for s in st]
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    st = ctx.run(p, off, T["h"], T["hu"], T["b"], T["x"], T["xi"], t0=tnow,
+                 max_steps=[args.steps] * ninst)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    kern_ms, launches = ctx.last_timing()
+    assert all(s.steps == args.steps and s.status == 0 for s in st), "run did not complete"
+    cell_stages = 3.0 * S * args.steps
+    value = cell_stages / wall
+    log(f"timed {args.steps} steps: {wall * 1e3:.1f} ms wall, {kern_ms:.1f} ms in {launches} "
+        f"compute launch(es); {value:.3e} cell-updates/s")
+
+    kernel = "k_persistent" if L.engine == alew.ENGINE_PERSISTENT else "step sequence"
+    per_launch_bytes = ALG_BYTES_PER_CELL_STEP * S * args.steps / max(1, launches)
+    achieved = per_launch_bytes / (kern_ms / 1e3 / max(1, launches)) / 1e9
+    traffic = load_traffic(kernel)
+    roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4),
+                traffic=None if traffic is None else traffic * S * args.steps / max(1, launches),
+                kernel=kernel, launch_ms=round(kern_ms / max(1, launches), 3),
+                alg_bytes_per_cell_step=ALG_BYTES_PER_CELL_STEP)
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"ragged batch of {ninst} 1D perturbation-of-still-water "
+                               f"instances, 1000-20000 cells each (seed 2208065881), {S} cells, "
+                               "transmissive, sine-moving mesh, CFL 0.6, FP64 SSP-RK3",
+                   "ninst": ninst, "cells": S, "engine": engine_name, "block": L.block,
+                   "parallelism": "single GPU"},
+        "roofline": roof,
+    }
+
+    if not args.no_speedup:
+        # batched (one call) vs one call per instance, same GPU, same 64 instances
+        k = min(64, ninst)
+        sub_off = off[:k + 1]
+        Ssub = sub_off[-1]
+        steps = 3
+        Tb = {kk: v[:Ssub + (k if kk in ("x", "xi") else 0)].clone() for kk, v in T.items()}
+        torch.cuda.synchronize()
+        a0 = time.perf_counter()
+        ctx.run(p, sub_off, Tb["h"], Tb["hu"], Tb["b"], Tb["x"], Tb["xi"], t0=tnow[:k],
+                max_steps=[steps] * k)
+        torch.cuda.synchronize()
+        batched = time.perf_counter() - a0
+        Tp = {kk: v[:Ssub + (k if kk in ("x", "xi") else 0)].clone() for kk, v in T.items()}
+        ctx1 = alew.Context(max(np.diff(sub_off)), 1)
+        ctx1.set_launch(engine=alew.ENGINE_STAGES, block=256, use_graph=1)
+        torch.cuda.synchronize()
+        a0 = time.perf_counter()
+        for i in range(k):
+            c0, c1 = sub_off[i], sub_off[i + 1]
+            ctx1.run(p, [0, c1 - c0], Tp["h"][c0:c1], Tp["hu"][c0:c1], Tp["b"][c0:c1],
+                     Tp["x"][c0 + i:c1 + i + 1], Tp["xi"][c0 + i:c1 + i + 1], t0=[tnow[i]],
+                     max_steps=[steps])
+        torch.cuda.synchronize()
+        per_inst = time.perf_counter() - a0
+        out["batched_speedup"] = dict(instances=k, steps=steps, batched_s=round(batched, 4),
+                                      per_instance_s=round(per_inst, 4),
+                                      speedup=round(per_inst / batched, 2))
+        del Tb, Tp, ctx1
+
+    if not args.no_cpu:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(bt, min(args.cpu_inst, ninst), args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -168,6 +168,13 @@ alew_status alew_adjoint(alew_ctx* ctx, const alew_params* p, int64_t ninst,
                          const double* gauge_x, double* gauge_h, const double* gauge_bar,
                          double* dh0, double* dhu0, double* db0);
 
+/* Device time of the compute launches of the last alew_step/alew_run on this
+ * context, measured with HIP events recorded on the context's stream around
+ * them: the persistent kernel launches (engine 1, launches = kernel launches)
+ * or the step sequences (engine 2, launches = graph or sequence launches).
+ * ms and launches are host pointers. */
+alew_status alew_last_timing(const alew_ctx* ctx, double* ms, int64_t* launches);
+
 /* Message for the calling thread's last non-OK status ("" if none). */
 const char* alew_last_error(void);
 

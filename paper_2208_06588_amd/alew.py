@@ -78,6 +78,8 @@ def lib():
                                dp, dp, C.POINTER(C.c_int64), vp, vp, i64, C.POINTER(Stats)]
         L.alew_adjoint.argtypes = [vp, C.POINTER(Params), i64, C.POINTER(C.c_int64), vp, vp, vp,
                                    vp, vp, i64, vp, i64, i64, vp, vp, vp, vp, vp, vp]
+        L.alew_last_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        L.alew_last_timing.restype = C.c_int
         L.alew_last_error.restype = C.c_char_p
         L.alew_version.restype = C.c_char_p
         for f in ("alew_create", "alew_set_stream", "alew_set_launch", "alew_get_launch",
@@ -148,6 +150,12 @@ class Context:
     def set_launch(self, engine=ENGINE_AUTO, block=256, steps_per_launch=0, use_graph=1):
         _check(lib().alew_set_launch(self._h, C.byref(Launch(engine, block, steps_per_launch,
                                                              use_graph))))
+
+    def last_timing(self):
+        """(milliseconds, launches) of the compute launches of the last call."""
+        ms, n = C.c_double(), C.c_int64()
+        _check(lib().alew_last_timing(self._h, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
 
     def get_launch(self) -> Launch:
         l = Launch()

@@ -57,6 +57,8 @@ __global__ __launch_bounds__(B) void k_prep(Bufs bf, Consts cs, const Tile* __re
     speed = fabs(u) + sqrt(cs.g * fmax(hh, 0.0));
     minJ = J; maxJ = J; hmin = hh;
     me = J * e; mb = J * b;
+    if (!(J > 0.0)) atomicOr(&I.status, (int)SB_MESH);
+    if (!isfinite(h) || !isfinite(m) || !isfinite(b)) atomicOr(&I.status, (int)SB_NONFINITE);
   }
   if (j <= v.n) {
     if (cs.mesh == MESH_SINE || cs.mesh == MESH_PAPER) {
@@ -401,6 +403,9 @@ struct alew_ctx {
   int cached_B = 0;
   int64_t n_tiles_stage = 0, n_tiles_plain = 0;
   alew_launch launch{0, 256, 0, 1};
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;  // around the compute launches of a call
+  double last_ms = 0.0;
+  int64_t last_launches = 0;
   // graph of a 2-step sequence (stage-launch engine)
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
@@ -532,6 +537,8 @@ alew_status run_stage_engine(alew_ctx* c, const Bufs& bf, const Consts& cs, int6
     }
   }
   int64_t it = 0;
+  c->last_launches = 0;
+  HIPCHK(hipEventRecord(c->ev0, c->stream));
   while (it < max_iters) {
     for (int k = 0; k < check_every && it < max_iters; ++k) {
       if (use_graph) {
@@ -541,12 +548,18 @@ alew_status run_stage_engine(alew_ctx* c, const Bufs& bf, const Consts& cs, int6
         launch_step_seq<B>(c, bf, cs, c->stream);
         it += 1;
       }
+      c->last_launches += 1;
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(c->nactive_h, c->nactive_d, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     if (*c->nactive_h == 0) break;
   }
+  HIPCHK(hipEventRecord(c->ev1, c->stream));
+  HIPCHK(hipEventSynchronize(c->ev1));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+  c->last_ms = ms;
   return ALEW_OK;
 }
 
@@ -559,17 +572,27 @@ alew_status run_persistent(alew_ctx* c, const Bufs& bf, const Consts& cs, int64_
   int64_t grid = (int64_t)std::max(1, ncu) * std::max(1, per_cu);
   grid = std::min<int64_t>(grid, ninst);
   const int limit = c->launch.steps_per_launch;
+  c->last_launches = 0;
+  double total = 0.0;
   for (;;) {
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, c->stream, c->queue_d);
+    HIPCHK(hipEventRecord(c->ev0, c->stream));
     hipLaunchKernelGGL(k_persistent<B>, dim3((unsigned)grid), dim3(B), 0, c->stream, bf, cs,
                        c->order_d, c->queue_d, limit);
+    HIPCHK(hipEventRecord(c->ev1, c->stream));
     HIPCHK(hipGetLastError());
+    HIPCHK(hipEventSynchronize(c->ev1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    total += ms;
+    c->last_launches += 1;
     if (limit <= 0) break;
     hipLaunchKernelGGL(k_count_active, dim3(1), dim3(1024), 0, c->stream, bf, c->nactive_d);
     HIPCHK(hipMemcpyAsync(c->nactive_h, c->nactive_d, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     if (*c->nactive_h == 0) break;
   }
+  c->last_ms = total;
   return ALEW_OK;
 }
 
@@ -690,6 +713,13 @@ alew_status drive(alew_ctx* c, const alew_params* p, int64_t ninst, const int64_
 extern "C" {
 
 const char* alew_last_error(void) { return g_err.c_str(); }
+
+alew_status alew_last_timing(const alew_ctx* c, double* ms, int64_t* launches) {
+  if (!c || !ms || !launches) return fail(ALEW_E_ARG, "NULL argument");
+  *ms = c->last_ms;
+  *launches = c->last_launches;
+  return ALEW_OK;
+}
 const char* alew_version(void) { return "alew 0.1 gfx950 fp64"; }
 
 alew_status alew_create(alew_ctx** out, int64_t max_cells, int64_t max_inst, void* hip_stream) {
@@ -715,6 +745,7 @@ alew_status alew_create(alew_ctx** out, int64_t max_cells, int64_t max_inst, voi
   ok = ok && hipHostMalloc((void**)&c->inst_h, max_inst * sizeof(Inst), hipHostMallocDefault) == hipSuccess;
   ok = ok && hipHostMalloc((void**)&c->nactive_h, sizeof(int), hipHostMallocDefault) == hipSuccess;
   ok = ok && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) == hipSuccess;
+  ok = ok && hipEventCreate(&c->ev0) == hipSuccess && hipEventCreate(&c->ev1) == hipSuccess;
   if (!ok) {
     alew_destroy(c);
     return fail(ALEW_E_NOMEM, "device allocation failed");
@@ -735,6 +766,8 @@ void alew_destroy(alew_ctx* c) {
   if (c->dt1_h) (void)hipHostFree(c->dt1_h);
   if (c->nactive_h) (void)hipHostFree(c->nactive_h);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
   delete c;
 }
 

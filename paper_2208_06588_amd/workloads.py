@@ -28,21 +28,25 @@ def uniform_nodes(n: int, x0: float, x1: float) -> np.ndarray:
 def cell_averages(f, nodes: np.ndarray, breaks=()) -> np.ndarray:
     """Average of f over each cell [nodes[j], nodes[j+1]] (5-point Gauss-Legendre,
     cells containing a breakpoint are split there)."""
-    a = nodes[:-1]
-    b = nodes[1:]
+    return interval_averages(lambda xs, idx: f(xs), nodes[:-1], nodes[1:], breaks)
 
-    def gl(lo, hi):
+
+def interval_averages(f, a: np.ndarray, b: np.ndarray, breaks=()) -> np.ndarray:
+    """Average over [a_j, b_j] of f(x, j) (f gets an (m, 5) array of points and
+    the (m,) cell indices), 5-point Gauss-Legendre, split at breakpoints."""
+
+    def gl(lo, hi, idx):
         mid = 0.5 * (lo + hi)
         half = 0.5 * (hi - lo)
         xs = mid[:, None] + half[:, None] * _GL5_X[None, :]
-        return (f(xs) * _GL5_W[None, :]).sum(axis=1) * half
+        return (f(xs, idx) * _GL5_W[None, :]).sum(axis=1) * half
 
-    integ = gl(a, b)
+    integ = gl(a, b, np.arange(a.size))
     for c in breaks:
         idx = np.nonzero((a < c) & (c < b))[0]
         if idx.size:
             cc = np.full(idx.size, c)
-            integ[idx] = gl(a[idx], cc) + gl(cc, b[idx])
+            integ[idx] = gl(a[idx], cc, idx) + gl(cc, b[idx], idx)
     return integ / (b - a)
 
 
@@ -105,13 +109,26 @@ def _lev_bottom(x):
     return np.where(np.abs(x - 1.5) < 0.1, 0.25 * (np.cos(10 * np.pi * (x - 1.5)) + 1.0), 0.0)
 
 
+def _perturbation_cells(a, b, eps_cell):
+    """Cell averages of the bump bottom and of h = 1 - b + eps 1_[1.1,1.2] over
+    cells [a, b]; cells away from [1.1, 1.6] hold the exact values b = 0, h = 1."""
+    br = (1.1, 1.2, 1.4, 1.6)
+    bb = np.zeros(a.size)
+    hh = np.ones(a.size)
+    sel = np.nonzero((b > 1.1) & (a < 1.6))[0]
+    if sel.size:
+        aa, bs, es = a[sel], b[sel], eps_cell[sel]
+        bb[sel] = interval_averages(lambda x, i: _lev_bottom(x), aa, bs, br)
+        hh[sel] = interval_averages(
+            lambda x, i: 1.0 - _lev_bottom(x) + np.where((x >= 1.1) & (x <= 1.2), es[i][:, None], 0.0),
+            aa, bs, br)
+    return hh, bb
+
+
 def perturbation_instance(n: int, eps: float):
     """[0,2]; bump bottom; h = 1 - b + eps on [1.1,1.2], else 1 - b; hu = 0."""
     xi = uniform_nodes(n, 0.0, 2.0)
-    br = (1.1, 1.2, 1.4, 1.6)
-    b = cell_averages(_lev_bottom, xi, br)
-    h = cell_averages(lambda x: 1.0 - _lev_bottom(x) + np.where((x >= 1.1) & (x <= 1.2), eps, 0.0),
-                      xi, br)
+    h, b = _perturbation_cells(xi[:-1], xi[1:], np.full(n, eps))
     return xi, h, np.zeros(n), b
 
 
@@ -120,16 +137,27 @@ def perturbation_batch(ninst: int = 4096, nmin: int = 1000, nmax: int = 20000,
     """Ragged batch: cell counts uniform in [nmin, nmax], eps uniform in
     [1e-5, 1e-2] (NumPy PCG64, drawn in that order).  Packed SoA with
     cell offsets; node arrays hold ncell+1 entries per instance.  subset=k
-    keeps the first k instances of the same draw."""
+    keeps the first k instances of the same draw.  Same values as
+    perturbation_instance, computed for all instances at once."""
     rng = np.random.Generator(np.random.PCG64(seed))
     ns = rng.integers(nmin, nmax + 1, ninst)
     eps = rng.uniform(1e-5, 1e-2, ninst)
     if subset is not None:
         ns = ns[:subset]
         eps = eps[:subset]
-    return pack([perturbation_instance(int(n), float(e)) for n, e in zip(ns, eps)],
-                bc="transmissive", t_end=0.2, cfl=0.6, weno_eps=1e-9, mesh="sine",
-                mesh_A=0.05, mesh_k=1.0, mesh_omega=math.pi, eps=eps)
+    ns = ns.astype(np.int64)
+    cell_off = np.zeros(len(ns) + 1, dtype=np.int64)
+    cell_off[1:] = np.cumsum(ns)
+    inst_of_cell = np.repeat(np.arange(len(ns)), ns)
+    local = np.arange(cell_off[-1]) - np.repeat(cell_off[:-1], ns)
+    nn = ns[inst_of_cell].astype(np.float64)
+    a = 0.0 + (2.0 - 0.0) * (local / nn)
+    bnd = 0.0 + (2.0 - 0.0) * ((local + 1) / nn)
+    hh, bb = _perturbation_cells(a, bnd, eps[inst_of_cell])
+    xi = np.concatenate([uniform_nodes(int(n), 0.0, 2.0) for n in ns])
+    return dict(cell_off=cell_off, xi=xi, x=xi.copy(), h=hh, hu=np.zeros(cell_off[-1]), b=bb,
+                bc="transmissive", t_end=0.2, cfl=0.6, weno_eps=1e-9, mesh="sine", mesh_A=0.05,
+                mesh_k=1.0, mesh_omega=math.pi, eps=eps)
 
 
 def pack(instances, **meta):

@@ -269,5 +269,11 @@ def test_device_errors_are_reported(dev):
     T = {k: _t(v, dev) for k, v in dict(h=h, hu=wl["hu"], b=wl["b"], x=wl["x"], xi=wl["xi"]).items()}
     st = ctx.run(p, [0, 64], T["h"], T["hu"], T["b"], T["x"], T["xi"], max_steps=[3], check=False)
     assert st[0].status == alew.E_NONFINITE
-    with pytest.raises(alew.AlewError):
+    with pytest.raises(ValueError):  # shapes do not match the offsets
         ctx.run(p, [0, 3], T["h"], T["hu"], T["b"], T["x"], T["xi"], max_steps=[1])
+    small = {k: v[:3] for k, v in T.items() if k in ("h", "hu", "b")}
+    small.update({k: T[k][:4] for k in ("x", "xi")})
+    with pytest.raises(alew.AlewError) as ei:  # fewer than 5 cells
+        ctx.run(p, [0, 3], small["h"], small["hu"], small["b"], small["x"], small["xi"],
+                max_steps=[1])
+    assert ei.value.status == alew.E_ARG

@@ -94,6 +94,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--engine", default="tune", choices=["tune", "persistent", "stages"])
     ap.add_argument("--block", type=int, default=256)
+    ap.add_argument("--graph", type=int, default=1, help="stage engine: replay steps as a hipGraph")
     ap.add_argument("--ninst", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-inst", type=int, default=64)
@@ -140,7 +141,7 @@ def main():
         log(f"autotune picked {best}")
     else:
         eng = alew.ENGINE_PERSISTENT if args.engine == "persistent" else alew.ENGINE_STAGES
-        ctx.set_launch(engine=eng, block=args.block, use_graph=1)
+        ctx.set_launch(engine=eng, block=args.block, use_graph=args.graph)
     L = ctx.get_launch()
     engine_name = "persistent" if L.engine == alew.ENGINE_PERSISTENT else "stage-launches"
 

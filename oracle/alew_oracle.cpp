@@ -882,15 +882,18 @@ int orc_adjoint(const Params* P, int64_t n_, const double* h0, const double* hu0
               (double*)nullptr, t, dts[k], (uint8_t*)nullptr, cnt);
     if (st != ST_OK && st != ST_NEGWEIGHT) break;
   }
-  std::vector<double> adj(tape.size(), 0.0);
+  /* gauge readings first: they add nodes to the tape */
+  std::vector<AD> hgs(ngauge);
   for (int64_t gI = 0; gI < ngauge; ++gI) {
     double xg = gauge_x[gI];
     int c = 0;
     while (c < n - 1 && !(xg < x[c + 1])) ++c;
-    AD hg = eta[c] - b[c];
-    if (gauge_h) gauge_h[gI] = hg.v;
-    if (hg.i >= 0) adj[hg.i] += gauge_bar[gI];
+    hgs[gI] = eta[c] - b[c];
+    if (gauge_h) gauge_h[gI] = hgs[gI].v;
   }
+  std::vector<double> adj(tape.size(), 0.0);
+  for (int64_t gI = 0; gI < ngauge; ++gI)
+    if (hgs[gI].i >= 0) adj[hgs[gI].i] += gauge_bar[gI];
   for (int64_t k = (int64_t)tape.size() - 1; k >= 0; --k) {
     double a = adj[k];
     if (a == 0.0) continue;

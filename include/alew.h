@@ -151,8 +151,8 @@ alew_status alew_run(alew_ctx* ctx, const alew_params* p, int64_t ninst, const i
                      const double* dts, double* dt_log, int64_t dts_stride, alew_stats* stats);
 
 /* Discrete adjoint of alew_run with frozen step sizes (prescribed mesh).
- * Forward: from (h0, hu0, b0, x0) run nsteps steps of sizes dts (device,
- * [ninst * nsteps]); gauge_h (device, out) [ninst * ngauge] receives the mean
+ * Forward: from (h0, hu0, b0, x0) at time t0 run nsteps steps of sizes dts
+ * (device, [ninst * nsteps]); gauge_h (device, out) [ninst * ngauge] receives the mean
  * depth at the final time of the cell containing gauge_x (device)
  * [ninst * ngauge] (positions in the final mesh).
  * Reverse: with gauge_bar (device) [ninst * ngauge] = dL/d gauge_h, writes
@@ -160,10 +160,14 @@ alew_status alew_run(alew_ctx* ctx, const alew_params* p, int64_t ninst, const i
  * the limiter's active set and argmin, the argmax of the LF speed, |.| signs and
  * dry cut-offs are frozen to the forward pass.  The forward is checkpointed every
  * ckpt_every steps and recomputed segment by segment (ckpt_every <= 0: 16).
- * gauge_h may be computed without the reverse pass by passing gauge_bar = NULL. */
+ * gauge_h may be computed without the reverse pass by passing gauge_bar = NULL.
+ * Checkpoints and per-step records of one segment live in a workspace that the
+ * context allocates on the first call and keeps (about (3 + 26 ckpt_every) * 8
+ * bytes per cell plus (4 + 24) * 8 per cell for the adjoint state). */
 alew_status alew_adjoint(alew_ctx* ctx, const alew_params* p, int64_t ninst,
                          const int64_t* cell_off, const double* h0, const double* hu0,
-                         const double* b0, const double* x0, const double* xi, int64_t nsteps,
+                         const double* b0, const double* x0, const double* xi, double t0,
+                         int64_t nsteps,
                          const double* dts, int64_t ckpt_every, int64_t ngauge,
                          const double* gauge_x, double* gauge_h, const double* gauge_bar,
                          double* dh0, double* dhu0, double* db0);

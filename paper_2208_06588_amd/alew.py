@@ -77,7 +77,7 @@ def lib():
         L.alew_run.argtypes = [vp, C.POINTER(Params), i64, C.POINTER(C.c_int64), vp, vp, vp, vp, vp,
                                dp, dp, C.POINTER(C.c_int64), vp, vp, i64, C.POINTER(Stats)]
         L.alew_adjoint.argtypes = [vp, C.POINTER(Params), i64, C.POINTER(C.c_int64), vp, vp, vp,
-                                   vp, vp, i64, vp, i64, i64, vp, vp, vp, vp, vp, vp]
+                                   vp, vp, C.c_double, i64, vp, i64, i64, vp, vp, vp, vp, vp, vp]
         L.alew_last_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.alew_last_timing.restype = C.c_int
         L.alew_last_error.restype = C.c_char_p
@@ -214,11 +214,25 @@ class Context:
         return list(stats)
 
     def adjoint(self, p: Params, cell_off, h0, hu0, b0, x0, xi, nsteps, dts, ngauge, gauge_x,
-                gauge_h, gauge_bar, dh0, dhu0, db0, ckpt_every=16):
+                gauge_h, gauge_bar=None, dh0=None, dhu0=None, db0=None, ckpt_every=16, t0=0.0):
+        """Gauge depths after nsteps frozen steps (gauge_h, out) and, when
+        gauge_bar is given, the gradients of sum(gauge_bar * gauge_h) with
+        respect to h0, hu0, b0 (written into dh0, dhu0, db0)."""
+        ninst = len(cell_off) - 1
+        S = int(cell_off[-1])
+        _sizes(S, ninst, h0, hu0, b0, x0, xi, None)
+        if dts.numel() < ninst * nsteps:
+            raise ValueError("dts must hold ninst * nsteps step sizes")
+        for t in (gauge_x, gauge_h, gauge_bar):
+            if t is not None and t.numel() != ninst * ngauge:
+                raise ValueError("gauge arrays must hold ninst * ngauge entries")
+        for t in (dh0, dhu0, db0):
+            if t is not None and t.numel() != S:
+                raise ValueError("gradient arrays must hold one entry per cell")
         self._sync_stream()
         off = (C.c_int64 * len(cell_off))(*[int(v) for v in cell_off])
-        st = lib().alew_adjoint(self._h, C.byref(p), len(cell_off) - 1, off, _ptr(h0), _ptr(hu0),
-                                _ptr(b0), _ptr(x0), _ptr(xi), int(nsteps), _ptr(dts),
+        st = lib().alew_adjoint(self._h, C.byref(p), ninst, off, _ptr(h0), _ptr(hu0),
+                                _ptr(b0), _ptr(x0), _ptr(xi), float(t0), int(nsteps), _ptr(dts),
                                 int(ckpt_every), int(ngauge), _ptr(gauge_x), _ptr(gauge_h),
                                 _ptr(gauge_bar), _ptr(dh0), _ptr(dhu0), _ptr(db0))
         _check(st)

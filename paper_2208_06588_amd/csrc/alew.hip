@@ -20,6 +20,7 @@
 #include <vector>
 
 #include "alew.h"
+#include "alew_adjoint.h"
 #include "alew_kernels.h"
 
 using namespace alew_dev;
@@ -188,6 +189,11 @@ __device__ void boundary_update(Inst& I, const Consts& cs, const Bufs& bf, int i
   I.dt = dt;
   if (bf.dt_log) bf.dt_log[(int64_t)i * bf.dts_stride + I.steps] = dt;
   I.dx[0] = bitsd(I.r_maxJ);
+  if (bf.dump.scal_next) {
+    bf.dump.scal_next[(int64_t)i * 8 + 0] = I.t;
+    bf.dump.scal_next[(int64_t)i * 8 + 1] = dt;
+    bf.dump.scal_next[(int64_t)i * 8 + 5] = I.dx[0];
+  }
   reset_step_slots(I);
 }
 
@@ -213,6 +219,10 @@ __global__ __launch_bounds__(1024) void k_after_stage(Bufs bf, int s) {
     if (!I.active) continue;
     I.alpha[s - 1] = bitsd(I.r_alpha);
     if (s < 3) I.dx[s] = bitsd(I.r_maxJs);
+    if (bf.dump.scal) {
+      bf.dump.scal[(int64_t)i * 8 + 1 + s] = I.alpha[s - 1];
+      if (s < 3) bf.dump.scal[(int64_t)i * 8 + 5 + s] = I.dx[s];
+    }
     I.r_alpha = 0ull;
     I.r_maxJs = 0ull;
   }
@@ -355,6 +365,63 @@ __global__ __launch_bounds__(B) void k_persistent(Bufs bf, Consts cs,
   }
 }
 
+// ---------------------------------------------------------------------------
+// adjoint driver kernels
+// ---------------------------------------------------------------------------
+// Mean depth at the final time in the cell containing each gauge (first cell
+// whose right node lies beyond the gauge, at most the last cell).
+__global__ void k_gauge(Bufs bf, int64_t ngauge, const double* __restrict__ gx,
+                        double* __restrict__ gh, int64_t* __restrict__ gcell) {
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (int64_t)bf.ninst * ngauge) return;
+  const int i = (int)(id / ngauge);
+  const Inst& I = bf.inst[i];
+  const View v = make_view(bf, i, I);
+  const double xg = gx[id];
+  int64_t lo = 0, hi = v.n - 1;  // smallest c with xg < x[c+1], capped at n-1
+  while (lo < hi) {
+    const int64_t mid = lo + (hi - lo) / 2;
+    if (xg < v.x[mid + 1]) hi = mid; else lo = mid + 1;
+  }
+  const int64_t g = v.co + lo;
+  gcell[id] = g;
+  if (gh) gh[id] = bf.eta[g] - bf.b[g];
+}
+
+__global__ void k_gauge_seed(int64_t ntot, int64_t S, const int64_t* __restrict__ gcell,
+                             const double* __restrict__ gbar, double* __restrict__ lam) {
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= ntot) return;
+  const int64_t g = gcell[id];
+  atomicAdd(&lam[g], gbar[id]);           // d hbar / d eta
+  atomicAdd(&lam[2 * S + g], -gbar[id]);  // d hbar / d b
+}
+
+__global__ void k_fill(double* __restrict__ p, int64_t n, double v) {
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id < n) p[id] = v;
+}
+
+// dL/dh0 = lambda_eta, dL/dhu0 = lambda_hu, dL/db0 = lambda_b + lambda_eta (eta = h + b)
+__global__ void k_adj_out(int64_t S, const double* __restrict__ lam, double* __restrict__ dh,
+                          double* __restrict__ dhu, double* __restrict__ db) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= S) return;
+  dh[g] = lam[g];
+  dhu[g] = lam[S + g];
+  db[g] = lam[2 * S + g] + lam[g];
+}
+
+// Record (t, dt, dx_0) of the first step of a recomputed segment.
+__global__ void k_seed_scal(Bufs bf, double* __restrict__ scal) {
+  for (int i = threadIdx.x; i < bf.ninst; i += blockDim.x) {
+    const Inst& I = bf.inst[i];
+    scal[(int64_t)i * 8 + 0] = I.t;
+    scal[(int64_t)i * 8 + 1] = I.dt;
+    scal[(int64_t)i * 8 + 5] = I.dx[0];
+  }
+}
+
 // ============================================================================
 // host side
 // ============================================================================
@@ -404,6 +471,9 @@ struct alew_ctx {
   int64_t n_tiles_stage = 0, n_tiles_plain = 0;
   alew_launch launch{0, 256, 0, 1};
   hipEvent_t ev0 = nullptr, ev1 = nullptr;  // around the compute launches of a call
+  // adjoint workspace (allocated by the first alew_adjoint call, grown on demand)
+  double* adj_ws = nullptr;
+  size_t adj_ws_bytes = 0;
   double last_ms = 0.0;
   int64_t last_launches = 0;
   // graph of a 2-step sequence (stage-launch engine)
@@ -487,6 +557,7 @@ Bufs make_bufs(alew_ctx* c, int64_t S, int64_t ninst, double* hu, double* b, con
   bf.cls = cls; bf.inst = c->inst;
   bf.dts = dts; bf.dt_log = dt_log; bf.dts_stride = dts_stride;
   bf.S = S; bf.ninst = (int32_t)ninst; bf.pad = 0;
+  bf.dump = Dump{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   return bf;
 }
 
@@ -759,7 +830,8 @@ void alew_destroy(alew_ctx* c) {
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
   void* ps[] = {c->eta, c->P0, c->D0, c->P1, c->D1, c->w, c->xa, c->xb, c->inst, c->cell_off_d,
-                c->order_d, c->queue_d, c->nactive_d, c->tiles_stage_d, c->tiles_plain_d, c->dt1_d};
+                c->order_d, c->queue_d, c->nactive_d, c->tiles_stage_d, c->tiles_plain_d, c->dt1_d,
+                c->adj_ws};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   if (c->inst_h) (void)hipHostFree(c->inst_h);
@@ -835,14 +907,158 @@ alew_status alew_run(alew_ctx* c, const alew_params* p, int64_t ninst, const int
 
 alew_status alew_adjoint(alew_ctx* c, const alew_params* p, int64_t ninst,
                          const int64_t* cell_off, const double* h0, const double* hu0,
-                         const double* b0, const double* x0, const double* xi, int64_t nsteps,
-                         const double* dts, int64_t ckpt_every, int64_t ngauge,
+                         const double* b0, const double* x0, const double* xi, double t0,
+                         int64_t nsteps, const double* dts, int64_t ckpt_every, int64_t ngauge,
                          const double* gauge_x, double* gauge_h, const double* gauge_bar,
                          double* dh0, double* dhu0, double* db0) {
-  (void)c; (void)p; (void)ninst; (void)cell_off; (void)h0; (void)hu0; (void)b0; (void)x0;
-  (void)xi; (void)nsteps; (void)dts; (void)ckpt_every; (void)ngauge; (void)gauge_x;
-  (void)gauge_h; (void)gauge_bar; (void)dh0; (void)dhu0; (void)db0;
-  return fail(ALEW_E_UNSUPPORTED, "adjoint not built yet");
+  alew_status ps = check_params(p);
+  if (ps != ALEW_OK) return ps;
+  if (!c) return fail(ALEW_E_ARG, "ctx is NULL");
+  if (p->mesh != ALEW_MESH_SINE && p->mesh != ALEW_MESH_PAPER)
+    return fail(ALEW_E_UNSUPPORTED, "the adjoint needs a prescribed (SINE or PAPER) mesh");
+  if (ninst <= 0 || ninst > c->max_inst || !cell_off) return fail(ALEW_E_ARG, "bad ninst / cell_off");
+  if (!h0 || !hu0 || !b0 || !x0 || !xi || !dts) return fail(ALEW_E_ARG, "NULL input array");
+  if (nsteps < 1) return fail(ALEW_E_ARG, "nsteps must be >= 1");
+  if (ngauge < 1 || !gauge_x) return fail(ALEW_E_ARG, "gauges required");
+  if (gauge_bar && (!dh0 || !dhu0 || !db0)) return fail(ALEW_E_ARG, "gradient outputs required");
+  if (cell_off[0] != 0) return fail(ALEW_E_ARG, "cell_off[0] must be 0");
+  for (int64_t i = 0; i < ninst; ++i)
+    if (cell_off[i + 1] - cell_off[i] < 5) return fail(ALEW_E_ARG, "every instance needs >= 5 cells");
+  const int64_t S = cell_off[ninst];
+  if (S > c->max_cells) return fail(ALEW_E_ARG, "total cells exceed the context capacity");
+  const int64_t K = ckpt_every > 0 ? ckpt_every : 16;
+  const int64_t nck = (nsteps + K - 1) / K;
+  const int64_t NN = S + ninst, CS = S + 2 * ninst;
+  const int B = 256;
+  alew_status ts = build_tiles(c, cell_off, ninst, B);
+  if (ts != ALEW_OK) return ts;
+  // workspace layout (doubles)
+  const size_t n_state = 2 * (size_t)S;                 // hu, b of the run
+  const size_t n_ck = (size_t)nck * (3 * S + NN);       // checkpoints
+  const size_t n_ckI = (size_t)nck * ninst * sizeof(Inst) / 8 + 1;
+  const size_t per_step = 18 * (size_t)S + 8 * (size_t)NN + 8 * (size_t)ninst;
+  const size_t n_seg = (size_t)(K + 1) * per_step;
+  const size_t n_adj = 6 * (size_t)S + 15 * (size_t)CS + 2 * (size_t)ninst + (size_t)ninst * ngauge;
+  const size_t need = (n_state + n_ck + n_ckI + n_seg + n_adj) * 8;
+  if (need > c->adj_ws_bytes) {
+    if (c->adj_ws) (void)hipFree(c->adj_ws);
+    c->adj_ws = nullptr;
+    c->adj_ws_bytes = 0;
+    if (hipMalloc(&c->adj_ws, need) != hipSuccess) return fail(ALEW_E_NOMEM, "adjoint workspace");
+    c->adj_ws_bytes = need;
+  }
+  double* wp = c->adj_ws;
+  double* st_m = wp; wp += S;
+  double* st_b = wp; wp += S;
+  double* ck = wp; wp += n_ck;
+  Inst* ckI = (Inst*)wp; wp += n_ckI;
+  double* seg = wp; wp += n_seg;
+  double* lam = wp; wp += 3 * S;
+  double* lbase = wp; wp += 3 * S;
+  double* Cb = wp; wp += 15 * CS;
+  double* lalpha = wp; wp += ninst;
+  unsigned long long* akey = (unsigned long long*)wp; wp += ninst;
+  int64_t* gcell = (int64_t*)wp; wp += ninst * ngauge;
+  hipStream_t st = c->stream;
+  // per-instance scalars: nsteps frozen steps from t0
+  for (int64_t i = 0; i < ninst; ++i) {
+    Inst& I = c->inst_h[i];
+    std::memset(&I, 0, sizeof(Inst));
+    I.t0 = t0; I.t = t0; I.t_end = 0.0; I.max_steps = nsteps; I.active = 1;
+    I.dt_min = INFINITY; I.dt_max = 0.0;
+    I.r_minJ = 0x7ff0000000000000ull;
+    I.r_hmin = 0xffffffffffffffffull;
+  }
+  HIPCHK(hipMemcpyAsync(c->inst, c->inst_h, ninst * sizeof(Inst), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(c->xa, x0, NN * 8, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(st_m, hu0, S * 8, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(st_b, b0, S * 8, hipMemcpyDeviceToDevice, st));
+  Bufs bf = make_bufs(c, S, ninst, st_m, st_b, xi, nullptr, dts, nullptr, nsteps);
+  const Consts cs = make_consts(p);
+  const dim3 gp((unsigned)c->n_tiles_plain), gs((unsigned)c->n_tiles_stage);
+  auto step_dump = [&](int64_t slot) {
+    Dump d;
+    double* base = seg + slot * per_step;
+    d.q = base;
+    d.D = base + 9 * S;
+    d.fs = base + 18 * S;
+    d.xw = base + 18 * S + 6 * NN;
+    d.scal = base + 18 * S + 8 * NN;
+    d.scal_next = d.scal + per_step;
+    return d;
+  };
+  auto xbuf_of = [&](int64_t k) { return (k & 1) ? c->xb : c->xa; };
+  hipLaunchKernelGGL(k_prep<256>, gp, dim3(256), 0, st, bf, cs, c->tiles_plain_d, h0, nullptr);
+  hipLaunchKernelGGL(k_boundary, dim3(1), dim3(1024), 0, st, bf, cs, 1, c->nactive_d);
+  // forward with checkpoints
+  for (int64_t k = 0; k < nsteps; ++k) {
+    if (k % K == 0) {
+      const int64_t q = k / K;
+      double* cq = ck + q * (3 * S + NN);
+      HIPCHK(hipMemcpyAsync(cq, c->eta, S * 8, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(cq + S, st_m, S * 8, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(cq + 2 * S, st_b, S * 8, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(cq + 3 * S, xbuf_of(k), NN * 8, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(ckI + q * ninst, c->inst, ninst * sizeof(Inst), hipMemcpyDeviceToDevice, st));
+    }
+    launch_step_seq<256>(c, bf, cs, st);
+  }
+  HIPCHK(hipGetLastError());
+  const int64_t ng = ninst * ngauge;
+  const unsigned gb = (unsigned)((ng + 255) / 256);
+  hipLaunchKernelGGL(k_gauge, dim3(gb), dim3(256), 0, st, bf, ngauge, gauge_x, gauge_h, gcell);
+  HIPCHK(hipMemcpyAsync(c->inst_h, c->inst, ninst * sizeof(Inst), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  for (int64_t i = 0; i < ninst; ++i) {
+    const alew_status si = map_status(c->inst_h[i].status);
+    if (si != ALEW_OK && si != ALEW_E_NEGWEIGHT) return fail(si, "forward run of the adjoint failed");
+    if (c->inst_h[i].steps != nsteps) return fail(ALEW_E_ARG, "forward run stopped early");
+  }
+  if (!gauge_bar) return ALEW_OK;
+  // reverse sweep
+  const unsigned g3 = (unsigned)((3 * S + 255) / 256);
+  hipLaunchKernelGGL(k_fill, dim3(g3), dim3(256), 0, st, lam, 3 * S, 0.0);
+  hipLaunchKernelGGL(k_gauge_seed, dim3(gb), dim3(256), 0, st, ng, S, gcell, gauge_bar, lam);
+  AdjBufs ab;
+  ab.cell_off = c->cell_off_d; ab.S = S; ab.ninst = (int32_t)ninst; ab.pad = 0;
+  ab.lam = lam; ab.lbase = lbase; ab.C = Cb; ab.lalpha = lalpha; ab.akey = akey;
+  const AdjTile* tst = (const AdjTile*)c->tiles_stage_d;
+  const AdjTile* tpl = (const AdjTile*)c->tiles_plain_d;
+  for (int64_t q = nck - 1; q >= 0; --q) {
+    const int64_t k0 = q * K, k1 = std::min(nsteps, k0 + K);
+    double* cq = ck + q * (3 * S + NN);
+    HIPCHK(hipMemcpyAsync(c->eta, cq, S * 8, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(st_m, cq + S, S * 8, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(st_b, cq + 2 * S, S * 8, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(xbuf_of(k0), cq + 3 * S, NN * 8, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(c->inst, ckI + q * ninst, ninst * sizeof(Inst), hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL(k_seed_scal, dim3(1), dim3(1024), 0, st, bf, step_dump(0).scal);
+    for (int64_t k = k0; k < k1; ++k) {
+      Bufs bd = bf;
+      bd.dump = step_dump(k - k0);
+      launch_step_seq<256>(c, bd, cs, st);
+    }
+    for (int64_t k = k1 - 1; k >= k0; --k) {
+      const Dump d = step_dump(k - k0);
+      ab.x = d.xw; ab.w = d.xw + NN; ab.scal = d.scal;
+      for (int s3 = 3; s3 >= 1; --s3) {
+        ab.q = d.q + (int64_t)3 * (s3 - 1) * S;
+        ab.D = d.D + (int64_t)3 * (s3 - 1) * S;
+        ab.fsl = d.fs + (int64_t)2 * (s3 - 1) * NN;
+        ab.fsr = ab.fsl + NN;
+        hipLaunchKernelGGL(k_adj_reset, dim3(1), dim3(1024), 0, st, ab);
+        hipLaunchKernelGGL(k_adj_alpha<256>, gp, dim3(256), 0, st, ab, tpl, s3);
+        hipLaunchKernelGGL(k_adj_stage<256>, gs, dim3(256), 0, st, ab, cs, tst, s3);
+        hipLaunchKernelGGL(k_adj_gather<256>, gp, dim3(256), 0, st, ab, cs, tpl, s3);
+      }
+    }
+    HIPCHK(hipGetLastError());
+  }
+  const unsigned g1 = (unsigned)((S + 255) / 256);
+  hipLaunchKernelGGL(k_adj_out, dim3(g1), dim3(256), 0, st, S, lam, dh0, dhu0, db0);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(st));
+  return ALEW_OK;
 }
 
 }  // extern "C"

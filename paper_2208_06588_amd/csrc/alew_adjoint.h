@@ -1,0 +1,654 @@
+// Discrete adjoint of one SSP-RK3 stage (reverse mode, written by hand).
+//
+// Stage s maps q^(s-1) to
+//   q^(s) = [a_s J^n q^n + b_s (J^(s-1) q^(s-1) + dt R(q^(s-1)))] / J^(s),
+//   R = A + alpha D,   alpha = max over faces and traces of |u - w| + sqrt(g h).
+// Given lambda^(s) = dL/dq^(s), with mu = lambda^(s) / J^(s) and rho = b_s dt mu:
+//   dL/dq^n     += a_s J^n mu
+//   dL/dq^(s-1)  = b_s J^(s-1) mu + (dR/dq^(s-1))^T rho,
+// where the alpha part enters through lambda_alpha = sum_j rho_j . D_j, sent to
+// the one trace that attains alpha (first face, left trace first, as a scan in
+// face order finds it).  Everything that switches is frozen to the forward
+// values: detector class, limiter activity and its argmin, |.| signs, dry
+// cut-offs, the argmax.  The mesh and the step sizes do not depend on the
+// state.
+//
+// Work split per stage (all gather form, no floating-point atomics in the
+// per-cell part):
+//   k_adj_alpha   lambda_alpha and the argmax face per instance;
+//   k_adj_stage   per reconstructed cell (ghosts included): face adjoints ->
+//                 limiter -> reconstruction, written as 5 stencil slots x
+//                 (eta, hu, b) contributions;
+//   k_adj_gather  per cell: sum of the contributions of the 5 cells whose
+//                 stencils contain it (ghost copies folded back), plus the
+//                 direct terms.
+#pragma once
+
+#include "alew_kernels.h"
+
+namespace alew_dev {
+
+struct AdjBufs {
+  const int64_t* cell_off;
+  int64_t S;
+  int32_t ninst;
+  int32_t pad;
+  const double* q;     // [3][S] stage input q^(s-1) (eta, hu, b)
+  const double* D;     // [3][S] alpha coefficient of the residual
+  const double* fsl;   // [S+ninst] left-trace speed per face
+  const double* fsr;   // [S+ninst] right-trace speed per face
+  const double* x;     // [S+ninst] x^n
+  const double* w;     // [S+ninst] w^n
+  const double* scal;  // [ninst][8] t, dt, alpha_1..3, dx_0..2 of the step
+  double* lam;         // [3][S] in: lambda^(s); out (gather): lambda^(s-1)
+  double* lbase;       // [3][S] adjoint of q^n accumulated over the stages
+  double* C;           // [15][S + 2 ninst] stencil contributions
+  double* lalpha;      // [ninst]
+  unsigned long long* akey;  // [ninst] argmax key 2*face + side
+};
+
+__device__ __forceinline__ double stage_a(int s) { return s == 1 ? 0.0 : (s == 2 ? 0.75 : 1.0 / 3.0); }
+__device__ __forceinline__ double stage_b(int s) { return s == 1 ? 1.0 : (s == 2 ? 0.25 : 2.0 / 3.0); }
+
+// Widths of cell k at the stage meshes: Jn, J^(s-1), J^(s).
+__device__ __forceinline__ void stage_widths(const double* x, const double* w, int64_t k, double dt,
+                                             int s, double& Jn, double& Jin, double& Jout) {
+  Jn = x[k + 1] - x[k];
+  const double dw = w[k + 1] - w[k];
+  const double J1 = Jn + dt * dw;
+  const double J2 = 0.75 * Jn + 0.25 * (J1 + dt * dw);
+  const double J3 = (1.0 / 3.0) * Jn + (2.0 / 3.0) * (J2 + dt * dw);
+  Jin = s == 1 ? Jn : (s == 2 ? J1 : J2);
+  Jout = s == 1 ? J1 : (s == 2 ? J2 : J3);
+}
+
+// ----------------------------------------------------------------------------
+// Reverse of one face: adjoints of the flux pieces (from the neighbouring
+// cells' rho) onto the two limited traces.
+// ----------------------------------------------------------------------------
+struct TraceAdj {
+  double h, m, b;
+};
+
+__device__ __forceinline__ void face_vjp(double hl, double ml, double bl, double hr, double mr,
+                                         double br, double w, double alpha, double g, double dry,
+                                         const double rl[3], const double rr[3], double etal_bar,
+                                         double etar_bar, TraceAdj& Ll, TraceAdj& Lr) {
+  // adjoints of F1, F2, G, B1, B2 at this face
+  const double lF1 = rr[0] - rl[0];
+  const double lF2 = rr[1] - rl[1];
+  const double lG = rr[2] - rl[2];
+  const double lB2 = 0.5 * g * (rl[1] - rr[1]);
+  const double lB1 = -g * etal_bar * rl[1] + g * etar_bar * rr[1];
+  const bool wl = hl > dry, wr = hr > dry;
+  const double mlp = wl ? ml : 0.0, mrp = wr ? mr : 0.0;
+  const double ul = wl ? ml / hl : 0.0, ur = wr ? mr / hr : 0.0;
+  double lel = 0.5 * alpha * lF1, ler = -0.5 * alpha * lF1;
+  const double lHl1 = 0.5 * lF1, lHr1 = 0.5 * lF1;
+  const double lHl2 = 0.5 * lF2, lHr2 = 0.5 * lF2;
+  double lmlp = 0.5 * alpha * lF2, lmrp = -0.5 * alpha * lF2;
+  double lbl = (-0.5 * w + 0.5 * alpha) * lG + 0.5 * lB1 + bl * lB2;
+  double lbr = (-0.5 * w - 0.5 * alpha) * lG + 0.5 * lB1 + br * lB2;
+  // H1 = m' - w eta
+  lmlp += lHl1; lel += -w * lHl1;
+  lmrp += lHr1; ler += -w * lHr1;
+  // H2 = m' u + g h^2 / 2 - w m'
+  lmlp += (ul - w) * lHl2;
+  lmrp += (ur - w) * lHr2;
+  double lul = mlp * lHl2, lur = mrp * lHr2;
+  double lhl = g * hl * lHl2, lhr = g * hr * lHr2;
+  // u = m'/h on wet traces
+  if (wl) { lmlp += lul / hl; lhl += -(ul / hl) * lul; }
+  if (wr) { lmrp += lur / hr; lhr += -(ur / hr) * lur; }
+  // eta = h + b
+  lhl += lel; lbl += lel;
+  lhr += ler; lbr += ler;
+  Ll.h = lhl; Ll.m = wl ? lmlp : 0.0; Ll.b = lbl;
+  Lr.h = lhr; Lr.m = wr ? lmrp : 0.0; Lr.b = lbr;
+}
+
+// Adjoint of alpha = |u - w| + sqrt(g max(h,0)) at the trace that attains it.
+__device__ __forceinline__ void alpha_trace_vjp(double h, double m, double w, double g, double dry,
+                                                double lalpha, TraceAdj& L) {
+  const bool wet = h > dry;
+  const double u = wet ? m / h : 0.0;
+  const double d = u - w;
+  const double sg = d > 0.0 ? 1.0 : (d < 0.0 ? -1.0 : 0.0);
+  const double lu = sg * lalpha;
+  if (wet) { L.m += lu / h; L.h += -(u / h) * lu; }
+  if (h > 0.0) {
+    const double sq = sqrt(g * h);
+    if (sq > 0.0) L.h += g * (0.5 / sq) * lalpha;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Reverse of the positivity limiter (1D eq. (3.20)-(3.21), Remark 4.1).
+// o: unlimited traces.  In: adjoints of the limited traces; out: adjoints of
+// the unlimited traces, plus the cell means.
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ void limit_vjp(double hbar, double mbar, double pp_eps, const CellRecon& o,
+                                          TraceAdj& LL, TraceAdj& LR, double& lhbar,
+                                          double& lmbar) {
+  if (hbar <= 0.0) {
+    // h' = hbar, m' = mbar, b' = (h + b) - hbar
+    lhbar += LL.h + LR.h - LL.b - LR.b;
+    lmbar += LL.m + LR.m;
+    LL.h = LL.b; LL.m = 0.0;
+    LR.h = LR.b; LR.m = 0.0;
+    return;
+  }
+  const double s1 = 1.0 / 12.0;
+  const double delta = (hbar - s1 * o.hL - s1 * o.hR) / (1.0 - 2.0 * s1);
+  double mn = o.hL;
+  int which = 0;
+  if (delta < mn) { mn = delta; which = 1; }
+  if (o.hR < mn) { mn = o.hR; which = 2; }
+  const bool eps_const = pp_eps < hbar;
+  const double epsj = eps_const ? pp_eps : hbar;
+  if (!(mn < epsj)) return;  // identity
+  double Phi = (hbar - epsj) / (hbar - mn);
+  const bool clamped = Phi > 1.0;
+  if (clamped) Phi = 1.0;
+  // b' = (h + b) - h'  ->  total adjoint of h' is lh' - lb'
+  const double lhLt = LL.h - LL.b, lhRt = LR.h - LR.b;
+  double lPhi = (o.hL - hbar) * lhLt + (o.hR - hbar) * lhRt;
+  double lhL = LL.b + Phi * lhLt;
+  double lhR = LR.b + Phi * lhRt;
+  lhbar += (1.0 - Phi) * (lhLt + lhRt);
+  lPhi += (o.mL - mbar) * LL.m + (o.mR - mbar) * LR.m;
+  const double lmL = Phi * LL.m, lmR = Phi * LR.m;
+  lmbar += (1.0 - Phi) * (LL.m + LR.m);
+  if (!clamped) {
+    const double den = hbar - mn;
+    lhbar += lPhi * ((eps_const ? 1.0 : 0.0) - Phi) / den;
+    const double lmn = lPhi * Phi / den;
+    if (which == 0) lhL += lmn;
+    else if (which == 2) lhR += lmn;
+    else {
+      const double ld = lmn / (1.0 - 2.0 * s1);
+      lhbar += ld;
+      lhL -= s1 * ld;
+      lhR -= s1 * ld;
+    }
+  }
+  LL.h = lhL; LL.m = lmL;  // LL.b unchanged: b enters only through eta = h + b
+  LR.h = lhR; LR.m = lmR;
+}
+
+// ----------------------------------------------------------------------------
+// Reverse of recon_cell.  Recomputes the forward values, then propagates the
+// adjoints of the unlimited traces (L, R) and of rint onto the stencil data.
+// ----------------------------------------------------------------------------
+struct ReconAdjOut {
+  double lv[5], lh[5], lm[5], lb[5];
+  double letabar;
+};
+
+__device__ __forceinline__ void recon_cell_vjp(const double* __restrict__ v5,
+                                               const double* __restrict__ h5,
+                                               const double* __restrict__ m5,
+                                               const double* __restrict__ b5,
+                                               const double* __restrict__ J5, double Dx,
+                                               double eps, double etabar, const TraceAdj& LL,
+                                               const TraceAdj& LR, double lrint,
+                                               ReconAdjOut& out) {
+  // ---------------- forward (as recon_cell) ----------------
+  const double J0 = J5[2];
+  const double iJ0 = 1.0 / J0;
+  const double em1 = -0.5 - J5[1] * iJ0;
+  const double em2 = em1 - J5[0] * iJ0;
+  const double ep1 = 0.5 + J5[3] * iJ0;
+  const double ep2 = ep1 + J5[4] * iJ0;
+  double M1[4], M2[4], M3[4], M4[4];
+  moments(em2, em1, M1[0], M2[0], M3[0], M4[0]);
+  moments(em1, -0.5, M1[1], M2[1], M3[1], M4[1]);
+  moments(0.5, ep1, M1[2], M2[2], M3[2], M4[2]);
+  moments(ep1, ep2, M1[3], M2[3], M3[3], M4[3]);
+  const int C1[3] = {2, 1, 0}, C2[3] = {3, 2, 1};
+  double kb1[3], kb2[3], kc1[3], kc2[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const int c1 = C1[r], c2 = C2[r];
+    const double idet = 1.0 / (M1[c1] * M2[c2] - M1[c2] * M2[c1]);
+    kb1[r] = M2[c2] * idet;
+    kb2[r] = -M2[c1] * idet;
+    kc1[r] = -M1[c2] * idet;
+    kc2[r] = M1[c1] * idet;
+  }
+  const double q = 0.22360679774997896964;
+  const double q3 = 0.011180339887498948482;
+  const double yv[4] = {-0.5, -q, q, 0.5};
+  const double p2v[4] = {1.0 / 6.0, -1.0 / 30.0, -1.0 / 30.0, 1.0 / 6.0};
+  const double f3v[4] = {-0.125, -q3, q3, 0.125};
+  const double f4v[4] = {0.05, -0.01, -0.01, 0.05};
+  double d[4][3];
+  {
+    double B3[3], C3[3], B4[3], C4[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const int c1 = C1[r], c2 = C2[r];
+      B3[r] = kb1[r] * M3[c1] + kb2[r] * M3[c2];
+      C3[r] = kc1[r] * M3[c1] + kc2[r] * M3[c2];
+      B4[r] = kb1[r] * M4[c1] + kb2[r] * M4[c2];
+      C4[r] = kc1[r] * M4[c1] + kc2[r] * M4[c2];
+    }
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+      double e3[3], e4[3];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        e3[r] = B3[r] * yv[mu] + C3[r] * p2v[mu] - f3v[mu];
+        e4[r] = B4[r] * yv[mu] + C4[r] * p2v[mu] - f4v[mu];
+      }
+      const double x0 = e3[1] * e4[2] - e3[2] * e4[1];
+      const double x1 = e3[2] * e4[0] - e3[0] * e4[2];
+      const double x2 = e3[0] * e4[1] - e3[1] * e4[0];
+      const double is = 1.0 / (x0 + x1 + x2);
+      d[mu][0] = x0 * is;
+      d[mu][1] = x1 * is;
+      d[mu][2] = x2 * is;
+    }
+  }
+  const int idx[4] = {0, 1, 3, 4};
+  double dv[4], dh[4], dm[4], db[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    dv[c] = v5[idx[c]] - v5[2];
+    dh[c] = h5[idx[c]] - h5[2];
+    dm[c] = m5[idx[c]] - m5[2];
+    db[c] = b5[idx[c]] - b5[2];
+  }
+  double Bv[3], Cv[3], Bh[3], Ch[3], Bm[3], Cm[3], Bb[3], Cb[3], beta[3];
+  const double kap = Dx * iJ0;
+  const double kapC = kap * (1.0 / 3.0) + 4.0 * kap * kap * kap;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const int c1 = C1[r], c2 = C2[r];
+    Bv[r] = kb1[r] * dv[c1] + kb2[r] * dv[c2];
+    Cv[r] = kc1[r] * dv[c1] + kc2[r] * dv[c2];
+    Bh[r] = kb1[r] * dh[c1] + kb2[r] * dh[c2];
+    Ch[r] = kc1[r] * dh[c1] + kc2[r] * dh[c2];
+    Bm[r] = kb1[r] * dm[c1] + kb2[r] * dm[c2];
+    Cm[r] = kc1[r] * dm[c1] + kc2[r] * dm[c2];
+    Bb[r] = kb1[r] * db[c1] + kb2[r] * db[c2];
+    Cb[r] = kc1[r] * db[c1] + kc2[r] * db[c2];
+    beta[r] = (kap * (Bv[r] * Bv[r]) + kapC * (Cv[r] * Cv[r])) +
+              (kap * (Bm[r] * Bm[r]) + kapC * (Cm[r] * Cm[r]));
+  }
+  const double tau = fabs(beta[0] - beta[2]);
+  const double betaA = (beta[0] + beta[1] + beta[2]) / 3.0;
+  const double gam = tau / (betaA + eps);
+  const int cls = (gam <= 0.5) ? 0 : ((gam >= 1.0) ? 2 : 1);
+  double K[3] = {1.0, 1.0, 1.0}, z[3] = {0.0, 0.0, 0.0};
+  if (cls != 0) {
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      z[r] = tau / (beta[r] + eps);
+      K[r] = 1.0 + z[r] * z[r];
+    }
+  }
+  const double Mg = 2.0 * gam - 1.0;
+  // ---------------- reverse ----------------
+  double lBv[3] = {0, 0, 0}, lCv[3] = {0, 0, 0}, lBh[3] = {0, 0, 0}, lCh[3] = {0, 0, 0};
+  double lBm[3] = {0, 0, 0}, lCm[3] = {0, 0, 0}, lBb[3] = {0, 0, 0}, lCb[3] = {0, 0, 0};
+  double lK[3] = {0, 0, 0}, lMg = 0.0;
+  double lh0 = 0.0, lm0 = 0.0, lb0 = 0.0, letab = 0.0;
+  const double wgl[4] = {1.0 / 12.0, 5.0 / 12.0, 5.0 / 12.0, 1.0 / 12.0};
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+    // forward weights at this point
+    double ph[3], phN[3] = {0, 0, 0}, sa = 1.0;
+    if (cls == 0) {
+      ph[0] = d[mu][0]; ph[1] = d[mu][1]; ph[2] = d[mu][2];
+    } else {
+      const double a0 = d[mu][0] * K[0], a1 = d[mu][1] * K[1], a2 = d[mu][2] * K[2];
+      sa = a0 + a1 + a2;
+      const double ia = 1.0 / sa;
+      phN[0] = a0 * ia; phN[1] = a1 * ia; phN[2] = a2 * ia;
+#pragma unroll
+      for (int r = 0; r < 3; ++r) ph[r] = cls == 1 ? Mg * phN[r] + (1.0 - Mg) * d[mu][r] : phN[r];
+    }
+    const double y = yv[mu], p2 = p2v[mu];
+    double sBh = 0, sCh = 0, sBb = 0, sCb = 0;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      sBh += ph[r] * Bh[r]; sCh += ph[r] * Ch[r];
+      sBb += ph[r] * Bb[r]; sCb += ph[r] * Cb[r];
+    }
+    const double hv = h5[2] + (sBh * y + sCh * p2);
+    const double bv = b5[2] + (sBb * y + sCb * p2);
+    const double bxv = (sBb + 2.0 * y * sCb) * iJ0;
+    // adjoints of the values at this point
+    double lhv = 0.0, lmv = 0.0, lbv = 0.0, lbx = 0.0;
+    if (mu == 0) { lhv += LL.h; lmv += LL.m; lbv += LL.b; }
+    if (mu == 3) { lhv += LR.h; lmv += LR.m; lbv += LR.b; }
+    // rint = sum_mu (w_mu J0) ((h + b) - etabar) b_x
+    const double cw = wgl[mu] * J0;
+    lhv += lrint * cw * bxv;
+    lbv += lrint * cw * bxv;
+    lbx += lrint * cw * ((hv + bv) - etabar);
+    letab -= lrint * cw * bxv;
+    // v = v0 + (sB y + sC p2); b_x = (sB_b + 2 y sC_b) / J0
+    lh0 += lhv; lm0 += lmv; lb0 += lbv;
+    const double lsBh = y * lhv, lsCh = p2 * lhv;
+    const double lsBm = y * lmv, lsCm = p2 * lmv;
+    const double lsBb = y * lbv + iJ0 * lbx, lsCb = p2 * lbv + 2.0 * y * iJ0 * lbx;
+    double lph[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      lph[r] = Bh[r] * lsBh + Ch[r] * lsCh + Bm[r] * lsBm + Cm[r] * lsCm + Bb[r] * lsBb +
+               Cb[r] * lsCb;
+      lBh[r] += ph[r] * lsBh; lCh[r] += ph[r] * lsCh;
+      lBm[r] += ph[r] * lsBm; lCm[r] += ph[r] * lsCm;
+      lBb[r] += ph[r] * lsBb; lCb[r] += ph[r] * lsCb;
+    }
+    if (cls != 0) {
+      double lphN[3];
+      if (cls == 1) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          lphN[r] = Mg * lph[r];
+          lMg += (phN[r] - d[mu][r]) * lph[r];
+        }
+      } else {
+        lphN[0] = lph[0]; lphN[1] = lph[1]; lphN[2] = lph[2];
+      }
+      const double dotp = phN[0] * lphN[0] + phN[1] * lphN[1] + phN[2] * lphN[2];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) lK[r] += d[mu][r] * ((lphN[r] - dotp) / sa);
+    }
+  }
+  double lbeta[3] = {0, 0, 0}, ltau = 0.0;
+  if (cls != 0) {
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const double lz = 2.0 * z[r] * lK[r];
+      const double den = beta[r] + eps;
+      ltau += lz / den;
+      lbeta[r] -= lz * z[r] / den;
+    }
+  }
+  if (cls == 1) {
+    const double lgam = 2.0 * lMg;
+    const double den = betaA + eps;
+    ltau += lgam / den;
+    const double lbA = -lgam * gam / den;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) lbeta[r] += lbA / 3.0;
+  }
+  {
+    const double dd = beta[0] - beta[2];
+    const double sg = dd > 0.0 ? 1.0 : (dd < 0.0 ? -1.0 : 0.0);
+    lbeta[0] += sg * ltau;
+    lbeta[2] -= sg * ltau;
+  }
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    lBv[r] += 2.0 * kap * Bv[r] * lbeta[r];
+    lCv[r] += 2.0 * kapC * Cv[r] * lbeta[r];
+    lBm[r] += 2.0 * kap * Bm[r] * lbeta[r];
+    lCm[r] += 2.0 * kapC * Cm[r] * lbeta[r];
+  }
+  double ldv[4] = {0, 0, 0, 0}, ldh[4] = {0, 0, 0, 0}, ldm[4] = {0, 0, 0, 0}, ldb[4] = {0, 0, 0, 0};
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const int c1 = C1[r], c2 = C2[r];
+    ldv[c1] += kb1[r] * lBv[r] + kc1[r] * lCv[r]; ldv[c2] += kb2[r] * lBv[r] + kc2[r] * lCv[r];
+    ldh[c1] += kb1[r] * lBh[r] + kc1[r] * lCh[r]; ldh[c2] += kb2[r] * lBh[r] + kc2[r] * lCh[r];
+    ldm[c1] += kb1[r] * lBm[r] + kc1[r] * lCm[r]; ldm[c2] += kb2[r] * lBm[r] + kc2[r] * lCm[r];
+    ldb[c1] += kb1[r] * lBb[r] + kc1[r] * lCb[r]; ldb[c2] += kb2[r] * lBb[r] + kc2[r] * lCb[r];
+  }
+#pragma unroll
+  for (int k = 0; k < 5; ++k) { out.lv[k] = 0; out.lh[k] = 0; out.lm[k] = 0; out.lb[k] = 0; }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    out.lv[idx[c]] += ldv[c]; out.lv[2] -= ldv[c];
+    out.lh[idx[c]] += ldh[c]; out.lh[2] -= ldh[c];
+    out.lm[idx[c]] += ldm[c]; out.lm[2] -= ldm[c];
+    out.lb[idx[c]] += ldb[c]; out.lb[2] -= ldb[c];
+  }
+  out.lh[2] += lh0;
+  out.lm[2] += lm0;
+  out.lb[2] += lb0;
+  out.letabar = letab;
+}
+
+// ----------------------------------------------------------------------------
+// Kernels of the reverse stage
+// ----------------------------------------------------------------------------
+struct AdjTile {
+  int32_t inst;
+  int32_t pad;
+  int64_t c0;
+};
+
+// rho . D summed per instance, and the face/trace that attains alpha.
+template <int B>
+__global__ __launch_bounds__(B) void k_adj_alpha(AdjBufs ab, const AdjTile* __restrict__ tiles,
+                                                 int s) {
+  __shared__ double red[(B / 64) * 8];
+  const AdjTile tl = tiles[blockIdx.x];
+  const int i = tl.inst;
+  const int64_t co = ab.cell_off[i], n = ab.cell_off[i + 1] - co, no = co + i;
+  const int64_t j = tl.c0 + threadIdx.x;
+  const double dt = ab.scal[(int64_t)i * 8 + 1];
+  const double alpha = ab.scal[(int64_t)i * 8 + 1 + s];
+  double acc = 0.0;
+  if (j < n) {
+    double Jn, Jin, Jout;
+    stage_widths(ab.x + no, ab.w + no, j, dt, s, Jn, Jin, Jout);
+    const double rf = stage_b(s) * dt / Jout;
+    const int64_t g = co + j;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc += (rf * ab.lam[c * ab.S + g]) * ab.D[c * ab.S + g];
+  }
+  if (j <= n) {
+    unsigned long long key = ~0ull;
+    if (ab.fsl[no + j] == alpha) key = 2ull * (unsigned long long)j;
+    else if (ab.fsr[no + j] == alpha) key = 2ull * (unsigned long long)j + 1ull;
+    if (key != ~0ull) atomicMin(&ab.akey[i], key);
+  }
+  double rv[1] = {acc};
+  const int op[1] = {2};
+  block_reduce<B, 1>(rv, op, red);
+  if (threadIdx.x == 0) atomicAdd(&ab.lalpha[i], rv[0]);
+}
+
+__global__ void k_adj_reset(AdjBufs ab) {
+  for (int i = threadIdx.x; i < ab.ninst; i += blockDim.x) {
+    ab.lalpha[i] = 0.0;
+    ab.akey[i] = ~0ull;
+  }
+}
+
+template <int B>
+struct SmemAdj {
+  double e[B + 4], m[B + 4], b[B + 4], J[B + 4];
+  double rho[3][B + 4];
+  double tr[6][B];
+  double lf[6][B];  // face t: adjoints of cell t-1's right trace (0..2) and cell t's left (3..5)
+  double B1[B];
+};
+
+template <int B>
+__global__ __launch_bounds__(B) void k_adj_stage(AdjBufs ab, Consts cs,
+                                                 const AdjTile* __restrict__ tiles, int s) {
+  __shared__ SmemAdj<B> sm;
+  const AdjTile tl = tiles[blockIdx.x];
+  const int i = tl.inst;
+  const int64_t co = ab.cell_off[i], n = ab.cell_off[i + 1] - co, no = co + i;
+  const int64_t CS = ab.S + 2 * (int64_t)ab.ninst;
+  const int64_t c0 = tl.c0;
+  const int t = threadIdx.x;
+  const double* x = ab.x + no;
+  const double* w = ab.w + no;
+  const double dt = ab.scal[(int64_t)i * 8 + 1];
+  const double alpha = ab.scal[(int64_t)i * 8 + 1 + s];
+  const double dx = ab.scal[(int64_t)i * 8 + 5 + (s - 1)];
+  const double lalpha = ab.lalpha[i];
+  const unsigned long long akey = ab.akey[i];
+  const double bs = stage_b(s);
+  // 1. stencil data and rho for cells c0-3 .. c0+B
+  for (int q = t; q < B + 4; q += B) {
+    const int64_t k = c0 - 3 + q;
+    double e = 0, m = 0, b = 0, J = 1, r0 = 0, r1 = 0, r2 = 0;
+    if (k >= -3 && k < n + 3) {
+      double ms;
+      const int64_t src = ghost_src(cs.bc, n, k, ms);
+      double Jn, Jin, Jout;
+      stage_widths(x, w, src, dt, s, Jn, Jin, Jout);
+      const int64_t g = co + src;
+      e = ab.q[g];
+      m = ab.q[ab.S + g] * ms;
+      b = ab.q[2 * ab.S + g];
+      J = Jin;
+      if (k >= 0 && k < n) {
+        const double rf = bs * dt / Jout;
+        r0 = rf * ab.lam[g];
+        r1 = rf * ab.lam[ab.S + g];
+        r2 = rf * ab.lam[2 * ab.S + g];
+      }
+    }
+    sm.e[q] = e; sm.m[q] = m; sm.b[q] = b; sm.J[q] = J;
+    sm.rho[0][q] = r0; sm.rho[1][q] = r1; sm.rho[2][q] = r2;
+  }
+  __syncthreads();
+  // 2. forward reconstruction and limiter of cell j = c0 - 1 + t
+  const int64_t j = c0 - 1 + t;
+  const bool active = (j >= -1) && (j <= n);
+  CellRecon o, ou;
+  double h5[5], v5[5];
+  double Dx = dx;
+  if (active) {
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      h5[k] = sm.e[t + k] - sm.b[t + k];
+      v5[k] = (cs.flags & F_BETA_FROM_H) ? h5[k] : sm.e[t + k];
+    }
+    if (cs.flags & F_BETA_LOCAL) Dx = sm.J[t + 2];
+    recon_cell(v5, h5, &sm.m[t], &sm.b[t], &sm.J[t], Dx, cs.weno_eps, sm.e[t + 2], o);
+    ou = o;
+    limit_cell(h5[2], sm.m[t + 2], cs.pp_eps, o);
+    sm.tr[0][t] = o.hL; sm.tr[1][t] = o.mL; sm.tr[2][t] = o.bL;
+    sm.tr[3][t] = o.hR; sm.tr[4][t] = o.mR; sm.tr[5][t] = o.bR;
+  }
+  __syncthreads();
+  // 3. face at node j between cells j-1 (LDS index t+1) and j (t+2)
+  if (t >= 1 && j >= 0 && j <= n) {
+    const double rl[3] = {sm.rho[0][t + 1], sm.rho[1][t + 1], sm.rho[2][t + 1]};
+    const double rr[3] = {sm.rho[0][t + 2], sm.rho[1][t + 2], sm.rho[2][t + 2]};
+    const double hl = sm.tr[3][t - 1], ml = sm.tr[4][t - 1], bl = sm.tr[5][t - 1];
+    const double hr = sm.tr[0][t], mr = sm.tr[1][t], br = sm.tr[2][t];
+    TraceAdj Ll, Lr;
+    face_vjp(hl, ml, bl, hr, mr, br, w[j], alpha, cs.g, cs.dry_eps, rl, rr, sm.e[t + 1],
+             sm.e[t + 2], Ll, Lr);
+    if (akey == 2ull * (unsigned long long)j)
+      alpha_trace_vjp(hl, ml, w[j], cs.g, cs.dry_eps, lalpha, Ll);
+    if (akey == 2ull * (unsigned long long)j + 1ull)
+      alpha_trace_vjp(hr, mr, w[j], cs.g, cs.dry_eps, lalpha, Lr);
+    sm.lf[0][t] = Ll.h; sm.lf[1][t] = Ll.m; sm.lf[2][t] = Ll.b;
+    sm.lf[3][t] = Lr.h; sm.lf[4][t] = Lr.m; sm.lf[5][t] = Lr.b;
+    sm.B1[t] = 0.5 * (bl + br);
+  }
+  __syncthreads();
+  // 4. cells written here: owned cells and the ghost cells -1, n
+  const bool owned = (t >= 1) && (t <= B - 2) && (j >= 0) && (j < n);
+  const bool ghost_out = active && (j == -1 || j == n);
+  if (!(owned || ghost_out)) return;
+  TraceAdj LL{0, 0, 0}, LR{0, 0, 0};
+  if (j >= 0) { LL.h = sm.lf[3][t]; LL.m = sm.lf[4][t]; LL.b = sm.lf[5][t]; }
+  if (j < n) { LR.h = sm.lf[0][t + 1]; LR.m = sm.lf[1][t + 1]; LR.b = sm.lf[2][t + 1]; }
+  double lrint = 0.0, letabar = 0.0;
+  if (j >= 0 && j < n) {
+    // S_j = g/2 dB2 - g etabar dB1 - g rint (dB2 part is in the face adjoints)
+    const double rm = sm.rho[1][t + 2];
+    lrint = -cs.g * rm;
+    letabar += -cs.g * rm * (sm.B1[t + 1] - sm.B1[t]);
+  }
+  double lhbar = 0.0, lmbar = 0.0;
+  limit_vjp(h5[2], sm.m[t + 2], cs.pp_eps, ou, LL, LR, lhbar, lmbar);
+  ReconAdjOut ra;
+  recon_cell_vjp(v5, h5, &sm.m[t], &sm.b[t], &sm.J[t], Dx, cs.weno_eps, sm.e[t + 2], LL, LR, lrint,
+                 ra);
+  // to (eta, hu, b): h = eta - b; indicator variable eta (or h)
+  const bool vh = (cs.flags & F_BETA_FROM_H) != 0;
+  const int64_t ci = co + 2 * (int64_t)i + (j + 1);
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    double lh = ra.lh[k] + (vh ? ra.lv[k] : 0.0);
+    double le = lh + (vh ? 0.0 : ra.lv[k]);
+    double lb = ra.lb[k] - lh;
+    double lm = ra.lm[k];
+    if (k == 2) {
+      le += lhbar + letabar + ra.letabar;
+      lb -= lhbar;
+      lm += lmbar;
+    }
+    ab.C[(int64_t)(3 * k + 0) * CS + ci] = le;
+    ab.C[(int64_t)(3 * k + 1) * CS + ci] = lm;
+    ab.C[(int64_t)(3 * k + 2) * CS + ci] = lb;
+  }
+}
+
+// lambda^(s-1) = b_s J^(s-1) mu + sum of stencil contributions; the base-state
+// adjoint a_s J^n mu is accumulated (stage 3 sets it, stage 1 adds it in).
+template <int B>
+__global__ __launch_bounds__(B) void k_adj_gather(AdjBufs ab, Consts cs,
+                                                  const AdjTile* __restrict__ tiles, int s) {
+  const AdjTile tl = tiles[blockIdx.x];
+  const int i = tl.inst;
+  const int64_t co = ab.cell_off[i], n = ab.cell_off[i + 1] - co, no = co + i;
+  const int64_t CS = ab.S + 2 * (int64_t)ab.ninst;
+  const int64_t k = tl.c0 + threadIdx.x;
+  if (k >= n) return;
+  const double dt = ab.scal[(int64_t)i * 8 + 1];
+  double Jn, Jin, Jout;
+  stage_widths(ab.x + no, ab.w + no, k, dt, s, Jn, Jin, Jout);
+  const int64_t g = co + k;
+  const int64_t cbase = co + 2 * (int64_t)i + 1;  // C index of cell 0
+  double acc[3];
+  double mu[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    mu[c] = ab.lam[c * ab.S + g] / Jout;
+    acc[c] = stage_b(s) * Jin * mu[c];
+  }
+#pragma unroll
+  for (int o = 0; o < 5; ++o) {
+    const int64_t jj = k + 2 - o;
+    if (jj < -1 || jj > n) continue;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[c] += ab.C[(int64_t)(3 * o + c) * CS + cbase + jj];
+  }
+  // ghost copies of this cell in the stencils of the boundary cells
+  if (k < 3 || k >= n - 3) {
+    const int64_t js[6] = {-1, 0, 1, n - 2, n - 1, n};
+    for (int a = 0; a < 6; ++a) {
+      const int64_t jj = js[a];
+      for (int o = 0; o < 5; ++o) {
+        const int64_t gk = jj - 2 + o;
+        if (gk >= 0 && gk < n) continue;
+        double ms;
+        if (ghost_src(cs.bc, n, gk, ms) != k) continue;
+        acc[0] += ab.C[(int64_t)(3 * o + 0) * CS + cbase + jj];
+        acc[1] += ms * ab.C[(int64_t)(3 * o + 1) * CS + cbase + jj];
+        acc[2] += ab.C[(int64_t)(3 * o + 2) * CS + cbase + jj];
+      }
+    }
+  }
+  const double as = stage_a(s);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double base = as * Jn * mu[c];
+    double lb = s == 3 ? base : ab.lbase[c * ab.S + g] + base;
+    if (s == 1) {
+      ab.lam[c * ab.S + g] = acc[c] + lb;
+    } else {
+      ab.lam[c * ab.S + g] = acc[c];
+      ab.lbase[c * ab.S + g] = lb;
+    }
+  }
+}
+
+}  // namespace alew_dev

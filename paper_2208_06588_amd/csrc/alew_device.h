@@ -366,7 +366,8 @@ __device__ __forceinline__ int limit_cell(double hbar, double mbar, double pp_ep
 // ----------------------------------------------------------------------------
 struct Face {
   double Fc1, Fc2, Gc, je, jm, jb, B1, B2;
-  double speed;  // max over both traces of |u - w| + sqrt(g h)
+  double speed;   // max over both traces of |u - w| + sqrt(g h)
+  double sl, sr;  // the two trace speeds
 };
 
 __device__ __forceinline__ void face_flux(double hl, double ml, double bl, double hr, double mr,
@@ -390,6 +391,8 @@ __device__ __forceinline__ void face_flux(double hl, double ml, double bl, doubl
   const double sl = fabs(ul - w) + sqrt(g * fmax(hl, 0.0));
   const double sr = fabs(ur - w) + sqrt(g * fmax(hr, 0.0));
   f.speed = fmax(sl, sr);
+  f.sl = sl;
+  f.sr = sr;
 }
 
 }  // namespace alew_dev

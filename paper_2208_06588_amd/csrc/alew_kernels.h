@@ -5,6 +5,16 @@
 
 namespace alew_dev {
 
+// Records kept by the forward recomputation of the adjoint (all NULL otherwise).
+struct Dump {
+  double* q;     // [3 stages][3 comps][S]: stage inputs q^(s-1)
+  double* D;     // [3][3][S]: alpha coefficient of the residual
+  double* fs;    // [3 stages][2 sides][S + ninst]: trace speeds |u - w| + sqrt(g h) per face
+  double* xw;    // [2][S + ninst]: x^n and w^n of the step
+  double* scal;       // [ninst][8] of this step: t, dt, alpha_1..3, dx_0..2
+  double* scal_next;  // the next step's record (t, dt, dx_0 are set at step end)
+};
+
 // Buffers of a packed batch.  Component c of a 3-vector array V lives at
 // V + c * S, S = total cell count.  Node arrays hold ncell+1 entries per
 // instance (node offset of instance i = cell_off[i] + i).
@@ -29,6 +39,7 @@ struct Bufs {
   int64_t S;
   int32_t ninst;
   int32_t pad;
+  Dump dump;
 };
 
 // Per-instance view used by the tile bodies.
@@ -148,6 +159,11 @@ __device__ __forceinline__ StageRes stage_tile(const Bufs& bf, const Consts& cs,
     sm.fl[0][t] = f.Fc1; sm.fl[1][t] = f.Fc2; sm.fl[2][t] = f.Gc; sm.fl[3][t] = f.je;
     sm.fl[4][t] = f.jm; sm.fl[5][t] = f.jb; sm.fl[6][t] = f.B1; sm.fl[7][t] = f.B2;
     fspeed = f.speed;
+    if (bf.dump.fs) {
+      const int64_t NN = bf.S + bf.ninst;
+      bf.dump.fs[(int64_t)(2 * (sc.s - 1)) * NN + v.no + j] = f.sl;
+      bf.dump.fs[(int64_t)(2 * (sc.s - 1) + 1) * NN + v.no + j] = f.sr;
+    }
   }
   __syncthreads();
   // 4. owned cells: residual split, stage combination
@@ -179,6 +195,11 @@ __device__ __forceinline__ StageRes stage_tile(const Bufs& bf, const Consts& cs,
     double* Do = (sc.s == 2) ? bf.D1 : bf.D0;
     Po[gi] = Pe; Po[bf.S + gi] = Pm; Po[2 * bf.S + gi] = Pb;
     Do[gi] = De; Do[bf.S + gi] = Dm; Do[2 * bf.S + gi] = Db;
+    if (bf.dump.q) {
+      const int64_t o = (int64_t)(3 * (sc.s - 1)) * bf.S + gi;
+      bf.dump.q[o] = ebar; bf.dump.q[o + bf.S] = mbar; bf.dump.q[o + 2 * bf.S] = bbar;
+      bf.dump.D[o] = De; bf.dump.D[o + bf.S] = Dm; bf.dump.D[o + 2 * bf.S] = Db;
+    }
     const double Jnext = sc.as * Jn + sc.bs * (Jj + sc.dt * dw);
     maxJ = Jnext;
     if (!(Jnext > 0.0)) st |= SB_MESH;
@@ -229,6 +250,15 @@ __device__ __forceinline__ FinalRes final_tile(const Bufs& bf, const Consts& cs,
     const double b = (bf.P0[2 * bf.S + gi] + c * bf.D0[2 * bf.S + gi]) / J3;
     bf.eta[gi] = e; bf.m[gi] = m; bf.b[gi] = b;
     const double xn0 = x0 + dt * w0, xn1 = x1 + dt * w1;
+    if (bf.dump.xw) {
+      const int64_t NN = bf.S + bf.ninst;
+      bf.dump.xw[v.no + j] = x0;
+      bf.dump.xw[NN + v.no + j] = w0;
+      if (j == v.n - 1) {
+        bf.dump.xw[v.no + v.n] = x1;
+        bf.dump.xw[NN + v.no + v.n] = w1;
+      }
+    }
     v.xnew[j] = xn0;
     if (j == v.n - 1) v.xnew[v.n] = xn1;
     const double Jnew = xn1 - xn0;

@@ -52,8 +52,12 @@ def _params(bc, cfl=0.6):
     return g, o
 
 
-@pytest.mark.parametrize("kind,ckpt", [("smooth", 3), ("step", 2), ("wetdry", 16)])
-def test_adjoint_matches_oracle(dev, kind, ckpt):
+# The wet/dry case divides by trace depths of order 1e-3 (u = hu/h and its
+# derivatives -u/h, 1/h), which multiplies the round-off difference between the
+# two evaluation orders; it gets a 10x looser bound.
+@pytest.mark.parametrize("kind,ckpt,tol", [("smooth", 3, 1e-11), ("step", 2, 1e-11),
+                                           ("wetdry", 16, 1e-10)])
+def test_adjoint_matches_oracle(dev, kind, ckpt, tol):
     n, nsteps, ng = 64, 7, 6
     xi, h, hu, b, bc = _case(kind, n)
     gp, op = _params(bc, cfl=0.3)
@@ -77,7 +81,7 @@ def test_adjoint_matches_oracle(dev, kind, ckpt):
         g = g.cpu().numpy()
         scale = max(1.0, np.abs(o).max())
         err = np.abs(g - o).max() / scale
-        assert err <= 1e-11, err
+        assert err <= tol, err
 
 
 def test_adjoint_against_gpu_finite_differences(dev):

@@ -87,6 +87,62 @@ def cpu_baseline(bt, ninst_sample, steps):
                        f"{steps} CFL steps each, one instance per thread; {wall:.1f} s wall")
 
 
+def adjoint_leg(dev, ninst, ncell, nsteps, ngauge, ckpt):
+    """Adjoint/forward time ratio on the bathymetry-inversion batch: ninst
+    instances of ncell cells, nsteps frozen CFL steps, gauge misfit at ngauge
+    gauges per instance, checkpoints every ckpt steps."""
+    import torch
+    from paper_2208_06588_amd import alew, workloads as W
+    t0 = time.perf_counter()
+    bt = W.inversion_batch(ninst=ninst, n=ncell, ngauge=ngauge)
+    log(f"adjoint workload: {ninst} x {ncell} cells ({time.perf_counter() - t0:.1f} s to build)")
+    off = [int(v) for v in bt["cell_off"]]
+    S = off[-1]
+    p = alew.params(bc="transmissive", mesh="sine", mesh_A=0.05, mesh_k=1.0, mesh_omega=np.pi,
+                    cfl=0.6)
+    T = {k: torch.tensor(bt[k], dtype=torch.float64, device=dev)
+         for k in ("h", "hu", "b", "x", "xi", "gauge_x", "b_true")}
+    ctx = alew.Context(S, ninst)
+    ctx.set_launch(engine=alew.ENGINE_STAGES, block=256, use_graph=1)
+    # frozen step sizes: the CFL steps of a run from the initial state
+    dts = torch.zeros(ninst * nsteps, dtype=torch.float64, device=dev)
+    W0 = {k: T[k].clone() for k in ("h", "hu", "b", "x")}
+    ctx.run(p, off, W0["h"], W0["hu"], W0["b"], W0["x"], T["xi"], max_steps=[nsteps] * ninst,
+            dt_log=dts, dts_stride=nsteps)
+    # observations from the same run over the "true" bottom
+    gh_obs = torch.zeros(ninst * ngauge, dtype=torch.float64, device=dev)
+    htrue = torch.clamp(T["h"] + T["b"] - T["b_true"], min=0.0)
+    ctx.adjoint(p, off, htrue, T["hu"], T["b_true"], T["x"], T["xi"], nsteps, dts, ngauge,
+                T["gauge_x"], gh_obs, None, ckpt_every=ckpt)
+    # forward alone (same frozen steps)
+    W1 = {k: T[k].clone() for k in ("h", "hu", "b", "x")}
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    ctx.run(p, off, W1["h"], W1["hu"], W1["b"], W1["x"], T["xi"], max_steps=[nsteps] * ninst,
+            dts=dts, dts_stride=nsteps)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - a
+    # gradient of 0.5 |gauge_h - obs|^2: forward value, then the adjoint call
+    gh = torch.zeros(ninst * ngauge, dtype=torch.float64, device=dev)
+    ctx.adjoint(p, off, T["h"], T["hu"], T["b"], T["x"], T["xi"], nsteps, dts, ngauge,
+                T["gauge_x"], gh, None, ckpt_every=ckpt)
+    gbar = gh - gh_obs
+    d3 = [torch.zeros(S, dtype=torch.float64, device=dev) for _ in range(3)]
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    ctx.adjoint(p, off, T["h"], T["hu"], T["b"], T["x"], T["xi"], nsteps, dts, ngauge,
+                T["gauge_x"], gh, gbar, *d3, ckpt_every=ckpt)
+    torch.cuda.synchronize()
+    t_adj = time.perf_counter() - a
+    loss = float(0.5 * (gbar ** 2).sum())
+    return dict(instances=ninst, cells=S, steps=nsteps, gauges_per_instance=ngauge,
+                ckpt_every=ckpt, forward_s=round(t_fwd, 4), adjoint_s=round(t_adj, 4),
+                ratio=round(t_adj / t_fwd, 3), loss=loss,
+                grad_b_norm=float(torch.linalg.vector_norm(d3[2])),
+                note="adjoint_s covers the checkpointed forward, the segment recomputation "
+                     "and the reverse sweep")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,6 +157,10 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-speedup", action="store_true",
                     help="skip the batched vs per-instance comparison")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward ratio")
+    ap.add_argument("--adj-ninst", type=int, default=256)
+    ap.add_argument("--adj-cells", type=int, default=65536)
+    ap.add_argument("--adj-steps", type=int, default=200)
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="first copy a buffer of this many MiB (calibrates profiler byte counters)")
     args = ap.parse_args()
@@ -216,6 +276,13 @@ def main():
                                       per_instance_s=round(per_inst, 4),
                                       speedup=round(per_inst / batched, 2))
         del Tb, Tp, ctx1
+
+    if not args.no_adjoint:
+        del ctx, T
+        torch.cuda.empty_cache()
+        out["adjoint"] = adjoint_leg(dev, args.adj_ninst, args.adj_cells, args.adj_steps, 64, 16)
+        out["adjoint_forward_ratio"] = out["adjoint"]["ratio"]
+        log(f"adjoint: {out['adjoint']}")
 
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")

@@ -240,3 +240,51 @@ class Context:
 
 def version() -> str:
     return lib().alew_version().decode()
+
+
+class _GaugeFn(torch.autograd.Function):
+    """gauge_h = G(h0, hu0, b0); backward runs alew_adjoint with the incoming
+    gradient as gauge_bar (checkpointed recomputation of the forward)."""
+
+    @staticmethod
+    def forward(fctx, h0, hu0, b0, problem):
+        gh = torch.empty(problem.ninst * problem.ngauge, dtype=torch.float64, device=h0.device)
+        problem.ctx.adjoint(problem.p, problem.cell_off, h0.contiguous(), hu0.contiguous(),
+                            b0.contiguous(), problem.x0, problem.xi, problem.nsteps, problem.dts,
+                            problem.ngauge, problem.gauge_x, gh, None, ckpt_every=problem.ckpt_every,
+                            t0=problem.t0)
+        fctx.save_for_backward(h0, hu0, b0)
+        fctx.problem = problem
+        return gh
+
+    @staticmethod
+    def backward(fctx, grad):
+        h0, hu0, b0 = fctx.saved_tensors
+        pr = fctx.problem
+        gh = torch.empty_like(grad)
+        dh, dhu, db = (torch.empty_like(h0) for _ in range(3))
+        pr.ctx.adjoint(pr.p, pr.cell_off, h0.contiguous(), hu0.contiguous(), b0.contiguous(), pr.x0,
+                       pr.xi, pr.nsteps, pr.dts, pr.ngauge, pr.gauge_x, gh,
+                       grad.contiguous().to(torch.float64), dh, dhu, db,
+                       ckpt_every=pr.ckpt_every, t0=pr.t0)
+        return dh, dhu, db, None
+
+
+class GaugeProblem:
+    """Differentiable map from an initial state (h0, hu0, b0) to the mean depths
+    at gauges after nsteps frozen steps on a prescribed moving mesh.
+
+    >>> G = GaugeProblem(ctx, params, cell_off, x0, xi, nsteps, dts, gauge_x, ngauge)
+    >>> loss = 0.5 * ((G(h0, hu0, b0) - obs) ** 2).sum(); loss.backward()
+    """
+
+    def __init__(self, ctx: Context, p: Params, cell_off, x0, xi, nsteps, dts, gauge_x, ngauge,
+                 ckpt_every=16, t0=0.0):
+        self.ctx, self.p, self.cell_off = ctx, p, [int(v) for v in cell_off]
+        self.ninst = len(self.cell_off) - 1
+        self.x0, self.xi, self.nsteps, self.dts = x0, xi, int(nsteps), dts
+        self.gauge_x, self.ngauge = gauge_x, int(ngauge)
+        self.ckpt_every, self.t0 = int(ckpt_every), float(t0)
+
+    def __call__(self, h0, hu0, b0):
+        return _GaugeFn.apply(h0, hu0, b0, self)

@@ -199,29 +199,56 @@ def inversion_batch(ninst: int = 256, n: int = 65536, seed: int = 2208065883,
     (amplitudes U[0,0.3], widths U[0.01,0.05], centres U[0,1]); still water
     eta = 1 plus a Gaussian hump 0.05 (centre U[0.25,0.75]); hu = 0;
     ngauge gauges per instance uniform in [0.02, 0.98]; also an independent
-    'true' bottom for synthetic observations."""
+    'true' bottom for synthetic observations.  Draw order per instance:
+    bottom (A, s, c), hump centre, true bottom (A, s, c), gauges."""
+    import torch  # multi-threaded exp on the host; values do not depend on the thread count
+
     rng = np.random.Generator(np.random.PCG64(seed))
-    xi = uniform_nodes(n, 0.0, 1.0)
-
-    def bottom():
-        A = rng.uniform(0.0, 0.3, 8)
-        s = rng.uniform(0.01, 0.05, 8)
-        c = rng.uniform(0.0, 1.0, 8)
-        return lambda x: sum(A[k] * np.exp(-((x - c[k]) / s[k]) ** 2) for k in range(8))
-
-    insts, true_b, gauges = [], [], []
+    params = []
     for _ in range(ninst):
-        bf = bottom()
+        bot = (rng.uniform(0.0, 0.3, 8), rng.uniform(0.01, 0.05, 8), rng.uniform(0.0, 1.0, 8))
         ch = rng.uniform(0.25, 0.75)
-        etaf = lambda x, ch=ch: 1.0 + 0.05 * np.exp(-((x - ch) / 0.05) ** 2)
-        b = cell_averages(bf, xi)
-        h = cell_averages(lambda x: np.maximum(0.0, etaf(x) - bf(x)), xi)
-        insts.append((xi, h, np.zeros(n), b))
-        bt = bottom()
-        true_b.append(cell_averages(bt, xi))
-        gauges.append(np.sort(rng.uniform(0.02, 0.98, ngauge)))
+        tru = (rng.uniform(0.0, 0.3, 8), rng.uniform(0.01, 0.05, 8), rng.uniform(0.0, 1.0, 8))
+        gx = np.sort(rng.uniform(0.02, 0.98, ngauge))
+        params.append((bot, ch, tru, gx))
+    xi = uniform_nodes(n, 0.0, 1.0)
+    a, bnd = xi[:-1], xi[1:]
+    mid = 0.5 * (a + bnd)
+    half = 0.5 * (bnd - a)
+    xs = torch.from_numpy(mid[:, None] + half[:, None] * _GL5_X[None, :])
+    wts = torch.from_numpy(_GL5_W)
+    hw = torch.from_numpy(half)
+    wid = torch.from_numpy(bnd - a)
+
+    def avg(vals):  # cell averages from values at the Gauss points, per instance row
+        return ((vals * wts).sum(dim=-1) * hw / wid).numpy()
+
+    def bumps(P):  # P: list of (A, s, c) per instance -> (m, n, 5) values
+        A = torch.tensor(np.stack([p[0] for p in P]))[:, :, None, None]
+        sw = torch.tensor(np.stack([p[1] for p in P]))[:, :, None, None]
+        c = torch.tensor(np.stack([p[2] for p in P]))[:, :, None, None]
+        v = torch.zeros((len(P),) + tuple(xs.shape), dtype=torch.float64)
+        z = torch.empty_like(v)
+        for k in range(8):
+            torch.sub(xs[None], c[:, k], out=z)
+            z.div_(sw[:, k])
+            z.mul_(z).neg_().exp_().mul_(A[:, k])
+            v.add_(z)
+        return v
+
+    hs, bs, bts, gxs = [], [], [], []
+    for c0 in range(0, ninst, 16):
+        chunk = params[c0:c0 + 16]
+        bv = bumps([q[0] for q in chunk])
+        ch = torch.tensor([q[1] for q in chunk])[:, None, None]
+        eta = 1.0 + 0.05 * torch.exp(-((xs[None] - ch) / 0.05) ** 2)
+        hs.extend(avg(torch.clamp(eta - bv, min=0.0)))
+        bs.extend(avg(bv))
+        bts.extend(avg(bumps([q[2] for q in chunk])))
+        gxs.extend(q[3] for q in chunk)
+    insts = [(xi, h, np.zeros(n), b) for h, b in zip(hs, bs)]
     out = pack(insts, bc="transmissive", cfl=0.6, weno_eps=1e-6, mesh="sine", mesh_A=0.05,
                mesh_k=1.0, mesh_omega=math.pi)
-    out["b_true"] = np.concatenate(true_b)
-    out["gauge_x"] = np.concatenate(gauges)
+    out["b_true"] = np.concatenate(bts)
+    out["gauge_x"] = np.concatenate(gxs)
     return out

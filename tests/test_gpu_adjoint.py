@@ -84,11 +84,20 @@ def test_adjoint_matches_oracle(dev, kind, ckpt, tol):
         assert err <= tol, err
 
 
+def _accuracy_case(n):
+    # Example 5.1 data: strongly varying, so the hybrid weights stay in the
+    # linear class and the map is smooth at the scale of the FD step (with
+    # nearly flat water the WENO-Z weights vary on the scale of weno_eps = 1e-6,
+    # below which central differences with step 1e-6 are not accurate).
+    wl = W.accuracy_1d(n)
+    return wl["xi"], wl["h"], wl["hu"], wl["b"], "periodic"
+
+
 def test_adjoint_against_gpu_finite_differences(dev):
     """Central differences of the GPU forward (alew_run with the same frozen
     steps) along random directions of (h0, hu0, b0)."""
     n, nsteps, ng = 96, 6, 8
-    xi, h, hu, b, bc = _case("smooth", n)
+    xi, h, hu, b, bc = _accuracy_case(n)
     gp, op = _params(bc)
     dts = np.full(nsteps, 1.5e-3)
     rng = np.random.default_rng(5)
@@ -174,3 +183,40 @@ def test_batched_adjoint_equals_single_instances(dev):
         for k in range(3):
             scale = float(o3[k].abs().max()) or 1.0
             assert float((o3[k] - g3[k][a:e]).abs().max()) <= 1e-13 * scale
+
+
+def test_autograd_function_gradients(dev):
+    """torch.autograd through the gauge map equals the direct adjoint call and
+    central differences of the loss."""
+    n, nsteps, ng = 72, 5, 6
+    xi, h, hu, b, bc = _accuracy_case(n)
+    gp, _ = _params(bc)
+    rng = np.random.default_rng(21)
+    T = {k: _t(v, dev) for k, v in dict(x=xi, xi=xi, dts=np.full(nsteps, 1e-3),
+                                         gx=np.sort(rng.uniform(0.05, 0.95, ng))).items()}
+    ctx = alew.Context(n, 1)
+    G = alew.GaugeProblem(ctx, gp, [0, n], T["x"], T["xi"], nsteps, T["dts"], T["gx"], ng,
+                          ckpt_every=2)
+    obs = _t(rng.normal(size=ng) * 0.1 + 6.0, dev)
+    h0 = _t(h, dev).requires_grad_()
+    hu0 = _t(hu, dev).requires_grad_()
+    b0 = _t(b, dev).requires_grad_()
+    loss = 0.5 * ((G(h0, hu0, b0) - obs) ** 2).sum()
+    loss.backward()
+    with torch.no_grad():
+        gbar = G(h0, hu0, b0) - obs
+        gh = torch.zeros(ng, dtype=torch.float64, device=dev)
+        d3 = [torch.zeros(n, dtype=torch.float64, device=dev) for _ in range(3)]
+        ctx.adjoint(gp, [0, n], h0.detach(), hu0.detach(), b0.detach(), T["x"], T["xi"], nsteps,
+                    T["dts"], ng, T["gx"], gh, gbar, *d3, ckpt_every=2)
+        for a, bb in zip((h0.grad, hu0.grad, b0.grad), d3):
+            assert torch.allclose(a, bb, rtol=0, atol=1e-14 * float(bb.abs().max() + 1))
+        v = [torch.randn(n, dtype=torch.float64, device=dev) for _ in range(3)]
+        e = 1e-6
+
+        def L(s):
+            return float(0.5 * ((G(h0 + s * v[0], hu0 + s * v[1], b0 + s * v[2]) - obs) ** 2).sum())
+
+        fd = (L(e) - L(-e)) / (2 * e)
+        ad = float(sum(torch.dot(g, vv) for g, vv in zip((h0.grad, hu0.grad, b0.grad), v)))
+        assert abs(fd - ad) <= 1e-6 * max(1e-3, abs(ad)), (fd, ad)

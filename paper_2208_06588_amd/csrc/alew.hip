@@ -63,7 +63,11 @@ __global__ __launch_bounds__(B) void k_prep(Bufs bf, Consts cs, const Tile* __re
   }
   if (j <= v.n) {
     if (cs.mesh == MESH_SINE || cs.mesh == MESH_PAPER) {
+      // the map's node amplitudes A S(xi); periodic meshes repeat node 0 at node n
       const double* xi = bf.xi + v.no;
+      const int64_t jj = (cs.bc == BC_PERIODIC && j == v.n) ? 0 : j;
+      const double S = mesh_shape(cs, xi[jj], xi[0], xi[v.n]);
+      bf.w[v.no + j] = cs.mesh_A * S;
       sabs = fabs(mesh_shape(cs, xi[j], xi[0], xi[v.n]));
     } else if (cs.mesh == MESH_GIVEN && wgiven) {
       const double wv = wgiven[j];
@@ -84,15 +88,6 @@ __global__ __launch_bounds__(B) void k_prep(Bufs bf, Consts cs, const Tile* __re
     if (cs.mesh == MESH_GIVEN) amax_pos(&I.r_W, rv[6]);
     else amax_pos((unsigned long long*)&I.smax, rv[6]);
   }
-}
-
-template <int B>
-__global__ __launch_bounds__(B) void k_wmap(Bufs bf, Consts cs, const Tile* __restrict__ tiles) {
-  const Tile tl = tiles[blockIdx.x];
-  const Inst& I = bf.inst[tl.inst];
-  if (!I.active) return;
-  View v = make_view(bf, tl.inst, I);
-  wmap_tile<B>(bf, cs, v, I.t, I.dt, tl.c0);
 }
 
 template <int B>
@@ -122,6 +117,7 @@ __global__ __launch_bounds__(B) void k_stage(Bufs bf, Consts cs, const Tile* __r
   const double bprev = s == 2 ? 1.0 : 0.25;
   sc.cprev = s == 1 ? 0.0 : bprev * I.dt * I.alpha[s - 2];
   sc.dx = I.dx[s - 1];
+  sc.wsc = I.wscale;
   uint8_t* cl = bf.cls ? bf.cls + (int64_t)(s - 1) * bf.S + v.co : nullptr;
   StageRes r = stage_tile<B>(bf, cs, v, sc, tl.c0, sm, cl);
   if (threadIdx.x == 0) {
@@ -143,7 +139,7 @@ __global__ __launch_bounds__(B) void k_final(Bufs bf, Consts cs, const Tile* __r
   Inst& I = bf.inst[tl.inst];
   if (!I.active) return;
   View v = make_view(bf, tl.inst, I);
-  FinalRes r = final_tile<B>(bf, cs, v, I.dt, I.alpha[2], tl.c0, red);
+  FinalRes r = final_tile<B>(bf, cs, v, I.dt, I.alpha[2], I.wscale, tl.c0, red);
   if (threadIdx.x == 0) {
     amax_pos(&I.r_speed, r.speed);
     amin_pos(&I.r_minJ, r.minJ);
@@ -187,6 +183,7 @@ __device__ void boundary_update(Inst& I, const Consts& cs, const Bufs& bf, int i
     return;
   }
   I.dt = dt;
+  I.wscale = (cs.mesh == MESH_SINE || cs.mesh == MESH_PAPER) ? chord_factor(cs, I.t, dt) : 1.0;
   if (bf.dt_log) bf.dt_log[(int64_t)i * bf.dts_stride + I.steps] = dt;
   I.dx[0] = bitsd(I.r_maxJ);
   if (bf.dump.scal_next) {
@@ -292,11 +289,7 @@ __global__ __launch_bounds__(B) void k_persistent(Bufs bf, Consts cs,
     while (sI.active && (steps_limit <= 0 || launched < steps_limit)) {
       const View v = make_view(bf, i, sI);
       const double dt = sI.dt;
-      if (cs.mesh == MESH_SINE || cs.mesh == MESH_PAPER) {
-        for (int64_t k0 = 0; k0 <= v.n; k0 += B) wmap_tile<B>(bf, cs, v, sI.t, dt, k0);
-        __syncthreads();
-      }
-      double c_cls[3] = {0, 0, 0}, c_lim = 0, c_neg = 0;
+      unsigned long long c_cls[3] = {0, 0, 0}, c_lim = 0, c_neg = 0;
       int st = 0;
       for (int s = 1; s <= 3; ++s) {
         StageScal sc;
@@ -307,6 +300,7 @@ __global__ __launch_bounds__(B) void k_persistent(Bufs bf, Consts cs,
         const double bprev = s == 2 ? 1.0 : 0.25;
         sc.cprev = s == 1 ? 0.0 : bprev * dt * sI.alpha[s - 2];
         sc.dx = sI.dx[s - 1];
+        sc.wsc = sI.wscale;
         double amax = 0.0, jmax = 0.0;
         for (int64_t c0 = 0; c0 < v.n; c0 += B - 2) {
           StageRes r = stage_tile<B>(bf, cs, v, sc, c0, sm, nullptr);
@@ -325,7 +319,7 @@ __global__ __launch_bounds__(B) void k_persistent(Bufs bf, Consts cs,
       }
       double fsp = 0.0, fminJ = INFINITY, fmaxJ = 0.0, fhmin = INFINITY;
       for (int64_t c0 = 0; c0 < v.n; c0 += B) {
-        FinalRes r = final_tile<B>(bf, cs, v, dt, sI.alpha[2], c0, sm.red);
+        FinalRes r = final_tile<B>(bf, cs, v, dt, sI.alpha[2], sI.wscale, c0, sm.red);
         fsp = fmax(fsp, r.speed);
         fminJ = fmin(fminJ, r.minJ);
         fmaxJ = fmax(fmaxJ, r.maxJ);
@@ -343,11 +337,11 @@ __global__ __launch_bounds__(B) void k_persistent(Bufs bf, Consts cs,
         __syncthreads();
       }
       if (threadIdx.x == 0) {
-        sI.n_class[0] += (unsigned long long)c_cls[0];
-        sI.n_class[1] += (unsigned long long)c_cls[1];
-        sI.n_class[2] += (unsigned long long)c_cls[2];
-        sI.n_limited += (unsigned long long)c_lim;
-        sI.n_negweight += (unsigned long long)c_neg;
+        sI.n_class[0] += c_cls[0];
+        sI.n_class[1] += c_cls[1];
+        sI.n_class[2] += c_cls[2];
+        sI.n_limited += c_lim;
+        sI.n_negweight += c_neg;
         sI.status |= st;
         sI.r_speed = dbits(fsp);
         sI.r_minJ = dbits(fminJ);
@@ -564,8 +558,6 @@ Bufs make_bufs(alew_ctx* c, int64_t S, int64_t ninst, double* hu, double* b, con
 template <int B>
 void launch_step_seq(alew_ctx* c, const Bufs& bf, const Consts& cs, hipStream_t st) {
   const dim3 gs((unsigned)c->n_tiles_stage), gp((unsigned)c->n_tiles_plain);
-  if (cs.mesh == MESH_SINE || cs.mesh == MESH_PAPER)
-    hipLaunchKernelGGL(k_wmap<B>, gp, dim3(B), 0, st, bf, cs, c->tiles_plain_d);
   for (int s = 1; s <= 3; ++s) {
     hipLaunchKernelGGL(k_stage<B>, gs, dim3(B), 0, st, bf, cs, c->tiles_stage_d, s);
     hipLaunchKernelGGL(k_after_stage, dim3(1), dim3(1024), 0, st, bf, s);

@@ -82,7 +82,8 @@ __device__ __forceinline__ void face_vjp(double hl, double ml, double bl, double
   const double lB1 = -g * etal_bar * rl[1] + g * etar_bar * rr[1];
   const bool wl = hl > dry, wr = hr > dry;
   const double mlp = wl ? ml : 0.0, mrp = wr ? mr : 0.0;
-  const double ul = wl ? ml / hl : 0.0, ur = wr ? mr / hr : 0.0;
+  const double ihl = wl ? frcp(hl) : 0.0, ihr = wr ? frcp(hr) : 0.0;
+  const double ul = wl ? ml * ihl : 0.0, ur = wr ? mr * ihr : 0.0;
   double lel = 0.5 * alpha * lF1, ler = -0.5 * alpha * lF1;
   const double lHl1 = 0.5 * lF1, lHr1 = 0.5 * lF1;
   const double lHl2 = 0.5 * lF2, lHr2 = 0.5 * lF2;
@@ -98,8 +99,8 @@ __device__ __forceinline__ void face_vjp(double hl, double ml, double bl, double
   double lul = mlp * lHl2, lur = mrp * lHr2;
   double lhl = g * hl * lHl2, lhr = g * hr * lHr2;
   // u = m'/h on wet traces
-  if (wl) { lmlp += lul / hl; lhl += -(ul / hl) * lul; }
-  if (wr) { lmrp += lur / hr; lhr += -(ur / hr) * lur; }
+  if (wl) { lmlp += lul * ihl; lhl += -(ul * ihl) * lul; }
+  if (wr) { lmrp += lur * ihr; lhr += -(ur * ihr) * lur; }
   // eta = h + b
   lhl += lel; lbl += lel;
   lhr += ler; lbr += ler;
@@ -111,11 +112,12 @@ __device__ __forceinline__ void face_vjp(double hl, double ml, double bl, double
 __device__ __forceinline__ void alpha_trace_vjp(double h, double m, double w, double g, double dry,
                                                 double lalpha, TraceAdj& L) {
   const bool wet = h > dry;
-  const double u = wet ? m / h : 0.0;
+  const double ih = wet ? frcp(h) : 0.0;
+  const double u = wet ? m * ih : 0.0;
   const double d = u - w;
   const double sg = d > 0.0 ? 1.0 : (d < 0.0 ? -1.0 : 0.0);
   const double lu = sg * lalpha;
-  if (wet) { L.m += lu / h; L.h += -(u / h) * lu; }
+  if (wet) { L.m += lu * ih; L.h += -(u * ih) * lu; }
   if (h > 0.0) {
     const double sq = sqrt(g * h);
     if (sq > 0.0) L.h += g * (0.5 / sq) * lalpha;
@@ -139,7 +141,7 @@ __device__ __forceinline__ void limit_vjp(double hbar, double mbar, double pp_ep
     return;
   }
   const double s1 = 1.0 / 12.0;
-  const double delta = (hbar - s1 * o.hL - s1 * o.hR) / (1.0 - 2.0 * s1);
+  const double delta = (hbar - s1 * o.hL - s1 * o.hR) * (1.0 / (1.0 - 2.0 * s1));
   double mn = o.hL;
   int which = 0;
   if (delta < mn) { mn = delta; which = 1; }
@@ -147,7 +149,8 @@ __device__ __forceinline__ void limit_vjp(double hbar, double mbar, double pp_ep
   const bool eps_const = pp_eps < hbar;
   const double epsj = eps_const ? pp_eps : hbar;
   if (!(mn < epsj)) return;  // identity
-  double Phi = (hbar - epsj) / (hbar - mn);
+  const double iden = frcp(hbar - mn);
+  double Phi = (hbar - epsj) * iden;
   const bool clamped = Phi > 1.0;
   if (clamped) Phi = 1.0;
   // b' = (h + b) - h'  ->  total adjoint of h' is lh' - lb'
@@ -160,13 +163,12 @@ __device__ __forceinline__ void limit_vjp(double hbar, double mbar, double pp_ep
   const double lmL = Phi * LL.m, lmR = Phi * LR.m;
   lmbar += (1.0 - Phi) * (LL.m + LR.m);
   if (!clamped) {
-    const double den = hbar - mn;
-    lhbar += lPhi * ((eps_const ? 1.0 : 0.0) - Phi) / den;
-    const double lmn = lPhi * Phi / den;
+    lhbar += lPhi * ((eps_const ? 1.0 : 0.0) - Phi) * iden;
+    const double lmn = lPhi * Phi * iden;
     if (which == 0) lhL += lmn;
     else if (which == 2) lhR += lmn;
     else {
-      const double ld = lmn / (1.0 - 2.0 * s1);
+      const double ld = lmn * (1.0 / (1.0 - 2.0 * s1));
       lhbar += ld;
       lhL -= s1 * ld;
       lhR -= s1 * ld;
@@ -195,7 +197,7 @@ __device__ __forceinline__ void recon_cell_vjp(const double* __restrict__ v5,
                                                ReconAdjOut& out) {
   // ---------------- forward (as recon_cell) ----------------
   const double J0 = J5[2];
-  const double iJ0 = 1.0 / J0;
+  const double iJ0 = frcp(J0);
   const double em1 = -0.5 - J5[1] * iJ0;
   const double em2 = em1 - J5[0] * iJ0;
   const double ep1 = 0.5 + J5[3] * iJ0;
@@ -210,7 +212,7 @@ __device__ __forceinline__ void recon_cell_vjp(const double* __restrict__ v5,
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
     const int c1 = C1[r], c2 = C2[r];
-    const double idet = 1.0 / (M1[c1] * M2[c2] - M1[c2] * M2[c1]);
+    const double idet = frcp(M1[c1] * M2[c2] - M1[c2] * M2[c1]);
     kb1[r] = M2[c2] * idet;
     kb2[r] = -M2[c1] * idet;
     kc1[r] = -M1[c2] * idet;
@@ -244,7 +246,7 @@ __device__ __forceinline__ void recon_cell_vjp(const double* __restrict__ v5,
       const double x0 = e3[1] * e4[2] - e3[2] * e4[1];
       const double x1 = e3[2] * e4[0] - e3[0] * e4[2];
       const double x2 = e3[0] * e4[1] - e3[1] * e4[0];
-      const double is = 1.0 / (x0 + x1 + x2);
+      const double is = frcp(x0 + x1 + x2);
       d[mu][0] = x0 * is;
       d[mu][1] = x1 * is;
       d[mu][2] = x2 * is;
@@ -277,14 +279,16 @@ __device__ __forceinline__ void recon_cell_vjp(const double* __restrict__ v5,
               (kap * (Bm[r] * Bm[r]) + kapC * (Cm[r] * Cm[r]));
   }
   const double tau = fabs(beta[0] - beta[2]);
-  const double betaA = (beta[0] + beta[1] + beta[2]) / 3.0;
-  const double gam = tau / (betaA + eps);
+  const double betaA = (beta[0] + beta[1] + beta[2]) * (1.0 / 3.0);
+  const double ibA = frcp(betaA + eps);
+  const double gam = tau * ibA;
   const int cls = (gam <= 0.5) ? 0 : ((gam >= 1.0) ? 2 : 1);
-  double K[3] = {1.0, 1.0, 1.0}, z[3] = {0.0, 0.0, 0.0};
+  double K[3] = {1.0, 1.0, 1.0}, z[3] = {0.0, 0.0, 0.0}, ib[3] = {0.0, 0.0, 0.0};
   if (cls != 0) {
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
-      z[r] = tau / (beta[r] + eps);
+      ib[r] = frcp(beta[r] + eps);
+      z[r] = tau * ib[r];
       K[r] = 1.0 + z[r] * z[r];
     }
   }
@@ -294,6 +298,7 @@ __device__ __forceinline__ void recon_cell_vjp(const double* __restrict__ v5,
   double lBm[3] = {0, 0, 0}, lCm[3] = {0, 0, 0}, lBb[3] = {0, 0, 0}, lCb[3] = {0, 0, 0};
   double lK[3] = {0, 0, 0}, lMg = 0.0;
   double lh0 = 0.0, lm0 = 0.0, lb0 = 0.0, letab = 0.0;
+  double isa_mu[4] = {0, 0, 0, 0};
   const double wgl[4] = {1.0 / 12.0, 5.0 / 12.0, 5.0 / 12.0, 1.0 / 12.0};
 #pragma unroll
   for (int mu = 0; mu < 4; ++mu) {
@@ -304,7 +309,8 @@ __device__ __forceinline__ void recon_cell_vjp(const double* __restrict__ v5,
     } else {
       const double a0 = d[mu][0] * K[0], a1 = d[mu][1] * K[1], a2 = d[mu][2] * K[2];
       sa = a0 + a1 + a2;
-      const double ia = 1.0 / sa;
+      const double ia = frcp(sa);
+      isa_mu[mu] = ia;
       phN[0] = a0 * ia; phN[1] = a1 * ia; phN[2] = a2 * ia;
 #pragma unroll
       for (int r = 0; r < 3; ++r) ph[r] = cls == 1 ? Mg * phN[r] + (1.0 - Mg) * d[mu][r] : phN[r];
@@ -356,7 +362,7 @@ __device__ __forceinline__ void recon_cell_vjp(const double* __restrict__ v5,
       }
       const double dotp = phN[0] * lphN[0] + phN[1] * lphN[1] + phN[2] * lphN[2];
 #pragma unroll
-      for (int r = 0; r < 3; ++r) lK[r] += d[mu][r] * ((lphN[r] - dotp) / sa);
+      for (int r = 0; r < 3; ++r) lK[r] += d[mu][r] * ((lphN[r] - dotp) * isa_mu[mu]);
     }
   }
   double lbeta[3] = {0, 0, 0}, ltau = 0.0;
@@ -364,18 +370,16 @@ __device__ __forceinline__ void recon_cell_vjp(const double* __restrict__ v5,
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
       const double lz = 2.0 * z[r] * lK[r];
-      const double den = beta[r] + eps;
-      ltau += lz / den;
-      lbeta[r] -= lz * z[r] / den;
+      ltau += lz * ib[r];
+      lbeta[r] -= lz * z[r] * ib[r];
     }
   }
   if (cls == 1) {
     const double lgam = 2.0 * lMg;
-    const double den = betaA + eps;
-    ltau += lgam / den;
-    const double lbA = -lgam * gam / den;
+    ltau += lgam * ibA;
+    const double lbA = -lgam * gam * ibA;
 #pragma unroll
-    for (int r = 0; r < 3; ++r) lbeta[r] += lbA / 3.0;
+    for (int r = 0; r < 3; ++r) lbeta[r] += lbA * (1.0 / 3.0);
   }
   {
     const double dd = beta[0] - beta[2];

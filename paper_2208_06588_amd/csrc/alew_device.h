@@ -37,6 +37,7 @@ struct Inst {
   double alpha[3];  // LF speed of stages 1..3
   double dx[3];     // Dx of the indicators at stages 1..3
   double smax;      // max_i |S(xi_i)| of the prescribed map
+  double wscale;    // node speed of this step = wscale * w[] (w[] holds A S(xi) for the map)
   double dt_min, dt_max;
   double mass_eta0, mass_b0, mass_eta, mass_b;
   int64_t steps, max_steps;
@@ -70,6 +71,16 @@ __device__ __forceinline__ void amax_pos(unsigned long long* p, double v) {
 }
 __device__ __forceinline__ void amin_pos(unsigned long long* p, double v) {
   atomicMin(p, dbits(v));
+}
+
+// Reciprocal: hardware estimate refined by two Newton steps (relative error of
+// a few ulp; every divisor here is a positive width, depth or sum).
+__device__ __forceinline__ double frcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
 }
 
 // ----------------------------------------------------------------------------
@@ -175,7 +186,7 @@ __device__ __forceinline__ void recon_cell(const double* __restrict__ v5,  // in
                                            const double* __restrict__ J5, double Dx, double eps,
                                            double etabar, CellRecon& o) {
   const double J0 = J5[2];
-  const double iJ0 = 1.0 / J0;
+  const double iJ0 = frcp(J0);
   // cell edges of the big stencil in y
   const double em1 = -0.5 - J5[1] * iJ0;
   const double em2 = em1 - J5[0] * iJ0;
@@ -193,7 +204,7 @@ __device__ __forceinline__ void recon_cell(const double* __restrict__ v5,  // in
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
     const int c1 = C1[r], c2 = C2[r];
-    const double idet = 1.0 / (M1[c1] * M2[c2] - M1[c2] * M2[c1]);
+    const double idet = frcp(M1[c1] * M2[c2] - M1[c2] * M2[c1]);
     kb1[r] = M2[c2] * idet;
     kb2[r] = -M2[c1] * idet;
     kc1[r] = -M1[c2] * idet;
@@ -229,7 +240,7 @@ __device__ __forceinline__ void recon_cell(const double* __restrict__ v5,  // in
       const double x0 = e3[1] * e4[2] - e3[2] * e4[1];
       const double x1 = e3[2] * e4[0] - e3[0] * e4[2];
       const double x2 = e3[0] * e4[1] - e3[1] * e4[0];
-      const double is = 1.0 / (x0 + x1 + x2);
+      const double is = frcp(x0 + x1 + x2);
       d[mu][0] = x0 * is;
       d[mu][1] = x1 * is;
       d[mu][2] = x2 * is;
@@ -267,14 +278,14 @@ __device__ __forceinline__ void recon_cell(const double* __restrict__ v5,  // in
   }
   // Step 2: detector
   const double tau = fabs(beta[0] - beta[2]);
-  const double betaA = (beta[0] + beta[1] + beta[2]) / 3.0;
-  const double gam = tau / (betaA + eps);
+  const double betaA = (beta[0] + beta[1] + beta[2]) * (1.0 / 3.0);
+  const double gam = tau * frcp(betaA + eps);
   const int cls = (gam <= 0.5) ? 0 : ((gam >= 1.0) ? 2 : 1);
   double K[3];
   if (cls != 0) {
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
-      const double z = tau / (beta[r] + eps);
+      const double z = tau * frcp(beta[r] + eps);
       K[r] = 1.0 + z * z;
     }
   }
@@ -290,7 +301,7 @@ __device__ __forceinline__ void recon_cell(const double* __restrict__ v5,  // in
       ph[2] = d[mu][2];
     } else {
       const double a0 = d[mu][0] * K[0], a1 = d[mu][1] * K[1], a2 = d[mu][2] * K[2];
-      const double ia = 1.0 / (a0 + a1 + a2);
+      const double ia = frcp(a0 + a1 + a2);
       ph[0] = a0 * ia;
       ph[1] = a1 * ia;
       ph[2] = a2 * ia;
@@ -341,13 +352,13 @@ __device__ __forceinline__ int limit_cell(double hbar, double mbar, double pp_ep
     return 1;
   }
   const double s1 = 1.0 / 12.0;
-  const double delta = (hbar - s1 * o.hL - s1 * o.hR) / (1.0 - 2.0 * s1);
+  const double delta = (hbar - s1 * o.hL - s1 * o.hR) * (1.0 / (1.0 - 2.0 * s1));
   double mn = o.hL;
   if (delta < mn) mn = delta;
   if (o.hR < mn) mn = o.hR;
   const double epsj = (pp_eps < hbar) ? pp_eps : hbar;
   if (!(mn < epsj)) return 0;
-  double Phi = (hbar - epsj) / (hbar - mn);
+  double Phi = (hbar - epsj) * frcp(hbar - mn);
   if (Phi > 1.0) Phi = 1.0;
   const double eL = o.hL + o.bL, eR = o.hR + o.bR;
   o.hL = Phi * (o.hL - hbar) + hbar;
@@ -374,8 +385,8 @@ __device__ __forceinline__ void face_flux(double hl, double ml, double bl, doubl
                                           double br, double w, double g, double dry, Face& f) {
   const double el = hl + bl, er = hr + br;
   double ul = 0.0, ur = 0.0;
-  if (hl > dry) ul = ml / hl; else ml = 0.0;
-  if (hr > dry) ur = mr / hr; else mr = 0.0;
+  if (hl > dry) ul = ml * frcp(hl); else ml = 0.0;
+  if (hr > dry) ur = mr * frcp(hr); else mr = 0.0;
   const double Hl1 = ml - w * el;
   const double Hl2 = ml * ul + 0.5 * g * hl * hl - w * ml;
   const double Hr1 = mr - w * er;

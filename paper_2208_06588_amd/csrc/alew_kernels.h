@@ -26,7 +26,7 @@ struct Bufs {
   double* xa;   // nodes, even steps read xa, write xb
   double* xb;
   const double* xi;
-  double* w;    // node speeds of the current step
+  double* w;    // node speeds (times Inst::wscale); for the prescribed map A S(xi)
   double* P0;   // stage buffers: stages 1 and 3 write (P0, D0), stage 2 writes (P1, D1)
   double* D0;
   double* P1;
@@ -63,12 +63,13 @@ __device__ __forceinline__ View make_view(const Bufs& bf, int i, const Inst& I) 
 struct StageScal {
   int s;           // 1..3
   double dt, cprev, dx, as, bs;
+  double wsc;      // node speed = wsc * w[]
 };
 
 // Block-level results of a stage tile.
 struct StageRes {
   double alpha, maxJ;
-  double ncls0, ncls1, ncls2, nlim, nneg;
+  unsigned ncls0, ncls1, ncls2, nlim, nneg;
   int status;
 };
 
@@ -78,6 +79,7 @@ struct SmemStage {
   double tr[6][B];
   double fl[8][B];
   double red[(B / 64) * 8];
+  unsigned cnt[8];  // class S/T/N, limited, negative weight, status bits
 };
 
 // Stage-input state (eta, hu, b) and width of cell k (ghosts mapped).
@@ -94,14 +96,15 @@ __device__ __forceinline__ void load_stage_cell(const Bufs& bf, const Consts& cs
     m = bf.m[g] * ms;
     b = bf.b[g];
   } else {
-    const double dw = bf.w[v.no + src + 1] - bf.w[v.no + src];
+    const double dw = bf.w[v.no + src + 1] * sc.wsc - bf.w[v.no + src] * sc.wsc;
     const double J1 = Jn + sc.dt * dw;
     J = (sc.s == 2) ? J1 : 0.75 * Jn + 0.25 * (J1 + sc.dt * dw);
     const double* P = (sc.s == 2) ? bf.P0 : bf.P1;
     const double* D = (sc.s == 2) ? bf.D0 : bf.D1;
-    e = (P[g] + sc.cprev * D[g]) / J;
-    m = ((P[bf.S + g] + sc.cprev * D[bf.S + g]) / J) * ms;
-    b = (P[2 * bf.S + g] + sc.cprev * D[2 * bf.S + g]) / J;
+    const double iJ = frcp(J);
+    e = (P[g] + sc.cprev * D[g]) * iJ;
+    m = ((P[bf.S + g] + sc.cprev * D[bf.S + g]) * iJ) * ms;
+    b = (P[2 * bf.S + g] + sc.cprev * D[2 * bf.S + g]) * iJ;
   }
   if (!(J > 0.0)) st |= SB_MESH;
 }
@@ -113,6 +116,7 @@ __device__ __forceinline__ StageRes stage_tile(const Bufs& bf, const Consts& cs,
                                                SmemStage<B>& sm, uint8_t* cls_inst) {
   const int t = threadIdx.x;
   int st = 0;
+  if (t < 8) sm.cnt[t] = 0u;
   // 1. stencil data for cells c0-3 .. c0+B
   for (int i = t; i < B + 4; i += B) {
     const int64_t k = c0 - 3 + i;
@@ -127,7 +131,8 @@ __device__ __forceinline__ StageRes stage_tile(const Bufs& bf, const Consts& cs,
   const bool owned = (t >= 1) && (t <= B - 2) && (j < v.n);
   CellRecon o;
   double ebar = 0, hbar = 0, mbar = 0, bbar = 0, Jj = 1;
-  double nlim = 0, ncls[3] = {0, 0, 0}, nneg = 0;
+  bool lim_owned = false, neg_cell = false;
+  int cls_owned = -1;
   if (active) {
     double h5[5], v5[5];
 #pragma unroll
@@ -140,12 +145,12 @@ __device__ __forceinline__ StageRes stage_tile(const Bufs& bf, const Consts& cs,
     recon_cell(v5, h5, &sm.m[t], &sm.b[t], &sm.J[t], Dx, cs.weno_eps, ebar, o);
     const int lim = limit_cell(hbar, mbar, cs.pp_eps, o);
     if (owned) {
-      ncls[o.cls] = 1.0;
-      nlim = lim ? 1.0 : 0.0;
+      cls_owned = o.cls;
+      lim_owned = lim != 0;
       if (hbar < -cs.pp_eps) st |= SB_NEGDEPTH;
       if (cls_inst) cls_inst[j] = (uint8_t)o.cls;
     }
-    if (o.negw && (owned || j == -1 || j == v.n)) { nneg = 1.0; st |= SB_NEGWEIGHT; }
+    if (o.negw && (owned || j == -1 || j == v.n)) { neg_cell = true; st |= SB_NEGWEIGHT; }
     sm.tr[0][t] = o.hL; sm.tr[1][t] = o.mL; sm.tr[2][t] = o.bL;
     sm.tr[3][t] = o.hR; sm.tr[4][t] = o.mR; sm.tr[5][t] = o.bR;
   }
@@ -155,7 +160,7 @@ __device__ __forceinline__ StageRes stage_tile(const Bufs& bf, const Consts& cs,
   if (t >= 1 && j >= 0 && j <= v.n) {
     Face f;
     face_flux(sm.tr[3][t - 1], sm.tr[4][t - 1], sm.tr[5][t - 1], sm.tr[0][t], sm.tr[1][t],
-              sm.tr[2][t], bf.w[v.no + j], cs.g, cs.dry_eps, f);
+              sm.tr[2][t], bf.w[v.no + j] * sc.wsc, cs.g, cs.dry_eps, f);
     sm.fl[0][t] = f.Fc1; sm.fl[1][t] = f.Fc2; sm.fl[2][t] = f.Gc; sm.fl[3][t] = f.je;
     sm.fl[4][t] = f.jm; sm.fl[5][t] = f.jb; sm.fl[6][t] = f.B1; sm.fl[7][t] = f.B2;
     fspeed = f.speed;
@@ -179,7 +184,7 @@ __device__ __forceinline__ StageRes stage_tile(const Bufs& bf, const Consts& cs,
     const double Db = 0.5 * (sm.fl[5][t + 1] - sm.fl[5][t]);
     const int64_t gi = v.co + j;
     const double Jn = v.x[j + 1] - v.x[j];
-    const double dw = bf.w[v.no + j + 1] - bf.w[v.no + j];
+    const double dw = bf.w[v.no + j + 1] * sc.wsc - bf.w[v.no + j] * sc.wsc;
     double Pe, Pm, Pb;
     if (sc.s == 1) {
       Pe = Jj * ebar + sc.dt * Ae;
@@ -204,20 +209,29 @@ __device__ __forceinline__ StageRes stage_tile(const Bufs& bf, const Consts& cs,
     maxJ = Jnext;
     if (!(Jnext > 0.0)) st |= SB_MESH;
   }
-  double rv[7] = {fspeed, maxJ, ncls[0], ncls[1], ncls[2], nlim, nneg};
-  const int op[7] = {0, 0, 2, 2, 2, 2, 2};
-  block_reduce<B, 7>(rv, op, sm.red);
-  // status bits: OR through shared memory
-  __syncthreads();
-  if (t == 0) sm.red[0] = 0.0;
-  __syncthreads();
-  if (st) atomicOr((int*)&sm.red[0], st);
-  __syncthreads();
+  // counters: one ballot per wave, summed in LDS
+  {
+    const unsigned long long b0 = __ballot(cls_owned == 0), b1 = __ballot(cls_owned == 1);
+    const unsigned long long b2 = __ballot(cls_owned == 2), bl = __ballot(lim_owned);
+    const unsigned long long bn = __ballot(neg_cell);
+    if ((t & 63) == 0) {
+      atomicAdd(&sm.cnt[0], (unsigned)__popcll(b0));
+      atomicAdd(&sm.cnt[1], (unsigned)__popcll(b1));
+      atomicAdd(&sm.cnt[2], (unsigned)__popcll(b2));
+      if (bl) atomicAdd(&sm.cnt[3], (unsigned)__popcll(bl));
+      if (bn) atomicAdd(&sm.cnt[4], (unsigned)__popcll(bn));
+    }
+    if (st) atomicOr(&sm.cnt[5], (unsigned)st);
+  }
+  double rv[2] = {fspeed, maxJ};
+  const int op[2] = {0, 0};
+  block_reduce<B, 2>(rv, op, sm.red);
   StageRes res;
   res.alpha = rv[0];
   res.maxJ = rv[1];
-  res.ncls0 = rv[2]; res.ncls1 = rv[3]; res.ncls2 = rv[4]; res.nlim = rv[5]; res.nneg = rv[6];
-  res.status = *(int*)&sm.red[0];
+  res.ncls0 = sm.cnt[0]; res.ncls1 = sm.cnt[1]; res.ncls2 = sm.cnt[2];
+  res.nlim = sm.cnt[3]; res.nneg = sm.cnt[4];
+  res.status = (int)sm.cnt[5];
   __syncthreads();
   return res;
 }
@@ -231,23 +245,25 @@ struct FinalRes {
 
 template <int B>
 __device__ __forceinline__ FinalRes final_tile(const Bufs& bf, const Consts& cs, const View& v,
-                                               double dt, double alpha3, int64_t c0, double* red) {
+                                               double dt, double alpha3, double wsc, int64_t c0,
+                                               double* red) {
   const int t = threadIdx.x;
   const int64_t j = c0 + t;
   int st = 0;
   double speed = 0.0, minJ = INFINITY, maxJ = 0.0, hmin = INFINITY;
   if (j < v.n) {
     const double x0 = v.x[j], x1 = v.x[j + 1];
-    const double w0 = bf.w[v.no + j], w1 = bf.w[v.no + j + 1];
+    const double w0 = bf.w[v.no + j] * wsc, w1 = bf.w[v.no + j + 1] * wsc;
     const double Jn = x1 - x0, dw = w1 - w0;
     const double J1 = Jn + dt * dw;
     const double J2 = 0.75 * Jn + 0.25 * (J1 + dt * dw);
     const double J3 = (1.0 / 3.0) * Jn + (2.0 / 3.0) * (J2 + dt * dw);
     const double c = (2.0 / 3.0) * dt * alpha3;
     const int64_t gi = v.co + j;
-    const double e = (bf.P0[gi] + c * bf.D0[gi]) / J3;
-    const double m = (bf.P0[bf.S + gi] + c * bf.D0[bf.S + gi]) / J3;
-    const double b = (bf.P0[2 * bf.S + gi] + c * bf.D0[2 * bf.S + gi]) / J3;
+    const double iJ3 = frcp(J3);
+    const double e = (bf.P0[gi] + c * bf.D0[gi]) * iJ3;
+    const double m = (bf.P0[bf.S + gi] + c * bf.D0[bf.S + gi]) * iJ3;
+    const double b = (bf.P0[2 * bf.S + gi] + c * bf.D0[2 * bf.S + gi]) * iJ3;
     bf.eta[gi] = e; bf.m[gi] = m; bf.b[gi] = b;
     const double xn0 = x0 + dt * w0, xn1 = x1 + dt * w1;
     if (bf.dump.xw) {
@@ -292,17 +308,12 @@ __device__ __forceinline__ double mesh_shape(const Consts& cs, double xi, double
   return (xi - x1) * (xi - x0) / (3.0 * L * L);
 }
 
-// Node speeds of the step [t, t+dt] for the prescribed map (chord of eq. (2.1)).
-template <int B>
-__device__ __forceinline__ void wmap_tile(const Bufs& bf, const Consts& cs, const View& v,
-                                          double t, double dt, int64_t k0) {
-  const int64_t k = k0 + threadIdx.x;
-  if (k > v.n) return;
+// Chord factor of the prescribed map over the step [t, t+dt] (eq. (2.1)):
+// (sin(om (t+dt)) - sin(om t)) / dt = 2 cos(om (t + dt/2)) sin(om dt/2) / dt;
+// the node speed is (A S(xi)) times this factor.
+__device__ __forceinline__ double chord_factor(const Consts& cs, double t, double dt) {
   const double om = cs.mesh_omega;
-  const double fac = 2.0 * cos(om * (t + 0.5 * dt)) * sin(0.5 * om * dt) / dt;
-  const double* xi = bf.xi + v.no;
-  const int64_t kk = (cs.bc == BC_PERIODIC && k == v.n) ? 0 : k;
-  bf.w[v.no + k] = cs.mesh_A * mesh_shape(cs, xi[kk], xi[0], xi[v.n]) * fac;
+  return 2.0 * cos(om * (t + 0.5 * dt)) * sin(0.5 * om * dt) / dt;
 }
 
 // Fluid-following node speeds for nodes [k0, k0+B): node average of the cell

@@ -151,6 +151,7 @@ def main():
     ap.add_argument("--engine", default="tune", choices=["tune", "persistent", "stages"])
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--graph", type=int, default=1, help="stage engine: replay steps as a hipGraph")
+    ap.add_argument("--cpt", type=int, default=1, help="stage engine: cells per thread (1 or 2)")
     ap.add_argument("--ninst", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-inst", type=int, default=64)
@@ -201,7 +202,8 @@ def main():
         log(f"autotune picked {best}")
     else:
         eng = alew.ENGINE_PERSISTENT if args.engine == "persistent" else alew.ENGINE_STAGES
-        ctx.set_launch(engine=eng, block=args.block, use_graph=args.graph)
+        ctx.set_launch(engine=eng, block=args.block, use_graph=args.graph,
+                       cells_per_thread=args.cpt)
     L = ctx.get_launch()
     engine_name = "persistent" if L.engine == alew.ENGINE_PERSISTENT else "stage-launches"
 
@@ -243,6 +245,7 @@ def main():
                                f"instances, 1000-20000 cells each (seed 2208065881), {S} cells, "
                                "transmissive, sine-moving mesh, CFL 0.6, FP64 SSP-RK3",
                    "ninst": ninst, "cells": S, "engine": engine_name, "block": L.block,
+                   "cells_per_thread": max(1, L.cells_per_thread),
                    "parallelism": "single GPU"},
         "roofline": roof,
     }

@@ -106,12 +106,15 @@ typedef struct {
  * block: work-group size (128, 256 or 512; 0 = 256).
  * steps_per_launch: persistent engine, steps per launch before control returns to
  * the host (0 = until every instance is done).
- * use_graph: stage-launch engine, replay the launches of a step as a hipGraph. */
+ * use_graph: stage-launch engine, replay the launches of a step as a hipGraph.
+ * cells_per_thread: stage-launch engine, cells each thread reconstructs per
+ * tile (1 or 2; 0 = 1); a tile spans block * cells_per_thread cells. */
 typedef struct {
   int32_t engine;
   int32_t block;
   int32_t steps_per_launch;
   int32_t use_graph;
+  int32_t cells_per_thread;
 } alew_launch;
 
 /* Create a context able to run up to max_cells cells in up to max_inst instances.

@@ -17,12 +17,21 @@ import torch
 from . import alew
 
 CANDIDATES = [
-    dict(engine=alew.ENGINE_PERSISTENT, block=128, steps_per_launch=0, use_graph=0),
-    dict(engine=alew.ENGINE_PERSISTENT, block=256, steps_per_launch=0, use_graph=0),
-    dict(engine=alew.ENGINE_STAGES, block=128, steps_per_launch=0, use_graph=1),
-    dict(engine=alew.ENGINE_STAGES, block=256, steps_per_launch=0, use_graph=1),
-    dict(engine=alew.ENGINE_STAGES, block=512, steps_per_launch=0, use_graph=1),
+    dict(engine=alew.ENGINE_PERSISTENT, block=128, steps_per_launch=0, use_graph=0,
+         cells_per_thread=1),
+    dict(engine=alew.ENGINE_PERSISTENT, block=256, steps_per_launch=0, use_graph=0,
+         cells_per_thread=1),
+    dict(engine=alew.ENGINE_STAGES, block=128, steps_per_launch=0, use_graph=1, cells_per_thread=1),
+    dict(engine=alew.ENGINE_STAGES, block=256, steps_per_launch=0, use_graph=1, cells_per_thread=1),
+    dict(engine=alew.ENGINE_STAGES, block=512, steps_per_launch=0, use_graph=1, cells_per_thread=1),
+    dict(engine=alew.ENGINE_STAGES, block=128, steps_per_launch=0, use_graph=1, cells_per_thread=2),
+    dict(engine=alew.ENGINE_STAGES, block=256, steps_per_launch=0, use_graph=1, cells_per_thread=2),
 ]
+
+
+def name_of(c) -> str:
+    return (f"engine{c['engine']}-b{c['block']}-g{c['use_graph']}"
+            f"-c{c.get('cells_per_thread', 1)}")
 
 CACHE = os.environ.get("ALEW_TUNE_CACHE", os.path.expanduser("~/.cache/alew/autotune.json"))
 
@@ -67,21 +76,21 @@ def tune(ctx: alew.Context, p: alew.Params, cell_off, state: dict, steps: int = 
     ninst = len(cell_off) - 1
     times = {}
     for cand in candidates:
-        T = {k: v.clone() for k, v in state.items()}
         ctx.set_launch(**cand)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ctx.run(p, cell_off, T["h"], T["hu"], T["b"], T["x"], T["xi"], max_steps=[steps] * ninst)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        name = f"engine{cand['engine']}-b{cand['block']}-g{cand['use_graph']}"
+        # one untimed step builds tile tables and graphs, then `steps` timed steps
+        for nrun, ns in ((0, 1), (1, steps)):
+            T = {k: v.clone() for k, v in state.items()}
+            torch.cuda.synchronize()
+            ctx.run(p, cell_off, T["h"], T["hu"], T["b"], T["x"], T["xi"], max_steps=[ns] * ninst)
+            torch.cuda.synchronize()
+            del T
+        dt = ctx.last_timing()[0] * 1e-3
+        name = name_of(cand)
         times[name] = dt
         if log:
             log(f"tune {name}: {dt * 1e3:.1f} ms for {steps} steps")
-        del T
     best_name = min(times, key=times.get)
-    best = next(c for c in candidates
-                if f"engine{c['engine']}-b{c['block']}-g{c['use_graph']}" == best_name)
+    best = next(c for c in candidates if name_of(c) == best_name)
     ctx.set_launch(**best)
     cache[key] = dict(best=best, times=times)
     _store(cache)

@@ -7,12 +7,16 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc", "alew.hip")
-DEPS = [os.path.join(HERE, "csrc", f) for f in ("alew.hip", "alew_device.h", "alew_kernels.h")]
+DEPS = [os.path.join(HERE, "csrc", f)
+        for f in ("alew.hip", "alew_device.h", "alew_kernels.h", "alew_adjoint.h")]
 LIB = os.path.join(HERE, "libalew.so")
 INCLUDE = os.path.join(ROOT, "include")
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    # multiply-adds fused only within one source expression, so a tile body
+    # rounds the same way wherever it is inlined (engines agree bit for bit)
+    "-ffp-contract=on",
     # keep the compiler from forming packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",

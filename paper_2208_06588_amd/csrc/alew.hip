@@ -101,10 +101,10 @@ __global__ __launch_bounds__(B) void k_wfluid(Bufs bf, Consts cs, const Tile* __
   if (threadIdx.x == 0) amax_pos(&I.r_W, W);
 }
 
-template <int B>
+template <int B, int CPT>
 __global__ __launch_bounds__(B) void k_stage(Bufs bf, Consts cs, const Tile* __restrict__ tiles,
                                              int s) {
-  __shared__ SmemStage<B> sm;
+  __shared__ SmemStage<B, CPT> sm;
   const Tile tl = tiles[blockIdx.x];
   Inst& I = bf.inst[tl.inst];
   if (!I.active) return;
@@ -119,7 +119,7 @@ __global__ __launch_bounds__(B) void k_stage(Bufs bf, Consts cs, const Tile* __r
   sc.dx = I.dx[s - 1];
   sc.wsc = I.wscale;
   uint8_t* cl = bf.cls ? bf.cls + (int64_t)(s - 1) * bf.S + v.co : nullptr;
-  StageRes r = stage_tile<B>(bf, cs, v, sc, tl.c0, sm, cl);
+  StageRes r = stage_tile<B, CPT>(bf, cs, v, sc, tl.c0, sm, cl);
   if (threadIdx.x == 0) {
     amax_pos(&I.r_alpha, r.alpha);
     if (s < 3) amax_pos(&I.r_maxJs, r.maxJ);
@@ -273,10 +273,10 @@ __global__ __launch_bounds__(B) void k_persistent(Bufs bf, Consts cs,
                                                   const int32_t* __restrict__ order,
                                                   unsigned* __restrict__ queue,
                                                   int32_t steps_limit) {
-  __shared__ SmemStage<B> sm;
+  __shared__ SmemStage<B, 1> sm;
   __shared__ Inst sI;
   __shared__ int s_idx;
-  __shared__ double su[B + 6], sv[B + 4];
+  __shared__ double su[B + 6], sv[B + 4], red[(B / 64) * 8];
   for (;;) {
     if (threadIdx.x == 0) s_idx = (int)atomicAdd(queue, 1u);
     __syncthreads();
@@ -303,7 +303,7 @@ __global__ __launch_bounds__(B) void k_persistent(Bufs bf, Consts cs,
         sc.wsc = sI.wscale;
         double amax = 0.0, jmax = 0.0;
         for (int64_t c0 = 0; c0 < v.n; c0 += B - 2) {
-          StageRes r = stage_tile<B>(bf, cs, v, sc, c0, sm, nullptr);
+          StageRes r = stage_tile<B, 1>(bf, cs, v, sc, c0, sm, nullptr);
           amax = fmax(amax, r.alpha);
           jmax = fmax(jmax, r.maxJ);
           c_cls[0] += r.ncls0; c_cls[1] += r.ncls1; c_cls[2] += r.ncls2;
@@ -319,7 +319,7 @@ __global__ __launch_bounds__(B) void k_persistent(Bufs bf, Consts cs,
       }
       double fsp = 0.0, fminJ = INFINITY, fmaxJ = 0.0, fhmin = INFINITY;
       for (int64_t c0 = 0; c0 < v.n; c0 += B) {
-        FinalRes r = final_tile<B>(bf, cs, v, dt, sI.alpha[2], sI.wscale, c0, sm.red);
+        FinalRes r = final_tile<B>(bf, cs, v, dt, sI.alpha[2], sI.wscale, c0, red);
         fsp = fmax(fsp, r.speed);
         fminJ = fmin(fminJ, r.minJ);
         fmaxJ = fmax(fmaxJ, r.maxJ);
@@ -333,7 +333,7 @@ __global__ __launch_bounds__(B) void k_persistent(Bufs bf, Consts cs,
         View vn = v;
         vn.x = v.xnew;
         for (int64_t k0 = 0; k0 <= v.n; k0 += B)
-          Wf = fmax(Wf, wfluid_tile<B>(bf, cs, vn, k0, su, sv, sm.red));
+          Wf = fmax(Wf, wfluid_tile<B>(bf, cs, vn, k0, su, sv, red));
         __syncthreads();
       }
       if (threadIdx.x == 0) {
@@ -461,9 +461,9 @@ struct alew_ctx {
   Tile* tiles_plain_d = nullptr;
   int64_t tiles_cap = 0;
   std::vector<int64_t> cell_off_h;  // cached batch layout
-  int cached_B = 0;
+  int cached_B = 0, cached_TB = 0;
   int64_t n_tiles_stage = 0, n_tiles_plain = 0;
-  alew_launch launch{0, 256, 0, 1};
+  alew_launch launch{0, 256, 0, 1, 1};
   hipEvent_t ev0 = nullptr, ev1 = nullptr;  // around the compute launches of a call
   // adjoint workspace (allocated by the first alew_adjoint call, grown on demand)
   double* adj_ws = nullptr;
@@ -502,14 +502,20 @@ int pick_block(const alew_ctx* c) {
   return (b == 128 || b == 256 || b == 512) ? b : 256;
 }
 
-// (Re)build the tile tables for a batch layout and block size.
-alew_status build_tiles(alew_ctx* c, const int64_t* cell_off, int64_t ninst, int B) {
+// Cells per thread of the stage-launch engine (block 512 runs one).
+int pick_cpt(const alew_ctx* c, int B) {
+  return (c->launch.cells_per_thread == 2 && B <= 256) ? 2 : 1;
+}
+
+// (Re)build the tile tables for a batch layout, block size B and stage tile
+// width TB (TB - 2 owned cells per stage tile; B items per plain tile).
+alew_status build_tiles(alew_ctx* c, const int64_t* cell_off, int64_t ninst, int B, int TB) {
   std::vector<int64_t> off(cell_off, cell_off + ninst + 1);
-  if (off == c->cell_off_h && c->cached_B == B) return ALEW_OK;
+  if (off == c->cell_off_h && c->cached_B == B && c->cached_TB == TB) return ALEW_OK;
   std::vector<Tile> ts, tp;
   for (int64_t i = 0; i < ninst; ++i) {
     const int64_t n = off[i + 1] - off[i];
-    for (int64_t c0 = 0; c0 < n; c0 += B - 2) ts.push_back(Tile{(int32_t)i, 0, c0});
+    for (int64_t c0 = 0; c0 < n; c0 += TB - 2) ts.push_back(Tile{(int32_t)i, 0, c0});
     for (int64_t c0 = 0; c0 <= n; c0 += B) tp.push_back(Tile{(int32_t)i, 0, c0});
   }
   const int64_t need = (int64_t)std::max(ts.size(), tp.size());
@@ -534,6 +540,7 @@ alew_status build_tiles(alew_ctx* c, const int64_t* cell_off, int64_t ninst, int
   HIPCHK(hipStreamSynchronize(c->stream));
   c->cell_off_h = off;
   c->cached_B = B;
+  c->cached_TB = TB;
   c->n_tiles_stage = (int64_t)ts.size();
   c->n_tiles_plain = (int64_t)tp.size();
   if (c->gexec) { (void)hipGraphExecDestroy(c->gexec); c->gexec = nullptr; }
@@ -555,11 +562,11 @@ Bufs make_bufs(alew_ctx* c, int64_t S, int64_t ninst, double* hu, double* b, con
   return bf;
 }
 
-template <int B>
+template <int B, int CPT>
 void launch_step_seq(alew_ctx* c, const Bufs& bf, const Consts& cs, hipStream_t st) {
   const dim3 gs((unsigned)c->n_tiles_stage), gp((unsigned)c->n_tiles_plain);
   for (int s = 1; s <= 3; ++s) {
-    hipLaunchKernelGGL(k_stage<B>, gs, dim3(B), 0, st, bf, cs, c->tiles_stage_d, s);
+    hipLaunchKernelGGL((k_stage<B, CPT>), gs, dim3(B), 0, st, bf, cs, c->tiles_stage_d, s);
     hipLaunchKernelGGL(k_after_stage, dim3(1), dim3(1024), 0, st, bf, s);
   }
   hipLaunchKernelGGL(k_final<B>, gp, dim3(B), 0, st, bf, cs, c->tiles_plain_d);
@@ -568,7 +575,7 @@ void launch_step_seq(alew_ctx* c, const Bufs& bf, const Consts& cs, hipStream_t 
   hipLaunchKernelGGL(k_boundary, dim3(1), dim3(1024), 0, st, bf, cs, 0, c->nactive_d);
 }
 
-GraphKey make_key(const Bufs& bf, const Consts& cs, int B, const alew_ctx* c) {
+GraphKey make_key(const Bufs& bf, const Consts& cs, int B, int CPT, const alew_ctx* c) {
   GraphKey k;
   auto put = [&](const void* p, size_t n) {
     const char* q = (const char*)p;
@@ -577,23 +584,24 @@ GraphKey make_key(const Bufs& bf, const Consts& cs, int B, const alew_ctx* c) {
   put(&bf, sizeof(bf));
   put(&cs, sizeof(cs));
   put(&B, sizeof(B));
+  put(&CPT, sizeof(CPT));
   put(&c->n_tiles_stage, sizeof(int64_t));
   put(&c->n_tiles_plain, sizeof(int64_t));
   return k;
 }
 
-template <int B>
+template <int B, int CPT>
 alew_status run_stage_engine(alew_ctx* c, const Bufs& bf, const Consts& cs, int64_t max_iters) {
   const bool use_graph = c->launch.use_graph != 0;
   const int check_every = 8;  // 2-step graphs between host checks
   if (use_graph) {
-    GraphKey key = make_key(bf, cs, B, c);
+    GraphKey key = make_key(bf, cs, B, CPT, c);
     if (!c->gexec || !(key == c->gkey)) {
       if (c->gexec) { (void)hipGraphExecDestroy(c->gexec); c->gexec = nullptr; }
       if (c->graph) { (void)hipGraphDestroy(c->graph); c->graph = nullptr; }
       HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-      launch_step_seq<B>(c, bf, cs, c->cap_stream);
-      launch_step_seq<B>(c, bf, cs, c->cap_stream);
+      launch_step_seq<B, CPT>(c, bf, cs, c->cap_stream);
+      launch_step_seq<B, CPT>(c, bf, cs, c->cap_stream);
       HIPCHK(hipStreamEndCapture(c->cap_stream, &c->graph));
       HIPCHK(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
       c->gkey = key;
@@ -608,7 +616,7 @@ alew_status run_stage_engine(alew_ctx* c, const Bufs& bf, const Consts& cs, int6
         HIPCHK(hipGraphLaunch(c->gexec, c->stream));
         it += 2;
       } else {
-        launch_step_seq<B>(c, bf, cs, c->stream);
+        launch_step_seq<B, CPT>(c, bf, cs, c->stream);
         it += 1;
       }
       c->last_launches += 1;
@@ -659,6 +667,14 @@ alew_status run_persistent(alew_ctx* c, const Bufs& bf, const Consts& cs, int64_
   return ALEW_OK;
 }
 
+template <int B>
+alew_status run_stages(alew_ctx* c, const Bufs& bf, const Consts& cs, int64_t max_iters, int cpt) {
+  if constexpr (B <= 256) {
+    if (cpt == 2) return run_stage_engine<B, 2>(c, bf, cs, max_iters);
+  }
+  return run_stage_engine<B, 1>(c, bf, cs, max_iters);
+}
+
 alew_status map_status(int bits) {
   if (bits & SB_MESH) return ALEW_E_MESH;
   if (bits & SB_NONFINITE) return ALEW_E_NONFINITE;
@@ -689,7 +705,8 @@ alew_status drive(alew_ctx* c, const alew_params* p, int64_t ninst, const int64_
   if (S > c->max_cells) return fail(ALEW_E_ARG, "total cells exceed the context capacity");
   if ((dts || dt_log) && dts_stride <= 0) return fail(ALEW_E_ARG, "dts_stride must be > 0");
   const int B = pick_block(c);
-  alew_status ts = build_tiles(c, cell_off, ninst, B);
+  const int CPT = (engine == 1) ? 1 : pick_cpt(c, B);
+  alew_status ts = build_tiles(c, cell_off, ninst, B, B * CPT);
   if (ts != ALEW_OK) return ts;
   // per-instance scalars
   int64_t max_iters = 0;
@@ -721,7 +738,7 @@ alew_status drive(alew_ctx* c, const alew_params* p, int64_t ninst, const int64_
     hipLaunchKernelGGL(k_boundary, dim3(1), dim3(1024), 0, c->stream, bf, cs, 1, c->nactive_d); \
     HIPCHK(hipGetLastError());                                                                  \
     alew_status rs = (engine == 1) ? run_persistent<BB>(c, bf, cs, ninst)                       \
-                                   : run_stage_engine<BB>(c, bf, cs, max_iters);                \
+                                   : run_stages<BB>(c, bf, cs, max_iters, CPT);                 \
     if (rs != ALEW_OK) return rs;                                                               \
     hipLaunchKernelGGL(k_finish<BB>, gp, dim3(BB), 0, c->stream, bf, cs, c->tiles_plain_d, h, x); \
   } while (0)
@@ -846,8 +863,9 @@ alew_status alew_set_launch(alew_ctx* c, const alew_launch* l) {
   if (l->engine < 0 || l->engine > 2) return fail(ALEW_E_ARG, "unknown engine");
   if (l->block != 0 && l->block != 128 && l->block != 256 && l->block != 512)
     return fail(ALEW_E_ARG, "block must be 0, 128, 256 or 512");
+  if (l->cells_per_thread < 0 || l->cells_per_thread > 2)
+    return fail(ALEW_E_ARG, "cells_per_thread must be 0, 1 or 2");
   c->launch = *l;
-  if (c->cached_B != pick_block(c)) c->cell_off_h.clear();
   return ALEW_OK;
 }
 
@@ -922,7 +940,7 @@ alew_status alew_adjoint(alew_ctx* c, const alew_params* p, int64_t ninst,
   const int64_t nck = (nsteps + K - 1) / K;
   const int64_t NN = S + ninst, CS = S + 2 * ninst;
   const int B = 256;
-  alew_status ts = build_tiles(c, cell_off, ninst, B);
+  alew_status ts = build_tiles(c, cell_off, ninst, B, B);
   if (ts != ALEW_OK) return ts;
   // workspace layout (doubles)
   const size_t n_state = 2 * (size_t)S;                 // hu, b of the run
@@ -993,7 +1011,7 @@ alew_status alew_adjoint(alew_ctx* c, const alew_params* p, int64_t ninst,
       HIPCHK(hipMemcpyAsync(cq + 3 * S, xbuf_of(k), NN * 8, hipMemcpyDeviceToDevice, st));
       HIPCHK(hipMemcpyAsync(ckI + q * ninst, c->inst, ninst * sizeof(Inst), hipMemcpyDeviceToDevice, st));
     }
-    launch_step_seq<256>(c, bf, cs, st);
+    launch_step_seq<256, 1>(c, bf, cs, st);
   }
   HIPCHK(hipGetLastError());
   const int64_t ng = ninst * ngauge;
@@ -1028,7 +1046,7 @@ alew_status alew_adjoint(alew_ctx* c, const alew_params* p, int64_t ninst,
     for (int64_t k = k0; k < k1; ++k) {
       Bufs bd = bf;
       bd.dump = step_dump(k - k0);
-      launch_step_seq<256>(c, bd, cs, st);
+      launch_step_seq<256, 1>(c, bd, cs, st);
     }
     for (int64_t k = k1 - 1; k >= k0; --k) {
       const Dump d = step_dump(k - k0);

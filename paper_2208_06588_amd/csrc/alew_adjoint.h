@@ -531,7 +531,8 @@ __global__ __launch_bounds__(B) void k_adj_stage(AdjBufs ab, Consts cs,
       v5[k] = (cs.flags & F_BETA_FROM_H) ? h5[k] : sm.e[t + k];
     }
     if (cs.flags & F_BETA_LOCAL) Dx = sm.J[t + 2];
-    recon_cell(v5, h5, &sm.m[t], &sm.b[t], &sm.J[t], Dx, cs.weno_eps, sm.e[t + 2], o);
+    recon_cell(v5, h5, &sm.m[t], &sm.b[t], &sm.J[t], frcp(sm.J[t + 2]), Dx, cs.weno_eps,
+               sm.e[t + 2], o);
     ou = o;
     limit_cell(h5[2], sm.m[t + 2], cs.pp_eps, o);
     sm.tr[0][t] = o.hL; sm.tr[1][t] = o.mL; sm.tr[2][t] = o.bL;

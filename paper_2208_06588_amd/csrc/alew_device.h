@@ -75,6 +75,10 @@ __device__ __forceinline__ void amin_pos(unsigned long long* p, double v) {
 
 // Reciprocal: hardware estimate refined by two Newton steps (relative error of
 // a few ulp; every divisor here is a positive width, depth or sum).
+__device__ __forceinline__ unsigned hiword(double x) {
+  return (unsigned)(__double_as_longlong(x) >> 32);
+}
+
 __device__ __forceinline__ double frcp(double x) {
   double r = __builtin_amdgcn_rcp(x);
   double e = fma(-x, r, 1.0);
@@ -177,16 +181,15 @@ __device__ __forceinline__ void moments(double a, double b, double& M1, double& 
   M4 = (a2 * a2 + a2 * ab + ab * ab + ab * b2 + b2 * b2) * 0.2 - 0.0125;
 }
 
-// e5: eta (or h under F_BETA_FROM_H: chosen by the caller via v5), stencil
-// order cells j-2..j+2.
+// v5: eta (or h under F_BETA_FROM_H: chosen by the caller), stencil order
+// cells j-2..j+2; iJ0 = frcp(J5[2]).
 __device__ __forceinline__ void recon_cell(const double* __restrict__ v5,  // indicator var
                                            const double* __restrict__ h5,
                                            const double* __restrict__ m5,
                                            const double* __restrict__ b5,
-                                           const double* __restrict__ J5, double Dx, double eps,
-                                           double etabar, CellRecon& o) {
+                                           const double* __restrict__ J5, double iJ0, double Dx,
+                                           double eps, double etabar, CellRecon& o) {
   const double J0 = J5[2];
-  const double iJ0 = frcp(J0);
   // cell edges of the big stencil in y
   const double em1 = -0.5 - J5[1] * iJ0;
   const double em2 = em1 - J5[0] * iJ0;
@@ -217,36 +220,18 @@ __device__ __forceinline__ void recon_cell(const double* __restrict__ v5,  // in
   const double p2v[4] = {1.0 / 6.0, -1.0 / 30.0, -1.0 / 30.0, 1.0 / 6.0};
   const double f3v[4] = {-0.125, -q3, q3, 0.125};
   const double f4v[4] = {0.05, -0.01, -0.01, 0.05};
-  double d[4][3];
-  int negw = 0;
-  {
-    double B3[3], C3[3], B4[3], C4[3];
+  // error coefficients of the stencils on y^3 and y^4 - 1/80 (the weights are
+  // formed point by point below)
+  double B3[3], C3[3], B4[3], C4[3];
 #pragma unroll
-    for (int r = 0; r < 3; ++r) {
-      const int c1 = C1[r], c2 = C2[r];
-      B3[r] = kb1[r] * M3[c1] + kb2[r] * M3[c2];
-      C3[r] = kc1[r] * M3[c1] + kc2[r] * M3[c2];
-      B4[r] = kb1[r] * M4[c1] + kb2[r] * M4[c2];
-      C4[r] = kc1[r] * M4[c1] + kc2[r] * M4[c2];
-    }
-#pragma unroll
-    for (int mu = 0; mu < 4; ++mu) {
-      double e3[3], e4[3];
-#pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        e3[r] = B3[r] * yv[mu] + C3[r] * p2v[mu] - f3v[mu];
-        e4[r] = B4[r] * yv[mu] + C4[r] * p2v[mu] - f4v[mu];
-      }
-      const double x0 = e3[1] * e4[2] - e3[2] * e4[1];
-      const double x1 = e3[2] * e4[0] - e3[0] * e4[2];
-      const double x2 = e3[0] * e4[1] - e3[1] * e4[0];
-      const double is = frcp(x0 + x1 + x2);
-      d[mu][0] = x0 * is;
-      d[mu][1] = x1 * is;
-      d[mu][2] = x2 * is;
-      negw |= (d[mu][0] < 0.0) | (d[mu][1] < 0.0) | (d[mu][2] < 0.0);
-    }
+  for (int r = 0; r < 3; ++r) {
+    const int c1 = C1[r], c2 = C2[r];
+    B3[r] = kb1[r] * M3[c1] + kb2[r] * M3[c2];
+    C3[r] = kc1[r] * M3[c1] + kc2[r] * M3[c2];
+    B4[r] = kb1[r] * M4[c1] + kb2[r] * M4[c2];
+    C4[r] = kc1[r] * M4[c1] + kc2[r] * M4[c2];
   }
+  unsigned sgn = 0u;  // OR of the high words: bit 31 set if some weight is negative
   // per-variable stencil coefficients
   double dv[4], dh[4], dm[4], db[4];
   {
@@ -294,20 +279,37 @@ __device__ __forceinline__ void recon_cell(const double* __restrict__ v5,  // in
   double hv[4], mv[4], bv[4], bxv[4];
 #pragma unroll
   for (int mu = 0; mu < 4; ++mu) {
+    double d[3];
+    {
+      double e3[3], e4[3];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        e3[r] = B3[r] * yv[mu] + C3[r] * p2v[mu] - f3v[mu];
+        e4[r] = B4[r] * yv[mu] + C4[r] * p2v[mu] - f4v[mu];
+      }
+      const double x0 = e3[1] * e4[2] - e3[2] * e4[1];
+      const double x1 = e3[2] * e4[0] - e3[0] * e4[2];
+      const double x2 = e3[0] * e4[1] - e3[1] * e4[0];
+      const double is = frcp(x0 + x1 + x2);
+      d[0] = x0 * is;
+      d[1] = x1 * is;
+      d[2] = x2 * is;
+      sgn |= hiword(d[0]) | hiword(d[1]) | hiword(d[2]);
+    }
     double ph[3];
     if (cls == 0) {
-      ph[0] = d[mu][0];
-      ph[1] = d[mu][1];
-      ph[2] = d[mu][2];
+      ph[0] = d[0];
+      ph[1] = d[1];
+      ph[2] = d[2];
     } else {
-      const double a0 = d[mu][0] * K[0], a1 = d[mu][1] * K[1], a2 = d[mu][2] * K[2];
+      const double a0 = d[0] * K[0], a1 = d[1] * K[1], a2 = d[2] * K[2];
       const double ia = frcp(a0 + a1 + a2);
       ph[0] = a0 * ia;
       ph[1] = a1 * ia;
       ph[2] = a2 * ia;
       if (cls == 1) {
 #pragma unroll
-        for (int r = 0; r < 3; ++r) ph[r] = Mg * ph[r] + (1.0 - Mg) * d[mu][r];
+        for (int r = 0; r < 3; ++r) ph[r] = Mg * ph[r] + (1.0 - Mg) * d[r];
       }
     }
     const double y = yv[mu], p2 = p2v[mu];
@@ -335,7 +337,7 @@ __device__ __forceinline__ void recon_cell(const double* __restrict__ v5,  // in
   for (int mu = 0; mu < 4; ++mu) ri += (wgl[mu] * J0) * (((hv[mu] + bv[mu]) - etabar) * bxv[mu]);
   o.rint = ri;
   o.cls = cls;
-  o.negw = negw;
+  o.negw = (int)(sgn >> 31);
 }
 
 // ----------------------------------------------------------------------------

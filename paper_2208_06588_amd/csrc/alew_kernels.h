@@ -73,156 +73,270 @@ struct StageRes {
   int status;
 };
 
-template <int B>
+// LDS of a stage tile: B threads, CPT cells per thread, TB = B * CPT cells
+// reconstructed per tile (TB - 2 of them owned).
+template <int B, int CPT>
 struct SmemStage {
-  double e[B + 4], m[B + 4], b[B + 4], J[B + 4];
-  double tr[6][B];
-  double fl[8][B];
+  static constexpr int TB = B * CPT;
+  // Stencil slot i holds cell k = c0 - 3 + i (ghosts mapped).  The stencil
+  // arrays are dead once the traces are formed, so the face values reuse them.
+  union {
+    struct {
+      double e[TB + 4], m[TB + 4], b[TB + 4], J[TB + 4], iJ[TB + 4];
+    } in;
+    double fl[8][TB];
+  } u;
+  double tr[6][TB];
+  double wn[TB + 4];     // node speed at the left node of slot i (nodes 0..n)
+  double qn[3][TB + 4];  // a_s Q^n of owned slots (stages 2 and 3)
+  double Jx[TB + 4];     // the width this stage produces, a_s J^n + b_s (J + dt dw)
   double red[(B / 64) * 8];
   unsigned cnt[8];  // class S/T/N, limited, negative weight, status bits
 };
 
-// Stage-input state (eta, hu, b) and width of cell k (ghosts mapped).
-__device__ __forceinline__ void load_stage_cell(const Bufs& bf, const Consts& cs, const View& v,
-                                                const StageScal& sc, int64_t k, double& e,
-                                                double& m, double& b, double& J, int& st) {
-  double ms;
-  const int64_t src = ghost_src(cs.bc, v.n, k, ms);
-  const double Jn = v.x[src + 1] - v.x[src];
-  const int64_t g = v.co + src;
-  if (sc.s == 1) {
-    J = Jn;
-    e = bf.eta[g];
-    m = bf.m[g] * ms;
-    b = bf.b[g];
-  } else {
-    const double dw = bf.w[v.no + src + 1] * sc.wsc - bf.w[v.no + src] * sc.wsc;
-    const double J1 = Jn + sc.dt * dw;
-    J = (sc.s == 2) ? J1 : 0.75 * Jn + 0.25 * (J1 + sc.dt * dw);
-    const double* P = (sc.s == 2) ? bf.P0 : bf.P1;
-    const double* D = (sc.s == 2) ? bf.D0 : bf.D1;
-    const double iJ = frcp(J);
-    e = (P[g] + sc.cprev * D[g]) * iJ;
-    m = ((P[bf.S + g] + sc.cprev * D[bf.S + g]) * iJ) * ms;
-    b = (P[2 * bf.S + g] + sc.cprev * D[2 * bf.S + g]) * iJ;
-  }
-  if (!(J > 0.0)) st |= SB_MESH;
+// 32-bit byte offsets from a work-group-uniform base (instances of fewer than
+// 2^28 cells), so every load of a slot shares one offset register.
+__device__ __forceinline__ double ldo(const double* base, unsigned off) {
+  return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(base) + off);
 }
 
-// One stage over the tile of owned cells [c0, c0 + B - 2) of one instance.
-template <int B>
+// Stage inputs of one stencil slot from its raw loads: x^n and w of the two
+// nodes, and either q^n (stage 1) or P, D of the previous stage together with
+// q^n of the cell (stages 2, 3).  ms = -1 mirrors hu (reflective ghosts).
+template <class SM>
+__device__ __forceinline__ void put_slot(const StageScal& sc, int i, double ms, bool real,
+                                         double x0, double x1, double w0r, double w1r,
+                                         double a0, double a1, double a2, double d0, double d1,
+                                         double d2, double q0, double q1, double q2, SM& sm,
+                                         int& st) {
+  const double Jn = x1 - x0;
+  const double w0 = w0r * sc.wsc;
+  const double dw = w1r * sc.wsc - w0;
+  double J, iJ, e, m, b, qe = 0.0, qm = 0.0, qb = 0.0;
+  if (sc.s == 1) {
+    J = Jn;
+    iJ = frcp(J);
+    e = a0;
+    m = a1 * ms;
+    b = a2;
+  } else {
+    const double J1 = Jn + sc.dt * dw;
+    J = (sc.s == 2) ? J1 : 0.75 * Jn + 0.25 * (J1 + sc.dt * dw);
+    iJ = frcp(J);
+    e = (a0 + sc.cprev * d0) * iJ;
+    m = ((a1 + sc.cprev * d1) * iJ) * ms;
+    b = (a2 + sc.cprev * d2) * iJ;
+    if (real) {
+      qe = sc.as * (Jn * q0);
+      qm = sc.as * (Jn * q1);
+      qb = sc.as * (Jn * q2);
+    }
+  }
+  if (!(J > 0.0)) st |= SB_MESH;
+  sm.u.in.e[i] = e; sm.u.in.m[i] = m; sm.u.in.b[i] = b; sm.u.in.J[i] = J; sm.u.in.iJ[i] = iJ;
+  sm.Jx[i] = sc.as * Jn + sc.bs * (J + sc.dt * dw);
+  sm.qn[0][i] = qe; sm.qn[1][i] = qm; sm.qn[2][i] = qb;
+  if (real) sm.wn[i] = w0;
+}
+
+// Slot of a tile whose stencil cells are all real cells (no ghosts).
+template <class SM>
+__device__ __forceinline__ void load_slot_inner(const Bufs& bf, const View& v, const StageScal& sc,
+                                                unsigned k, int i, SM& sm, int& st) {
+  const unsigned o = k * 8u;
+  const double* xs = v.x;
+  const double* ws = bf.w + v.no;
+  const double x0 = ldo(xs, o), x1 = ldo(xs, o + 8u);
+  const double w0 = ldo(ws, o), w1 = ldo(ws, o + 8u);
+  const double* eta = bf.eta + v.co;
+  const double* hu = bf.m + v.co;
+  const double* bb = bf.b + v.co;
+  if (sc.s == 1) {
+    put_slot(sc, i, 1.0, true, x0, x1, w0, w1, ldo(eta, o), ldo(hu, o), ldo(bb, o), 0.0, 0.0, 0.0,
+             0.0, 0.0, 0.0, sm, st);
+  } else {
+    const double* P = ((sc.s == 2) ? bf.P0 : bf.P1) + v.co;
+    const double* D = ((sc.s == 2) ? bf.D0 : bf.D1) + v.co;
+    const int64_t S = bf.S;
+    put_slot(sc, i, 1.0, true, x0, x1, w0, w1, ldo(P, o), ldo(P + S, o), ldo(P + 2 * S, o),
+             ldo(D, o), ldo(D + S, o), ldo(D + 2 * S, o), ldo(eta, o), ldo(hu, o), ldo(bb, o), sm,
+             st);
+  }
+}
+
+// Slot of a tile that touches an end of the instance: ghosts mapped by the
+// boundary condition; slots beyond the ghosts get a harmless placeholder.
+template <class SM>
+__device__ __forceinline__ void load_slot_edge(const Bufs& bf, const Consts& cs, const View& v,
+                                               const StageScal& sc, int64_t k, int i, SM& sm,
+                                               int& st) {
+  sm.wn[i] = (k == v.n) ? bf.w[v.no + v.n] * sc.wsc : 0.0;
+  if (k >= -3 && k < v.n + 3) {
+    double ms;
+    const int64_t src = ghost_src(cs.bc, v.n, k, ms);
+    const bool real = k >= 0 && k < v.n;
+    const double x0 = v.x[src], x1 = v.x[src + 1];
+    const double w0 = bf.w[v.no + src], w1 = bf.w[v.no + src + 1];
+    const int64_t g = v.co + src;
+    if (sc.s == 1) {
+      put_slot(sc, i, ms, real, x0, x1, w0, w1, bf.eta[g], bf.m[g], bf.b[g], 0.0, 0.0, 0.0, 0.0,
+               0.0, 0.0, sm, st);
+    } else {
+      const double* P = (sc.s == 2) ? bf.P0 : bf.P1;
+      const double* D = (sc.s == 2) ? bf.D0 : bf.D1;
+      const int64_t S = bf.S;
+      put_slot(sc, i, ms, real, x0, x1, w0, w1, P[g], P[S + g], P[2 * S + g], D[g], D[S + g],
+               D[2 * S + g], bf.eta[g], bf.m[g], bf.b[g], sm, st);
+    }
+  } else {
+    sm.u.in.e[i] = 0.0; sm.u.in.m[i] = 0.0; sm.u.in.b[i] = 0.0;
+    sm.u.in.J[i] = 1.0; sm.u.in.iJ[i] = 1.0; sm.Jx[i] = 0.0;
+    sm.qn[0][i] = 0.0; sm.qn[1][i] = 0.0; sm.qn[2][i] = 0.0;
+  }
+}
+
+// One stage over the tile of owned cells [c0, c0 + TB - 2) of one instance.
+// Thread t handles the tile cells t + c B, c < CPT.
+template <int B, int CPT>
 __device__ __forceinline__ StageRes stage_tile(const Bufs& bf, const Consts& cs, const View& v,
                                                const StageScal& sc, int64_t c0,
-                                               SmemStage<B>& sm, uint8_t* cls_inst) {
+                                               SmemStage<B, CPT>& sm, uint8_t* cls_inst) {
+  constexpr int TB = B * CPT;
   const int t = threadIdx.x;
   int st = 0;
   if (t < 8) sm.cnt[t] = 0u;
-  // 1. stencil data for cells c0-3 .. c0+B
-  for (int i = t; i < B + 4; i += B) {
-    const int64_t k = c0 - 3 + i;
-    double e = 0, m = 0, b = 0, J = 1;
-    if (k >= -3 && k < v.n + 3) load_stage_cell(bf, cs, v, sc, k, e, m, b, J, st);
-    sm.e[i] = e; sm.m[i] = m; sm.b[i] = b; sm.J[i] = J;
-  }
-  __syncthreads();
-  // 2. reconstruct cell j = c0 - 1 + t (cells -1 and n are ghosts for the end faces)
-  const int64_t j = c0 - 1 + t;
-  const bool active = (j >= -1) && (j <= v.n);
-  const bool owned = (t >= 1) && (t <= B - 2) && (j < v.n);
-  CellRecon o;
-  double ebar = 0, hbar = 0, mbar = 0, bbar = 0, Jj = 1;
-  bool lim_owned = false, neg_cell = false;
-  int cls_owned = -1;
-  if (active) {
-    double h5[5], v5[5];
+  // 1. stencil data for cells c0-3 .. c0+TB
+  if (c0 >= 3 && c0 + TB < v.n && v.n < (int64_t(1) << 28)) {
 #pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      h5[k] = sm.e[t + k] - sm.b[t + k];
-      v5[k] = (cs.flags & F_BETA_FROM_H) ? h5[k] : sm.e[t + k];
-    }
-    ebar = sm.e[t + 2]; mbar = sm.m[t + 2]; bbar = sm.b[t + 2]; hbar = h5[2]; Jj = sm.J[t + 2];
-    const double Dx = (cs.flags & F_BETA_LOCAL) ? Jj : sc.dx;
-    recon_cell(v5, h5, &sm.m[t], &sm.b[t], &sm.J[t], Dx, cs.weno_eps, ebar, o);
-    const int lim = limit_cell(hbar, mbar, cs.pp_eps, o);
-    if (owned) {
-      cls_owned = o.cls;
-      lim_owned = lim != 0;
-      if (hbar < -cs.pp_eps) st |= SB_NEGDEPTH;
-      if (cls_inst) cls_inst[j] = (uint8_t)o.cls;
-    }
-    if (o.negw && (owned || j == -1 || j == v.n)) { neg_cell = true; st |= SB_NEGWEIGHT; }
-    sm.tr[0][t] = o.hL; sm.tr[1][t] = o.mL; sm.tr[2][t] = o.bL;
-    sm.tr[3][t] = o.hR; sm.tr[4][t] = o.mR; sm.tr[5][t] = o.bR;
+    for (int c = 0; c < CPT; ++c)
+      load_slot_inner(bf, v, sc, (unsigned)(c0 - 3 + t + c * B), t + c * B, sm, st);
+    if (t < 4) load_slot_inner(bf, v, sc, (unsigned)(c0 - 3 + TB + t), TB + t, sm, st);
+  } else {
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) load_slot_edge(bf, cs, v, sc, c0 - 3 + t + c * B, t + c * B, sm, st);
+    if (t < 4) load_slot_edge(bf, cs, v, sc, c0 - 3 + TB + t, TB + t, sm, st);
   }
   __syncthreads();
-  // 3. face at node k = j (between cells j-1 and j), t = 1 .. B-1
+  // 2. reconstruct tile cell i (cell j = c0 - 1 + i; cells -1 and n are ghosts
+  // for the end faces); one cell after the other
+  double ebar[CPT], mbar[CPT], bbar[CPT], Jj[CPT], rint[CPT];
+  unsigned n0 = 0, n1 = 0, n2 = 0, nl = 0, nn = 0;
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+    const int i = t + c * B;
+    const int64_t j = c0 - 1 + i;
+    const bool active = (j >= -1) && (j <= v.n);
+    const bool owned = (i >= 1) && (i <= TB - 2) && (j < v.n);
+    int cls_owned = -1;
+    bool lim_owned = false, neg_cell = false;
+    ebar[c] = 0.0; mbar[c] = 0.0; bbar[c] = 0.0; Jj[c] = 1.0; rint[c] = 0.0;
+    if (active) {
+      CellRecon o;
+      const double* se = sm.u.in.e + i;
+      const double* sb = sm.u.in.b + i;
+      double h5[5], v5[5];
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        h5[k] = se[k] - sb[k];
+        v5[k] = (cs.flags & F_BETA_FROM_H) ? h5[k] : se[k];
+      }
+      const double hbar = h5[2];
+      ebar[c] = se[2]; mbar[c] = sm.u.in.m[i + 2]; bbar[c] = sb[2]; Jj[c] = sm.u.in.J[i + 2];
+      const double Dx = (cs.flags & F_BETA_LOCAL) ? Jj[c] : sc.dx;
+      recon_cell(v5, h5, sm.u.in.m + i, sb, sm.u.in.J + i, sm.u.in.iJ[i + 2], Dx, cs.weno_eps,
+                 ebar[c], o);
+      const int lim = limit_cell(hbar, mbar[c], cs.pp_eps, o);
+      rint[c] = o.rint;
+      if (owned) {
+        cls_owned = o.cls;
+        lim_owned = lim != 0;
+        if (hbar < -cs.pp_eps) st |= SB_NEGDEPTH;
+        if (cls_inst) cls_inst[j] = (uint8_t)o.cls;
+      }
+      if (o.negw && (owned || j == -1 || j == v.n)) { neg_cell = true; st |= SB_NEGWEIGHT; }
+      sm.tr[0][i] = o.hL; sm.tr[1][i] = o.mL; sm.tr[2][i] = o.bL;
+      sm.tr[3][i] = o.hR; sm.tr[4][i] = o.mR; sm.tr[5][i] = o.bR;
+    }
+    // counters: one ballot per wave
+    n0 += (unsigned)__popcll(__ballot(cls_owned == 0));
+    n1 += (unsigned)__popcll(__ballot(cls_owned == 1));
+    n2 += (unsigned)__popcll(__ballot(cls_owned == 2));
+    nl += (unsigned)__popcll(__ballot(lim_owned));
+    nn += (unsigned)__popcll(__ballot(neg_cell));
+    // keep the reconstructions of different cells apart in the schedule (register pressure)
+    if (CPT > 1) __builtin_amdgcn_sched_barrier(0);
+  }
+  __syncthreads();
+  // 3. face at node j of tile cell i (between cells j-1 and j), i = 1 .. TB-1
   double fspeed = 0.0;
-  if (t >= 1 && j >= 0 && j <= v.n) {
-    Face f;
-    face_flux(sm.tr[3][t - 1], sm.tr[4][t - 1], sm.tr[5][t - 1], sm.tr[0][t], sm.tr[1][t],
-              sm.tr[2][t], bf.w[v.no + j] * sc.wsc, cs.g, cs.dry_eps, f);
-    sm.fl[0][t] = f.Fc1; sm.fl[1][t] = f.Fc2; sm.fl[2][t] = f.Gc; sm.fl[3][t] = f.je;
-    sm.fl[4][t] = f.jm; sm.fl[5][t] = f.jb; sm.fl[6][t] = f.B1; sm.fl[7][t] = f.B2;
-    fspeed = f.speed;
-    if (bf.dump.fs) {
-      const int64_t NN = bf.S + bf.ninst;
-      bf.dump.fs[(int64_t)(2 * (sc.s - 1)) * NN + v.no + j] = f.sl;
-      bf.dump.fs[(int64_t)(2 * (sc.s - 1) + 1) * NN + v.no + j] = f.sr;
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+    const int i = t + c * B;
+    const int64_t j = c0 - 1 + i;
+    if (i >= 1 && j >= 0 && j <= v.n) {
+      Face f;
+      face_flux(sm.tr[3][i - 1], sm.tr[4][i - 1], sm.tr[5][i - 1], sm.tr[0][i], sm.tr[1][i],
+                sm.tr[2][i], sm.wn[i + 2], cs.g, cs.dry_eps, f);
+      sm.u.fl[0][i] = f.Fc1; sm.u.fl[1][i] = f.Fc2; sm.u.fl[2][i] = f.Gc; sm.u.fl[3][i] = f.je;
+      sm.u.fl[4][i] = f.jm; sm.u.fl[5][i] = f.jb; sm.u.fl[6][i] = f.B1; sm.u.fl[7][i] = f.B2;
+      fspeed = fmax(fspeed, f.speed);
+      if (bf.dump.fs) {
+        const int64_t NN = bf.S + bf.ninst;
+        bf.dump.fs[(int64_t)(2 * (sc.s - 1)) * NN + v.no + j] = f.sl;
+        bf.dump.fs[(int64_t)(2 * (sc.s - 1) + 1) * NN + v.no + j] = f.sr;
+      }
     }
   }
   __syncthreads();
   // 4. owned cells: residual split, stage combination
   double maxJ = 0.0;
-  if (owned) {
-    const double g = cs.g;
-    const double Ae = -(sm.fl[0][t + 1] - sm.fl[0][t]);
-    const double S = 0.5 * g * (sm.fl[7][t + 1] - sm.fl[7][t]) - g * ebar * (sm.fl[6][t + 1] - sm.fl[6][t]) - g * o.rint;
-    const double Am = -(sm.fl[1][t + 1] - sm.fl[1][t]) + S;
-    const double Ab = -(sm.fl[2][t + 1] - sm.fl[2][t]);
-    const double De = 0.5 * (sm.fl[3][t + 1] - sm.fl[3][t]);
-    const double Dm = 0.5 * (sm.fl[4][t + 1] - sm.fl[4][t]);
-    const double Db = 0.5 * (sm.fl[5][t + 1] - sm.fl[5][t]);
-    const int64_t gi = v.co + j;
-    const double Jn = v.x[j + 1] - v.x[j];
-    const double dw = bf.w[v.no + j + 1] * sc.wsc - bf.w[v.no + j] * sc.wsc;
-    double Pe, Pm, Pb;
-    if (sc.s == 1) {
-      Pe = Jj * ebar + sc.dt * Ae;
-      Pm = Jj * mbar + sc.dt * Am;
-      Pb = Jj * bbar + sc.dt * Ab;
-    } else {
-      const double Qe = Jn * bf.eta[gi], Qm = Jn * bf.m[gi], Qb = Jn * bf.b[gi];
-      Pe = sc.as * Qe + sc.bs * (Jj * ebar + sc.dt * Ae);
-      Pm = sc.as * Qm + sc.bs * (Jj * mbar + sc.dt * Am);
-      Pb = sc.as * Qb + sc.bs * (Jj * bbar + sc.dt * Ab);
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+    const int i = t + c * B;
+    const int64_t j = c0 - 1 + i;
+    if ((i >= 1) && (i <= TB - 2) && (j < v.n)) {
+      const double g = cs.g;
+      const double(*fl)[TB] = sm.u.fl;
+      const double Ae = -(fl[0][i + 1] - fl[0][i]);
+      const double S = 0.5 * g * (fl[7][i + 1] - fl[7][i]) - g * ebar[c] * (fl[6][i + 1] - fl[6][i]) - g * rint[c];
+      const double Am = -(fl[1][i + 1] - fl[1][i]) + S;
+      const double Ab = -(fl[2][i + 1] - fl[2][i]);
+      const double De = 0.5 * (fl[3][i + 1] - fl[3][i]);
+      const double Dm = 0.5 * (fl[4][i + 1] - fl[4][i]);
+      const double Db = 0.5 * (fl[5][i + 1] - fl[5][i]);
+      const int64_t gi = v.co + j;
+      double Pe, Pm, Pb;
+      if (sc.s == 1) {
+        Pe = Jj[c] * ebar[c] + sc.dt * Ae;
+        Pm = Jj[c] * mbar[c] + sc.dt * Am;
+        Pb = Jj[c] * bbar[c] + sc.dt * Ab;
+      } else {
+        Pe = sm.qn[0][i + 2] + sc.bs * (Jj[c] * ebar[c] + sc.dt * Ae);
+        Pm = sm.qn[1][i + 2] + sc.bs * (Jj[c] * mbar[c] + sc.dt * Am);
+        Pb = sm.qn[2][i + 2] + sc.bs * (Jj[c] * bbar[c] + sc.dt * Ab);
+      }
+      double* Po = (sc.s == 2) ? bf.P1 : bf.P0;
+      double* Do = (sc.s == 2) ? bf.D1 : bf.D0;
+      Po[gi] = Pe; Po[bf.S + gi] = Pm; Po[2 * bf.S + gi] = Pb;
+      Do[gi] = De; Do[bf.S + gi] = Dm; Do[2 * bf.S + gi] = Db;
+      if (bf.dump.q) {
+        const int64_t o = (int64_t)(3 * (sc.s - 1)) * bf.S + gi;
+        bf.dump.q[o] = ebar[c]; bf.dump.q[o + bf.S] = mbar[c]; bf.dump.q[o + 2 * bf.S] = bbar[c];
+        bf.dump.D[o] = De; bf.dump.D[o + bf.S] = Dm; bf.dump.D[o + 2 * bf.S] = Db;
+      }
+      const double Jnext = sm.Jx[i + 2];
+      maxJ = fmax(maxJ, Jnext);
+      if (!(Jnext > 0.0)) st |= SB_MESH;
     }
-    double* Po = (sc.s == 2) ? bf.P1 : bf.P0;
-    double* Do = (sc.s == 2) ? bf.D1 : bf.D0;
-    Po[gi] = Pe; Po[bf.S + gi] = Pm; Po[2 * bf.S + gi] = Pb;
-    Do[gi] = De; Do[bf.S + gi] = Dm; Do[2 * bf.S + gi] = Db;
-    if (bf.dump.q) {
-      const int64_t o = (int64_t)(3 * (sc.s - 1)) * bf.S + gi;
-      bf.dump.q[o] = ebar; bf.dump.q[o + bf.S] = mbar; bf.dump.q[o + 2 * bf.S] = bbar;
-      bf.dump.D[o] = De; bf.dump.D[o + bf.S] = Dm; bf.dump.D[o + 2 * bf.S] = Db;
-    }
-    const double Jnext = sc.as * Jn + sc.bs * (Jj + sc.dt * dw);
-    maxJ = Jnext;
-    if (!(Jnext > 0.0)) st |= SB_MESH;
   }
-  // counters: one ballot per wave, summed in LDS
-  {
-    const unsigned long long b0 = __ballot(cls_owned == 0), b1 = __ballot(cls_owned == 1);
-    const unsigned long long b2 = __ballot(cls_owned == 2), bl = __ballot(lim_owned);
-    const unsigned long long bn = __ballot(neg_cell);
-    if ((t & 63) == 0) {
-      atomicAdd(&sm.cnt[0], (unsigned)__popcll(b0));
-      atomicAdd(&sm.cnt[1], (unsigned)__popcll(b1));
-      atomicAdd(&sm.cnt[2], (unsigned)__popcll(b2));
-      if (bl) atomicAdd(&sm.cnt[3], (unsigned)__popcll(bl));
-      if (bn) atomicAdd(&sm.cnt[4], (unsigned)__popcll(bn));
-    }
-    if (st) atomicOr(&sm.cnt[5], (unsigned)st);
+  if ((t & 63) == 0) {
+    atomicAdd(&sm.cnt[0], n0);
+    atomicAdd(&sm.cnt[1], n1);
+    atomicAdd(&sm.cnt[2], n2);
+    if (nl) atomicAdd(&sm.cnt[3], nl);
+    if (nn) atomicAdd(&sm.cnt[4], nn);
   }
+  if (st) atomicOr(&sm.cnt[5], (unsigned)st);
   double rv[2] = {fspeed, maxJ};
   const int op[2] = {0, 0};
   block_reduce<B, 2>(rv, op, sm.red);

@@ -151,9 +151,9 @@ def test_given_mesh_reflective_step(dev):
     _assert_parity(g, r)
 
 
-def _small_batch(seed=5, ninst=6):
+def _small_batch(seed=5, ninst=6, big=()):
     rng = np.random.default_rng(seed)
-    ns = rng.integers(40, 400, ninst)
+    ns = list(rng.integers(40, 400, ninst)) + list(big)
     eps = rng.uniform(1e-5, 1e-2, ninst)
     insts = [W.perturbation_instance(int(n), float(e)) for n, e in zip(ns, eps)]
     return W.pack(insts, bc="transmissive", t_end=0.2, cfl=0.6, weno_eps=1e-9, mesh="sine",
@@ -162,28 +162,31 @@ def _small_batch(seed=5, ninst=6):
 
 def test_batched_engines_bitwise_and_oracle(dev):
     """Ragged batch: the persistent engine and the stage-launch engine (three
-    block sizes) give bitwise identical results; each instance matches the
-    oracle run on its own."""
-    bt = _small_batch()
+    block sizes, one and two cells per thread) give bitwise identical results;
+    each instance matches the oracle run on its own.  Two larger instances have
+    stage tiles away from both ends (the ghost-free load path) at every tile
+    width."""
+    bt = _small_batch(big=(1100, 1733))
     off = bt["cell_off"]
     n = int(off[-1])
     ninst = len(off) - 1
     p = _gp(bt)
     nsteps = 25
     outs = []
-    for engine, block in ((alew.ENGINE_PERSISTENT, 256), (alew.ENGINE_STAGES, 128),
-                          (alew.ENGINE_STAGES, 256), (alew.ENGINE_STAGES, 512),
-                          (alew.ENGINE_PERSISTENT, 128)):
+    for engine, block, cpt in ((alew.ENGINE_PERSISTENT, 256, 1), (alew.ENGINE_STAGES, 128, 1),
+                               (alew.ENGINE_STAGES, 256, 1), (alew.ENGINE_STAGES, 512, 1),
+                               (alew.ENGINE_PERSISTENT, 128, 1), (alew.ENGINE_STAGES, 128, 2),
+                               (alew.ENGINE_STAGES, 256, 2)):
         ctx = alew.Context(n, ninst)
-        ctx.set_launch(engine=engine, block=block, use_graph=1)
+        ctx.set_launch(engine=engine, block=block, use_graph=1, cells_per_thread=cpt)
         T = {k: _t(bt[k], dev) for k in ("h", "hu", "b", "x", "xi")}
         st = ctx.run(p, off, T["h"], T["hu"], T["b"], T["x"], T["xi"], max_steps=[nsteps] * ninst)
         torch.cuda.synchronize()
         outs.append(({k: v.cpu().numpy() for k, v in T.items()}, st))
     ref = outs[0][0]
-    for o, st in outs[1:]:
+    for ci, (o, st) in enumerate(outs[1:], 1):
         for k in ("h", "hu", "b", "x"):
-            assert np.array_equal(o[k], ref[k]), k
+            assert np.array_equal(o[k], ref[k]), (ci, k, float(np.max(np.abs(o[k] - ref[k]))))
     for i in range(ninst):
         a, e = int(off[i]), int(off[i + 1])
         r = O.run(_op(bt), bt["h"][a:e], bt["hu"][a:e], bt["b"][a:e], bt["x"][a + i:e + i + 1],

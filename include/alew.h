@@ -108,13 +108,17 @@ typedef struct {
  * the host (0 = until every instance is done).
  * use_graph: stage-launch engine, replay the launches of a step as a hipGraph.
  * cells_per_thread: stage-launch engine, cells each thread reconstructs per
- * tile (1 or 2; 0 = 1); a tile spans block * cells_per_thread cells. */
+ * tile (1 or 2; 0 = 1); a tile spans block * cells_per_thread cells.
+ * prefetch: stage-launch engine with one cell per thread: 1 = tiles away from
+ * the instance ends run in a kernel that streams each work-group's next tile
+ * into LDS while it computes the current one; 0 = one plain kernel (default). */
 typedef struct {
   int32_t engine;
   int32_t block;
   int32_t steps_per_launch;
   int32_t use_graph;
   int32_t cells_per_thread;
+  int32_t prefetch;
 } alew_launch;
 
 /* Create a context able to run up to max_cells cells in up to max_inst instances.

@@ -101,6 +101,18 @@ __global__ __launch_bounds__(B) void k_wfluid(Bufs bf, Consts cs, const Tile* __
   if (threadIdx.x == 0) amax_pos(&I.r_W, W);
 }
 
+// Per-instance results of one stage tile.
+__device__ __forceinline__ void publish_stage(Inst& I, int s, const StageRes& r) {
+  amax_pos(&I.r_alpha, r.alpha);
+  if (s < 3) amax_pos(&I.r_maxJs, r.maxJ);
+  atomicAdd(&I.n_class[0], (unsigned long long)r.ncls0);
+  atomicAdd(&I.n_class[1], (unsigned long long)r.ncls1);
+  atomicAdd(&I.n_class[2], (unsigned long long)r.ncls2);
+  atomicAdd(&I.n_limited, (unsigned long long)r.nlim);
+  atomicAdd(&I.n_negweight, (unsigned long long)r.nneg);
+  if (r.status) atomicOr(&I.status, r.status);
+}
+
 template <int B, int CPT>
 __global__ __launch_bounds__(B) void k_stage(Bufs bf, Consts cs, const Tile* __restrict__ tiles,
                                              int s) {
@@ -109,26 +121,57 @@ __global__ __launch_bounds__(B) void k_stage(Bufs bf, Consts cs, const Tile* __r
   Inst& I = bf.inst[tl.inst];
   if (!I.active) return;
   View v = make_view(bf, tl.inst, I);
-  StageScal sc;
-  sc.s = s;
-  sc.dt = I.dt;
-  sc.as = s == 1 ? 0.0 : (s == 2 ? 0.75 : 1.0 / 3.0);
-  sc.bs = s == 1 ? 1.0 : (s == 2 ? 0.25 : 2.0 / 3.0);
-  const double bprev = s == 2 ? 1.0 : 0.25;
-  sc.cprev = s == 1 ? 0.0 : bprev * I.dt * I.alpha[s - 2];
-  sc.dx = I.dx[s - 1];
-  sc.wsc = I.wscale;
+  const StageScal sc = stage_scal(I, s);
   uint8_t* cl = bf.cls ? bf.cls + (int64_t)(s - 1) * bf.S + v.co : nullptr;
   StageRes r = stage_tile<B, CPT>(bf, cs, v, sc, tl.c0, sm, cl);
-  if (threadIdx.x == 0) {
-    amax_pos(&I.r_alpha, r.alpha);
-    if (s < 3) amax_pos(&I.r_maxJs, r.maxJ);
-    atomicAdd(&I.n_class[0], (unsigned long long)r.ncls0);
-    atomicAdd(&I.n_class[1], (unsigned long long)r.ncls1);
-    atomicAdd(&I.n_class[2], (unsigned long long)r.ncls2);
-    atomicAdd(&I.n_limited, (unsigned long long)r.nlim);
-    atomicAdd(&I.n_negweight, (unsigned long long)r.nneg);
-    if (r.status) atomicOr(&I.status, r.status);
+  if (threadIdx.x == 0) publish_stage(I, s, r);
+}
+
+// Stage-launch engine, ghost-free tiles: work-group b takes the tiles b, b+G,
+// b+2G, ... of the table (G = grid size) and streams the raw rows of its next
+// tile into LDS while it computes the current one.
+// The thread index as a value the compiler cannot carry across iterations:
+// without it, loop-invariant code motion keeps every per-thread LDS address
+// of the tile body live through the whole loop (about 60 extra registers).
+__device__ __forceinline__ int tid_fresh() {
+  int t;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(t) : "v"((int)threadIdx.x));
+  return t;
+}
+
+template <int B>
+__global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(3))) void k_stage_pipe(
+    Bufs bf, Consts cs, const Tile* __restrict__ tiles, int64_t ntiles, int s) {
+  __shared__ RawRows<B> sp;
+  __shared__ SmemStage<B, 1> sm;
+  const int64_t G = gridDim.x;
+  int64_t k = blockIdx.x;
+  if (k >= ntiles) return;
+  // tile k is copied while its predecessor computes; the records of tile k+G
+  // are read one iteration ahead
+  TileInfo cur = tile_info(bf, tiles, k, s);
+  issue_tile<B>(bf, cur.v, s, cur.c0, sp, (int)threadIdx.x);
+  TileInfo nxt = cur;
+  if (k + G < ntiles) nxt = tile_info(bf, tiles, k + G, s);
+  for (; k < ntiles; k += G) {
+    const int t = tid_fresh();
+    int st = 0;
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's copies into LDS have landed
+    lds_sync();
+    slot_from_raw<B>(cur.sc, t, sp, sm, st);
+    if (t < 4) slot_from_raw<B>(cur.sc, B + t, sp, sm, st);
+    lds_sync();
+    const bool more = k + G < ntiles;
+    if (more) issue_tile<B>(bf, nxt.v, s, nxt.c0, sp, t);
+    TileInfo after = nxt;
+    if (k + 2 * G < ntiles) after = tile_info(bf, tiles, k + 2 * G, s);
+    if (cur.active) {
+      uint8_t* cl = bf.cls ? bf.cls + (int64_t)(s - 1) * bf.S + cur.v.co : nullptr;
+      const StageRes r = stage_compute<B, 1>(bf, cs, cur.v, cur.sc, cur.c0, sm, cl, st, t);
+      if (t == 0) publish_stage(bf.inst[cur.inst], s, r);
+    }
+    cur = nxt;
+    nxt = after;
   }
 }
 
@@ -292,15 +335,7 @@ __global__ __launch_bounds__(B) void k_persistent(Bufs bf, Consts cs,
       unsigned long long c_cls[3] = {0, 0, 0}, c_lim = 0, c_neg = 0;
       int st = 0;
       for (int s = 1; s <= 3; ++s) {
-        StageScal sc;
-        sc.s = s;
-        sc.dt = dt;
-        sc.as = s == 1 ? 0.0 : (s == 2 ? 0.75 : 1.0 / 3.0);
-        sc.bs = s == 1 ? 1.0 : (s == 2 ? 0.25 : 2.0 / 3.0);
-        const double bprev = s == 2 ? 1.0 : 0.25;
-        sc.cprev = s == 1 ? 0.0 : bprev * dt * sI.alpha[s - 2];
-        sc.dx = sI.dx[s - 1];
-        sc.wsc = sI.wscale;
+        const StageScal sc = stage_scal(sI, s);
         double amax = 0.0, jmax = 0.0;
         for (int64_t c0 = 0; c0 < v.n; c0 += B - 2) {
           StageRes r = stage_tile<B, 1>(bf, cs, v, sc, c0, sm, nullptr);
@@ -459,11 +494,16 @@ struct alew_ctx {
   double* dt1_h = nullptr;   // pinned staging
   Tile* tiles_stage_d = nullptr;
   Tile* tiles_plain_d = nullptr;
+  Tile* tiles_edge_d = nullptr;   // stage tiles touching an instance end
+  Tile* tiles_inner_d = nullptr;  // ghost-free stage tiles (prefetching kernel)
   int64_t tiles_cap = 0;
+  int64_t n_tiles_edge = 0, n_tiles_inner = 0;
+  int pipe_blocks[3] = {0, 0, 0};  // resident work-groups per CU of k_stage_pipe<128/256/512>
+  int n_cu = 0;
   std::vector<int64_t> cell_off_h;  // cached batch layout
   int cached_B = 0, cached_TB = 0;
   int64_t n_tiles_stage = 0, n_tiles_plain = 0;
-  alew_launch launch{0, 256, 0, 1, 1};
+  alew_launch launch{0, 256, 0, 1, 1, 0};
   hipEvent_t ev0 = nullptr, ev1 = nullptr;  // around the compute launches of a call
   // adjoint workspace (allocated by the first alew_adjoint call, grown on demand)
   double* adj_ws = nullptr;
@@ -512,23 +552,35 @@ int pick_cpt(const alew_ctx* c, int B) {
 alew_status build_tiles(alew_ctx* c, const int64_t* cell_off, int64_t ninst, int B, int TB) {
   std::vector<int64_t> off(cell_off, cell_off + ninst + 1);
   if (off == c->cell_off_h && c->cached_B == B && c->cached_TB == TB) return ALEW_OK;
-  std::vector<Tile> ts, tp;
+  std::vector<Tile> ts, tp, te, tin;
   for (int64_t i = 0; i < ninst; ++i) {
     const int64_t n = off[i + 1] - off[i];
-    for (int64_t c0 = 0; c0 < n; c0 += TB - 2) ts.push_back(Tile{(int32_t)i, 0, c0});
+    for (int64_t c0 = 0; c0 < n; c0 += TB - 2) {
+      ts.push_back(Tile{(int32_t)i, 0, c0});
+      // same test as tile_inner() on the device
+      const bool inner = c0 >= 3 && c0 + TB < n && n < (int64_t(1) << 28);
+      (inner ? tin : te).push_back(Tile{(int32_t)i, 0, c0});
+    }
     for (int64_t c0 = 0; c0 <= n; c0 += B) tp.push_back(Tile{(int32_t)i, 0, c0});
   }
   const int64_t need = (int64_t)std::max(ts.size(), tp.size());
   if (need > c->tiles_cap) {
-    if (c->tiles_stage_d) (void)hipFree(c->tiles_stage_d);
-    if (c->tiles_plain_d) (void)hipFree(c->tiles_plain_d);
-    c->tiles_stage_d = c->tiles_plain_d = nullptr;
+    for (Tile** tp_ : {&c->tiles_stage_d, &c->tiles_plain_d, &c->tiles_edge_d, &c->tiles_inner_d}) {
+      if (*tp_) (void)hipFree(*tp_);
+      *tp_ = nullptr;
+    }
     HIPCHK(hipMalloc(&c->tiles_stage_d, need * sizeof(Tile)));
     HIPCHK(hipMalloc(&c->tiles_plain_d, need * sizeof(Tile)));
+    HIPCHK(hipMalloc(&c->tiles_edge_d, need * sizeof(Tile)));
+    HIPCHK(hipMalloc(&c->tiles_inner_d, need * sizeof(Tile)));
     c->tiles_cap = need;
   }
   HIPCHK(hipMemcpyAsync(c->tiles_stage_d, ts.data(), ts.size() * sizeof(Tile), hipMemcpyHostToDevice, c->stream));
   HIPCHK(hipMemcpyAsync(c->tiles_plain_d, tp.data(), tp.size() * sizeof(Tile), hipMemcpyHostToDevice, c->stream));
+  if (!te.empty())
+    HIPCHK(hipMemcpyAsync(c->tiles_edge_d, te.data(), te.size() * sizeof(Tile), hipMemcpyHostToDevice, c->stream));
+  if (!tin.empty())
+    HIPCHK(hipMemcpyAsync(c->tiles_inner_d, tin.data(), tin.size() * sizeof(Tile), hipMemcpyHostToDevice, c->stream));
   HIPCHK(hipMemcpyAsync(c->cell_off_d, off.data(), off.size() * sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
   // largest work first for the persistent queue
   std::vector<int32_t> order(ninst);
@@ -543,6 +595,8 @@ alew_status build_tiles(alew_ctx* c, const int64_t* cell_off, int64_t ninst, int
   c->cached_TB = TB;
   c->n_tiles_stage = (int64_t)ts.size();
   c->n_tiles_plain = (int64_t)tp.size();
+  c->n_tiles_edge = (int64_t)te.size();
+  c->n_tiles_inner = (int64_t)tin.size();
   if (c->gexec) { (void)hipGraphExecDestroy(c->gexec); c->gexec = nullptr; }
   if (c->graph) { (void)hipGraphDestroy(c->graph); c->graph = nullptr; }
   return ALEW_OK;
@@ -562,11 +616,35 @@ Bufs make_bufs(alew_ctx* c, int64_t S, int64_t ninst, double* hu, double* b, con
   return bf;
 }
 
+// Work-groups of the prefetching stage kernel: as many as stay resident.
+template <int B>
+int pipe_grid(alew_ctx* c) {
+  const int slot = B == 128 ? 0 : (B == 256 ? 1 : 2);
+  if (c->pipe_blocks[slot] == 0) {
+    int dev = 0, per_cu = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_stage_pipe<B>, B, 0);
+    c->pipe_blocks[slot] = std::max(1, per_cu);
+  }
+  const int64_t g = (int64_t)std::max(1, c->n_cu) * c->pipe_blocks[slot];
+  return (int)std::min<int64_t>(g, c->n_tiles_inner);
+}
+
 template <int B, int CPT>
 void launch_step_seq(alew_ctx* c, const Bufs& bf, const Consts& cs, hipStream_t st) {
   const dim3 gs((unsigned)c->n_tiles_stage), gp((unsigned)c->n_tiles_plain);
+  const bool pipe = CPT == 1 && c->launch.prefetch == 1 && c->n_tiles_inner > 0;
   for (int s = 1; s <= 3; ++s) {
-    hipLaunchKernelGGL((k_stage<B, CPT>), gs, dim3(B), 0, st, bf, cs, c->tiles_stage_d, s);
+    if (pipe) {
+      if (c->n_tiles_edge > 0)
+        hipLaunchKernelGGL((k_stage<B, 1>), dim3((unsigned)c->n_tiles_edge), dim3(B), 0, st, bf,
+                           cs, c->tiles_edge_d, s);
+      hipLaunchKernelGGL(k_stage_pipe<B>, dim3((unsigned)pipe_grid<B>(c)), dim3(B), 0, st, bf, cs,
+                         c->tiles_inner_d, c->n_tiles_inner, s);
+    } else {
+      hipLaunchKernelGGL((k_stage<B, CPT>), gs, dim3(B), 0, st, bf, cs, c->tiles_stage_d, s);
+    }
     hipLaunchKernelGGL(k_after_stage, dim3(1), dim3(1024), 0, st, bf, s);
   }
   hipLaunchKernelGGL(k_final<B>, gp, dim3(B), 0, st, bf, cs, c->tiles_plain_d);
@@ -585,6 +663,7 @@ GraphKey make_key(const Bufs& bf, const Consts& cs, int B, int CPT, const alew_c
   put(&cs, sizeof(cs));
   put(&B, sizeof(B));
   put(&CPT, sizeof(CPT));
+  put(&c->launch.prefetch, sizeof(int32_t));
   put(&c->n_tiles_stage, sizeof(int64_t));
   put(&c->n_tiles_plain, sizeof(int64_t));
   return k;
@@ -839,7 +918,8 @@ void alew_destroy(alew_ctx* c) {
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
   void* ps[] = {c->eta, c->P0, c->D0, c->P1, c->D1, c->w, c->xa, c->xb, c->inst, c->cell_off_d,
-                c->order_d, c->queue_d, c->nactive_d, c->tiles_stage_d, c->tiles_plain_d, c->dt1_d,
+                c->order_d, c->queue_d, c->nactive_d, c->tiles_stage_d, c->tiles_plain_d,
+                c->tiles_edge_d, c->tiles_inner_d, c->dt1_d,
                 c->adj_ws};
   for (void* p : ps)
     if (p) (void)hipFree(p);
@@ -865,6 +945,7 @@ alew_status alew_set_launch(alew_ctx* c, const alew_launch* l) {
     return fail(ALEW_E_ARG, "block must be 0, 128, 256 or 512");
   if (l->cells_per_thread < 0 || l->cells_per_thread > 2)
     return fail(ALEW_E_ARG, "cells_per_thread must be 0, 1 or 2");
+  if (l->prefetch < 0 || l->prefetch > 1) return fail(ALEW_E_ARG, "prefetch must be 0 or 1");
   c->launch = *l;
   return ALEW_OK;
 }

@@ -111,6 +111,19 @@ __device__ __forceinline__ unsigned wave_usum(unsigned v) {
   return v;
 }
 
+// Work-group barrier for LDS traffic only: each wave waits for its own LDS
+// accesses (s_waitcnt lgkmcnt(0); the vector-memory and export counters are
+// left at their maxima), not for global loads, stores or direct-to-LDS copies
+// still in flight.  The signal fences keep the compiler from moving memory
+// accesses across the barrier.  Used only where the waves exchange data
+// through LDS that they wrote with ordinary LDS stores.
+__device__ __forceinline__ void lds_sync() {
+  __builtin_amdgcn_s_waitcnt(0xc07f);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 // Reduce NV values per thread across the work-group.  op[k]: 0 max, 1 min, 2 sum.
 template <int B, int NV>
 __device__ __forceinline__ void block_reduce(double (&v)[NV], const int (&op)[NV], double* red) {
@@ -118,12 +131,12 @@ __device__ __forceinline__ void block_reduce(double (&v)[NV], const int (&op)[NV
 #pragma unroll
   for (int k = 0; k < NV; ++k)
     v[k] = op[k] == 0 ? wave_max(v[k]) : (op[k] == 1 ? wave_min(v[k]) : wave_sum(v[k]));
-  __syncthreads();
+  lds_sync();
   if (lane == 0) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) red[wid * NV + k] = v[k];
   }
-  __syncthreads();
+  lds_sync();
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
     double r = red[k];

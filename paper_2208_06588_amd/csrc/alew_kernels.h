@@ -66,6 +66,20 @@ struct StageScal {
   double wsc;      // node speed = wsc * w[]
 };
 
+// Scalars of stage s of an instance.
+__device__ __forceinline__ StageScal stage_scal(const Inst& I, int s) {
+  StageScal sc;
+  sc.s = s;
+  sc.dt = I.dt;
+  sc.as = s == 1 ? 0.0 : (s == 2 ? 0.75 : 1.0 / 3.0);
+  sc.bs = s == 1 ? 1.0 : (s == 2 ? 0.25 : 2.0 / 3.0);
+  const double bprev = s == 2 ? 1.0 : 0.25;
+  sc.cprev = s == 1 ? 0.0 : bprev * I.dt * I.alpha[s - 2];
+  sc.dx = I.dx[s - 1];
+  sc.wsc = I.wscale;
+  return sc;
+}
+
 // Block-level results of a stage tile.
 struct StageRes {
   double alpha, maxJ;
@@ -78,6 +92,7 @@ struct StageRes {
 template <int B, int CPT>
 struct SmemStage {
   static constexpr int TB = B * CPT;
+  static constexpr int NW = B / 64;
   // Stencil slot i holds cell k = c0 - 3 + i (ghosts mapped).  The stencil
   // arrays are dead once the traces are formed, so the face values reuse them.
   union {
@@ -86,12 +101,12 @@ struct SmemStage {
     } in;
     double fl[8][TB];
   } u;
-  double tr[6][TB];
   double wn[TB + 4];     // node speed at the left node of slot i (nodes 0..n)
   double qn[3][TB + 4];  // a_s Q^n of owned slots (stages 2 and 3)
   double Jx[TB + 4];     // the width this stage produces, a_s J^n + b_s (J + dt dw)
-  double red[(B / 64) * 8];
-  unsigned cnt[8];  // class S/T/N, limited, negative weight, status bits
+  double xr[CPT * NW][3];  // right traces of the last lane of each wave
+  double red[NW * 8];
+  unsigned cntw[NW][8];  // per wave: class S/T/N, limited, negative weight, status bits
 };
 
 // 32-bit byte offsets from a work-group-uniform base (instances of fewer than
@@ -195,18 +210,20 @@ __device__ __forceinline__ void load_slot_edge(const Bufs& bf, const Consts& cs,
   }
 }
 
-// One stage over the tile of owned cells [c0, c0 + TB - 2) of one instance.
-// Thread t handles the tile cells t + c B, c < CPT.
+// True if every stencil slot of the tile at c0 is a real cell.
+template <int TB>
+__device__ __forceinline__ bool tile_inner(const View& v, int64_t c0) {
+  return c0 >= 3 && c0 + TB < v.n && v.n < (int64_t(1) << 28);
+}
+
+// Phase 1 of a stage tile: stencil data for cells c0-3 .. c0+TB in LDS.
 template <int B, int CPT>
-__device__ __forceinline__ StageRes stage_tile(const Bufs& bf, const Consts& cs, const View& v,
-                                               const StageScal& sc, int64_t c0,
-                                               SmemStage<B, CPT>& sm, uint8_t* cls_inst) {
+__device__ __forceinline__ void stage_load(const Bufs& bf, const Consts& cs, const View& v,
+                                           const StageScal& sc, int64_t c0,
+                                           SmemStage<B, CPT>& sm, int& st) {
   constexpr int TB = B * CPT;
   const int t = threadIdx.x;
-  int st = 0;
-  if (t < 8) sm.cnt[t] = 0u;
-  // 1. stencil data for cells c0-3 .. c0+TB
-  if (c0 >= 3 && c0 + TB < v.n && v.n < (int64_t(1) << 28)) {
+  if (tile_inner<TB>(v, c0)) {
 #pragma unroll
     for (int c = 0; c < CPT; ++c)
       load_slot_inner(bf, v, sc, (unsigned)(c0 - 3 + t + c * B), t + c * B, sm, st);
@@ -216,10 +233,36 @@ __device__ __forceinline__ StageRes stage_tile(const Bufs& bf, const Consts& cs,
     for (int c = 0; c < CPT; ++c) load_slot_edge(bf, cs, v, sc, c0 - 3 + t + c * B, t + c * B, sm, st);
     if (t < 4) load_slot_edge(bf, cs, v, sc, c0 - 3 + TB + t, TB + t, sm, st);
   }
-  __syncthreads();
+}
+
+// Double as two 32-bit lanes through ds_bpermute: value of lane (lane - 1)
+// (lane 0 receives its own value).
+__device__ __forceinline__ double shfl_prev(double x, int lane) {
+  const int addr = (lane == 0 ? 0 : lane - 1) << 2;
+  const long long u = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_ds_bpermute(addr, (int)(u & 0xffffffffll));
+  const int hi = __builtin_amdgcn_ds_bpermute(addr, (int)(u >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Phases 2-4 of a stage tile (the stencil data is in LDS and visible to the
+// whole work-group): reconstruction and limiter per cell, interface fluxes,
+// residual split and stage combination of the owned cells, and the tile's
+// reductions.  Thread t handles the tile cells t + c B, c < CPT.
+template <int B, int CPT>
+__device__ __forceinline__ StageRes stage_compute(const Bufs& bf, const Consts& cs, const View& v,
+                                                  const StageScal& sc, int64_t c0,
+                                                  SmemStage<B, CPT>& sm, uint8_t* cls_inst,
+                                                  int st, int t) {
+  constexpr int TB = B * CPT;
+  constexpr int NW = B / 64;
+  const int lane = t & 63, wv = t >> 6;
   // 2. reconstruct tile cell i (cell j = c0 - 1 + i; cells -1 and n are ghosts
-  // for the end faces); one cell after the other
+  // for the end faces); one cell after the other.  The left state of the face
+  // at node j is the right trace of cell j-1: from the previous lane, or for
+  // lane 0 through LDS after the barrier.
   double ebar[CPT], mbar[CPT], bbar[CPT], Jj[CPT], rint[CPT];
+  double tl0[CPT], tl1[CPT], tl2[CPT], tp0[CPT], tp1[CPT], tp2[CPT];
   unsigned n0 = 0, n1 = 0, n2 = 0, nl = 0, nn = 0;
 #pragma unroll
   for (int c = 0; c < CPT; ++c) {
@@ -230,6 +273,8 @@ __device__ __forceinline__ StageRes stage_tile(const Bufs& bf, const Consts& cs,
     int cls_owned = -1;
     bool lim_owned = false, neg_cell = false;
     ebar[c] = 0.0; mbar[c] = 0.0; bbar[c] = 0.0; Jj[c] = 1.0; rint[c] = 0.0;
+    double hR = 0.0, mR = 0.0, bR = 0.0;
+    tl0[c] = 0.0; tl1[c] = 0.0; tl2[c] = 0.0;
     if (active) {
       CellRecon o;
       const double* se = sm.u.in.e + i;
@@ -254,8 +299,12 @@ __device__ __forceinline__ StageRes stage_tile(const Bufs& bf, const Consts& cs,
         if (cls_inst) cls_inst[j] = (uint8_t)o.cls;
       }
       if (o.negw && (owned || j == -1 || j == v.n)) { neg_cell = true; st |= SB_NEGWEIGHT; }
-      sm.tr[0][i] = o.hL; sm.tr[1][i] = o.mL; sm.tr[2][i] = o.bL;
-      sm.tr[3][i] = o.hR; sm.tr[4][i] = o.mR; sm.tr[5][i] = o.bR;
+      tl0[c] = o.hL; tl1[c] = o.mL; tl2[c] = o.bL;
+      hR = o.hR; mR = o.mR; bR = o.bR;
+    }
+    tp0[c] = shfl_prev(hR, lane); tp1[c] = shfl_prev(mR, lane); tp2[c] = shfl_prev(bR, lane);
+    if (lane == 63) {
+      sm.xr[c * NW + wv][0] = hR; sm.xr[c * NW + wv][1] = mR; sm.xr[c * NW + wv][2] = bR;
     }
     // counters: one ballot per wave
     n0 += (unsigned)__popcll(__ballot(cls_owned == 0));
@@ -266,7 +315,7 @@ __device__ __forceinline__ StageRes stage_tile(const Bufs& bf, const Consts& cs,
     // keep the reconstructions of different cells apart in the schedule (register pressure)
     if (CPT > 1) __builtin_amdgcn_sched_barrier(0);
   }
-  __syncthreads();
+  lds_sync();
   // 3. face at node j of tile cell i (between cells j-1 and j), i = 1 .. TB-1
   double fspeed = 0.0;
 #pragma unroll
@@ -274,9 +323,12 @@ __device__ __forceinline__ StageRes stage_tile(const Bufs& bf, const Consts& cs,
     const int i = t + c * B;
     const int64_t j = c0 - 1 + i;
     if (i >= 1 && j >= 0 && j <= v.n) {
+      if (lane == 0) {
+        const int q = c * NW + wv - 1;
+        tp0[c] = sm.xr[q][0]; tp1[c] = sm.xr[q][1]; tp2[c] = sm.xr[q][2];
+      }
       Face f;
-      face_flux(sm.tr[3][i - 1], sm.tr[4][i - 1], sm.tr[5][i - 1], sm.tr[0][i], sm.tr[1][i],
-                sm.tr[2][i], sm.wn[i + 2], cs.g, cs.dry_eps, f);
+      face_flux(tp0[c], tp1[c], tp2[c], tl0[c], tl1[c], tl2[c], sm.wn[i + 2], cs.g, cs.dry_eps, f);
       sm.u.fl[0][i] = f.Fc1; sm.u.fl[1][i] = f.Fc2; sm.u.fl[2][i] = f.Gc; sm.u.fl[3][i] = f.je;
       sm.u.fl[4][i] = f.jm; sm.u.fl[5][i] = f.jb; sm.u.fl[6][i] = f.B1; sm.u.fl[7][i] = f.B2;
       fspeed = fmax(fspeed, f.speed);
@@ -287,7 +339,7 @@ __device__ __forceinline__ StageRes stage_tile(const Bufs& bf, const Consts& cs,
       }
     }
   }
-  __syncthreads();
+  lds_sync();
   // 4. owned cells: residual split, stage combination
   double maxJ = 0.0;
 #pragma unroll
@@ -329,25 +381,161 @@ __device__ __forceinline__ StageRes stage_tile(const Bufs& bf, const Consts& cs,
       if (!(Jnext > 0.0)) st |= SB_MESH;
     }
   }
-  if ((t & 63) == 0) {
-    atomicAdd(&sm.cnt[0], n0);
-    atomicAdd(&sm.cnt[1], n1);
-    atomicAdd(&sm.cnt[2], n2);
-    if (nl) atomicAdd(&sm.cnt[3], nl);
-    if (nn) atomicAdd(&sm.cnt[4], nn);
+  // per-wave counts and status bits (wave-uniform), plain LDS stores
+  unsigned stw = 0u;
+#pragma unroll
+  for (int bit = 1; bit <= 8; bit <<= 1)
+    if (__ballot((st & bit) != 0)) stw |= (unsigned)bit;
+  if (lane == 0) {
+    sm.cntw[wv][0] = n0; sm.cntw[wv][1] = n1; sm.cntw[wv][2] = n2;
+    sm.cntw[wv][3] = nl; sm.cntw[wv][4] = nn; sm.cntw[wv][5] = stw;
   }
-  if (st) atomicOr(&sm.cnt[5], (unsigned)st);
   double rv[2] = {fspeed, maxJ};
   const int op[2] = {0, 0};
   block_reduce<B, 2>(rv, op, sm.red);
   StageRes res;
   res.alpha = rv[0];
   res.maxJ = rv[1];
-  res.ncls0 = sm.cnt[0]; res.ncls1 = sm.cnt[1]; res.ncls2 = sm.cnt[2];
-  res.nlim = sm.cnt[3]; res.nneg = sm.cnt[4];
-  res.status = (int)sm.cnt[5];
-  __syncthreads();
+  res.ncls0 = 0u; res.ncls1 = 0u; res.ncls2 = 0u; res.nlim = 0u; res.nneg = 0u;
+  unsigned sta = 0u;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    res.ncls0 += sm.cntw[w][0]; res.ncls1 += sm.cntw[w][1]; res.ncls2 += sm.cntw[w][2];
+    res.nlim += sm.cntw[w][3]; res.nneg += sm.cntw[w][4];
+    sta |= sm.cntw[w][5];
+  }
+  res.status = (int)sta;
+  lds_sync();
   return res;
+}
+
+// One stage over the tile of owned cells [c0, c0 + TB - 2) of one instance.
+template <int B, int CPT>
+__device__ __forceinline__ StageRes stage_tile(const Bufs& bf, const Consts& cs, const View& v,
+                                               const StageScal& sc, int64_t c0,
+                                               SmemStage<B, CPT>& sm, uint8_t* cls_inst) {
+  int st = 0;
+  stage_load<B, CPT>(bf, cs, v, sc, c0, sm, st);
+  lds_sync();
+  return stage_compute<B, CPT>(bf, cs, v, sc, c0, sm, cls_inst, st, (int)threadIdx.x);
+}
+
+// ----------------------------------------------------------------------------
+// Software-pipelined stage tiles (ghost-free tiles only): while a work-group
+// computes one tile, the raw rows of its next tile stream into LDS through the
+// direct-to-LDS loads, which hold no registers.
+// Raw rows of a tile at c0: x^n and w at nodes c0-3 .. c0+B+1 (B+5 values),
+// then q^n (stage 1) or P, D and q^n (stages 2, 3) of cells c0-3 .. c0+B.
+// ----------------------------------------------------------------------------
+// Raw rows live in an LDS object of their own: the compiler then knows that
+// the stencil reads of the current tile do not touch what the copies in flight
+// write, and does not wait for those copies.
+template <int B>
+struct RawRows {
+  static constexpr int RL = B + 8;  // row length (>= B + 5)
+  double r[11][RL];
+};
+
+typedef __attribute__((address_space(3))) void* lds_ptr;
+
+// Copy n doubles from global memory to LDS (both contiguous): the waves of the
+// work-group take 256-byte pieces in turn, one dword per lane.
+template <int B>
+__device__ __forceinline__ void dma_row(const double* src, double* dst, int n, int t) {
+  const int lane = t & 63, wv = t >> 6;
+  const int ndw = 2 * n;
+  const unsigned* s32 = reinterpret_cast<const unsigned*>(src);
+  for (int q = wv; q * 64 < ndw; q += B / 64) {
+    const int d = q * 64 + lane;
+    if (d < ndw)
+      __builtin_amdgcn_global_load_lds(s32 + d, (lds_ptr)(reinterpret_cast<char*>(dst) + q * 256),
+                                       4, 0, 0);
+  }
+}
+
+// Start the raw-row copies of the ghost-free tile at c0 for stage s.
+template <int B>
+__device__ __forceinline__ void issue_tile(const Bufs& bf, const View& v, int s, int64_t c0,
+                                           RawRows<B>& sp, int t) {
+  const int64_t k0 = c0 - 3;
+  dma_row<B>(v.x + k0, sp.r[0], B + 5, t);
+  dma_row<B>(bf.w + v.no + k0, sp.r[1], B + 5, t);
+  const int64_t g0 = v.co + k0;
+  const int64_t S = bf.S;
+  if (s == 1) {
+    dma_row<B>(bf.eta + g0, sp.r[2], B + 4, t);
+    dma_row<B>(bf.m + g0, sp.r[3], B + 4, t);
+    dma_row<B>(bf.b + g0, sp.r[4], B + 4, t);
+  } else {
+    const double* P = (s == 2) ? bf.P0 : bf.P1;
+    const double* D = (s == 2) ? bf.D0 : bf.D1;
+    dma_row<B>(P + g0, sp.r[2], B + 4, t);
+    dma_row<B>(P + S + g0, sp.r[3], B + 4, t);
+    dma_row<B>(P + 2 * S + g0, sp.r[4], B + 4, t);
+    dma_row<B>(D + g0, sp.r[5], B + 4, t);
+    dma_row<B>(D + S + g0, sp.r[6], B + 4, t);
+    dma_row<B>(D + 2 * S + g0, sp.r[7], B + 4, t);
+    dma_row<B>(bf.eta + g0, sp.r[8], B + 4, t);
+    dma_row<B>(bf.m + g0, sp.r[9], B + 4, t);
+    dma_row<B>(bf.b + g0, sp.r[10], B + 4, t);
+  }
+}
+
+// Everything a tile needs from the per-instance records, read through the
+// constant address space so that the loads are scalar (SGPR, the LGKM
+// counter): waiting for them never waits for vector-memory traffic in flight.
+// The fields read here (and the tile table) are not written while a stage
+// kernel runs; only the reduction slots and counters are, by atomics.
+struct TileInfo {
+  View v;
+  StageScal sc;
+  int64_t c0;
+  int inst;
+  int active;
+};
+
+template <class TT>
+__device__ __forceinline__ TileInfo tile_info(const Bufs& bf, const TT* tiles, int64_t k, int s) {
+  typedef const __attribute__((address_space(4))) TT* ctile;
+  typedef const __attribute__((address_space(4))) Inst* cinst;
+  typedef const __attribute__((address_space(4))) int64_t* ci64;
+  const ctile tp = (ctile)tiles + k;
+  const int inst = tp->inst;
+  const cinst I = (cinst)bf.inst + inst;
+  const ci64 off = (ci64)bf.cell_off;
+  TileInfo ti;
+  ti.inst = inst;
+  ti.c0 = tp->c0;
+  ti.active = I->active;
+  ti.v.co = off[inst];
+  ti.v.n = off[inst + 1] - ti.v.co;
+  ti.v.no = ti.v.co + inst;
+  const bool odd = (I->steps & 1) != 0;
+  ti.v.x = (odd ? bf.xb : bf.xa) + ti.v.no;
+  ti.v.xnew = (odd ? bf.xa : bf.xb) + ti.v.no;
+  const double dt = I->dt;
+  ti.sc.s = s;
+  ti.sc.dt = dt;
+  ti.sc.as = s == 1 ? 0.0 : (s == 2 ? 0.75 : 1.0 / 3.0);
+  ti.sc.bs = s == 1 ? 1.0 : (s == 2 ? 0.25 : 2.0 / 3.0);
+  const double bprev = s == 2 ? 1.0 : 0.25;
+  ti.sc.cprev = s == 1 ? 0.0 : bprev * dt * I->alpha[s - 2];
+  ti.sc.dx = I->dx[s - 1];
+  ti.sc.wsc = I->wscale;
+  return ti;
+}
+
+// Stencil slot i of a tile from its raw rows (same arithmetic as the direct loads).
+template <int B>
+__device__ __forceinline__ void slot_from_raw(const StageScal& sc, int i, const RawRows<B>& sp,
+                                              SmemStage<B, 1>& sm, int& st) {
+  const double(*r)[RawRows<B>::RL] = sp.r;
+  if (sc.s == 1)
+    put_slot(sc, i, 1.0, true, r[0][i], r[0][i + 1], r[1][i], r[1][i + 1], r[2][i], r[3][i],
+             r[4][i], 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, sm, st);
+  else
+    put_slot(sc, i, 1.0, true, r[0][i], r[0][i + 1], r[1][i], r[1][i + 1], r[2][i], r[3][i],
+             r[4][i], r[5][i], r[6][i], r[7][i], r[8][i], r[9][i], r[10][i], sm, st);
 }
 
 // Step epilogue over cells [c0, c0+B): q^{n+1}, x^{n+1}, and the reductions

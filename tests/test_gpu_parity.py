@@ -173,12 +173,17 @@ def test_batched_engines_bitwise_and_oracle(dev):
     p = _gp(bt)
     nsteps = 25
     outs = []
-    for engine, block, cpt in ((alew.ENGINE_PERSISTENT, 256, 1), (alew.ENGINE_STAGES, 128, 1),
-                               (alew.ENGINE_STAGES, 256, 1), (alew.ENGINE_STAGES, 512, 1),
-                               (alew.ENGINE_PERSISTENT, 128, 1), (alew.ENGINE_STAGES, 128, 2),
-                               (alew.ENGINE_STAGES, 256, 2)):
+    for engine, block, cpt, pf in ((alew.ENGINE_PERSISTENT, 256, 1, 0),
+                                     (alew.ENGINE_STAGES, 128, 1, 0),
+                                     (alew.ENGINE_STAGES, 256, 1, 0),
+                                     (alew.ENGINE_STAGES, 512, 1, 0),
+                                     (alew.ENGINE_PERSISTENT, 128, 1, 0),
+                                     (alew.ENGINE_STAGES, 128, 2, 0),
+                                     (alew.ENGINE_STAGES, 256, 2, 0),
+                                     (alew.ENGINE_STAGES, 256, 1, 1)):
         ctx = alew.Context(n, ninst)
-        ctx.set_launch(engine=engine, block=block, use_graph=1, cells_per_thread=cpt)
+        ctx.set_launch(engine=engine, block=block, use_graph=1, cells_per_thread=cpt,
+                       prefetch=pf)
         T = {k: _t(bt[k], dev) for k in ("h", "hu", "b", "x", "xi")}
         st = ctx.run(p, off, T["h"], T["hu"], T["b"], T["x"], T["xi"], max_steps=[nsteps] * ninst)
         torch.cuda.synchronize()
@@ -194,6 +199,40 @@ def test_batched_engines_bitwise_and_oracle(dev):
         g = dict(h=ref["h"][a:e], hu=ref["hu"][a:e], b=ref["b"][a:e], x=ref["x"][a + i:e + i + 1])
         _assert_parity(g, r)
         assert outs[0][1][i].steps == nsteps
+
+
+def test_prefetching_stage_kernel_many_tiles(dev):
+    """A batch with more ghost-free tiles than resident work-groups, so every
+    work-group of the prefetching kernel streams several tiles: bitwise equal
+    to the plain stage kernel, and sampled instances match the oracle."""
+    rng = np.random.default_rng(11)
+    ns = [int(v) for v in rng.integers(3000, 9000, 160)]
+    eps = rng.uniform(1e-5, 1e-2, len(ns))
+    insts = [W.perturbation_instance(n, float(e)) for n, e in zip(ns, eps)]
+    bt = W.pack(insts, bc="transmissive", t_end=0.2, cfl=0.6, weno_eps=1e-9, mesh="sine",
+                mesh_A=0.05, mesh_k=1.0, mesh_omega=math.pi)
+    off = bt["cell_off"]
+    n, ninst = int(off[-1]), len(off) - 1
+    p = _gp(bt)
+    nsteps = 6
+    outs = []
+    for pf in (0, 1):
+        ctx = alew.Context(n, ninst)
+        ctx.set_launch(engine=alew.ENGINE_STAGES, block=256, use_graph=1, prefetch=pf)
+        T = {k: _t(bt[k], dev) for k in ("h", "hu", "b", "x", "xi")}
+        st = ctx.run(p, off, T["h"], T["hu"], T["b"], T["x"], T["xi"], max_steps=[nsteps] * ninst)
+        torch.cuda.synchronize()
+        outs.append(({k: v.cpu().numpy() for k, v in T.items()}, st))
+    for k in ("h", "hu", "b", "x"):
+        assert np.array_equal(outs[0][0][k], outs[1][0][k]), k
+    assert [tuple(s.n_class) for s in outs[0][1]] == [tuple(s.n_class) for s in outs[1][1]]
+    ref = outs[1][0]
+    for i in (0, ninst // 2, ninst - 1):
+        a, e = int(off[i]), int(off[i + 1])
+        r = O.run(_op(bt), bt["h"][a:e], bt["hu"][a:e], bt["b"][a:e], bt["x"][a + i:e + i + 1],
+                  bt["xi"][a + i:e + i + 1], max_steps=nsteps)
+        g = dict(h=ref["h"][a:e], hu=ref["hu"][a:e], b=ref["b"][a:e], x=ref["x"][a + i:e + i + 1])
+        _assert_parity(g, r)
 
 
 def test_batched_to_t_end_matches_per_instance(dev):

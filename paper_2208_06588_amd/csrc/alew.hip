@@ -1019,7 +1019,7 @@ alew_status alew_adjoint(alew_ctx* c, const alew_params* p, int64_t ninst,
   if (S > c->max_cells) return fail(ALEW_E_ARG, "total cells exceed the context capacity");
   const int64_t K = ckpt_every > 0 ? ckpt_every : 16;
   const int64_t nck = (nsteps + K - 1) / K;
-  const int64_t NN = S + ninst, CS = S + 2 * ninst;
+  const int64_t NN = S + ninst;
   const int B = 256;
   alew_status ts = build_tiles(c, cell_off, ninst, B, B);
   if (ts != ALEW_OK) return ts;
@@ -1029,7 +1029,15 @@ alew_status alew_adjoint(alew_ctx* c, const alew_params* p, int64_t ninst,
   const size_t n_ckI = (size_t)nck * ninst * sizeof(Inst) / 8 + 1;
   const size_t per_step = 18 * (size_t)S + 8 * (size_t)NN + 8 * (size_t)ninst;
   const size_t n_seg = (size_t)(K + 1) * per_step;
-  const size_t n_adj = 6 * (size_t)S + 15 * (size_t)CS + 2 * (size_t)ninst + (size_t)ninst * ngauge;
+  // tiles of the fused reverse stage: 250 owned cells each (256 threads)
+  constexpr int BA = 256, TBA = BA - 6;
+  std::vector<AdjTile> atiles;
+  for (int64_t i = 0; i < ninst; ++i)
+    for (int64_t c0 = 0; c0 < cell_off[i + 1] - cell_off[i]; c0 += TBA)
+      atiles.push_back(AdjTile{(int32_t)i, 0, c0});
+  const size_t n_at = 2 * atiles.size();
+  const size_t n_adj = 9 * (size_t)S + 2 * (size_t)ninst + (size_t)ninst * ngauge +
+                       18 * (size_t)ninst + n_at + (size_t)c->n_tiles_plain + (size_t)ninst + 1;
   const size_t need = (n_state + n_ck + n_ckI + n_seg + n_adj) * 8;
   if (need > c->adj_ws_bytes) {
     if (c->adj_ws) (void)hipFree(c->adj_ws);
@@ -1045,9 +1053,13 @@ alew_status alew_adjoint(alew_ctx* c, const alew_params* p, int64_t ninst,
   Inst* ckI = (Inst*)wp; wp += n_ckI;
   double* seg = wp; wp += n_seg;
   double* lam = wp; wp += 3 * S;
+  double* lam2 = wp; wp += 3 * S;
   double* lbase = wp; wp += 3 * S;
-  double* Cb = wp; wp += 15 * CS;
+  double* gfold = wp; wp += 18 * ninst;
+  AdjTile* atiles_d = (AdjTile*)wp; wp += n_at;
   double* lalpha = wp; wp += ninst;
+  double* lpart = wp; wp += c->n_tiles_plain;
+  int64_t* tfirst_d = (int64_t*)wp; wp += ninst + 1;
   unsigned long long* akey = (unsigned long long*)wp; wp += ninst;
   int64_t* gcell = (int64_t*)wp; wp += ninst * ngauge;
   hipStream_t st = c->stream;
@@ -1066,7 +1078,7 @@ alew_status alew_adjoint(alew_ctx* c, const alew_params* p, int64_t ninst,
   HIPCHK(hipMemcpyAsync(st_b, b0, S * 8, hipMemcpyDeviceToDevice, st));
   Bufs bf = make_bufs(c, S, ninst, st_m, st_b, xi, nullptr, dts, nullptr, nsteps);
   const Consts cs = make_consts(p);
-  const dim3 gp((unsigned)c->n_tiles_plain), gs((unsigned)c->n_tiles_stage);
+  const dim3 gp((unsigned)c->n_tiles_plain);
   auto step_dump = [&](int64_t slot) {
     Dump d;
     double* base = seg + slot * per_step;
@@ -1112,9 +1124,21 @@ alew_status alew_adjoint(alew_ctx* c, const alew_params* p, int64_t ninst,
   hipLaunchKernelGGL(k_gauge_seed, dim3(gb), dim3(256), 0, st, ng, S, gcell, gauge_bar, lam);
   AdjBufs ab;
   ab.cell_off = c->cell_off_d; ab.S = S; ab.ninst = (int32_t)ninst; ab.pad = 0;
-  ab.lam = lam; ab.lbase = lbase; ab.C = Cb; ab.lalpha = lalpha; ab.akey = akey;
-  const AdjTile* tst = (const AdjTile*)c->tiles_stage_d;
+  ab.lam = lam; ab.lam_out = lam2; ab.lbase = lbase; ab.lalpha = lalpha; ab.akey = akey;
+  ab.lpart = lpart;
+  {
+    // first plain tile of each instance (plain tiles: B = 256 cells, n+1 nodes)
+    std::vector<int64_t> tf(ninst + 1, 0);
+    for (int64_t i = 0; i < ninst; ++i) tf[i + 1] = tf[i] + (cell_off[i + 1] - cell_off[i]) / 256 + 1;
+    if (tf[ninst] != c->n_tiles_plain) return fail(ALEW_E_ARG, "internal: plain tile count");
+    HIPCHK(hipMemcpyAsync(tfirst_d, tf.data(), tf.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
   const AdjTile* tpl = (const AdjTile*)c->tiles_plain_d;
+  HIPCHK(hipMemcpyAsync(atiles_d, atiles.data(), atiles.size() * sizeof(AdjTile),
+                        hipMemcpyHostToDevice, st));
+  const dim3 ga((unsigned)atiles.size());
+  const unsigned gfb = (unsigned)((ninst + 255) / 256);
   for (int64_t q = nck - 1; q >= 0; --q) {
     const int64_t k0 = q * K, k1 = std::min(nsteps, k0 + K);
     double* cq = ck + q * (3 * S + NN);
@@ -1139,14 +1163,16 @@ alew_status alew_adjoint(alew_ctx* c, const alew_params* p, int64_t ninst,
         ab.fsr = ab.fsl + NN;
         hipLaunchKernelGGL(k_adj_reset, dim3(1), dim3(1024), 0, st, ab);
         hipLaunchKernelGGL(k_adj_alpha<256>, gp, dim3(256), 0, st, ab, tpl, s3);
-        hipLaunchKernelGGL(k_adj_stage<256>, gs, dim3(256), 0, st, ab, cs, tst, s3);
-        hipLaunchKernelGGL(k_adj_gather<256>, gp, dim3(256), 0, st, ab, cs, tpl, s3);
+        hipLaunchKernelGGL(k_adj_lsum, dim3(gfb), dim3(256), 0, st, ab, tfirst_d);
+        hipLaunchKernelGGL(k_adj_fused<BA>, ga, dim3(BA), 0, st, ab, cs, atiles_d, s3, gfold);
+        hipLaunchKernelGGL(k_adj_fold, dim3(gfb), dim3(256), 0, st, ab, cs, gfold);
+        std::swap(ab.lam, ab.lam_out);
       }
     }
     HIPCHK(hipGetLastError());
   }
   const unsigned g1 = (unsigned)((S + 255) / 256);
-  hipLaunchKernelGGL(k_adj_out, dim3(g1), dim3(256), 0, st, S, lam, dh0, dhu0, db0);
+  hipLaunchKernelGGL(k_adj_out, dim3(g1), dim3(256), 0, st, S, ab.lam, dh0, dhu0, db0);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(st));
   return ALEW_OK;

@@ -13,15 +13,13 @@
 // cut-offs, the argmax.  The mesh and the step sizes do not depend on the
 // state.
 //
-// Work split per stage (all gather form, no floating-point atomics in the
-// per-cell part):
+// Work split per stage (gather form, no floating-point atomics):
 //   k_adj_alpha   lambda_alpha and the argmax face per instance;
-//   k_adj_stage   per reconstructed cell (ghosts included): face adjoints ->
-//                 limiter -> reconstruction, written as 5 stencil slots x
-//                 (eta, hu, b) contributions;
-//   k_adj_gather  per cell: sum of the contributions of the 5 cells whose
-//                 stencils contain it (ghost copies folded back), plus the
-//                 direct terms.
+//   k_adj_fused   per tile: forward reconstruction and limiter of its cells and
+//                 a two-cell halo, face adjoints, reverse of limiter and
+//                 reconstruction, stencil contributions summed in LDS, and
+//                 lambda^(s-1) of the owned cells;
+//   k_adj_fold    contributions to ghost cells onto their source cells.
 #pragma once
 
 #include "alew_kernels.h"
@@ -40,10 +38,12 @@ struct AdjBufs {
   const double* x;     // [S+ninst] x^n
   const double* w;     // [S+ninst] w^n
   const double* scal;  // [ninst][8] t, dt, alpha_1..3, dx_0..2 of the step
-  double* lam;         // [3][S] in: lambda^(s); out (gather): lambda^(s-1)
+  double* lam;         // [3][S] lambda^(s)
+  double* lam_out;     // [3][S] lambda^(s-1) (a different buffer: tiles read
+                       // lambda^(s) of their halo cells while others write)
   double* lbase;       // [3][S] adjoint of q^n accumulated over the stages
-  double* C;           // [15][S + 2 ninst] stencil contributions
   double* lalpha;      // [ninst]
+  double* lpart;       // [plain tiles] per-tile parts of lambda_alpha
   unsigned long long* akey;  // [ninst] argmax key 2*face + side
 };
 
@@ -427,7 +427,8 @@ struct AdjTile {
   int64_t c0;
 };
 
-// rho . D summed per instance, and the face/trace that attains alpha.
+// rho . D summed per plain tile (the per-instance sum is taken in a fixed
+// order by k_adj_lsum), and the face/trace that attains alpha.
 template <int B>
 __global__ __launch_bounds__(B) void k_adj_alpha(AdjBufs ab, const AdjTile* __restrict__ tiles,
                                                  int s) {
@@ -456,33 +457,59 @@ __global__ __launch_bounds__(B) void k_adj_alpha(AdjBufs ab, const AdjTile* __re
   double rv[1] = {acc};
   const int op[1] = {2};
   block_reduce<B, 1>(rv, op, red);
-  if (threadIdx.x == 0) atomicAdd(&ab.lalpha[i], rv[0]);
+  if (threadIdx.x == 0) ab.lpart[blockIdx.x] = rv[0];
+}
+
+// lambda_alpha of each instance: its plain tiles' parts in tile order (the
+// tiles of instance i are tfirst[i] .. tfirst[i+1]-1).
+__global__ void k_adj_lsum(AdjBufs ab, const int64_t* __restrict__ tfirst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ab.ninst) return;
+  double acc = 0.0;
+  for (int64_t k = tfirst[i]; k < tfirst[i + 1]; ++k) acc += ab.lpart[k];
+  ab.lalpha[i] = acc;
 }
 
 __global__ void k_adj_reset(AdjBufs ab) {
-  for (int i = threadIdx.x; i < ab.ninst; i += blockDim.x) {
-    ab.lalpha[i] = 0.0;
-    ab.akey[i] = ~0ull;
-  }
+  for (int i = threadIdx.x; i < ab.ninst; i += blockDim.x) ab.akey[i] = ~0ull;
 }
 
+// ----------------------------------------------------------------------------
+// Fused reverse stage.  A tile owns the TB = B - 6 cells [c0, c0 + TB) and
+// recomputes two cells of halo on each side, so that every stencil
+// contribution to an owned cell is formed inside the tile and summed in LDS:
+//   slots      cells c0-5 .. c0+B-2        (stencil data, rho)
+//   thread t   reconstructs cell j = c0-3+t (forward, limited traces),
+//              owns the face at node j,
+//              for 1 <= t <= B-2 takes the reverse of cell j (limiter and
+//              reconstruction), writing its 5 x 3 stencil contributions.
+// Contributions to ghost cells (only the first and the last tile of an
+// instance see them) go to a per-instance buffer and are folded onto their
+// source cells by k_adj_fold, so tiles never add into each other's cells.
+// ----------------------------------------------------------------------------
 template <int B>
-struct SmemAdj {
+struct SmemAdjF {
   double e[B + 4], m[B + 4], b[B + 4], J[B + 4];
   double rho[3][B + 4];
-  double tr[6][B];
-  double lf[6][B];  // face t: adjoints of cell t-1's right trace (0..2) and cell t's left (3..5)
+  union {
+    double tr[6][B];   // limited traces (faces)
+    double cl[15][B];  // stencil contributions of the reversed cells
+  } u;
+  double lf[6][B];
   double B1[B];
 };
 
+// gfold layout: [ninst][2 ends][3 ghost cells][3 components], ends: left
+// ghosts -3..-1, right ghosts n..n+2.
 template <int B>
-__global__ __launch_bounds__(B) void k_adj_stage(AdjBufs ab, Consts cs,
-                                                 const AdjTile* __restrict__ tiles, int s) {
-  __shared__ SmemAdj<B> sm;
+__global__ __launch_bounds__(B) void k_adj_fused(AdjBufs ab, Consts cs,
+                                                 const AdjTile* __restrict__ tiles, int s,
+                                                 double* __restrict__ gfold) {
+  constexpr int TB = B - 6;
+  __shared__ SmemAdjF<B> sm;
   const AdjTile tl = tiles[blockIdx.x];
   const int i = tl.inst;
   const int64_t co = ab.cell_off[i], n = ab.cell_off[i + 1] - co, no = co + i;
-  const int64_t CS = ab.S + 2 * (int64_t)ab.ninst;
   const int64_t c0 = tl.c0;
   const int t = threadIdx.x;
   const double* x = ab.x + no;
@@ -493,9 +520,9 @@ __global__ __launch_bounds__(B) void k_adj_stage(AdjBufs ab, Consts cs,
   const double lalpha = ab.lalpha[i];
   const unsigned long long akey = ab.akey[i];
   const double bs = stage_b(s);
-  // 1. stencil data and rho for cells c0-3 .. c0+B
+  // 1. stencil data and rho for cells c0-5 .. c0+B-2
   for (int q = t; q < B + 4; q += B) {
-    const int64_t k = c0 - 3 + q;
+    const int64_t k = c0 - 5 + q;
     double e = 0, m = 0, b = 0, J = 1, r0 = 0, r1 = 0, r2 = 0;
     if (k >= -3 && k < n + 3) {
       double ms;
@@ -518,8 +545,8 @@ __global__ __launch_bounds__(B) void k_adj_stage(AdjBufs ab, Consts cs,
     sm.rho[0][q] = r0; sm.rho[1][q] = r1; sm.rho[2][q] = r2;
   }
   __syncthreads();
-  // 2. forward reconstruction and limiter of cell j = c0 - 1 + t
-  const int64_t j = c0 - 1 + t;
+  // 2. forward reconstruction and limiter of cell j = c0 - 3 + t (stencil slots t .. t+4)
+  const int64_t j = c0 - 3 + t;
   const bool active = (j >= -1) && (j <= n);
   CellRecon o, ou;
   double h5[5], v5[5];
@@ -535,16 +562,16 @@ __global__ __launch_bounds__(B) void k_adj_stage(AdjBufs ab, Consts cs,
                sm.e[t + 2], o);
     ou = o;
     limit_cell(h5[2], sm.m[t + 2], cs.pp_eps, o);
-    sm.tr[0][t] = o.hL; sm.tr[1][t] = o.mL; sm.tr[2][t] = o.bL;
-    sm.tr[3][t] = o.hR; sm.tr[4][t] = o.mR; sm.tr[5][t] = o.bR;
+    sm.u.tr[0][t] = o.hL; sm.u.tr[1][t] = o.mL; sm.u.tr[2][t] = o.bL;
+    sm.u.tr[3][t] = o.hR; sm.u.tr[4][t] = o.mR; sm.u.tr[5][t] = o.bR;
   }
   __syncthreads();
-  // 3. face at node j between cells j-1 (LDS index t+1) and j (t+2)
+  // 3. face at node j between cells j-1 (slot t+1) and j (slot t+2)
   if (t >= 1 && j >= 0 && j <= n) {
     const double rl[3] = {sm.rho[0][t + 1], sm.rho[1][t + 1], sm.rho[2][t + 1]};
     const double rr[3] = {sm.rho[0][t + 2], sm.rho[1][t + 2], sm.rho[2][t + 2]};
-    const double hl = sm.tr[3][t - 1], ml = sm.tr[4][t - 1], bl = sm.tr[5][t - 1];
-    const double hr = sm.tr[0][t], mr = sm.tr[1][t], br = sm.tr[2][t];
+    const double hl = sm.u.tr[3][t - 1], ml = sm.u.tr[4][t - 1], bl = sm.u.tr[5][t - 1];
+    const double hr = sm.u.tr[0][t], mr = sm.u.tr[1][t], br = sm.u.tr[2][t];
     TraceAdj Ll, Lr;
     face_vjp(hl, ml, bl, hr, mr, br, w[j], alpha, cs.g, cs.dry_eps, rl, rr, sm.e[t + 1],
              sm.e[t + 2], Ll, Lr);
@@ -556,104 +583,112 @@ __global__ __launch_bounds__(B) void k_adj_stage(AdjBufs ab, Consts cs,
     sm.lf[3][t] = Lr.h; sm.lf[4][t] = Lr.m; sm.lf[5][t] = Lr.b;
     sm.B1[t] = 0.5 * (bl + br);
   }
-  __syncthreads();
-  // 4. cells written here: owned cells and the ghost cells -1, n
-  const bool owned = (t >= 1) && (t <= B - 2) && (j >= 0) && (j < n);
-  const bool ghost_out = active && (j == -1 || j == n);
-  if (!(owned || ghost_out)) return;
-  TraceAdj LL{0, 0, 0}, LR{0, 0, 0};
-  if (j >= 0) { LL.h = sm.lf[3][t]; LL.m = sm.lf[4][t]; LL.b = sm.lf[5][t]; }
-  if (j < n) { LR.h = sm.lf[0][t + 1]; LR.m = sm.lf[1][t + 1]; LR.b = sm.lf[2][t + 1]; }
-  double lrint = 0.0, letabar = 0.0;
-  if (j >= 0 && j < n) {
-    // S_j = g/2 dB2 - g etabar dB1 - g rint (dB2 part is in the face adjoints)
-    const double rm = sm.rho[1][t + 2];
-    lrint = -cs.g * rm;
-    letabar += -cs.g * rm * (sm.B1[t + 1] - sm.B1[t]);
-  }
-  double lhbar = 0.0, lmbar = 0.0;
-  limit_vjp(h5[2], sm.m[t + 2], cs.pp_eps, ou, LL, LR, lhbar, lmbar);
-  ReconAdjOut ra;
-  recon_cell_vjp(v5, h5, &sm.m[t], &sm.b[t], &sm.J[t], Dx, cs.weno_eps, sm.e[t + 2], LL, LR, lrint,
-                 ra);
-  // to (eta, hu, b): h = eta - b; indicator variable eta (or h)
-  const bool vh = (cs.flags & F_BETA_FROM_H) != 0;
-  const int64_t ci = co + 2 * (int64_t)i + (j + 1);
+  __syncthreads();  // the traces are dead from here on: their LDS takes the contributions
+  // 4. reverse of cell j for 1 <= t <= B-2; contributions to stencil slots t .. t+4
+  double cv[15];
 #pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    double lh = ra.lh[k] + (vh ? ra.lv[k] : 0.0);
-    double le = lh + (vh ? 0.0 : ra.lv[k]);
-    double lb = ra.lb[k] - lh;
-    double lm = ra.lm[k];
-    if (k == 2) {
-      le += lhbar + letabar + ra.letabar;
-      lb -= lhbar;
-      lm += lmbar;
+  for (int k = 0; k < 15; ++k) cv[k] = 0.0;
+  if (t >= 1 && t <= B - 2 && active) {
+    TraceAdj LL{0, 0, 0}, LR{0, 0, 0};
+    if (j >= 0) { LL.h = sm.lf[3][t]; LL.m = sm.lf[4][t]; LL.b = sm.lf[5][t]; }
+    if (j < n) { LR.h = sm.lf[0][t + 1]; LR.m = sm.lf[1][t + 1]; LR.b = sm.lf[2][t + 1]; }
+    double lrint = 0.0, letabar = 0.0;
+    if (j >= 0 && j < n) {
+      const double rm = sm.rho[1][t + 2];
+      lrint = -cs.g * rm;
+      letabar += -cs.g * rm * (sm.B1[t + 1] - sm.B1[t]);
     }
-    ab.C[(int64_t)(3 * k + 0) * CS + ci] = le;
-    ab.C[(int64_t)(3 * k + 1) * CS + ci] = lm;
-    ab.C[(int64_t)(3 * k + 2) * CS + ci] = lb;
-  }
-}
-
-// lambda^(s-1) = b_s J^(s-1) mu + sum of stencil contributions; the base-state
-// adjoint a_s J^n mu is accumulated (stage 3 sets it, stage 1 adds it in).
-template <int B>
-__global__ __launch_bounds__(B) void k_adj_gather(AdjBufs ab, Consts cs,
-                                                  const AdjTile* __restrict__ tiles, int s) {
-  const AdjTile tl = tiles[blockIdx.x];
-  const int i = tl.inst;
-  const int64_t co = ab.cell_off[i], n = ab.cell_off[i + 1] - co, no = co + i;
-  const int64_t CS = ab.S + 2 * (int64_t)ab.ninst;
-  const int64_t k = tl.c0 + threadIdx.x;
-  if (k >= n) return;
-  const double dt = ab.scal[(int64_t)i * 8 + 1];
-  double Jn, Jin, Jout;
-  stage_widths(ab.x + no, ab.w + no, k, dt, s, Jn, Jin, Jout);
-  const int64_t g = co + k;
-  const int64_t cbase = co + 2 * (int64_t)i + 1;  // C index of cell 0
-  double acc[3];
-  double mu[3];
+    double lhbar = 0.0, lmbar = 0.0;
+    limit_vjp(h5[2], sm.m[t + 2], cs.pp_eps, ou, LL, LR, lhbar, lmbar);
+    ReconAdjOut ra;
+    recon_cell_vjp(v5, h5, &sm.m[t], &sm.b[t], &sm.J[t], Dx, cs.weno_eps, sm.e[t + 2], LL, LR,
+                   lrint, ra);
+    const bool vh = (cs.flags & F_BETA_FROM_H) != 0;
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    mu[c] = ab.lam[c * ab.S + g] / Jout;
-    acc[c] = stage_b(s) * Jin * mu[c];
+    for (int k = 0; k < 5; ++k) {
+      double lh = ra.lh[k] + (vh ? ra.lv[k] : 0.0);
+      double le = lh + (vh ? 0.0 : ra.lv[k]);
+      double lb = ra.lb[k] - lh;
+      double lm = ra.lm[k];
+      if (k == 2) {
+        le += lhbar + letabar + ra.letabar;
+        lb -= lhbar;
+        lm += lmbar;
+      }
+      cv[3 * k + 0] = le; cv[3 * k + 1] = lm; cv[3 * k + 2] = lb;
+    }
   }
 #pragma unroll
-  for (int o = 0; o < 5; ++o) {
-    const int64_t jj = k + 2 - o;
-    if (jj < -1 || jj > n) continue;
+  for (int k = 0; k < 15; ++k) sm.u.cl[k][t] = cv[k];
+  __syncthreads();
+  // 5. owned cell k = c0 + t: slot i = t + 5 collects offset o from the cell of thread i - o
+  if (t < TB && c0 + t < n) {
+    const int64_t k = c0 + t;
+    const int si = t + 5;
+    double Jn, Jin, Jout;
+    stage_widths(x, w, k, dt, s, Jn, Jin, Jout);
+    const int64_t g = co + k;
+    double acc[3], mu[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) acc[c] += ab.C[(int64_t)(3 * o + c) * CS + cbase + jj];
-  }
-  // ghost copies of this cell in the stencils of the boundary cells
-  if (k < 3 || k >= n - 3) {
-    const int64_t js[6] = {-1, 0, 1, n - 2, n - 1, n};
-    for (int a = 0; a < 6; ++a) {
-      const int64_t jj = js[a];
-      for (int o = 0; o < 5; ++o) {
-        const int64_t gk = jj - 2 + o;
-        if (gk >= 0 && gk < n) continue;
-        double ms;
-        if (ghost_src(cs.bc, n, gk, ms) != k) continue;
-        acc[0] += ab.C[(int64_t)(3 * o + 0) * CS + cbase + jj];
-        acc[1] += ms * ab.C[(int64_t)(3 * o + 1) * CS + cbase + jj];
-        acc[2] += ab.C[(int64_t)(3 * o + 2) * CS + cbase + jj];
+    for (int c = 0; c < 3; ++c) {
+      mu[c] = ab.lam[c * ab.S + g] / Jout;
+      acc[c] = bs * Jin * mu[c];
+    }
+    double* lo = ab.lam_out;
+#pragma unroll
+    for (int oo = 0; oo < 5; ++oo) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc[c] += sm.u.cl[3 * oo + c][si - oo];
+    }
+    const double as = stage_a(s);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double base = as * Jn * mu[c];
+      const double lb = s == 3 ? base : ab.lbase[c * ab.S + g] + base;
+      if (s == 1) {
+        lo[c * ab.S + g] = acc[c] + lb;
+      } else {
+        lo[c * ab.S + g] = acc[c];
+        ab.lbase[c * ab.S + g] = lb;
       }
     }
   }
-  const double as = stage_a(s);
+  // ghost cells: the first tile has the left ones (slots 2..4), the last tile
+  // the right ones (slots n-c0+5 .. n-c0+7)
+  const int gi = t % 3, gc = (t / 3) % 3, gend = t / 9;  // t < 18: 2 ends x 3 cells x 3 comps
+  if (t < 18) {
+    const bool mine = gend == 0 ? (c0 == 0) : (c0 + TB >= n);
+    if (mine) {
+      const int64_t kg = gend == 0 ? (-3 + gi) : (n + gi);
+      const int si = (int)(kg - (c0 - 5));
+      double acc = 0.0;
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const double base = as * Jn * mu[c];
-    double lb = s == 3 ? base : ab.lbase[c * ab.S + g] + base;
-    if (s == 1) {
-      ab.lam[c * ab.S + g] = acc[c] + lb;
-    } else {
-      ab.lam[c * ab.S + g] = acc[c];
-      ab.lbase[c * ab.S + g] = lb;
+      for (int oo = 0; oo < 5; ++oo) {
+        const int tv = si - oo;
+        if (tv >= 0 && tv < B) acc += sm.u.cl[3 * oo + gc][tv];
+      }
+      gfold[(((int64_t)i * 2 + gend) * 3 + gi) * 3 + gc] = acc;
     }
   }
+}
+
+// Ghost-cell contributions onto their source cells (after k_adj_fused); one
+// thread per instance, fixed order.
+__global__ void k_adj_fold(AdjBufs ab, Consts cs, const double* __restrict__ gfold) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ab.ninst) return;
+  const int64_t co = ab.cell_off[i], n = ab.cell_off[i + 1] - co;
+  for (int gend = 0; gend < 2; ++gend)
+    for (int gi = 0; gi < 3; ++gi) {
+      const int64_t kg = gend == 0 ? (-3 + gi) : (n + gi);
+      double ms;
+      const int64_t src = ghost_src(cs.bc, n, kg, ms);
+      const double* v = gfold + (((int64_t)i * 2 + gend) * 3 + gi) * 3;
+      const int64_t g = co + src;
+      ab.lam_out[g] += v[0];
+      ab.lam_out[ab.S + g] += ms * v[1];
+      ab.lam_out[2 * ab.S + g] += v[2];
+    }
 }
 
 }  // namespace alew_dev

@@ -55,12 +55,18 @@ def _params(bc, cfl=0.6):
 # The wet/dry case divides by trace depths of order 1e-3 (u = hu/h and its
 # derivatives -u/h, 1/h), which multiplies the round-off difference between the
 # two evaluation orders; it gets a 10x looser bound.
-@pytest.mark.parametrize("kind,ckpt,tol", [("smooth", 3, 1e-11), ("step", 2, 1e-11),
-                                           ("wetdry", 16, 1e-10)])
-def test_adjoint_matches_oracle(dev, kind, ckpt, tol):
-    n, nsteps, ng = 64, 7, 6
+# The 560-cell cases span three tiles of the reverse-stage kernel (250 owned
+# cells each), with gauges dense enough that the adjoint is nonzero across the
+# tile seams.
+# (The wet/dry case on 560 cells runs at CFL 0.08, the positivity bound of the
+# scheme; at 0.3 its forward run reaches negative depths.)
+@pytest.mark.parametrize("kind,ckpt,tol,n,nsteps,ng,cfl", [
+    ("smooth", 3, 1e-11, 64, 7, 6, 0.3), ("step", 2, 1e-11, 64, 7, 6, 0.3),
+    ("wetdry", 16, 1e-10, 64, 7, 6, 0.3), ("smooth", 3, 1e-11, 560, 8, 40, 0.3),
+    ("step", 4, 1e-11, 560, 8, 40, 0.3), ("wetdry", 5, 1e-10, 560, 8, 40, 0.08)])
+def test_adjoint_matches_oracle(dev, kind, ckpt, tol, n, nsteps, ng, cfl):
     xi, h, hu, b, bc = _case(kind, n)
-    gp, op = _params(bc, cfl=0.3)
+    gp, op = _params(bc, cfl=cfl)
     # step sizes: those the CFL rule picks in the oracle's own run
     r = O.run(op, h, hu, b, xi, xi, max_steps=1)
     dts = np.full(nsteps, r["stats"].dt_max)
@@ -183,6 +189,49 @@ def test_batched_adjoint_equals_single_instances(dev):
         for k in range(3):
             scale = float(o3[k].abs().max()) or 1.0
             assert float((o3[k] - g3[k][a:e]).abs().max()) <= 1e-13 * scale
+
+
+def test_adjoint_many_tiles_deterministic(dev):
+    """A batch of many multi-tile instances (far more reverse-stage tiles than
+    run at once): two calls agree bit for bit, and every instance has the
+    gradient of its own one-instance call."""
+    ninst, n, nsteps, ng = 96, 3000, 6, 8
+    base = [_case("smooth", n), _case("step", n)]
+    insts = [(xi, h, hu, b) for (xi, h, hu, b, bc) in (base[k % 2] for k in range(ninst))]
+    gp, _ = _params("transmissive")
+    bt = W.pack(insts)
+    off = bt["cell_off"]
+    S = int(off[-1])
+    rng = np.random.default_rng(21)
+    gx = np.concatenate([np.sort(rng.uniform(0.02, 0.98, ng)) for _ in range(ninst)])
+    gb = rng.normal(size=ninst * ng)
+    dts = np.full(ninst * nsteps, 2e-5)  # CFL about 0.2 on 3000 cells
+    T = {k: _t(v, dev) for k, v in dict(h=bt["h"], hu=bt["hu"], b=bt["b"], x=bt["x"], xi=bt["xi"],
+                                         dts=dts, gx=gx, gb=gb).items()}
+    ctx = alew.Context(S, ninst)
+    runs = []
+    for _ in range(2):
+        gh = torch.zeros(ninst * ng, dtype=torch.float64, device=dev)
+        g3 = [torch.zeros(S, dtype=torch.float64, device=dev) for _ in range(3)]
+        ctx.adjoint(gp, off, T["h"], T["hu"], T["b"], T["x"], T["xi"], nsteps, T["dts"], ng,
+                    T["gx"], gh, T["gb"], *g3, ckpt_every=4)
+        torch.cuda.synchronize()
+        runs.append([g.cpu().numpy() for g in g3])
+    for k in range(3):
+        assert np.array_equal(runs[0][k], runs[1][k]), k
+    c1 = alew.Context(n, 1)
+    for i in range(ninst):
+        a, e = int(off[i]), int(off[i + 1])
+        gh1 = torch.zeros(ng, dtype=torch.float64, device=dev)
+        o3 = [torch.zeros(n, dtype=torch.float64, device=dev) for _ in range(3)]
+        c1.adjoint(gp, [0, n], T["h"][a:e], T["hu"][a:e], T["b"][a:e], T["x"][a + i:e + i + 1],
+                   T["xi"][a + i:e + i + 1], nsteps, T["dts"][i * nsteps:(i + 1) * nsteps], ng,
+                   T["gx"][i * ng:(i + 1) * ng], gh1, T["gb"][i * ng:(i + 1) * ng], *o3,
+                   ckpt_every=4)
+        for k in range(3):
+            o = o3[k].cpu().numpy()
+            scale = max(float(np.abs(o).max()), 1e-300)
+            assert np.abs(o - runs[0][k][a:e]).max() <= 1e-13 * scale, (i, k)
 
 
 def test_autograd_function_gradients(dev):

@@ -1093,9 +1093,12 @@ alew_status alew_adjoint(alew_ctx* c, const alew_params* p, int64_t ninst,
   auto xbuf_of = [&](int64_t k) { return (k & 1) ? c->xb : c->xa; };
   hipLaunchKernelGGL(k_prep<256>, gp, dim3(256), 0, st, bf, cs, c->tiles_plain_d, h0, nullptr);
   hipLaunchKernelGGL(k_boundary, dim3(1), dim3(1024), 0, st, bf, cs, 1, c->nactive_d);
-  // forward with checkpoints
+  // forward with checkpoints; when a gradient follows, the last segment keeps
+  // its records right away (the reverse sweep starts there)
+  const int64_t qlast = nck - 1, klast = qlast * K;
+  const bool keep_last = gauge_bar != nullptr;
   for (int64_t k = 0; k < nsteps; ++k) {
-    if (k % K == 0) {
+    if (k % K == 0 && !(keep_last && k / K == qlast)) {
       const int64_t q = k / K;
       double* cq = ck + q * (3 * S + NN);
       HIPCHK(hipMemcpyAsync(cq, c->eta, S * 8, hipMemcpyDeviceToDevice, st));
@@ -1104,7 +1107,15 @@ alew_status alew_adjoint(alew_ctx* c, const alew_params* p, int64_t ninst,
       HIPCHK(hipMemcpyAsync(cq + 3 * S, xbuf_of(k), NN * 8, hipMemcpyDeviceToDevice, st));
       HIPCHK(hipMemcpyAsync(ckI + q * ninst, c->inst, ninst * sizeof(Inst), hipMemcpyDeviceToDevice, st));
     }
-    launch_step_seq<256, 1>(c, bf, cs, st);
+    if (keep_last && k >= klast) {
+      if (k == klast)
+        hipLaunchKernelGGL(k_seed_scal, dim3(1), dim3(1024), 0, st, bf, step_dump(0).scal);
+      Bufs bd = bf;
+      bd.dump = step_dump(k - klast);
+      launch_step_seq<256, 1>(c, bd, cs, st);
+    } else {
+      launch_step_seq<256, 1>(c, bf, cs, st);
+    }
   }
   HIPCHK(hipGetLastError());
   const int64_t ng = ninst * ngauge;
@@ -1141,17 +1152,19 @@ alew_status alew_adjoint(alew_ctx* c, const alew_params* p, int64_t ninst,
   const unsigned gfb = (unsigned)((ninst + 255) / 256);
   for (int64_t q = nck - 1; q >= 0; --q) {
     const int64_t k0 = q * K, k1 = std::min(nsteps, k0 + K);
-    double* cq = ck + q * (3 * S + NN);
-    HIPCHK(hipMemcpyAsync(c->eta, cq, S * 8, hipMemcpyDeviceToDevice, st));
-    HIPCHK(hipMemcpyAsync(st_m, cq + S, S * 8, hipMemcpyDeviceToDevice, st));
-    HIPCHK(hipMemcpyAsync(st_b, cq + 2 * S, S * 8, hipMemcpyDeviceToDevice, st));
-    HIPCHK(hipMemcpyAsync(xbuf_of(k0), cq + 3 * S, NN * 8, hipMemcpyDeviceToDevice, st));
-    HIPCHK(hipMemcpyAsync(c->inst, ckI + q * ninst, ninst * sizeof(Inst), hipMemcpyDeviceToDevice, st));
-    hipLaunchKernelGGL(k_seed_scal, dim3(1), dim3(1024), 0, st, bf, step_dump(0).scal);
-    for (int64_t k = k0; k < k1; ++k) {
-      Bufs bd = bf;
-      bd.dump = step_dump(k - k0);
-      launch_step_seq<256, 1>(c, bd, cs, st);
+    if (q != qlast) {  // recompute the segment from its checkpoint, keeping records
+      double* cq = ck + q * (3 * S + NN);
+      HIPCHK(hipMemcpyAsync(c->eta, cq, S * 8, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(st_m, cq + S, S * 8, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(st_b, cq + 2 * S, S * 8, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(xbuf_of(k0), cq + 3 * S, NN * 8, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(c->inst, ckI + q * ninst, ninst * sizeof(Inst), hipMemcpyDeviceToDevice, st));
+      hipLaunchKernelGGL(k_seed_scal, dim3(1), dim3(1024), 0, st, bf, step_dump(0).scal);
+      for (int64_t k = k0; k < k1; ++k) {
+        Bufs bd = bf;
+        bd.dump = step_dump(k - k0);
+        launch_step_seq<256, 1>(c, bd, cs, st);
+      }
     }
     for (int64_t k = k1 - 1; k >= k0; --k) {
       const Dump d = step_dump(k - k0);
@@ -1163,7 +1176,7 @@ alew_status alew_adjoint(alew_ctx* c, const alew_params* p, int64_t ninst,
         ab.fsr = ab.fsl + NN;
         hipLaunchKernelGGL(k_adj_reset, dim3(1), dim3(1024), 0, st, ab);
         hipLaunchKernelGGL(k_adj_alpha<256>, gp, dim3(256), 0, st, ab, tpl, s3);
-        hipLaunchKernelGGL(k_adj_lsum, dim3(gfb), dim3(256), 0, st, ab, tfirst_d);
+        hipLaunchKernelGGL(k_adj_lsum, dim3((unsigned)((ninst + 3) / 4)), dim3(256), 0, st, ab, tfirst_d);
         hipLaunchKernelGGL(k_adj_fused<BA>, ga, dim3(BA), 0, st, ab, cs, atiles_d, s3, gfold);
         hipLaunchKernelGGL(k_adj_fold, dim3(gfb), dim3(256), 0, st, ab, cs, gfold);
         std::swap(ab.lam, ab.lam_out);

@@ -460,14 +460,18 @@ __global__ __launch_bounds__(B) void k_adj_alpha(AdjBufs ab, const AdjTile* __re
   if (threadIdx.x == 0) ab.lpart[blockIdx.x] = rv[0];
 }
 
-// lambda_alpha of each instance: its plain tiles' parts in tile order (the
-// tiles of instance i are tfirst[i] .. tfirst[i+1]-1).
-__global__ void k_adj_lsum(AdjBufs ab, const int64_t* __restrict__ tfirst) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// lambda_alpha of each instance from its plain tiles' parts (the tiles of
+// instance i are tfirst[i] .. tfirst[i+1]-1): one wave per instance, lane l
+// sums the parts l, l+64, ... and the lanes are combined by a fixed butterfly,
+// so the result does not depend on scheduling.
+__global__ __launch_bounds__(256) void k_adj_lsum(AdjBufs ab, const int64_t* __restrict__ tfirst) {
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (i >= ab.ninst) return;
   double acc = 0.0;
-  for (int64_t k = tfirst[i]; k < tfirst[i + 1]; ++k) acc += ab.lpart[k];
-  ab.lalpha[i] = acc;
+  for (int64_t k = tfirst[i] + lane; k < tfirst[i + 1]; k += 64) acc += ab.lpart[k];
+  acc = wave_sum(acc);
+  if (lane == 0) ab.lalpha[i] = acc;
 }
 
 __global__ void k_adj_reset(AdjBufs ab) {

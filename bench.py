@@ -47,18 +47,109 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel):
-    """HBM bytes per launch measured with rocprofv3 counters for this source
-    (profiles/traffic.json), or None when the kernel changed since."""
+def load_counters(kernel):
+    """rocprofv3 counter results for this kernel and this library source
+    (profiles/counters.json; how each figure is derived from the counters is
+    stated in the profile summaries beside it), or None when the library
+    source changed since they were taken."""
     try:
-        with open(os.path.join(ROOT, "profiles", "traffic.json")) as f:
+        with open(os.path.join(ROOT, "profiles", "counters.json")) as f:
             d = json.load(f)
     except (OSError, ValueError):
         return None
     e = d.get(kernel)
     if not e or e.get("source_hash") != source_hash():
         return None
-    return e.get("bytes_per_cell_step")
+    return e
+
+
+def roofline(ctx, p, off, T, tnow, L, S, kern_ms, launches, steps):
+    """Roofline object of the dominant kernel.  For the stage-launch engine the
+    same number of steps runs once more with an event pair around every stage
+    launch (no graph); achieved = the method's bytes per cell and stage (256/3 B)
+    x cells of a launch / average stage-launch time.  Counter results (HBM
+    bytes, VALU instructions) come from profiles/counters.json when they were
+    taken on this source."""
+    from paper_2208_06588_amd import alew
+    import torch
+    per_stage = ALG_BYTES_PER_CELL_STEP / 3.0
+    if L.engine == alew.ENGINE_PERSISTENT:
+        kernel = f"k_persistent<{L.block}>"
+        ms_launch = kern_ms / max(1, launches)
+        achieved = ALG_BYTES_PER_CELL_STEP * S * steps / max(1, launches) / (ms_launch / 1e3) / 1e9
+        stage_launches, epi = None, None
+    else:
+        cpt = max(1, L.cells_per_thread)
+        kernel = (f"k_stage_pipe<{L.block}>" if (L.prefetch and cpt == 1)
+                  else f"k_stage<{L.block}, {cpt}>")
+        ctx.set_kernel_timing(True)
+        W = {k: v.clone() for k, v in T.items()}
+        ctx.run(p, off, W["h"], W["hu"], W["b"], W["x"], W["xi"], t0=tnow,
+                max_steps=[steps] * (len(off) - 1))
+        torch.cuda.synchronize()
+        ctx.set_kernel_timing(False)
+        sms, sn, scells = ctx.kernel_timing(0)
+        ems, en, _ = ctx.kernel_timing(1)
+        del W
+        ms_launch = sms / max(1, sn)
+        achieved = per_stage * scells / (sms / 1e3) / 1e9
+        stage_launches = sn
+        epi = dict(kernel=f"k_final<{L.block}>", launches=en, launch_ms=round(ems / max(1, en), 4))
+        log(f"kernel timing: {sn} stage launches, {ms_launch:.4f} ms each; "
+            f"{en} epilogues, {ems / max(1, en):.4f} ms each")
+    roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None, kernel=kernel,
+                launch_ms=round(ms_launch, 4), launches=stage_launches,
+                alg_bytes_per_cell_stage=round(per_stage, 3),
+                timing="HIP events on the library stream around each launch")
+    if epi is not None:
+        roof["step_epilogue"] = epi
+    c = load_counters(kernel)
+    if c is not None:
+        cells_per_launch = S
+        roof["traffic"] = round(c["hbm_bytes_per_cell_stage"] * cells_per_launch)
+        roof["traffic_note"] = ("FETCH_SIZE x %.2f + WRITE_SIZE x %.2f per launch (copy-kernel "
+                                "calibration), scaled to this batch" % (c["fetch_factor"],
+                                                                         c["write_factor"]))
+        # FP64 VALU against the chip: 256 CUs x 4 SIMDs x 2.4 GHz issue one wave64
+        # instruction per SIMD every 4 cycles; FP64 peak 78.6 TFLOP/s
+        waves = c["waves_per_cell_stage"] * cells_per_launch
+        issue_s = c["valu_per_wave"] * waves * 4 / (1024 * 2.4e9)
+        flops = c["fp64_flops_per_cell_stage"] * cells_per_launch
+        roof["valu"] = dict(valu_insts_per_wave=round(c["valu_per_wave"], 1),
+                            fp64_flops_per_cell_stage=round(c["fp64_flops_per_cell_stage"], 1),
+                            issue_utilisation=round(issue_s / (ms_launch / 1e3), 4),
+                            fp64_tflops=round(flops / (ms_launch / 1e3) / 1e12, 2),
+                            fp64_peak_tflops=78.6,
+                            fp64_frac=round(flops / (ms_launch / 1e3) / 78.6e12, 4))
+    return roof
+
+
+def bowl_leg(dev, n, steps, warmup):
+    """Single 2^24-cell wet/dry run (parabolic bowl, fluid-following mesh,
+    limiter active): forward throughput and the HBM fraction of the whole step."""
+    import torch
+    from paper_2208_06588_amd import alew, workloads as W
+    t0 = time.perf_counter()
+    wl = W.bowl_1d(n)
+    log(f"bowl workload: {n} cells ({time.perf_counter() - t0:.1f} s to build)")
+    p = alew.params(bc="transmissive", mesh="fluid", cfl=wl["cfl"], weno_eps=wl["weno_eps"])
+    T = {k: torch.tensor(wl[k], dtype=torch.float64, device=dev) for k in ("h", "hu", "b", "x", "xi")}
+    ctx = alew.Context(n, 1)
+    ctx.set_launch(engine=alew.ENGINE_STAGES, block=256, use_graph=1)
+    st = ctx.run(p, [0, n], T["h"], T["hu"], T["b"], T["x"], T["xi"], max_steps=[warmup])
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    st = ctx.run(p, [0, n], T["h"], T["hu"], T["b"], T["x"], T["xi"], t0=[st[0].t], max_steps=[steps])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - a
+    assert st[0].steps == steps and st[0].status == 0, "bowl run did not complete"
+    value = 3.0 * n * steps / wall
+    return dict(workload=f"parabolic bowl, {n} cells, transmissive, fluid-following mesh, CFL 0.08",
+                steps=steps, value=value, unit="cell-updates/s",
+                step_hbm_frac=round(ALG_BYTES_PER_CELL_STEP * n * steps / wall / 1e9 / HBM_PEAK_GBS, 4),
+                limited_cells_per_step=round(st[0].n_limited / steps, 1),
+                h_min=st[0].h_min)
 
 
 def cpu_baseline(bt, ninst_sample, steps):
@@ -162,6 +253,8 @@ def main():
     ap.add_argument("--adj-ninst", type=int, default=256)
     ap.add_argument("--adj-cells", type=int, default=65536)
     ap.add_argument("--adj-steps", type=int, default=200)
+    ap.add_argument("--no-bowl", action="store_true", help="skip the 2^24-cell wet/dry run")
+    ap.add_argument("--bowl-steps", type=int, default=20)
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="first copy a buffer of this many MiB (calibrates profiler byte counters)")
     args = ap.parse_args()
@@ -226,15 +319,8 @@ def main():
     log(f"timed {args.steps} steps: {wall * 1e3:.1f} ms wall, {kern_ms:.1f} ms in {launches} "
         f"compute launch(es); {value:.3e} cell-updates/s")
 
-    kernel = "k_persistent" if L.engine == alew.ENGINE_PERSISTENT else "step sequence"
-    per_launch_bytes = ALG_BYTES_PER_CELL_STEP * S * args.steps / max(1, launches)
-    achieved = per_launch_bytes / (kern_ms / 1e3 / max(1, launches)) / 1e9
-    traffic = load_traffic(kernel)
-    roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4),
-                traffic=None if traffic is None else traffic * S * args.steps / max(1, launches),
-                kernel=kernel, launch_ms=round(kern_ms / max(1, launches), 3),
-                alg_bytes_per_cell_step=ALG_BYTES_PER_CELL_STEP)
+    roof = roofline(ctx, p, off, T, tnow=[s.t for s in st], L=L, S=S, kern_ms=kern_ms,
+                    launches=launches, steps=args.steps)
 
     out = {
         "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1,
@@ -279,6 +365,10 @@ def main():
                                       per_instance_s=round(per_inst, 4),
                                       speedup=round(per_inst / batched, 2))
         del Tb, Tp, ctx1
+
+    if not args.no_bowl:
+        out["bowl"] = bowl_leg(dev, 1 << 24, args.bowl_steps, 2)
+        log(f"bowl: {out['bowl']}")
 
     if not args.no_adjoint:
         del ctx, T

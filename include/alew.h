@@ -186,6 +186,22 @@ alew_status alew_adjoint(alew_ctx* ctx, const alew_params* p, int64_t ninst,
  * ms and launches are host pointers. */
 alew_status alew_last_timing(const alew_ctx* ctx, double* ms, int64_t* launches);
 
+/* Per-kernel timing of the stage-launch engine.  With on != 0, later
+ * alew_step/alew_run calls launch the step sequence without a graph and record
+ * a HIP event pair on the context's stream around every stage launch (all
+ * stage kernels of one RK stage: the tile kernel, or the end-tile and
+ * prefetching kernels) and every step-epilogue launch (new state, nodes and
+ * step-size reductions).  It adds an event pair per launch and is off by
+ * default. */
+alew_status alew_set_kernel_timing(alew_ctx* ctx, int on);
+
+/* Totals of the last call with kernel timing on.  which: 0 = stage launches,
+ * 1 = step epilogues.  ms: summed device time; launches: number of launches;
+ * cells: summed batch cells over those launches (every launch covers the whole
+ * batch; tiles of instances already finished return at once).  Host pointers. */
+alew_status alew_kernel_timing(const alew_ctx* ctx, int which, double* ms, int64_t* launches,
+                               double* cells);
+
 /* Message for the calling thread's last non-OK status ("" if none). */
 const char* alew_last_error(void);
 

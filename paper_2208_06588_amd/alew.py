@@ -81,6 +81,11 @@ def lib():
                                    vp, vp, C.c_double, i64, vp, i64, i64, vp, vp, vp, vp, vp, vp]
         L.alew_last_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.alew_last_timing.restype = C.c_int
+        L.alew_set_kernel_timing.argtypes = [vp, C.c_int]
+        L.alew_set_kernel_timing.restype = C.c_int
+        L.alew_kernel_timing.argtypes = [vp, C.c_int, C.POINTER(C.c_double),
+                                         C.POINTER(C.c_int64), C.POINTER(C.c_double)]
+        L.alew_kernel_timing.restype = C.c_int
         L.alew_last_error.restype = C.c_char_p
         L.alew_version.restype = C.c_char_p
         for f in ("alew_create", "alew_set_stream", "alew_set_launch", "alew_get_launch",
@@ -159,6 +164,18 @@ class Context:
         ms, n = C.c_double(), C.c_int64()
         _check(lib().alew_last_timing(self._h, C.byref(ms), C.byref(n)))
         return ms.value, n.value
+
+    def set_kernel_timing(self, on=True):
+        """Event pairs around every stage launch and step epilogue of later
+        runs (the step sequence then runs without a graph)."""
+        _check(lib().alew_set_kernel_timing(self._h, 1 if on else 0))
+
+    def kernel_timing(self, which=0):
+        """(milliseconds, launches, cells) summed over the stage launches
+        (which=0) or step epilogues (which=1) of the last timed run."""
+        ms, n, cells = C.c_double(), C.c_int64(), C.c_double()
+        _check(lib().alew_kernel_timing(self._h, which, C.byref(ms), C.byref(n), C.byref(cells)))
+        return ms.value, n.value, cells.value
 
     def get_launch(self) -> Launch:
         l = Launch()

@@ -102,14 +102,17 @@ __global__ __launch_bounds__(B) void k_wfluid(Bufs bf, Consts cs, const Tile* __
 }
 
 // Per-instance results of one stage tile.
-__device__ __forceinline__ void publish_stage(Inst& I, int s, const StageRes& r) {
-  amax_pos(&I.r_alpha, r.alpha);
-  if (s < 3) amax_pos(&I.r_maxJs, r.maxJ);
-  atomicAdd(&I.n_class[0], (unsigned long long)r.ncls0);
-  atomicAdd(&I.n_class[1], (unsigned long long)r.ncls1);
-  atomicAdd(&I.n_class[2], (unsigned long long)r.ncls2);
-  atomicAdd(&I.n_limited, (unsigned long long)r.nlim);
-  atomicAdd(&I.n_negweight, (unsigned long long)r.nneg);
+__device__ __forceinline__ void publish_stage(Inst& I, int s, const StageRes& r,
+                                              unsigned long long seen_a,
+                                              unsigned long long seen_j) {
+  amax_seen(&I.r_alpha, dbits(r.alpha), seen_a);
+  if (s < 3) amax_seen(&I.r_maxJs, dbits(r.maxJ), seen_j);
+  const int q = blockIdx.x & (NSPREAD - 1);
+  if (r.ncls0) atomicAdd(&I.n_class[0][q], (unsigned long long)r.ncls0);
+  if (r.ncls1) atomicAdd(&I.n_class[1][q], (unsigned long long)r.ncls1);
+  if (r.ncls2) atomicAdd(&I.n_class[2][q], (unsigned long long)r.ncls2);
+  if (r.nlim) atomicAdd(&I.n_limited[q], (unsigned long long)r.nlim);
+  if (r.nneg) atomicAdd(&I.n_negweight[q], (unsigned long long)r.nneg);
   if (r.status) atomicOr(&I.status, r.status);
 }
 
@@ -123,8 +126,10 @@ __global__ __launch_bounds__(B) void k_stage(Bufs bf, Consts cs, const Tile* __r
   View v = make_view(bf, tl.inst, I);
   const StageScal sc = stage_scal(I, s);
   uint8_t* cl = bf.cls ? bf.cls + (int64_t)(s - 1) * bf.S + v.co : nullptr;
+  unsigned long long sa = 0ull, sj = 0ull;
+  if (threadIdx.x == 0) { sa = slot_read(&I.r_alpha); sj = slot_read(&I.r_maxJs); }
   StageRes r = stage_tile<B, CPT>(bf, cs, v, sc, tl.c0, sm, cl);
-  if (threadIdx.x == 0) publish_stage(I, s, r);
+  if (threadIdx.x == 0) publish_stage(I, s, r, sa, sj);
 }
 
 // Stage-launch engine, ghost-free tiles: work-group b takes the tiles b, b+G,
@@ -168,7 +173,7 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(3))) void k_s
     if (cur.active) {
       uint8_t* cl = bf.cls ? bf.cls + (int64_t)(s - 1) * bf.S + cur.v.co : nullptr;
       const StageRes r = stage_compute<B, 1>(bf, cs, cur.v, cur.sc, cur.c0, sm, cl, st, t);
-      if (t == 0) publish_stage(bf.inst[cur.inst], s, r);
+      if (t == 0) publish_stage(bf.inst[cur.inst], s, r, 0ull, 0ull);
     }
     cur = nxt;
     nxt = after;
@@ -182,12 +187,17 @@ __global__ __launch_bounds__(B) void k_final(Bufs bf, Consts cs, const Tile* __r
   Inst& I = bf.inst[tl.inst];
   if (!I.active) return;
   View v = make_view(bf, tl.inst, I);
+  unsigned long long seen[4] = {0ull, 0ull, 0ull, 0ull};
+  if (threadIdx.x == 0) {
+    seen[0] = slot_read(&I.r_speed); seen[1] = slot_read(&I.r_minJ);
+    seen[2] = slot_read(&I.r_maxJ); seen[3] = slot_read(&I.r_hmin);
+  }
   FinalRes r = final_tile<B>(bf, cs, v, I.dt, I.alpha[2], I.wscale, tl.c0, red);
   if (threadIdx.x == 0) {
-    amax_pos(&I.r_speed, r.speed);
-    amin_pos(&I.r_minJ, r.minJ);
-    amax_pos(&I.r_maxJ, r.maxJ);
-    atomicMin(&I.r_hmin, okey(r.hmin));
+    amax_seen(&I.r_speed, dbits(r.speed), seen[0]);
+    amin_seen(&I.r_minJ, dbits(r.minJ), seen[1]);
+    amax_seen(&I.r_maxJ, dbits(r.maxJ), seen[2]);
+    amin_seen(&I.r_hmin, okey(r.hmin), seen[3]);
     if (r.status) atomicOr(&I.status, r.status);
   }
 }
@@ -372,11 +382,11 @@ __global__ __launch_bounds__(B) void k_persistent(Bufs bf, Consts cs,
         __syncthreads();
       }
       if (threadIdx.x == 0) {
-        sI.n_class[0] += c_cls[0];
-        sI.n_class[1] += c_cls[1];
-        sI.n_class[2] += c_cls[2];
-        sI.n_limited += c_lim;
-        sI.n_negweight += c_neg;
+        sI.n_class[0][0] += c_cls[0];
+        sI.n_class[1][0] += c_cls[1];
+        sI.n_class[2][0] += c_cls[2];
+        sI.n_limited[0] += c_lim;
+        sI.n_negweight[0] += c_neg;
         sI.status |= st;
         sI.r_speed = dbits(fsp);
         sI.r_minJ = dbits(fminJ);
@@ -505,6 +515,13 @@ struct alew_ctx {
   int64_t n_tiles_stage = 0, n_tiles_plain = 0;
   alew_launch launch{0, 256, 0, 1, 1, 0};
   hipEvent_t ev0 = nullptr, ev1 = nullptr;  // around the compute launches of a call
+  // per-kernel timing (alew_set_kernel_timing): event pairs around launches
+  int ktime_on = 0;
+  bool ktime_rec = false;  // recording in the current call
+  std::vector<hipEvent_t> kt_ev;
+  std::vector<int> kt_kind;
+  std::vector<double> kt_cells;
+  size_t kt_used = 0;
   // adjoint workspace (allocated by the first alew_adjoint call, grown on demand)
   double* adj_ws = nullptr;
   size_t adj_ws_bytes = 0;
@@ -631,11 +648,35 @@ int pipe_grid(alew_ctx* c) {
   return (int)std::min<int64_t>(g, c->n_tiles_inner);
 }
 
+// Event pair around a launch for per-kernel timing (kind 0: stage, 1: epilogue).
+int kt_begin(alew_ctx* c, hipStream_t st, int kind, double cells) {
+  if (!c->ktime_rec) return -1;
+  const size_t k = c->kt_used;
+  if (2 * k + 2 > c->kt_ev.size()) {
+    for (int q = 0; q < 2; ++q) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreate(&e) != hipSuccess) return -1;
+      c->kt_ev.push_back(e);
+    }
+    c->kt_kind.push_back(0);
+    c->kt_cells.push_back(0.0);
+  }
+  c->kt_kind[k] = kind;
+  c->kt_cells[k] = cells;
+  (void)hipEventRecord(c->kt_ev[2 * k], st);
+  c->kt_used = k + 1;
+  return (int)k;
+}
+void kt_end(alew_ctx* c, hipStream_t st, int k) {
+  if (k >= 0) (void)hipEventRecord(c->kt_ev[2 * (size_t)k + 1], st);
+}
+
 template <int B, int CPT>
 void launch_step_seq(alew_ctx* c, const Bufs& bf, const Consts& cs, hipStream_t st) {
   const dim3 gs((unsigned)c->n_tiles_stage), gp((unsigned)c->n_tiles_plain);
   const bool pipe = CPT == 1 && c->launch.prefetch == 1 && c->n_tiles_inner > 0;
   for (int s = 1; s <= 3; ++s) {
+    const int kt = kt_begin(c, st, 0, (double)bf.S);
     if (pipe) {
       if (c->n_tiles_edge > 0)
         hipLaunchKernelGGL((k_stage<B, 1>), dim3((unsigned)c->n_tiles_edge), dim3(B), 0, st, bf,
@@ -645,9 +686,12 @@ void launch_step_seq(alew_ctx* c, const Bufs& bf, const Consts& cs, hipStream_t 
     } else {
       hipLaunchKernelGGL((k_stage<B, CPT>), gs, dim3(B), 0, st, bf, cs, c->tiles_stage_d, s);
     }
+    kt_end(c, st, kt);
     hipLaunchKernelGGL(k_after_stage, dim3(1), dim3(1024), 0, st, bf, s);
   }
+  const int kf = kt_begin(c, st, 1, (double)bf.S);
   hipLaunchKernelGGL(k_final<B>, gp, dim3(B), 0, st, bf, cs, c->tiles_plain_d);
+  kt_end(c, st, kf);
   if (cs.mesh == MESH_FLUID)
     hipLaunchKernelGGL(k_wfluid<B>, gp, dim3(B), 0, st, bf, cs, c->tiles_plain_d);
   hipLaunchKernelGGL(k_boundary, dim3(1), dim3(1024), 0, st, bf, cs, 0, c->nactive_d);
@@ -671,7 +715,9 @@ GraphKey make_key(const Bufs& bf, const Consts& cs, int B, int CPT, const alew_c
 
 template <int B, int CPT>
 alew_status run_stage_engine(alew_ctx* c, const Bufs& bf, const Consts& cs, int64_t max_iters) {
-  const bool use_graph = c->launch.use_graph != 0;
+  const bool use_graph = c->launch.use_graph != 0 && !c->ktime_on;
+  c->kt_used = 0;
+  c->ktime_rec = c->ktime_on != 0;
   const int check_every = 8;  // 2-step graphs between host checks
   if (use_graph) {
     GraphKey key = make_key(bf, cs, B, CPT, c);
@@ -705,6 +751,7 @@ alew_status run_stage_engine(alew_ctx* c, const Bufs& bf, const Consts& cs, int6
     HIPCHK(hipStreamSynchronize(c->stream));
     if (*c->nactive_h == 0) break;
   }
+  c->ktime_rec = false;
   HIPCHK(hipEventRecord(c->ev1, c->stream));
   HIPCHK(hipEventSynchronize(c->ev1));
   float ms = 0.f;
@@ -838,9 +885,11 @@ alew_status drive(alew_ctx* c, const alew_params* p, int64_t ninst, const int64_
       alew_stats& S_ = stats[i];
       std::memset(&S_, 0, sizeof(S_));
       S_.steps = I.steps;
-      for (int k = 0; k < 3; ++k) S_.n_class[k] = (int64_t)I.n_class[k];
-      S_.n_limited = (int64_t)I.n_limited;
-      S_.n_negweight = (int64_t)I.n_negweight;
+      for (int q = 0; q < NSPREAD; ++q) {
+        for (int k = 0; k < 3; ++k) S_.n_class[k] += (int64_t)I.n_class[k][q];
+        S_.n_limited += (int64_t)I.n_limited[q];
+        S_.n_negweight += (int64_t)I.n_negweight[q];
+      }
       S_.t = I.t;
       S_.dt_min = I.dt_min;
       S_.dt_max = I.dt_max;
@@ -879,6 +928,32 @@ alew_status alew_last_timing(const alew_ctx* c, double* ms, int64_t* launches) {
   *launches = c->last_launches;
   return ALEW_OK;
 }
+alew_status alew_set_kernel_timing(alew_ctx* c, int on) {
+  if (!c) return fail(ALEW_E_ARG, "ctx is NULL");
+  c->ktime_on = on != 0;
+  return ALEW_OK;
+}
+
+alew_status alew_kernel_timing(const alew_ctx* c, int which, double* ms, int64_t* launches,
+                               double* cells) {
+  if (!c || !ms || !launches || !cells) return fail(ALEW_E_ARG, "NULL argument");
+  if (which != 0 && which != 1) return fail(ALEW_E_ARG, "which must be 0 or 1");
+  double tot = 0.0, cel = 0.0;
+  int64_t n = 0;
+  for (size_t k = 0; k < c->kt_used; ++k) {
+    if (c->kt_kind[k] != which) continue;
+    float e = 0.f;
+    HIPCHK(hipEventElapsedTime(&e, c->kt_ev[2 * k], c->kt_ev[2 * k + 1]));
+    tot += e;
+    cel += c->kt_cells[k];
+    ++n;
+  }
+  *ms = tot;
+  *launches = n;
+  *cells = cel;
+  return ALEW_OK;
+}
+
 const char* alew_version(void) { return "alew 0.1 gfx950 fp64"; }
 
 alew_status alew_create(alew_ctx** out, int64_t max_cells, int64_t max_inst, void* hip_stream) {
@@ -929,6 +1004,7 @@ void alew_destroy(alew_ctx* c) {
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
+  for (hipEvent_t e : c->kt_ev) (void)hipEventDestroy(e);
   delete c;
 }
 

@@ -32,6 +32,8 @@ struct Consts {
 
 // Per-instance scalars.  Reduction slots hold IEEE bit patterns so that
 // integer atomics give order-independent max/min.
+enum { NSPREAD = 8 };
+
 struct Inst {
   double t, t0, t_end, dt;
   double alpha[3];  // LF speed of stages 1..3
@@ -45,7 +47,10 @@ struct Inst {
   unsigned long long r_speed, r_minJ, r_maxJ, r_W;  // for the next step size
   unsigned long long r_alpha, r_maxJs;              // stage slots
   unsigned long long r_hmin;                        // ordered key of min depth
-  unsigned long long n_class[3], n_limited, n_negweight;
+  // statistics counters, spread over NSPREAD slots (work-group index mod
+  // NSPREAD) so that the tiles of one large instance do not all add into one
+  // address; the host sums the slots
+  unsigned long long n_class[3][NSPREAD], n_limited[NSPREAD], n_negweight[NSPREAD];
 };
 
 // ----------------------------------------------------------------------------
@@ -71,6 +76,22 @@ __device__ __forceinline__ void amax_pos(unsigned long long* p, double v) {
 }
 __device__ __forceinline__ void amin_pos(unsigned long long* p, double v) {
   atomicMin(p, dbits(v));
+}
+// The slots only move one way (max up, min down): a tile whose value cannot
+// change what the slot held when the tile started skips the atomic.  After
+// the first tiles of a large instance almost all do, which keeps its tiles
+// from queueing on one address.  The slot is read at the start of the tile
+// (the load is long done by the end); a stale value only costs an atomic.
+__device__ __forceinline__ unsigned long long slot_read(unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void amax_seen(unsigned long long* p, unsigned long long k,
+                                          unsigned long long seen) {
+  if (k > seen) atomicMax(p, k);
+}
+__device__ __forceinline__ void amin_seen(unsigned long long* p, unsigned long long k,
+                                          unsigned long long seen) {
+  if (k < seen) atomicMin(p, k);
 }
 
 // Reciprocal: hardware estimate refined by two Newton steps (relative error of

@@ -30,7 +30,7 @@ using namespace alew_dev;
 // ============================================================================
 struct Tile {
   int32_t inst;
-  int32_t pad;
+  int32_t rec;  // index of the tile's result record (stage or plain table)
   int64_t c0;
 };
 
@@ -75,18 +75,13 @@ __global__ __launch_bounds__(B) void k_prep(Bufs bf, Consts cs, const Tile* __re
       sabs = fabs(wv);
     }
   }
-  double rv[7] = {speed, minJ, maxJ, hmin, me, mb, sabs};
-  const int op[7] = {0, 1, 0, 1, 2, 2, 0};
+  double rv[7] = {speed, minJ, maxJ, hmin, sabs, me, mb};
+  const int op[7] = {0, 1, 0, 1, 0, 2, 2};
   block_reduce<B, 7>(rv, op, red);
   if (threadIdx.x == 0) {
-    amax_pos(&I.r_speed, rv[0]);
-    amin_pos(&I.r_minJ, rv[1]);
-    amax_pos(&I.r_maxJ, rv[2]);
-    atomicMin(&I.r_hmin, okey(rv[3]));
-    atomicAdd(&I.mass_eta0, rv[4]);
-    atomicAdd(&I.mass_b0, rv[5]);
-    if (cs.mesh == MESH_GIVEN) amax_pos(&I.r_W, rv[6]);
-    else amax_pos((unsigned long long*)&I.smax, rv[6]);
+    double* r = bf.prec + (int64_t)tl.rec * PREC;
+#pragma unroll
+    for (int k = 0; k < 7; ++k) r[k] = rv[k];
   }
 }
 
@@ -98,22 +93,20 @@ __global__ __launch_bounds__(B) void k_wfluid(Bufs bf, Consts cs, const Tile* __
   if (!I.active) return;
   View v = make_view(bf, tl.inst, I);
   const double W = wfluid_tile<B>(bf, cs, v, tl.c0, su, sv, red);
-  if (threadIdx.x == 0) amax_pos(&I.r_W, W);
+  if (threadIdx.x == 0) bf.prec[(int64_t)tl.rec * PREC + 4] = W;
 }
 
-// Per-instance results of one stage tile.
-__device__ __forceinline__ void publish_stage(Inst& I, int s, const StageRes& r,
-                                              unsigned long long seen_a,
-                                              unsigned long long seen_j) {
-  amax_seen(&I.r_alpha, dbits(r.alpha), seen_a);
-  if (s < 3) amax_seen(&I.r_maxJs, dbits(r.maxJ), seen_j);
-  const int q = blockIdx.x & (NSPREAD - 1);
-  if (r.ncls0) atomicAdd(&I.n_class[0][q], (unsigned long long)r.ncls0);
-  if (r.ncls1) atomicAdd(&I.n_class[1][q], (unsigned long long)r.ncls1);
-  if (r.ncls2) atomicAdd(&I.n_class[2][q], (unsigned long long)r.ncls2);
-  if (r.nlim) atomicAdd(&I.n_limited[q], (unsigned long long)r.nlim);
-  if (r.nneg) atomicAdd(&I.n_negweight[q], (unsigned long long)r.nneg);
-  if (r.status) atomicOr(&I.status, r.status);
+// Result record of one stage tile.
+__device__ __forceinline__ void publish_stage(const Bufs& bf, int rec, const StageRes& r) {
+  double* d = bf.srec + (int64_t)rec * SREC;
+  d[0] = r.alpha;
+  d[1] = r.maxJ;
+  d[2] = (double)r.ncls0;
+  d[3] = (double)r.ncls1;
+  d[4] = (double)r.ncls2;
+  d[5] = (double)r.nlim;
+  d[6] = (double)r.nneg;
+  d[7] = (double)r.status;
 }
 
 template <int B, int CPT>
@@ -126,10 +119,8 @@ __global__ __launch_bounds__(B) void k_stage(Bufs bf, Consts cs, const Tile* __r
   View v = make_view(bf, tl.inst, I);
   const StageScal sc = stage_scal(I, s);
   uint8_t* cl = bf.cls ? bf.cls + (int64_t)(s - 1) * bf.S + v.co : nullptr;
-  unsigned long long sa = 0ull, sj = 0ull;
-  if (threadIdx.x == 0) { sa = slot_read(&I.r_alpha); sj = slot_read(&I.r_maxJs); }
   StageRes r = stage_tile<B, CPT>(bf, cs, v, sc, tl.c0, sm, cl);
-  if (threadIdx.x == 0) publish_stage(I, s, r, sa, sj);
+  if (threadIdx.x == 0) publish_stage(bf, tl.rec, r);
 }
 
 // Stage-launch engine, ghost-free tiles: work-group b takes the tiles b, b+G,
@@ -173,7 +164,7 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(3))) void k_s
     if (cur.active) {
       uint8_t* cl = bf.cls ? bf.cls + (int64_t)(s - 1) * bf.S + cur.v.co : nullptr;
       const StageRes r = stage_compute<B, 1>(bf, cs, cur.v, cur.sc, cur.c0, sm, cl, st, t);
-      if (t == 0) publish_stage(bf.inst[cur.inst], s, r, 0ull, 0ull);
+      if (t == 0) publish_stage(bf, cur.rec, r);
     }
     cur = nxt;
     nxt = after;
@@ -187,18 +178,11 @@ __global__ __launch_bounds__(B) void k_final(Bufs bf, Consts cs, const Tile* __r
   Inst& I = bf.inst[tl.inst];
   if (!I.active) return;
   View v = make_view(bf, tl.inst, I);
-  unsigned long long seen[4] = {0ull, 0ull, 0ull, 0ull};
-  if (threadIdx.x == 0) {
-    seen[0] = slot_read(&I.r_speed); seen[1] = slot_read(&I.r_minJ);
-    seen[2] = slot_read(&I.r_maxJ); seen[3] = slot_read(&I.r_hmin);
-  }
   FinalRes r = final_tile<B>(bf, cs, v, I.dt, I.alpha[2], I.wscale, tl.c0, red);
   if (threadIdx.x == 0) {
-    amax_seen(&I.r_speed, dbits(r.speed), seen[0]);
-    amin_seen(&I.r_minJ, dbits(r.minJ), seen[1]);
-    amax_seen(&I.r_maxJ, dbits(r.maxJ), seen[2]);
-    amin_seen(&I.r_hmin, okey(r.hmin), seen[3]);
-    if (r.status) atomicOr(&I.status, r.status);
+    double* d = bf.prec + (int64_t)tl.rec * PREC;
+    d[0] = r.speed; d[1] = r.minJ; d[2] = r.maxJ; d[3] = r.hmin;
+    if (r.status) atomicOr(&I.status, r.status);  // rare: a failed cell
   }
 }
 
@@ -247,34 +231,74 @@ __device__ void boundary_update(Inst& I, const Consts& cs, const Bufs& bf, int i
   reset_step_slots(I);
 }
 
-__global__ __launch_bounds__(1024) void k_boundary(Bufs bf, Consts cs, int first,
-                                                   int* __restrict__ n_active) {
-  __shared__ int cnt;
-  if (threadIdx.x == 0) cnt = 0;
-  __syncthreads();
-  int c = 0;
-  for (int i = threadIdx.x; i < bf.ninst; i += blockDim.x) {
-    Inst& I = bf.inst[i];
-    boundary_update(I, cs, bf, i, first != 0);
-    c += I.active ? 1 : 0;
+// End of a step (first: start of a call): step results of each instance
+// from its plain-tile records (one wave per instance), then boundary_update.
+__global__ __launch_bounds__(256) void k_boundary(Bufs bf, Consts cs, int first) {
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= bf.ninst) return;
+  Inst& I = bf.inst[i];
+  if (!I.active) return;
+  double sp = 0.0, mnJ = INFINITY, mxJ = 0.0, hm = INFINITY, w4 = 0.0, me = 0.0, mb = 0.0;
+  for (int64_t k = bf.pfirst[i] + lane; k < bf.pfirst[i + 1]; k += 64) {
+    const double* r = bf.prec + k * PREC;
+    sp = fmax(sp, r[0]);
+    mnJ = fmin(mnJ, r[1]);
+    mxJ = fmax(mxJ, r[2]);
+    hm = fmin(hm, r[3]);
+    w4 = fmax(w4, r[4]);
+    if (first) { me += r[5]; mb += r[6]; }
   }
-  atomicAdd(&cnt, c);
-  __syncthreads();
-  if (threadIdx.x == 0) *n_active = cnt;
+  sp = wave_max(sp); mnJ = wave_min(mnJ); mxJ = wave_max(mxJ); hm = wave_min(hm);
+  w4 = wave_max(w4);
+  if (first) { me = wave_sum(me); mb = wave_sum(mb); }
+  if (lane == 0) {
+    I.r_speed = dbits(sp);
+    I.r_minJ = dbits(mnJ);
+    I.r_maxJ = dbits(mxJ);
+    const unsigned long long hk = okey(hm);
+    if (hk < I.r_hmin) I.r_hmin = hk;
+    if (first) {
+      I.mass_eta0 = me;
+      I.mass_b0 = mb;
+      if (cs.mesh == MESH_SINE || cs.mesh == MESH_PAPER) I.smax = w4;
+    }
+    if (cs.mesh == MESH_GIVEN || cs.mesh == MESH_FLUID) I.r_W = dbits(w4);
+    boundary_update(I, cs, bf, i, first != 0);
+  }
 }
 
-__global__ __launch_bounds__(1024) void k_after_stage(Bufs bf, int s) {
-  for (int i = threadIdx.x; i < bf.ninst; i += blockDim.x) {
-    Inst& I = bf.inst[i];
-    if (!I.active) continue;
-    I.alpha[s - 1] = bitsd(I.r_alpha);
-    if (s < 3) I.dx[s] = bitsd(I.r_maxJs);
+// Stage results of each instance from its stage-tile records (one wave per
+// instance): LF speed, indicator scale of the next stage, statistics.
+__global__ __launch_bounds__(256) void k_after_stage(Bufs bf, int s) {
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= bf.ninst) return;
+  Inst& I = bf.inst[i];
+  if (!I.active) return;
+  double a = 0.0, mj = 0.0;
+  unsigned n0 = 0u, n1 = 0u, n2 = 0u, nl = 0u, nn = 0u, stt = 0u;
+  for (int64_t k = bf.sfirst[i] + lane; k < bf.sfirst[i + 1]; k += 64) {
+    const double* r = bf.srec + k * SREC;
+    a = fmax(a, r[0]);
+    mj = fmax(mj, r[1]);
+    n0 += (unsigned)r[2]; n1 += (unsigned)r[3]; n2 += (unsigned)r[4];
+    nl += (unsigned)r[5]; nn += (unsigned)r[6];
+    stt |= (unsigned)r[7];
+  }
+  a = wave_max(a); mj = wave_max(mj);
+  n0 = wave_usum(n0); n1 = wave_usum(n1); n2 = wave_usum(n2);
+  nl = wave_usum(nl); nn = wave_usum(nn); stt = wave_or(stt);
+  if (lane == 0) {
+    I.alpha[s - 1] = a;
+    if (s < 3) I.dx[s] = mj;
+    I.n_class[0] += n0; I.n_class[1] += n1; I.n_class[2] += n2;
+    I.n_limited += nl; I.n_negweight += nn;
+    if (stt) I.status |= (int)stt;
     if (bf.dump.scal) {
       bf.dump.scal[(int64_t)i * 8 + 1 + s] = I.alpha[s - 1];
       if (s < 3) bf.dump.scal[(int64_t)i * 8 + 5 + s] = I.dx[s];
     }
-    I.r_alpha = 0ull;
-    I.r_maxJs = 0ull;
   }
 }
 
@@ -302,8 +326,26 @@ __global__ __launch_bounds__(B) void k_finish(Bufs bf, Consts cs, const Tile* __
   const int op[2] = {2, 2};
   block_reduce<B, 2>(rv, op, red);
   if (threadIdx.x == 0) {
-    atomicAdd(&I.mass_eta, rv[0]);
-    atomicAdd(&I.mass_b, rv[1]);
+    bf.prec[(int64_t)tl.rec * PREC + 5] = rv[0];
+    bf.prec[(int64_t)tl.rec * PREC + 6] = rv[1];
+  }
+}
+
+// Final masses of each instance from the plain-tile records of k_finish.
+__global__ __launch_bounds__(256) void k_masses(Bufs bf) {
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= bf.ninst) return;
+  double me = 0.0, mb = 0.0;
+  for (int64_t k = bf.pfirst[i] + lane; k < bf.pfirst[i + 1]; k += 64) {
+    me += bf.prec[k * PREC + 5];
+    mb += bf.prec[k * PREC + 6];
+  }
+  me = wave_sum(me);
+  mb = wave_sum(mb);
+  if (lane == 0) {
+    bf.inst[i].mass_eta = me;
+    bf.inst[i].mass_b = mb;
   }
 }
 
@@ -382,11 +424,11 @@ __global__ __launch_bounds__(B) void k_persistent(Bufs bf, Consts cs,
         __syncthreads();
       }
       if (threadIdx.x == 0) {
-        sI.n_class[0][0] += c_cls[0];
-        sI.n_class[1][0] += c_cls[1];
-        sI.n_class[2][0] += c_cls[2];
-        sI.n_limited[0] += c_lim;
-        sI.n_negweight[0] += c_neg;
+        sI.n_class[0] += c_cls[0];
+        sI.n_class[1] += c_cls[1];
+        sI.n_class[2] += c_cls[2];
+        sI.n_limited += c_lim;
+        sI.n_negweight += c_neg;
         sI.status |= st;
         sI.r_speed = dbits(fsp);
         sI.r_minJ = dbits(fminJ);
@@ -506,6 +548,10 @@ struct alew_ctx {
   Tile* tiles_plain_d = nullptr;
   Tile* tiles_edge_d = nullptr;   // stage tiles touching an instance end
   Tile* tiles_inner_d = nullptr;  // ghost-free stage tiles (prefetching kernel)
+  double* srec = nullptr;          // per-tile stage results
+  double* prec = nullptr;          // per-tile step results
+  int64_t* sfirst_d = nullptr;     // [max_inst+1] first stage / plain tile of each instance
+  int64_t* pfirst_d = nullptr;
   int64_t tiles_cap = 0;
   int64_t n_tiles_edge = 0, n_tiles_inner = 0;
   int pipe_blocks[3] = {0, 0, 0};  // resident work-groups per CU of k_stage_pipe<128/256/512>
@@ -569,29 +615,47 @@ int pick_cpt(const alew_ctx* c, int B) {
 alew_status build_tiles(alew_ctx* c, const int64_t* cell_off, int64_t ninst, int B, int TB) {
   std::vector<int64_t> off(cell_off, cell_off + ninst + 1);
   if (off == c->cell_off_h && c->cached_B == B && c->cached_TB == TB) return ALEW_OK;
+  // stage tiles carry their index in the full stage table as record index (the
+  // end-tile and ghost-free tables are subsets of it); plain tiles their own
   std::vector<Tile> ts, tp, te, tin;
+  std::vector<int64_t> sfirst(ninst + 1, 0), pfirst(ninst + 1, 0);
   for (int64_t i = 0; i < ninst; ++i) {
     const int64_t n = off[i + 1] - off[i];
+    sfirst[i] = (int64_t)ts.size();
+    pfirst[i] = (int64_t)tp.size();
     for (int64_t c0 = 0; c0 < n; c0 += TB - 2) {
-      ts.push_back(Tile{(int32_t)i, 0, c0});
+      const Tile tl{(int32_t)i, (int32_t)ts.size(), c0};
+      ts.push_back(tl);
       // same test as tile_inner() on the device
       const bool inner = c0 >= 3 && c0 + TB < n && n < (int64_t(1) << 28);
-      (inner ? tin : te).push_back(Tile{(int32_t)i, 0, c0});
+      (inner ? tin : te).push_back(tl);
     }
-    for (int64_t c0 = 0; c0 <= n; c0 += B) tp.push_back(Tile{(int32_t)i, 0, c0});
+    for (int64_t c0 = 0; c0 <= n; c0 += B) tp.push_back(Tile{(int32_t)i, (int32_t)tp.size(), c0});
   }
+  sfirst[ninst] = (int64_t)ts.size();
+  pfirst[ninst] = (int64_t)tp.size();
+  if (ts.size() >= (size_t)INT32_MAX || tp.size() >= (size_t)INT32_MAX)
+    return fail(ALEW_E_ARG, "too many tiles");
   const int64_t need = (int64_t)std::max(ts.size(), tp.size());
   if (need > c->tiles_cap) {
     for (Tile** tp_ : {&c->tiles_stage_d, &c->tiles_plain_d, &c->tiles_edge_d, &c->tiles_inner_d}) {
       if (*tp_) (void)hipFree(*tp_);
       *tp_ = nullptr;
     }
+    for (double** rp : {&c->srec, &c->prec}) {
+      if (*rp) (void)hipFree(*rp);
+      *rp = nullptr;
+    }
     HIPCHK(hipMalloc(&c->tiles_stage_d, need * sizeof(Tile)));
     HIPCHK(hipMalloc(&c->tiles_plain_d, need * sizeof(Tile)));
     HIPCHK(hipMalloc(&c->tiles_edge_d, need * sizeof(Tile)));
     HIPCHK(hipMalloc(&c->tiles_inner_d, need * sizeof(Tile)));
+    HIPCHK(hipMalloc(&c->srec, need * SREC * sizeof(double)));
+    HIPCHK(hipMalloc(&c->prec, need * PREC * sizeof(double)));
     c->tiles_cap = need;
   }
+  HIPCHK(hipMemcpyAsync(c->sfirst_d, sfirst.data(), sfirst.size() * sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(c->pfirst_d, pfirst.data(), pfirst.size() * sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
   HIPCHK(hipMemcpyAsync(c->tiles_stage_d, ts.data(), ts.size() * sizeof(Tile), hipMemcpyHostToDevice, c->stream));
   HIPCHK(hipMemcpyAsync(c->tiles_plain_d, tp.data(), tp.size() * sizeof(Tile), hipMemcpyHostToDevice, c->stream));
   if (!te.empty())
@@ -629,6 +693,8 @@ Bufs make_bufs(alew_ctx* c, int64_t S, int64_t ninst, double* hu, double* b, con
   bf.cls = cls; bf.inst = c->inst;
   bf.dts = dts; bf.dt_log = dt_log; bf.dts_stride = dts_stride;
   bf.S = S; bf.ninst = (int32_t)ninst; bf.pad = 0;
+  bf.srec = c->srec; bf.prec = c->prec;
+  bf.sfirst = c->sfirst_d; bf.pfirst = c->pfirst_d;
   bf.dump = Dump{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   return bf;
 }
@@ -687,14 +753,14 @@ void launch_step_seq(alew_ctx* c, const Bufs& bf, const Consts& cs, hipStream_t 
       hipLaunchKernelGGL((k_stage<B, CPT>), gs, dim3(B), 0, st, bf, cs, c->tiles_stage_d, s);
     }
     kt_end(c, st, kt);
-    hipLaunchKernelGGL(k_after_stage, dim3(1), dim3(1024), 0, st, bf, s);
+    hipLaunchKernelGGL(k_after_stage, dim3((unsigned)((bf.ninst + 3) / 4)), dim3(256), 0, st, bf, s);
   }
   const int kf = kt_begin(c, st, 1, (double)bf.S);
   hipLaunchKernelGGL(k_final<B>, gp, dim3(B), 0, st, bf, cs, c->tiles_plain_d);
   kt_end(c, st, kf);
   if (cs.mesh == MESH_FLUID)
     hipLaunchKernelGGL(k_wfluid<B>, gp, dim3(B), 0, st, bf, cs, c->tiles_plain_d);
-  hipLaunchKernelGGL(k_boundary, dim3(1), dim3(1024), 0, st, bf, cs, 0, c->nactive_d);
+  hipLaunchKernelGGL(k_boundary, dim3((unsigned)((bf.ninst + 3) / 4)), dim3(256), 0, st, bf, cs, 0);
 }
 
 GraphKey make_key(const Bufs& bf, const Consts& cs, int B, int CPT, const alew_ctx* c) {
@@ -747,6 +813,7 @@ alew_status run_stage_engine(alew_ctx* c, const Bufs& bf, const Consts& cs, int6
       c->last_launches += 1;
     }
     HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_count_active, dim3(1), dim3(1024), 0, c->stream, bf, c->nactive_d);
     HIPCHK(hipMemcpyAsync(c->nactive_h, c->nactive_d, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     if (*c->nactive_h == 0) break;
@@ -861,12 +928,13 @@ alew_status drive(alew_ctx* c, const alew_params* p, int64_t ninst, const int64_
     hipLaunchKernelGGL(k_prep<BB>, gp, dim3(BB), 0, c->stream, bf, cs, c->tiles_plain_d, h, wgiven); \
     if (cs.mesh == MESH_FLUID)                                                                  \
       hipLaunchKernelGGL(k_wfluid<BB>, gp, dim3(BB), 0, c->stream, bf, cs, c->tiles_plain_d);  \
-    hipLaunchKernelGGL(k_boundary, dim3(1), dim3(1024), 0, c->stream, bf, cs, 1, c->nactive_d); \
+    hipLaunchKernelGGL(k_boundary, dim3((unsigned)((ninst + 3) / 4)), dim3(256), 0, c->stream, bf, cs, 1); \
     HIPCHK(hipGetLastError());                                                                  \
     alew_status rs = (engine == 1) ? run_persistent<BB>(c, bf, cs, ninst)                       \
                                    : run_stages<BB>(c, bf, cs, max_iters, CPT);                 \
     if (rs != ALEW_OK) return rs;                                                               \
     hipLaunchKernelGGL(k_finish<BB>, gp, dim3(BB), 0, c->stream, bf, cs, c->tiles_plain_d, h, x); \
+    hipLaunchKernelGGL(k_masses, dim3((unsigned)((ninst + 3) / 4)), dim3(256), 0, c->stream, bf); \
   } while (0)
   if (B == 128) ALEW_DISPATCH(128);
   else if (B == 512) ALEW_DISPATCH(512);
@@ -885,11 +953,9 @@ alew_status drive(alew_ctx* c, const alew_params* p, int64_t ninst, const int64_
       alew_stats& S_ = stats[i];
       std::memset(&S_, 0, sizeof(S_));
       S_.steps = I.steps;
-      for (int q = 0; q < NSPREAD; ++q) {
-        for (int k = 0; k < 3; ++k) S_.n_class[k] += (int64_t)I.n_class[k][q];
-        S_.n_limited += (int64_t)I.n_limited[q];
-        S_.n_negweight += (int64_t)I.n_negweight[q];
-      }
+      for (int k = 0; k < 3; ++k) S_.n_class[k] = (int64_t)I.n_class[k];
+      S_.n_limited = (int64_t)I.n_limited;
+      S_.n_negweight = (int64_t)I.n_negweight;
       S_.t = I.t;
       S_.dt_min = I.dt_min;
       S_.dt_max = I.dt_max;
@@ -972,6 +1038,8 @@ alew_status alew_create(alew_ctx** out, int64_t max_cells, int64_t max_inst, voi
             alloc((void**)&c->xa, Nn * 8) && alloc((void**)&c->xb, Nn * 8) &&
             alloc((void**)&c->inst, max_inst * sizeof(Inst)) &&
             alloc((void**)&c->cell_off_d, (max_inst + 1) * sizeof(int64_t)) &&
+            alloc((void**)&c->sfirst_d, (max_inst + 1) * sizeof(int64_t)) &&
+            alloc((void**)&c->pfirst_d, (max_inst + 1) * sizeof(int64_t)) &&
             alloc((void**)&c->order_d, max_inst * sizeof(int32_t)) &&
             alloc((void**)&c->queue_d, sizeof(unsigned)) && alloc((void**)&c->nactive_d, sizeof(int)) &&
             alloc((void**)&c->dt1_d, sizeof(double));
@@ -994,7 +1062,8 @@ void alew_destroy(alew_ctx* c) {
   if (c->graph) (void)hipGraphDestroy(c->graph);
   void* ps[] = {c->eta, c->P0, c->D0, c->P1, c->D1, c->w, c->xa, c->xb, c->inst, c->cell_off_d,
                 c->order_d, c->queue_d, c->nactive_d, c->tiles_stage_d, c->tiles_plain_d,
-                c->tiles_edge_d, c->tiles_inner_d, c->dt1_d,
+                c->tiles_edge_d, c->tiles_inner_d, c->srec, c->prec, c->sfirst_d, c->pfirst_d,
+                c->dt1_d,
                 c->adj_ws};
   for (void* p : ps)
     if (p) (void)hipFree(p);
@@ -1168,7 +1237,7 @@ alew_status alew_adjoint(alew_ctx* c, const alew_params* p, int64_t ninst,
   };
   auto xbuf_of = [&](int64_t k) { return (k & 1) ? c->xb : c->xa; };
   hipLaunchKernelGGL(k_prep<256>, gp, dim3(256), 0, st, bf, cs, c->tiles_plain_d, h0, nullptr);
-  hipLaunchKernelGGL(k_boundary, dim3(1), dim3(1024), 0, st, bf, cs, 1, c->nactive_d);
+  hipLaunchKernelGGL(k_boundary, dim3((unsigned)((ninst + 3) / 4)), dim3(256), 0, st, bf, cs, 1);
   // forward with checkpoints; when a gradient follows, the last segment keeps
   // its records right away (the reverse sweep starts there)
   const int64_t qlast = nck - 1, klast = qlast * K;

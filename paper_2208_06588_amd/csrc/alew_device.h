@@ -32,8 +32,6 @@ struct Consts {
 
 // Per-instance scalars.  Reduction slots hold IEEE bit patterns so that
 // integer atomics give order-independent max/min.
-enum { NSPREAD = 8 };
-
 struct Inst {
   double t, t0, t_end, dt;
   double alpha[3];  // LF speed of stages 1..3
@@ -45,13 +43,19 @@ struct Inst {
   int64_t steps, max_steps;
   int32_t active, status;
   unsigned long long r_speed, r_minJ, r_maxJ, r_W;  // for the next step size
-  unsigned long long r_alpha, r_maxJs;              // stage slots
   unsigned long long r_hmin;                        // ordered key of min depth
-  // statistics counters, spread over NSPREAD slots (work-group index mod
-  // NSPREAD) so that the tiles of one large instance do not all add into one
-  // address; the host sums the slots
-  unsigned long long n_class[3][NSPREAD], n_limited[NSPREAD], n_negweight[NSPREAD];
+  unsigned long long n_class[3], n_limited, n_negweight;
 };
+
+// Per-tile results.  Every tile writes its record with plain stores; a small
+// kernel then reduces the records of each instance in tile order (one wave
+// per instance), so no tile ever waits on, or queues behind, a shared address
+// and every sum is taken in a fixed order.
+//   stage record: LF speed, max next width, classes S/T/N, limited, negative
+//                 weights, status bits
+//   plain record: max speed, min width, max width, min depth, node-speed
+//                 bound (or shape bound), two mass sums, unused
+enum { SREC = 8, PREC = 8 };
 
 // ----------------------------------------------------------------------------
 // order-independent atomics on doubles
@@ -73,25 +77,6 @@ __device__ __forceinline__ double okey_inv(unsigned long long k) {
 }
 __device__ __forceinline__ void amax_pos(unsigned long long* p, double v) {
   atomicMax(p, dbits(v));
-}
-__device__ __forceinline__ void amin_pos(unsigned long long* p, double v) {
-  atomicMin(p, dbits(v));
-}
-// The slots only move one way (max up, min down): a tile whose value cannot
-// change what the slot held when the tile started skips the atomic.  After
-// the first tiles of a large instance almost all do, which keeps its tiles
-// from queueing on one address.  The slot is read at the start of the tile
-// (the load is long done by the end); a stale value only costs an atomic.
-__device__ __forceinline__ unsigned long long slot_read(unsigned long long* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void amax_seen(unsigned long long* p, unsigned long long k,
-                                          unsigned long long seen) {
-  if (k > seen) atomicMax(p, k);
-}
-__device__ __forceinline__ void amin_seen(unsigned long long* p, unsigned long long k,
-                                          unsigned long long seen) {
-  if (k < seen) atomicMin(p, k);
 }
 
 // Reciprocal: hardware estimate refined by two Newton steps (relative error of
@@ -124,6 +109,11 @@ __device__ __forceinline__ double wave_min(double v) {
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ unsigned wave_or(unsigned v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v |= (unsigned)__shfl_xor((int)v, o, 64);
   return v;
 }
 __device__ __forceinline__ unsigned wave_usum(unsigned v) {

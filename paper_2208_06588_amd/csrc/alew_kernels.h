@@ -39,6 +39,10 @@ struct Bufs {
   int64_t S;
   int32_t ninst;
   int32_t pad;
+  double* srec;            // [stage tiles][SREC] per-tile stage results
+  double* prec;            // [plain tiles][PREC] per-tile step results
+  const int64_t* sfirst;   // [ninst+1] first stage tile of each instance
+  const int64_t* pfirst;   // [ninst+1] first plain tile of each instance
   Dump dump;
 };
 
@@ -491,6 +495,7 @@ struct TileInfo {
   StageScal sc;
   int64_t c0;
   int inst;
+  int rec;
   int active;
 };
 
@@ -505,6 +510,7 @@ __device__ __forceinline__ TileInfo tile_info(const Bufs& bf, const TT* tiles, i
   const ci64 off = (ci64)bf.cell_off;
   TileInfo ti;
   ti.inst = inst;
+  ti.rec = tp->rec;
   ti.c0 = tp->c0;
   ti.active = I->active;
   ti.v.co = off[inst];

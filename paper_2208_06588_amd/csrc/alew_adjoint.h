@@ -548,7 +548,7 @@ __global__ __launch_bounds__(B) void k_adj_fused(AdjBufs ab, Consts cs,
     sm.e[q] = e; sm.m[q] = m; sm.b[q] = b; sm.J[q] = J;
     sm.rho[0][q] = r0; sm.rho[1][q] = r1; sm.rho[2][q] = r2;
   }
-  __syncthreads();
+  lds_sync();
   // 2. forward reconstruction and limiter of cell j = c0 - 3 + t (stencil slots t .. t+4)
   const int64_t j = c0 - 3 + t;
   const bool active = (j >= -1) && (j <= n);
@@ -569,7 +569,7 @@ __global__ __launch_bounds__(B) void k_adj_fused(AdjBufs ab, Consts cs,
     sm.u.tr[0][t] = o.hL; sm.u.tr[1][t] = o.mL; sm.u.tr[2][t] = o.bL;
     sm.u.tr[3][t] = o.hR; sm.u.tr[4][t] = o.mR; sm.u.tr[5][t] = o.bR;
   }
-  __syncthreads();
+  lds_sync();
   // 3. face at node j between cells j-1 (slot t+1) and j (slot t+2)
   if (t >= 1 && j >= 0 && j <= n) {
     const double rl[3] = {sm.rho[0][t + 1], sm.rho[1][t + 1], sm.rho[2][t + 1]};
@@ -587,7 +587,7 @@ __global__ __launch_bounds__(B) void k_adj_fused(AdjBufs ab, Consts cs,
     sm.lf[3][t] = Lr.h; sm.lf[4][t] = Lr.m; sm.lf[5][t] = Lr.b;
     sm.B1[t] = 0.5 * (bl + br);
   }
-  __syncthreads();  // the traces are dead from here on: their LDS takes the contributions
+  lds_sync();  // the traces are dead from here on: their LDS takes the contributions
   // 4. reverse of cell j for 1 <= t <= B-2; contributions to stencil slots t .. t+4
   double cv[15];
 #pragma unroll
@@ -624,7 +624,7 @@ __global__ __launch_bounds__(B) void k_adj_fused(AdjBufs ab, Consts cs,
   }
 #pragma unroll
   for (int k = 0; k < 15; ++k) sm.u.cl[k][t] = cv[k];
-  __syncthreads();
+  lds_sync();
   // 5. owned cell k = c0 + t: slot i = t + 5 collects offset o from the cell of thread i - o
   if (t < TB && c0 + t < n) {
     const int64_t k = c0 + t;

@@ -107,6 +107,7 @@ __device__ __forceinline__ void publish_stage(const Bufs& bf, int rec, const Sta
   d[5] = (double)r.nlim;
   d[6] = (double)r.nneg;
   d[7] = (double)r.status;
+  d[8] = r.akey;
 }
 
 template <int B, int CPT>
@@ -289,6 +290,16 @@ __global__ __launch_bounds__(256) void k_after_stage(Bufs bf, int s) {
   a = wave_max(a); mj = wave_max(mj);
   n0 = wave_usum(n0); n1 = wave_usum(n1); n2 = wave_usum(n2);
   nl = wave_usum(nl); nn = wave_usum(nn); stt = wave_or(stt);
+  double ak = 1e300;
+  if (bf.dump.akey) {
+    // first face trace of the instance attaining alpha: smallest key among
+    // the tiles whose LF speed is the instance's
+    for (int64_t k = bf.sfirst[i] + lane; k < bf.sfirst[i + 1]; k += 64) {
+      const double* r = bf.srec + k * SREC;
+      if (r[0] == a) ak = fmin(ak, r[8]);
+    }
+    ak = wave_min(ak);
+  }
   if (lane == 0) {
     I.alpha[s - 1] = a;
     if (s < 3) I.dx[s] = mj;
@@ -299,6 +310,7 @@ __global__ __launch_bounds__(256) void k_after_stage(Bufs bf, int s) {
       bf.dump.scal[(int64_t)i * 8 + 1 + s] = I.alpha[s - 1];
       if (s < 3) bf.dump.scal[(int64_t)i * 8 + 5 + s] = I.dx[s];
     }
+    if (bf.dump.akey) bf.dump.akey[(int64_t)(s - 1) * bf.ninst + i] = ak;
   }
 }
 
@@ -1172,7 +1184,9 @@ alew_status alew_adjoint(alew_ctx* c, const alew_params* p, int64_t ninst,
   const size_t n_state = 2 * (size_t)S;                 // hu, b of the run
   const size_t n_ck = (size_t)nck * (3 * S + NN);       // checkpoints
   const size_t n_ckI = (size_t)nck * ninst * sizeof(Inst) / 8 + 1;
-  const size_t per_step = 18 * (size_t)S + 8 * (size_t)NN + 8 * (size_t)ninst;
+  // records of one step: q and D of the three stages, x^n and w^n, the step
+  // scalars, and the argmax keys of the three stages
+  const size_t per_step = 18 * (size_t)S + 2 * (size_t)NN + 11 * (size_t)ninst;
   const size_t n_seg = (size_t)(K + 1) * per_step;
   // tiles of the fused reverse stage: 250 owned cells each (256 threads)
   constexpr int BA = 256, TBA = BA - 6;
@@ -1181,8 +1195,8 @@ alew_status alew_adjoint(alew_ctx* c, const alew_params* p, int64_t ninst,
     for (int64_t c0 = 0; c0 < cell_off[i + 1] - cell_off[i]; c0 += TBA)
       atiles.push_back(AdjTile{(int32_t)i, 0, c0});
   const size_t n_at = 2 * atiles.size();
-  const size_t n_adj = 9 * (size_t)S + 2 * (size_t)ninst + (size_t)ninst * ngauge +
-                       18 * (size_t)ninst + n_at + (size_t)c->n_tiles_plain + (size_t)ninst + 1;
+  const size_t n_adj = 9 * (size_t)S + (size_t)ninst + (size_t)ninst * ngauge +
+                       18 * (size_t)ninst + n_at + atiles.size() + (size_t)ninst + 1;
   const size_t need = (n_state + n_ck + n_ckI + n_seg + n_adj) * 8;
   if (need > c->adj_ws_bytes) {
     if (c->adj_ws) (void)hipFree(c->adj_ws);
@@ -1203,9 +1217,8 @@ alew_status alew_adjoint(alew_ctx* c, const alew_params* p, int64_t ninst,
   double* gfold = wp; wp += 18 * ninst;
   AdjTile* atiles_d = (AdjTile*)wp; wp += n_at;
   double* lalpha = wp; wp += ninst;
-  double* lpart = wp; wp += c->n_tiles_plain;
+  double* lpart = wp; wp += atiles.size();
   int64_t* tfirst_d = (int64_t*)wp; wp += ninst + 1;
-  unsigned long long* akey = (unsigned long long*)wp; wp += ninst;
   int64_t* gcell = (int64_t*)wp; wp += ninst * ngauge;
   hipStream_t st = c->stream;
   // per-instance scalars: nsteps frozen steps from t0
@@ -1229,9 +1242,9 @@ alew_status alew_adjoint(alew_ctx* c, const alew_params* p, int64_t ninst,
     double* base = seg + slot * per_step;
     d.q = base;
     d.D = base + 9 * S;
-    d.fs = base + 18 * S;
-    d.xw = base + 18 * S + 6 * NN;
-    d.scal = base + 18 * S + 8 * NN;
+    d.xw = base + 18 * S;
+    d.scal = base + 18 * S + 2 * NN;
+    d.akey = d.scal + 8 * ninst;
     d.scal_next = d.scal + per_step;
     return d;
   };
@@ -1280,19 +1293,19 @@ alew_status alew_adjoint(alew_ctx* c, const alew_params* p, int64_t ninst,
   hipLaunchKernelGGL(k_gauge_seed, dim3(gb), dim3(256), 0, st, ng, S, gcell, gauge_bar, lam);
   AdjBufs ab;
   ab.cell_off = c->cell_off_d; ab.S = S; ab.ninst = (int32_t)ninst; ab.pad = 0;
-  ab.lam = lam; ab.lam_out = lam2; ab.lbase = lbase; ab.lalpha = lalpha; ab.akey = akey;
+  ab.lam = lam; ab.lam_out = lam2; ab.lbase = lbase; ab.lalpha = lalpha;
   ab.lpart = lpart;
   {
-    // first plain tile of each instance (plain tiles: B = 256 cells, n+1 nodes)
+    // first fused tile of each instance
     std::vector<int64_t> tf(ninst + 1, 0);
-    for (int64_t i = 0; i < ninst; ++i) tf[i + 1] = tf[i] + (cell_off[i + 1] - cell_off[i]) / 256 + 1;
-    if (tf[ninst] != c->n_tiles_plain) return fail(ALEW_E_ARG, "internal: plain tile count");
+    for (int64_t i = 0; i < ninst; ++i)
+      tf[i + 1] = tf[i] + (cell_off[i + 1] - cell_off[i] + TBA - 1) / TBA;
+    if (tf[ninst] != (int64_t)atiles.size()) return fail(ALEW_E_ARG, "internal: fused tile count");
     HIPCHK(hipMemcpyAsync(tfirst_d, tf.data(), tf.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(atiles_d, atiles.data(), atiles.size() * sizeof(AdjTile),
+                          hipMemcpyHostToDevice, st));
     HIPCHK(hipStreamSynchronize(st));
   }
-  const AdjTile* tpl = (const AdjTile*)c->tiles_plain_d;
-  HIPCHK(hipMemcpyAsync(atiles_d, atiles.data(), atiles.size() * sizeof(AdjTile),
-                        hipMemcpyHostToDevice, st));
   const dim3 ga((unsigned)atiles.size());
   const unsigned gfb = (unsigned)((ninst + 255) / 256);
   for (int64_t q = nck - 1; q >= 0; --q) {
@@ -1317,13 +1330,11 @@ alew_status alew_adjoint(alew_ctx* c, const alew_params* p, int64_t ninst,
       for (int s3 = 3; s3 >= 1; --s3) {
         ab.q = d.q + (int64_t)3 * (s3 - 1) * S;
         ab.D = d.D + (int64_t)3 * (s3 - 1) * S;
-        ab.fsl = d.fs + (int64_t)2 * (s3 - 1) * NN;
-        ab.fsr = ab.fsl + NN;
-        hipLaunchKernelGGL(k_adj_reset, dim3(1), dim3(1024), 0, st, ab);
-        hipLaunchKernelGGL(k_adj_alpha<256>, gp, dim3(256), 0, st, ab, tpl, s3);
-        hipLaunchKernelGGL(k_adj_lsum, dim3((unsigned)((ninst + 3) / 4)), dim3(256), 0, st, ab, tfirst_d);
+        ab.akeyd = d.akey + (int64_t)(s3 - 1) * ninst;
         hipLaunchKernelGGL(k_adj_fused<BA>, ga, dim3(BA), 0, st, ab, cs, atiles_d, s3, gfold);
         hipLaunchKernelGGL(k_adj_fold, dim3(gfb), dim3(256), 0, st, ab, cs, gfold);
+        hipLaunchKernelGGL(k_adj_lsum, dim3((unsigned)((ninst + 3) / 4)), dim3(256), 0, st, ab, tfirst_d);
+        hipLaunchKernelGGL(k_adj_patch, dim3((unsigned)((ninst + 63) / 64)), dim3(64), 0, st, ab, cs, s3);
         std::swap(ab.lam, ab.lam_out);
       }
     }

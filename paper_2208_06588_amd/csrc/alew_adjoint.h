@@ -14,12 +14,17 @@
 // state.
 //
 // Work split per stage (gather form, no floating-point atomics):
-//   k_adj_alpha   lambda_alpha and the argmax face per instance;
 //   k_adj_fused   per tile: forward reconstruction and limiter of its cells and
-//                 a two-cell halo, face adjoints, reverse of limiter and
-//                 reconstruction, stencil contributions summed in LDS, and
-//                 lambda^(s-1) of the owned cells;
-//   k_adj_fold    contributions to ghost cells onto their source cells.
+//                 a two-cell halo, face adjoints without the alpha term, reverse
+//                 of limiter and reconstruction, stencil contributions summed in
+//                 LDS, lambda^(s-1) of the owned cells, and the tile's part of
+//                 lambda_alpha;
+//   k_adj_fold    contributions to ghost cells onto their source cells;
+//   k_adj_lsum    lambda_alpha per instance (tile parts in tile order);
+//   k_adj_patch   the alpha term: one trace per instance (found by the forward
+//                 records), through the limiter and reconstruction of its cell.
+// The alpha term is linear in the adjoints given the frozen switches, so it can
+// be added after the rest.
 #pragma once
 
 #include "alew_kernels.h"
@@ -33,8 +38,7 @@ struct AdjBufs {
   int32_t pad;
   const double* q;     // [3][S] stage input q^(s-1) (eta, hu, b)
   const double* D;     // [3][S] alpha coefficient of the residual
-  const double* fsl;   // [S+ninst] left-trace speed per face
-  const double* fsr;   // [S+ninst] right-trace speed per face
+  const double* akeyd; // [ninst] 2 f + side of the trace attaining alpha (forward record)
   const double* x;     // [S+ninst] x^n
   const double* w;     // [S+ninst] w^n
   const double* scal;  // [ninst][8] t, dt, alpha_1..3, dx_0..2 of the step
@@ -43,8 +47,7 @@ struct AdjBufs {
                        // lambda^(s) of their halo cells while others write)
   double* lbase;       // [3][S] adjoint of q^n accumulated over the stages
   double* lalpha;      // [ninst]
-  double* lpart;       // [plain tiles] per-tile parts of lambda_alpha
-  unsigned long long* akey;  // [ninst] argmax key 2*face + side
+  double* lpart;       // [fused tiles] per-tile parts of lambda_alpha
 };
 
 __device__ __forceinline__ double stage_a(int s) { return s == 1 ? 0.0 : (s == 2 ? 0.75 : 1.0 / 3.0); }
@@ -427,40 +430,7 @@ struct AdjTile {
   int64_t c0;
 };
 
-// rho . D summed per plain tile (the per-instance sum is taken in a fixed
-// order by k_adj_lsum), and the face/trace that attains alpha.
-template <int B>
-__global__ __launch_bounds__(B) void k_adj_alpha(AdjBufs ab, const AdjTile* __restrict__ tiles,
-                                                 int s) {
-  __shared__ double red[(B / 64) * 8];
-  const AdjTile tl = tiles[blockIdx.x];
-  const int i = tl.inst;
-  const int64_t co = ab.cell_off[i], n = ab.cell_off[i + 1] - co, no = co + i;
-  const int64_t j = tl.c0 + threadIdx.x;
-  const double dt = ab.scal[(int64_t)i * 8 + 1];
-  const double alpha = ab.scal[(int64_t)i * 8 + 1 + s];
-  double acc = 0.0;
-  if (j < n) {
-    double Jn, Jin, Jout;
-    stage_widths(ab.x + no, ab.w + no, j, dt, s, Jn, Jin, Jout);
-    const double rf = stage_b(s) * dt / Jout;
-    const int64_t g = co + j;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) acc += (rf * ab.lam[c * ab.S + g]) * ab.D[c * ab.S + g];
-  }
-  if (j <= n) {
-    unsigned long long key = ~0ull;
-    if (ab.fsl[no + j] == alpha) key = 2ull * (unsigned long long)j;
-    else if (ab.fsr[no + j] == alpha) key = 2ull * (unsigned long long)j + 1ull;
-    if (key != ~0ull) atomicMin(&ab.akey[i], key);
-  }
-  double rv[1] = {acc};
-  const int op[1] = {2};
-  block_reduce<B, 1>(rv, op, red);
-  if (threadIdx.x == 0) ab.lpart[blockIdx.x] = rv[0];
-}
-
-// lambda_alpha of each instance from its plain tiles' parts (the tiles of
+// lambda_alpha of each instance from its fused tiles' parts (the tiles of
 // instance i are tfirst[i] .. tfirst[i+1]-1): one wave per instance, lane l
 // sums the parts l, l+64, ... and the lanes are combined by a fixed butterfly,
 // so the result does not depend on scheduling.
@@ -474,9 +444,6 @@ __global__ __launch_bounds__(256) void k_adj_lsum(AdjBufs ab, const int64_t* __r
   if (lane == 0) ab.lalpha[i] = acc;
 }
 
-__global__ void k_adj_reset(AdjBufs ab) {
-  for (int i = threadIdx.x; i < ab.ninst; i += blockDim.x) ab.akey[i] = ~0ull;
-}
 
 // ----------------------------------------------------------------------------
 // Fused reverse stage.  A tile owns the TB = B - 6 cells [c0, c0 + TB) and
@@ -521,8 +488,6 @@ __global__ __launch_bounds__(B) void k_adj_fused(AdjBufs ab, Consts cs,
   const double dt = ab.scal[(int64_t)i * 8 + 1];
   const double alpha = ab.scal[(int64_t)i * 8 + 1 + s];
   const double dx = ab.scal[(int64_t)i * 8 + 5 + (s - 1)];
-  const double lalpha = ab.lalpha[i];
-  const unsigned long long akey = ab.akey[i];
   const double bs = stage_b(s);
   // 1. stencil data and rho for cells c0-5 .. c0+B-2
   for (int q = t; q < B + 4; q += B) {
@@ -579,10 +544,6 @@ __global__ __launch_bounds__(B) void k_adj_fused(AdjBufs ab, Consts cs,
     TraceAdj Ll, Lr;
     face_vjp(hl, ml, bl, hr, mr, br, w[j], alpha, cs.g, cs.dry_eps, rl, rr, sm.e[t + 1],
              sm.e[t + 2], Ll, Lr);
-    if (akey == 2ull * (unsigned long long)j)
-      alpha_trace_vjp(hl, ml, w[j], cs.g, cs.dry_eps, lalpha, Ll);
-    if (akey == 2ull * (unsigned long long)j + 1ull)
-      alpha_trace_vjp(hr, mr, w[j], cs.g, cs.dry_eps, lalpha, Lr);
     sm.lf[0][t] = Ll.h; sm.lf[1][t] = Ll.m; sm.lf[2][t] = Ll.b;
     sm.lf[3][t] = Lr.h; sm.lf[4][t] = Lr.m; sm.lf[5][t] = Lr.b;
     sm.B1[t] = 0.5 * (bl + br);
@@ -626,6 +587,7 @@ __global__ __launch_bounds__(B) void k_adj_fused(AdjBufs ab, Consts cs,
   for (int k = 0; k < 15; ++k) sm.u.cl[k][t] = cv[k];
   lds_sync();
   // 5. owned cell k = c0 + t: slot i = t + 5 collects offset o from the cell of thread i - o
+  double lap = 0.0;  // rho . D of the owned cell (part of lambda_alpha)
   if (t < TB && c0 + t < n) {
     const int64_t k = c0 + t;
     const int si = t + 5;
@@ -639,6 +601,8 @@ __global__ __launch_bounds__(B) void k_adj_fused(AdjBufs ab, Consts cs,
       acc[c] = bs * Jin * mu[c];
     }
     double* lo = ab.lam_out;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) lap += (bs * dt * mu[c]) * ab.D[c * ab.S + g];
 #pragma unroll
     for (int oo = 0; oo < 5; ++oo) {
 #pragma unroll
@@ -673,6 +637,83 @@ __global__ __launch_bounds__(B) void k_adj_fused(AdjBufs ab, Consts cs,
       }
       gfold[(((int64_t)i * 2 + gend) * 3 + gi) * 3 + gc] = acc;
     }
+  }
+  double rv[1] = {lap};
+  const int op[1] = {2};
+  block_reduce<B, 1>(rv, op, sm.lf[0]);
+  if (t == 0) ab.lpart[blockIdx.x] = rv[0];
+}
+
+// The alpha term of the reverse stage: lambda_alpha times the derivative of
+// the LF speed at the trace that attains it, through the limiter and the
+// reconstruction of that trace's cell (a ghost cell at an end is possible),
+// added onto lambda^(s-1) after k_adj_fused and k_adj_fold.  One thread per
+// instance.
+__global__ __launch_bounds__(64) void k_adj_patch(AdjBufs ab, Consts cs, int s) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ab.ninst) return;
+  const double lal = ab.lalpha[i];
+  const double kd = ab.akeyd[i];
+  if (lal == 0.0 || !(kd >= 0.0 && kd < 1e18)) return;
+  const int64_t co = ab.cell_off[i], n = ab.cell_off[i + 1] - co, no = co + i;
+  const int64_t key = (int64_t)kd;
+  const int64_t f = key >> 1;
+  const int side = (int)(key & 1);
+  if (f < 0 || f > n) return;
+  const int64_t cc = side ? f : f - 1;  // the cell whose trace it is (-1 .. n)
+  const double* x = ab.x + no;
+  const double* w = ab.w + no;
+  const double dt = ab.scal[(int64_t)i * 8 + 1];
+  double Dx = ab.scal[(int64_t)i * 8 + 5 + (s - 1)];
+  double e5[5], m5[5], b5[5], J5[5], h5[5], v5[5], ms5[5];
+  int64_t src5[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    double ms;
+    const int64_t src = ghost_src(cs.bc, n, cc - 2 + k, ms);
+    double Jn, Jin, Jout;
+    stage_widths(x, w, src, dt, s, Jn, Jin, Jout);
+    const int64_t g = co + src;
+    e5[k] = ab.q[g];
+    m5[k] = ab.q[ab.S + g] * ms;
+    b5[k] = ab.q[2 * ab.S + g];
+    J5[k] = Jin;
+    src5[k] = src;
+    ms5[k] = ms;
+  }
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    h5[k] = e5[k] - b5[k];
+    v5[k] = (cs.flags & F_BETA_FROM_H) ? h5[k] : e5[k];
+  }
+  if (cs.flags & F_BETA_LOCAL) Dx = J5[2];
+  CellRecon o;
+  recon_cell(v5, h5, m5, b5, J5, frcp(J5[2]), Dx, cs.weno_eps, e5[2], o);
+  const CellRecon ou = o;
+  limit_cell(h5[2], m5[2], cs.pp_eps, o);
+  TraceAdj LL{0, 0, 0}, LR{0, 0, 0};
+  if (side == 0) alpha_trace_vjp(o.hR, o.mR, w[f], cs.g, cs.dry_eps, lal, LR);
+  else alpha_trace_vjp(o.hL, o.mL, w[f], cs.g, cs.dry_eps, lal, LL);
+  double lhbar = 0.0, lmbar = 0.0;
+  limit_vjp(h5[2], m5[2], cs.pp_eps, ou, LL, LR, lhbar, lmbar);
+  ReconAdjOut ra;
+  recon_cell_vjp(v5, h5, m5, b5, J5, Dx, cs.weno_eps, e5[2], LL, LR, 0.0, ra);
+  const bool vh = (cs.flags & F_BETA_FROM_H) != 0;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    double lh = ra.lh[k] + (vh ? ra.lv[k] : 0.0);
+    double le = lh + (vh ? 0.0 : ra.lv[k]);
+    double lb = ra.lb[k] - lh;
+    double lm = ra.lm[k];
+    if (k == 2) {
+      le += lhbar + ra.letabar;
+      lb -= lhbar;
+      lm += lmbar;
+    }
+    const int64_t g = co + src5[k];
+    ab.lam_out[g] += le;
+    ab.lam_out[ab.S + g] += ms5[k] * lm;
+    ab.lam_out[2 * ab.S + g] += lb;
   }
 }
 

@@ -52,10 +52,11 @@ struct Inst {
 // per instance), so no tile ever waits on, or queues behind, a shared address
 // and every sum is taken in a fixed order.
 //   stage record: LF speed, max next width, classes S/T/N, limited, negative
-//                 weights, status bits
+//                 weights, status bits, (records kept) first face trace
+//                 attaining the tile's LF speed, unused
 //   plain record: max speed, min width, max width, min depth, node-speed
 //                 bound (or shape bound), two mass sums, unused
-enum { SREC = 8, PREC = 8 };
+enum { SREC = 10, PREC = 8 };
 
 // ----------------------------------------------------------------------------
 // order-independent atomics on doubles

@@ -9,7 +9,7 @@ namespace alew_dev {
 struct Dump {
   double* q;     // [3 stages][3 comps][S]: stage inputs q^(s-1)
   double* D;     // [3][3][S]: alpha coefficient of the residual
-  double* fs;    // [3 stages][2 sides][S + ninst]: trace speeds |u - w| + sqrt(g h) per face
+  double* akey;  // [3 stages][ninst]: 2 f + side of the first face trace attaining alpha
   double* xw;    // [2][S + ninst]: x^n and w^n of the step
   double* scal;       // [ninst][8] of this step: t, dt, alpha_1..3, dx_0..2
   double* scal_next;  // the next step's record (t, dt, dx_0 are set at step end)
@@ -87,6 +87,7 @@ __device__ __forceinline__ StageScal stage_scal(const Inst& I, int s) {
 // Block-level results of a stage tile.
 struct StageRes {
   double alpha, maxJ;
+  double akey;  // (records kept) first face trace of the tile attaining its alpha
   unsigned ncls0, ncls1, ncls2, nlim, nneg;
   int status;
 };
@@ -322,10 +323,12 @@ __device__ __forceinline__ StageRes stage_compute(const Bufs& bf, const Consts& 
   lds_sync();
   // 3. face at node j of tile cell i (between cells j-1 and j), i = 1 .. TB-1
   double fspeed = 0.0;
+  double fsl[CPT], fsr[CPT];
 #pragma unroll
   for (int c = 0; c < CPT; ++c) {
     const int i = t + c * B;
     const int64_t j = c0 - 1 + i;
+    fsl[c] = -1.0; fsr[c] = -1.0;
     if (i >= 1 && j >= 0 && j <= v.n) {
       if (lane == 0) {
         const int q = c * NW + wv - 1;
@@ -336,11 +339,8 @@ __device__ __forceinline__ StageRes stage_compute(const Bufs& bf, const Consts& 
       sm.u.fl[0][i] = f.Fc1; sm.u.fl[1][i] = f.Fc2; sm.u.fl[2][i] = f.Gc; sm.u.fl[3][i] = f.je;
       sm.u.fl[4][i] = f.jm; sm.u.fl[5][i] = f.jb; sm.u.fl[6][i] = f.B1; sm.u.fl[7][i] = f.B2;
       fspeed = fmax(fspeed, f.speed);
-      if (bf.dump.fs) {
-        const int64_t NN = bf.S + bf.ninst;
-        bf.dump.fs[(int64_t)(2 * (sc.s - 1)) * NN + v.no + j] = f.sl;
-        bf.dump.fs[(int64_t)(2 * (sc.s - 1) + 1) * NN + v.no + j] = f.sr;
-      }
+      fsl[c] = f.sl;
+      fsr[c] = f.sr;
     }
   }
   lds_sync();
@@ -400,6 +400,21 @@ __device__ __forceinline__ StageRes stage_compute(const Bufs& bf, const Consts& 
   StageRes res;
   res.alpha = rv[0];
   res.maxJ = rv[1];
+  res.akey = 0.0;
+  if (bf.dump.akey) {
+    // first face trace of the tile (left trace first) whose speed is the tile's alpha
+    double kmin = 1e300;
+#pragma unroll
+    for (int c = CPT - 1; c >= 0; --c) {
+      const double j2 = 2.0 * (double)(c0 - 1 + t + c * B);
+      if (fsr[c] == rv[0]) kmin = j2 + 1.0;
+      if (fsl[c] == rv[0]) kmin = j2;
+    }
+    double kv[1] = {kmin};
+    const int kop[1] = {1};
+    block_reduce<B, 1>(kv, kop, sm.red);
+    res.akey = kv[0];
+  }
   res.ncls0 = 0u; res.ncls1 = 0u; res.ncls2 = 0u; res.nlim = 0u; res.nneg = 0u;
   unsigned sta = 0u;
 #pragma unroll

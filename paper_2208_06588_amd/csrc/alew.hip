@@ -32,6 +32,8 @@ struct Tile {
   int32_t inst;
   int32_t rec;  // index of the tile's result record (stage or plain table)
   int64_t c0;
+  int64_t co;   // cell offset of the instance
+  int64_t n;    // cells of the instance
 };
 
 // Start of a call: eta = h + b, reductions for the first step, shape bound of
@@ -110,12 +112,27 @@ __device__ __forceinline__ void publish_stage(const Bufs& bf, int rec, const Sta
   d[8] = r.akey;
 }
 
+// Stage s of one tile; par is the parity of the step (x^n in xa or xb).
 template <int B, int CPT>
 __global__ __launch_bounds__(B) void k_stage(Bufs bf, Consts cs, const Tile* __restrict__ tiles,
-                                             int s) {
+                                             int s, int par) {
   __shared__ SmemStage<B, CPT> sm;
   const Tile tl = tiles[blockIdx.x];
   Inst& I = bf.inst[tl.inst];
+  if (tile_inner<B * CPT>(tl.n, tl.c0)) {
+    View v;
+    v.n = tl.n;
+    v.co = tl.co;
+    v.no = tl.co + tl.inst;
+    v.x = (par ? bf.xb : bf.xa) + v.no;
+    v.xnew = (par ? bf.xa : bf.xb) + v.no;
+    StageRes r;
+    const bool on =
+        (s == 1) ? stage_tile_direct<B, CPT, true>(bf, cs, v, tl.inst, s, par, tl.c0, sm, r)
+                 : stage_tile_direct<B, CPT, false>(bf, cs, v, tl.inst, s, par, tl.c0, sm, r);
+    if (on && threadIdx.x == 0) publish_stage(bf, tl.rec, r);
+    return;
+  }
   if (!I.active) return;
   View v = make_view(bf, tl.inst, I);
   const StageScal sc = stage_scal(I, s);
@@ -636,13 +653,14 @@ alew_status build_tiles(alew_ctx* c, const int64_t* cell_off, int64_t ninst, int
     sfirst[i] = (int64_t)ts.size();
     pfirst[i] = (int64_t)tp.size();
     for (int64_t c0 = 0; c0 < n; c0 += TB - 2) {
-      const Tile tl{(int32_t)i, (int32_t)ts.size(), c0};
+      const Tile tl{(int32_t)i, (int32_t)ts.size(), c0, off[i], n};
       ts.push_back(tl);
       // same test as tile_inner() on the device
       const bool inner = c0 >= 3 && c0 + TB < n && n < (int64_t(1) << 28);
       (inner ? tin : te).push_back(tl);
     }
-    for (int64_t c0 = 0; c0 <= n; c0 += B) tp.push_back(Tile{(int32_t)i, (int32_t)tp.size(), c0});
+    for (int64_t c0 = 0; c0 <= n; c0 += B)
+      tp.push_back(Tile{(int32_t)i, (int32_t)tp.size(), c0, off[i], n});
   }
   sfirst[ninst] = (int64_t)ts.size();
   pfirst[ninst] = (int64_t)tp.size();
@@ -750,7 +768,8 @@ void kt_end(alew_ctx* c, hipStream_t st, int k) {
 }
 
 template <int B, int CPT>
-void launch_step_seq(alew_ctx* c, const Bufs& bf, const Consts& cs, hipStream_t st) {
+void launch_step_seq(alew_ctx* c, const Bufs& bf, const Consts& cs, hipStream_t st, int64_t step) {
+  const int par = (int)(step & 1);
   const dim3 gs((unsigned)c->n_tiles_stage), gp((unsigned)c->n_tiles_plain);
   const bool pipe = CPT == 1 && c->launch.prefetch == 1 && c->n_tiles_inner > 0;
   for (int s = 1; s <= 3; ++s) {
@@ -758,11 +777,11 @@ void launch_step_seq(alew_ctx* c, const Bufs& bf, const Consts& cs, hipStream_t 
     if (pipe) {
       if (c->n_tiles_edge > 0)
         hipLaunchKernelGGL((k_stage<B, 1>), dim3((unsigned)c->n_tiles_edge), dim3(B), 0, st, bf,
-                           cs, c->tiles_edge_d, s);
+                           cs, c->tiles_edge_d, s, par);
       hipLaunchKernelGGL(k_stage_pipe<B>, dim3((unsigned)pipe_grid<B>(c)), dim3(B), 0, st, bf, cs,
                          c->tiles_inner_d, c->n_tiles_inner, s);
     } else {
-      hipLaunchKernelGGL((k_stage<B, CPT>), gs, dim3(B), 0, st, bf, cs, c->tiles_stage_d, s);
+      hipLaunchKernelGGL((k_stage<B, CPT>), gs, dim3(B), 0, st, bf, cs, c->tiles_stage_d, s, par);
     }
     kt_end(c, st, kt);
     hipLaunchKernelGGL(k_after_stage, dim3((unsigned)((bf.ninst + 3) / 4)), dim3(256), 0, st, bf, s);
@@ -803,8 +822,9 @@ alew_status run_stage_engine(alew_ctx* c, const Bufs& bf, const Consts& cs, int6
       if (c->gexec) { (void)hipGraphExecDestroy(c->gexec); c->gexec = nullptr; }
       if (c->graph) { (void)hipGraphDestroy(c->graph); c->graph = nullptr; }
       HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-      launch_step_seq<B, CPT>(c, bf, cs, c->cap_stream);
-      launch_step_seq<B, CPT>(c, bf, cs, c->cap_stream);
+      // the graph starts at an even step and holds two
+      launch_step_seq<B, CPT>(c, bf, cs, c->cap_stream, 0);
+      launch_step_seq<B, CPT>(c, bf, cs, c->cap_stream, 1);
       HIPCHK(hipStreamEndCapture(c->cap_stream, &c->graph));
       HIPCHK(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
       c->gkey = key;
@@ -819,7 +839,7 @@ alew_status run_stage_engine(alew_ctx* c, const Bufs& bf, const Consts& cs, int6
         HIPCHK(hipGraphLaunch(c->gexec, c->stream));
         it += 2;
       } else {
-        launch_step_seq<B, CPT>(c, bf, cs, c->stream);
+        launch_step_seq<B, CPT>(c, bf, cs, c->stream, it);
         it += 1;
       }
       c->last_launches += 1;
@@ -885,6 +905,7 @@ alew_status map_status(int bits) {
   if (bits & SB_NONFINITE) return ALEW_E_NONFINITE;
   if (bits & SB_NEGDEPTH) return ALEW_E_NEGDEPTH;
   if (bits & SB_NEGWEIGHT) return ALEW_E_NEGWEIGHT;
+  if (bits & SB_SEQUENCE) return ALEW_E_UNSUPPORTED;  // instances of a batch out of step
   return ALEW_OK;
 }
 
@@ -1270,9 +1291,9 @@ alew_status alew_adjoint(alew_ctx* c, const alew_params* p, int64_t ninst,
         hipLaunchKernelGGL(k_seed_scal, dim3(1), dim3(1024), 0, st, bf, step_dump(0).scal);
       Bufs bd = bf;
       bd.dump = step_dump(k - klast);
-      launch_step_seq<256, 1>(c, bd, cs, st);
+      launch_step_seq<256, 1>(c, bd, cs, st, k);
     } else {
-      launch_step_seq<256, 1>(c, bf, cs, st);
+      launch_step_seq<256, 1>(c, bf, cs, st, k);
     }
   }
   HIPCHK(hipGetLastError());
@@ -1321,7 +1342,7 @@ alew_status alew_adjoint(alew_ctx* c, const alew_params* p, int64_t ninst,
       for (int64_t k = k0; k < k1; ++k) {
         Bufs bd = bf;
         bd.dump = step_dump(k - k0);
-        launch_step_seq<256, 1>(c, bd, cs, st);
+        launch_step_seq<256, 1>(c, bd, cs, st, k);
       }
     }
     for (int64_t k = k1 - 1; k >= k0; --k) {

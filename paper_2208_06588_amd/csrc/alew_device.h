@@ -22,7 +22,7 @@ enum { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1, BC_REFLECTIVE = 2 };
 enum { MESH_GIVEN = 0, MESH_SINE = 1, MESH_PAPER = 2, MESH_FLUID = 3 };
 enum { F_BETA_LOCAL = 1, F_BETA_FROM_H = 2 };
 // status bits (combined per instance; mapped to alew_status on the host)
-enum { SB_MESH = 1, SB_NEGDEPTH = 2, SB_NONFINITE = 4, SB_NEGWEIGHT = 8 };
+enum { SB_MESH = 1, SB_NEGDEPTH = 2, SB_NONFINITE = 4, SB_NEGWEIGHT = 8, SB_SEQUENCE = 16 };
 
 struct Consts {
   double g, cfl, weno_eps, pp_eps;

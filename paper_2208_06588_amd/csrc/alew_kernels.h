@@ -159,29 +159,64 @@ __device__ __forceinline__ void put_slot(const StageScal& sc, int i, double ms, 
   if (real) sm.wn[i] = w0;
 }
 
-// Slot of a tile whose stencil cells are all real cells (no ghosts).
-template <class SM>
-__device__ __forceinline__ void load_slot_inner(const Bufs& bf, const View& v, const StageScal& sc,
-                                                unsigned k, int i, SM& sm, int& st) {
-  const unsigned o = k * 8u;
-  const double* xs = v.x;
+// Raw values of one ghost-free stencil slot: x^n and w at its two nodes, and
+// q^n (first stage) or P, D of the previous stage and q^n (later stages).
+struct RawSlot {
+  double x0, x1, w0, w1, a0, a1, a2, d0, d1, d2, q0, q1, q2;
+};
+
+// Issue the loads of the ghost-free slot at byte offset o of the instance.
+// P, D are the previous stage's rows (unused in the first stage).
+template <bool FIRST>
+__device__ __forceinline__ RawSlot raw_inner(const Bufs& bf, const View& v, const double* P,
+                                             const double* D, unsigned o) {
+  RawSlot r;
   const double* ws = bf.w + v.no;
-  const double x0 = ldo(xs, o), x1 = ldo(xs, o + 8u);
-  const double w0 = ldo(ws, o), w1 = ldo(ws, o + 8u);
+  r.x0 = ldo(v.x, o); r.x1 = ldo(v.x, o + 8u);
+  r.w0 = ldo(ws, o); r.w1 = ldo(ws, o + 8u);
   const double* eta = bf.eta + v.co;
   const double* hu = bf.m + v.co;
   const double* bb = bf.b + v.co;
-  if (sc.s == 1) {
-    put_slot(sc, i, 1.0, true, x0, x1, w0, w1, ldo(eta, o), ldo(hu, o), ldo(bb, o), 0.0, 0.0, 0.0,
-             0.0, 0.0, 0.0, sm, st);
+  if (FIRST) {
+    r.a0 = ldo(eta, o); r.a1 = ldo(hu, o); r.a2 = ldo(bb, o);
+    r.d0 = 0.0; r.d1 = 0.0; r.d2 = 0.0;
+    r.q0 = 0.0; r.q1 = 0.0; r.q2 = 0.0;
   } else {
-    const double* P = ((sc.s == 2) ? bf.P0 : bf.P1) + v.co;
-    const double* D = ((sc.s == 2) ? bf.D0 : bf.D1) + v.co;
     const int64_t S = bf.S;
-    put_slot(sc, i, 1.0, true, x0, x1, w0, w1, ldo(P, o), ldo(P + S, o), ldo(P + 2 * S, o),
-             ldo(D, o), ldo(D + S, o), ldo(D + 2 * S, o), ldo(eta, o), ldo(hu, o), ldo(bb, o), sm,
-             st);
+    r.a0 = ldo(P, o); r.a1 = ldo(P + S, o); r.a2 = ldo(P + 2 * S, o);
+    r.d0 = ldo(D, o); r.d1 = ldo(D + S, o); r.d2 = ldo(D + 2 * S, o);
+    r.q0 = ldo(eta, o); r.q1 = ldo(hu, o); r.q2 = ldo(bb, o);
   }
+  return r;
+}
+
+template <class SM>
+__device__ __forceinline__ void put_raw(const StageScal& sc, int i, const RawSlot& r, SM& sm,
+                                        int& st) {
+  put_slot(sc, i, 1.0, true, r.x0, r.x1, r.w0, r.w1, r.a0, r.a1, r.a2, r.d0, r.d1, r.d2, r.q0,
+           r.q1, r.q2, sm, st);
+}
+
+// Ghost-free tile: every load of the thread's slots (and of the four slots
+// past the last thread) is issued before the first of them is used, so a
+// tile waits for memory once.
+template <int B, int CPT, bool FIRST, class SM>
+__device__ __forceinline__ void load_tile_inner(const Bufs& bf, const View& v, const StageScal& sc,
+                                                int64_t c0, SM& sm, int& st) {
+  constexpr int TB = B * CPT;
+  const int t = threadIdx.x;
+  const double* P = ((sc.s == 2) ? bf.P0 : bf.P1) + v.co;
+  const double* D = ((sc.s == 2) ? bf.D0 : bf.D1) + v.co;
+  RawSlot r[CPT];
+#pragma unroll
+  for (int c = 0; c < CPT; ++c)
+    r[c] = raw_inner<FIRST>(bf, v, P, D, (unsigned)(c0 - 3 + t + c * B) * 8u);
+  const bool ext = t < 4;
+  RawSlot rx;
+  if (ext) rx = raw_inner<FIRST>(bf, v, P, D, (unsigned)(c0 - 3 + TB + t) * 8u);
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) put_raw(sc, t + c * B, r[c], sm, st);
+  if (ext) put_raw(sc, TB + t, rx, sm, st);
 }
 
 // Slot of a tile that touches an end of the instance: ghosts mapped by the
@@ -217,8 +252,8 @@ __device__ __forceinline__ void load_slot_edge(const Bufs& bf, const Consts& cs,
 
 // True if every stencil slot of the tile at c0 is a real cell.
 template <int TB>
-__device__ __forceinline__ bool tile_inner(const View& v, int64_t c0) {
-  return c0 >= 3 && c0 + TB < v.n && v.n < (int64_t(1) << 28);
+__device__ __forceinline__ bool tile_inner(int64_t n, int64_t c0) {
+  return c0 >= 3 && c0 + TB < n && n < (int64_t(1) << 28);
 }
 
 // Phase 1 of a stage tile: stencil data for cells c0-3 .. c0+TB in LDS.
@@ -228,11 +263,11 @@ __device__ __forceinline__ void stage_load(const Bufs& bf, const Consts& cs, con
                                            SmemStage<B, CPT>& sm, int& st) {
   constexpr int TB = B * CPT;
   const int t = threadIdx.x;
-  if (tile_inner<TB>(v, c0)) {
-#pragma unroll
-    for (int c = 0; c < CPT; ++c)
-      load_slot_inner(bf, v, sc, (unsigned)(c0 - 3 + t + c * B), t + c * B, sm, st);
-    if (t < 4) load_slot_inner(bf, v, sc, (unsigned)(c0 - 3 + TB + t), TB + t, sm, st);
+  if (tile_inner<TB>(v.n, c0)) {
+    if (sc.s == 1)
+      load_tile_inner<B, CPT, true>(bf, v, sc, c0, sm, st);
+    else
+      load_tile_inner<B, CPT, false>(bf, v, sc, c0, sm, st);
   } else {
 #pragma unroll
     for (int c = 0; c < CPT; ++c) load_slot_edge(bf, cs, v, sc, c0 - 3 + t + c * B, t + c * B, sm, st);
@@ -388,7 +423,7 @@ __device__ __forceinline__ StageRes stage_compute(const Bufs& bf, const Consts& 
   // per-wave counts and status bits (wave-uniform), plain LDS stores
   unsigned stw = 0u;
 #pragma unroll
-  for (int bit = 1; bit <= 8; bit <<= 1)
+  for (int bit = 1; bit <= SB_SEQUENCE; bit <<= 1)
     if (__ballot((st & bit) != 0)) stw |= (unsigned)bit;
   if (lane == 0) {
     sm.cntw[wv][0] = n0; sm.cntw[wv][1] = n1; sm.cntw[wv][2] = n2;
@@ -437,6 +472,51 @@ __device__ __forceinline__ StageRes stage_tile(const Bufs& bf, const Consts& cs,
   stage_load<B, CPT>(bf, cs, v, sc, c0, sm, st);
   lds_sync();
   return stage_compute<B, CPT>(bf, cs, v, sc, c0, sm, cls_inst, st, (int)threadIdx.x);
+}
+
+// Stage tile of a ghost-free tile of the stage-launch engine, whose instance
+// offsets come with the tile: the loads of the tile are issued before the
+// instance record is read, so the two latencies overlap.  par is the parity of
+// the step, the same for every active instance of a batch (all of them start
+// together and step together).  Returns false for an inactive instance.
+// The instance scalars are read through the constant address space, so that
+// they are scalar loads whose wait does not wait for the tile's vector loads:
+// no instance record is written while a stage kernel runs.
+template <int B, int CPT, bool FIRST>
+__device__ __forceinline__ bool stage_tile_direct(const Bufs& bf, const Consts& cs, const View& v,
+                                                  int inst, int s, int par, int64_t c0,
+                                                  SmemStage<B, CPT>& sm, StageRes& res) {
+  constexpr int TB = B * CPT;
+  const int t = threadIdx.x;
+  const double* P = ((s == 2) ? bf.P0 : bf.P1) + v.co;
+  const double* D = ((s == 2) ? bf.D0 : bf.D1) + v.co;
+  RawSlot r[CPT];
+#pragma unroll
+  for (int c = 0; c < CPT; ++c)
+    r[c] = raw_inner<FIRST>(bf, v, P, D, (unsigned)(c0 - 3 + t + c * B) * 8u);
+  const bool ext = t < 4;
+  RawSlot rx;
+  if (ext) rx = raw_inner<FIRST>(bf, v, P, D, (unsigned)(c0 - 3 + TB + t) * 8u);
+  typedef const __attribute__((address_space(4))) Inst* cinst;
+  const cinst I = (cinst)bf.inst + inst;
+  if (!I->active) return false;
+  // an instance out of step with the batch would have read the wrong nodes
+  int st = ((int)(I->steps & 1) != par) ? SB_SEQUENCE : 0;
+  StageScal sc;
+  sc.s = s;
+  sc.dt = I->dt;
+  sc.as = s == 1 ? 0.0 : (s == 2 ? 0.75 : 1.0 / 3.0);
+  sc.bs = s == 1 ? 1.0 : (s == 2 ? 0.25 : 2.0 / 3.0);
+  sc.cprev = s == 1 ? 0.0 : (s == 2 ? 1.0 : 0.25) * sc.dt * I->alpha[s == 1 ? 0 : s - 2];
+  sc.dx = I->dx[s - 1];
+  sc.wsc = I->wscale;
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) put_raw(sc, t + c * B, r[c], sm, st);
+  if (ext) put_raw(sc, TB + t, rx, sm, st);
+  lds_sync();
+  uint8_t* cl = bf.cls ? bf.cls + (int64_t)(s - 1) * bf.S + v.co : nullptr;
+  res = stage_compute<B, CPT>(bf, cs, v, sc, c0, sm, cl, st, t);
+  return true;
 }
 
 // ----------------------------------------------------------------------------

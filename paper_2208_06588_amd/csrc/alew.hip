@@ -118,26 +118,29 @@ __global__ __launch_bounds__(B) void k_stage(Bufs bf, Consts cs, const Tile* __r
                                              int s, int par) {
   __shared__ SmemStage<B, CPT> sm;
   const Tile tl = tiles[blockIdx.x];
-  Inst& I = bf.inst[tl.inst];
+  View v;
+  StageScal sc;
+  int st = 0;
   if (tile_inner<B * CPT>(tl.n, tl.c0)) {
-    View v;
     v.n = tl.n;
     v.co = tl.co;
     v.no = tl.co + tl.inst;
     v.x = (par ? bf.xb : bf.xa) + v.no;
     v.xnew = (par ? bf.xa : bf.xb) + v.no;
-    StageRes r;
     const bool on =
-        (s == 1) ? stage_tile_direct<B, CPT, true>(bf, cs, v, tl.inst, s, par, tl.c0, sm, r)
-                 : stage_tile_direct<B, CPT, false>(bf, cs, v, tl.inst, s, par, tl.c0, sm, r);
-    if (on && threadIdx.x == 0) publish_stage(bf, tl.rec, r);
-    return;
+        (s == 1) ? stage_load_direct<B, CPT, true>(bf, v, tl.inst, s, par, tl.c0, sm, sc, st)
+                 : stage_load_direct<B, CPT, false>(bf, v, tl.inst, s, par, tl.c0, sm, sc, st);
+    if (!on) return;
+  } else {
+    const Inst& I = bf.inst[tl.inst];
+    if (!I.active) return;
+    v = make_view(bf, tl.inst, I);
+    sc = stage_scal(I, s);
+    load_tile_edge<B, CPT>(bf, cs, v, sc, tl.c0, sm, st);
   }
-  if (!I.active) return;
-  View v = make_view(bf, tl.inst, I);
-  const StageScal sc = stage_scal(I, s);
+  lds_sync();
   uint8_t* cl = bf.cls ? bf.cls + (int64_t)(s - 1) * bf.S + v.co : nullptr;
-  StageRes r = stage_tile<B, CPT>(bf, cs, v, sc, tl.c0, sm, cl);
+  const StageRes r = stage_compute<B, CPT>(bf, cs, v, sc, tl.c0, sm, cl, st, (int)threadIdx.x);
   if (threadIdx.x == 0) publish_stage(bf, tl.rec, r);
 }
 

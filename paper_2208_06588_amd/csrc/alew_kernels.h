@@ -256,6 +256,18 @@ __device__ __forceinline__ bool tile_inner(int64_t n, int64_t c0) {
   return c0 >= 3 && c0 + TB < n && n < (int64_t(1) << 28);
 }
 
+// Tile that touches an end of the instance, slot by slot.
+template <int B, int CPT>
+__device__ __forceinline__ void load_tile_edge(const Bufs& bf, const Consts& cs, const View& v,
+                                               const StageScal& sc, int64_t c0,
+                                               SmemStage<B, CPT>& sm, int& st) {
+  constexpr int TB = B * CPT;
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) load_slot_edge(bf, cs, v, sc, c0 - 3 + t + c * B, t + c * B, sm, st);
+  if (t < 4) load_slot_edge(bf, cs, v, sc, c0 - 3 + TB + t, TB + t, sm, st);
+}
+
 // Phase 1 of a stage tile: stencil data for cells c0-3 .. c0+TB in LDS.
 template <int B, int CPT>
 __device__ __forceinline__ void stage_load(const Bufs& bf, const Consts& cs, const View& v,
@@ -269,9 +281,7 @@ __device__ __forceinline__ void stage_load(const Bufs& bf, const Consts& cs, con
     else
       load_tile_inner<B, CPT, false>(bf, v, sc, c0, sm, st);
   } else {
-#pragma unroll
-    for (int c = 0; c < CPT; ++c) load_slot_edge(bf, cs, v, sc, c0 - 3 + t + c * B, t + c * B, sm, st);
-    if (t < 4) load_slot_edge(bf, cs, v, sc, c0 - 3 + TB + t, TB + t, sm, st);
+    load_tile_edge<B, CPT>(bf, cs, v, sc, c0, sm, st);
   }
 }
 
@@ -474,18 +484,18 @@ __device__ __forceinline__ StageRes stage_tile(const Bufs& bf, const Consts& cs,
   return stage_compute<B, CPT>(bf, cs, v, sc, c0, sm, cls_inst, st, (int)threadIdx.x);
 }
 
-// Stage tile of a ghost-free tile of the stage-launch engine, whose instance
+// Phase 1 of a ghost-free tile of the stage-launch engine, whose instance
 // offsets come with the tile: the loads of the tile are issued before the
-// instance record is read, so the two latencies overlap.  par is the parity of
-// the step, the same for every active instance of a batch (all of them start
-// together and step together).  Returns false for an inactive instance.
-// The instance scalars are read through the constant address space, so that
-// they are scalar loads whose wait does not wait for the tile's vector loads:
-// no instance record is written while a stage kernel runs.
+// instance record is read, so the two latencies overlap.  The instance
+// scalars are read through the constant address space (scalar loads whose
+// wait does not wait for the tile's vector loads): no instance record is
+// written while a stage kernel runs.  par is the parity of the step, the same
+// for every active instance of a batch (all of them start together and step
+// together).  Returns false for an inactive instance.
 template <int B, int CPT, bool FIRST>
-__device__ __forceinline__ bool stage_tile_direct(const Bufs& bf, const Consts& cs, const View& v,
-                                                  int inst, int s, int par, int64_t c0,
-                                                  SmemStage<B, CPT>& sm, StageRes& res) {
+__device__ __forceinline__ bool stage_load_direct(const Bufs& bf, const View& v, int inst, int s,
+                                                  int par, int64_t c0, SmemStage<B, CPT>& sm,
+                                                  StageScal& sc, int& st) {
   constexpr int TB = B * CPT;
   const int t = threadIdx.x;
   const double* P = ((s == 2) ? bf.P0 : bf.P1) + v.co;
@@ -501,8 +511,7 @@ __device__ __forceinline__ bool stage_tile_direct(const Bufs& bf, const Consts& 
   const cinst I = (cinst)bf.inst + inst;
   if (!I->active) return false;
   // an instance out of step with the batch would have read the wrong nodes
-  int st = ((int)(I->steps & 1) != par) ? SB_SEQUENCE : 0;
-  StageScal sc;
+  if ((int)(I->steps & 1) != par) st |= SB_SEQUENCE;
   sc.s = s;
   sc.dt = I->dt;
   sc.as = s == 1 ? 0.0 : (s == 2 ? 0.75 : 1.0 / 3.0);
@@ -513,9 +522,6 @@ __device__ __forceinline__ bool stage_tile_direct(const Bufs& bf, const Consts& 
 #pragma unroll
   for (int c = 0; c < CPT; ++c) put_raw(sc, t + c * B, r[c], sm, st);
   if (ext) put_raw(sc, TB + t, rx, sm, st);
-  lds_sync();
-  uint8_t* cl = bf.cls ? bf.cls + (int64_t)(s - 1) * bf.S + v.co : nullptr;
-  res = stage_compute<B, CPT>(bf, cs, v, sc, c0, sm, cl, st, t);
   return true;
 }
 

@@ -119,7 +119,6 @@ __global__ __launch_bounds__(B) void k_stage(Bufs bf, Consts cs, const Tile* __r
   __shared__ SmemStage<B, CPT> sm;
   const Tile tl = tiles[blockIdx.x];
   View v;
-  StageScal sc;
   int st = 0;
   if (tile_inner<B * CPT>(tl.n, tl.c0)) {
     v.n = tl.n;
@@ -127,17 +126,17 @@ __global__ __launch_bounds__(B) void k_stage(Bufs bf, Consts cs, const Tile* __r
     v.no = tl.co + tl.inst;
     v.x = (par ? bf.xb : bf.xa) + v.no;
     v.xnew = (par ? bf.xa : bf.xb) + v.no;
-    const bool on =
-        (s == 1) ? stage_load_direct<B, CPT, true>(bf, v, tl.inst, s, par, tl.c0, sm, sc, st)
-                 : stage_load_direct<B, CPT, false>(bf, v, tl.inst, s, par, tl.c0, sm, sc, st);
+    const bool on = (s == 1) ? stage_load_direct<B, CPT, true>(bf, v, tl.inst, s, par, tl.c0, sm, st)
+                             : stage_load_direct<B, CPT, false>(bf, v, tl.inst, s, par, tl.c0, sm, st);
     if (!on) return;
   } else {
     const Inst& I = bf.inst[tl.inst];
     if (!I.active) return;
     v = make_view(bf, tl.inst, I);
-    sc = stage_scal(I, s);
-    load_tile_edge<B, CPT>(bf, cs, v, sc, tl.c0, sm, st);
+    load_tile_edge<B, CPT>(bf, cs, v, stage_scal(I, s), tl.c0, sm, st);
   }
+  // read again after the two paths join, so that they stay scalar
+  const StageScal sc = stage_scal_const(bf.inst, tl.inst, s);
   lds_sync();
   uint8_t* cl = bf.cls ? bf.cls + (int64_t)(s - 1) * bf.S + v.co : nullptr;
   const StageRes r = stage_compute<B, CPT>(bf, cs, v, sc, tl.c0, sm, cl, st, (int)threadIdx.x);

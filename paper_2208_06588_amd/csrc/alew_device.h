@@ -291,52 +291,30 @@ __device__ __forceinline__ void recon_cell(const double* __restrict__ v5,  // in
   const double betaA = (beta[0] + beta[1] + beta[2]) * (1.0 / 3.0);
   const double gam = tau * frcp(betaA + eps);
   const int cls = (gam <= 0.5) ? 0 : ((gam >= 1.0) ? 2 : 1);
-  double K[3];
-  if (cls != 0) {
+  // Steps 3-4 at the 4 points: h, m, b at the end points (traces); at every
+  // point the term of the interior Gauss-Lobatto quadrature of
+  // (eta - etabar) b_x, weights (1,5,5,1)/12, summed in point order
+  const double wgl[4] = {1.0 / 12.0, 5.0 / 12.0, 5.0 / 12.0, 1.0 / 12.0};
+  double ri = 0.0;
+  // linear weights d_r at point mu
+  auto lin_weights = [&](int mu, double* d) {
+    double e3[3], e4[3];
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
-      const double z = tau * frcp(beta[r] + eps);
-      K[r] = 1.0 + z * z;
+      e3[r] = B3[r] * yv[mu] + C3[r] * p2v[mu] - f3v[mu];
+      e4[r] = B4[r] * yv[mu] + C4[r] * p2v[mu] - f4v[mu];
     }
-  }
-  const double Mg = 2.0 * gam - 1.0;
-  // Steps 3-4 at the 4 points; values h, m, b (traces) and eta, b_x (source)
-  double hv[4], mv[4], bv[4], bxv[4];
-#pragma unroll
-  for (int mu = 0; mu < 4; ++mu) {
-    double d[3];
-    {
-      double e3[3], e4[3];
-#pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        e3[r] = B3[r] * yv[mu] + C3[r] * p2v[mu] - f3v[mu];
-        e4[r] = B4[r] * yv[mu] + C4[r] * p2v[mu] - f4v[mu];
-      }
-      const double x0 = e3[1] * e4[2] - e3[2] * e4[1];
-      const double x1 = e3[2] * e4[0] - e3[0] * e4[2];
-      const double x2 = e3[0] * e4[1] - e3[1] * e4[0];
-      const double is = frcp(x0 + x1 + x2);
-      d[0] = x0 * is;
-      d[1] = x1 * is;
-      d[2] = x2 * is;
-      sgn |= hiword(d[0]) | hiword(d[1]) | hiword(d[2]);
-    }
-    double ph[3];
-    if (cls == 0) {
-      ph[0] = d[0];
-      ph[1] = d[1];
-      ph[2] = d[2];
-    } else {
-      const double a0 = d[0] * K[0], a1 = d[1] * K[1], a2 = d[2] * K[2];
-      const double ia = frcp(a0 + a1 + a2);
-      ph[0] = a0 * ia;
-      ph[1] = a1 * ia;
-      ph[2] = a2 * ia;
-      if (cls == 1) {
-#pragma unroll
-        for (int r = 0; r < 3; ++r) ph[r] = Mg * ph[r] + (1.0 - Mg) * d[r];
-      }
-    }
+    const double x0 = e3[1] * e4[2] - e3[2] * e4[1];
+    const double x1 = e3[2] * e4[0] - e3[0] * e4[2];
+    const double x2 = e3[0] * e4[1] - e3[1] * e4[0];
+    const double is = frcp(x0 + x1 + x2);
+    d[0] = x0 * is;
+    d[1] = x1 * is;
+    d[2] = x2 * is;
+    sgn |= hiword(d[0]) | hiword(d[1]) | hiword(d[2]);
+  };
+  // reconstructed values at point mu with the weights ph_r
+  auto at_point = [&](int mu, const double* ph) {
     const double y = yv[mu], p2 = p2v[mu];
     double sBh = 0, sCh = 0, sBm = 0, sCm = 0, sBb = 0, sCb = 0;
 #pragma unroll
@@ -348,18 +326,45 @@ __device__ __forceinline__ void recon_cell(const double* __restrict__ v5,  // in
       sBb += ph[r] * Bb[r];
       sCb += ph[r] * Cb[r];
     }
-    hv[mu] = h5[2] + (sBh * y + sCh * p2);
-    mv[mu] = m5[2] + (sBm * y + sCm * p2);
-    bv[mu] = b5[2] + (sBb * y + sCb * p2);
-    bxv[mu] = (sBb + 2.0 * y * sCb) * iJ0;
-  }
-  o.hL = hv[0]; o.mL = mv[0]; o.bL = bv[0];
-  o.hR = hv[3]; o.mR = mv[3]; o.bR = bv[3];
-  // interior Gauss-Lobatto quadrature of (eta - etabar) b_x, weights (1,5,5,1)/12
-  const double wgl[4] = {1.0 / 12.0, 5.0 / 12.0, 5.0 / 12.0, 1.0 / 12.0};
-  double ri = 0.0;
+    const double hv = h5[2] + (sBh * y + sCh * p2);
+    const double bv = b5[2] + (sBb * y + sCb * p2);
+    const double bxv = (sBb + 2.0 * y * sCb) * iJ0;
+    ri += (wgl[mu] * J0) * (((hv + bv) - etabar) * bxv);
+    if (mu == 0) { o.hL = hv; o.mL = m5[2] + (sBm * y + sCm * p2); o.bL = bv; }
+    if (mu == 3) { o.hR = hv; o.mR = m5[2] + (sBm * y + sCm * p2); o.bR = bv; }
+  };
+  // one branch per cell (not per point): a smooth cell takes the linear weights
+  if (cls == 0) {
 #pragma unroll
-  for (int mu = 0; mu < 4; ++mu) ri += (wgl[mu] * J0) * (((hv[mu] + bv[mu]) - etabar) * bxv[mu]);
+    for (int mu = 0; mu < 4; ++mu) {
+      double d[3];
+      lin_weights(mu, d);
+      at_point(mu, d);
+    }
+  } else {
+    double K[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const double z = tau * frcp(beta[r] + eps);
+      K[r] = 1.0 + z * z;
+    }
+    const double Mg = 2.0 * gam - 1.0;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+      double d[3], ph[3];
+      lin_weights(mu, d);
+      const double a0 = d[0] * K[0], a1 = d[1] * K[1], a2 = d[2] * K[2];
+      const double ia = frcp(a0 + a1 + a2);
+      ph[0] = a0 * ia;
+      ph[1] = a1 * ia;
+      ph[2] = a2 * ia;
+      if (cls == 1) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) ph[r] = Mg * ph[r] + (1.0 - Mg) * d[r];
+      }
+      at_point(mu, ph);
+    }
+  }
   o.rint = ri;
   o.cls = cls;
   o.negw = (int)(sgn >> 31);

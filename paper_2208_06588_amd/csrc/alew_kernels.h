@@ -98,9 +98,11 @@ template <int B, int CPT>
 struct SmemStage {
   static constexpr int TB = B * CPT;
   static constexpr int NW = B / 64;
-  // Stencil slot i holds cell k = c0 - 3 + i (ghosts mapped).  The stencil
-  // arrays are dead once the traces are formed, so the face values reuse them.
-  union {
+  // Stencil slot i holds cell k = c0 - 3 + i (ghosts mapped).  The update
+  // reads the cell averages and widths again from the stencil arrays (fewer
+  // registers held through the reconstruction), so the face values have
+  // arrays of their own.
+  struct {
     struct {
       double e[TB + 4], m[TB + 4], b[TB + 4], J[TB + 4], iJ[TB + 4];
     } in;
@@ -311,18 +313,26 @@ __device__ __forceinline__ StageRes stage_compute(const Bufs& bf, const Consts& 
   // for the end faces); one cell after the other.  The left state of the face
   // at node j is the right trace of cell j-1: from the previous lane, or for
   // lane 0 through LDS after the barrier.
-  double ebar[CPT], mbar[CPT], bbar[CPT], Jj[CPT], rint[CPT];
+  double rint[CPT];
   double tl0[CPT], tl1[CPT], tl2[CPT], tp0[CPT], tp1[CPT], tp2[CPT];
   unsigned n0 = 0, n1 = 0, n2 = 0, nl = 0, nn = 0;
+  // tile-local bounds (work-group uniform): tile cell i is cell c0 - 1 + i, so
+  // it is a real cell or an end ghost for i <= iact, owned for 1 <= i <= iown;
+  // ighr is the tile index of the right ghost (cell n), if in the tile
+  const int64_t nrel = v.n - c0;
+  const int iact = (int)(nrel + 1 < TB ? nrel + 1 : TB);
+  const int iown = (int)(nrel < TB - 2 ? nrel : TB - 2);
+  const int ighr = (nrel + 1 < TB) ? (int)(nrel + 1) : -1;
+  const bool lghost = c0 == 0;
+  uint8_t* cls_tile = cls_inst ? cls_inst + c0 : nullptr;  // tile cell i at [i - 1]
 #pragma unroll
   for (int c = 0; c < CPT; ++c) {
     const int i = t + c * B;
-    const int64_t j = c0 - 1 + i;
-    const bool active = (j >= -1) && (j <= v.n);
-    const bool owned = (i >= 1) && (i <= TB - 2) && (j < v.n);
+    const bool active = i <= iact;
+    const bool owned = (i >= 1) && (i <= iown);
     int cls_owned = -1;
     bool lim_owned = false, neg_cell = false;
-    ebar[c] = 0.0; mbar[c] = 0.0; bbar[c] = 0.0; Jj[c] = 1.0; rint[c] = 0.0;
+    rint[c] = 0.0;
     double hR = 0.0, mR = 0.0, bR = 0.0;
     tl0[c] = 0.0; tl1[c] = 0.0; tl2[c] = 0.0;
     if (active) {
@@ -336,19 +346,19 @@ __device__ __forceinline__ StageRes stage_compute(const Bufs& bf, const Consts& 
         v5[k] = (cs.flags & F_BETA_FROM_H) ? h5[k] : se[k];
       }
       const double hbar = h5[2];
-      ebar[c] = se[2]; mbar[c] = sm.u.in.m[i + 2]; bbar[c] = sb[2]; Jj[c] = sm.u.in.J[i + 2];
-      const double Dx = (cs.flags & F_BETA_LOCAL) ? Jj[c] : sc.dx;
+      const double mbar = sm.u.in.m[i + 2];
+      const double Dx = (cs.flags & F_BETA_LOCAL) ? sm.u.in.J[i + 2] : sc.dx;
       recon_cell(v5, h5, sm.u.in.m + i, sb, sm.u.in.J + i, sm.u.in.iJ[i + 2], Dx, cs.weno_eps,
-                 ebar[c], o);
-      const int lim = limit_cell(hbar, mbar[c], cs.pp_eps, o);
+                 se[2], o);
+      const int lim = limit_cell(hbar, mbar, cs.pp_eps, o);
       rint[c] = o.rint;
       if (owned) {
         cls_owned = o.cls;
         lim_owned = lim != 0;
         if (hbar < -cs.pp_eps) st |= SB_NEGDEPTH;
-        if (cls_inst) cls_inst[j] = (uint8_t)o.cls;
+        if (cls_tile) cls_tile[i - 1] = (uint8_t)o.cls;
       }
-      if (o.negw && (owned || j == -1 || j == v.n)) { neg_cell = true; st |= SB_NEGWEIGHT; }
+      if (o.negw && (owned || (lghost && i == 0) || i == ighr)) { neg_cell = true; st |= SB_NEGWEIGHT; }
       tl0[c] = o.hL; tl1[c] = o.mL; tl2[c] = o.bL;
       hR = o.hR; mR = o.mR; bR = o.bR;
     }
@@ -372,9 +382,8 @@ __device__ __forceinline__ StageRes stage_compute(const Bufs& bf, const Consts& 
 #pragma unroll
   for (int c = 0; c < CPT; ++c) {
     const int i = t + c * B;
-    const int64_t j = c0 - 1 + i;
     fsl[c] = -1.0; fsr[c] = -1.0;
-    if (i >= 1 && j >= 0 && j <= v.n) {
+    if (i >= 1 && i <= iact) {
       if (lane == 0) {
         const int q = c * NW + wv - 1;
         tp0[c] = sm.xr[q][0]; tp1[c] = sm.xr[q][1]; tp2[c] = sm.xr[q][2];
@@ -391,39 +400,41 @@ __device__ __forceinline__ StageRes stage_compute(const Bufs& bf, const Consts& 
   lds_sync();
   // 4. owned cells: residual split, stage combination
   double maxJ = 0.0;
+  const int64_t gt = v.co + c0 - 1;  // global index of tile cell 0
+  const int64_t NS = bf.S;
+  double* Po = ((sc.s == 2) ? bf.P1 : bf.P0) + gt;
+  double* Do = ((sc.s == 2) ? bf.D1 : bf.D0) + gt;
 #pragma unroll
   for (int c = 0; c < CPT; ++c) {
     const int i = t + c * B;
-    const int64_t j = c0 - 1 + i;
-    if ((i >= 1) && (i <= TB - 2) && (j < v.n)) {
+    if ((i >= 1) && (i <= iown)) {
       const double g = cs.g;
       const double(*fl)[TB] = sm.u.fl;
+      const double ebar = sm.u.in.e[i + 2], mbar = sm.u.in.m[i + 2], bbar = sm.u.in.b[i + 2];
+      const double Jj = sm.u.in.J[i + 2];
       const double Ae = -(fl[0][i + 1] - fl[0][i]);
-      const double S = 0.5 * g * (fl[7][i + 1] - fl[7][i]) - g * ebar[c] * (fl[6][i + 1] - fl[6][i]) - g * rint[c];
+      const double S = 0.5 * g * (fl[7][i + 1] - fl[7][i]) - g * ebar * (fl[6][i + 1] - fl[6][i]) - g * rint[c];
       const double Am = -(fl[1][i + 1] - fl[1][i]) + S;
       const double Ab = -(fl[2][i + 1] - fl[2][i]);
       const double De = 0.5 * (fl[3][i + 1] - fl[3][i]);
       const double Dm = 0.5 * (fl[4][i + 1] - fl[4][i]);
       const double Db = 0.5 * (fl[5][i + 1] - fl[5][i]);
-      const int64_t gi = v.co + j;
       double Pe, Pm, Pb;
       if (sc.s == 1) {
-        Pe = Jj[c] * ebar[c] + sc.dt * Ae;
-        Pm = Jj[c] * mbar[c] + sc.dt * Am;
-        Pb = Jj[c] * bbar[c] + sc.dt * Ab;
+        Pe = Jj * ebar + sc.dt * Ae;
+        Pm = Jj * mbar + sc.dt * Am;
+        Pb = Jj * bbar + sc.dt * Ab;
       } else {
-        Pe = sm.qn[0][i + 2] + sc.bs * (Jj[c] * ebar[c] + sc.dt * Ae);
-        Pm = sm.qn[1][i + 2] + sc.bs * (Jj[c] * mbar[c] + sc.dt * Am);
-        Pb = sm.qn[2][i + 2] + sc.bs * (Jj[c] * bbar[c] + sc.dt * Ab);
+        Pe = sm.qn[0][i + 2] + sc.bs * (Jj * ebar + sc.dt * Ae);
+        Pm = sm.qn[1][i + 2] + sc.bs * (Jj * mbar + sc.dt * Am);
+        Pb = sm.qn[2][i + 2] + sc.bs * (Jj * bbar + sc.dt * Ab);
       }
-      double* Po = (sc.s == 2) ? bf.P1 : bf.P0;
-      double* Do = (sc.s == 2) ? bf.D1 : bf.D0;
-      Po[gi] = Pe; Po[bf.S + gi] = Pm; Po[2 * bf.S + gi] = Pb;
-      Do[gi] = De; Do[bf.S + gi] = Dm; Do[2 * bf.S + gi] = Db;
+      Po[i] = Pe; (Po + NS)[i] = Pm; (Po + 2 * NS)[i] = Pb;
+      Do[i] = De; (Do + NS)[i] = Dm; (Do + 2 * NS)[i] = Db;
       if (bf.dump.q) {
-        const int64_t o = (int64_t)(3 * (sc.s - 1)) * bf.S + gi;
-        bf.dump.q[o] = ebar[c]; bf.dump.q[o + bf.S] = mbar[c]; bf.dump.q[o + 2 * bf.S] = bbar[c];
-        bf.dump.D[o] = De; bf.dump.D[o + bf.S] = Dm; bf.dump.D[o + 2 * bf.S] = Db;
+        const int64_t o = (int64_t)(3 * (sc.s - 1)) * NS + gt + i;
+        bf.dump.q[o] = ebar; bf.dump.q[o + NS] = mbar; bf.dump.q[o + 2 * NS] = bbar;
+        bf.dump.D[o] = De; bf.dump.D[o + NS] = Dm; bf.dump.D[o + 2 * NS] = Db;
       }
       const double Jnext = sm.Jx[i + 2];
       maxJ = fmax(maxJ, Jnext);
@@ -484,6 +495,22 @@ __device__ __forceinline__ StageRes stage_tile(const Bufs& bf, const Consts& cs,
   return stage_compute<B, CPT>(bf, cs, v, sc, c0, sm, cls_inst, st, (int)threadIdx.x);
 }
 
+// Scalars of stage s of instance i read through the constant address space
+// (scalar loads; no instance record is written while a stage kernel runs).
+__device__ __forceinline__ StageScal stage_scal_const(const Inst* inst, int i, int s) {
+  typedef const __attribute__((address_space(4))) Inst* cinst;
+  const cinst I = (cinst)inst + i;
+  StageScal sc;
+  sc.s = s;
+  sc.dt = I->dt;
+  sc.as = s == 1 ? 0.0 : (s == 2 ? 0.75 : 1.0 / 3.0);
+  sc.bs = s == 1 ? 1.0 : (s == 2 ? 0.25 : 2.0 / 3.0);
+  sc.cprev = s == 1 ? 0.0 : (s == 2 ? 1.0 : 0.25) * sc.dt * I->alpha[s == 1 ? 0 : s - 2];
+  sc.dx = I->dx[s - 1];
+  sc.wsc = I->wscale;
+  return sc;
+}
+
 // Phase 1 of a ghost-free tile of the stage-launch engine, whose instance
 // offsets come with the tile: the loads of the tile are issued before the
 // instance record is read, so the two latencies overlap.  The instance
@@ -495,7 +522,7 @@ __device__ __forceinline__ StageRes stage_tile(const Bufs& bf, const Consts& cs,
 template <int B, int CPT, bool FIRST>
 __device__ __forceinline__ bool stage_load_direct(const Bufs& bf, const View& v, int inst, int s,
                                                   int par, int64_t c0, SmemStage<B, CPT>& sm,
-                                                  StageScal& sc, int& st) {
+                                                  int& st) {
   constexpr int TB = B * CPT;
   const int t = threadIdx.x;
   const double* P = ((s == 2) ? bf.P0 : bf.P1) + v.co;
@@ -512,13 +539,7 @@ __device__ __forceinline__ bool stage_load_direct(const Bufs& bf, const View& v,
   if (!I->active) return false;
   // an instance out of step with the batch would have read the wrong nodes
   if ((int)(I->steps & 1) != par) st |= SB_SEQUENCE;
-  sc.s = s;
-  sc.dt = I->dt;
-  sc.as = s == 1 ? 0.0 : (s == 2 ? 0.75 : 1.0 / 3.0);
-  sc.bs = s == 1 ? 1.0 : (s == 2 ? 0.25 : 2.0 / 3.0);
-  sc.cprev = s == 1 ? 0.0 : (s == 2 ? 1.0 : 0.25) * sc.dt * I->alpha[s == 1 ? 0 : s - 2];
-  sc.dx = I->dx[s - 1];
-  sc.wsc = I->wscale;
+  const StageScal sc = stage_scal_const(bf.inst, inst, s);
 #pragma unroll
   for (int c = 0; c < CPT; ++c) put_raw(sc, t + c * B, r[c], sm, st);
   if (ext) put_raw(sc, TB + t, rx, sm, st);

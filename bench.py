@@ -74,14 +74,14 @@ def roofline(ctx, p, off, T, tnow, L, S, kern_ms, launches, steps):
     import torch
     per_stage = ALG_BYTES_PER_CELL_STEP / 3.0
     if L.engine == alew.ENGINE_PERSISTENT:
-        kernel = f"k_persistent<{L.block}>"
+        kernel = f"k_persistent<{L.block or 256}>"
         ms_launch = kern_ms / max(1, launches)
         achieved = ALG_BYTES_PER_CELL_STEP * S * steps / max(1, launches) / (ms_launch / 1e3) / 1e9
         stage_launches, epi = None, None
     else:
-        cpt = max(1, L.cells_per_thread)
-        kernel = (f"k_stage_pipe<{L.block}>" if (L.prefetch and cpt == 1)
-                  else f"k_stage<{L.block}, {cpt}>")
+        blk = L.block or 64  # 0 = the library's choice for the stage launches
+        cpt = L.cells_per_thread or (2 if blk == 64 else 1)
+        kernel = f"k_stage<{blk}, {cpt}, {'true' if L.compact_tiles else 'false'}>"
         ctx.set_kernel_timing(True)
         W = {k: v.clone() for k, v in T.items()}
         ctx.run(p, off, W["h"], W["hu"], W["b"], W["x"], W["xi"], t0=tnow,
@@ -94,7 +94,7 @@ def roofline(ctx, p, off, T, tnow, L, S, kern_ms, launches, steps):
         ms_launch = sms / max(1, sn)
         achieved = per_stage * scells / (sms / 1e3) / 1e9
         stage_launches = sn
-        epi = dict(kernel=f"k_final<{L.block}>", launches=en, launch_ms=round(ems / max(1, en), 4))
+        epi = dict(kernel="k_final<256>", launches=en, launch_ms=round(ems / max(1, en), 4))
         log(f"kernel timing: {sn} stage launches, {ms_launch:.4f} ms each; "
             f"{en} epilogues, {ems / max(1, en):.4f} ms each")
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
@@ -243,10 +243,12 @@ def main():
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--graph", type=int, default=1, help="stage engine: replay steps as a hipGraph")
     ap.add_argument("--cpt", type=int, default=1, help="stage engine: cells per thread (1 or 2)")
+    ap.add_argument("--compact", type=int, default=0,
+                    help="stage engine: 1 = tiles without the four extra stencil slots")
     ap.add_argument("--ninst", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-inst", type=int, default=64)
-    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-steps", type=int, default=30)
     ap.add_argument("--no-speedup", action="store_true",
                     help="skip the batched vs per-instance comparison")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward ratio")
@@ -296,7 +298,7 @@ def main():
     else:
         eng = alew.ENGINE_PERSISTENT if args.engine == "persistent" else alew.ENGINE_STAGES
         ctx.set_launch(engine=eng, block=args.block, use_graph=args.graph,
-                       cells_per_thread=args.cpt)
+                       cells_per_thread=args.cpt, compact_tiles=args.compact)
     L = ctx.get_launch()
     engine_name = "persistent" if L.engine == alew.ENGINE_PERSISTENT else "stage-launches"
 
@@ -330,8 +332,11 @@ def main():
         "config": {"workload": f"ragged batch of {ninst} 1D perturbation-of-still-water "
                                f"instances, 1000-20000 cells each (seed 2208065881), {S} cells, "
                                "transmissive, sine-moving mesh, CFL 0.6, FP64 SSP-RK3",
-                   "ninst": ninst, "cells": S, "engine": engine_name, "block": L.block,
-                   "cells_per_thread": max(1, L.cells_per_thread),
+                   "ninst": ninst, "cells": S, "engine": engine_name,
+                   "block": L.block or (256 if L.engine == alew.ENGINE_PERSISTENT else 64),
+                   "cells_per_thread": L.cells_per_thread or
+                   (2 if L.engine != alew.ENGINE_PERSISTENT and L.block in (0, 64) else 1),
+                   "compact_tiles": int(L.compact_tiles),
                    "parallelism": "single GPU"},
         "roofline": roof,
     }

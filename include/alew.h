@@ -100,25 +100,29 @@ typedef struct {
 } alew_stats;
 
 /* Launch configuration (normally chosen by the autotuner).
- * engine 0 = automatic, 1 = persistent (one launch runs a whole ragged batch,
- * a work-group per instance, instances taken largest first from a device queue),
- * 2 = stage launches (every tile of every instance in each stage kernel).
- * block: work-group size (128, 256 or 512; 0 = 256).
+ * engine 0 = automatic (the stage launches), 1 = persistent (one launch runs a
+ * whole ragged batch, a work-group per instance, instances taken largest first
+ * from a device queue), 2 = stage launches (every tile of every instance in
+ * each stage kernel).
+ * block: work-group size (64, 128, 256 or 512; 0 = 64 for the stage launches,
+ * 256 for the persistent engine).
  * steps_per_launch: persistent engine, steps per launch before control returns to
  * the host (0 = until every instance is done).
  * use_graph: stage-launch engine, replay the launches of a step as a hipGraph.
  * cells_per_thread: stage-launch engine, cells each thread reconstructs per
- * tile (1 or 2; 0 = 1); a tile spans block * cells_per_thread cells.
- * prefetch: stage-launch engine with one cell per thread: 1 = tiles away from
- * the instance ends run in a kernel that streams each work-group's next tile
- * into LDS while it computes the current one; 0 = one plain kernel (default). */
+ * tile (1 or 2; 0 = 2 for block 64, else 1); a tile spans block *
+ * cells_per_thread cells.
+ * compact_tiles: stage-launch engine: 0 = a stage tile of T = block x
+ * cells_per_thread cells loads T + 4 stencil slots (the first four threads load
+ * the last four) and owns T - 2 cells (default); 1 = it loads T slots, one per
+ * cell a thread handles, and owns T - 6 cells. */
 typedef struct {
   int32_t engine;
   int32_t block;
   int32_t steps_per_launch;
   int32_t use_graph;
   int32_t cells_per_thread;
-  int32_t prefetch;
+  int32_t compact_tiles;
 } alew_launch;
 
 /* Create a context able to run up to max_cells cells in up to max_inst instances.
@@ -189,8 +193,7 @@ alew_status alew_last_timing(const alew_ctx* ctx, double* ms, int64_t* launches)
 /* Per-kernel timing of the stage-launch engine.  With on != 0, later
  * alew_step/alew_run calls launch the step sequence without a graph and record
  * a HIP event pair on the context's stream around every stage launch (all
- * stage kernels of one RK stage: the tile kernel, or the end-tile and
- * prefetching kernels) and every step-epilogue launch (new state, nodes and
+ * stage kernels of one RK stage) and every step-epilogue launch (new state, nodes and
  * step-size reductions).  It adds an event pair per launch and is off by
  * default. */
 alew_status alew_set_kernel_timing(alew_ctx* ctx, int on);

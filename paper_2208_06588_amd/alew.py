@@ -49,7 +49,7 @@ class Stats(C.Structure):
 class Launch(C.Structure):
     _fields_ = [("engine", C.c_int32), ("block", C.c_int32), ("steps_per_launch", C.c_int32),
                 ("use_graph", C.c_int32), ("cells_per_thread", C.c_int32),
-                ("prefetch", C.c_int32)]
+                ("compact_tiles", C.c_int32)]
 
 
 class AlewError(RuntimeError):
@@ -153,11 +153,11 @@ class Context:
     def _sync_stream(self):
         _check(lib().alew_set_stream(self._h, C.c_void_p(torch.cuda.current_stream().cuda_stream)))
 
-    def set_launch(self, engine=ENGINE_AUTO, block=256, steps_per_launch=0, use_graph=1,
-                   cells_per_thread=1, prefetch=0):
+    def set_launch(self, engine=ENGINE_AUTO, block=0, steps_per_launch=0, use_graph=1,
+                   cells_per_thread=0, compact_tiles=0):
         _check(lib().alew_set_launch(self._h, C.byref(Launch(engine, block, steps_per_launch,
                                                              use_graph, cells_per_thread,
-                                                             prefetch))))
+                                                             compact_tiles))))
 
     def last_timing(self):
         """(milliseconds, launches) of the compute launches of the last call."""

@@ -27,13 +27,17 @@ CANDIDATES = [
     dict(engine=alew.ENGINE_STAGES, block=128, steps_per_launch=0, use_graph=1, cells_per_thread=2),
     dict(engine=alew.ENGINE_STAGES, block=256, steps_per_launch=0, use_graph=1, cells_per_thread=2),
     dict(engine=alew.ENGINE_STAGES, block=256, steps_per_launch=0, use_graph=1, cells_per_thread=1,
-         prefetch=1),
+         compact_tiles=1),
+    dict(engine=alew.ENGINE_STAGES, block=64, steps_per_launch=0, use_graph=1, cells_per_thread=1),
+    dict(engine=alew.ENGINE_STAGES, block=64, steps_per_launch=0, use_graph=1, cells_per_thread=2),
+    dict(engine=alew.ENGINE_STAGES, block=64, steps_per_launch=0, use_graph=1, cells_per_thread=2,
+         compact_tiles=1),
 ]
 
 
 def name_of(c) -> str:
     return (f"engine{c['engine']}-b{c['block']}-g{c['use_graph']}"
-            f"-c{c.get('cells_per_thread', 1)}-p{c.get('prefetch', 0)}")
+            f"-c{c.get('cells_per_thread', 1)}-t{c.get('compact_tiles', 0)}")
 
 CACHE = os.environ.get("ALEW_TUNE_CACHE", os.path.expanduser("~/.cache/alew/autotune.json"))
 

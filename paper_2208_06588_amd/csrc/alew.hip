@@ -28,6 +28,10 @@ using namespace alew_dev;
 // ============================================================================
 // kernels
 // ============================================================================
+// Items per plain tile (set-up, step epilogue, finish): independent of the
+// stage kernels' work-group size.
+constexpr int PB = 256;
+
 struct Tile {
   int32_t inst;
   int32_t rec;  // index of the tile's result record (stage or plain table)
@@ -113,82 +117,38 @@ __device__ __forceinline__ void publish_stage(const Bufs& bf, int rec, const Sta
 }
 
 // Stage s of one tile; par is the parity of the step (x^n in xa or xb).
-template <int B, int CPT>
+// NOEXT: tiles of TB slots (TB - 6 owned cells) instead of TB + 4 slots.
+template <int B, int CPT, bool NOEXT>
 __global__ __launch_bounds__(B) void k_stage(Bufs bf, Consts cs, const Tile* __restrict__ tiles,
                                              int s, int par) {
+  constexpr int TB = B * CPT;
+  constexpr int NR = NOEXT ? TB - 4 : TB;
   __shared__ SmemStage<B, CPT> sm;
   const Tile tl = tiles[blockIdx.x];
   View v;
   int st = 0;
-  if (tile_inner<B * CPT>(tl.n, tl.c0)) {
+  if (tile_inner<NOEXT ? TB : TB + 4>(tl.n, tl.c0)) {
     v.n = tl.n;
     v.co = tl.co;
     v.no = tl.co + tl.inst;
     v.x = (par ? bf.xb : bf.xa) + v.no;
     v.xnew = (par ? bf.xa : bf.xb) + v.no;
-    const bool on = (s == 1) ? stage_load_direct<B, CPT, true>(bf, v, tl.inst, s, par, tl.c0, sm, st)
-                             : stage_load_direct<B, CPT, false>(bf, v, tl.inst, s, par, tl.c0, sm, st);
+    const bool on =
+        (s == 1) ? stage_load_direct<B, CPT, true, NOEXT>(bf, v, tl.inst, s, par, tl.c0, sm, st)
+                 : stage_load_direct<B, CPT, false, NOEXT>(bf, v, tl.inst, s, par, tl.c0, sm, st);
     if (!on) return;
   } else {
     const Inst& I = bf.inst[tl.inst];
     if (!I.active) return;
     v = make_view(bf, tl.inst, I);
-    load_tile_edge<B, CPT>(bf, cs, v, stage_scal(I, s), tl.c0, sm, st);
+    load_tile_edge<B, CPT, NOEXT>(bf, cs, v, stage_scal(I, s), tl.c0, sm, st);
   }
   // read again after the two paths join, so that they stay scalar
   const StageScal sc = stage_scal_const(bf.inst, tl.inst, s);
   lds_sync();
   uint8_t* cl = bf.cls ? bf.cls + (int64_t)(s - 1) * bf.S + v.co : nullptr;
-  const StageRes r = stage_compute<B, CPT>(bf, cs, v, sc, tl.c0, sm, cl, st, (int)threadIdx.x);
+  const StageRes r = stage_compute<B, CPT, NR>(bf, cs, v, sc, tl.c0, sm, cl, st, (int)threadIdx.x);
   if (threadIdx.x == 0) publish_stage(bf, tl.rec, r);
-}
-
-// Stage-launch engine, ghost-free tiles: work-group b takes the tiles b, b+G,
-// b+2G, ... of the table (G = grid size) and streams the raw rows of its next
-// tile into LDS while it computes the current one.
-// The thread index as a value the compiler cannot carry across iterations:
-// without it, loop-invariant code motion keeps every per-thread LDS address
-// of the tile body live through the whole loop (about 60 extra registers).
-__device__ __forceinline__ int tid_fresh() {
-  int t;
-  asm volatile("v_mov_b32 %0, %1" : "=v"(t) : "v"((int)threadIdx.x));
-  return t;
-}
-
-template <int B>
-__global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(3))) void k_stage_pipe(
-    Bufs bf, Consts cs, const Tile* __restrict__ tiles, int64_t ntiles, int s) {
-  __shared__ RawRows<B> sp;
-  __shared__ SmemStage<B, 1> sm;
-  const int64_t G = gridDim.x;
-  int64_t k = blockIdx.x;
-  if (k >= ntiles) return;
-  // tile k is copied while its predecessor computes; the records of tile k+G
-  // are read one iteration ahead
-  TileInfo cur = tile_info(bf, tiles, k, s);
-  issue_tile<B>(bf, cur.v, s, cur.c0, sp, (int)threadIdx.x);
-  TileInfo nxt = cur;
-  if (k + G < ntiles) nxt = tile_info(bf, tiles, k + G, s);
-  for (; k < ntiles; k += G) {
-    const int t = tid_fresh();
-    int st = 0;
-    __builtin_amdgcn_s_waitcnt(0);  // this wave's copies into LDS have landed
-    lds_sync();
-    slot_from_raw<B>(cur.sc, t, sp, sm, st);
-    if (t < 4) slot_from_raw<B>(cur.sc, B + t, sp, sm, st);
-    lds_sync();
-    const bool more = k + G < ntiles;
-    if (more) issue_tile<B>(bf, nxt.v, s, nxt.c0, sp, t);
-    TileInfo after = nxt;
-    if (k + 2 * G < ntiles) after = tile_info(bf, tiles, k + 2 * G, s);
-    if (cur.active) {
-      uint8_t* cl = bf.cls ? bf.cls + (int64_t)(s - 1) * bf.S + cur.v.co : nullptr;
-      const StageRes r = stage_compute<B, 1>(bf, cs, cur.v, cur.sc, cur.c0, sm, cl, st, t);
-      if (t == 0) publish_stage(bf, cur.rec, r);
-    }
-    cur = nxt;
-    nxt = after;
-  }
 }
 
 template <int B>
@@ -578,19 +538,20 @@ struct alew_ctx {
   Tile* tiles_stage_d = nullptr;
   Tile* tiles_plain_d = nullptr;
   Tile* tiles_edge_d = nullptr;   // stage tiles touching an instance end
-  Tile* tiles_inner_d = nullptr;  // ghost-free stage tiles (prefetching kernel)
+  Tile* tiles_inner_d = nullptr;  // ghost-free stage tiles
   double* srec = nullptr;          // per-tile stage results
   double* prec = nullptr;          // per-tile step results
   int64_t* sfirst_d = nullptr;     // [max_inst+1] first stage / plain tile of each instance
   int64_t* pfirst_d = nullptr;
   int64_t tiles_cap = 0;
   int64_t n_tiles_edge = 0, n_tiles_inner = 0;
-  int pipe_blocks[3] = {0, 0, 0};  // resident work-groups per CU of k_stage_pipe<128/256/512>
   int n_cu = 0;
   std::vector<int64_t> cell_off_h;  // cached batch layout
   int cached_B = 0, cached_TB = 0;
+  bool cached_noext = false;
+  bool tiles_noext = false;  // stage tiles of TB slots (TB - 6 owned): compact tiles
   int64_t n_tiles_stage = 0, n_tiles_plain = 0;
-  alew_launch launch{0, 256, 0, 1, 1, 0};
+  alew_launch launch{0, 0, 0, 1, 0, 0};
   hipEvent_t ev0 = nullptr, ev1 = nullptr;  // around the compute launches of a call
   // per-kernel timing (alew_set_kernel_timing): event pairs around launches
   int ktime_on = 0;
@@ -631,21 +592,33 @@ alew_status check_params(const alew_params* p) {
   return ALEW_OK;
 }
 
-int pick_block(const alew_ctx* c) {
+// Work-group size: block 0 = 64 for the stage-launch engine (one-wave tiles,
+// no barrier across SIMDs), 256 for the persistent engine.
+int pick_block(const alew_ctx* c, int engine) {
   const int b = c->launch.block;
-  return (b == 128 || b == 256 || b == 512) ? b : 256;
+  if (b == 64 || b == 128 || b == 256 || b == 512) return b;
+  return engine == 1 ? 256 : 64;
 }
 
-// Cells per thread of the stage-launch engine (block 512 runs one).
+// Cells per thread of the stage-launch engine (block 512 runs one; 0 = two
+// for block 64, else one).
 int pick_cpt(const alew_ctx* c, int B) {
-  return (c->launch.cells_per_thread == 2 && B <= 256) ? 2 : 1;
+  const int k = c->launch.cells_per_thread;
+  if (B > 256) return 1;
+  if (k == 0) return B == 64 ? 2 : 1;
+  return k == 2 ? 2 : 1;
 }
 
 // (Re)build the tile tables for a batch layout, block size B and stage tile
-// width TB (TB - 2 owned cells per stage tile; B items per plain tile).
-alew_status build_tiles(alew_ctx* c, const int64_t* cell_off, int64_t ninst, int B, int TB) {
+// width TB: TB + 4 stencil slots and TB - 2 owned cells per stage tile, or
+// with noext TB slots and TB - 6 owned cells; B items per plain tile.
+alew_status build_tiles(alew_ctx* c, const int64_t* cell_off, int64_t ninst, int B, int TB,
+                        bool noext) {
   std::vector<int64_t> off(cell_off, cell_off + ninst + 1);
-  if (off == c->cell_off_h && c->cached_B == B && c->cached_TB == TB) return ALEW_OK;
+  if (off == c->cell_off_h && c->cached_B == B && c->cached_TB == TB && c->cached_noext == noext)
+    return ALEW_OK;
+  const int64_t own = noext ? TB - 6 : TB - 2;
+  const int64_t NS = noext ? TB : TB + 4;
   // stage tiles carry their index in the full stage table as record index (the
   // end-tile and ghost-free tables are subsets of it); plain tiles their own
   std::vector<Tile> ts, tp, te, tin;
@@ -654,11 +627,11 @@ alew_status build_tiles(alew_ctx* c, const int64_t* cell_off, int64_t ninst, int
     const int64_t n = off[i + 1] - off[i];
     sfirst[i] = (int64_t)ts.size();
     pfirst[i] = (int64_t)tp.size();
-    for (int64_t c0 = 0; c0 < n; c0 += TB - 2) {
+    for (int64_t c0 = 0; c0 < n; c0 += own) {
       const Tile tl{(int32_t)i, (int32_t)ts.size(), c0, off[i], n};
       ts.push_back(tl);
       // same test as tile_inner() on the device
-      const bool inner = c0 >= 3 && c0 + TB < n && n < (int64_t(1) << 28);
+      const bool inner = c0 >= 3 && c0 + NS - 4 < n && n < (int64_t(1) << 28);
       (inner ? tin : te).push_back(tl);
     }
     for (int64_t c0 = 0; c0 <= n; c0 += B)
@@ -706,6 +679,8 @@ alew_status build_tiles(alew_ctx* c, const int64_t* cell_off, int64_t ninst, int
   c->cell_off_h = off;
   c->cached_B = B;
   c->cached_TB = TB;
+  c->cached_noext = noext;
+  c->tiles_noext = noext;
   c->n_tiles_stage = (int64_t)ts.size();
   c->n_tiles_plain = (int64_t)tp.size();
   c->n_tiles_edge = (int64_t)te.size();
@@ -729,21 +704,6 @@ Bufs make_bufs(alew_ctx* c, int64_t S, int64_t ninst, double* hu, double* b, con
   bf.sfirst = c->sfirst_d; bf.pfirst = c->pfirst_d;
   bf.dump = Dump{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   return bf;
-}
-
-// Work-groups of the prefetching stage kernel: as many as stay resident.
-template <int B>
-int pipe_grid(alew_ctx* c) {
-  const int slot = B == 128 ? 0 : (B == 256 ? 1 : 2);
-  if (c->pipe_blocks[slot] == 0) {
-    int dev = 0, per_cu = 0;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, dev);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_stage_pipe<B>, B, 0);
-    c->pipe_blocks[slot] = std::max(1, per_cu);
-  }
-  const int64_t g = (int64_t)std::max(1, c->n_cu) * c->pipe_blocks[slot];
-  return (int)std::min<int64_t>(g, c->n_tiles_inner);
 }
 
 // Event pair around a launch for per-kernel timing (kind 0: stage, 1: epilogue).
@@ -773,26 +733,22 @@ template <int B, int CPT>
 void launch_step_seq(alew_ctx* c, const Bufs& bf, const Consts& cs, hipStream_t st, int64_t step) {
   const int par = (int)(step & 1);
   const dim3 gs((unsigned)c->n_tiles_stage), gp((unsigned)c->n_tiles_plain);
-  const bool pipe = CPT == 1 && c->launch.prefetch == 1 && c->n_tiles_inner > 0;
   for (int s = 1; s <= 3; ++s) {
     const int kt = kt_begin(c, st, 0, (double)bf.S);
-    if (pipe) {
-      if (c->n_tiles_edge > 0)
-        hipLaunchKernelGGL((k_stage<B, 1>), dim3((unsigned)c->n_tiles_edge), dim3(B), 0, st, bf,
-                           cs, c->tiles_edge_d, s, par);
-      hipLaunchKernelGGL(k_stage_pipe<B>, dim3((unsigned)pipe_grid<B>(c)), dim3(B), 0, st, bf, cs,
-                         c->tiles_inner_d, c->n_tiles_inner, s);
-    } else {
-      hipLaunchKernelGGL((k_stage<B, CPT>), gs, dim3(B), 0, st, bf, cs, c->tiles_stage_d, s, par);
-    }
+    if (c->tiles_noext)
+      hipLaunchKernelGGL((k_stage<B, CPT, true>), gs, dim3(B), 0, st, bf, cs, c->tiles_stage_d, s,
+                         par);
+    else
+      hipLaunchKernelGGL((k_stage<B, CPT, false>), gs, dim3(B), 0, st, bf, cs, c->tiles_stage_d, s,
+                         par);
     kt_end(c, st, kt);
     hipLaunchKernelGGL(k_after_stage, dim3((unsigned)((bf.ninst + 3) / 4)), dim3(256), 0, st, bf, s);
   }
   const int kf = kt_begin(c, st, 1, (double)bf.S);
-  hipLaunchKernelGGL(k_final<B>, gp, dim3(B), 0, st, bf, cs, c->tiles_plain_d);
+  hipLaunchKernelGGL(k_final<PB>, gp, dim3(PB), 0, st, bf, cs, c->tiles_plain_d);
   kt_end(c, st, kf);
   if (cs.mesh == MESH_FLUID)
-    hipLaunchKernelGGL(k_wfluid<B>, gp, dim3(B), 0, st, bf, cs, c->tiles_plain_d);
+    hipLaunchKernelGGL(k_wfluid<PB>, gp, dim3(PB), 0, st, bf, cs, c->tiles_plain_d);
   hipLaunchKernelGGL(k_boundary, dim3((unsigned)((bf.ninst + 3) / 4)), dim3(256), 0, st, bf, cs, 0);
 }
 
@@ -806,7 +762,7 @@ GraphKey make_key(const Bufs& bf, const Consts& cs, int B, int CPT, const alew_c
   put(&cs, sizeof(cs));
   put(&B, sizeof(B));
   put(&CPT, sizeof(CPT));
-  put(&c->launch.prefetch, sizeof(int32_t));
+  put(&c->tiles_noext, sizeof(bool));
   put(&c->n_tiles_stage, sizeof(int64_t));
   put(&c->n_tiles_plain, sizeof(int64_t));
   return k;
@@ -932,9 +888,10 @@ alew_status drive(alew_ctx* c, const alew_params* p, int64_t ninst, const int64_
   const int64_t S = cell_off[ninst];
   if (S > c->max_cells) return fail(ALEW_E_ARG, "total cells exceed the context capacity");
   if ((dts || dt_log) && dts_stride <= 0) return fail(ALEW_E_ARG, "dts_stride must be > 0");
-  const int B = pick_block(c);
+  const int B = pick_block(c, engine);
   const int CPT = (engine == 1) ? 1 : pick_cpt(c, B);
-  alew_status ts = build_tiles(c, cell_off, ninst, B, B * CPT);
+  const bool noext = engine != 1 && c->launch.compact_tiles == 1;
+  alew_status ts = build_tiles(c, cell_off, ninst, PB, B * CPT, noext);
   if (ts != ALEW_OK) return ts;
   // per-instance scalars
   int64_t max_iters = 0;
@@ -960,18 +917,19 @@ alew_status drive(alew_ctx* c, const alew_params* p, int64_t ninst, const int64_
   const dim3 gp((unsigned)c->n_tiles_plain);
 #define ALEW_DISPATCH(BB)                                                                       \
   do {                                                                                          \
-    hipLaunchKernelGGL(k_prep<BB>, gp, dim3(BB), 0, c->stream, bf, cs, c->tiles_plain_d, h, wgiven); \
+    hipLaunchKernelGGL(k_prep<PB>, gp, dim3(PB), 0, c->stream, bf, cs, c->tiles_plain_d, h, wgiven); \
     if (cs.mesh == MESH_FLUID)                                                                  \
-      hipLaunchKernelGGL(k_wfluid<BB>, gp, dim3(BB), 0, c->stream, bf, cs, c->tiles_plain_d);  \
+      hipLaunchKernelGGL(k_wfluid<PB>, gp, dim3(PB), 0, c->stream, bf, cs, c->tiles_plain_d);  \
     hipLaunchKernelGGL(k_boundary, dim3((unsigned)((ninst + 3) / 4)), dim3(256), 0, c->stream, bf, cs, 1); \
     HIPCHK(hipGetLastError());                                                                  \
     alew_status rs = (engine == 1) ? run_persistent<BB>(c, bf, cs, ninst)                       \
                                    : run_stages<BB>(c, bf, cs, max_iters, CPT);                 \
     if (rs != ALEW_OK) return rs;                                                               \
-    hipLaunchKernelGGL(k_finish<BB>, gp, dim3(BB), 0, c->stream, bf, cs, c->tiles_plain_d, h, x); \
+    hipLaunchKernelGGL(k_finish<PB>, gp, dim3(PB), 0, c->stream, bf, cs, c->tiles_plain_d, h, x); \
     hipLaunchKernelGGL(k_masses, dim3((unsigned)((ninst + 3) / 4)), dim3(256), 0, c->stream, bf); \
   } while (0)
-  if (B == 128) ALEW_DISPATCH(128);
+  if (B == 64) ALEW_DISPATCH(64);
+  else if (B == 128) ALEW_DISPATCH(128);
   else if (B == 512) ALEW_DISPATCH(512);
   else ALEW_DISPATCH(256);
 #undef ALEW_DISPATCH
@@ -1121,11 +1079,12 @@ alew_status alew_set_stream(alew_ctx* c, void* s) {
 alew_status alew_set_launch(alew_ctx* c, const alew_launch* l) {
   if (!c || !l) return fail(ALEW_E_ARG, "ctx or launch is NULL");
   if (l->engine < 0 || l->engine > 2) return fail(ALEW_E_ARG, "unknown engine");
-  if (l->block != 0 && l->block != 128 && l->block != 256 && l->block != 512)
-    return fail(ALEW_E_ARG, "block must be 0, 128, 256 or 512");
+  if (l->block != 0 && l->block != 64 && l->block != 128 && l->block != 256 && l->block != 512)
+    return fail(ALEW_E_ARG, "block must be 0, 64, 128, 256 or 512");
   if (l->cells_per_thread < 0 || l->cells_per_thread > 2)
     return fail(ALEW_E_ARG, "cells_per_thread must be 0, 1 or 2");
-  if (l->prefetch < 0 || l->prefetch > 1) return fail(ALEW_E_ARG, "prefetch must be 0 or 1");
+  if (l->compact_tiles < 0 || l->compact_tiles > 1)
+    return fail(ALEW_E_ARG, "compact_tiles must be 0 or 1");
   c->launch = *l;
   return ALEW_OK;
 }
@@ -1169,7 +1128,7 @@ alew_status alew_run(alew_ctx* c, const alew_params* p, int64_t ninst, const int
   if (p && p->mesh == ALEW_MESH_GIVEN) return fail(ALEW_E_UNSUPPORTED, "alew_run needs a SINE, PAPER or FLUID mesh");
   if (!c) return fail(ALEW_E_ARG, "ctx is NULL");
   int engine = c->launch.engine;
-  if (engine == 0) engine = ninst >= 64 ? 1 : 2;
+  if (engine == 0) engine = 2;
   std::vector<alew_stats> tmp;
   if (!stats) { tmp.resize(ninst > 0 ? ninst : 1); stats = tmp.data(); }
   return drive(c, p, ninst, cell_off, h, hu, b, x, xi, nullptr, t0, t_end, max_steps, dts, dt_log,
@@ -1201,7 +1160,7 @@ alew_status alew_adjoint(alew_ctx* c, const alew_params* p, int64_t ninst,
   const int64_t nck = (nsteps + K - 1) / K;
   const int64_t NN = S + ninst;
   const int B = 256;
-  alew_status ts = build_tiles(c, cell_off, ninst, B, B);
+  alew_status ts = build_tiles(c, cell_off, ninst, PB, B, c->launch.compact_tiles == 1);
   if (ts != ALEW_OK) return ts;
   // workspace layout (doubles)
   const size_t n_state = 2 * (size_t)S;                 // hu, b of the run

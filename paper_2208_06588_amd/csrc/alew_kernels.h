@@ -98,11 +98,9 @@ template <int B, int CPT>
 struct SmemStage {
   static constexpr int TB = B * CPT;
   static constexpr int NW = B / 64;
-  // Stencil slot i holds cell k = c0 - 3 + i (ghosts mapped).  The update
-  // reads the cell averages and widths again from the stencil arrays (fewer
-  // registers held through the reconstruction), so the face values have
-  // arrays of their own.
-  struct {
+  // Stencil slot i holds cell k = c0 - 3 + i (ghosts mapped).  The stencil
+  // arrays are dead once the traces are formed, so the face values reuse them.
+  union {
     struct {
       double e[TB + 4], m[TB + 4], b[TB + 4], J[TB + 4], iJ[TB + 4];
     } in;
@@ -253,13 +251,15 @@ __device__ __forceinline__ void load_slot_edge(const Bufs& bf, const Consts& cs,
 }
 
 // True if every stencil slot of the tile at c0 is a real cell.
-template <int TB>
+// NS stencil slots per tile (TB + 4 with the extra slots, TB without).
+template <int NS>
 __device__ __forceinline__ bool tile_inner(int64_t n, int64_t c0) {
-  return c0 >= 3 && c0 + TB < n && n < (int64_t(1) << 28);
+  return c0 >= 3 && c0 + NS - 4 < n && n < (int64_t(1) << 28);
 }
 
-// Tile that touches an end of the instance, slot by slot.
-template <int B, int CPT>
+// Tile that touches an end of the instance, slot by slot (with or without
+// the four slots past the last thread).
+template <int B, int CPT, bool NOEXT = false>
 __device__ __forceinline__ void load_tile_edge(const Bufs& bf, const Consts& cs, const View& v,
                                                const StageScal& sc, int64_t c0,
                                                SmemStage<B, CPT>& sm, int& st) {
@@ -267,7 +267,7 @@ __device__ __forceinline__ void load_tile_edge(const Bufs& bf, const Consts& cs,
   const int t = threadIdx.x;
 #pragma unroll
   for (int c = 0; c < CPT; ++c) load_slot_edge(bf, cs, v, sc, c0 - 3 + t + c * B, t + c * B, sm, st);
-  if (t < 4) load_slot_edge(bf, cs, v, sc, c0 - 3 + TB + t, TB + t, sm, st);
+  if (!NOEXT && t < 4) load_slot_edge(bf, cs, v, sc, c0 - 3 + TB + t, TB + t, sm, st);
 }
 
 // Phase 1 of a stage tile: stencil data for cells c0-3 .. c0+TB in LDS.
@@ -277,7 +277,7 @@ __device__ __forceinline__ void stage_load(const Bufs& bf, const Consts& cs, con
                                            SmemStage<B, CPT>& sm, int& st) {
   constexpr int TB = B * CPT;
   const int t = threadIdx.x;
-  if (tile_inner<TB>(v.n, c0)) {
+  if (tile_inner<TB + 4>(v.n, c0)) {
     if (sc.s == 1)
       load_tile_inner<B, CPT, true>(bf, v, sc, c0, sm, st);
     else
@@ -300,8 +300,10 @@ __device__ __forceinline__ double shfl_prev(double x, int lane) {
 // Phases 2-4 of a stage tile (the stencil data is in LDS and visible to the
 // whole work-group): reconstruction and limiter per cell, interface fluxes,
 // residual split and stage combination of the owned cells, and the tile's
-// reductions.  Thread t handles the tile cells t + c B, c < CPT.
-template <int B, int CPT>
+// reductions.  Thread t handles the tile cells t + c B, c < CPT.  NR tile
+// cells are reconstructed (NR - 2 owned): TB with the four extra stencil
+// slots loaded, TB - 4 without them.
+template <int B, int CPT, int NR = B * CPT>
 __device__ __forceinline__ StageRes stage_compute(const Bufs& bf, const Consts& cs, const View& v,
                                                   const StageScal& sc, int64_t c0,
                                                   SmemStage<B, CPT>& sm, uint8_t* cls_inst,
@@ -313,16 +315,17 @@ __device__ __forceinline__ StageRes stage_compute(const Bufs& bf, const Consts& 
   // for the end faces); one cell after the other.  The left state of the face
   // at node j is the right trace of cell j-1: from the previous lane, or for
   // lane 0 through LDS after the barrier.
-  double rint[CPT];
+  double rint[CPT], ebar[CPT], mbar[CPT], bbar[CPT], Jj[CPT];
   double tl0[CPT], tl1[CPT], tl2[CPT], tp0[CPT], tp1[CPT], tp2[CPT];
   unsigned n0 = 0, n1 = 0, n2 = 0, nl = 0, nn = 0;
   // tile-local bounds (work-group uniform): tile cell i is cell c0 - 1 + i, so
   // it is a real cell or an end ghost for i <= iact, owned for 1 <= i <= iown;
   // ighr is the tile index of the right ghost (cell n), if in the tile
   const int64_t nrel = v.n - c0;
-  const int iact = (int)(nrel + 1 < TB ? nrel + 1 : TB);
-  const int iown = (int)(nrel < TB - 2 ? nrel : TB - 2);
-  const int ighr = (nrel + 1 < TB) ? (int)(nrel + 1) : -1;
+  static_assert(NR == TB || NR == TB - 4, "tile cells reconstructed");
+  const int iact = (int)(nrel + 1 < NR - 1 ? nrel + 1 : NR - 1);
+  const int iown = (int)(nrel < NR - 2 ? nrel : NR - 2);
+  const int ighr = (nrel + 1 < NR) ? (int)(nrel + 1) : -1;
   const bool lghost = c0 == 0;
   uint8_t* cls_tile = cls_inst ? cls_inst + c0 : nullptr;  // tile cell i at [i - 1]
 #pragma unroll
@@ -332,7 +335,7 @@ __device__ __forceinline__ StageRes stage_compute(const Bufs& bf, const Consts& 
     const bool owned = (i >= 1) && (i <= iown);
     int cls_owned = -1;
     bool lim_owned = false, neg_cell = false;
-    rint[c] = 0.0;
+    rint[c] = 0.0; ebar[c] = 0.0; mbar[c] = 0.0; bbar[c] = 0.0; Jj[c] = 1.0;
     double hR = 0.0, mR = 0.0, bR = 0.0;
     tl0[c] = 0.0; tl1[c] = 0.0; tl2[c] = 0.0;
     if (active) {
@@ -346,11 +349,11 @@ __device__ __forceinline__ StageRes stage_compute(const Bufs& bf, const Consts& 
         v5[k] = (cs.flags & F_BETA_FROM_H) ? h5[k] : se[k];
       }
       const double hbar = h5[2];
-      const double mbar = sm.u.in.m[i + 2];
-      const double Dx = (cs.flags & F_BETA_LOCAL) ? sm.u.in.J[i + 2] : sc.dx;
+      ebar[c] = se[2]; mbar[c] = sm.u.in.m[i + 2]; bbar[c] = sb[2]; Jj[c] = sm.u.in.J[i + 2];
+      const double Dx = (cs.flags & F_BETA_LOCAL) ? Jj[c] : sc.dx;
       recon_cell(v5, h5, sm.u.in.m + i, sb, sm.u.in.J + i, sm.u.in.iJ[i + 2], Dx, cs.weno_eps,
-                 se[2], o);
-      const int lim = limit_cell(hbar, mbar, cs.pp_eps, o);
+                 ebar[c], o);
+      const int lim = limit_cell(hbar, mbar[c], cs.pp_eps, o);
       rint[c] = o.rint;
       if (owned) {
         cls_owned = o.cls;
@@ -410,10 +413,9 @@ __device__ __forceinline__ StageRes stage_compute(const Bufs& bf, const Consts& 
     if ((i >= 1) && (i <= iown)) {
       const double g = cs.g;
       const double(*fl)[TB] = sm.u.fl;
-      const double ebar = sm.u.in.e[i + 2], mbar = sm.u.in.m[i + 2], bbar = sm.u.in.b[i + 2];
-      const double Jj = sm.u.in.J[i + 2];
+      const double eb = ebar[c], mb = mbar[c], bb = bbar[c], Jc = Jj[c];
       const double Ae = -(fl[0][i + 1] - fl[0][i]);
-      const double S = 0.5 * g * (fl[7][i + 1] - fl[7][i]) - g * ebar * (fl[6][i + 1] - fl[6][i]) - g * rint[c];
+      const double S = 0.5 * g * (fl[7][i + 1] - fl[7][i]) - g * eb * (fl[6][i + 1] - fl[6][i]) - g * rint[c];
       const double Am = -(fl[1][i + 1] - fl[1][i]) + S;
       const double Ab = -(fl[2][i + 1] - fl[2][i]);
       const double De = 0.5 * (fl[3][i + 1] - fl[3][i]);
@@ -421,19 +423,19 @@ __device__ __forceinline__ StageRes stage_compute(const Bufs& bf, const Consts& 
       const double Db = 0.5 * (fl[5][i + 1] - fl[5][i]);
       double Pe, Pm, Pb;
       if (sc.s == 1) {
-        Pe = Jj * ebar + sc.dt * Ae;
-        Pm = Jj * mbar + sc.dt * Am;
-        Pb = Jj * bbar + sc.dt * Ab;
+        Pe = Jc * eb + sc.dt * Ae;
+        Pm = Jc * mb + sc.dt * Am;
+        Pb = Jc * bb + sc.dt * Ab;
       } else {
-        Pe = sm.qn[0][i + 2] + sc.bs * (Jj * ebar + sc.dt * Ae);
-        Pm = sm.qn[1][i + 2] + sc.bs * (Jj * mbar + sc.dt * Am);
-        Pb = sm.qn[2][i + 2] + sc.bs * (Jj * bbar + sc.dt * Ab);
+        Pe = sm.qn[0][i + 2] + sc.bs * (Jc * eb + sc.dt * Ae);
+        Pm = sm.qn[1][i + 2] + sc.bs * (Jc * mb + sc.dt * Am);
+        Pb = sm.qn[2][i + 2] + sc.bs * (Jc * bb + sc.dt * Ab);
       }
       Po[i] = Pe; (Po + NS)[i] = Pm; (Po + 2 * NS)[i] = Pb;
       Do[i] = De; (Do + NS)[i] = Dm; (Do + 2 * NS)[i] = Db;
       if (bf.dump.q) {
         const int64_t o = (int64_t)(3 * (sc.s - 1)) * NS + gt + i;
-        bf.dump.q[o] = ebar; bf.dump.q[o + NS] = mbar; bf.dump.q[o + 2 * NS] = bbar;
+        bf.dump.q[o] = eb; bf.dump.q[o + NS] = mb; bf.dump.q[o + 2 * NS] = bb;
         bf.dump.D[o] = De; bf.dump.D[o + NS] = Dm; bf.dump.D[o + 2 * NS] = Db;
       }
       const double Jnext = sm.Jx[i + 2];
@@ -519,7 +521,7 @@ __device__ __forceinline__ StageScal stage_scal_const(const Inst* inst, int i, i
 // written while a stage kernel runs.  par is the parity of the step, the same
 // for every active instance of a batch (all of them start together and step
 // together).  Returns false for an inactive instance.
-template <int B, int CPT, bool FIRST>
+template <int B, int CPT, bool FIRST, bool NOEXT>
 __device__ __forceinline__ bool stage_load_direct(const Bufs& bf, const View& v, int inst, int s,
                                                   int par, int64_t c0, SmemStage<B, CPT>& sm,
                                                   int& st) {
@@ -531,7 +533,7 @@ __device__ __forceinline__ bool stage_load_direct(const Bufs& bf, const View& v,
 #pragma unroll
   for (int c = 0; c < CPT; ++c)
     r[c] = raw_inner<FIRST>(bf, v, P, D, (unsigned)(c0 - 3 + t + c * B) * 8u);
-  const bool ext = t < 4;
+  const bool ext = !NOEXT && t < 4;
   RawSlot rx;
   if (ext) rx = raw_inner<FIRST>(bf, v, P, D, (unsigned)(c0 - 3 + TB + t) * 8u);
   typedef const __attribute__((address_space(4))) Inst* cinst;
@@ -544,126 +546,6 @@ __device__ __forceinline__ bool stage_load_direct(const Bufs& bf, const View& v,
   for (int c = 0; c < CPT; ++c) put_raw(sc, t + c * B, r[c], sm, st);
   if (ext) put_raw(sc, TB + t, rx, sm, st);
   return true;
-}
-
-// ----------------------------------------------------------------------------
-// Software-pipelined stage tiles (ghost-free tiles only): while a work-group
-// computes one tile, the raw rows of its next tile stream into LDS through the
-// direct-to-LDS loads, which hold no registers.
-// Raw rows of a tile at c0: x^n and w at nodes c0-3 .. c0+B+1 (B+5 values),
-// then q^n (stage 1) or P, D and q^n (stages 2, 3) of cells c0-3 .. c0+B.
-// ----------------------------------------------------------------------------
-// Raw rows live in an LDS object of their own: the compiler then knows that
-// the stencil reads of the current tile do not touch what the copies in flight
-// write, and does not wait for those copies.
-template <int B>
-struct RawRows {
-  static constexpr int RL = B + 8;  // row length (>= B + 5)
-  double r[11][RL];
-};
-
-typedef __attribute__((address_space(3))) void* lds_ptr;
-
-// Copy n doubles from global memory to LDS (both contiguous): the waves of the
-// work-group take 256-byte pieces in turn, one dword per lane.
-template <int B>
-__device__ __forceinline__ void dma_row(const double* src, double* dst, int n, int t) {
-  const int lane = t & 63, wv = t >> 6;
-  const int ndw = 2 * n;
-  const unsigned* s32 = reinterpret_cast<const unsigned*>(src);
-  for (int q = wv; q * 64 < ndw; q += B / 64) {
-    const int d = q * 64 + lane;
-    if (d < ndw)
-      __builtin_amdgcn_global_load_lds(s32 + d, (lds_ptr)(reinterpret_cast<char*>(dst) + q * 256),
-                                       4, 0, 0);
-  }
-}
-
-// Start the raw-row copies of the ghost-free tile at c0 for stage s.
-template <int B>
-__device__ __forceinline__ void issue_tile(const Bufs& bf, const View& v, int s, int64_t c0,
-                                           RawRows<B>& sp, int t) {
-  const int64_t k0 = c0 - 3;
-  dma_row<B>(v.x + k0, sp.r[0], B + 5, t);
-  dma_row<B>(bf.w + v.no + k0, sp.r[1], B + 5, t);
-  const int64_t g0 = v.co + k0;
-  const int64_t S = bf.S;
-  if (s == 1) {
-    dma_row<B>(bf.eta + g0, sp.r[2], B + 4, t);
-    dma_row<B>(bf.m + g0, sp.r[3], B + 4, t);
-    dma_row<B>(bf.b + g0, sp.r[4], B + 4, t);
-  } else {
-    const double* P = (s == 2) ? bf.P0 : bf.P1;
-    const double* D = (s == 2) ? bf.D0 : bf.D1;
-    dma_row<B>(P + g0, sp.r[2], B + 4, t);
-    dma_row<B>(P + S + g0, sp.r[3], B + 4, t);
-    dma_row<B>(P + 2 * S + g0, sp.r[4], B + 4, t);
-    dma_row<B>(D + g0, sp.r[5], B + 4, t);
-    dma_row<B>(D + S + g0, sp.r[6], B + 4, t);
-    dma_row<B>(D + 2 * S + g0, sp.r[7], B + 4, t);
-    dma_row<B>(bf.eta + g0, sp.r[8], B + 4, t);
-    dma_row<B>(bf.m + g0, sp.r[9], B + 4, t);
-    dma_row<B>(bf.b + g0, sp.r[10], B + 4, t);
-  }
-}
-
-// Everything a tile needs from the per-instance records, read through the
-// constant address space so that the loads are scalar (SGPR, the LGKM
-// counter): waiting for them never waits for vector-memory traffic in flight.
-// The fields read here (and the tile table) are not written while a stage
-// kernel runs; only the reduction slots and counters are, by atomics.
-struct TileInfo {
-  View v;
-  StageScal sc;
-  int64_t c0;
-  int inst;
-  int rec;
-  int active;
-};
-
-template <class TT>
-__device__ __forceinline__ TileInfo tile_info(const Bufs& bf, const TT* tiles, int64_t k, int s) {
-  typedef const __attribute__((address_space(4))) TT* ctile;
-  typedef const __attribute__((address_space(4))) Inst* cinst;
-  typedef const __attribute__((address_space(4))) int64_t* ci64;
-  const ctile tp = (ctile)tiles + k;
-  const int inst = tp->inst;
-  const cinst I = (cinst)bf.inst + inst;
-  const ci64 off = (ci64)bf.cell_off;
-  TileInfo ti;
-  ti.inst = inst;
-  ti.rec = tp->rec;
-  ti.c0 = tp->c0;
-  ti.active = I->active;
-  ti.v.co = off[inst];
-  ti.v.n = off[inst + 1] - ti.v.co;
-  ti.v.no = ti.v.co + inst;
-  const bool odd = (I->steps & 1) != 0;
-  ti.v.x = (odd ? bf.xb : bf.xa) + ti.v.no;
-  ti.v.xnew = (odd ? bf.xa : bf.xb) + ti.v.no;
-  const double dt = I->dt;
-  ti.sc.s = s;
-  ti.sc.dt = dt;
-  ti.sc.as = s == 1 ? 0.0 : (s == 2 ? 0.75 : 1.0 / 3.0);
-  ti.sc.bs = s == 1 ? 1.0 : (s == 2 ? 0.25 : 2.0 / 3.0);
-  const double bprev = s == 2 ? 1.0 : 0.25;
-  ti.sc.cprev = s == 1 ? 0.0 : bprev * dt * I->alpha[s - 2];
-  ti.sc.dx = I->dx[s - 1];
-  ti.sc.wsc = I->wscale;
-  return ti;
-}
-
-// Stencil slot i of a tile from its raw rows (same arithmetic as the direct loads).
-template <int B>
-__device__ __forceinline__ void slot_from_raw(const StageScal& sc, int i, const RawRows<B>& sp,
-                                              SmemStage<B, 1>& sm, int& st) {
-  const double(*r)[RawRows<B>::RL] = sp.r;
-  if (sc.s == 1)
-    put_slot(sc, i, 1.0, true, r[0][i], r[0][i + 1], r[1][i], r[1][i + 1], r[2][i], r[3][i],
-             r[4][i], 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, sm, st);
-  else
-    put_slot(sc, i, 1.0, true, r[0][i], r[0][i + 1], r[1][i], r[1][i + 1], r[2][i], r[3][i],
-             r[4][i], r[5][i], r[6][i], r[7][i], r[8][i], r[9][i], r[10][i], sm, st);
 }
 
 // Step epilogue over cells [c0, c0+B): q^{n+1}, x^{n+1}, and the reductions

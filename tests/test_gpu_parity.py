@@ -173,17 +173,22 @@ def test_batched_engines_bitwise_and_oracle(dev):
     p = _gp(bt)
     nsteps = 25
     outs = []
-    for engine, block, cpt, pf in ((alew.ENGINE_PERSISTENT, 256, 1, 0),
-                                     (alew.ENGINE_STAGES, 128, 1, 0),
-                                     (alew.ENGINE_STAGES, 256, 1, 0),
-                                     (alew.ENGINE_STAGES, 512, 1, 0),
-                                     (alew.ENGINE_PERSISTENT, 128, 1, 0),
-                                     (alew.ENGINE_STAGES, 128, 2, 0),
-                                     (alew.ENGINE_STAGES, 256, 2, 0),
-                                     (alew.ENGINE_STAGES, 256, 1, 1)):
+    for engine, block, cpt, compact in ((alew.ENGINE_PERSISTENT, 256, 1, 0),
+                                          (alew.ENGINE_STAGES, 128, 1, 0),
+                                          (alew.ENGINE_STAGES, 256, 1, 0),
+                                          (alew.ENGINE_STAGES, 512, 1, 0),
+                                          (alew.ENGINE_PERSISTENT, 128, 1, 0),
+                                          (alew.ENGINE_PERSISTENT, 64, 1, 0),
+                                          (alew.ENGINE_STAGES, 128, 2, 0),
+                                          (alew.ENGINE_STAGES, 256, 2, 0),
+                                          (alew.ENGINE_STAGES, 256, 1, 1),
+                                          (alew.ENGINE_STAGES, 64, 1, 0),
+                                          (alew.ENGINE_STAGES, 64, 2, 0),
+                                          (alew.ENGINE_STAGES, 64, 2, 1),
+                                          (alew.ENGINE_STAGES, 128, 2, 1)):
         ctx = alew.Context(n, ninst)
         ctx.set_launch(engine=engine, block=block, use_graph=1, cells_per_thread=cpt,
-                       prefetch=pf)
+                       compact_tiles=compact)
         T = {k: _t(bt[k], dev) for k in ("h", "hu", "b", "x", "xi")}
         st = ctx.run(p, off, T["h"], T["hu"], T["b"], T["x"], T["xi"], max_steps=[nsteps] * ninst)
         torch.cuda.synchronize()
@@ -201,10 +206,11 @@ def test_batched_engines_bitwise_and_oracle(dev):
         assert outs[0][1][i].steps == nsteps
 
 
-def test_prefetching_stage_kernel_many_tiles(dev):
-    """A batch with more ghost-free tiles than resident work-groups, so every
-    work-group of the prefetching kernel streams several tiles: bitwise equal
-    to the plain stage kernel, and sampled instances match the oracle."""
+def test_stage_tile_shapes_many_tiles(dev):
+    """A batch of 160 instances of 3000-9000 cells, many more stage tiles than
+    resident work-groups: tiles of 256 x 1 cells with four extra stencil slots,
+    64 x 2 cells with and without them, are bitwise equal (state, nodes, class
+    counts), and sampled instances match the oracle."""
     rng = np.random.default_rng(11)
     ns = [int(v) for v in rng.integers(3000, 9000, 160)]
     eps = rng.uniform(1e-5, 1e-2, len(ns))
@@ -216,17 +222,19 @@ def test_prefetching_stage_kernel_many_tiles(dev):
     p = _gp(bt)
     nsteps = 6
     outs = []
-    for pf in (0, 1):
+    for block, cpt, compact in ((256, 1, 0), (64, 2, 0), (64, 2, 1)):
         ctx = alew.Context(n, ninst)
-        ctx.set_launch(engine=alew.ENGINE_STAGES, block=256, use_graph=1, prefetch=pf)
+        ctx.set_launch(engine=alew.ENGINE_STAGES, block=block, use_graph=1,
+                       cells_per_thread=cpt, compact_tiles=compact)
         T = {k: _t(bt[k], dev) for k in ("h", "hu", "b", "x", "xi")}
         st = ctx.run(p, off, T["h"], T["hu"], T["b"], T["x"], T["xi"], max_steps=[nsteps] * ninst)
         torch.cuda.synchronize()
         outs.append(({k: v.cpu().numpy() for k, v in T.items()}, st))
-    for k in ("h", "hu", "b", "x"):
-        assert np.array_equal(outs[0][0][k], outs[1][0][k]), k
-    assert [tuple(s.n_class) for s in outs[0][1]] == [tuple(s.n_class) for s in outs[1][1]]
-    ref = outs[1][0]
+    for o, st in outs[1:]:
+        for k in ("h", "hu", "b", "x"):
+            assert np.array_equal(outs[0][0][k], o[k]), k
+        assert [tuple(s.n_class) for s in outs[0][1]] == [tuple(s.n_class) for s in st]
+    ref = outs[2][0]
     for i in (0, ninst // 2, ninst - 1):
         a, e = int(off[i]), int(off[i + 1])
         r = O.run(_op(bt), bt["h"][a:e], bt["hu"][a:e], bt["b"][a:e], bt["x"][a + i:e + i + 1],

@@ -136,7 +136,7 @@ def bowl_leg(dev, n, steps, warmup):
     p = alew.params(bc="transmissive", mesh="fluid", cfl=wl["cfl"], weno_eps=wl["weno_eps"])
     T = {k: torch.tensor(wl[k], dtype=torch.float64, device=dev) for k in ("h", "hu", "b", "x", "xi")}
     ctx = alew.Context(n, 1)
-    ctx.set_launch(engine=alew.ENGINE_STAGES, block=256, use_graph=1)
+    ctx.set_launch(engine=alew.ENGINE_STAGES, use_graph=1)
     st = ctx.run(p, [0, n], T["h"], T["hu"], T["b"], T["x"], T["xi"], max_steps=[warmup])
     torch.cuda.synchronize()
     a = time.perf_counter()
@@ -194,7 +194,7 @@ def adjoint_leg(dev, ninst, ncell, nsteps, ngauge, ckpt):
     T = {k: torch.tensor(bt[k], dtype=torch.float64, device=dev)
          for k in ("h", "hu", "b", "x", "xi", "gauge_x", "b_true")}
     ctx = alew.Context(S, ninst)
-    ctx.set_launch(engine=alew.ENGINE_STAGES, block=256, use_graph=1)
+    ctx.set_launch(engine=alew.ENGINE_STAGES, use_graph=1)
     # frozen step sizes: the CFL steps of a run from the initial state
     dts = torch.zeros(ninst * nsteps, dtype=torch.float64, device=dev)
     W0 = {k: T[k].clone() for k in ("h", "hu", "b", "x")}
@@ -356,7 +356,9 @@ def main():
         batched = time.perf_counter() - a0
         Tp = {kk: v[:Ssub + (k if kk in ("x", "xi") else 0)].clone() for kk, v in T.items()}
         ctx1 = alew.Context(max(np.diff(sub_off)), 1)
-        ctx1.set_launch(engine=alew.ENGINE_STAGES, block=256, use_graph=1)
+        ctx1.set_launch(engine=L.engine, block=L.block, steps_per_launch=L.steps_per_launch,
+                        use_graph=L.use_graph, cells_per_thread=L.cells_per_thread,
+                        compact_tiles=L.compact_tiles)  # the batched run's launch
         torch.cuda.synchronize()
         a0 = time.perf_counter()
         for i in range(k):

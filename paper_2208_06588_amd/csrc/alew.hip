@@ -752,6 +752,19 @@ void launch_step_seq(alew_ctx* c, const Bufs& bf, const Consts& cs, hipStream_t 
   hipLaunchKernelGGL(k_boundary, dim3((unsigned)((bf.ninst + 3) / 4)), dim3(256), 0, st, bf, cs, 0);
 }
 
+// Step sequence for a run-time tile shape (block B, CPT cells per thread).
+void launch_step_shape(alew_ctx* c, int B, int CPT, const Bufs& bf, const Consts& cs,
+                       hipStream_t st, int64_t step) {
+  if (B == 64)
+    CPT == 2 ? launch_step_seq<64, 2>(c, bf, cs, st, step) : launch_step_seq<64, 1>(c, bf, cs, st, step);
+  else if (B == 128)
+    CPT == 2 ? launch_step_seq<128, 2>(c, bf, cs, st, step) : launch_step_seq<128, 1>(c, bf, cs, st, step);
+  else if (B == 512)
+    launch_step_seq<512, 1>(c, bf, cs, st, step);
+  else
+    CPT == 2 ? launch_step_seq<256, 2>(c, bf, cs, st, step) : launch_step_seq<256, 1>(c, bf, cs, st, step);
+}
+
 GraphKey make_key(const Bufs& bf, const Consts& cs, int B, int CPT, const alew_ctx* c) {
   GraphKey k;
   auto put = [&](const void* p, size_t n) {
@@ -1159,8 +1172,9 @@ alew_status alew_adjoint(alew_ctx* c, const alew_params* p, int64_t ninst,
   const int64_t K = ckpt_every > 0 ? ckpt_every : 16;
   const int64_t nck = (nsteps + K - 1) / K;
   const int64_t NN = S + ninst;
-  const int B = 256;
-  alew_status ts = build_tiles(c, cell_off, ninst, PB, B, c->launch.compact_tiles == 1);
+  // forward passes in the stage-launch engine's tile shape
+  const int B = pick_block(c, 2), CPT = pick_cpt(c, B);
+  alew_status ts = build_tiles(c, cell_off, ninst, PB, B * CPT, c->launch.compact_tiles == 1);
   if (ts != ALEW_OK) return ts;
   // workspace layout (doubles)
   const size_t n_state = 2 * (size_t)S;                 // hu, b of the run
@@ -1175,8 +1189,8 @@ alew_status alew_adjoint(alew_ctx* c, const alew_params* p, int64_t ninst,
   std::vector<AdjTile> atiles;
   for (int64_t i = 0; i < ninst; ++i)
     for (int64_t c0 = 0; c0 < cell_off[i + 1] - cell_off[i]; c0 += TBA)
-      atiles.push_back(AdjTile{(int32_t)i, 0, c0});
-  const size_t n_at = 2 * atiles.size();
+      atiles.push_back(AdjTile{(int32_t)i, 0, c0, cell_off[i], cell_off[i + 1] - cell_off[i]});
+  const size_t n_at = (sizeof(AdjTile) / 8) * atiles.size();
   const size_t n_adj = 9 * (size_t)S + (size_t)ninst + (size_t)ninst * ngauge +
                        18 * (size_t)ninst + n_at + atiles.size() + (size_t)ninst + 1;
   const size_t need = (n_state + n_ck + n_ckI + n_seg + n_adj) * 8;
@@ -1252,9 +1266,9 @@ alew_status alew_adjoint(alew_ctx* c, const alew_params* p, int64_t ninst,
         hipLaunchKernelGGL(k_seed_scal, dim3(1), dim3(1024), 0, st, bf, step_dump(0).scal);
       Bufs bd = bf;
       bd.dump = step_dump(k - klast);
-      launch_step_seq<256, 1>(c, bd, cs, st, k);
+      launch_step_shape(c, B, CPT, bd, cs, st, k);
     } else {
-      launch_step_seq<256, 1>(c, bf, cs, st, k);
+      launch_step_shape(c, B, CPT, bf, cs, st, k);
     }
   }
   HIPCHK(hipGetLastError());
@@ -1303,7 +1317,7 @@ alew_status alew_adjoint(alew_ctx* c, const alew_params* p, int64_t ninst,
       for (int64_t k = k0; k < k1; ++k) {
         Bufs bd = bf;
         bd.dump = step_dump(k - k0);
-        launch_step_seq<256, 1>(c, bd, cs, st, k);
+        launch_step_shape(c, B, CPT, bd, cs, st, k);
       }
     }
     for (int64_t k = k1 - 1; k >= k0; --k) {

@@ -428,6 +428,8 @@ struct AdjTile {
   int32_t inst;
   int32_t pad;
   int64_t c0;
+  int64_t co;  // cell offset of the instance
+  int64_t n;   // cells of the instance
 };
 
 // lambda_alpha of each instance from its fused tiles' parts (the tiles of
@@ -468,10 +470,98 @@ struct SmemAdjF {
   } u;
   double lf[6][B];
   double B1[B];
+  // owned slots (loaded with the stencil, used by the last phase):
+  double accb[3][B];  // b_s J^(s-1) mu, mu = lambda^(s) / J^(s)
+  double lb[3][B];    // lambda of q^n accumulated up to this stage
 };
 
 // gfold layout: [ninst][2 ends][3 ghost cells][3 components], ends: left
 // ghosts -3..-1, right ghosts n..n+2.
+// Stencil slot q of a fused tile (cell k = c0 - 5 + q): the stage input, the
+// stage width and rho = b_s dt lambda^(s) / J^(s) into LDS; for an owned cell
+// also the pieces the last phase combines, and its part of lambda_alpha.  All
+// loads of a thread's slots are issued before the first use.
+struct AdjSlotRaw {
+  double x0, x1, w0, w1, e, m, b, l0, l1, l2, d0, d1, d2, lb0, lb1, lb2;
+  double ms;
+  bool in, real, own;
+};
+
+__device__ __forceinline__ AdjSlotRaw adj_slot_load(const AdjBufs& ab, const Consts& cs,
+                                                    const double* x, const double* w, int64_t co,
+                                                    int64_t n, int64_t k, int64_t own_beg,
+                                                    int64_t own_end, int s) {
+  AdjSlotRaw r;
+  r.in = k >= -3 && k < n + 3;
+  r.real = k >= 0 && k < n;
+  r.own = r.real && k >= own_beg && k < own_end;
+  r.x0 = r.x1 = r.w0 = r.w1 = 0.0;
+  r.e = r.m = r.b = 0.0;
+  r.l0 = r.l1 = r.l2 = r.d0 = r.d1 = r.d2 = r.lb0 = r.lb1 = r.lb2 = 0.0;
+  r.ms = 1.0;
+  if (r.in) {
+    const int64_t src = ghost_src(cs.bc, n, k, r.ms);
+    r.x0 = x[src]; r.x1 = x[src + 1]; r.w0 = w[src]; r.w1 = w[src + 1];
+    const int64_t g = co + src;
+    r.e = ab.q[g]; r.m = ab.q[ab.S + g]; r.b = ab.q[2 * ab.S + g];
+    if (r.real) {
+      r.l0 = ab.lam[g]; r.l1 = ab.lam[ab.S + g]; r.l2 = ab.lam[2 * ab.S + g];
+    }
+    if (r.own) {
+      r.d0 = ab.D[g]; r.d1 = ab.D[ab.S + g]; r.d2 = ab.D[2 * ab.S + g];
+      if (s != 3) {
+        r.lb0 = ab.lbase[g]; r.lb1 = ab.lbase[ab.S + g]; r.lb2 = ab.lbase[2 * ab.S + g];
+      }
+    }
+  }
+  return r;
+}
+
+// Widths and LDS stores of a loaded slot; returns the owned cell's rho . D
+// (its part of lambda_alpha), 0 otherwise.
+template <int B>
+__device__ __forceinline__ double adj_slot_put(const AdjSlotRaw& r, int q, double dt, int s,
+                                               SmemAdjF<B>& sm) {
+  double e = 0, m = 0, b = 0, J = 1, r0 = 0, r1 = 0, r2 = 0, lap = 0.0;
+  if (r.in) {
+    // the widths of stage_widths() from the raw node values
+    const double Jn = r.x1 - r.x0;
+    const double dw = r.w1 - r.w0;
+    const double J1 = Jn + dt * dw;
+    const double J2 = 0.75 * Jn + 0.25 * (J1 + dt * dw);
+    const double J3 = (1.0 / 3.0) * Jn + (2.0 / 3.0) * (J2 + dt * dw);
+    const double Jin = s == 1 ? Jn : (s == 2 ? J1 : J2);
+    const double Jout = s == 1 ? J1 : (s == 2 ? J2 : J3);
+    const double bs = stage_b(s);
+    e = r.e;
+    m = r.m * r.ms;
+    b = r.b;
+    J = Jin;
+    if (r.real) {
+      const double rf = bs * dt / Jout;
+      r0 = rf * r.l0;
+      r1 = rf * r.l1;
+      r2 = rf * r.l2;
+    }
+    if (r.own) {
+      const double mu[3] = {r.l0 / Jout, r.l1 / Jout, r.l2 / Jout};
+      const double dd[3] = {r.d0, r.d1, r.d2};
+      const double lbv[3] = {r.lb0, r.lb1, r.lb2};
+      const double as = stage_a(s);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        lap += (bs * dt * mu[c]) * dd[c];
+        sm.accb[c][q] = bs * Jin * mu[c];
+        const double base = as * Jn * mu[c];
+        sm.lb[c][q] = s == 3 ? base : lbv[c] + base;
+      }
+    }
+  }
+  sm.e[q] = e; sm.m[q] = m; sm.b[q] = b; sm.J[q] = J;
+  sm.rho[0][q] = r0; sm.rho[1][q] = r1; sm.rho[2][q] = r2;
+  return lap;
+}
+
 template <int B>
 __global__ __launch_bounds__(B) void k_adj_fused(AdjBufs ab, Consts cs,
                                                  const AdjTile* __restrict__ tiles, int s,
@@ -480,39 +570,26 @@ __global__ __launch_bounds__(B) void k_adj_fused(AdjBufs ab, Consts cs,
   __shared__ SmemAdjF<B> sm;
   const AdjTile tl = tiles[blockIdx.x];
   const int i = tl.inst;
-  const int64_t co = ab.cell_off[i], n = ab.cell_off[i + 1] - co, no = co + i;
+  const int64_t co = tl.co, n = tl.n, no = co + i;
   const int64_t c0 = tl.c0;
   const int t = threadIdx.x;
   const double* x = ab.x + no;
   const double* w = ab.w + no;
-  const double dt = ab.scal[(int64_t)i * 8 + 1];
-  const double alpha = ab.scal[(int64_t)i * 8 + 1 + s];
-  const double dx = ab.scal[(int64_t)i * 8 + 5 + (s - 1)];
-  const double bs = stage_b(s);
-  // 1. stencil data and rho for cells c0-5 .. c0+B-2
-  for (int q = t; q < B + 4; q += B) {
-    const int64_t k = c0 - 5 + q;
-    double e = 0, m = 0, b = 0, J = 1, r0 = 0, r1 = 0, r2 = 0;
-    if (k >= -3 && k < n + 3) {
-      double ms;
-      const int64_t src = ghost_src(cs.bc, n, k, ms);
-      double Jn, Jin, Jout;
-      stage_widths(x, w, src, dt, s, Jn, Jin, Jout);
-      const int64_t g = co + src;
-      e = ab.q[g];
-      m = ab.q[ab.S + g] * ms;
-      b = ab.q[2 * ab.S + g];
-      J = Jin;
-      if (k >= 0 && k < n) {
-        const double rf = bs * dt / Jout;
-        r0 = rf * ab.lam[g];
-        r1 = rf * ab.lam[ab.S + g];
-        r2 = rf * ab.lam[2 * ab.S + g];
-      }
-    }
-    sm.e[q] = e; sm.m[q] = m; sm.b[q] = b; sm.J[q] = J;
-    sm.rho[0][q] = r0; sm.rho[1][q] = r1; sm.rho[2][q] = r2;
-  }
+  // 1. stencil data and rho for cells c0-5 .. c0+B-2 (slots 0 .. B+3); the
+  // owned cells c0 .. c0+TB-1 are the slots 5 .. TB+4
+  const int64_t own_end = c0 + TB < n ? c0 + TB : n;
+  const AdjSlotRaw ra0 = adj_slot_load(ab, cs, x, w, co, n, c0 - 5 + t, c0, own_end, s);
+  const bool ext = t < 4;
+  AdjSlotRaw ra1;
+  if (ext) ra1 = adj_slot_load(ab, cs, x, w, co, n, c0 - 5 + B + t, c0, own_end, s);
+  // per-instance scalars of the step (not written during the reverse sweep)
+  typedef const __attribute__((address_space(4))) double* cdbl;
+  const cdbl sc8 = (cdbl)ab.scal + (int64_t)i * 8;
+  const double dt = sc8[1];
+  const double alpha = sc8[1 + s];
+  const double dx = sc8[5 + (s - 1)];
+  double lap = adj_slot_put<B>(ra0, t, dt, s, sm);  // rho . D of an owned cell (lambda_alpha)
+  if (ext) (void)adj_slot_put<B>(ra1, B + t, dt, s, sm);
   lds_sync();
   // 2. forward reconstruction and limiter of cell j = c0 - 3 + t (stencil slots t .. t+4)
   const int64_t j = c0 - 3 + t;
@@ -587,32 +664,21 @@ __global__ __launch_bounds__(B) void k_adj_fused(AdjBufs ab, Consts cs,
   for (int k = 0; k < 15; ++k) sm.u.cl[k][t] = cv[k];
   lds_sync();
   // 5. owned cell k = c0 + t: slot i = t + 5 collects offset o from the cell of thread i - o
-  double lap = 0.0;  // rho . D of the owned cell (part of lambda_alpha)
   if (t < TB && c0 + t < n) {
-    const int64_t k = c0 + t;
+    const int64_t g = co + c0 + t;
     const int si = t + 5;
-    double Jn, Jin, Jout;
-    stage_widths(x, w, k, dt, s, Jn, Jin, Jout);
-    const int64_t g = co + k;
-    double acc[3], mu[3];
+    double acc[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      mu[c] = ab.lam[c * ab.S + g] / Jout;
-      acc[c] = bs * Jin * mu[c];
-    }
-    double* lo = ab.lam_out;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) lap += (bs * dt * mu[c]) * ab.D[c * ab.S + g];
+    for (int c = 0; c < 3; ++c) acc[c] = sm.accb[c][si];
 #pragma unroll
     for (int oo = 0; oo < 5; ++oo) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) acc[c] += sm.u.cl[3 * oo + c][si - oo];
     }
-    const double as = stage_a(s);
+    double* lo = ab.lam_out;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const double base = as * Jn * mu[c];
-      const double lb = s == 3 ? base : ab.lbase[c * ab.S + g] + base;
+      const double lb = sm.lb[c][si];
       if (s == 1) {
         lo[c * ab.S + g] = acc[c] + lb;
       } else {

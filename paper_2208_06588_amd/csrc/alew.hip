@@ -702,7 +702,7 @@ Bufs make_bufs(alew_ctx* c, int64_t S, int64_t ninst, double* hu, double* b, con
   bf.S = S; bf.ninst = (int32_t)ninst; bf.pad = 0;
   bf.srec = c->srec; bf.prec = c->prec;
   bf.sfirst = c->sfirst_d; bf.pfirst = c->pfirst_d;
-  bf.dump = Dump{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  bf.dump = Dump{nullptr, nullptr, nullptr, nullptr, nullptr};
   return bf;
 }
 
@@ -1180,9 +1180,9 @@ alew_status alew_adjoint(alew_ctx* c, const alew_params* p, int64_t ninst,
   const size_t n_state = 2 * (size_t)S;                 // hu, b of the run
   const size_t n_ck = (size_t)nck * (3 * S + NN);       // checkpoints
   const size_t n_ckI = (size_t)nck * ninst * sizeof(Inst) / 8 + 1;
-  // records of one step: q and D of the three stages, x^n and w^n, the step
+  // records of one step: q of the three stages, x^n and w^n, the step
   // scalars, and the argmax keys of the three stages
-  const size_t per_step = 18 * (size_t)S + 2 * (size_t)NN + 11 * (size_t)ninst;
+  const size_t per_step = 9 * (size_t)S + 2 * (size_t)NN + 11 * (size_t)ninst;
   const size_t n_seg = (size_t)(K + 1) * per_step;
   // tiles of the fused reverse stage: 250 owned cells each (256 threads)
   constexpr int BA = 256, TBA = BA - 6;
@@ -1237,9 +1237,8 @@ alew_status alew_adjoint(alew_ctx* c, const alew_params* p, int64_t ninst,
     Dump d;
     double* base = seg + slot * per_step;
     d.q = base;
-    d.D = base + 9 * S;
-    d.xw = base + 18 * S;
-    d.scal = base + 18 * S + 2 * NN;
+    d.xw = base + 9 * S;
+    d.scal = base + 9 * S + 2 * NN;
     d.akey = d.scal + 8 * ninst;
     d.scal_next = d.scal + per_step;
     return d;
@@ -1325,7 +1324,6 @@ alew_status alew_adjoint(alew_ctx* c, const alew_params* p, int64_t ninst,
       ab.x = d.xw; ab.w = d.xw + NN; ab.scal = d.scal;
       for (int s3 = 3; s3 >= 1; --s3) {
         ab.q = d.q + (int64_t)3 * (s3 - 1) * S;
-        ab.D = d.D + (int64_t)3 * (s3 - 1) * S;
         ab.akeyd = d.akey + (int64_t)(s3 - 1) * ninst;
         hipLaunchKernelGGL(k_adj_fused<BA>, ga, dim3(BA), 0, st, ab, cs, atiles_d, s3, gfold);
         hipLaunchKernelGGL(k_adj_fold, dim3(gfb), dim3(256), 0, st, ab, cs, gfold);

@@ -37,7 +37,6 @@ struct AdjBufs {
   int32_t ninst;
   int32_t pad;
   const double* q;     // [3][S] stage input q^(s-1) (eta, hu, b)
-  const double* D;     // [3][S] alpha coefficient of the residual
   const double* akeyd; // [ninst] 2 f + side of the trace attaining alpha (forward record)
   const double* x;     // [S+ninst] x^n
   const double* w;     // [S+ninst] w^n
@@ -470,8 +469,10 @@ struct SmemAdjF {
   } u;
   double lf[6][B];
   double B1[B];
+  double wn[B + 4];   // node speed at the left node of slot q (nodes 0..n)
+  double jd[3][B];    // jumps of eta, hu, b at the faces (alpha coefficients)
   // owned slots (loaded with the stencil, used by the last phase):
-  double accb[3][B];  // b_s J^(s-1) mu, mu = lambda^(s) / J^(s)
+  double mu[3][B];    // lambda^(s) / J^(s)
   double lb[3][B];    // lambda of q^n accumulated up to this stage
 };
 
@@ -482,7 +483,7 @@ struct SmemAdjF {
 // also the pieces the last phase combines, and its part of lambda_alpha.  All
 // loads of a thread's slots are issued before the first use.
 struct AdjSlotRaw {
-  double x0, x1, w0, w1, e, m, b, l0, l1, l2, d0, d1, d2, lb0, lb1, lb2;
+  double x0, x1, w0, w1, wk, e, m, b, l0, l1, l2, lb0, lb1, lb2;
   double ms;
   bool in, real, own;
 };
@@ -497,8 +498,9 @@ __device__ __forceinline__ AdjSlotRaw adj_slot_load(const AdjBufs& ab, const Con
   r.own = r.real && k >= own_beg && k < own_end;
   r.x0 = r.x1 = r.w0 = r.w1 = 0.0;
   r.e = r.m = r.b = 0.0;
-  r.l0 = r.l1 = r.l2 = r.d0 = r.d1 = r.d2 = r.lb0 = r.lb1 = r.lb2 = 0.0;
+  r.l0 = r.l1 = r.l2 = r.lb0 = r.lb1 = r.lb2 = 0.0;
   r.ms = 1.0;
+  r.wk = (k >= 0 && k <= n) ? w[k] : 0.0;
   if (r.in) {
     const int64_t src = ghost_src(cs.bc, n, k, r.ms);
     r.x0 = x[src]; r.x1 = x[src + 1]; r.w0 = w[src]; r.w1 = w[src + 1];
@@ -507,22 +509,18 @@ __device__ __forceinline__ AdjSlotRaw adj_slot_load(const AdjBufs& ab, const Con
     if (r.real) {
       r.l0 = ab.lam[g]; r.l1 = ab.lam[ab.S + g]; r.l2 = ab.lam[2 * ab.S + g];
     }
-    if (r.own) {
-      r.d0 = ab.D[g]; r.d1 = ab.D[ab.S + g]; r.d2 = ab.D[2 * ab.S + g];
-      if (s != 3) {
-        r.lb0 = ab.lbase[g]; r.lb1 = ab.lbase[ab.S + g]; r.lb2 = ab.lbase[2 * ab.S + g];
-      }
+    if (r.own && s != 3) {
+      r.lb0 = ab.lbase[g]; r.lb1 = ab.lbase[ab.S + g]; r.lb2 = ab.lbase[2 * ab.S + g];
     }
   }
   return r;
 }
 
-// Widths and LDS stores of a loaded slot; returns the owned cell's rho . D
-// (its part of lambda_alpha), 0 otherwise.
+// Widths and LDS stores of a loaded slot.
 template <int B>
-__device__ __forceinline__ double adj_slot_put(const AdjSlotRaw& r, int q, double dt, int s,
-                                               SmemAdjF<B>& sm) {
-  double e = 0, m = 0, b = 0, J = 1, r0 = 0, r1 = 0, r2 = 0, lap = 0.0;
+__device__ __forceinline__ void adj_slot_put(const AdjSlotRaw& r, int q, double dt, int s,
+                                             SmemAdjF<B>& sm) {
+  double e = 0, m = 0, b = 0, J = 1, r0 = 0, r1 = 0, r2 = 0;
   if (r.in) {
     // the widths of stage_widths() from the raw node values
     const double Jn = r.x1 - r.x0;
@@ -545,13 +543,11 @@ __device__ __forceinline__ double adj_slot_put(const AdjSlotRaw& r, int q, doubl
     }
     if (r.own) {
       const double mu[3] = {r.l0 / Jout, r.l1 / Jout, r.l2 / Jout};
-      const double dd[3] = {r.d0, r.d1, r.d2};
       const double lbv[3] = {r.lb0, r.lb1, r.lb2};
       const double as = stage_a(s);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        lap += (bs * dt * mu[c]) * dd[c];
-        sm.accb[c][q] = bs * Jin * mu[c];
+        sm.mu[c][q] = mu[c];
         const double base = as * Jn * mu[c];
         sm.lb[c][q] = s == 3 ? base : lbv[c] + base;
       }
@@ -559,7 +555,7 @@ __device__ __forceinline__ double adj_slot_put(const AdjSlotRaw& r, int q, doubl
   }
   sm.e[q] = e; sm.m[q] = m; sm.b[q] = b; sm.J[q] = J;
   sm.rho[0][q] = r0; sm.rho[1][q] = r1; sm.rho[2][q] = r2;
-  return lap;
+  sm.wn[q] = r.wk;
 }
 
 template <int B>
@@ -588,8 +584,8 @@ __global__ __launch_bounds__(B) void k_adj_fused(AdjBufs ab, Consts cs,
   const double dt = sc8[1];
   const double alpha = sc8[1 + s];
   const double dx = sc8[5 + (s - 1)];
-  double lap = adj_slot_put<B>(ra0, t, dt, s, sm);  // rho . D of an owned cell (lambda_alpha)
-  if (ext) (void)adj_slot_put<B>(ra1, B + t, dt, s, sm);
+  adj_slot_put<B>(ra0, t, dt, s, sm);
+  if (ext) adj_slot_put<B>(ra1, B + t, dt, s, sm);
   lds_sync();
   // 2. forward reconstruction and limiter of cell j = c0 - 3 + t (stencil slots t .. t+4)
   const int64_t j = c0 - 3 + t;
@@ -619,11 +615,15 @@ __global__ __launch_bounds__(B) void k_adj_fused(AdjBufs ab, Consts cs,
     const double hl = sm.u.tr[3][t - 1], ml = sm.u.tr[4][t - 1], bl = sm.u.tr[5][t - 1];
     const double hr = sm.u.tr[0][t], mr = sm.u.tr[1][t], br = sm.u.tr[2][t];
     TraceAdj Ll, Lr;
-    face_vjp(hl, ml, bl, hr, mr, br, w[j], alpha, cs.g, cs.dry_eps, rl, rr, sm.e[t + 1],
+    face_vjp(hl, ml, bl, hr, mr, br, sm.wn[t + 2], alpha, cs.g, cs.dry_eps, rl, rr, sm.e[t + 1],
              sm.e[t + 2], Ll, Lr);
     sm.lf[0][t] = Ll.h; sm.lf[1][t] = Ll.m; sm.lf[2][t] = Ll.b;
     sm.lf[3][t] = Lr.h; sm.lf[4][t] = Lr.m; sm.lf[5][t] = Lr.b;
     sm.B1[t] = 0.5 * (bl + br);
+    // the jumps of the forward face (its alpha coefficients), dry momenta cut
+    sm.jd[0][t] = (hr + br) - (hl + bl);
+    sm.jd[1][t] = (hr > cs.dry_eps ? mr : 0.0) - (hl > cs.dry_eps ? ml : 0.0);
+    sm.jd[2][t] = br - bl;
   }
   lds_sync();  // the traces are dead from here on: their LDS takes the contributions
   // 4. reverse of cell j for 1 <= t <= B-2; contributions to stencil slots t .. t+4
@@ -663,13 +663,21 @@ __global__ __launch_bounds__(B) void k_adj_fused(AdjBufs ab, Consts cs,
 #pragma unroll
   for (int k = 0; k < 15; ++k) sm.u.cl[k][t] = cv[k];
   lds_sync();
-  // 5. owned cell k = c0 + t: slot i = t + 5 collects offset o from the cell of thread i - o
+  // 5. owned cell k = c0 + t: slot i = t + 5 collects offset o from the cell of thread i - o;
+  // its faces are those of threads t + 3 and t + 4
+  double lap = 0.0;  // rho . D of the owned cell (part of lambda_alpha)
   if (t < TB && c0 + t < n) {
     const int64_t g = co + c0 + t;
     const int si = t + 5;
+    const double bs = stage_b(s), Jin = sm.J[si];
     double acc[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) acc[c] = sm.accb[c][si];
+    for (int c = 0; c < 3; ++c) {
+      const double mu = sm.mu[c][si];
+      const double Dc = 0.5 * (sm.jd[c][t + 4] - sm.jd[c][t + 3]);
+      lap += (bs * dt * mu) * Dc;
+      acc[c] = bs * Jin * mu;
+    }
 #pragma unroll
     for (int oo = 0; oo < 5; ++oo) {
 #pragma unroll

@@ -8,7 +8,6 @@ namespace alew_dev {
 // Records kept by the forward recomputation of the adjoint (all NULL otherwise).
 struct Dump {
   double* q;     // [3 stages][3 comps][S]: stage inputs q^(s-1)
-  double* D;     // [3][3][S]: alpha coefficient of the residual
   double* akey;  // [3 stages][ninst]: 2 f + side of the first face trace attaining alpha
   double* xw;    // [2][S + ninst]: x^n and w^n of the step
   double* scal;       // [ninst][8] of this step: t, dt, alpha_1..3, dx_0..2
@@ -436,7 +435,6 @@ __device__ __forceinline__ StageRes stage_compute(const Bufs& bf, const Consts& 
       if (bf.dump.q) {
         const int64_t o = (int64_t)(3 * (sc.s - 1)) * NS + gt + i;
         bf.dump.q[o] = eb; bf.dump.q[o + NS] = mb; bf.dump.q[o + 2 * NS] = bb;
-        bf.dump.D[o] = De; bf.dump.D[o + NS] = Dm; bf.dump.D[o + 2 * NS] = Db;
       }
       const double Jnext = sm.Jx[i + 2];
       maxJ = fmax(maxJ, Jnext);

@@ -136,7 +136,12 @@ def bowl_leg(dev, n, steps, warmup):
     p = alew.params(bc="transmissive", mesh="fluid", cfl=wl["cfl"], weno_eps=wl["weno_eps"])
     T = {k: torch.tensor(wl[k], dtype=torch.float64, device=dev) for k in ("h", "hu", "b", "x", "xi")}
     ctx = alew.Context(n, 1)
-    ctx.set_launch(engine=alew.ENGINE_STAGES, use_graph=1)
+    # the autotuner over the stage-launch shapes (one work-group per instance, the
+    # persistent engine, is no candidate for a single 2^24-cell instance)
+    from paper_2208_06588_amd import autotune
+    best, _ = autotune.tune(ctx, p, [0, n], T, steps=2, use_cache=False, log=log,
+                            candidates=[c for c in autotune.CANDIDATES
+                                        if c["engine"] == alew.ENGINE_STAGES])
     st = ctx.run(p, [0, n], T["h"], T["hu"], T["b"], T["x"], T["xi"], max_steps=[warmup])
     torch.cuda.synchronize()
     a = time.perf_counter()
@@ -147,6 +152,7 @@ def bowl_leg(dev, n, steps, warmup):
     value = 3.0 * n * steps / wall
     return dict(workload=f"parabolic bowl, {n} cells, transmissive, fluid-following mesh, CFL 0.08",
                 steps=steps, value=value, unit="cell-updates/s",
+                launch=autotune.name_of(best),
                 step_hbm_frac=round(ALG_BYTES_PER_CELL_STEP * n * steps / wall / 1e9 / HBM_PEAK_GBS, 4),
                 limited_cells_per_step=round(st[0].n_limited / steps, 1),
                 h_min=st[0].h_min)

@@ -1,0 +1,130 @@
+"""Full-size cases, in the launch bench.py times (the library's automatic
+shape: one-wave stage tiles of 64 threads, two cells per thread).
+
+* The 4096-instance perturbation batch (1000-20000 cells each, 43,017,136
+  cells) runs a few CFL steps on the GPU.  Sampled instances (first, last,
+  largest, smallest and two more) are run one by one by the oracle and
+  compared element by element at 1e-11, with identical step counts, step sizes
+  and detector class counts.  Every instance must keep h >= 0 and conserve the
+  discrete masses of eta and b (the waves have not reached the transmissive
+  ends and the mesh does not move there, so no mass crosses them).
+* The 256 x 65536-cell inversion batch, 200 frozen steps, checkpoints every
+  16: the gradient of the gauge misfit with respect to b along smooth random
+  directions against central differences of the GPU forward.
+"""
+import concurrent.futures as cf
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2208_06588_amd import alew, workloads as W
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-11
+
+
+@pytest.fixture(scope="module")
+def dev():
+    torch.cuda.set_device(0)
+    return torch.device("cuda", 0)
+
+
+def _relerr(g, r):
+    g = np.asarray(g)
+    r = np.asarray(r)
+    return float(np.abs(g - r).max() / max(1.0, np.abs(r).max()))
+
+
+def test_full_perturbation_batch_sampled_instances(dev):
+    bt = W.perturbation_batch()
+    off = [int(v) for v in bt["cell_off"]]
+    ninst, S = len(off) - 1, off[-1]
+    assert ninst == 4096 and S == 43017136
+    p = alew.params(bc="transmissive", mesh="sine", mesh_A=0.05, mesh_k=1.0, mesh_omega=math.pi,
+                    cfl=0.6, weno_eps=1e-9)
+    op = O.params(bc=O.BC_TRANSMISSIVE, mesh=O.MESH_SINE, mesh_A=0.05, mesh_k=1.0,
+                  mesh_omega=math.pi, cfl=0.6, weno_eps=1e-9)
+    ctx = alew.Context(S, ninst)
+    ctx.set_launch(engine=alew.ENGINE_STAGES, use_graph=1)
+    T = {k: torch.tensor(bt[k], dtype=torch.float64, device=dev) for k in ("h", "hu", "b", "x", "xi")}
+    nsteps = 12
+    st = ctx.run(p, off, T["h"], T["hu"], T["b"], T["x"], T["xi"], max_steps=[nsteps] * ninst)
+    torch.cuda.synchronize()
+    assert all(s.status == 0 and s.steps == nsteps for s in st)
+    for s in st:
+        assert s.h_min >= 0.0
+        assert abs(s.mass_eta - s.mass_eta0) <= 1e-13 * abs(s.mass_eta0)
+        assert abs(s.mass_b - s.mass_b0) <= 1e-13 * max(1.0, abs(s.mass_b0))
+    G = {k: v.cpu().numpy() for k, v in T.items()}
+    del T
+    ns = np.diff(off)
+    sample = sorted({0, ninst - 1, int(np.argmax(ns)), int(np.argmin(ns)), 1234, 2718})
+
+    def oracle_one(i):
+        a, e = off[i], off[i + 1]
+        return O.run(op, bt["h"][a:e], bt["hu"][a:e], bt["b"][a:e], bt["x"][a + i:e + i + 1],
+                     bt["xi"][a + i:e + i + 1], max_steps=nsteps)
+
+    with cf.ThreadPoolExecutor(max_workers=len(sample)) as ex:
+        refs = dict(zip(sample, ex.map(oracle_one, sample)))
+    for i in sample:
+        a, e = off[i], off[i + 1]
+        r = refs[i]
+        assert r["status"] == 0
+        g = dict(h=G["h"][a:e], hu=G["hu"][a:e], b=G["b"][a:e], x=G["x"][a + i:e + i + 1])
+        for k in ("h", "hu", "b", "x"):
+            err = _relerr(g[k], r[k])
+            assert err <= TOL, (i, k, err)
+        rs = r["stats"]
+        assert st[i].steps == rs.steps
+        assert tuple(st[i].n_class) == tuple(rs.n_class), (i, tuple(st[i].n_class), tuple(rs.n_class))
+        assert abs(st[i].dt_min - rs.dt_min) <= 1e-13 * rs.dt_min
+        assert abs(st[i].dt_max - rs.dt_max) <= 1e-13 * rs.dt_max
+
+
+def test_full_inversion_gradient_against_central_differences(dev):
+    ninst, n, ng, nsteps, ckpt = 256, 65536, 64, 200, 16
+    bt = W.inversion_batch(ninst=ninst, n=n, ngauge=ng)
+    off = [int(v) for v in bt["cell_off"]]
+    S = off[-1]
+    p = alew.params(bc="transmissive", mesh="sine", mesh_A=0.05, mesh_k=1.0, mesh_omega=math.pi,
+                    cfl=0.6)
+    T = {k: torch.tensor(bt[k], dtype=torch.float64, device=dev)
+         for k in ("h", "hu", "b", "x", "xi", "gauge_x")}
+    ctx = alew.Context(S, ninst)
+    ctx.set_launch(engine=alew.ENGINE_STAGES, use_graph=1)
+    # frozen step sizes: the CFL steps of a run from the initial state
+    dts = torch.zeros(ninst * nsteps, dtype=torch.float64, device=dev)
+    W0 = {k: T[k].clone() for k in ("h", "hu", "b", "x")}
+    ctx.run(p, off, W0["h"], W0["hu"], W0["b"], W0["x"], T["xi"], max_steps=[nsteps] * ninst,
+            dt_log=dts, dts_stride=nsteps)
+    del W0
+    rng = np.random.default_rng(2208)
+    gbar = torch.tensor(rng.normal(size=ninst * ng), dtype=torch.float64, device=dev)
+    gh = torch.zeros(ninst * ng, dtype=torch.float64, device=dev)
+    d3 = [torch.zeros(S, dtype=torch.float64, device=dev) for _ in range(3)]
+    ctx.adjoint(p, off, T["h"], T["hu"], T["b"], T["x"], T["xi"], nsteps, dts, ng, T["gauge_x"],
+                gh, gbar, *d3, ckpt_every=ckpt)
+    db = d3[2]
+    assert torch.isfinite(db).all()
+
+    def J(bb):
+        g = torch.zeros(ninst * ng, dtype=torch.float64, device=dev)
+        ctx.adjoint(p, off, T["h"], T["hu"], bb, T["x"], T["xi"], nsteps, dts, ng, T["gauge_x"],
+                    g, None, ckpt_every=ckpt)
+        return float(torch.dot(gbar, g))
+
+    xc = torch.tensor(np.tile(0.5 * (bt["xi"][:n] + bt["xi"][1:n + 1]), ninst),
+                      dtype=torch.float64, device=dev)
+    for k in range(2):
+        # smooth direction: one Gaussian bump per instance, random centre and sign
+        c = torch.tensor(np.repeat(rng.uniform(0.2, 0.8, ninst), n), device=dev)
+        sgn = torch.tensor(np.repeat(rng.choice([-1.0, 1.0], ninst), n), device=dev)
+        v = sgn * torch.exp(-((xc - c) / 0.05) ** 2)
+        e = 1e-6
+        fd = (J(T["b"] + e * v) - J(T["b"] - e * v)) / (2 * e)
+        ad = float(torch.dot(db, v))
+        assert abs(fd - ad) <= 1e-6 * max(1.0, abs(ad)), (k, fd, ad)

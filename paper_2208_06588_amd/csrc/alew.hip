@@ -211,86 +211,160 @@ __device__ void boundary_update(Inst& I, const Consts& cs, const Bufs& bf, int i
   reset_step_slots(I);
 }
 
-// End of a step (first: start of a call): step results of each instance
-// from its plain-tile records (one wave per instance), then boundary_update.
-__global__ __launch_bounds__(256) void k_boundary(Bufs bf, Consts cs, int first) {
-  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (i >= bf.ninst) return;
-  Inst& I = bf.inst[i];
-  if (!I.active) return;
+// End of a step (first: start of a call): step results of each instance from
+// its plain-tile records, then boundary_update.
+struct PlainSum {
+  double sp, mnJ, mxJ, hm, w4, me, mb;
+};
+
+__device__ __forceinline__ PlainSum reduce_plain_recs(const double* recs, int64_t k0, int64_t k1,
+                                                      bool first, int lane) {
   double sp = 0.0, mnJ = INFINITY, mxJ = 0.0, hm = INFINITY, w4 = 0.0, me = 0.0, mb = 0.0;
-  for (int64_t k = bf.pfirst[i] + lane; k < bf.pfirst[i + 1]; k += 64) {
-    const double* r = bf.prec + k * PREC;
-    sp = fmax(sp, r[0]);
-    mnJ = fmin(mnJ, r[1]);
-    mxJ = fmax(mxJ, r[2]);
-    hm = fmin(hm, r[3]);
-    w4 = fmax(w4, r[4]);
-    if (first) { me += r[5]; mb += r[6]; }
+  for (int64_t k = k0 + lane; k < k1; k += 64) {
+    const double* q = recs + k * PREC;
+    sp = fmax(sp, q[0]);
+    mnJ = fmin(mnJ, q[1]);
+    mxJ = fmax(mxJ, q[2]);
+    hm = fmin(hm, q[3]);
+    w4 = fmax(w4, q[4]);
+    if (first) { me += q[5]; mb += q[6]; }
   }
-  sp = wave_max(sp); mnJ = wave_min(mnJ); mxJ = wave_max(mxJ); hm = wave_min(hm);
-  w4 = wave_max(w4);
-  if (first) { me = wave_sum(me); mb = wave_sum(mb); }
+  PlainSum r;
+  r.sp = wave_max(sp); r.mnJ = wave_min(mnJ); r.mxJ = wave_max(mxJ); r.hm = wave_min(hm);
+  r.w4 = wave_max(w4);
+  r.me = first ? wave_sum(me) : 0.0;
+  r.mb = first ? wave_sum(mb) : 0.0;
+  return r;
+}
+
+__device__ __forceinline__ void put_plain_sum(double* q, const PlainSum& r) {
+  q[0] = r.sp; q[1] = r.mnJ; q[2] = r.mxJ; q[3] = r.hm; q[4] = r.w4; q[5] = r.me; q[6] = r.mb;
+}
+
+__device__ __forceinline__ void apply_boundary(const Bufs& bf, const Consts& cs, int i,
+                                               bool first, const PlainSum& r) {
+  Inst& I = bf.inst[i];
+  I.r_speed = dbits(r.sp);
+  I.r_minJ = dbits(r.mnJ);
+  I.r_maxJ = dbits(r.mxJ);
+  const unsigned long long hk = okey(r.hm);
+  if (hk < I.r_hmin) I.r_hmin = hk;
+  if (first) {
+    I.mass_eta0 = r.me;
+    I.mass_b0 = r.mb;
+    if (cs.mesh == MESH_SINE || cs.mesh == MESH_PAPER) I.smax = r.w4;
+  }
+  if (cs.mesh == MESH_GIVEN || cs.mesh == MESH_FLUID) I.r_W = dbits(r.w4);
+  boundary_update(I, cs, bf, i, first);
+}
+
+// One wave per plain-record chunk; a chunk that holds a whole instance
+// finishes it, others leave a partial result.
+__global__ __launch_bounds__(256) void k_boundary(Bufs bf, Consts cs, int64_t nchunks, int first) {
+  const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (c >= nchunks) return;
+  const RChunk ch = bf.pchunk[c];
+  if (!bf.inst[ch.inst].active) return;
+  const PlainSum r = reduce_plain_recs(bf.prec, ch.k0, ch.k1, first != 0, lane);
   if (lane == 0) {
-    I.r_speed = dbits(sp);
-    I.r_minJ = dbits(mnJ);
-    I.r_maxJ = dbits(mxJ);
-    const unsigned long long hk = okey(hm);
-    if (hk < I.r_hmin) I.r_hmin = hk;
-    if (first) {
-      I.mass_eta0 = me;
-      I.mass_b0 = mb;
-      if (cs.mesh == MESH_SINE || cs.mesh == MESH_PAPER) I.smax = w4;
-    }
-    if (cs.mesh == MESH_GIVEN || cs.mesh == MESH_FLUID) I.r_W = dbits(w4);
-    boundary_update(I, cs, bf, i, first != 0);
+    if (ch.whole) apply_boundary(bf, cs, ch.inst, first != 0, r);
+    else put_plain_sum(bf.pcrec + c * PREC, r);
   }
 }
 
-// Stage results of each instance from its stage-tile records (one wave per
-// instance): LF speed, indicator scale of the next stage, statistics.
-__global__ __launch_bounds__(256) void k_after_stage(Bufs bf, int s) {
+// Second pass for instances split over several chunks (one wave per instance;
+// the masses of a split instance are summed chunk by chunk, in chunk order).
+__global__ __launch_bounds__(256) void k_boundary_split(Bufs bf, Consts cs, int first) {
   const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (i >= bf.ninst) return;
-  Inst& I = bf.inst[i];
-  if (!I.active) return;
+  if (!bf.inst[i].active || bf.pcfirst[i + 1] - bf.pcfirst[i] < 2) return;
+  const PlainSum r = reduce_plain_recs(bf.pcrec, bf.pcfirst[i], bf.pcfirst[i + 1], first != 0, lane);
+  if (lane == 0) apply_boundary(bf, cs, i, first != 0, r);
+}
+
+// Stage results of an instance from records [k0, k1) (tile records, or the
+// partial results of its chunks: same layout), reduced by one wave.
+struct StageSum {
+  double a, mj, ak;
+  unsigned n0, n1, n2, nl, nn, stt;
+};
+
+__device__ __forceinline__ StageSum reduce_stage_recs(const double* recs, int64_t k0, int64_t k1,
+                                                      bool keys, int lane) {
+  StageSum r;
   double a = 0.0, mj = 0.0;
   unsigned n0 = 0u, n1 = 0u, n2 = 0u, nl = 0u, nn = 0u, stt = 0u;
-  for (int64_t k = bf.sfirst[i] + lane; k < bf.sfirst[i + 1]; k += 64) {
-    const double* r = bf.srec + k * SREC;
-    a = fmax(a, r[0]);
-    mj = fmax(mj, r[1]);
-    n0 += (unsigned)r[2]; n1 += (unsigned)r[3]; n2 += (unsigned)r[4];
-    nl += (unsigned)r[5]; nn += (unsigned)r[6];
-    stt |= (unsigned)r[7];
+  for (int64_t k = k0 + lane; k < k1; k += 64) {
+    const double* q = recs + k * SREC;
+    a = fmax(a, q[0]);
+    mj = fmax(mj, q[1]);
+    n0 += (unsigned)q[2]; n1 += (unsigned)q[3]; n2 += (unsigned)q[4];
+    nl += (unsigned)q[5]; nn += (unsigned)q[6];
+    stt |= (unsigned)q[7];
   }
-  a = wave_max(a); mj = wave_max(mj);
-  n0 = wave_usum(n0); n1 = wave_usum(n1); n2 = wave_usum(n2);
-  nl = wave_usum(nl); nn = wave_usum(nn); stt = wave_or(stt);
+  r.a = wave_max(a); r.mj = wave_max(mj);
+  r.n0 = wave_usum(n0); r.n1 = wave_usum(n1); r.n2 = wave_usum(n2);
+  r.nl = wave_usum(nl); r.nn = wave_usum(nn); r.stt = wave_or(stt);
   double ak = 1e300;
-  if (bf.dump.akey) {
-    // first face trace of the instance attaining alpha: smallest key among
-    // the tiles whose LF speed is the instance's
-    for (int64_t k = bf.sfirst[i] + lane; k < bf.sfirst[i + 1]; k += 64) {
-      const double* r = bf.srec + k * SREC;
-      if (r[0] == a) ak = fmin(ak, r[8]);
+  if (keys) {
+    // first face trace attaining alpha: smallest key among the records whose
+    // LF speed is the reduced one
+    for (int64_t k = k0 + lane; k < k1; k += 64) {
+      const double* q = recs + k * SREC;
+      if (q[0] == r.a) ak = fmin(ak, q[8]);
     }
     ak = wave_min(ak);
   }
-  if (lane == 0) {
-    I.alpha[s - 1] = a;
-    if (s < 3) I.dx[s] = mj;
-    I.n_class[0] += n0; I.n_class[1] += n1; I.n_class[2] += n2;
-    I.n_limited += nl; I.n_negweight += nn;
-    if (stt) I.status |= (int)stt;
-    if (bf.dump.scal) {
-      bf.dump.scal[(int64_t)i * 8 + 1 + s] = I.alpha[s - 1];
-      if (s < 3) bf.dump.scal[(int64_t)i * 8 + 5 + s] = I.dx[s];
-    }
-    if (bf.dump.akey) bf.dump.akey[(int64_t)(s - 1) * bf.ninst + i] = ak;
+  r.ak = ak;
+  return r;
+}
+
+__device__ __forceinline__ void put_stage_sum(double* q, const StageSum& r) {
+  q[0] = r.a; q[1] = r.mj;
+  q[2] = (double)r.n0; q[3] = (double)r.n1; q[4] = (double)r.n2;
+  q[5] = (double)r.nl; q[6] = (double)r.nn; q[7] = (double)r.stt; q[8] = r.ak;
+}
+
+__device__ __forceinline__ void apply_stage(const Bufs& bf, int i, int s, const StageSum& r) {
+  Inst& I = bf.inst[i];
+  I.alpha[s - 1] = r.a;
+  if (s < 3) I.dx[s] = r.mj;
+  I.n_class[0] += r.n0; I.n_class[1] += r.n1; I.n_class[2] += r.n2;
+  I.n_limited += r.nl; I.n_negweight += r.nn;
+  if (r.stt) I.status |= (int)r.stt;
+  if (bf.dump.scal) {
+    bf.dump.scal[(int64_t)i * 8 + 1 + s] = I.alpha[s - 1];
+    if (s < 3) bf.dump.scal[(int64_t)i * 8 + 5 + s] = I.dx[s];
   }
+  if (bf.dump.akey) bf.dump.akey[(int64_t)(s - 1) * bf.ninst + i] = r.ak;
+}
+
+// After stage s: one wave per record chunk; a chunk that holds a whole
+// instance sets the instance's stage results, others leave a partial result.
+__global__ __launch_bounds__(256) void k_after_stage(Bufs bf, int64_t nchunks, int s) {
+  const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (c >= nchunks) return;
+  const RChunk ch = bf.schunk[c];
+  if (!bf.inst[ch.inst].active) return;
+  const StageSum r = reduce_stage_recs(bf.srec, ch.k0, ch.k1, bf.dump.akey != nullptr, lane);
+  if (lane == 0) {
+    if (ch.whole) apply_stage(bf, ch.inst, s, r);
+    else put_stage_sum(bf.screc + c * SREC, r);
+  }
+}
+
+// Second pass for instances split over several chunks (one wave per instance).
+__global__ __launch_bounds__(256) void k_after_stage_split(Bufs bf, int s) {
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= bf.ninst) return;
+  if (!bf.inst[i].active || bf.scfirst[i + 1] - bf.scfirst[i] < 2) return;
+  const StageSum r =
+      reduce_stage_recs(bf.screc, bf.scfirst[i], bf.scfirst[i + 1], bf.dump.akey != nullptr, lane);
+  if (lane == 0) apply_stage(bf, i, s, r);
 }
 
 // End of a call: h = eta - b, final nodes back into the caller's array, masses.
@@ -543,6 +617,14 @@ struct alew_ctx {
   double* prec = nullptr;          // per-tile step results
   int64_t* sfirst_d = nullptr;     // [max_inst+1] first stage / plain tile of each instance
   int64_t* pfirst_d = nullptr;
+  int64_t* scfirst_d = nullptr;    // [max_inst+1] first stage / plain record chunk
+  int64_t* pcfirst_d = nullptr;
+  RChunk* schunk_d = nullptr;      // record chunks (at most one per tile)
+  RChunk* pchunk_d = nullptr;
+  double* screc = nullptr;         // partial results of split instances
+  double* pcrec = nullptr;
+  int64_t n_schunks = 0, n_pchunks = 0;
+  bool split_s = false, split_p = false;  // some instance has several chunks
   int64_t tiles_cap = 0;
   int64_t n_tiles_edge = 0, n_tiles_inner = 0;
   int n_cu = 0;
@@ -647,9 +729,13 @@ alew_status build_tiles(alew_ctx* c, const int64_t* cell_off, int64_t ninst, int
       if (*tp_) (void)hipFree(*tp_);
       *tp_ = nullptr;
     }
-    for (double** rp : {&c->srec, &c->prec}) {
+    for (double** rp : {&c->srec, &c->prec, &c->screc, &c->pcrec}) {
       if (*rp) (void)hipFree(*rp);
       *rp = nullptr;
+    }
+    for (RChunk** cp : {&c->schunk_d, &c->pchunk_d}) {
+      if (*cp) (void)hipFree(*cp);
+      *cp = nullptr;
     }
     HIPCHK(hipMalloc(&c->tiles_stage_d, need * sizeof(Tile)));
     HIPCHK(hipMalloc(&c->tiles_plain_d, need * sizeof(Tile)));
@@ -657,8 +743,35 @@ alew_status build_tiles(alew_ctx* c, const int64_t* cell_off, int64_t ninst, int
     HIPCHK(hipMalloc(&c->tiles_inner_d, need * sizeof(Tile)));
     HIPCHK(hipMalloc(&c->srec, need * SREC * sizeof(double)));
     HIPCHK(hipMalloc(&c->prec, need * PREC * sizeof(double)));
+    HIPCHK(hipMalloc(&c->screc, need * SREC * sizeof(double)));
+    HIPCHK(hipMalloc(&c->pcrec, need * PREC * sizeof(double)));
+    HIPCHK(hipMalloc(&c->schunk_d, need * sizeof(RChunk)));
+    HIPCHK(hipMalloc(&c->pchunk_d, need * sizeof(RChunk)));
     c->tiles_cap = need;
   }
+  // record chunks: up to RCHUNK consecutive records of one instance
+  auto chunk = [&](const std::vector<int64_t>& first, std::vector<RChunk>& out,
+                   std::vector<int64_t>& cfirst, bool& split) {
+    split = false;
+    for (int64_t i = 0; i < ninst; ++i) {
+      cfirst[i] = (int64_t)out.size();
+      const int64_t a = first[i], e = first[i + 1];
+      const int32_t whole = e - a <= RCHUNK ? 1 : 0;
+      if (!whole) split = true;
+      for (int64_t k0 = a; k0 < e; k0 += RCHUNK)
+        out.push_back(RChunk{(int32_t)i, whole, k0, std::min<int64_t>(k0 + RCHUNK, e)});
+    }
+    cfirst[ninst] = (int64_t)out.size();
+  };
+  std::vector<RChunk> sch, pch;
+  std::vector<int64_t> scfirst(ninst + 1, 0), pcfirst(ninst + 1, 0);
+  bool split_s = false, split_p = false;
+  chunk(sfirst, sch, scfirst, split_s);
+  chunk(pfirst, pch, pcfirst, split_p);
+  HIPCHK(hipMemcpyAsync(c->scfirst_d, scfirst.data(), scfirst.size() * sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(c->pcfirst_d, pcfirst.data(), pcfirst.size() * sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(c->schunk_d, sch.data(), sch.size() * sizeof(RChunk), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(c->pchunk_d, pch.data(), pch.size() * sizeof(RChunk), hipMemcpyHostToDevice, c->stream));
   HIPCHK(hipMemcpyAsync(c->sfirst_d, sfirst.data(), sfirst.size() * sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
   HIPCHK(hipMemcpyAsync(c->pfirst_d, pfirst.data(), pfirst.size() * sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
   HIPCHK(hipMemcpyAsync(c->tiles_stage_d, ts.data(), ts.size() * sizeof(Tile), hipMemcpyHostToDevice, c->stream));
@@ -685,6 +798,10 @@ alew_status build_tiles(alew_ctx* c, const int64_t* cell_off, int64_t ninst, int
   c->n_tiles_plain = (int64_t)tp.size();
   c->n_tiles_edge = (int64_t)te.size();
   c->n_tiles_inner = (int64_t)tin.size();
+  c->n_schunks = (int64_t)sch.size();
+  c->n_pchunks = (int64_t)pch.size();
+  c->split_s = split_s;
+  c->split_p = split_p;
   if (c->gexec) { (void)hipGraphExecDestroy(c->gexec); c->gexec = nullptr; }
   if (c->graph) { (void)hipGraphDestroy(c->graph); c->graph = nullptr; }
   return ALEW_OK;
@@ -702,6 +819,9 @@ Bufs make_bufs(alew_ctx* c, int64_t S, int64_t ninst, double* hu, double* b, con
   bf.S = S; bf.ninst = (int32_t)ninst; bf.pad = 0;
   bf.srec = c->srec; bf.prec = c->prec;
   bf.sfirst = c->sfirst_d; bf.pfirst = c->pfirst_d;
+  bf.schunk = c->schunk_d; bf.pchunk = c->pchunk_d;
+  bf.scfirst = c->scfirst_d; bf.pcfirst = c->pcfirst_d;
+  bf.screc = c->screc; bf.pcrec = c->pcrec;
   bf.dump = Dump{nullptr, nullptr, nullptr, nullptr, nullptr};
   return bf;
 }
@@ -729,6 +849,25 @@ void kt_end(alew_ctx* c, hipStream_t st, int k) {
   if (k >= 0) (void)hipEventRecord(c->kt_ev[2 * (size_t)k + 1], st);
 }
 
+// Per-instance reductions of the stage and plain tile records: a wave per
+// record chunk, and a second pass only when some instance is split.
+void launch_after_stage(const alew_ctx* c, const Bufs& bf, hipStream_t st, int s) {
+  hipLaunchKernelGGL(k_after_stage, dim3((unsigned)((c->n_schunks + 3) / 4)), dim3(256), 0, st, bf,
+                     c->n_schunks, s);
+  if (c->split_s)
+    hipLaunchKernelGGL(k_after_stage_split, dim3((unsigned)((bf.ninst + 3) / 4)), dim3(256), 0, st,
+                       bf, s);
+}
+
+void launch_boundary(const alew_ctx* c, const Bufs& bf, const Consts& cs, hipStream_t st,
+                     int first) {
+  hipLaunchKernelGGL(k_boundary, dim3((unsigned)((c->n_pchunks + 3) / 4)), dim3(256), 0, st, bf, cs,
+                     c->n_pchunks, first);
+  if (c->split_p)
+    hipLaunchKernelGGL(k_boundary_split, dim3((unsigned)((bf.ninst + 3) / 4)), dim3(256), 0, st, bf,
+                       cs, first);
+}
+
 template <int B, int CPT>
 void launch_step_seq(alew_ctx* c, const Bufs& bf, const Consts& cs, hipStream_t st, int64_t step) {
   const int par = (int)(step & 1);
@@ -742,14 +881,14 @@ void launch_step_seq(alew_ctx* c, const Bufs& bf, const Consts& cs, hipStream_t 
       hipLaunchKernelGGL((k_stage<B, CPT, false>), gs, dim3(B), 0, st, bf, cs, c->tiles_stage_d, s,
                          par);
     kt_end(c, st, kt);
-    hipLaunchKernelGGL(k_after_stage, dim3((unsigned)((bf.ninst + 3) / 4)), dim3(256), 0, st, bf, s);
+    launch_after_stage(c, bf, st, s);
   }
   const int kf = kt_begin(c, st, 1, (double)bf.S);
   hipLaunchKernelGGL(k_final<PB>, gp, dim3(PB), 0, st, bf, cs, c->tiles_plain_d);
   kt_end(c, st, kf);
   if (cs.mesh == MESH_FLUID)
     hipLaunchKernelGGL(k_wfluid<PB>, gp, dim3(PB), 0, st, bf, cs, c->tiles_plain_d);
-  hipLaunchKernelGGL(k_boundary, dim3((unsigned)((bf.ninst + 3) / 4)), dim3(256), 0, st, bf, cs, 0);
+  launch_boundary(c, bf, cs, st, 0);
 }
 
 // Step sequence for a run-time tile shape (block B, CPT cells per thread).
@@ -933,7 +1072,7 @@ alew_status drive(alew_ctx* c, const alew_params* p, int64_t ninst, const int64_
     hipLaunchKernelGGL(k_prep<PB>, gp, dim3(PB), 0, c->stream, bf, cs, c->tiles_plain_d, h, wgiven); \
     if (cs.mesh == MESH_FLUID)                                                                  \
       hipLaunchKernelGGL(k_wfluid<PB>, gp, dim3(PB), 0, c->stream, bf, cs, c->tiles_plain_d);  \
-    hipLaunchKernelGGL(k_boundary, dim3((unsigned)((ninst + 3) / 4)), dim3(256), 0, c->stream, bf, cs, 1); \
+    launch_boundary(c, bf, cs, c->stream, 1);                                                 \
     HIPCHK(hipGetLastError());                                                                  \
     alew_status rs = (engine == 1) ? run_persistent<BB>(c, bf, cs, ninst)                       \
                                    : run_stages<BB>(c, bf, cs, max_iters, CPT);                 \
@@ -1046,6 +1185,8 @@ alew_status alew_create(alew_ctx** out, int64_t max_cells, int64_t max_inst, voi
             alloc((void**)&c->cell_off_d, (max_inst + 1) * sizeof(int64_t)) &&
             alloc((void**)&c->sfirst_d, (max_inst + 1) * sizeof(int64_t)) &&
             alloc((void**)&c->pfirst_d, (max_inst + 1) * sizeof(int64_t)) &&
+            alloc((void**)&c->scfirst_d, (max_inst + 1) * sizeof(int64_t)) &&
+            alloc((void**)&c->pcfirst_d, (max_inst + 1) * sizeof(int64_t)) &&
             alloc((void**)&c->order_d, max_inst * sizeof(int32_t)) &&
             alloc((void**)&c->queue_d, sizeof(unsigned)) && alloc((void**)&c->nactive_d, sizeof(int)) &&
             alloc((void**)&c->dt1_d, sizeof(double));
@@ -1069,6 +1210,7 @@ void alew_destroy(alew_ctx* c) {
   void* ps[] = {c->eta, c->P0, c->D0, c->P1, c->D1, c->w, c->xa, c->xb, c->inst, c->cell_off_d,
                 c->order_d, c->queue_d, c->nactive_d, c->tiles_stage_d, c->tiles_plain_d,
                 c->tiles_edge_d, c->tiles_inner_d, c->srec, c->prec, c->sfirst_d, c->pfirst_d,
+                c->scfirst_d, c->pcfirst_d, c->schunk_d, c->pchunk_d, c->screc, c->pcrec,
                 c->dt1_d,
                 c->adj_ws};
   for (void* p : ps)
@@ -1245,7 +1387,7 @@ alew_status alew_adjoint(alew_ctx* c, const alew_params* p, int64_t ninst,
   };
   auto xbuf_of = [&](int64_t k) { return (k & 1) ? c->xb : c->xa; };
   hipLaunchKernelGGL(k_prep<256>, gp, dim3(256), 0, st, bf, cs, c->tiles_plain_d, h0, nullptr);
-  hipLaunchKernelGGL(k_boundary, dim3((unsigned)((ninst + 3) / 4)), dim3(256), 0, st, bf, cs, 1);
+  launch_boundary(c, bf, cs, st, 1);
   // forward with checkpoints; when a gradient follows, the last segment keeps
   // its records right away (the reverse sweep starts there)
   const int64_t qlast = nck - 1, klast = qlast * K;

@@ -14,6 +14,16 @@ struct Dump {
   double* scal_next;  // the next step's record (t, dt, dx_0 are set at step end)
 };
 
+// Up to RCHUNK consecutive tile records of one instance, reduced by one wave.
+// An instance with more records has several chunks; their partial results are
+// reduced by a second pass (max, min and integer sums: order-free, exact).
+enum { RCHUNK = 512 };
+struct RChunk {
+  int32_t inst;
+  int32_t whole;  // 1 if the chunk holds every record of its instance
+  int64_t k0, k1;
+};
+
 // Buffers of a packed batch.  Component c of a 3-vector array V lives at
 // V + c * S, S = total cell count.  Node arrays hold ncell+1 entries per
 // instance (node offset of instance i = cell_off[i] + i).
@@ -42,6 +52,12 @@ struct Bufs {
   double* prec;            // [plain tiles][PREC] per-tile step results
   const int64_t* sfirst;   // [ninst+1] first stage tile of each instance
   const int64_t* pfirst;   // [ninst+1] first plain tile of each instance
+  const RChunk* schunk;    // record chunks of the stage / plain tables
+  const RChunk* pchunk;
+  const int64_t* scfirst;  // [ninst+1] first stage / plain chunk of each instance
+  const int64_t* pcfirst;
+  double* screc;           // [stage chunks][SREC] partial results of split instances
+  double* pcrec;           // [plain chunks][PREC]
   Dump dump;
 };
 

@@ -243,6 +243,37 @@ def test_stage_tile_shapes_many_tiles(dev):
         _assert_parity(g, r)
 
 
+def test_instance_split_over_record_chunks(dev):
+    """An instance of 140,000 cells has more stage and plain tiles than one
+    reduction chunk holds (its per-stage and per-step results are reduced in
+    two passes), next to a small one: both match the oracle, with identical
+    class counts and step sizes."""
+    insts = [W.perturbation_instance(140000, 5e-3), W.perturbation_instance(1500, 2e-3)]
+    bt = W.pack(insts, bc="transmissive", t_end=0.2, cfl=0.6, weno_eps=1e-9, mesh="sine",
+                mesh_A=0.05, mesh_k=1.0, mesh_omega=math.pi)
+    off = bt["cell_off"]
+    n, ninst = int(off[-1]), len(off) - 1
+    p = _gp(bt)
+    nsteps = 4
+    ctx = alew.Context(n, ninst)
+    ctx.set_launch(engine=alew.ENGINE_STAGES, use_graph=1)
+    T = {k: _t(bt[k], dev) for k in ("h", "hu", "b", "x", "xi")}
+    st = ctx.run(p, off, T["h"], T["hu"], T["b"], T["x"], T["xi"], max_steps=[nsteps] * ninst)
+    torch.cuda.synchronize()
+    G = {k: v.cpu().numpy() for k, v in T.items()}
+    for i in range(ninst):
+        a, e = int(off[i]), int(off[i + 1])
+        r = O.run(_op(bt), bt["h"][a:e], bt["hu"][a:e], bt["b"][a:e], bt["x"][a + i:e + i + 1],
+                  bt["xi"][a + i:e + i + 1], max_steps=nsteps)
+        g = dict(h=G["h"][a:e], hu=G["hu"][a:e], b=G["b"][a:e], x=G["x"][a + i:e + i + 1])
+        _assert_parity(g, r)
+        assert st[i].steps == nsteps and st[i].status == 0
+        assert tuple(st[i].n_class) == tuple(r["stats"].n_class)
+        assert abs(st[i].dt_min - r["stats"].dt_min) <= 1e-13 * r["stats"].dt_min
+        # the oracle sums the cells in order: its rounding error bound grows with n
+        assert abs(st[i].mass_eta0 - r["stats"].mass_eta0) <= (e - a) * 2.3e-16 * abs(r["stats"].mass_eta0)
+
+
 def test_batched_to_t_end_matches_per_instance(dev):
     """Instances of different sizes run to the same end time with their own
     step sizes in one call; each equals a one-instance call."""

@@ -152,17 +152,35 @@ __global__ __launch_bounds__(B) void k_stage(Bufs bf, Consts cs, const Tile* __r
 }
 
 template <int B>
-__global__ __launch_bounds__(B) void k_final(Bufs bf, Consts cs, const Tile* __restrict__ tiles) {
+// par is the parity of the step (x^n in xa or xb); the cell loads go out
+// before the instance record is read (scalar loads through the constant
+// address space: no instance record is written while this kernel runs).
+__global__ __launch_bounds__(B) void k_final(Bufs bf, Consts cs, const Tile* __restrict__ tiles,
+                                             int par) {
   __shared__ double red[(B / 64) * 8];
   const Tile tl = tiles[blockIdx.x];
-  Inst& I = bf.inst[tl.inst];
-  if (!I.active) return;
-  View v = make_view(bf, tl.inst, I);
-  FinalRes r = final_tile<B>(bf, cs, v, I.dt, I.alpha[2], I.wscale, tl.c0, red);
+  View v;
+  v.n = tl.n;
+  v.co = tl.co;
+  v.no = tl.co + tl.inst;
+  v.x = (par ? bf.xb : bf.xa) + v.no;
+  v.xnew = (par ? bf.xa : bf.xb) + v.no;
+  const int64_t j = tl.c0 + threadIdx.x;
+  const bool cell = j < v.n;
+  FinalRaw raw;
+  if (cell) raw = final_load(bf, v, j);
+  typedef const __attribute__((address_space(4))) Inst* cinst;
+  const cinst I = (cinst)bf.inst + tl.inst;
+  if (!I->active) return;
+  int st = ((int)(I->steps & 1) != par) ? SB_SEQUENCE : 0;
+  double speed = 0.0, minJ = INFINITY, maxJ = 0.0, hmin = INFINITY;
+  if (cell)
+    final_cell(bf, cs, v, j, raw, I->dt, I->alpha[2], I->wscale, speed, minJ, maxJ, hmin, st);
+  const FinalRes r = final_reduce<B>(speed, minJ, maxJ, hmin, st, red);
   if (threadIdx.x == 0) {
     double* d = bf.prec + (int64_t)tl.rec * PREC;
     d[0] = r.speed; d[1] = r.minJ; d[2] = r.maxJ; d[3] = r.hmin;
-    if (r.status) atomicOr(&I.status, r.status);  // rare: a failed cell
+    if (r.status) atomicOr(&bf.inst[tl.inst].status, r.status);  // rare: a failed cell
   }
 }
 
@@ -884,7 +902,7 @@ void launch_step_seq(alew_ctx* c, const Bufs& bf, const Consts& cs, hipStream_t 
     launch_after_stage(c, bf, st, s);
   }
   const int kf = kt_begin(c, st, 1, (double)bf.S);
-  hipLaunchKernelGGL(k_final<PB>, gp, dim3(PB), 0, st, bf, cs, c->tiles_plain_d);
+  hipLaunchKernelGGL(k_final<PB>, gp, dim3(PB), 0, st, bf, cs, c->tiles_plain_d, par);
   kt_end(c, st, kf);
   if (cs.mesh == MESH_FLUID)
     hipLaunchKernelGGL(k_wfluid<PB>, gp, dim3(PB), 0, st, bf, cs, c->tiles_plain_d);

@@ -569,62 +569,101 @@ struct FinalRes {
   int status;
 };
 
+// Raw values of cell j: its two nodes and node speeds, P and D of stage 3.
+struct FinalRaw {
+  double x0, x1, w0, w1, p0, p1, p2, d0, d1, d2;
+};
+
+__device__ __forceinline__ FinalRaw final_load(const Bufs& bf, const View& v, int64_t j) {
+  FinalRaw r;
+  r.x0 = v.x[j]; r.x1 = v.x[j + 1];
+  r.w0 = bf.w[v.no + j]; r.w1 = bf.w[v.no + j + 1];
+  const int64_t gi = v.co + j;
+  r.p0 = bf.P0[gi]; r.p1 = bf.P0[bf.S + gi]; r.p2 = bf.P0[2 * bf.S + gi];
+  r.d0 = bf.D0[gi]; r.d1 = bf.D0[bf.S + gi]; r.d2 = bf.D0[2 * bf.S + gi];
+  return r;
+}
+
+// New state and nodes of cell j (< n) from its raw values; the cell's part
+// of the reductions and its status bits.
+__device__ __forceinline__ void final_cell(const Bufs& bf, const Consts& cs, const View& v,
+                                           int64_t j, const FinalRaw& r, double dt, double alpha3,
+                                           double wsc, double& speed, double& minJ, double& maxJ,
+                                           double& hmin, int& st) {
+  const double x0 = r.x0, x1 = r.x1;
+  const double w0 = r.w0 * wsc, w1 = r.w1 * wsc;
+  const double Jn = x1 - x0, dw = w1 - w0;
+  const double J1 = Jn + dt * dw;
+  const double J2 = 0.75 * Jn + 0.25 * (J1 + dt * dw);
+  const double J3 = (1.0 / 3.0) * Jn + (2.0 / 3.0) * (J2 + dt * dw);
+  const double c = (2.0 / 3.0) * dt * alpha3;
+  const int64_t gi = v.co + j;
+  const double iJ3 = frcp(J3);
+  const double e = (r.p0 + c * r.d0) * iJ3;
+  const double m = (r.p1 + c * r.d1) * iJ3;
+  const double b = (r.p2 + c * r.d2) * iJ3;
+  bf.eta[gi] = e; bf.m[gi] = m; bf.b[gi] = b;
+  const double xn0 = x0 + dt * w0, xn1 = x1 + dt * w1;
+  if (bf.dump.xw) {
+    const int64_t NN = bf.S + bf.ninst;
+    bf.dump.xw[v.no + j] = x0;
+    bf.dump.xw[NN + v.no + j] = w0;
+    if (j == v.n - 1) {
+      bf.dump.xw[v.no + v.n] = x1;
+      bf.dump.xw[NN + v.no + v.n] = w1;
+    }
+  }
+  v.xnew[j] = xn0;
+  if (j == v.n - 1) v.xnew[v.n] = xn1;
+  const double Jnew = xn1 - xn0;
+  const double h = e - b;
+  const double u = h > cs.dry_eps ? m / h : 0.0;
+  speed = fabs(u) + sqrt(cs.g * fmax(h, 0.0));
+  minJ = Jnew; maxJ = Jnew; hmin = h;
+  if (!(J3 > 0.0) || !(Jnew > 0.0)) st |= SB_MESH;
+  if (!isfinite(e) || !isfinite(m) || !isfinite(b)) st |= SB_NONFINITE;
+  if (h < -cs.pp_eps) st |= SB_NEGDEPTH;
+}
+
+// Reductions of an epilogue tile; the status bits through one ballot per
+// bit and wave.  red holds B / 64 * 8 doubles (its first slots are reused).
+template <int B>
+__device__ __forceinline__ FinalRes final_reduce(double speed, double minJ, double maxJ,
+                                                 double hmin, int st, double* red) {
+  constexpr int NW = B / 64;
+  const int t = threadIdx.x;
+  unsigned stw = 0u;
+#pragma unroll
+  for (int bit = 1; bit <= SB_SEQUENCE; bit <<= 1)
+    if (__ballot((st & bit) != 0)) stw |= (unsigned)bit;
+  double rv[4] = {speed, minJ, maxJ, hmin};
+  const int op[4] = {0, 1, 0, 1};
+  block_reduce<B, 4>(rv, op, red);
+  __shared__ unsigned stws[NW];
+  if ((t & 63) == 0) stws[t >> 6] = stw;
+  __syncthreads();
+  FinalRes r;
+  r.speed = rv[0]; r.minJ = rv[1]; r.maxJ = rv[2]; r.hmin = rv[3];
+  unsigned sa = 0u;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) sa |= stws[w];
+  r.status = (int)sa;
+  __syncthreads();
+  return r;
+}
+
 template <int B>
 __device__ __forceinline__ FinalRes final_tile(const Bufs& bf, const Consts& cs, const View& v,
                                                double dt, double alpha3, double wsc, int64_t c0,
                                                double* red) {
-  const int t = threadIdx.x;
-  const int64_t j = c0 + t;
+  const int64_t j = c0 + threadIdx.x;
   int st = 0;
   double speed = 0.0, minJ = INFINITY, maxJ = 0.0, hmin = INFINITY;
   if (j < v.n) {
-    const double x0 = v.x[j], x1 = v.x[j + 1];
-    const double w0 = bf.w[v.no + j] * wsc, w1 = bf.w[v.no + j + 1] * wsc;
-    const double Jn = x1 - x0, dw = w1 - w0;
-    const double J1 = Jn + dt * dw;
-    const double J2 = 0.75 * Jn + 0.25 * (J1 + dt * dw);
-    const double J3 = (1.0 / 3.0) * Jn + (2.0 / 3.0) * (J2 + dt * dw);
-    const double c = (2.0 / 3.0) * dt * alpha3;
-    const int64_t gi = v.co + j;
-    const double iJ3 = frcp(J3);
-    const double e = (bf.P0[gi] + c * bf.D0[gi]) * iJ3;
-    const double m = (bf.P0[bf.S + gi] + c * bf.D0[bf.S + gi]) * iJ3;
-    const double b = (bf.P0[2 * bf.S + gi] + c * bf.D0[2 * bf.S + gi]) * iJ3;
-    bf.eta[gi] = e; bf.m[gi] = m; bf.b[gi] = b;
-    const double xn0 = x0 + dt * w0, xn1 = x1 + dt * w1;
-    if (bf.dump.xw) {
-      const int64_t NN = bf.S + bf.ninst;
-      bf.dump.xw[v.no + j] = x0;
-      bf.dump.xw[NN + v.no + j] = w0;
-      if (j == v.n - 1) {
-        bf.dump.xw[v.no + v.n] = x1;
-        bf.dump.xw[NN + v.no + v.n] = w1;
-      }
-    }
-    v.xnew[j] = xn0;
-    if (j == v.n - 1) v.xnew[v.n] = xn1;
-    const double Jnew = xn1 - xn0;
-    const double h = e - b;
-    const double u = h > cs.dry_eps ? m / h : 0.0;
-    speed = fabs(u) + sqrt(cs.g * fmax(h, 0.0));
-    minJ = Jnew; maxJ = Jnew; hmin = h;
-    if (!(J3 > 0.0) || !(Jnew > 0.0)) st |= SB_MESH;
-    if (!isfinite(e) || !isfinite(m) || !isfinite(b)) st |= SB_NONFINITE;
-    if (h < -cs.pp_eps) st |= SB_NEGDEPTH;
+    const FinalRaw r = final_load(bf, v, j);
+    final_cell(bf, cs, v, j, r, dt, alpha3, wsc, speed, minJ, maxJ, hmin, st);
   }
-  double rv[4] = {speed, minJ, maxJ, hmin};
-  const int op[4] = {0, 1, 0, 1};
-  block_reduce<B, 4>(rv, op, red);
-  __syncthreads();
-  if (t == 0) red[0] = 0.0;
-  __syncthreads();
-  if (st) atomicOr((int*)&red[0], st);
-  __syncthreads();
-  FinalRes r;
-  r.speed = rv[0]; r.minJ = rv[1]; r.maxJ = rv[2]; r.hmin = rv[3];
-  r.status = *(int*)&red[0];
-  __syncthreads();
-  return r;
+  return final_reduce<B>(speed, minJ, maxJ, hmin, st, red);
 }
 
 // Shape function of the prescribed mesh map.

@@ -124,7 +124,7 @@ __global__ __launch_bounds__(B) void k_stage(Bufs bf, Consts cs, const Tile* __r
   constexpr int TB = B * CPT;
   constexpr int NR = NOEXT ? TB - 4 : TB;
   __shared__ SmemStage<B, CPT> sm;
-  const Tile tl = tiles[blockIdx.x];
+  const Tile tl = tiles[xcd_tile(blockIdx.x, gridDim.x)];
   View v;
   int st = 0;
   if (tile_inner<NOEXT ? TB : TB + 4>(tl.n, tl.c0)) {

@@ -135,6 +135,15 @@ __device__ __forceinline__ double ldo(const double* base, unsigned off) {
   return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(base) + off);
 }
 
+// Work-group b of a G-group launch is dispatched to XCD b mod 8; this maps
+// the groups of each XCD onto one contiguous eighth of the tile table, so
+// that neighbouring tiles, whose stencils share the cache lines at the tile
+// ends, run on the same XCD and meet in its L2.
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t G) {
+  const int64_t x = b & 7, q = G >> 3, r = G & 7;
+  return x * q + (x < r ? x : r) + (b >> 3);
+}
+
 // Stage inputs of one stencil slot from its raw loads: x^n and w of the two
 // nodes, and either q^n (stage 1) or P, D of the previous stage together with
 // q^n of the cell (stages 2, 3).  ms = -1 mirrors hu (reflective ghosts).

@@ -119,7 +119,7 @@ struct SmemStage {
     struct {
       double e[TB + 4], m[TB + 4], b[TB + 4], J[TB + 4], iJ[TB + 4];
     } in;
-    double fl[8][TB];
+    double fl[7][TB];
   } u;
   double wn[TB + 4];     // node speed at the left node of slot i (nodes 0..n)
   double qn[3][TB + 4];  // a_s Q^n of owned slots (stages 2 and 3)
@@ -417,8 +417,10 @@ __device__ __forceinline__ StageRes stage_compute(const Bufs& bf, const Consts& 
       }
       Face f;
       face_flux(tp0[c], tp1[c], tp2[c], tl0[c], tl1[c], tl2[c], sm.wn[i + 2], cs.g, cs.dry_eps, f);
-      sm.u.fl[0][i] = f.Fc1; sm.u.fl[1][i] = f.Fc2; sm.u.fl[2][i] = f.Gc; sm.u.fl[3][i] = f.je;
-      sm.u.fl[4][i] = f.jm; sm.u.fl[5][i] = f.jb; sm.u.fl[6][i] = f.B1; sm.u.fl[7][i] = f.B2;
+      // the g/2 b^2 part of the special source joins the momentum flux at the
+      // face (one LDS array less; still water still cancels to round-off)
+      sm.u.fl[0][i] = f.Fc1; sm.u.fl[1][i] = f.Fc2 - 0.5 * cs.g * f.B2; sm.u.fl[2][i] = f.Gc;
+      sm.u.fl[3][i] = f.je; sm.u.fl[4][i] = f.jm; sm.u.fl[5][i] = f.jb; sm.u.fl[6][i] = f.B1;
       fspeed = fmax(fspeed, f.speed);
       fsl[c] = f.sl;
       fsr[c] = f.sr;
@@ -439,7 +441,7 @@ __device__ __forceinline__ StageRes stage_compute(const Bufs& bf, const Consts& 
       const double(*fl)[TB] = sm.u.fl;
       const double eb = ebar[c], mb = mbar[c], bb = bbar[c], Jc = Jj[c];
       const double Ae = -(fl[0][i + 1] - fl[0][i]);
-      const double S = 0.5 * g * (fl[7][i + 1] - fl[7][i]) - g * eb * (fl[6][i + 1] - fl[6][i]) - g * rint[c];
+      const double S = -g * eb * (fl[6][i + 1] - fl[6][i]) - g * rint[c];
       const double Am = -(fl[1][i + 1] - fl[1][i]) + S;
       const double Ab = -(fl[2][i + 1] - fl[2][i]);
       const double De = 0.5 * (fl[3][i + 1] - fl[3][i]);

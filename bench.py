@@ -63,6 +63,28 @@ def load_counters(kernel):
     return e
 
 
+def copy_bandwidth(nbytes=4 << 30, reps=10):
+    """Device-to-device copy of nbytes, timed with events over reps copies:
+    bytes read + written per second (GB/s), the practical HBM rate for
+    streaming work on this GPU (context for the 8 TB/s peak)."""
+    import torch
+    n = nbytes // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    del a, b
+    torch.cuda.empty_cache()
+    return round(2.0 * n * 8 * reps / (ms / 1e3) / 1e9, 1)
+
+
 def roofline(ctx, p, off, T, tnow, L, S, kern_ms, launches, steps):
     """Roofline object of the dominant kernel.  For the stage-launch engine the
     same number of steps runs once more with an event pair around every stage
@@ -104,6 +126,7 @@ def roofline(ctx, p, off, T, tnow, L, S, kern_ms, launches, steps):
                 timing="HIP events on the library stream around each launch")
     if epi is not None:
         roof["step_epilogue"] = epi
+    roof["copy_gbs"] = copy_bandwidth()
     c = load_counters(kernel)
     if c is not None:
         cells_per_launch = S

@@ -3,9 +3,11 @@
 //
 // Two engines run the same tile bodies (alew_kernels.h):
 //  * stage launches: each kernel covers every tile of every active instance;
-//    per-instance reductions (LF speed, widths, step-size inputs) go through
-//    integer atomics on IEEE bit patterns, so they are order independent.  One
-//    time step is 9-10 launches; a 2-step sequence is replayed as a hipGraph.
+//    every tile writes a record of its results (LF speed, widths, counts,
+//    status), and the per-instance reductions of the records (maxima, minima,
+//    integer counts: order independent) run as small launches between the
+//    stage kernels.  One time step is 9-10 launches; a 2-step sequence is
+//    replayed as a hipGraph.
 //  * persistent: one launch runs a whole ragged batch.  A work-group takes the
 //    next instance from a device queue (largest first), runs all of its steps
 //    with work-group reductions only, and takes the next one.

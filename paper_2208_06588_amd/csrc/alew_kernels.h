@@ -367,10 +367,12 @@ __device__ __forceinline__ StageRes stage_compute(const Bufs& bf, const Consts& 
       const double* se = sm.u.in.e + i;
       const double* sb = sm.u.in.b + i;
       double h5[5], v5[5];
+      // indicator variable: h (fb = 1) or eta (fb = 0), exact either way
+      const double fb = (cs.flags & F_BETA_FROM_H) ? 1.0 : 0.0;
 #pragma unroll
       for (int k = 0; k < 5; ++k) {
         h5[k] = se[k] - sb[k];
-        v5[k] = (cs.flags & F_BETA_FROM_H) ? h5[k] : se[k];
+        v5[k] = fma(-fb, sb[k], se[k]);
       }
       const double hbar = h5[2];
       ebar[c] = se[2]; mbar[c] = sm.u.in.m[i + 2]; bbar[c] = sb[2]; Jj[c] = sm.u.in.J[i + 2];

@@ -311,13 +311,14 @@ __device__ __forceinline__ void stage_load(const Bufs& bf, const Consts& cs, con
   }
 }
 
-// Double as two 32-bit lanes through ds_bpermute: value of lane (lane - 1)
-// (lane 0 receives its own value).
+// Value of lane (lane - 1) of a double (lane 0 keeps its own): two DPP row
+// moves with the wave-wide right shift by one lane, no LDS traffic.
 __device__ __forceinline__ double shfl_prev(double x, int lane) {
-  const int addr = (lane == 0 ? 0 : lane - 1) << 2;
+  (void)lane;
   const long long u = __double_as_longlong(x);
-  const int lo = __builtin_amdgcn_ds_bpermute(addr, (int)(u & 0xffffffffll));
-  const int hi = __builtin_amdgcn_ds_bpermute(addr, (int)(u >> 32));
+  const int lo0 = (int)(u & 0xffffffffll), hi0 = (int)(u >> 32);
+  const int lo = __builtin_amdgcn_update_dpp(lo0, lo0, 0x138, 0xf, 0xf, false);  // wave_shr:1
+  const int hi = __builtin_amdgcn_update_dpp(hi0, hi0, 0x138, 0xf, 0xf, false);
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 

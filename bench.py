@@ -85,7 +85,7 @@ def copy_bandwidth(nbytes=4 << 30, reps=10):
     return round(2.0 * n * 8 * reps / (ms / 1e3) / 1e9, 1)
 
 
-def roofline(ctx, p, off, T, tnow, L, S, kern_ms, launches, steps):
+def roofline(ctx, p, off, T, tnow, L, S, kern_ms, launches, steps, copy_bw=True):
     """Roofline object of the dominant kernel.  For the stage-launch engine the
     same number of steps runs once more with an event pair around every stage
     launch (no graph); achieved = the method's bytes per cell and stage (256/3 B)
@@ -126,7 +126,8 @@ def roofline(ctx, p, off, T, tnow, L, S, kern_ms, launches, steps):
                 timing="HIP events on the library stream around each launch")
     if epi is not None:
         roof["step_epilogue"] = epi
-    roof["copy_gbs"] = copy_bandwidth()
+    if copy_bw:  # (profiler runs calibrate their byte counters with a copy of their own)
+        roof["copy_gbs"] = copy_bandwidth()
     c = load_counters(kernel)
     if c is not None:
         cells_per_launch = S
@@ -285,6 +286,9 @@ def main():
     ap.add_argument("--adj-cells", type=int, default=65536)
     ap.add_argument("--adj-steps", type=int, default=200)
     ap.add_argument("--no-bowl", action="store_true", help="skip the 2^24-cell wet/dry run")
+    ap.add_argument("--full-run", action="store_true",
+                    help="also time the whole batch to t = 0.2 (every instance its own CFL steps; "
+                         "about a minute)")
     ap.add_argument("--bowl-steps", type=int, default=20)
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="first copy a buffer of this many MiB (calibrates profiler byte counters)")
@@ -351,7 +355,7 @@ def main():
         f"compute launch(es); {value:.3e} cell-updates/s")
 
     roof = roofline(ctx, p, off, T, tnow=[s.t for s in st], L=L, S=S, kern_ms=kern_ms,
-                    launches=launches, steps=args.steps)
+                    launches=launches, steps=args.steps, copy_bw=args.copy_probe == 0)
 
     out = {
         "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1,
@@ -369,6 +373,24 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": roof,
     }
+
+    if args.full_run:
+        # the whole job: every instance from t = 0 to t = 0.2 in one call
+        W2 = {k: v.clone() for k, v in T.items()}
+        torch.cuda.synchronize()
+        a0 = time.perf_counter()
+        stf = ctx.run(p, off, W2["h"], W2["hu"], W2["b"], W2["x"], W2["xi"], t_end=[0.2] * ninst)
+        torch.cuda.synchronize()
+        wall_f = time.perf_counter() - a0
+        assert all(s.status == 0 and abs(s.t - 0.2) < 1e-12 for s in stf), "full run did not finish"
+        ns = np.diff(off)
+        work = float(sum(3.0 * int(ns[i]) * stf[i].steps for i in range(ninst)))
+        out["full_run"] = dict(t_end=0.2, wall_s=round(wall_f, 3), cell_stages=work,
+                               value=work / wall_f, unit="cell-updates/s",
+                               steps_min=int(min(s.steps for s in stf)),
+                               steps_max=int(max(s.steps for s in stf)))
+        log(f"full run: {out['full_run']}")
+        del W2
 
     if not args.no_speedup:
         # batched (one call) vs one call per instance, same GPU, same 64 instances

@@ -50,7 +50,9 @@ typedef enum {
   ALEW_E_NONFINITE = 4,   /* NaN or Inf in the state                               */
   ALEW_E_HIP = 5,         /* HIP runtime error                                     */
   ALEW_E_NOMEM = 6,       /* device allocation failed                              */
-  ALEW_E_UNSUPPORTED = 7, /* combination not supported by this entry point          */
+  ALEW_E_UNSUPPORTED = 7, /* combination not supported by this entry point; also an
+                           * instance of a batch out of step with the others (the
+                           * stage kernels take one node-buffer parity per launch) */
   ALEW_E_NEGWEIGHT = 8    /* a negative linear weight d_r (Sec. 2.2, after Step 4)  */
 } alew_status;
 

@@ -436,12 +436,18 @@ __global__ __launch_bounds__(256) void k_masses(Bufs bf) {
 
 __global__ void k_zero_u32(unsigned* p) { *p = 0u; }
 
-__global__ __launch_bounds__(1024) void k_count_active(Bufs bf, int* __restrict__ n_active) {
+// Number of active instances, and (act non-NULL) one activity byte per instance.
+__global__ __launch_bounds__(1024) void k_count_active(Bufs bf, int* __restrict__ n_active,
+                                                      uint8_t* __restrict__ act) {
   __shared__ int cnt;
   if (threadIdx.x == 0) cnt = 0;
   __syncthreads();
   int c = 0;
-  for (int i = threadIdx.x; i < bf.ninst; i += blockDim.x) c += bf.inst[i].active ? 1 : 0;
+  for (int i = threadIdx.x; i < bf.ninst; i += blockDim.x) {
+    const int a = bf.inst[i].active ? 1 : 0;
+    c += a;
+    if (act) act[i] = (uint8_t)a;
+  }
   atomicAdd(&cnt, c);
   __syncthreads();
   if (threadIdx.x == 0) *n_active = cnt;
@@ -644,6 +650,12 @@ struct alew_ctx {
   double* screc = nullptr;         // partial results of split instances
   double* pcrec = nullptr;
   int64_t n_schunks = 0, n_pchunks = 0;
+  uint8_t* act_d = nullptr;        // [max_inst] activity bytes (k_count_active)
+  uint8_t* act_h = nullptr;        // pinned copy
+  int64_t tables_ninst = 0;        // instances with tiles in the current tables
+  int64_t tables_cells = 0;        // their cells
+  bool tables_masked = false;      // tables hold only the instances active at a check
+  std::vector<uint8_t> cached_mask;
   bool split_s = false, split_p = false;  // some instance has several chunks
   int64_t tiles_cap = 0;
   int64_t n_tiles_edge = 0, n_tiles_inner = 0;
@@ -713,11 +725,16 @@ int pick_cpt(const alew_ctx* c, int B) {
 
 // (Re)build the tile tables for a batch layout, block size B and stage tile
 // width TB: TB + 4 stencil slots and TB - 2 owned cells per stage tile, or
-// with noext TB slots and TB - 6 owned cells; B items per plain tile.
+// with noext TB slots and TB - 6 owned cells; B items per plain tile.  With a
+// host mask (one byte per instance) only the instances marked active get
+// tiles; the others have empty record ranges.
 alew_status build_tiles(alew_ctx* c, const int64_t* cell_off, int64_t ninst, int B, int TB,
-                        bool noext) {
+                        bool noext, const uint8_t* mask = nullptr) {
   std::vector<int64_t> off(cell_off, cell_off + ninst + 1);
-  if (off == c->cell_off_h && c->cached_B == B && c->cached_TB == TB && c->cached_noext == noext)
+  std::vector<uint8_t> mk;
+  if (mask) mk.assign(mask, mask + ninst);
+  if (off == c->cell_off_h && c->cached_B == B && c->cached_TB == TB && c->cached_noext == noext &&
+      mk == c->cached_mask)
     return ALEW_OK;
   const int64_t own = noext ? TB - 6 : TB - 2;
   const int64_t NS = noext ? TB : TB + 4;
@@ -725,10 +742,14 @@ alew_status build_tiles(alew_ctx* c, const int64_t* cell_off, int64_t ninst, int
   // end-tile and ghost-free tables are subsets of it); plain tiles their own
   std::vector<Tile> ts, tp, te, tin;
   std::vector<int64_t> sfirst(ninst + 1, 0), pfirst(ninst + 1, 0);
+  int64_t tab_ninst = 0, tab_cells = 0;
   for (int64_t i = 0; i < ninst; ++i) {
     const int64_t n = off[i + 1] - off[i];
     sfirst[i] = (int64_t)ts.size();
     pfirst[i] = (int64_t)tp.size();
+    if (mask && !mask[i]) continue;
+    tab_ninst += 1;
+    tab_cells += n;
     for (int64_t c0 = 0; c0 < n; c0 += own) {
       const Tile tl{(int32_t)i, (int32_t)ts.size(), c0, off[i], n};
       ts.push_back(tl);
@@ -813,7 +834,11 @@ alew_status build_tiles(alew_ctx* c, const int64_t* cell_off, int64_t ninst, int
   c->cached_B = B;
   c->cached_TB = TB;
   c->cached_noext = noext;
+  c->cached_mask = mk;
   c->tiles_noext = noext;
+  c->tables_ninst = tab_ninst;
+  c->tables_cells = tab_cells;
+  c->tables_masked = mask != nullptr;
   c->n_tiles_stage = (int64_t)ts.size();
   c->n_tiles_plain = (int64_t)tp.size();
   c->n_tiles_edge = (int64_t)te.size();
@@ -893,7 +918,7 @@ void launch_step_seq(alew_ctx* c, const Bufs& bf, const Consts& cs, hipStream_t 
   const int par = (int)(step & 1);
   const dim3 gs((unsigned)c->n_tiles_stage), gp((unsigned)c->n_tiles_plain);
   for (int s = 1; s <= 3; ++s) {
-    const int kt = kt_begin(c, st, 0, (double)bf.S);
+    const int kt = kt_begin(c, st, 0, (double)c->tables_cells);
     if (c->tiles_noext)
       hipLaunchKernelGGL((k_stage<B, CPT, true>), gs, dim3(B), 0, st, bf, cs, c->tiles_stage_d, s,
                          par);
@@ -903,7 +928,7 @@ void launch_step_seq(alew_ctx* c, const Bufs& bf, const Consts& cs, hipStream_t 
     kt_end(c, st, kt);
     launch_after_stage(c, bf, st, s);
   }
-  const int kf = kt_begin(c, st, 1, (double)bf.S);
+  const int kf = kt_begin(c, st, 1, (double)c->tables_cells);
   hipLaunchKernelGGL(k_final<PB>, gp, dim3(PB), 0, st, bf, cs, c->tiles_plain_d, par);
   kt_end(c, st, kf);
   if (cs.mesh == MESH_FLUID)
@@ -937,6 +962,11 @@ GraphKey make_key(const Bufs& bf, const Consts& cs, int B, int CPT, const alew_c
   put(&c->tiles_noext, sizeof(bool));
   put(&c->n_tiles_stage, sizeof(int64_t));
   put(&c->n_tiles_plain, sizeof(int64_t));
+  put(&c->n_schunks, sizeof(int64_t));
+  put(&c->n_pchunks, sizeof(int64_t));
+  put(&c->split_s, sizeof(bool));
+  put(&c->split_p, sizeof(bool));
+  put(&c->tables_cells, sizeof(int64_t));
   return k;
 }
 
@@ -946,20 +976,25 @@ alew_status run_stage_engine(alew_ctx* c, const Bufs& bf, const Consts& cs, int6
   c->kt_used = 0;
   c->ktime_rec = c->ktime_on != 0;
   const int check_every = 8;  // 2-step graphs between host checks
-  if (use_graph) {
+  auto ensure_graph = [&]() -> hipError_t {
+    if (!use_graph) return hipSuccess;
     GraphKey key = make_key(bf, cs, B, CPT, c);
-    if (!c->gexec || !(key == c->gkey)) {
-      if (c->gexec) { (void)hipGraphExecDestroy(c->gexec); c->gexec = nullptr; }
-      if (c->graph) { (void)hipGraphDestroy(c->graph); c->graph = nullptr; }
-      HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-      // the graph starts at an even step and holds two
-      launch_step_seq<B, CPT>(c, bf, cs, c->cap_stream, 0);
-      launch_step_seq<B, CPT>(c, bf, cs, c->cap_stream, 1);
-      HIPCHK(hipStreamEndCapture(c->cap_stream, &c->graph));
-      HIPCHK(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
-      c->gkey = key;
-    }
-  }
+    if (c->gexec && key == c->gkey) return hipSuccess;
+    if (c->gexec) { (void)hipGraphExecDestroy(c->gexec); c->gexec = nullptr; }
+    if (c->graph) { (void)hipGraphDestroy(c->graph); c->graph = nullptr; }
+    hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    // the graph starts at an even step and holds two
+    launch_step_seq<B, CPT>(c, bf, cs, c->cap_stream, 0);
+    launch_step_seq<B, CPT>(c, bf, cs, c->cap_stream, 1);
+    e = hipStreamEndCapture(c->cap_stream, &c->graph);
+    if (e != hipSuccess) return e;
+    e = hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return e;
+    c->gkey = key;
+    return hipSuccess;
+  };
+  HIPCHK(ensure_graph());
   int64_t it = 0;
   c->last_launches = 0;
   HIPCHK(hipEventRecord(c->ev0, c->stream));
@@ -975,10 +1010,22 @@ alew_status run_stage_engine(alew_ctx* c, const Bufs& bf, const Consts& cs, int6
       c->last_launches += 1;
     }
     HIPCHK(hipGetLastError());
-    hipLaunchKernelGGL(k_count_active, dim3(1), dim3(1024), 0, c->stream, bf, c->nactive_d);
+    hipLaunchKernelGGL(k_count_active, dim3(1), dim3(1024), 0, c->stream, bf, c->nactive_d, c->act_d);
     HIPCHK(hipMemcpyAsync(c->nactive_h, c->nactive_d, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
-    if (*c->nactive_h == 0) break;
+    const int64_t na = *c->nactive_h;
+    if (na == 0) break;
+    // once half of the instances in the tile tables are done, the tables keep
+    // only the active ones: a done instance's tiles would still load their
+    // stencils before reading that the instance is done
+    if (2 * na <= c->tables_ninst) {
+      HIPCHK(hipMemcpyAsync(c->act_h, c->act_d, (size_t)bf.ninst, hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(hipStreamSynchronize(c->stream));
+      alew_status ts = build_tiles(c, c->cell_off_h.data(), bf.ninst, c->cached_B, c->cached_TB,
+                                   c->cached_noext, c->act_h);
+      if (ts != ALEW_OK) return ts;
+      HIPCHK(ensure_graph());
+    }
   }
   c->ktime_rec = false;
   HIPCHK(hipEventRecord(c->ev1, c->stream));
@@ -1013,7 +1060,7 @@ alew_status run_persistent(alew_ctx* c, const Bufs& bf, const Consts& cs, int64_
     total += ms;
     c->last_launches += 1;
     if (limit <= 0) break;
-    hipLaunchKernelGGL(k_count_active, dim3(1), dim3(1024), 0, c->stream, bf, c->nactive_d);
+    hipLaunchKernelGGL(k_count_active, dim3(1), dim3(1024), 0, c->stream, bf, c->nactive_d, nullptr);
     HIPCHK(hipMemcpyAsync(c->nactive_h, c->nactive_d, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     if (*c->nactive_h == 0) break;
@@ -1097,6 +1144,10 @@ alew_status drive(alew_ctx* c, const alew_params* p, int64_t ninst, const int64_
     alew_status rs = (engine == 1) ? run_persistent<BB>(c, bf, cs, ninst)                       \
                                    : run_stages<BB>(c, bf, cs, max_iters, CPT);                 \
     if (rs != ALEW_OK) return rs;                                                               \
+    if (c->tables_masked) { /* every instance's tiles again for the finish */                   \
+      rs = build_tiles(c, cell_off, ninst, PB, B * CPT, noext);                                 \
+      if (rs != ALEW_OK) return rs;                                                             \
+    }                                                                                           \
     hipLaunchKernelGGL(k_finish<PB>, gp, dim3(PB), 0, c->stream, bf, cs, c->tiles_plain_d, h, x); \
     hipLaunchKernelGGL(k_masses, dim3((unsigned)((ninst + 3) / 4)), dim3(256), 0, c->stream, bf); \
   } while (0)
@@ -1209,10 +1260,12 @@ alew_status alew_create(alew_ctx** out, int64_t max_cells, int64_t max_inst, voi
             alloc((void**)&c->pcfirst_d, (max_inst + 1) * sizeof(int64_t)) &&
             alloc((void**)&c->order_d, max_inst * sizeof(int32_t)) &&
             alloc((void**)&c->queue_d, sizeof(unsigned)) && alloc((void**)&c->nactive_d, sizeof(int)) &&
+            alloc((void**)&c->act_d, max_inst) &&
             alloc((void**)&c->dt1_d, sizeof(double));
   ok = ok && hipHostMalloc((void**)&c->dt1_h, sizeof(double), hipHostMallocDefault) == hipSuccess;
   ok = ok && hipHostMalloc((void**)&c->inst_h, max_inst * sizeof(Inst), hipHostMallocDefault) == hipSuccess;
   ok = ok && hipHostMalloc((void**)&c->nactive_h, sizeof(int), hipHostMallocDefault) == hipSuccess;
+  ok = ok && hipHostMalloc((void**)&c->act_h, max_inst, hipHostMallocDefault) == hipSuccess;
   ok = ok && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) == hipSuccess;
   ok = ok && hipEventCreate(&c->ev0) == hipSuccess && hipEventCreate(&c->ev1) == hipSuccess;
   if (!ok) {
@@ -1230,7 +1283,7 @@ void alew_destroy(alew_ctx* c) {
   void* ps[] = {c->eta, c->P0, c->D0, c->P1, c->D1, c->w, c->xa, c->xb, c->inst, c->cell_off_d,
                 c->order_d, c->queue_d, c->nactive_d, c->tiles_stage_d, c->tiles_plain_d,
                 c->tiles_edge_d, c->tiles_inner_d, c->srec, c->prec, c->sfirst_d, c->pfirst_d,
-                c->scfirst_d, c->pcfirst_d, c->schunk_d, c->pchunk_d, c->screc, c->pcrec,
+                c->scfirst_d, c->pcfirst_d, c->schunk_d, c->pchunk_d, c->screc, c->pcrec, c->act_d,
                 c->dt1_d,
                 c->adj_ws};
   for (void* p : ps)
@@ -1238,6 +1291,7 @@ void alew_destroy(alew_ctx* c) {
   if (c->inst_h) (void)hipHostFree(c->inst_h);
   if (c->dt1_h) (void)hipHostFree(c->dt1_h);
   if (c->nactive_h) (void)hipHostFree(c->nactive_h);
+  if (c->act_h) (void)hipHostFree(c->act_h);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);

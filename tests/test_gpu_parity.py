@@ -301,6 +301,42 @@ def test_batched_to_t_end_matches_per_instance(dev):
             assert np.array_equal(one[k].cpu().numpy(), T[k][a:e].cpu().numpy()), (i, k)
 
 
+def test_stage_engine_tables_shrink_as_instances_finish(dev):
+    """Stage engine, instances with end times 1..24 x 0.004: once half of the
+    instances in the tile tables are done the tables keep only the active ones
+    (and are rebuilt whole for the finish).  Every instance equals its own
+    one-instance call bitwise, with the same step count and end time."""
+    rng = np.random.default_rng(21)
+    ns = [int(v) for v in rng.integers(300, 1500, 24)]
+    insts = [W.perturbation_instance(n, 3e-3) for n in ns]
+    bt = W.pack(insts, bc="transmissive", t_end=0.2, cfl=0.6, weno_eps=1e-9, mesh="sine",
+                mesh_A=0.05, mesh_k=1.0, mesh_omega=math.pi)
+    off = bt["cell_off"]
+    n, ninst = int(off[-1]), len(off) - 1
+    p = _gp(bt)
+    t_end = [0.004 * (1 + i) for i in range(ninst)]
+    ctx = alew.Context(n, ninst)
+    ctx.set_launch(engine=alew.ENGINE_STAGES, use_graph=1)
+    T = {k: _t(bt[k], dev) for k in ("h", "hu", "b", "x", "xi")}
+    st = ctx.run(p, off, T["h"], T["hu"], T["b"], T["x"], T["xi"], t_end=t_end)
+    torch.cuda.synchronize()
+    c1 = alew.Context(max(ns), 1)
+    c1.set_launch(engine=alew.ENGINE_STAGES, use_graph=1)
+    for i in range(ninst):
+        a, e = int(off[i]), int(off[i + 1])
+        one = {k: _t(bt[k][a:e], dev) for k in ("h", "hu", "b")}
+        one["x"] = _t(bt["x"][a + i:e + i + 1], dev)
+        one["xi"] = _t(bt["xi"][a + i:e + i + 1], dev)
+        s1 = c1.run(p, [0, e - a], one["h"], one["hu"], one["b"], one["x"], one["xi"],
+                    t_end=[t_end[i]])[0]
+        assert st[i].status == 0 and s1.steps == st[i].steps
+        assert abs(st[i].t - t_end[i]) < 1e-15 and st[i].mass_eta == s1.mass_eta
+        for k in ("h", "hu", "b", "x"):
+            assert np.array_equal(one[k].cpu().numpy(), T[k][(a + i if k == "x" else a):
+                                                              (e + i + 1 if k == "x" else e)]
+                                  .cpu().numpy()), (i, k)
+
+
 def test_fluid_mesh_wet_dry_bowl(dev):
     """1D parabolic bowl (wet/dry, fluid-following mesh, CFL 0.08) at 2048 cells."""
     wl = W.bowl_1d(2048)

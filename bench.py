@@ -18,6 +18,7 @@ import argparse
 import concurrent.futures as cf
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -208,6 +209,80 @@ def cpu_baseline(bt, ninst_sample, steps):
                        f"{steps} CFL steps each, one instance per thread; {wall:.1f} s wall")
 
 
+def oracle_suite(dev):
+    """The oracle beside the GPU on the other configurations, single threaded
+    (one instance per call): the 200-cell periodic smooth run to t = 0.1 in
+    full (and the GPU on the same run); one perturbation instance of the
+    4096-instance draw, 30 steps; the parabolic bowl at 2^22 cells, one step;
+    one 65536-cell instance of the inversion batch, 2 steps forward and the
+    tape adjoint of those steps."""
+    import torch
+    import oracle as O
+    from paper_2208_06588_amd import alew, workloads as W
+    out = {}
+    try:
+        with open("/proc/cpuinfo") as f:
+            out["cpu"] = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
+    except (OSError, StopIteration):
+        out["cpu"] = "unknown"
+    out["nproc"] = os.cpu_count()
+    # C0 in full, oracle and GPU (one instance: launch-bound on the GPU)
+    wl = W.accuracy_1d(200, "sine")
+    op = O.params(bc=O.BC_PERIODIC, mesh=O.MESH_SINE, mesh_A=0.05, mesh_k=1.0,
+                  mesh_omega=math.pi, cfl=0.6, weno_eps=1e-6)
+    a = time.perf_counter()
+    r = O.run(op, wl["h"], wl["hu"], wl["b"], wl["x"], wl["xi"], t_end=0.1)
+    t_o = time.perf_counter() - a
+    st = r["stats"].steps
+    gp = alew.params(bc="periodic", mesh="sine", mesh_A=0.05, mesh_k=1.0, mesh_omega=math.pi,
+                     cfl=0.6, weno_eps=1e-6)
+    T = {k: torch.tensor(wl[k], dtype=torch.float64, device=dev) for k in ("h", "hu", "b", "x", "xi")}
+    ctx = alew.Context(200, 1)
+    ctx.set_launch(engine=alew.ENGINE_STAGES, use_graph=1)
+    W1 = {k: v.clone() for k, v in T.items()}
+    ctx.run(gp, [0, 200], W1["h"], W1["hu"], W1["b"], W1["x"], W1["xi"], t_end=[0.1])
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    sg = ctx.run(gp, [0, 200], T["h"], T["hu"], T["b"], T["x"], T["xi"], t_end=[0.1])[0]
+    torch.cuda.synchronize()
+    t_g = time.perf_counter() - a
+    out["c0_full"] = dict(cells=200, steps=st, oracle_s=round(t_o, 3),
+                          oracle_cell_stages_per_s=3.0 * 200 * st / t_o, gpu_s=round(t_g, 4),
+                          gpu_steps=sg.steps)
+    # one instance of the perturbation draw, 30 steps
+    bt = W.perturbation_batch(subset=1)
+    n = int(bt["cell_off"][1])
+    op = O.params(bc=O.BC_TRANSMISSIVE, mesh=O.MESH_SINE, mesh_A=0.05, mesh_k=1.0,
+                  mesh_omega=math.pi, cfl=0.6, weno_eps=1e-9)
+    a = time.perf_counter()
+    r = O.run(op, bt["h"], bt["hu"], bt["b"], bt["x"], bt["xi"], max_steps=30)
+    t_o = time.perf_counter() - a
+    out["c1_one_instance"] = dict(cells=n, steps=30, oracle_cell_stages_per_s=3.0 * n * 30 / t_o)
+    # bowl, 2^22 cells, one step
+    wl = W.bowl_1d(1 << 22)
+    op = O.params(bc=O.BC_TRANSMISSIVE, mesh=O.MESH_FLUID, cfl=0.08, weno_eps=1e-6)
+    a = time.perf_counter()
+    r = O.run(op, wl["h"], wl["hu"], wl["b"], wl["x"], wl["xi"], max_steps=1)
+    t_o = time.perf_counter() - a
+    out["c2_bowl_2p22_one_step"] = dict(cells=1 << 22,
+                                       oracle_cell_stages_per_s=3.0 * (1 << 22) / t_o)
+    # inversion batch, one instance, 2 steps forward and tape adjoint
+    bt = W.inversion_batch(ninst=1, n=65536, ngauge=64)
+    op = O.params(bc=O.BC_TRANSMISSIVE, mesh=O.MESH_SINE, mesh_A=0.05, mesh_k=1.0,
+                  mesh_omega=math.pi, cfl=0.6)
+    a = time.perf_counter()
+    r = O.run(op, bt["h"], bt["hu"], bt["b"], bt["x"], bt["xi"], max_steps=2)
+    t_f = time.perf_counter() - a
+    dts = np.full(2, r["stats"].dt_min)
+    a = time.perf_counter()
+    O.adjoint(op, bt["h"], bt["hu"], bt["b"], bt["x"], bt["xi"], dts, bt["gauge_x"], np.ones(64))
+    t_a = time.perf_counter() - a
+    out["c3_one_instance_2_steps"] = dict(cells=65536, forward_s=round(t_f, 3),
+                                         adjoint_s=round(t_a, 3),
+                                         adjoint_over_forward=round(t_a / t_f, 2))
+    return out
+
+
 def adjoint_leg(dev, ninst, ncell, nsteps, ngauge, ckpt):
     """Adjoint/forward time ratio on the bathymetry-inversion batch: ninst
     instances of ncell cells, nsteps frozen CFL steps, gauge misfit at ngauge
@@ -286,6 +361,8 @@ def main():
     ap.add_argument("--adj-cells", type=int, default=65536)
     ap.add_argument("--adj-steps", type=int, default=200)
     ap.add_argument("--no-bowl", action="store_true", help="skip the 2^24-cell wet/dry run")
+    ap.add_argument("--oracle-suite", action="store_true",
+                    help="also time the oracle on the other configurations (about 2 minutes)")
     ap.add_argument("--full-run", action="store_true",
                     help="also time the whole batch to t = 0.2 (every instance its own CFL steps; "
                          "about a minute)")
@@ -438,6 +515,10 @@ def main():
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(bt, min(args.cpu_inst, ninst), args.cpu_steps)
+    if args.oracle_suite:
+        log("oracle on the other configurations ...")
+        out["oracle_suite"] = oracle_suite(dev)
+        log(f"oracle suite: {out['oracle_suite']}")
     print(json.dumps(out), flush=True)
 
 

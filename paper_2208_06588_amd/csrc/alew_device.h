@@ -80,18 +80,33 @@ __device__ __forceinline__ void amax_pos(unsigned long long* p, double v) {
   atomicMax(p, dbits(v));
 }
 
-// Reciprocal: hardware estimate refined by two Newton steps (relative error of
-// a few ulp; every divisor here is a positive width, depth or sum).
 __device__ __forceinline__ unsigned hiword(double x) {
   return (unsigned)(__double_as_longlong(x) >> 32);
 }
 
+// Reciprocal: the hardware estimate r (relative error below 2^-24 on gfx950)
+// refined by one third-order step, r (1 + e + e^2) with e = 1 - x r, whose
+// error is of order e^3 (every divisor here is a positive width, depth or sum).
 __device__ __forceinline__ double frcp(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-x, r, 1.0);
-  return fma(r, e, r);
+  const double r = __builtin_amdgcn_rcp(x);
+  const double e = fma(-x, r, 1.0);
+  return fma(r, fma(e, e, e), r);
+}
+
+// max / min of two values as the single VALU instruction.  fmax / fmin on
+// operands the compiler cannot prove canonical (loads, selects, lane
+// shuffles) first quiet each operand with an extra instruction; no operand
+// here can be a signalling NaN, and a quiet NaN operand gives the other one
+// as fmax / fmin do.
+__device__ __forceinline__ double vmax(double a, double b) {
+  double r;
+  asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+__device__ __forceinline__ double vmin(double a, double b) {
+  double r;
+  asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
 }
 
 // ----------------------------------------------------------------------------
@@ -99,12 +114,12 @@ __device__ __forceinline__ double frcp(double x) {
 // ----------------------------------------------------------------------------
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  for (int o = 32; o > 0; o >>= 1) v = vmax(v, __shfl_xor(v, o, 64));
   return v;
 }
 __device__ __forceinline__ double wave_min(double v) {
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  for (int o = 32; o > 0; o >>= 1) v = vmin(v, __shfl_xor(v, o, 64));
   return v;
 }
 __device__ __forceinline__ double wave_sum(double v) {
@@ -154,7 +169,7 @@ __device__ __forceinline__ void block_reduce(double (&v)[NV], const int (&op)[NV
     double r = red[k];
     for (int q = 1; q < B / 64; ++q) {
       double o = red[q * NV + k];
-      r = op[k] == 0 ? fmax(r, o) : (op[k] == 1 ? fmin(r, o) : r + o);
+      r = op[k] == 0 ? vmax(r, o) : (op[k] == 1 ? vmin(r, o) : r + o);
     }
     v[k] = r;
   }
@@ -431,9 +446,9 @@ __device__ __forceinline__ void face_flux(double hl, double ml, double bl, doubl
   f.jb = br - bl;
   f.B1 = 0.5 * (bl + br);
   f.B2 = 0.5 * (bl * bl + br * br);
-  const double sl = fabs(ul - w) + sqrt(g * fmax(hl, 0.0));
-  const double sr = fabs(ur - w) + sqrt(g * fmax(hr, 0.0));
-  f.speed = fmax(sl, sr);
+  const double sl = fabs(ul - w) + sqrt(g * vmax(hl, 0.0));
+  const double sr = fabs(ur - w) + sqrt(g * vmax(hr, 0.0));
+  f.speed = vmax(sl, sr);
   f.sl = sl;
   f.sr = sr;
 }

@@ -424,7 +424,7 @@ __device__ __forceinline__ StageRes stage_compute(const Bufs& bf, const Consts& 
       // face (one LDS array less; still water still cancels to round-off)
       sm.u.fl[0][i] = f.Fc1; sm.u.fl[1][i] = f.Fc2 - 0.5 * cs.g * f.B2; sm.u.fl[2][i] = f.Gc;
       sm.u.fl[3][i] = f.je; sm.u.fl[4][i] = f.jm; sm.u.fl[5][i] = f.jb; sm.u.fl[6][i] = f.B1;
-      fspeed = fmax(fspeed, f.speed);
+      fspeed = vmax(fspeed, f.speed);
       fsl[c] = f.sl;
       fsr[c] = f.sr;
     }
@@ -467,7 +467,7 @@ __device__ __forceinline__ StageRes stage_compute(const Bufs& bf, const Consts& 
         bf.dump.q[o] = eb; bf.dump.q[o + NS] = mb; bf.dump.q[o + 2 * NS] = bb;
       }
       const double Jnext = sm.Jx[i + 2];
-      maxJ = fmax(maxJ, Jnext);
+      maxJ = vmax(maxJ, Jnext);
       if (!(Jnext > 0.0)) st |= SB_MESH;
     }
   }
@@ -632,7 +632,7 @@ __device__ __forceinline__ void final_cell(const Bufs& bf, const Consts& cs, con
   const double Jnew = xn1 - xn0;
   const double h = e - b;
   const double u = h > cs.dry_eps ? m / h : 0.0;
-  speed = fabs(u) + sqrt(cs.g * fmax(h, 0.0));
+  speed = fabs(u) + sqrt(cs.g * vmax(h, 0.0));
   minJ = Jnew; maxJ = Jnew; hmin = h;
   if (!(J3 > 0.0) || !(Jnew > 0.0)) st |= SB_MESH;
   if (!isfinite(e) || !isfinite(m) || !isfinite(b)) st |= SB_NONFINITE;

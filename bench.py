@@ -209,24 +209,22 @@ def cpu_baseline(bt, ninst_sample, steps):
                        f"{steps} CFL steps each, one instance per thread; {wall:.1f} s wall")
 
 
-def oracle_suite(dev):
-    """The oracle beside the GPU on the other configurations, single threaded
-    (one instance per call): the 200-cell periodic smooth run to t = 0.1 in
-    full (and the GPU on the same run); one perturbation instance of the
-    4096-instance draw, 30 steps; the parabolic bowl at 2^22 cells, one step;
-    one 65536-cell instance of the inversion batch, 2 steps forward and the
-    tape adjoint of those steps."""
-    import torch
+def oracle_other_configs():
+    """Part of the CPU baseline: the oracle, single threaded (one instance per
+    call), on the other configurations: the 200-cell periodic smooth run to
+    t = 0.1 in full; one perturbation instance of the 4096-instance draw, 30
+    steps; the parabolic bowl at 2^22 cells, one step; one 65536-cell instance
+    of the inversion batch, 2 steps forward and the tape adjoint of those
+    steps."""
     import oracle as O
-    from paper_2208_06588_amd import alew, workloads as W
+    from paper_2208_06588_amd import workloads as W
     out = {}
     try:
         with open("/proc/cpuinfo") as f:
             out["cpu"] = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
     except (OSError, StopIteration):
         out["cpu"] = "unknown"
-    out["nproc"] = os.cpu_count()
-    # C0 in full, oracle and GPU (one instance: launch-bound on the GPU)
+    out["threads"] = 1
     wl = W.accuracy_1d(200, "sine")
     op = O.params(bc=O.BC_PERIODIC, mesh=O.MESH_SINE, mesh_A=0.05, mesh_k=1.0,
                   mesh_omega=math.pi, cfl=0.6, weno_eps=1e-6)
@@ -234,6 +232,46 @@ def oracle_suite(dev):
     r = O.run(op, wl["h"], wl["hu"], wl["b"], wl["x"], wl["xi"], t_end=0.1)
     t_o = time.perf_counter() - a
     st = r["stats"].steps
+    out["smooth_200_to_t0.1"] = dict(cells=200, steps=st, wall_s=round(t_o, 3),
+                                     value=3.0 * 200 * st / t_o)
+    bt = W.perturbation_batch(subset=1)
+    n = int(bt["cell_off"][1])
+    op = O.params(bc=O.BC_TRANSMISSIVE, mesh=O.MESH_SINE, mesh_A=0.05, mesh_k=1.0,
+                  mesh_omega=math.pi, cfl=0.6, weno_eps=1e-9)
+    a = time.perf_counter()
+    O.run(op, bt["h"], bt["hu"], bt["b"], bt["x"], bt["xi"], max_steps=30)
+    out["perturbation_one_instance"] = dict(cells=n, steps=30,
+                                            value=3.0 * n * 30 / (time.perf_counter() - a))
+    wl = W.bowl_1d(1 << 22)
+    op = O.params(bc=O.BC_TRANSMISSIVE, mesh=O.MESH_FLUID, cfl=0.08, weno_eps=1e-6)
+    a = time.perf_counter()
+    O.run(op, wl["h"], wl["hu"], wl["b"], wl["x"], wl["xi"], max_steps=1)
+    out["bowl_2p22_one_step"] = dict(cells=1 << 22, value=3.0 * (1 << 22) / (time.perf_counter() - a))
+    bt = W.inversion_batch(ninst=1, n=65536, ngauge=64)
+    op = O.params(bc=O.BC_TRANSMISSIVE, mesh=O.MESH_SINE, mesh_A=0.05, mesh_k=1.0,
+                  mesh_omega=math.pi, cfl=0.6)
+    a = time.perf_counter()
+    r = O.run(op, bt["h"], bt["hu"], bt["b"], bt["x"], bt["xi"], max_steps=2)
+    t_f = time.perf_counter() - a
+    dts = np.full(2, r["stats"].dt_min)
+    a = time.perf_counter()
+    O.adjoint(op, bt["h"], bt["hu"], bt["b"], bt["x"], bt["xi"], dts, bt["gauge_x"], np.ones(64))
+    t_a = time.perf_counter() - a
+    out["inversion_one_instance_2_steps"] = dict(cells=65536, forward_s=round(t_f, 3),
+                                                 adjoint_s=round(t_a, 3),
+                                                 adjoint_over_forward=round(t_a / t_f, 2))
+    for v in out.values():
+        if isinstance(v, dict) and "value" in v:
+            v["unit"] = "cell-updates/s"
+    return out
+
+
+def small_run_leg(dev):
+    """The 200-cell smooth periodic run to t = 0.1 on the GPU (one instance:
+    bound by launch latency, not by the kernels)."""
+    import torch
+    from paper_2208_06588_amd import alew, workloads as W
+    wl = W.accuracy_1d(200, "sine")
     gp = alew.params(bc="periodic", mesh="sine", mesh_A=0.05, mesh_k=1.0, mesh_omega=math.pi,
                      cfl=0.6, weno_eps=1e-6)
     T = {k: torch.tensor(wl[k], dtype=torch.float64, device=dev) for k in ("h", "hu", "b", "x", "xi")}
@@ -246,41 +284,9 @@ def oracle_suite(dev):
     sg = ctx.run(gp, [0, 200], T["h"], T["hu"], T["b"], T["x"], T["xi"], t_end=[0.1])[0]
     torch.cuda.synchronize()
     t_g = time.perf_counter() - a
-    out["c0_full"] = dict(cells=200, steps=st, oracle_s=round(t_o, 3),
-                          oracle_cell_stages_per_s=3.0 * 200 * st / t_o, gpu_s=round(t_g, 4),
-                          gpu_steps=sg.steps)
-    # one instance of the perturbation draw, 30 steps
-    bt = W.perturbation_batch(subset=1)
-    n = int(bt["cell_off"][1])
-    op = O.params(bc=O.BC_TRANSMISSIVE, mesh=O.MESH_SINE, mesh_A=0.05, mesh_k=1.0,
-                  mesh_omega=math.pi, cfl=0.6, weno_eps=1e-9)
-    a = time.perf_counter()
-    r = O.run(op, bt["h"], bt["hu"], bt["b"], bt["x"], bt["xi"], max_steps=30)
-    t_o = time.perf_counter() - a
-    out["c1_one_instance"] = dict(cells=n, steps=30, oracle_cell_stages_per_s=3.0 * n * 30 / t_o)
-    # bowl, 2^22 cells, one step
-    wl = W.bowl_1d(1 << 22)
-    op = O.params(bc=O.BC_TRANSMISSIVE, mesh=O.MESH_FLUID, cfl=0.08, weno_eps=1e-6)
-    a = time.perf_counter()
-    r = O.run(op, wl["h"], wl["hu"], wl["b"], wl["x"], wl["xi"], max_steps=1)
-    t_o = time.perf_counter() - a
-    out["c2_bowl_2p22_one_step"] = dict(cells=1 << 22,
-                                       oracle_cell_stages_per_s=3.0 * (1 << 22) / t_o)
-    # inversion batch, one instance, 2 steps forward and tape adjoint
-    bt = W.inversion_batch(ninst=1, n=65536, ngauge=64)
-    op = O.params(bc=O.BC_TRANSMISSIVE, mesh=O.MESH_SINE, mesh_A=0.05, mesh_k=1.0,
-                  mesh_omega=math.pi, cfl=0.6)
-    a = time.perf_counter()
-    r = O.run(op, bt["h"], bt["hu"], bt["b"], bt["x"], bt["xi"], max_steps=2)
-    t_f = time.perf_counter() - a
-    dts = np.full(2, r["stats"].dt_min)
-    a = time.perf_counter()
-    O.adjoint(op, bt["h"], bt["hu"], bt["b"], bt["x"], bt["xi"], dts, bt["gauge_x"], np.ones(64))
-    t_a = time.perf_counter() - a
-    out["c3_one_instance_2_steps"] = dict(cells=65536, forward_s=round(t_f, 3),
-                                         adjoint_s=round(t_a, 3),
-                                         adjoint_over_forward=round(t_a / t_f, 2))
-    return out
+    ctx.close()
+    return dict(cells=200, steps=sg.steps, wall_s=round(t_g, 4), value=3.0 * 200 * sg.steps / t_g,
+                unit="cell-updates/s")
 
 
 def adjoint_leg(dev, ninst, ncell, nsteps, ngauge, ckpt):
@@ -362,7 +368,8 @@ def main():
     ap.add_argument("--adj-steps", type=int, default=200)
     ap.add_argument("--no-bowl", action="store_true", help="skip the 2^24-cell wet/dry run")
     ap.add_argument("--oracle-suite", action="store_true",
-                    help="also time the oracle on the other configurations (about 2 minutes)")
+                    help="CPU baseline: also time the oracle on the other configurations, "
+                         "single threaded (about 2 minutes); and the 200-cell run on the GPU")
     ap.add_argument("--full-run", action="store_true",
                     help="also time the whole batch to t = 0.2 (every instance its own CFL steps; "
                          "about a minute)")
@@ -373,8 +380,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: the batched instances are independent and this "
-              "build measures one GPU's share; use --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: the batched instances are independent and the "
+              "figure is one GPU's throughput; use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -512,13 +519,16 @@ def main():
         out["adjoint_forward_ratio"] = out["adjoint"]["ratio"]
         log(f"adjoint: {out['adjoint']}")
 
+    if args.oracle_suite:
+        log("smooth 200-cell run on the GPU ...")
+        out["smooth_200_gpu"] = small_run_leg(dev)
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(bt, min(args.cpu_inst, ninst), args.cpu_steps)
-    if args.oracle_suite:
-        log("oracle on the other configurations ...")
-        out["oracle_suite"] = oracle_suite(dev)
-        log(f"oracle suite: {out['oracle_suite']}")
+        if args.oracle_suite:
+            log("oracle on the other configurations ...")
+            out["cpu_baseline"]["other_configs"] = oracle_other_configs()
+            log(f"oracle, other configurations: {out['cpu_baseline']['other_configs']}")
     print(json.dumps(out), flush=True)
 
 

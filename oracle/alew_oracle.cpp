@@ -20,7 +20,7 @@
  * (detector class, limiter activity, argmin/argmax, |.| signs, dry cut-offs)
  * taken from the forward values.
  *
- * Readings of points the paper leaves open (each also listed in the design doc):
+ * Readings of points the paper leaves open:
  *  R1  Dx in the smoothness indicators is the global max cell width of the
  *      stage mesh (Sec. 2.2, Step 1 defines Dx^n as max_j Delta_j^n); flag
  *      FLAG_BETA_LOCAL switches to the cell's own width.

@@ -63,7 +63,7 @@ __global__ __launch_bounds__(B) void k_prep(Bufs bf, Consts cs, const Tile* __re
     const double J = v.x[j + 1] - v.x[j];
     const double hh = e - b;
     const double u = hh > cs.dry_eps ? m / hh : 0.0;
-    speed = fabs(u) + sqrt(cs.g * fmax(hh, 0.0));
+    speed = fabs(u) + fsqrt(cs.g * vmax(hh, 0.0));
     minJ = J; maxJ = J; hmin = hh;
     me = J * e; mb = J * b;
     if (!(J > 0.0)) atomicOr(&I.status, (int)SB_MESH);

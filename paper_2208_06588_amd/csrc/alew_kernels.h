@@ -632,7 +632,7 @@ __device__ __forceinline__ void final_cell(const Bufs& bf, const Consts& cs, con
   const double Jnew = xn1 - xn0;
   const double h = e - b;
   const double u = h > cs.dry_eps ? m / h : 0.0;
-  speed = fabs(u) + sqrt(cs.g * vmax(h, 0.0));
+  speed = fabs(u) + fsqrt(cs.g * vmax(h, 0.0));
   minJ = Jnew; maxJ = Jnew; hmin = h;
   if (!(J3 > 0.0) || !(Jnew > 0.0)) st |= SB_MESH;
   if (!isfinite(e) || !isfinite(m) || !isfinite(b)) st |= SB_NONFINITE;

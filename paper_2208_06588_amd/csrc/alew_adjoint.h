@@ -200,15 +200,8 @@ __device__ __forceinline__ void recon_cell_vjp(const double* __restrict__ v5,
   // ---------------- forward (as recon_cell) ----------------
   const double J0 = J5[2];
   const double iJ0 = frcp(J0);
-  const double em1 = -0.5 - J5[1] * iJ0;
-  const double em2 = em1 - J5[0] * iJ0;
-  const double ep1 = 0.5 + J5[3] * iJ0;
-  const double ep2 = ep1 + J5[4] * iJ0;
   double M1[4], M2[4], M3[4], M4[4];
-  moments(em2, em1, M1[0], M2[0], M3[0], M4[0]);
-  moments(em1, -0.5, M1[1], M2[1], M3[1], M4[1]);
-  moments(0.5, ep1, M1[2], M2[2], M3[2], M4[2]);
-  moments(ep1, ep2, M1[3], M2[3], M3[3], M4[3]);
+  stencil_moments(J5, iJ0, M1, M2, M3, M4);
   const int C1[3] = {2, 1, 0}, C2[3] = {3, 2, 1};
   double kb1[3], kb2[3], kc1[3], kc2[3];
 #pragma unroll

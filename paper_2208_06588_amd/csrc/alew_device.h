@@ -234,13 +234,23 @@ struct CellRecon {
   int negw;
 };
 
-__device__ __forceinline__ void moments(double a, double b, double& M1, double& M2, double& M3,
-                                        double& M4) {
-  const double a2 = a * a, b2 = b * b, ab = a * b;
-  M1 = 0.5 * (a + b);
-  M2 = (a2 + ab + b2) * (1.0 / 3.0) - (1.0 / 12.0);
-  M3 = 0.25 * (a + b) * (a2 + b2);
-  M4 = (a2 * a2 + a2 * ab + ab * ab + ab * b2 + b2 * b2) * 0.2 - 0.0125;
+// Averages over the neighbour cells j-2, j-1, j+1, j+2 (slots 0..3) of y,
+// y^2 - 1/12, y^3 and y^4 - 1/80, with y the coordinate in which cell j is
+// [-1/2, 1/2].  A cell of centre c and width w averages y^2 to c^2 + w^2/12,
+// y^3 to c^3 + c w^2/4 and y^4 to c^4 + c^2 w^2/2 + w^4/80.
+__device__ __forceinline__ void stencil_moments(const double* __restrict__ J5, double iJ0,
+                                                double* M1, double* M2, double* M3, double* M4) {
+  const double w[4] = {J5[0] * iJ0, J5[1] * iJ0, J5[3] * iJ0, J5[4] * iJ0};
+  const double em1 = -0.5 - w[1], ep1 = 0.5 + w[2];
+  const double c[4] = {em1 - 0.5 * w[0], -0.5 - 0.5 * w[1], 0.5 + 0.5 * w[2], ep1 + 0.5 * w[3]};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double c2 = c[k] * c[k], w2 = w[k] * w[k];
+    M1[k] = c[k];
+    M2[k] = fma(w2, 1.0 / 12.0, c2) - 1.0 / 12.0;
+    M3[k] = c[k] * fma(w2, 0.25, c2);
+    M4[k] = fma(c2, fma(w2, 0.5, c2), fma(w2 * w2, 0.0125, -0.0125));
+  }
 }
 
 // v5: eta (or h under F_BETA_FROM_H: chosen by the caller), stencil order
@@ -252,16 +262,8 @@ __device__ __forceinline__ void recon_cell(const double* __restrict__ v5,  // in
                                            const double* __restrict__ J5, double iJ0, double Dx,
                                            double eps, double etabar, CellRecon& o) {
   const double J0 = J5[2];
-  // cell edges of the big stencil in y
-  const double em1 = -0.5 - J5[1] * iJ0;
-  const double em2 = em1 - J5[0] * iJ0;
-  const double ep1 = 0.5 + J5[3] * iJ0;
-  const double ep2 = ep1 + J5[4] * iJ0;
   double M1[4], M2[4], M3[4], M4[4];  // cells j-2, j-1, j+1, j+2
-  moments(em2, em1, M1[0], M2[0], M3[0], M4[0]);
-  moments(em1, -0.5, M1[1], M2[1], M3[1], M4[1]);
-  moments(0.5, ep1, M1[2], M2[2], M3[2], M4[2]);
-  moments(ep1, ep2, M1[3], M2[3], M3[3], M4[3]);
+  stencil_moments(J5, iJ0, M1, M2, M3, M4);
   // stencil r uses neighbour slots (c1, c2): r=0 -> (j+1, j+2), r=1 -> (j-1, j+1),
   // r=2 -> (j-2, j-1)
   const int C1[3] = {2, 1, 0}, C2[3] = {3, 2, 1};

@@ -206,6 +206,53 @@ def test_batched_engines_bitwise_and_oracle(dev):
         assert outs[0][1][i].steps == nsteps
 
 
+@pytest.mark.parametrize("bc", ["periodic", "transmissive", "reflective"])
+def test_small_and_tile_edge_sizes_every_boundary(dev, bc):
+    """Degenerate and tile-edge instance sizes in one ragged batch: 5 cells
+    (the smallest allowed, fewer cells than a periodic wrap of the ghosts
+    spans twice), sizes around the owned cells of one-wave 64 x 2 tiles (126),
+    of 128 x 1 and 256 x 1 tiles, smooth data, sine-moving mesh, 8 steps.  The
+    automatic launch, 256 x 1 stage tiles and the persistent engine agree
+    bitwise; every instance matches the oracle (state, nodes, step sizes,
+    class counts)."""
+    sizes = [5, 6, 7, 9, 13, 63, 64, 65, 125, 126, 127, 128, 131, 132, 133, 250, 252, 253, 257]
+    insts = []
+    for n in sizes:
+        wl = W.accuracy_1d(n)
+        insts.append((wl["xi"], wl["h"], wl["hu"], wl["b"]))
+    bt = W.pack(insts, bc=bc, cfl=0.6, weno_eps=1e-6, mesh="sine", mesh_A=0.05, mesh_k=1.0,
+                mesh_omega=math.pi)
+    off = bt["cell_off"]
+    n, ninst = int(off[-1]), len(off) - 1
+    p = _gp(bt)
+    nsteps = 8
+    outs = []
+    for engine, block, cpt in ((alew.ENGINE_AUTO, 0, 0), (alew.ENGINE_STAGES, 256, 1),
+                               (alew.ENGINE_PERSISTENT, 128, 1)):
+        ctx = alew.Context(n, ninst)
+        ctx.set_launch(engine=engine, block=block, use_graph=1, cells_per_thread=cpt)
+        T = {k: _t(bt[k], dev) for k in ("h", "hu", "b", "x", "xi")}
+        st = ctx.run(p, off, T["h"], T["hu"], T["b"], T["x"], T["xi"], max_steps=[nsteps] * ninst)
+        torch.cuda.synchronize()
+        outs.append(({k: v.cpu().numpy() for k, v in T.items()}, st))
+    ref, sref = outs[0]
+    for o, st in outs[1:]:
+        for k in ("h", "hu", "b", "x"):
+            assert np.array_equal(o[k], ref[k]), k
+        assert [tuple(s.n_class) for s in st] == [tuple(s.n_class) for s in sref]
+    for i in range(ninst):
+        a, e = int(off[i]), int(off[i + 1])
+        r = O.run(_op(bt), bt["h"][a:e], bt["hu"][a:e], bt["b"][a:e], bt["x"][a + i:e + i + 1],
+                  bt["xi"][a + i:e + i + 1], max_steps=nsteps)
+        assert r["status"] == 0
+        g = dict(h=ref["h"][a:e], hu=ref["hu"][a:e], b=ref["b"][a:e], x=ref["x"][a + i:e + i + 1])
+        _assert_parity(g, r)
+        rs = r["stats"]
+        assert sref[i].steps == rs.steps == nsteps
+        assert tuple(sref[i].n_class) == tuple(rs.n_class), (sizes[i], sref[i].n_class, rs.n_class)
+        assert abs(sref[i].dt_min - rs.dt_min) <= 1e-13 * rs.dt_min
+
+
 def test_stage_tile_shapes_many_tiles(dev):
     """A batch of 160 instances of 3000-9000 cells, many more stage tiles than
     resident work-groups: tiles of 256 x 1 cells with four extra stencil slots,

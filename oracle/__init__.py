@@ -23,7 +23,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 BC_PERIODIC, BC_TRANSMISSIVE, BC_REFLECTIVE = 0, 1, 2
 MESH_GIVEN, MESH_SINE, MESH_PAPER, MESH_FLUID = 0, 1, 2, 3
 ST_OK, ST_ARG, ST_MESH, ST_NEGDEPTH, ST_NONFINITE, ST_NEGWEIGHT = 0, 1, 2, 3, 4, 8
-FLAG_BETA_LOCAL, FLAG_BETA_FROM_H = 1, 2
+FLAG_BETA_LOCAL, FLAG_BETA_FROM_H, FLAG_HYDROSTATIC = 1, 2, 4
 
 
 class Params(C.Structure):

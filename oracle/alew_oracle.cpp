@@ -67,6 +67,25 @@
  *      boundary cell (values and width); reflective mirrors with hu negated.
  *  R15 The state carried through a run is (eta, hu, b); h = eta - b is
  *      formed on entry and on exit of each library call.
+ *  R16 Hydrostatic reconstruction (Sec. 4.1, eq. (4.2)-(4.3) in 1D; flag
+ *      FLAG_HYDROSTATIC).  At each face of cell j, q- is the cell's own
+ *      limited trace and q+ the neighbour's, n the outward normal (+1 on the
+ *      right face, -1 on the left).  h*+- = max(0, eta+- - max(b+, b-)),
+ *      eta*+- = h*+- + b+-, q*+- = (eta*+-, (hu)+-): the discharge is kept as
+ *      printed.  The momentum flux of q* uses u* = (hu)/h* where h* > dry_eps
+ *      (R11), else 0.  H^mod = H(q*-, q*+, n) + (theta, (g/2 (eta- - b-)^2 -
+ *      g/2 (h*-)^2) n), H the Lax-Friedrichs flux of eq. (3.13) with the
+ *      alpha of R6 (taken on the traces q+-, not q*+-).  The bottom keeps the
+ *      ALE flux of R13.
+ *  R17 Hydrostatic source (the sentence after eq. (4.3)): "fourth-order
+ *      polynomials" are read as the cubics (four coefficients) eta_h, b_h
+ *      that interpolate the values at the 4 Gauss-Lobatto points of the cell
+ *      (the limited traces at the two ends, the unlimited hybrid values
+ *      inside).  A degree-4 polynomial is not fixed by these values and the
+ *      cell average: the 4-point Gauss-Lobatto rule is exact to degree 5, so
+ *      the average follows from the point values.  The integral of
+ *      -g (eta_h - b_h) d b_h / dx over the cell is taken by the 5-point
+ *      Gauss-Legendre rule, exact for the degree-5 integrand.
  */
 #include <cmath>
 #include <cstdint>
@@ -132,7 +151,7 @@ enum { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1, BC_REFLECTIVE = 2 };
 enum { MESH_GIVEN = 0, MESH_SINE = 1, MESH_PAPER = 2, MESH_FLUID = 3 };
 enum { ST_OK = 0, ST_ARG = 1, ST_MESH = 2, ST_NEGDEPTH = 3, ST_NONFINITE = 4, ST_NEGWEIGHT = 8 };
 
-enum { FLAG_BETA_LOCAL = 1, FLAG_BETA_FROM_H = 2 };
+enum { FLAG_BETA_LOCAL = 1, FLAG_BETA_FROM_H = 2, FLAG_HYDROSTATIC = 4 };
 
 struct Params {
   double g, cfl, weno_eps, pp_eps;
@@ -446,6 +465,89 @@ static TraceFlux<T> trace_state(T h, T m, T b, double dry_eps) {
   return s;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Hydrostatic reconstruction (Sec. 4.1, eq. (4.2)-(4.3)), readings R16-R17   */
+/* ------------------------------------------------------------------------ */
+/* H^mod of eq. (4.2) at one face of a cell: q- its own trace, q+ the
+ * neighbour's, nrm the outward normal, w the node speed.  Components eta, hu. */
+template <class T>
+static void hydro_face_flux(const Params& P, const TraceFlux<T>& qm, const TraceFlux<T>& qp,
+                            double nrm, double w, T alpha, T& H1, T& H2) {
+  T bmax = (val(qm.b) > val(qp.b)) ? qm.b : qp.b;
+  T hsm = qm.eta - bmax, hsp = qp.eta - bmax;
+  if (val(hsm) < 0.0) hsm = 0.0;
+  if (val(hsp) < 0.0) hsp = 0.0;
+  T esm = hsm + qm.b, esp = hsp + qp.b;
+  T usm = 0.0, usp = 0.0;
+  if (val(hsm) > P.dry_eps) usm = qm.m / hsm;
+  if (val(hsp) > P.dry_eps) usp = qp.m / hsp;
+  /* calH(w, q*) . n for both states, then the Lax-Friedrichs flux */
+  T Hm1 = nrm * (qm.m - w * esm);
+  T Hp1 = nrm * (qp.m - w * esp);
+  T Hm2 = nrm * (qm.m * usm + 0.5 * P.g * hsm * hsm - w * qm.m);
+  T Hp2 = nrm * (qp.m * usp + 0.5 * P.g * hsp * hsp - w * qp.m);
+  H1 = 0.5 * (Hm1 + Hp1) - 0.5 * alpha * (esp - esm);
+  H2 = 0.5 * (Hm2 + Hp2) - 0.5 * alpha * (qp.m - qm.m);
+  T theta = 0.5 * (w * nrm + alpha) * (esp - qp.eta) + 0.5 * (w * nrm - alpha) * (esm - qm.eta);
+  T hm = qm.eta - qm.b;
+  H1 = H1 + theta;
+  H2 = H2 + (0.5 * P.g * hm * hm - 0.5 * P.g * hsm * hsm) * nrm;
+}
+
+/* 5-point Gauss-Legendre rule on [0,1] (exact to degree 9). */
+static const double kGL5_s[5] = {0.5 - 0.5 * 0.90617984593866399280, 0.5 - 0.5 * 0.53846931010568309104,
+                                 0.5, 0.5 + 0.5 * 0.53846931010568309104,
+                                 0.5 + 0.5 * 0.90617984593866399280};
+static const double kGL5_w[5] = {0.5 * 0.23692688505618908751, 0.5 * 0.47862867049936646804,
+                                 0.5 * 0.56888888888888888889, 0.5 * 0.47862867049936646804,
+                                 0.5 * 0.23692688505618908751};
+
+/* Inverse of the interpolation system of R17 in the cell coordinate
+ * s in [0,1]: p(s) = sum_k c_k s^k, k = 0..3, with p at the 4 Gauss-Lobatto
+ * points kS. */
+struct InterpInverse {
+  double a[16];
+  InterpInverse() {
+    double A[16];
+    for (int r = 0; r < 4; ++r)
+      for (int k = 0; k < 4; ++k) A[r * 4 + k] = std::pow(kS[r], k);
+    invert(4, A, a);
+  }
+};
+static const double* hydro_interp_inverse() {
+  static const InterpInverse inv;  /* initialised once, thread-safe */
+  return inv.a;
+}
+
+/* R17: integral over cell j of -g (eta_h - b_h) d b_h / dx.  ev, bv: values
+ * at the 4 Gauss-Lobatto points.  With x = x_{j-1/2} + s J, dx = J ds and
+ * d/dx = (1/J) d/ds, so J drops out. */
+template <class T>
+static T hydro_source(double g, const T ev[4], const T bv[4]) {
+  const double* Ai = hydro_interp_inverse();
+  T ce[4], cb[4];
+  for (int k = 0; k < 4; ++k) {
+    ce[k] = 0.0;
+    cb[k] = 0.0;
+    for (int r = 0; r < 4; ++r) {
+      ce[k] = ce[k] + Ai[k * 4 + r] * ev[r];
+      cb[k] = cb[k] + Ai[k * 4 + r] * bv[r];
+    }
+  }
+  T S = 0.0;
+  for (int q = 0; q < 5; ++q) {
+    const double s = kGL5_s[q];
+    T eh = 0.0, bh = 0.0, dbh = 0.0;
+    for (int k = 3; k >= 0; --k) {
+      eh = eh * s + ce[k];
+      bh = bh * s + cb[k];
+      if (k >= 1) dbh = dbh * s + (double)k * cb[k];
+    }
+    S = S + kGL5_w[q] * ((-g) * (eh - bh) * dbh);
+  }
+  return S;
+}
+
 template <class T>
 static void residual(const Params& P, int n, const T* eta, const T* m, const T* b, const double* J,
                      const double* w, T* R, double* alpha_out, uint8_t* cls, Counters& cnt) {
@@ -524,6 +626,22 @@ static void residual(const Params& P, int n, const T* eta, const T* m, const T* 
     Gb[i] = -0.5 * wi * (l.b + r.b) - 0.5 * alpha * (r.b - l.b);
     B1[i] = 0.5 * (l.b + r.b);
     B2[i] = 0.5 * (l.b * l.b + r.b * r.b);
+  }
+  if (P.flags & FLAG_HYDROSTATIC) {
+    /* Residuals with the hydrostatic reconstruction (R16-R17): each cell sums
+     * H^mod over its two faces with outward normals; the bottom keeps Gb. */
+    for (int j = 0; j < n; ++j) {
+      T He_r, Hm_r, He_l, Hm_l;
+      hydro_face_flux(P, Lt[j + 1], Rt[j + 1], +1.0, w[j + 1], alpha, He_r, Hm_r);
+      hydro_face_flux(P, Rt[j], Lt[j], -1.0, w[j], alpha, He_l, Hm_l);
+      const Recon<T>& o = rec[j + 1];
+      T ev[4] = {Rt[j].eta, o.h[1] + o.b[1], o.h[2] + o.b[2], Lt[j + 1].eta};
+      T bv[4] = {Rt[j].b, o.b[1], o.b[2], Lt[j + 1].b};
+      R[j] = -(He_r + He_l);
+      R[n + j] = -(Hm_r + Hm_l) + hydro_source(P.g, ev, bv);
+      R[2 * n + j] = -(Gb[j + 1] - Gb[j]);
+    }
+    return;
   }
   /* Residuals with the special source (eq. (4.7)-(4.10)). */
   for (int j = 0; j < n; ++j) {

@@ -410,6 +410,126 @@ def test_accuracy_table_5_2():
         assert math.log2(errs[100][k] / errs[200][k]) > 3.5
 
 
+# ----------------------------------------------------------------------------
+# Hydrostatic-reconstruction variant (Sec. 4.1, eq. (4.2)-(4.3))
+# ----------------------------------------------------------------------------
+def _smooth_random_state(n, seed, flat_b=False):
+    J = _moving_widths(n, seed, L=2.0)
+    x = np.concatenate([[0.0], np.cumsum(J)])
+    xc = 0.5 * (x[1:] + x[:-1])
+    rng = np.random.default_rng(seed)
+    eta = 1.0 + 0.1 * np.sin(np.pi * xc + rng.uniform(0, 6))
+    hu = 0.2 * np.cos(np.pi * xc + rng.uniform(0, 6))
+    b = np.full(n, 0.25) if flat_b else 0.3 * np.exp(-((xc - 1.0) / 0.3) ** 2)
+    w = rng.normal(size=n + 1) * 0.2
+    w[-1] = w[0]
+    return eta, hu, b, J, w
+
+
+def test_hydrostatic_flat_bottom_is_the_plain_scheme():
+    """Over a flat bottom h* = h, theta = 0, the pressure corrections and the
+    source vanish: the hydrostatic-reconstruction residual equals the special-
+    source one (both are then the plain Lax-Friedrichs ALE scheme of eq. (3.12))."""
+    eta, hu, b, J, w = _smooth_random_state(48, 3, flat_b=True)
+    Ps = O.params(bc=O.BC_PERIODIC, mesh=O.MESH_GIVEN)
+    Ph = O.params(bc=O.BC_PERIODIC, mesh=O.MESH_GIVEN, flags=O.FLAG_HYDROSTATIC)
+    Rs, als, _ = O.residual(Ps, eta, hu, b, J, w)
+    Rh, alh, _ = O.residual(Ph, eta, hu, b, J, w)
+    assert als == alh
+    np.testing.assert_allclose(Rh, Rs, rtol=0, atol=1e-13 * np.abs(Rs).max())
+
+
+def test_hydrostatic_eta_and_bottom_equations_unchanged():
+    """The remark after Property 4.3: with the discharge kept in q*, theta
+    turns the eta component of H^mod back into the unmodified Lax-Friedrichs
+    flux, so the eta and b residuals equal those of the special-source scheme
+    over any bottom, while the momentum residual differs (by truncation)."""
+    eta, hu, b, J, w = _smooth_random_state(48, 4)
+    Ps = O.params(bc=O.BC_PERIODIC, mesh=O.MESH_GIVEN)
+    Ph = O.params(bc=O.BC_PERIODIC, mesh=O.MESH_GIVEN, flags=O.FLAG_HYDROSTATIC)
+    Rs, _, _ = O.residual(Ps, eta, hu, b, J, w)
+    Rh, _, _ = O.residual(Ph, eta, hu, b, J, w)
+    np.testing.assert_allclose(Rh[0], Rs[0], rtol=0, atol=1e-14 * np.abs(Rs[0]).max())
+    np.testing.assert_array_equal(Rh[2], Rs[2])
+    d = np.abs(Rh[1] - Rs[1]).max()
+    assert 1e-12 < d < 1e-3 * np.abs(Rs[1]).max()
+
+
+@pytest.mark.parametrize("bottom", ["smooth", "bumps"])
+def test_hydrostatic_lake_at_rest_residual(bottom):
+    """Lemma 4.1 (hydrostatic reconstruction): for eta = const, hu = 0 the
+    momentum residual vanishes and the eta residual is eta * dw on a moving
+    mesh, over a smooth bottom and over a bottom with steps."""
+    n = 60
+    J = _moving_widths(n, 5, L=10.0)
+    x = np.concatenate([[0.0], np.cumsum(J)])
+    xc = 0.5 * (x[1:] + x[:-1])
+    if bottom == "smooth":
+        b = 5.0 * np.exp(-0.4 * (xc - 5.0) ** 2)
+    else:
+        b = np.where((xc > 4) & (xc < 8), 4.0, 0.0) + 0.3 * np.sin(xc)
+    rng = np.random.default_rng(9)
+    w = rng.normal(size=n + 1) * 0.3
+    P = O.params(bc=O.BC_TRANSMISSIVE, mesh=O.MESH_GIVEN, flags=O.FLAG_HYDROSTATIC)
+    R, alpha, cls = O.residual(P, np.full(n, 10.0), np.zeros(n), b, J, w)
+    np.testing.assert_allclose(R[0], 10.0 * np.diff(w), atol=1e-11)
+    np.testing.assert_allclose(R[1], 0.0, atol=1e-11)
+
+
+@pytest.mark.parametrize("bottom,table", [("smooth", "table5.4hr"), ("step", "table5.5hr")])
+def test_hydrostatic_still_water_tables(bottom, table):
+    """Example 5.3 with the hydrostatic reconstruction: exact up to round-off
+    (Tables 5.4/5.5, hydrostatic rows, ~1e-13)."""
+    wl = W.still_water_1d(200, bottom)
+    r = O.run(_params_for(wl, flags=O.FLAG_HYDROSTATIC), wl["h"], wl["hu"], wl["b"], wl["x"],
+              wl["xi"], t_end=0.5)
+    assert r["status"] == 0
+    J = np.diff(r["x"])
+    e_eta = r["h"] + r["b"] - 10.0
+    got = [np.sum(np.abs(e_eta) * J), np.sum(np.abs(r["hu"]) * J), np.abs(e_eta).max(),
+           np.abs(r["hu"]).max()]
+    paper = [float(v) for row in _gold("paper_tables.txt") if row[0] == table for v in row[1:]]
+    for g, p in zip(got, paper):
+        assert g < 20 * p, (got, paper)
+
+
+def test_hydrostatic_accuracy_table_5_2():
+    """Example 5.1 with the hydrostatic reconstruction: L1 errors at N = 50,
+    100, 200 against a 800-cell run within a factor 2 of Table 5.2
+    (hydrostatic reconstruction columns), near-fifth-order decay 100 -> 200."""
+    paper = {int(r[1]): (float(r[2]), float(r[3])) for r in _gold("paper_tables.txt")
+             if r[0] == "table5.2hr"}
+    res = {}
+    for n in (50, 100, 200, 800):
+        wl = W.accuracy_1d(n, mesh="paper")
+        res[n] = O.run(_params_for(wl, flags=O.FLAG_HYDROSTATIC), wl["h"], wl["hu"], wl["b"],
+                       wl["x"], wl["xi"], t_end=0.1)
+        assert res[n]["status"] == 0
+    ref = res[800]
+    errs = {}
+    for n in (50, 100, 200):
+        f = 800 // n
+        ce = (ref["h"] + ref["b"]).reshape(-1, f).mean(1)
+        cm = ref["hu"].reshape(-1, f).mean(1)
+        errs[n] = (np.abs(ce - (res[n]["h"] + res[n]["b"])).mean(), np.abs(cm - res[n]["hu"]).mean())
+        for k in range(2):
+            assert paper[n][k] / 2 < errs[n][k] < paper[n][k] * 2, (n, errs[n], paper[n])
+    for k in range(2):
+        assert math.log2(errs[100][k] / errs[200][k]) > 3.5
+
+
+def test_hydrostatic_mass_conservation_periodic():
+    """eta and b stay conservative with the modified flux (its eta component is
+    a single-valued face flux)."""
+    wl = W.accuracy_1d(200)
+    r = O.run(_params_for(wl, flags=O.FLAG_HYDROSTATIC), wl["h"], wl["hu"], wl["b"], wl["x"],
+              wl["xi"], t_end=0.1)
+    S = r["stats"]
+    assert r["status"] == 0 and S.steps > 100
+    assert abs(S.mass_eta - S.mass_eta0) <= 1e-13 * abs(S.mass_eta0)
+    assert abs(S.mass_b - S.mass_b0) <= 1e-13 * abs(S.mass_b0)
+
+
 def test_adjoint_matches_central_differences():
     """The tape adjoint of the oracle against central finite differences of the
     same run (frozen step sizes, prescribed mesh)."""

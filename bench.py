@@ -104,7 +104,8 @@ def roofline(ctx, p, off, T, tnow, L, S, kern_ms, launches, steps, copy_bw=True)
     else:
         blk = L.block or 64  # 0 = the library's choice for the stage launches
         cpt = L.cells_per_thread or (2 if blk == 64 else 1)
-        kernel = f"k_stage<{blk}, {cpt}, {'true' if L.compact_tiles else 'false'}>"
+        hr = 'true' if p.flags & alew.F_HYDROSTATIC else 'false'
+        kernel = f"k_stage<{blk}, {cpt}, {'true' if L.compact_tiles else 'false'}, {hr}>"
         ctx.set_kernel_timing(True)
         W = {k: v.clone() for k, v in T.items()}
         ctx.run(p, off, W["h"], W["hu"], W["b"], W["x"], W["xi"], t0=tnow,

@@ -71,7 +71,19 @@ enum { ALEW_MESH_GIVEN = 0, ALEW_MESH_SINE = 1, ALEW_MESH_PAPER = 2, ALEW_MESH_F
 enum {
   ALEW_F_BETA_LOCAL = 1,  /* Dx in the indicators = the cell's own width instead of
                              the max width of the stage mesh (Sec. 2.2, Step 1)     */
-  ALEW_F_BETA_FROM_H = 2  /* indicators on (h, hu) instead of (eta, hu)             */
+  ALEW_F_BETA_FROM_H = 2, /* indicators on (h, hu) instead of (eta, hu)             */
+  ALEW_F_HYDROSTATIC = 4  /* well-balanced scheme with the hydrostatic reconstruction
+                             of Sec. 4.1, eq. (4.2)-(4.3), instead of the special
+                             source-term treatment of eq. (4.4)-(4.6): at each face
+                             h* = max(0, eta - max(b-, b+)) on both sides, the
+                             discharge kept, the momentum flux of the starred states
+                             plus each cell's pressure correction g/2 (h^2 - h*^2);
+                             the source is the integral of -g (eta_h - b_h) b_h' with
+                             eta_h, b_h the cubics through the values at the 4
+                             Gauss-Lobatto points.  The eta and b equations are those
+                             of the default scheme.  Stage-launch engine only
+                             (alew_run, alew_step); the persistent engine and
+                             alew_adjoint return ALEW_E_UNSUPPORTED.               */
 };
 
 typedef struct {

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libalew.so")
 OK, E_ARG, E_MESH, E_NEGDEPTH, E_NONFINITE, E_HIP, E_NOMEM, E_UNSUPPORTED, E_NEGWEIGHT = range(9)
 BC = {"periodic": 0, "transmissive": 1, "reflective": 2}
 MESH = {"given": 0, "sine": 1, "paper": 2, "fluid": 3}
-F_BETA_LOCAL, F_BETA_FROM_H = 1, 2
+F_BETA_LOCAL, F_BETA_FROM_H, F_HYDROSTATIC = 1, 2, 4
 ENGINE_AUTO, ENGINE_PERSISTENT, ENGINE_STAGES = 0, 1, 2
 
 

@@ -120,7 +120,7 @@ __device__ __forceinline__ void publish_stage(const Bufs& bf, int rec, const Sta
 
 // Stage s of one tile; par is the parity of the step (x^n in xa or xb).
 // NOEXT: tiles of TB slots (TB - 6 owned cells) instead of TB + 4 slots.
-template <int B, int CPT, bool NOEXT>
+template <int B, int CPT, bool NOEXT, bool HR>
 __global__ __launch_bounds__(B) void k_stage(Bufs bf, Consts cs, const Tile* __restrict__ tiles,
                                              int s, int par) {
   constexpr int TB = B * CPT;
@@ -149,7 +149,7 @@ __global__ __launch_bounds__(B) void k_stage(Bufs bf, Consts cs, const Tile* __r
   const StageScal sc = stage_scal_const(bf.inst, tl.inst, s);
   lds_sync();
   uint8_t* cl = bf.cls ? bf.cls + (int64_t)(s - 1) * bf.S + v.co : nullptr;
-  const StageRes r = stage_compute<B, CPT, NR>(bf, cs, v, sc, tl.c0, sm, cl, st, (int)threadIdx.x);
+  const StageRes r = stage_compute<B, CPT, NR, HR>(bf, cs, v, sc, tl.c0, sm, cl, st, (int)threadIdx.x);
   if (threadIdx.x == 0) publish_stage(bf, tl.rec, r);
 }
 
@@ -919,12 +919,22 @@ void launch_step_seq(alew_ctx* c, const Bufs& bf, const Consts& cs, hipStream_t 
   const dim3 gs((unsigned)c->n_tiles_stage), gp((unsigned)c->n_tiles_plain);
   for (int s = 1; s <= 3; ++s) {
     const int kt = kt_begin(c, st, 0, (double)c->tables_cells);
-    if (c->tiles_noext)
-      hipLaunchKernelGGL((k_stage<B, CPT, true>), gs, dim3(B), 0, st, bf, cs, c->tiles_stage_d, s,
-                         par);
-    else
-      hipLaunchKernelGGL((k_stage<B, CPT, false>), gs, dim3(B), 0, st, bf, cs, c->tiles_stage_d, s,
-                         par);
+    const bool hr = (cs.flags & F_HYDROSTATIC) != 0;
+    if (c->tiles_noext) {
+      if (hr)
+        hipLaunchKernelGGL((k_stage<B, CPT, true, true>), gs, dim3(B), 0, st, bf, cs,
+                           c->tiles_stage_d, s, par);
+      else
+        hipLaunchKernelGGL((k_stage<B, CPT, true, false>), gs, dim3(B), 0, st, bf, cs,
+                           c->tiles_stage_d, s, par);
+    } else {
+      if (hr)
+        hipLaunchKernelGGL((k_stage<B, CPT, false, true>), gs, dim3(B), 0, st, bf, cs,
+                           c->tiles_stage_d, s, par);
+      else
+        hipLaunchKernelGGL((k_stage<B, CPT, false, false>), gs, dim3(B), 0, st, bf, cs,
+                           c->tiles_stage_d, s, par);
+    }
     kt_end(c, st, kt);
     launch_after_stage(c, bf, st, s);
   }
@@ -1107,6 +1117,8 @@ alew_status drive(alew_ctx* c, const alew_params* p, int64_t ninst, const int64_
   const int64_t S = cell_off[ninst];
   if (S > c->max_cells) return fail(ALEW_E_ARG, "total cells exceed the context capacity");
   if ((dts || dt_log) && dts_stride <= 0) return fail(ALEW_E_ARG, "dts_stride must be > 0");
+  if (engine == 1 && (p->flags & F_HYDROSTATIC))
+    return fail(ALEW_E_UNSUPPORTED, "the hydrostatic reconstruction runs in the stage-launch engine only");
   const int B = pick_block(c, engine);
   const int CPT = (engine == 1) ? 1 : pick_cpt(c, B);
   const bool noext = engine != 1 && c->launch.compact_tiles == 1;
@@ -1375,6 +1387,8 @@ alew_status alew_adjoint(alew_ctx* c, const alew_params* p, int64_t ninst,
   if (!c) return fail(ALEW_E_ARG, "ctx is NULL");
   if (p->mesh != ALEW_MESH_SINE && p->mesh != ALEW_MESH_PAPER)
     return fail(ALEW_E_UNSUPPORTED, "the adjoint needs a prescribed (SINE or PAPER) mesh");
+  if (p->flags & F_HYDROSTATIC)
+    return fail(ALEW_E_UNSUPPORTED, "the adjoint covers the special source-term scheme only");
   if (ninst <= 0 || ninst > c->max_inst || !cell_off) return fail(ALEW_E_ARG, "bad ninst / cell_off");
   if (!h0 || !hu0 || !b0 || !x0 || !xi || !dts) return fail(ALEW_E_ARG, "NULL input array");
   if (nsteps < 1) return fail(ALEW_E_ARG, "nsteps must be >= 1");

@@ -20,7 +20,7 @@ namespace alew_dev {
 
 enum { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1, BC_REFLECTIVE = 2 };
 enum { MESH_GIVEN = 0, MESH_SINE = 1, MESH_PAPER = 2, MESH_FLUID = 3 };
-enum { F_BETA_LOCAL = 1, F_BETA_FROM_H = 2 };
+enum { F_BETA_LOCAL = 1, F_BETA_FROM_H = 2, F_HYDROSTATIC = 4 };
 // status bits (combined per instance; mapped to alew_status on the host)
 enum { SB_MESH = 1, SB_NEGDEPTH = 2, SB_NONFINITE = 4, SB_NEGWEIGHT = 8, SB_SEQUENCE = 16 };
 
@@ -230,6 +230,8 @@ __device__ __forceinline__ int64_t ghost_src(int bc, int64_t n, int64_t k, doubl
 struct CellRecon {
   double hL, mL, bL, hR, mR, bR;  // unlimited traces
   double rint;                    // sum_mu w_mu (eta_mu - etabar) b_x(x_mu) * Delta_j
+  double e1, e2, b1, b2;          // eta and b at the two interior Gauss-Lobatto points
+                                  // (hydrostatic reconstruction only)
   int cls;
   int negw;
 };
@@ -254,7 +256,9 @@ __device__ __forceinline__ void stencil_moments(const double* __restrict__ J5, d
 }
 
 // v5: eta (or h under F_BETA_FROM_H: chosen by the caller), stencil order
-// cells j-2..j+2; iJ0 = frcp(J5[2]).
+// cells j-2..j+2; iJ0 = frcp(J5[2]).  HR: instead of the special-source
+// quadrature term, keep eta and b at the two interior points.
+template <bool HR = false>
 __device__ __forceinline__ void recon_cell(const double* __restrict__ v5,  // indicator var
                                            const double* __restrict__ h5,
                                            const double* __restrict__ m5,
@@ -367,8 +371,13 @@ __device__ __forceinline__ void recon_cell(const double* __restrict__ v5,  // in
     }
     const double hv = h5[2] + (sBh * y + sCh * p2);
     const double bv = b5[2] + (sBb * y + sCb * p2);
-    const double bxv = (sBb + 2.0 * y * sCb) * iJ0;
-    ri += (wgl[mu] * J0) * (((hv + bv) - etabar) * bxv);
+    if (HR) {
+      if (mu == 1) { o.e1 = hv + bv; o.b1 = bv; }
+      if (mu == 2) { o.e2 = hv + bv; o.b2 = bv; }
+    } else {
+      const double bxv = (sBb + 2.0 * y * sCb) * iJ0;
+      ri += (wgl[mu] * J0) * (((hv + bv) - etabar) * bxv);
+    }
     if (mu == 0) { o.hL = hv; o.mL = m5[2] + (sBm * y + sCm * p2); o.bL = bv; }
     if (mu == 3) { o.hR = hv; o.mR = m5[2] + (sBm * y + sCm * p2); o.bR = bv; }
   };
@@ -475,6 +484,66 @@ __device__ __forceinline__ void face_flux(double hl, double ml, double bl, doubl
   f.speed = vmax(sl, sr);
   f.sl = sl;
   f.sr = sr;
+}
+
+// Hydrostatic reconstruction (Sec. 4.1, eq. (4.2)-(4.3)) at the face between
+// a left cell (own right trace hl, ml, bl) and a right cell (own left trace
+// hr, mr, br).  h* = max(0, eta - max(bl, br)) on both sides, the discharge
+// kept; the momentum flux of the starred states is Fc2 (same for both cells),
+// and each cell adds the pressure correction g/2 (h^2 - h*^2) of its own trace
+// (cl for the left cell, cr for the right one).  The eta flux of eq. (4.2)
+// reduces to the unmodified one: the theta term undoes the starred eta in
+// the central part and in the alpha jump.  Fc1, Gc, the jumps and the speeds
+// are those of face_flux (alpha from the unstarred traces).
+struct FaceHR {
+  double Fc1, Fc2, Gc, je, jm, jb, cl, cr;
+  double speed, sl, sr;
+};
+
+__device__ __forceinline__ void face_flux_hydro(double hl, double ml, double bl, double hr, double mr,
+                                                double br, double w, double g, double dry, FaceHR& f) {
+  const double el = hl + bl, er = hr + br;
+  double ul = 0.0, ur = 0.0;
+  if (hl > dry) ul = ml * frcp(hl); else ml = 0.0;
+  if (hr > dry) ur = mr * frcp(hr); else mr = 0.0;
+  const double bmax = vmax(bl, br);
+  const double hsl = vmax(el - bmax, 0.0), hsr = vmax(er - bmax, 0.0);
+  const double usl = hsl > dry ? ml * frcp(hsl) : 0.0;
+  const double usr = hsr > dry ? mr * frcp(hsr) : 0.0;
+  const double g2 = 0.5 * g;
+  f.Fc1 = 0.5 * ((ml - w * el) + (mr - w * er));
+  f.Fc2 = 0.5 * ((ml * usl + g2 * hsl * hsl - w * ml) + (mr * usr + g2 * hsr * hsr - w * mr));
+  f.Gc = -0.5 * w * (bl + br);
+  f.je = er - el;
+  f.jm = mr - ml;
+  f.jb = br - bl;
+  f.cl = g2 * (hl * hl - hsl * hsl);
+  f.cr = g2 * (hr * hr - hsr * hsr);
+  const double sl = fabs(ul - w) + fsqrt(g * vmax(hl, 0.0));
+  const double sr = fabs(ur - w) + fsqrt(g * vmax(hr, 0.0));
+  f.speed = vmax(sl, sr);
+  f.sl = sl;
+  f.sr = sr;
+}
+
+// Hydrostatic source of one cell (after eq. (4.3)): the integral over the cell
+// of -g (eta_h - b_h) d b_h / dx, eta_h and b_h the cubics through the values
+// at the 4 Gauss-Lobatto points (e0, b0 the left trace, e3, b3 the right one).
+// In the cell coordinate s in [0,1] the width cancels; the 4-point
+// Gauss-Lobatto rule (weights 1, 5, 5, 1 over 12) is exact for the degree-5
+// integrand, and d b_h / ds at the points is the cubic's differentiation
+// matrix, whose entries are 6, 1, sqrt 5 and multiples of the golden ratio
+// phi and of phi - 1.
+__device__ __forceinline__ double hydro_source(double g, double e0, double e1, double e2, double e3,
+                                               double b0, double b1, double b2, double b3) {
+  const double PHI = 1.6180339887498948482, PHI1 = 0.6180339887498948482;
+  const double R5 = 2.2360679774997896964;
+  const double d0 = -6.0 * b0 + 5.0 * PHI * b1 - 5.0 * PHI1 * b2 + b3;
+  const double d1 = -PHI * b0 + R5 * b2 - PHI1 * b3;
+  const double d2 = PHI1 * b0 - R5 * b1 + PHI * b3;
+  const double d3 = -b0 + 5.0 * PHI1 * b1 - 5.0 * PHI * b2 + 6.0 * b3;
+  const double q = ((e0 - b0) * d0 + (e3 - b3) * d3) + 5.0 * ((e1 - b1) * d1 + (e2 - b2) * d2);
+  return (-g / 12.0) * q;
 }
 
 }  // namespace alew_dev

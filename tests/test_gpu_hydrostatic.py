@@ -1,0 +1,184 @@
+"""GPU parity for the hydrostatic-reconstruction scheme (Sec. 4.1, eq. (4.2)-(4.3);
+flag HYDROSTATIC) against the oracle, through the C ABI.
+
+Bar as for the default scheme: 1e-11 relative L-inf for the state and nodes,
+identical step counts and detector class counts, bitwise equality between
+stage tile shapes; still water at round-off.  Combinations the library does
+not cover (persistent engine, adjoint) must be refused, not run.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2208_06588_amd import alew, workloads as W
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-11
+HR = alew.F_HYDROSTATIC
+
+
+@pytest.fixture(scope="module")
+def dev():
+    torch.cuda.set_device(0)
+    return torch.device("cuda", 0)
+
+
+def _t(a, dev):
+    return torch.tensor(np.asarray(a), dtype=torch.float64, device=dev)
+
+
+def _gp(wl):
+    return alew.params(bc=wl["bc"], mesh=wl["mesh"], mesh_A=wl["mesh_A"], mesh_k=wl["mesh_k"],
+                       mesh_omega=wl["mesh_omega"], cfl=wl["cfl"], weno_eps=wl["weno_eps"],
+                       flags=HR)
+
+
+def _op(wl):
+    bc = dict(periodic=O.BC_PERIODIC, transmissive=O.BC_TRANSMISSIVE, reflective=O.BC_REFLECTIVE)
+    mesh = dict(given=O.MESH_GIVEN, sine=O.MESH_SINE, paper=O.MESH_PAPER, fluid=O.MESH_FLUID)
+    return O.params(bc=bc[wl["bc"]], mesh=mesh[wl["mesh"]], mesh_A=wl["mesh_A"],
+                    mesh_k=wl["mesh_k"], mesh_omega=wl["mesh_omega"], cfl=wl["cfl"],
+                    weno_eps=wl["weno_eps"], flags=O.FLAG_HYDROSTATIC)
+
+
+def _relerr(g, r):
+    g = np.asarray(g)
+    r = np.asarray(r)
+    return float(np.abs(g - r).max() / max(1.0, np.abs(r).max()))
+
+
+def _run_gpu(ctx, p, wl, dev, **kw):
+    n = len(wl["h"])
+    t = {k: _t(wl[k], dev) for k in ("h", "hu", "b", "x", "xi")}
+    st = ctx.run(p, [0, n], t["h"], t["hu"], t["b"], t["x"], t["xi"], **kw)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in t.items()}, st[0]
+
+
+def _assert_parity(g, r):
+    for k in ("h", "hu", "b", "x"):
+        e = _relerr(g[k], r[k])
+        assert e <= TOL, (k, e)
+
+
+def test_hydrostatic_periodic_smooth_full_run(dev):
+    """200 cells on periodic [0,1] (Example 5.1 data), sine mesh, CFL 0.6, to
+    t = 0.1: state, nodes, step count and class counts as the oracle."""
+    wl = W.accuracy_1d(200)
+    ctx = alew.Context(200, 1)
+    g, st = _run_gpu(ctx, _gp(wl), wl, dev, t_end=[0.1])
+    r = O.run(_op(wl), wl["h"], wl["hu"], wl["b"], wl["x"], wl["xi"], t_end=0.1)
+    assert st.status == 0 and r["status"] == 0
+    assert st.steps == r["stats"].steps
+    assert tuple(st.n_class) == tuple(r["stats"].n_class)
+    _assert_parity(g, r)
+
+
+@pytest.mark.parametrize("bottom", ["smooth", "step"])
+def test_hydrostatic_still_water_on_gpu(dev, bottom):
+    """Example 5.3 with the hydrostatic reconstruction: round-off on the GPU
+    (Tables 5.4/5.5, hydrostatic rows) and the oracle's result."""
+    wl = W.still_water_1d(200, bottom)
+    ctx = alew.Context(200, 1)
+    g, st = _run_gpu(ctx, _gp(wl), wl, dev, t_end=[0.5])
+    assert st.status == 0
+    assert np.abs(g["h"] + g["b"] - 10).max() < 1e-12
+    assert np.abs(g["hu"]).max() < 1e-11
+    r = O.run(_op(wl), wl["h"], wl["hu"], wl["b"], wl["x"], wl["xi"], t_end=0.5)
+    _assert_parity(g, r)
+
+
+def test_hydrostatic_dry_bed_and_bowl(dev):
+    """Wet/dry with the limiter active: Moses's second problem (Example 5.2,
+    CFL 0.08) to t = 1 and the parabolic bowl with the fluid-following mesh
+    (2048 cells, 30 steps); h >= 0 and the oracle's result."""
+    wl = W.moses2_1d(200, t_end=1.0)
+    ctx = alew.Context(2048, 1)
+    g, st = _run_gpu(ctx, _gp(wl), wl, dev, t_end=[1.0])
+    r = O.run(_op(wl), wl["h"], wl["hu"], wl["b"], wl["x"], wl["xi"], t_end=1.0)
+    assert st.status == 0 and r["status"] == 0 and st.n_limited > 0
+    assert st.h_min >= -1e-20
+    assert st.steps == r["stats"].steps
+    _assert_parity(g, r)
+    wl = W.bowl_1d(2048)
+    g, st = _run_gpu(ctx, _gp(wl), wl, dev, max_steps=[30])
+    r = O.run(_op(wl), wl["h"], wl["hu"], wl["b"], wl["x"], wl["xi"], max_steps=30)
+    assert st.status == 0 and r["status"] == 0 and st.n_limited > 0
+    assert g["h"].min() >= -1e-20
+    _assert_parity(g, r)
+
+
+def test_hydrostatic_batch_tile_shapes_and_oracle(dev):
+    """Ragged perturbation batch (Example 5.4 shape; six small instances and
+    two with ghost-free tiles at every width), 20 steps: stage tiles of 64 x 2
+    (automatic), 64 x 1, 128 x 2, 256 x 1 and the compact 64 x 2 and 256 x 1
+    forms are bitwise equal; every instance matches the oracle with equal class
+    counts; and the scheme differs from the special-source one (the flag takes
+    effect) by far less than the perturbation."""
+    rng = np.random.default_rng(7)
+    ns = list(rng.integers(40, 400, 6)) + [1100, 1733]
+    eps = rng.uniform(1e-5, 1e-2, len(ns))
+    insts = [W.perturbation_instance(int(n), float(e)) for n, e in zip(ns, eps)]
+    bt = W.pack(insts, bc="transmissive", cfl=0.6, weno_eps=1e-9, mesh="sine", mesh_A=0.05,
+                mesh_k=1.0, mesh_omega=math.pi)
+    off = bt["cell_off"]
+    n, ninst = int(off[-1]), len(off) - 1
+    nsteps = 20
+    outs = []
+    for block, cpt, compact in ((0, 0, 0), (64, 1, 0), (128, 2, 0), (256, 1, 0), (64, 2, 1),
+                                (256, 1, 1)):
+        ctx = alew.Context(n, ninst)
+        ctx.set_launch(engine=alew.ENGINE_STAGES, block=block, use_graph=1, cells_per_thread=cpt,
+                       compact_tiles=compact)
+        T = {k: _t(bt[k], dev) for k in ("h", "hu", "b", "x", "xi")}
+        st = ctx.run(_gp(bt), off, T["h"], T["hu"], T["b"], T["x"], T["xi"],
+                     max_steps=[nsteps] * ninst)
+        torch.cuda.synchronize()
+        outs.append(({k: v.cpu().numpy() for k, v in T.items()}, st))
+    ref, sref = outs[0]
+    for o, st in outs[1:]:
+        for k in ("h", "hu", "b", "x"):
+            assert np.array_equal(o[k], ref[k]), k
+        assert [tuple(s.n_class) for s in st] == [tuple(s.n_class) for s in sref]
+    for i in range(ninst):
+        a, e = int(off[i]), int(off[i + 1])
+        r = O.run(_op(bt), bt["h"][a:e], bt["hu"][a:e], bt["b"][a:e], bt["x"][a + i:e + i + 1],
+                  bt["xi"][a + i:e + i + 1], max_steps=nsteps)
+        assert r["status"] == 0
+        g = dict(h=ref["h"][a:e], hu=ref["hu"][a:e], b=ref["b"][a:e], x=ref["x"][a + i:e + i + 1])
+        _assert_parity(g, r)
+        assert sref[i].steps == r["stats"].steps == nsteps
+        assert tuple(sref[i].n_class) == tuple(r["stats"].n_class)
+    # the special-source scheme on the same batch
+    p_ss = alew.params(bc="transmissive", mesh="sine", mesh_A=0.05, mesh_k=1.0,
+                       mesh_omega=math.pi, cfl=0.6, weno_eps=1e-9)
+    ctx = alew.Context(n, ninst)
+    T = {k: _t(bt[k], dev) for k in ("h", "hu", "b", "x", "xi")}
+    ctx.run(p_ss, off, T["h"], T["hu"], T["b"], T["x"], T["xi"], max_steps=[nsteps] * ninst)
+    d = float(np.abs(T["hu"].cpu().numpy() - ref["hu"]).max())
+    assert 1e-12 < d < 1e-4, d
+
+
+def test_hydrostatic_unsupported_combinations_are_refused(dev):
+    """The persistent engine and the adjoint cover the special-source scheme
+    only: with the flag they return ALEW_E_UNSUPPORTED and leave the state
+    untouched."""
+    wl = W.accuracy_1d(64)
+    ctx = alew.Context(64, 1)
+    ctx.set_launch(engine=alew.ENGINE_PERSISTENT, block=128)
+    T = {k: _t(wl[k], dev) for k in ("h", "hu", "b", "x", "xi")}
+    h0 = T["h"].clone()
+    with pytest.raises(alew.AlewError) as ei:
+        ctx.run(_gp(wl), [0, 64], T["h"], T["hu"], T["b"], T["x"], T["xi"], max_steps=[2])
+    assert ei.value.status == alew.E_UNSUPPORTED
+    assert torch.equal(T["h"], h0)
+    ctx.set_launch(engine=alew.ENGINE_STAGES)
+    dts = torch.full((2,), 1e-4, dtype=torch.float64, device=dev)
+    gx = _t([0.3, 0.6], dev)
+    gh = torch.zeros(2, dtype=torch.float64, device=dev)
+    with pytest.raises(alew.AlewError) as ei:
+        ctx.adjoint(_gp(wl), [0, 64], T["h"], T["hu"], T["b"], T["x"], T["xi"], 2, dts, 2, gx, gh)
+    assert ei.value.status == alew.E_UNSUPPORTED

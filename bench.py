@@ -184,6 +184,31 @@ def bowl_leg(dev, n, steps, warmup):
                 h_min=st[0].h_min)
 
 
+def hydrostatic_leg(ctx, p, off, T, tnow, L, S, steps):
+    """The hydrostatic-reconstruction scheme (Sec. 4.1) on the forward batch,
+    in the forward leg's launch: 2 warm-up steps, then `steps` timed steps in
+    one call, and its stage kernel's roofline from the event-timed pass."""
+    import torch
+    ninst = len(off) - 1
+    W = {k: v.clone() for k, v in T.items()}
+    st = ctx.run(p, off, W["h"], W["hu"], W["b"], W["x"], W["xi"], t0=tnow, max_steps=[2] * ninst)
+    tnow = [s.t for s in st]
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    st = ctx.run(p, off, W["h"], W["hu"], W["b"], W["x"], W["xi"], t0=tnow,
+                 max_steps=[steps] * ninst)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - a
+    assert all(s.steps == steps and s.status == 0 for s in st), "hydrostatic run did not complete"
+    kern_ms, launches = ctx.last_timing()
+    roof = roofline(ctx, p, off, W, tnow=[s.t for s in st], L=L, S=S, kern_ms=kern_ms,
+                    launches=launches, steps=steps, copy_bw=False)
+    del W
+    return dict(workload="the forward batch with the hydrostatic reconstruction (Sec. 4.1)",
+                steps=steps, value=3.0 * S * steps / wall, unit="cell-updates/s",
+                ms_per_step=round(wall * 1e3 / steps, 4), roofline=roof)
+
+
 def cpu_baseline(bt, ninst_sample, steps):
     """The oracle on the host cores: first ninst_sample instances of the same
     draw, `steps` CFL steps each, one instance per thread."""
@@ -351,7 +376,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--engine", default="tune", choices=["tune", "persistent", "stages"])
+    ap.add_argument("--engine", default="auto", choices=["auto", "tune", "persistent", "stages"],
+                    help="auto: the library's automatic launch (stage launches, one-wave tiles "
+                         "of two cells per thread); tune: the autotuner's pick")
+    ap.add_argument("--no-tune-report", action="store_true",
+                    help="skip running the autotuner beside the automatic launch")
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--graph", type=int, default=1, help="stage engine: replay steps as a hipGraph")
     ap.add_argument("--cpt", type=int, default=1, help="stage engine: cells per thread (1 or 2)")
@@ -375,6 +404,12 @@ def main():
                     help="also time the whole batch to t = 0.2 (every instance its own CFL steps; "
                          "about a minute)")
     ap.add_argument("--bowl-steps", type=int, default=20)
+    ap.add_argument("--scheme", default="special", choices=["special", "hydrostatic"],
+                    help="well-balanced form of the timed forward leg (Sec. 4.2 special source "
+                         "term, or Sec. 4.1 hydrostatic reconstruction)")
+    ap.add_argument("--no-hydrostatic", action="store_true",
+                    help="skip the hydrostatic-reconstruction leg")
+    ap.add_argument("--hr-steps", type=int, default=10)
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="first copy a buffer of this many MiB (calibrates profiler byte counters)")
     args = ap.parse_args()
@@ -405,14 +440,22 @@ def main():
     ninst = len(off) - 1
     S = off[-1]
     log(f"workload: {ninst} instances, {S} cells ({time.perf_counter() - t0:.1f} s to build)")
+    hydro = args.scheme == "hydrostatic"
     p = alew.params(bc="transmissive", mesh="sine", mesh_A=0.05, mesh_k=1.0, mesh_omega=np.pi,
-                    cfl=0.6, weno_eps=1e-9)
+                    cfl=0.6, weno_eps=1e-9, flags=alew.F_HYDROSTATIC if hydro else 0)
     T = {k: torch.tensor(bt[k], dtype=torch.float64, device=dev) for k in ("h", "hu", "b", "x", "xi")}
     ctx = alew.Context(S, ninst)
 
-    if args.engine == "tune":
+    tune_report = None
+    if args.engine in ("auto", "tune") and not (args.engine == "auto" and args.no_tune_report):
         best, times = autotune.tune(ctx, p, off, T, steps=2, use_cache=False, log=log)
         log(f"autotune picked {best}")
+        tune_report = dict(picked=autotune.name_of(best),
+                           first_round_ms={k: round(v * 1e3, 2) for k, v in times.items()})
+    if args.engine == "auto":
+        ctx.set_launch()  # the library's automatic launch
+    elif args.engine == "tune":
+        pass
     else:
         eng = alew.ENGINE_PERSISTENT if args.engine == "persistent" else alew.ENGINE_STAGES
         ctx.set_launch(engine=eng, block=args.block, use_graph=args.graph,
@@ -449,7 +492,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"ragged batch of {ninst} 1D perturbation-of-still-water "
                                f"instances, 1000-20000 cells each (seed 2208065881), {S} cells, "
-                               "transmissive, sine-moving mesh, CFL 0.6, FP64 SSP-RK3",
+                               "transmissive, sine-moving mesh, CFL 0.6, FP64 SSP-RK3, "
+                               + ("hydrostatic reconstruction" if hydro else
+                                  "special source-term treatment"),
                    "ninst": ninst, "cells": S, "engine": engine_name,
                    "block": L.block or (256 if L.engine == alew.ENGINE_PERSISTENT else 64),
                    "cells_per_thread": L.cells_per_thread or
@@ -458,6 +503,8 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": roof,
     }
+    if tune_report is not None:
+        out["autotune"] = tune_report
 
     if args.full_run:
         # the whole job: every instance from t = 0 to t = 0.2 in one call
@@ -476,6 +523,14 @@ def main():
                                steps_max=int(max(s.steps for s in stf)))
         log(f"full run: {out['full_run']}")
         del W2
+
+    if not hydro and not args.no_hydrostatic and L.engine != alew.ENGINE_PERSISTENT:
+        # the hydrostatic-reconstruction scheme on the same batch, same launch
+        p_hr = alew.params(bc="transmissive", mesh="sine", mesh_A=0.05, mesh_k=1.0,
+                           mesh_omega=np.pi, cfl=0.6, weno_eps=1e-9, flags=alew.F_HYDROSTATIC)
+        out["hydrostatic"] = hydrostatic_leg(ctx, p_hr, off, T, [s.t for s in st], L, S,
+                                             args.hr_steps)
+        log(f"hydrostatic: {out['hydrostatic']}")
 
     if not args.no_speedup:
         # batched (one call) vs one call per instance, same GPU, same 64 instances

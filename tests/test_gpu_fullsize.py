@@ -2,7 +2,8 @@
 shape: one-wave stage tiles of 64 threads, two cells per thread).
 
 * The 4096-instance perturbation batch (1000-20000 cells each, 43,017,136
-  cells) runs a few CFL steps on the GPU.  Sampled instances (first, last,
+  cells) runs a few CFL steps on the GPU, with the special source-term
+  treatment and with the hydrostatic reconstruction.  Sampled instances (first, last,
   largest, smallest and two more) are run one by one by the oracle and
   compared element by element at 1e-11, with identical step counts, step sizes
   and detector class counts.  Every instance must keep h >= 0 and conserve the
@@ -38,15 +39,18 @@ def _relerr(g, r):
     return float(np.abs(g - r).max() / max(1.0, np.abs(r).max()))
 
 
-def test_full_perturbation_batch_sampled_instances(dev):
+@pytest.mark.parametrize("scheme", ["special", "hydrostatic"])
+def test_full_perturbation_batch_sampled_instances(dev, scheme):
     bt = W.perturbation_batch()
     off = [int(v) for v in bt["cell_off"]]
     ninst, S = len(off) - 1, off[-1]
     assert ninst == 4096 and S == 43017136
+    hr = scheme == "hydrostatic"
     p = alew.params(bc="transmissive", mesh="sine", mesh_A=0.05, mesh_k=1.0, mesh_omega=math.pi,
-                    cfl=0.6, weno_eps=1e-9)
+                    cfl=0.6, weno_eps=1e-9, flags=alew.F_HYDROSTATIC if hr else 0)
     op = O.params(bc=O.BC_TRANSMISSIVE, mesh=O.MESH_SINE, mesh_A=0.05, mesh_k=1.0,
-                  mesh_omega=math.pi, cfl=0.6, weno_eps=1e-9)
+                  mesh_omega=math.pi, cfl=0.6, weno_eps=1e-9,
+                  flags=O.FLAG_HYDROSTATIC if hr else 0)
     ctx = alew.Context(S, ninst)
     ctx.set_launch(engine=alew.ENGINE_STAGES, use_graph=1)
     T = {k: torch.tensor(bt[k], dtype=torch.float64, device=dev) for k in ("h", "hu", "b", "x", "xi")}

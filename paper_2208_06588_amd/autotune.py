@@ -88,8 +88,6 @@ def tune(ctx: alew.Context, p: alew.Params, cell_off, state: dict, steps: int = 
         ctx.set_launch(**best)
         return best, cache[key]["times"]
     ninst = len(cell_off) - 1
-    if p.flags & alew.F_HYDROSTATIC:  # the stage-launch engine only
-        candidates = [c for c in candidates if c["engine"] == alew.ENGINE_STAGES]
 
     def time_one(cand, ns):
         ctx.set_launch(**cand)

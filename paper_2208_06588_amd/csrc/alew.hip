@@ -454,7 +454,7 @@ __global__ __launch_bounds__(1024) void k_count_active(Bufs bf, int* __restrict_
 }
 
 // Persistent engine: one launch for the whole batch.
-template <int B>
+template <int B, bool HR>
 __global__ __launch_bounds__(B) void k_persistent(Bufs bf, Consts cs,
                                                   const int32_t* __restrict__ order,
                                                   unsigned* __restrict__ queue,
@@ -481,7 +481,7 @@ __global__ __launch_bounds__(B) void k_persistent(Bufs bf, Consts cs,
         const StageScal sc = stage_scal(sI, s);
         double amax = 0.0, jmax = 0.0;
         for (int64_t c0 = 0; c0 < v.n; c0 += B - 2) {
-          StageRes r = stage_tile<B, 1>(bf, cs, v, sc, c0, sm, nullptr);
+          StageRes r = stage_tile<B, 1, HR>(bf, cs, v, sc, c0, sm, nullptr);
           amax = fmax(amax, r.alpha);
           jmax = fmax(jmax, r.maxJ);
           c_cls[0] += r.ncls0; c_cls[1] += r.ncls1; c_cls[2] += r.ncls2;
@@ -1051,7 +1051,9 @@ alew_status run_persistent(alew_ctx* c, const Bufs& bf, const Consts& cs, int64_
   int dev = 0, ncu = 0, per_cu = 0;
   HIPCHK(hipGetDevice(&dev));
   HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-  HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<B>, B, 0));
+  const bool hr = (cs.flags & F_HYDROSTATIC) != 0;
+  if (hr) HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<B, true>, B, 0));
+  else HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<B, false>, B, 0));
   int64_t grid = (int64_t)std::max(1, ncu) * std::max(1, per_cu);
   grid = std::min<int64_t>(grid, ninst);
   const int limit = c->launch.steps_per_launch;
@@ -1060,8 +1062,12 @@ alew_status run_persistent(alew_ctx* c, const Bufs& bf, const Consts& cs, int64_
   for (;;) {
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, c->stream, c->queue_d);
     HIPCHK(hipEventRecord(c->ev0, c->stream));
-    hipLaunchKernelGGL(k_persistent<B>, dim3((unsigned)grid), dim3(B), 0, c->stream, bf, cs,
-                       c->order_d, c->queue_d, limit);
+    if (hr)
+      hipLaunchKernelGGL((k_persistent<B, true>), dim3((unsigned)grid), dim3(B), 0, c->stream, bf,
+                         cs, c->order_d, c->queue_d, limit);
+    else
+      hipLaunchKernelGGL((k_persistent<B, false>), dim3((unsigned)grid), dim3(B), 0, c->stream, bf,
+                         cs, c->order_d, c->queue_d, limit);
     HIPCHK(hipEventRecord(c->ev1, c->stream));
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventSynchronize(c->ev1));
@@ -1117,8 +1123,6 @@ alew_status drive(alew_ctx* c, const alew_params* p, int64_t ninst, const int64_
   const int64_t S = cell_off[ninst];
   if (S > c->max_cells) return fail(ALEW_E_ARG, "total cells exceed the context capacity");
   if ((dts || dt_log) && dts_stride <= 0) return fail(ALEW_E_ARG, "dts_stride must be > 0");
-  if (engine == 1 && (p->flags & F_HYDROSTATIC))
-    return fail(ALEW_E_UNSUPPORTED, "the hydrostatic reconstruction runs in the stage-launch engine only");
   const int B = pick_block(c, engine);
   const int CPT = (engine == 1) ? 1 : pick_cpt(c, B);
   const bool noext = engine != 1 && c->launch.compact_tiles == 1;

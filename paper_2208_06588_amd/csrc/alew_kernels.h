@@ -532,14 +532,14 @@ __device__ __forceinline__ StageRes stage_compute(const Bufs& bf, const Consts& 
 }
 
 // One stage over the tile of owned cells [c0, c0 + TB - 2) of one instance.
-template <int B, int CPT>
+template <int B, int CPT, bool HR>
 __device__ __forceinline__ StageRes stage_tile(const Bufs& bf, const Consts& cs, const View& v,
                                                const StageScal& sc, int64_t c0,
                                                SmemStage<B, CPT>& sm, uint8_t* cls_inst) {
   int st = 0;
   stage_load<B, CPT>(bf, cs, v, sc, c0, sm, st);
   lds_sync();
-  return stage_compute<B, CPT>(bf, cs, v, sc, c0, sm, cls_inst, st, (int)threadIdx.x);
+  return stage_compute<B, CPT, B * CPT, HR>(bf, cs, v, sc, c0, sm, cls_inst, st, (int)threadIdx.x);
 }
 
 // Scalars of stage s of instance i read through the constant address space

@@ -3,8 +3,8 @@ flag HYDROSTATIC) against the oracle, through the C ABI.
 
 Bar as for the default scheme: 1e-11 relative L-inf for the state and nodes,
 identical step counts and detector class counts, bitwise equality between
-stage tile shapes; still water at round-off.  Combinations the library does
-not cover (persistent engine, adjoint) must be refused, not run.
+stage tile shapes and engines; still water at round-off.  The adjoint does not
+cover this form and must refuse it, not run.
 """
 import math
 
@@ -115,9 +115,10 @@ def test_hydrostatic_batch_tile_shapes_and_oracle(dev):
     """Ragged perturbation batch (Example 5.4 shape; six small instances and
     two with ghost-free tiles at every width), 20 steps: stage tiles of 64 x 2
     (automatic), 64 x 1, 128 x 2, 256 x 1 and the compact 64 x 2 and 256 x 1
-    forms are bitwise equal; every instance matches the oracle with equal class
-    counts; and the scheme differs from the special-source one (the flag takes
-    effect) by far less than the perturbation."""
+    forms, and the persistent engine at 128 and 256 threads, are bitwise equal;
+    every instance matches the oracle with equal class counts; and the scheme
+    differs from the special-source one (the flag takes effect) by far less
+    than the perturbation."""
     rng = np.random.default_rng(7)
     ns = list(rng.integers(40, 400, 6)) + [1100, 1733]
     eps = rng.uniform(1e-5, 1e-2, len(ns))
@@ -128,10 +129,12 @@ def test_hydrostatic_batch_tile_shapes_and_oracle(dev):
     n, ninst = int(off[-1]), len(off) - 1
     nsteps = 20
     outs = []
-    for block, cpt, compact in ((0, 0, 0), (64, 1, 0), (128, 2, 0), (256, 1, 0), (64, 2, 1),
-                                (256, 1, 1)):
+    S_, P_ = alew.ENGINE_STAGES, alew.ENGINE_PERSISTENT
+    for engine, block, cpt, compact in ((S_, 0, 0, 0), (S_, 64, 1, 0), (S_, 128, 2, 0),
+                                        (S_, 256, 1, 0), (S_, 64, 2, 1), (S_, 256, 1, 1),
+                                        (P_, 128, 1, 0), (P_, 256, 1, 0)):
         ctx = alew.Context(n, ninst)
-        ctx.set_launch(engine=alew.ENGINE_STAGES, block=block, use_graph=1, cells_per_thread=cpt,
+        ctx.set_launch(engine=engine, block=block, use_graph=1, cells_per_thread=cpt,
                        compact_tiles=compact)
         T = {k: _t(bt[k], dev) for k in ("h", "hu", "b", "x", "xi")}
         st = ctx.run(_gp(bt), off, T["h"], T["hu"], T["b"], T["x"], T["xi"],
@@ -162,23 +165,16 @@ def test_hydrostatic_batch_tile_shapes_and_oracle(dev):
     assert 1e-12 < d < 1e-4, d
 
 
-def test_hydrostatic_unsupported_combinations_are_refused(dev):
-    """The persistent engine and the adjoint cover the special-source scheme
-    only: with the flag they return ALEW_E_UNSUPPORTED and leave the state
-    untouched."""
+def test_hydrostatic_adjoint_is_refused(dev):
+    """The adjoint covers the special-source scheme only: with the flag it
+    returns ALEW_E_UNSUPPORTED and writes nothing."""
     wl = W.accuracy_1d(64)
     ctx = alew.Context(64, 1)
-    ctx.set_launch(engine=alew.ENGINE_PERSISTENT, block=128)
     T = {k: _t(wl[k], dev) for k in ("h", "hu", "b", "x", "xi")}
-    h0 = T["h"].clone()
-    with pytest.raises(alew.AlewError) as ei:
-        ctx.run(_gp(wl), [0, 64], T["h"], T["hu"], T["b"], T["x"], T["xi"], max_steps=[2])
-    assert ei.value.status == alew.E_UNSUPPORTED
-    assert torch.equal(T["h"], h0)
-    ctx.set_launch(engine=alew.ENGINE_STAGES)
     dts = torch.full((2,), 1e-4, dtype=torch.float64, device=dev)
     gx = _t([0.3, 0.6], dev)
-    gh = torch.zeros(2, dtype=torch.float64, device=dev)
+    gh = torch.full((2,), -1.0, dtype=torch.float64, device=dev)
     with pytest.raises(alew.AlewError) as ei:
         ctx.adjoint(_gp(wl), [0, 64], T["h"], T["hu"], T["b"], T["x"], T["xi"], 2, dts, 2, gx, gh)
     assert ei.value.status == alew.E_UNSUPPORTED
+    assert (gh == -1.0).all()

@@ -206,15 +206,17 @@ def test_batched_engines_bitwise_and_oracle(dev):
         assert outs[0][1][i].steps == nsteps
 
 
+@pytest.mark.parametrize("scheme", ["special", "hydrostatic"])
 @pytest.mark.parametrize("bc", ["periodic", "transmissive", "reflective"])
-def test_small_and_tile_edge_sizes_every_boundary(dev, bc):
+def test_small_and_tile_edge_sizes_every_boundary(dev, bc, scheme):
     """Degenerate and tile-edge instance sizes in one ragged batch: 5 cells
     (the smallest allowed, fewer cells than a periodic wrap of the ghosts
     spans twice), sizes around the owned cells of one-wave 64 x 2 tiles (126),
     of 128 x 1 and 256 x 1 tiles, smooth data, sine-moving mesh, 8 steps.  The
     automatic launch, 256 x 1 stage tiles and the persistent engine agree
     bitwise; every instance matches the oracle (state, nodes, step sizes,
-    class counts)."""
+    class counts).  Both well-balanced forms (special source term, hydrostatic
+    reconstruction)."""
     sizes = [5, 6, 7, 9, 13, 63, 64, 65, 125, 126, 127, 128, 131, 132, 133, 250, 252, 253, 257]
     insts = []
     for n in sizes:
@@ -224,7 +226,9 @@ def test_small_and_tile_edge_sizes_every_boundary(dev, bc):
                 mesh_omega=math.pi)
     off = bt["cell_off"]
     n, ninst = int(off[-1]), len(off) - 1
-    p = _gp(bt)
+    hr = scheme == "hydrostatic"
+    p = _gp(bt, flags=alew.F_HYDROSTATIC if hr else 0)
+    op = _op(bt, flags=O.FLAG_HYDROSTATIC if hr else 0)
     nsteps = 8
     outs = []
     for engine, block, cpt in ((alew.ENGINE_AUTO, 0, 0), (alew.ENGINE_STAGES, 256, 1),
@@ -242,7 +246,7 @@ def test_small_and_tile_edge_sizes_every_boundary(dev, bc):
         assert [tuple(s.n_class) for s in st] == [tuple(s.n_class) for s in sref]
     for i in range(ninst):
         a, e = int(off[i]), int(off[i + 1])
-        r = O.run(_op(bt), bt["h"][a:e], bt["hu"][a:e], bt["b"][a:e], bt["x"][a + i:e + i + 1],
+        r = O.run(op, bt["h"][a:e], bt["hu"][a:e], bt["b"][a:e], bt["x"][a + i:e + i + 1],
                   bt["xi"][a + i:e + i + 1], max_steps=nsteps)
         assert r["status"] == 0
         g = dict(h=ref["h"][a:e], hu=ref["hu"][a:e], b=ref["b"][a:e], x=ref["x"][a + i:e + i + 1])

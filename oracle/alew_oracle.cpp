@@ -473,7 +473,11 @@ static TraceFlux<T> trace_state(T h, T m, T b, double dry_eps) {
 template <class T>
 static void hydro_face_flux(const Params& P, const TraceFlux<T>& qm, const TraceFlux<T>& qp,
                             double nrm, double w, T alpha, T& H1, T& H2) {
-  T bmax = (val(qm.b) > val(qp.b)) ? qm.b : qp.b;
+  /* max(b-, b+), ties resolved by the face's orientation (its left trace
+   * first), so that both cells of the face take the same branch */
+  const TraceFlux<T>& fl = nrm > 0.0 ? qm : qp;
+  const TraceFlux<T>& fr = nrm > 0.0 ? qp : qm;
+  T bmax = (val(fl.b) >= val(fr.b)) ? fl.b : fr.b;
   T hsm = qm.eta - bmax, hsp = qp.eta - bmax;
   if (val(hsm) < 0.0) hsm = 0.0;
   if (val(hsp) < 0.0) hsp = 0.0;

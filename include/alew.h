@@ -81,9 +81,8 @@ enum {
                              the source is the integral of -g (eta_h - b_h) b_h' with
                              eta_h, b_h the cubics through the values at the 4
                              Gauss-Lobatto points.  The eta and b equations are those
-                             of the default scheme.  Forward only (alew_run,
-                             alew_step, either engine); alew_adjoint returns
-                             ALEW_E_UNSUPPORTED.                                   */
+                             of the default scheme.  Every entry point and engine
+                             (alew_step, alew_run, alew_adjoint).                  */
 };
 
 typedef struct {

@@ -1391,8 +1391,6 @@ alew_status alew_adjoint(alew_ctx* c, const alew_params* p, int64_t ninst,
   if (!c) return fail(ALEW_E_ARG, "ctx is NULL");
   if (p->mesh != ALEW_MESH_SINE && p->mesh != ALEW_MESH_PAPER)
     return fail(ALEW_E_UNSUPPORTED, "the adjoint needs a prescribed (SINE or PAPER) mesh");
-  if (p->flags & F_HYDROSTATIC)
-    return fail(ALEW_E_UNSUPPORTED, "the adjoint covers the special source-term scheme only");
   if (ninst <= 0 || ninst > c->max_inst || !cell_off) return fail(ALEW_E_ARG, "bad ninst / cell_off");
   if (!h0 || !hu0 || !b0 || !x0 || !xi || !dts) return fail(ALEW_E_ARG, "NULL input array");
   if (nsteps < 1) return fail(ALEW_E_ARG, "nsteps must be >= 1");
@@ -1559,7 +1557,12 @@ alew_status alew_adjoint(alew_ctx* c, const alew_params* p, int64_t ninst,
       for (int s3 = 3; s3 >= 1; --s3) {
         ab.q = d.q + (int64_t)3 * (s3 - 1) * S;
         ab.akeyd = d.akey + (int64_t)(s3 - 1) * ninst;
-        hipLaunchKernelGGL(k_adj_fused<BA>, ga, dim3(BA), 0, st, ab, cs, atiles_d, s3, gfold);
+        if (cs.flags & F_HYDROSTATIC)
+          hipLaunchKernelGGL((k_adj_fused<BA, true>), ga, dim3(BA), 0, st, ab, cs, atiles_d, s3,
+                             gfold);
+        else
+          hipLaunchKernelGGL((k_adj_fused<BA, false>), ga, dim3(BA), 0, st, ab, cs, atiles_d, s3,
+                             gfold);
         hipLaunchKernelGGL(k_adj_fold, dim3(gfb), dim3(256), 0, st, ab, cs, gfold);
         hipLaunchKernelGGL(k_adj_lsum, dim3((unsigned)((ninst + 3) / 4)), dim3(256), 0, st, ab, tfirst_d);
         hipLaunchKernelGGL(k_adj_patch, dim3((unsigned)((ninst + 63) / 64)), dim3(64), 0, st, ab, cs, s3);

@@ -110,6 +110,86 @@ __device__ __forceinline__ void face_vjp(double hl, double ml, double bl, double
   Lr.h = lhr; Lr.m = wr ? lmrp : 0.0; Lr.b = lbr;
 }
 
+// Reverse of one face of the hydrostatic form (face_flux_hydro): the left
+// cell's residual takes -(F1, F2 + cl, G) and the right cell's +(F1, F2 + cr,
+// G), each with the alpha jump; alpha is a constant here (its own adjoint
+// goes through the trace that attains it).  max(bl, br) at a tie takes bl.
+__device__ __forceinline__ void face_vjp_hydro(double hl, double ml, double bl, double hr,
+                                               double mr, double br, double w, double alpha,
+                                               double g, double dry, const double rl[3],
+                                               const double rr[3], TraceAdj& Ll, TraceAdj& Lr) {
+  const double lF1 = rr[0] - rl[0];
+  const double lF2 = rr[1] - rl[1];
+  const double lG = rr[2] - rl[2];
+  const double lcl = -rl[1], lcr = rr[1];
+  const bool wl = hl > dry, wr = hr > dry;
+  const double mlp = wl ? ml : 0.0, mrp = wr ? mr : 0.0;
+  const double el = hl + bl, er = hr + br;
+  const bool lmax = bl >= br;
+  const double bmax = lmax ? bl : br;
+  const double xl = el - bmax, xr = er - bmax;
+  const double hsl = xl > 0.0 ? xl : 0.0, hsr = xr > 0.0 ? xr : 0.0;
+  const bool sl = hsl > dry, sr = hsr > dry;
+  const double ihsl = sl ? frcp(hsl) : 0.0, ihsr = sr ? frcp(hsr) : 0.0;
+  const double usl = sl ? mlp * ihsl : 0.0, usr = sr ? mrp * ihsr : 0.0;
+  // F1 = (m'l - w el + m'r - w er)/2 - alpha/2 (er - el)
+  double lel = 0.5 * (alpha - w) * lF1, ler = -0.5 * (alpha + w) * lF1;
+  double lmlp = 0.5 * lF1, lmrp = 0.5 * lF1;
+  // alpha part of the momentum: -alpha/2 (m'r - m'l)
+  lmlp += 0.5 * alpha * lF2;
+  lmrp -= 0.5 * alpha * lF2;
+  // F2 = (m'l usl + g/2 hsl^2 - w m'l + m'r usr + g/2 hsr^2 - w m'r)/2, usl = m'l/hsl
+  const double A = 0.5 * lF2;
+  lmlp += A * ((sl ? 2.0 * usl : 0.0) - w);
+  lmrp += A * ((sr ? 2.0 * usr : 0.0) - w);
+  double lhsl = A * (g * hsl - (sl ? usl * usl : 0.0));
+  double lhsr = A * (g * hsr - (sr ? usr * usr : 0.0));
+  // cl = g/2 (hl^2 - hsl^2), cr = g/2 (hr^2 - hsr^2)
+  double lhl = g * hl * lcl, lhr = g * hr * lcr;
+  lhsl -= g * hsl * lcl;
+  lhsr -= g * hsr * lcr;
+  // hs = max(e - bmax, 0)
+  double lbmax = 0.0;
+  if (xl >= 0.0) { lel += lhsl; lbmax -= lhsl; }
+  if (xr >= 0.0) { ler += lhsr; lbmax -= lhsr; }
+  // G = -w (bl + br)/2 - alpha/2 (br - bl)
+  double lbl = (-0.5 * w + 0.5 * alpha) * lG, lbr = (-0.5 * w - 0.5 * alpha) * lG;
+  if (lmax) lbl += lbmax; else lbr += lbmax;
+  // e = h + b
+  lhl += lel; lbl += lel;
+  lhr += ler; lbr += ler;
+  Ll.h = lhl; Ll.m = wl ? lmlp : 0.0; Ll.b = lbl;
+  Lr.h = lhr; Lr.m = wr ? lmrp : 0.0; Lr.b = lbr;
+}
+
+// Reverse of hydro_source: cotangents of the eta and b values at the four
+// Gauss-Lobatto points from the cotangent lS of the source.
+__device__ __forceinline__ void hydro_source_vjp(double g, const double e[4], const double b[4],
+                                                 double lS, double le[4], double lb[4]) {
+  const double PHI = 1.6180339887498948482, PHI1 = 0.6180339887498948482;
+  const double R5 = 2.2360679774997896964;
+  const double D[4][4] = {{-6.0, 5.0 * PHI, -5.0 * PHI1, 1.0},
+                          {-PHI, 0.0, R5, -PHI1},
+                          {PHI1, -R5, 0.0, PHI},
+                          {-1.0, 5.0 * PHI1, -5.0 * PHI, 6.0}};
+  const double om[4] = {1.0, 5.0, 5.0, 1.0};
+  const double lq = (-g / 12.0) * lS;
+  double d[4], gq[4];
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+    d[mu] = D[mu][0] * b[0] + D[mu][1] * b[1] + D[mu][2] * b[2] + D[mu][3] * b[3];
+    gq[mu] = om[mu] * (e[mu] - b[mu]);
+  }
+#pragma unroll
+  for (int nu = 0; nu < 4; ++nu) {
+    double t = -om[nu] * d[nu];
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) t += gq[mu] * D[mu][nu];
+    le[nu] = lq * om[nu] * d[nu];
+    lb[nu] = lq * t;
+  }
+}
+
 // Adjoint of alpha = |u - w| + sqrt(g max(h,0)) at the trace that attains it.
 __device__ __forceinline__ void alpha_trace_vjp(double h, double m, double w, double g, double dry,
                                                 double lalpha, TraceAdj& L) {
@@ -189,6 +269,9 @@ struct ReconAdjOut {
   double letabar;
 };
 
+// HR: the interior values of eta and b (points 1, 2) take the cotangents
+// le[mu], lb[mu] of the hydrostatic source instead of the special-source term.
+template <bool HR = false>
 __device__ __forceinline__ void recon_cell_vjp(const double* __restrict__ v5,
                                                const double* __restrict__ h5,
                                                const double* __restrict__ m5,
@@ -196,7 +279,8 @@ __device__ __forceinline__ void recon_cell_vjp(const double* __restrict__ v5,
                                                const double* __restrict__ J5, double Dx,
                                                double eps, double etabar, const TraceAdj& LL,
                                                const TraceAdj& LR, double lrint,
-                                               ReconAdjOut& out) {
+                                               ReconAdjOut& out, const double* hle = nullptr,
+                                               const double* hlb = nullptr) {
   // ---------------- forward (as recon_cell) ----------------
   const double J0 = J5[2];
   const double iJ0 = frcp(J0);
@@ -324,12 +408,17 @@ __device__ __forceinline__ void recon_cell_vjp(const double* __restrict__ v5,
     double lhv = 0.0, lmv = 0.0, lbv = 0.0, lbx = 0.0;
     if (mu == 0) { lhv += LL.h; lmv += LL.m; lbv += LL.b; }
     if (mu == 3) { lhv += LR.h; lmv += LR.m; lbv += LR.b; }
-    // rint = sum_mu (w_mu J0) ((h + b) - etabar) b_x
-    const double cw = wgl[mu] * J0;
-    lhv += lrint * cw * bxv;
-    lbv += lrint * cw * bxv;
-    lbx += lrint * cw * ((hv + bv) - etabar);
-    letab -= lrint * cw * bxv;
+    if (HR) {
+      // eta = h + b and b at the interior points feed the hydrostatic source
+      if (mu == 1 || mu == 2) { lhv += hle[mu]; lbv += hle[mu] + hlb[mu]; }
+    } else {
+      // rint = sum_mu (w_mu J0) ((h + b) - etabar) b_x
+      const double cw = wgl[mu] * J0;
+      lhv += lrint * cw * bxv;
+      lbv += lrint * cw * bxv;
+      lbx += lrint * cw * ((hv + bv) - etabar);
+      letab -= lrint * cw * bxv;
+    }
     // v = v0 + (sB y + sC p2); b_x = (sB_b + 2 y sC_b) / J0
     lh0 += lhv; lm0 += lmv; lb0 += lbv;
     const double lsBh = y * lhv, lsCh = p2 * lhv;
@@ -551,7 +640,7 @@ __device__ __forceinline__ void adj_slot_put(const AdjSlotRaw& r, int q, double 
   sm.wn[q] = r.wk;
 }
 
-template <int B>
+template <int B, bool HR>
 __global__ __launch_bounds__(B) void k_adj_fused(AdjBufs ab, Consts cs,
                                                  const AdjTile* __restrict__ tiles, int s,
                                                  double* __restrict__ gfold) {
@@ -593,8 +682,8 @@ __global__ __launch_bounds__(B) void k_adj_fused(AdjBufs ab, Consts cs,
       v5[k] = (cs.flags & F_BETA_FROM_H) ? h5[k] : sm.e[t + k];
     }
     if (cs.flags & F_BETA_LOCAL) Dx = sm.J[t + 2];
-    recon_cell(v5, h5, &sm.m[t], &sm.b[t], &sm.J[t], frcp(sm.J[t + 2]), Dx, cs.weno_eps,
-               sm.e[t + 2], o);
+    recon_cell<HR>(v5, h5, &sm.m[t], &sm.b[t], &sm.J[t], frcp(sm.J[t + 2]), Dx, cs.weno_eps,
+                   sm.e[t + 2], o);
     ou = o;
     limit_cell(h5[2], sm.m[t + 2], cs.pp_eps, o);
     sm.u.tr[0][t] = o.hL; sm.u.tr[1][t] = o.mL; sm.u.tr[2][t] = o.bL;
@@ -608,8 +697,11 @@ __global__ __launch_bounds__(B) void k_adj_fused(AdjBufs ab, Consts cs,
     const double hl = sm.u.tr[3][t - 1], ml = sm.u.tr[4][t - 1], bl = sm.u.tr[5][t - 1];
     const double hr = sm.u.tr[0][t], mr = sm.u.tr[1][t], br = sm.u.tr[2][t];
     TraceAdj Ll, Lr;
-    face_vjp(hl, ml, bl, hr, mr, br, sm.wn[t + 2], alpha, cs.g, cs.dry_eps, rl, rr, sm.e[t + 1],
-             sm.e[t + 2], Ll, Lr);
+    if (HR)
+      face_vjp_hydro(hl, ml, bl, hr, mr, br, sm.wn[t + 2], alpha, cs.g, cs.dry_eps, rl, rr, Ll, Lr);
+    else
+      face_vjp(hl, ml, bl, hr, mr, br, sm.wn[t + 2], alpha, cs.g, cs.dry_eps, rl, rr, sm.e[t + 1],
+               sm.e[t + 2], Ll, Lr);
     sm.lf[0][t] = Ll.h; sm.lf[1][t] = Ll.m; sm.lf[2][t] = Ll.b;
     sm.lf[3][t] = Lr.h; sm.lf[4][t] = Lr.m; sm.lf[5][t] = Lr.b;
     sm.B1[t] = 0.5 * (bl + br);
@@ -628,16 +720,26 @@ __global__ __launch_bounds__(B) void k_adj_fused(AdjBufs ab, Consts cs,
     if (j >= 0) { LL.h = sm.lf[3][t]; LL.m = sm.lf[4][t]; LL.b = sm.lf[5][t]; }
     if (j < n) { LR.h = sm.lf[0][t + 1]; LR.m = sm.lf[1][t + 1]; LR.b = sm.lf[2][t + 1]; }
     double lrint = 0.0, letabar = 0.0;
+    double hle[4] = {0.0, 0.0, 0.0, 0.0}, hlb[4] = {0.0, 0.0, 0.0, 0.0};
     if (j >= 0 && j < n) {
       const double rm = sm.rho[1][t + 2];
-      lrint = -cs.g * rm;
-      letabar += -cs.g * rm * (sm.B1[t + 1] - sm.B1[t]);
+      if (HR) {
+        // hydrostatic source of the cell: limited end traces, interior values
+        const double ev[4] = {o.hL + o.bL, o.e1, o.e2, o.hR + o.bR};
+        const double bv[4] = {o.bL, o.b1, o.b2, o.bR};
+        hydro_source_vjp(cs.g, ev, bv, rm, hle, hlb);
+        LL.h += hle[0]; LL.b += hle[0] + hlb[0];
+        LR.h += hle[3]; LR.b += hle[3] + hlb[3];
+      } else {
+        lrint = -cs.g * rm;
+        letabar += -cs.g * rm * (sm.B1[t + 1] - sm.B1[t]);
+      }
     }
     double lhbar = 0.0, lmbar = 0.0;
     limit_vjp(h5[2], sm.m[t + 2], cs.pp_eps, ou, LL, LR, lhbar, lmbar);
     ReconAdjOut ra;
-    recon_cell_vjp(v5, h5, &sm.m[t], &sm.b[t], &sm.J[t], Dx, cs.weno_eps, sm.e[t + 2], LL, LR,
-                   lrint, ra);
+    recon_cell_vjp<HR>(v5, h5, &sm.m[t], &sm.b[t], &sm.J[t], Dx, cs.weno_eps, sm.e[t + 2], LL, LR,
+                       lrint, ra, hle, hlb);
     const bool vh = (cs.flags & F_BETA_FROM_H) != 0;
 #pragma unroll
     for (int k = 0; k < 5; ++k) {

@@ -3,8 +3,8 @@ flag HYDROSTATIC) against the oracle, through the C ABI.
 
 Bar as for the default scheme: 1e-11 relative L-inf for the state and nodes,
 identical step counts and detector class counts, bitwise equality between
-stage tile shapes and engines; still water at round-off.  The adjoint does not
-cover this form and must refuse it, not run.
+stage tile shapes and engines; still water at round-off.  The adjoint of this
+form is checked with the other adjoint tests (test_gpu_adjoint.py).
 """
 import math
 
@@ -163,18 +163,3 @@ def test_hydrostatic_batch_tile_shapes_and_oracle(dev):
     ctx.run(p_ss, off, T["h"], T["hu"], T["b"], T["x"], T["xi"], max_steps=[nsteps] * ninst)
     d = float(np.abs(T["hu"].cpu().numpy() - ref["hu"]).max())
     assert 1e-12 < d < 1e-4, d
-
-
-def test_hydrostatic_adjoint_is_refused(dev):
-    """The adjoint covers the special-source scheme only: with the flag it
-    returns ALEW_E_UNSUPPORTED and writes nothing."""
-    wl = W.accuracy_1d(64)
-    ctx = alew.Context(64, 1)
-    T = {k: _t(wl[k], dev) for k in ("h", "hu", "b", "x", "xi")}
-    dts = torch.full((2,), 1e-4, dtype=torch.float64, device=dev)
-    gx = _t([0.3, 0.6], dev)
-    gh = torch.full((2,), -1.0, dtype=torch.float64, device=dev)
-    with pytest.raises(alew.AlewError) as ei:
-        ctx.adjoint(_gp(wl), [0, 64], T["h"], T["hu"], T["b"], T["x"], T["xi"], 2, dts, 2, gx, gh)
-    assert ei.value.status == alew.E_UNSUPPORTED
-    assert (gh == -1.0).all()

@@ -317,10 +317,11 @@ def small_run_leg(dev):
                 unit="cell-updates/s")
 
 
-def adjoint_leg(dev, ninst, ncell, nsteps, ngauge, ckpt):
+def adjoint_leg(dev, ninst, ncell, nsteps, ngauge, ckpt, flags=0):
     """Adjoint/forward time ratio on the bathymetry-inversion batch: ninst
     instances of ncell cells, nsteps frozen CFL steps, gauge misfit at ngauge
-    gauges per instance, checkpoints every ckpt steps."""
+    gauges per instance, checkpoints every ckpt steps (flags: the well-balanced
+    form)."""
     import torch
     from paper_2208_06588_amd import alew, workloads as W
     t0 = time.perf_counter()
@@ -329,7 +330,7 @@ def adjoint_leg(dev, ninst, ncell, nsteps, ngauge, ckpt):
     off = [int(v) for v in bt["cell_off"]]
     S = off[-1]
     p = alew.params(bc="transmissive", mesh="sine", mesh_A=0.05, mesh_k=1.0, mesh_omega=np.pi,
-                    cfl=0.6)
+                    cfl=0.6, flags=flags)
     T = {k: torch.tensor(bt[k], dtype=torch.float64, device=dev)
          for k in ("h", "hu", "b", "x", "xi", "gauge_x", "b_true")}
     ctx = alew.Context(S, ninst)
@@ -410,7 +411,7 @@ def main():
                     help="well-balanced form of the timed forward leg (Sec. 4.2 special source "
                          "term, or Sec. 4.1 hydrostatic reconstruction)")
     ap.add_argument("--no-hydrostatic", action="store_true",
-                    help="skip the hydrostatic-reconstruction leg")
+                    help="skip the hydrostatic-reconstruction legs (forward and adjoint)")
     ap.add_argument("--hr-steps", type=int, default=20)
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="first copy a buffer of this many MiB (calibrates profiler byte counters)")
@@ -575,6 +576,12 @@ def main():
         torch.cuda.empty_cache()
         out["adjoint"] = adjoint_leg(dev, args.adj_ninst, args.adj_cells, args.adj_steps, 64, 16)
         out["adjoint_forward_ratio"] = out["adjoint"]["ratio"]
+        if not args.no_hydrostatic:
+            torch.cuda.empty_cache()
+            out["adjoint_hydrostatic"] = adjoint_leg(dev, args.adj_ninst, args.adj_cells,
+                                                     args.adj_steps, 64, 16,
+                                                     flags=alew.F_HYDROSTATIC)
+            log(f"adjoint (hydrostatic reconstruction): {out['adjoint_hydrostatic']}")
         log(f"adjoint: {out['adjoint']}")
 
     if args.oracle_suite:

@@ -1,5 +1,7 @@
-// MI355X (gfx950) library for the 1D well-balanced ALE-WENO hybrid scheme:
-// kernels and the C ABI declared in include/alew.h.
+// MI355X (gfx950) library for the 1D well-balanced ALE-WENO hybrid scheme
+// (special source-term treatment, or the hydrostatic reconstruction under
+// F_HYDROSTATIC: a template parameter of the stage, persistent and reverse
+// kernels): kernels and the C ABI declared in include/alew.h.
 //
 // Two engines run the same tile bodies (alew_kernels.h):
 //  * stage launches: each kernel covers every tile of every active instance;

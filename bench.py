@@ -20,6 +20,7 @@ import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -40,11 +41,21 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def _code_only(text):
+    """C++ source without comments and with whitespace runs collapsed (string
+    literals here hold no comment markers), so that edits of comments alone
+    keep the counters of profiles/counters.json valid."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def source_hash():
+    """Hash of the code (comments stripped) of the stage kernels' sources."""
     h = hashlib.sha1()
     for f in ("alew.hip", "alew_device.h", "alew_kernels.h"):
-        with open(os.path.join(ROOT, "paper_2208_06588_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2208_06588_amd", "csrc", f)) as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -67,7 +67,8 @@
  *      boundary cell (values and width); reflective mirrors with hu negated.
  *  R15 The state carried through a run is (eta, hu, b); h = eta - b is
  *      formed on entry and on exit of each library call.
- *  R16 Hydrostatic reconstruction (Sec. 4.1, eq. (4.2)-(4.3) in 1D; flag
+ *  R16 A mean depth counts as negative only below -eps (the end of R11).
+ *  R17 Hydrostatic reconstruction (Sec. 4.1, eq. (4.2)-(4.3) in 1D; flag
  *      FLAG_HYDROSTATIC).  At each face of cell j, q- is the cell's own
  *      limited trace and q+ the neighbour's, n the outward normal (+1 on the
  *      right face, -1 on the left).  h*+- = max(0, eta+- - max(b+, b-)),
@@ -77,7 +78,7 @@
  *      g/2 (h*-)^2) n), H the Lax-Friedrichs flux of eq. (3.13) with the
  *      alpha of R6 (taken on the traces q+-, not q*+-).  The bottom keeps the
  *      ALE flux of R13.
- *  R17 Hydrostatic source (the sentence after eq. (4.3)): "fourth-order
+ *  R18 Hydrostatic source (the sentence after eq. (4.3)): "fourth-order
  *      polynomials" are read as the cubics (four coefficients) eta_h, b_h
  *      that interpolate the values at the 4 Gauss-Lobatto points of the cell
  *      (the limited traces at the two ends, the unlimited hybrid values
@@ -466,7 +467,7 @@ static TraceFlux<T> trace_state(T h, T m, T b, double dry_eps) {
 }
 
 /* ------------------------------------------------------------------------ */
-/* Hydrostatic reconstruction (Sec. 4.1, eq. (4.2)-(4.3)), readings R16-R17   */
+/* Hydrostatic reconstruction (Sec. 4.1, eq. (4.2)-(4.3)), readings R17-R18   */
 /* ------------------------------------------------------------------------ */
 /* H^mod of eq. (4.2) at one face of a cell: q- its own trace, q+ the
  * neighbour's, nrm the outward normal, w the node speed.  Components eta, hu. */
@@ -506,7 +507,7 @@ static const double kGL5_w[5] = {0.5 * 0.23692688505618908751, 0.5 * 0.478628670
                                  0.5 * 0.56888888888888888889, 0.5 * 0.47862867049936646804,
                                  0.5 * 0.23692688505618908751};
 
-/* Inverse of the interpolation system of R17 in the cell coordinate
+/* Inverse of the interpolation system of R18 in the cell coordinate
  * s in [0,1]: p(s) = sum_k c_k s^k, k = 0..3, with p at the 4 Gauss-Lobatto
  * points kS. */
 struct InterpInverse {
@@ -523,7 +524,7 @@ static const double* hydro_interp_inverse() {
   return inv.a;
 }
 
-/* R17: integral over cell j of -g (eta_h - b_h) d b_h / dx.  ev, bv: values
+/* R18: integral over cell j of -g (eta_h - b_h) d b_h / dx.  ev, bv: values
  * at the 4 Gauss-Lobatto points.  With x = x_{j-1/2} + s J, dx = J ds and
  * d/dx = (1/J) d/ds, so J drops out. */
 template <class T>
@@ -632,7 +633,7 @@ static void residual(const Params& P, int n, const T* eta, const T* m, const T* 
     B2[i] = 0.5 * (l.b * l.b + r.b * r.b);
   }
   if (P.flags & FLAG_HYDROSTATIC) {
-    /* Residuals with the hydrostatic reconstruction (R16-R17): each cell sums
+    /* Residuals with the hydrostatic reconstruction (R17-R18): each cell sums
      * H^mod over its two faces with outward normals; the bottom keeps Gb. */
     for (int j = 0; j < n; ++j) {
       T He_r, Hm_r, He_l, Hm_l;

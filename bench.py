@@ -195,6 +195,16 @@ def bowl_leg(dev, n, steps, warmup):
                 h_min=st[0].h_min)
 
 
+def guarded(name, fn):
+    """Run one of the legs beside the main measurement; a failure there is
+    reported in its place instead of costing the whole line."""
+    try:
+        return fn()
+    except (AssertionError, RuntimeError, ValueError) as e:
+        log(f"{name} failed: {e!r}")
+        return dict(error=f"{type(e).__name__}: {e}")
+
+
 def hydrostatic_leg(ctx, p, off, T, tnow, L, S, steps):
     """The hydrostatic-reconstruction scheme (Sec. 4.1) on the forward batch,
     in the forward leg's launch: 2 warm-up steps, then `steps` timed steps in
@@ -524,8 +534,9 @@ def main():
         # the hydrostatic-reconstruction scheme on the same batch, same launch
         p_hr = alew.params(bc="transmissive", mesh="sine", mesh_A=0.05, mesh_k=1.0,
                            mesh_omega=np.pi, cfl=0.6, weno_eps=1e-9, flags=alew.F_HYDROSTATIC)
-        out["hydrostatic"] = hydrostatic_leg(ctx, p_hr, off, T, [s.t for s in st], L, S,
-                                             args.hr_steps)
+        tn = [s.t for s in st]
+        out["hydrostatic"] = guarded("hydrostatic", lambda: hydrostatic_leg(
+            ctx, p_hr, off, T, tn, L, S, args.hr_steps))
         log(f"hydrostatic: {out['hydrostatic']}")
 
     if args.full_run:
@@ -579,31 +590,34 @@ def main():
         del Tb, Tp, ctx1
 
     if not args.no_bowl:
-        out["bowl"] = bowl_leg(dev, 1 << 24, args.bowl_steps, 2)
+        out["bowl"] = guarded("bowl", lambda: bowl_leg(dev, 1 << 24, args.bowl_steps, 2))
         log(f"bowl: {out['bowl']}")
 
     if not args.no_adjoint:
         del ctx, T
         torch.cuda.empty_cache()
-        out["adjoint"] = adjoint_leg(dev, args.adj_ninst, args.adj_cells, args.adj_steps, 64, 16)
-        out["adjoint_forward_ratio"] = out["adjoint"]["ratio"]
+        out["adjoint"] = guarded("adjoint", lambda: adjoint_leg(
+            dev, args.adj_ninst, args.adj_cells, args.adj_steps, 64, 16))
+        out["adjoint_forward_ratio"] = out["adjoint"].get("ratio")
         if not args.no_hydrostatic:
             torch.cuda.empty_cache()
-            out["adjoint_hydrostatic"] = adjoint_leg(dev, args.adj_ninst, args.adj_cells,
-                                                     args.adj_steps, 64, 16,
-                                                     flags=alew.F_HYDROSTATIC)
+            out["adjoint_hydrostatic"] = guarded("adjoint (hydrostatic)", lambda: adjoint_leg(
+                dev, args.adj_ninst, args.adj_cells, args.adj_steps, 64, 16,
+                flags=alew.F_HYDROSTATIC))
             log(f"adjoint (hydrostatic reconstruction): {out['adjoint_hydrostatic']}")
         log(f"adjoint: {out['adjoint']}")
 
     if args.oracle_suite:
         log("smooth 200-cell run on the GPU ...")
-        out["smooth_200_gpu"] = small_run_leg(dev)
+        out["smooth_200_gpu"] = guarded("smooth 200-cell run", lambda: small_run_leg(dev))
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(bt, min(args.cpu_inst, ninst), args.cpu_steps)
+        out["cpu_baseline"] = guarded("cpu baseline", lambda: cpu_baseline(
+            bt, min(args.cpu_inst, ninst), args.cpu_steps))
         if args.oracle_suite:
             log("oracle on the other configurations ...")
-            out["cpu_baseline"]["other_configs"] = oracle_other_configs()
+            out["cpu_baseline"]["other_configs"] = guarded("oracle, other configurations",
+                                                           oracle_other_configs)
             log(f"oracle, other configurations: {out['cpu_baseline']['other_configs']}")
     print(json.dumps(out), flush=True)
 

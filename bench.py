@@ -254,6 +254,7 @@ def cpu_baseline(bt, ninst_sample, steps):
     wall = time.perf_counter() - t0
     ncell = int(off[ninst_sample])
     return dict(value=work / wall, unit="cell-updates/s", cores=cores, kind="oracle",
+                per_core=work / wall / cores,
                 sample=f"first {ninst_sample} instances of the same draw ({ncell} cells), "
                        f"{steps} CFL steps each, one instance per thread; {wall:.1f} s wall")
 

@@ -129,8 +129,10 @@ def test_positivity_dry_bed(dev):
     _assert_parity(g, r)
 
 
-def test_given_mesh_reflective_step(dev):
-    """alew_step with caller-given node speeds and reflective walls."""
+@pytest.mark.parametrize("hydro", [False, True])
+def test_given_mesh_reflective_step(dev, hydro):
+    """alew_step with caller-given node speeds and reflective walls, both
+    well-balanced forms."""
     n = 97
     xi = W.uniform_nodes(n, 0.0, 1.0)
     xc = 0.5 * (xi[1:] + xi[:-1])
@@ -138,14 +140,15 @@ def test_given_mesh_reflective_step(dev):
     b = 0.2 * np.sin(3 * xc) ** 2
     hu = 0.1 * np.sin(2 * np.pi * xc)
     w = 0.2 * np.sin(np.pi * xi)  # zero at both walls
-    p = alew.params(bc="reflective", mesh="given")
+    p = alew.params(bc="reflective", mesh="given", flags=alew.F_HYDROSTATIC if hydro else 0)
     ctx = alew.Context(n, 1)
     T = {k: _t(v, dev) for k, v in dict(h=h, hu=hu, b=b, x=xi, w=w).items()}
     tt = 0.0
     for _ in range(12):
         st = ctx.step(p, T["h"], T["hu"], T["b"], T["x"], None, T["w"], t=tt)
         tt = st.t
-    r = O.run(O.params(bc=O.BC_REFLECTIVE, mesh=O.MESH_GIVEN), h, hu, b, xi, w=w, max_steps=12)
+    r = O.run(O.params(bc=O.BC_REFLECTIVE, mesh=O.MESH_GIVEN,
+                       flags=O.FLAG_HYDROSTATIC if hydro else 0), h, hu, b, xi, w=w, max_steps=12)
     g = {k: v.cpu().numpy() for k, v in T.items()}
     assert abs(tt - r["t"]) <= 1e-15
     _assert_parity(g, r)

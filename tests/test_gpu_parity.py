@@ -78,13 +78,14 @@ def test_periodic_smooth_full_run(dev):
     assert abs(st.mass_eta - st.mass_eta0) <= 1e-13 * st.mass_eta0
 
 
-def test_classes_per_cell_per_stage(dev):
+@pytest.mark.parametrize("hydro", [False, True])
+def test_classes_per_cell_per_stage(dev, hydro):
     """alew_step, one call per step with the CFL rule; classes of every cell at
-    every stage against the oracle's."""
+    every stage against the oracle's (both well-balanced forms)."""
     wl = W.still_water_1d(200, "step")
     wl["h"] = wl["h"] + 0.05 * np.exp(-((np.linspace(0, 10, 200) - 2.0) ** 2))  # moving pulse
     nsteps = 30
-    p = _gp(wl)
+    p = _gp(wl, flags=alew.F_HYDROSTATIC if hydro else 0)
     ctx = alew.Context(200, 1)
     t = {k: _t(wl[k], dev) for k in ("h", "hu", "b", "x", "xi")}
     cls = torch.zeros(3 * 200, dtype=torch.uint8, device=dev)
@@ -94,8 +95,8 @@ def test_classes_per_cell_per_stage(dev):
         st = ctx.step(p, t["h"], t["hu"], t["b"], t["x"], t["xi"], t=tt, t_end=wl["t_end"], cls=cls)
         tt = st.t
         got.append(cls.cpu().numpy().reshape(3, 200).copy())
-    r = O.run(_op(wl), wl["h"], wl["hu"], wl["b"], wl["x"], wl["xi"], t_end=wl["t_end"],
-              max_steps=nsteps, record_cls=True)
+    r = O.run(_op(wl, flags=O.FLAG_HYDROSTATIC if hydro else 0), wl["h"], wl["hu"], wl["b"],
+              wl["x"], wl["xi"], t_end=wl["t_end"], max_steps=nsteps, record_cls=True)
     got = np.stack(got)
     flips = int((got != r["cls"]).sum())
     assert flips == 0, f"{flips} class flips"
@@ -328,14 +329,15 @@ def test_instance_split_over_record_chunks(dev):
         assert abs(st[i].mass_eta0 - r["stats"].mass_eta0) <= (e - a) * 2.3e-16 * abs(r["stats"].mass_eta0)
 
 
-def test_batched_to_t_end_matches_per_instance(dev):
+@pytest.mark.parametrize("hydro", [False, True])
+def test_batched_to_t_end_matches_per_instance(dev, hydro):
     """Instances of different sizes run to the same end time with their own
-    step sizes in one call; each equals a one-instance call."""
+    step sizes in one call; each equals a one-instance call (both forms)."""
     bt = _small_batch(seed=9, ninst=4)
     off = bt["cell_off"]
     n = int(off[-1])
     ninst = len(off) - 1
-    p = _gp(bt)
+    p = _gp(bt, flags=alew.F_HYDROSTATIC if hydro else 0)
     T_end = 0.02
     ctx = alew.Context(n, ninst)
     ctx.set_launch(engine=alew.ENGINE_PERSISTENT, block=256)

@@ -70,6 +70,8 @@ def lib():
         L.orc_geometry.argtypes = [dp, dp, dp, dp, dp]
         L.orc_reconstruct.argtypes = [dp, dp, dp, dp, dp, C.c_double, C.c_double, dp, dp, dp]
         L.orc_limit.argtypes = [C.c_double, C.c_double, dp, C.c_double, dp]
+        L.orc_hydro_source.argtypes = [C.c_double, dp, dp]
+        L.orc_hydro_source.restype = C.c_double
         L.orc_residual.argtypes = [C.POINTER(Params), C.c_int64, dp, dp, dp, dp, dp, dp, dp, u8p]
         L.orc_mesh_velocity.argtypes = [C.POINTER(Params), C.c_int64, dp, dp, dp, dp, C.c_double,
                                         C.c_double, dp]
@@ -129,6 +131,12 @@ def limit(hbar, mbar, traces6, pp_eps=1e-11):
     out = np.zeros(6)
     r = lib().orc_limit(float(hbar), float(mbar), _p(_f64(traces6)), float(pp_eps), _p(out))
     return out, r
+
+
+def hydro_source(g, eta4, b4):
+    """Hydrostatic source of one cell (Sec. 4.1, after eq. (4.3)) from eta and b
+    at the 4 Gauss-Lobatto points (cell ends first and last)."""
+    return float(lib().orc_hydro_source(float(g), _p(_f64(eta4)), _p(_f64(b4))))
 
 
 def residual(P: Params, eta, hu, b, J, w):

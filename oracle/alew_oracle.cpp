@@ -891,6 +891,14 @@ int orc_limit(double hbar, double mbar, const double* in, double pp_eps, double*
   return r;
 }
 
+/* Hydrostatic source of one cell (R18) from eta and b at the 4 Gauss-Lobatto
+ * points of the cell (ends first and last). */
+double orc_hydro_source(double g, const double* ev, const double* bv) {
+  double e[4], b[4];
+  for (int k = 0; k < 4; ++k) { e[k] = ev[k]; b[k] = bv[k]; }
+  return hydro_source(g, e, b);
+}
+
 /* Residual RHS_j (3n: eta, hu, b) of the state (eta, hu, b) on widths J and
  * node speeds w.  Returns the LF speed in *alpha. */
 int orc_residual(const Params* P, int64_t n, const double* eta, const double* m, const double* b,

@@ -426,6 +426,22 @@ def _smooth_random_state(n, seed, flat_b=False):
     return eta, hu, b, J, w
 
 
+@pytest.mark.parametrize("seed", range(4))
+def test_hydrostatic_source_exact_on_cubics(seed):
+    """The source of the hydrostatic form integrates -g (eta - b) b' over the
+    cell exactly when eta and b are cubics in the cell coordinate (the values
+    at the Gauss-Lobatto points determine them): against the integral of the
+    polynomial product, from its antiderivative.  The cell width drops out."""
+    rng = np.random.default_rng(40 + seed)
+    pe, pb = rng.normal(size=4), rng.normal(size=4)
+    P = np.polynomial.polynomial
+    ev, bv = P.polyval(GL_S, pe), P.polyval(GL_S, pb)
+    integrand = P.polymul(P.polysub(pe, pb), P.polyder(pb))
+    anti = P.polyint(integrand)
+    exact = -9.812 * (P.polyval(1.0, anti) - P.polyval(0.0, anti))
+    np.testing.assert_allclose(O.hydro_source(9.812, ev, bv), exact, rtol=1e-12, atol=1e-12)
+
+
 def test_hydrostatic_flat_bottom_is_the_plain_scheme():
     """Over a flat bottom h* = h, theta = 0, the pressure corrections and the
     source vanish: the hydrostatic-reconstruction residual equals the special-

@@ -53,7 +53,10 @@ typedef enum {
   ALEW_E_UNSUPPORTED = 7, /* combination not supported by this entry point; also an
                            * instance of a batch out of step with the others (the
                            * stage kernels take one node-buffer parity per launch) */
-  ALEW_E_NEGWEIGHT = 8    /* a negative linear weight d_r (Sec. 2.2, after Step 4)  */
+  ALEW_E_NEGWEIGHT = 8,   /* a negative linear weight d_r (Sec. 2.2, after Step 4)  */
+  ALEW_E_CAPACITY = 9     /* the step-size buffer of alew_run (dts or dt_log) holds
+                           * fewer than the steps an instance needed: the instance
+                           * stopped there, before its t_end / max_steps            */
 } alew_status;
 
 enum { ALEW_BC_PERIODIC = 0, ALEW_BC_TRANSMISSIVE = 1, ALEW_BC_REFLECTIVE = 2 };
@@ -72,7 +75,7 @@ enum {
   ALEW_F_BETA_LOCAL = 1,  /* Dx in the indicators = the cell's own width instead of
                              the max width of the stage mesh (Sec. 2.2, Step 1)     */
   ALEW_F_BETA_FROM_H = 2, /* indicators on (h, hu) instead of (eta, hu)             */
-  ALEW_F_HYDROSTATIC = 4  /* well-balanced scheme with the hydrostatic reconstruction
+  ALEW_F_HYDROSTATIC = 4, /* well-balanced scheme with the hydrostatic reconstruction
                              of Sec. 4.1, eq. (4.2)-(4.3), instead of the special
                              source-term treatment of eq. (4.4)-(4.6): at each face
                              h* = max(0, eta - max(b-, b+)) on both sides, the
@@ -83,6 +86,22 @@ enum {
                              Gauss-Lobatto points.  The eta and b equations are those
                              of the default scheme.  Every entry point and engine
                              (alew_step, alew_run, alew_adjoint).                  */
+  /* Alternative readings of points the paper leaves open (the defaults are the
+   * readings the oracle and the library take without flags):                     */
+  ALEW_F_ALPHA_CELLAVG = 8,  /* Lax-Friedrichs speed of eq. (3.13) taken over the cell
+                                averages of the stage input instead of the limited
+                                face traces: max over the cells j of an instance of
+                                max(|u_j - w_{j-1/2}|, |u_j - w_{j+1/2}|) + sqrt(g h_j)
+                                (u_j = hu_j / h_j if h_j > dry_eps, else 0); not
+                                with alew_adjoint                                     */
+  ALEW_F_NO_HU_LIMIT = 16,   /* the positivity limiter of eq. (3.20)-(3.21) scales the
+                                h traces (and the b traces through Remark 4.1) only;
+                                by default the hu traces are scaled by the same Phi
+                                about the cell mean of hu                             */
+  ALEW_F_W_TANGENT = 32      /* SINE / PAPER meshes: the node speed of a step is the
+                                map's time derivative at the start of the step,
+                                A S(xi) omega cos(omega t_n), instead of the chord of
+                                eq. (2.1) (nodes then leave the map by O(dt^2) a step) */
 };
 
 typedef struct {
@@ -139,7 +158,11 @@ typedef struct {
 } alew_launch;
 
 /* Create a context able to run up to max_cells cells in up to max_inst instances.
- * Scratch memory (about 110 bytes per cell) is allocated here and nowhere else.
+ * The scratch memory of alew_step and alew_run (state and stage buffers, tile
+ * tables and result records: about 120 bytes per cell) is allocated here;
+ * alew_step and alew_run never allocate device memory.  alew_adjoint's larger
+ * workspace is allocated by alew_adjoint_reserve, or by the first alew_adjoint
+ * call that needs more than the context holds.
  * hip_stream: hipStream_t to enqueue on (NULL = default stream). */
 alew_status alew_create(alew_ctx** ctx, int64_t max_cells, int64_t max_inst, void* hip_stream);
 void alew_destroy(alew_ctx* ctx);
@@ -167,12 +190,24 @@ alew_status alew_step(alew_ctx* ctx, const alew_params* p, int64_t ncell, double
  * t0[i] (0) and advances until t_end[i] (if > t0[i]) and/or max_steps[i] steps
  * (if > 0).  dts (device, optional) [ninst * dts_stride] fixes the step sizes
  * (the CFL rule is used when NULL).  dt_log (device, optional)
- * [ninst * dts_stride] receives the step sizes used.  stats (host, optional)
- * [ninst].  mesh must be SINE, PAPER or FLUID. */
+ * [ninst * dts_stride] receives the step sizes used.  With either of them an
+ * instance that would need more than dts_stride steps stops after dts_stride
+ * steps with ALEW_E_CAPACITY.
+ * cls_count, cls_sig (device, optional, both or neither): a record of the
+ * detector class (Sec. 2.2, Step 2) of every cell at every stage of the run,
+ * accumulated onto what the arrays hold (zero them for a fresh record):
+ * cls_count [3 * S] (S = cell_off[ninst]) counts the stages at which cell g
+ * was classified smooth (cls_count[g]), transition (cls_count[S + g]) or
+ * non-smooth (cls_count[2 S + g]); cls_sig [S] is a signature of the cell's
+ * class sequence: at every stage, in time order,
+ *     cls_sig[g] = cls_sig[g] * 1099511628211 + class + 1   (mod 2^64),
+ * class 0 smooth, 1 transition, 2 non-smooth.
+ * stats (host, optional) [ninst].  mesh must be SINE, PAPER or FLUID. */
 alew_status alew_run(alew_ctx* ctx, const alew_params* p, int64_t ninst, const int64_t* cell_off,
                      double* h, double* hu, double* b, double* x, const double* xi,
                      const double* t0, const double* t_end, const int64_t* max_steps,
-                     const double* dts, double* dt_log, int64_t dts_stride, alew_stats* stats);
+                     const double* dts, double* dt_log, int64_t dts_stride, uint32_t* cls_count,
+                     uint64_t* cls_sig, alew_stats* stats);
 
 /* Discrete adjoint of alew_run with frozen step sizes (prescribed mesh).
  * Forward: from (h0, hu0, b0, x0) at time t0 run nsteps steps of sizes dts
@@ -185,9 +220,10 @@ alew_status alew_run(alew_ctx* ctx, const alew_params* p, int64_t ninst, const i
  * dry cut-offs are frozen to the forward pass.  The forward is checkpointed every
  * ckpt_every steps and recomputed segment by segment (ckpt_every <= 0: 16).
  * gauge_h may be computed without the reverse pass by passing gauge_bar = NULL.
- * Checkpoints and per-step records of one segment live in a workspace that the
- * context allocates on the first call and keeps (about (3 + 26 ckpt_every) * 8
- * bytes per cell plus (4 + 24) * 8 per cell for the adjoint state). */
+ * Checkpoints and per-step records of one segment live in the context's
+ * adjoint workspace (alew_adjoint_reserve); a call that needs more than the
+ * workspace holds allocates a larger one first.  ALEW_F_ALPHA_CELLAVG is not
+ * supported here (ALEW_E_UNSUPPORTED). */
 alew_status alew_adjoint(alew_ctx* ctx, const alew_params* p, int64_t ninst,
                          const int64_t* cell_off, const double* h0, const double* hu0,
                          const double* b0, const double* x0, const double* xi, double t0,
@@ -195,6 +231,15 @@ alew_status alew_adjoint(alew_ctx* ctx, const alew_params* p, int64_t ninst,
                          const double* dts, int64_t ckpt_every, int64_t ngauge,
                          const double* gauge_x, double* gauge_h, const double* gauge_bar,
                          double* dh0, double* dhu0, double* db0);
+
+/* Allocate alew_adjoint's workspace ahead of time for runs of up to nsteps
+ * steps with checkpoints every ckpt_every steps (<= 0: 16) and up to ngauge
+ * gauges per instance, at the context's max_cells and max_inst.  A later
+ * alew_adjoint call within these sizes allocates nothing.  The workspace is
+ * about (3 + 26 ckpt_every) * 8 bytes per cell plus 40 bytes per cell for each
+ * checkpoint. */
+alew_status alew_adjoint_reserve(alew_ctx* ctx, int64_t nsteps, int64_t ckpt_every,
+                                 int64_t ngauge);
 
 /* Device time of the compute launches of the last alew_step/alew_run on this
  * context, measured with HIP events recorded on the context's stream around

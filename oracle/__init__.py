@@ -24,6 +24,7 @@ BC_PERIODIC, BC_TRANSMISSIVE, BC_REFLECTIVE = 0, 1, 2
 MESH_GIVEN, MESH_SINE, MESH_PAPER, MESH_FLUID = 0, 1, 2, 3
 ST_OK, ST_ARG, ST_MESH, ST_NEGDEPTH, ST_NONFINITE, ST_NEGWEIGHT = 0, 1, 2, 3, 4, 8
 FLAG_BETA_LOCAL, FLAG_BETA_FROM_H, FLAG_HYDROSTATIC = 1, 2, 4
+FLAG_ALPHA_CELLAVG, FLAG_NO_HU_LIMIT, FLAG_W_TANGENT = 8, 16, 32
 
 
 class Params(C.Structure):
@@ -69,7 +70,7 @@ def lib():
         u8p = C.POINTER(C.c_uint8)
         L.orc_geometry.argtypes = [dp, dp, dp, dp, dp]
         L.orc_reconstruct.argtypes = [dp, dp, dp, dp, dp, C.c_double, C.c_double, dp, dp, dp]
-        L.orc_limit.argtypes = [C.c_double, C.c_double, dp, C.c_double, dp]
+        L.orc_limit.argtypes = [C.c_double, C.c_double, dp, C.c_double, C.c_int, dp]
         L.orc_hydro_source.argtypes = [C.c_double, dp, dp]
         L.orc_hydro_source.restype = C.c_double
         L.orc_residual.argtypes = [C.POINTER(Params), C.c_int64, dp, dp, dp, dp, dp, dp, dp, u8p]
@@ -126,10 +127,12 @@ def reconstruct(widths5, h5, m5, b5, dx, eps=1e-6, v5=None):
     return out, cls, beta, float(gam[0])
 
 
-def limit(hbar, mbar, traces6, pp_eps=1e-11):
-    """1D positivity limiter (eq. (3.20)-(3.21), Remark 4.1) on (hL,huL,bL,hR,huR,bR)."""
+def limit(hbar, mbar, traces6, pp_eps=1e-11, hu_lim=True):
+    """1D positivity limiter (eq. (3.20)-(3.21), Remark 4.1) on (hL,huL,bL,hR,huR,bR);
+    hu_lim=False leaves the hu traces alone."""
     out = np.zeros(6)
-    r = lib().orc_limit(float(hbar), float(mbar), _p(_f64(traces6)), float(pp_eps), _p(out))
+    r = lib().orc_limit(float(hbar), float(mbar), _p(_f64(traces6)), float(pp_eps),
+                        1 if hu_lim else 0, _p(out))
     return out, r
 
 

@@ -87,6 +87,16 @@
  *      the average follows from the point values.  The integral of
  *      -g (eta_h - b_h) d b_h / dx over the cell is taken by the 5-point
  *      Gauss-Legendre rule, exact for the degree-5 integrand.
+ *  Alternative readings, each behind a flag (the defaults are R6, R10, R8):
+ *  R19 FLAG_ALPHA_CELLAVG: the Lax-Friedrichs speed of a stage is taken over the
+ *      cell averages of the stage input (eq. (3.13) names u, v without saying
+ *      where): max over the cells j of max(|u_j - w_{j-1/2}|, |u_j - w_{j+1/2}|)
+ *      + sqrt(g h_j), u_j = hu_j / h_j if h_j > dry_eps, else 0.
+ *  R20 FLAG_NO_HU_LIMIT: the limiter of eq. (3.20)-(3.21) acts on h (and on b
+ *      through Remark 4.1) only; the hu traces stay as reconstructed.
+ *  R21 FLAG_W_TANGENT: the node speed of a step on a prescribed map is the map's
+ *      time derivative at the start of the step, dX/dt(xi, t_n), instead of the
+ *      chord of eq. (2.1).
  */
 #include <cmath>
 #include <cstdint>
@@ -152,7 +162,10 @@ enum { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1, BC_REFLECTIVE = 2 };
 enum { MESH_GIVEN = 0, MESH_SINE = 1, MESH_PAPER = 2, MESH_FLUID = 3 };
 enum { ST_OK = 0, ST_ARG = 1, ST_MESH = 2, ST_NEGDEPTH = 3, ST_NONFINITE = 4, ST_NEGWEIGHT = 8 };
 
-enum { FLAG_BETA_LOCAL = 1, FLAG_BETA_FROM_H = 2, FLAG_HYDROSTATIC = 4 };
+enum {
+  FLAG_BETA_LOCAL = 1, FLAG_BETA_FROM_H = 2, FLAG_HYDROSTATIC = 4, FLAG_ALPHA_CELLAVG = 8,
+  FLAG_NO_HU_LIMIT = 16, FLAG_W_TANGENT = 32
+};
 
 struct Params {
   double g, cfl, weno_eps, pp_eps;
@@ -387,9 +400,11 @@ struct Traces {
   T hL, mL, bL, hR, mR, bR;
 };
 
-/* Returns 1 if the limiter modified the traces, 2 if hbar < 0. */
+/* Returns 1 if the limiter modified the traces, 2 if hbar < 0.  hu_lim = false
+ * (FLAG_NO_HU_LIMIT) leaves the hu traces as reconstructed. */
 template <class T>
-static int limit_cell(T hbar, T mbar, const Recon<T>& o, double pp_eps, Traces<T>& tr) {
+static int limit_cell(T hbar, T mbar, const Recon<T>& o, double pp_eps, Traces<T>& tr,
+                      bool hu_lim = true) {
   tr.hL = o.h[0]; tr.mL = o.m[0]; tr.bL = o.b[0];
   tr.hR = o.h[3]; tr.mR = o.m[3]; tr.bR = o.b[3];
   const double s1 = kGLW[0];
@@ -397,7 +412,7 @@ static int limit_cell(T hbar, T mbar, const Recon<T>& o, double pp_eps, Traces<T
     /* Phi = 0: the traces collapse onto the cell mean. */
     T etaL = tr.hL + tr.bL, etaR = tr.hR + tr.bR;
     tr.hL = hbar; tr.hR = hbar;
-    tr.mL = mbar; tr.mR = mbar;
+    if (hu_lim) { tr.mL = mbar; tr.mR = mbar; }
     tr.bL = etaL - tr.hL;
     tr.bR = etaR - tr.hR;
     return val(hbar) < 0.0 ? 2 : 1;
@@ -414,8 +429,10 @@ static int limit_cell(T hbar, T mbar, const Recon<T>& o, double pp_eps, Traces<T
   T etaL = tr.hL + tr.bL, etaR = tr.hR + tr.bR;
   tr.hL = Phi * (tr.hL - hbar) + hbar;
   tr.hR = Phi * (tr.hR - hbar) + hbar;
-  tr.mL = Phi * (tr.mL - mbar) + mbar;
-  tr.mR = Phi * (tr.mR - mbar) + mbar;
+  if (hu_lim) {
+    tr.mL = Phi * (tr.mL - mbar) + mbar;
+    tr.mR = Phi * (tr.mR - mbar) + mbar;
+  }
   tr.bL = etaL - tr.hL;
   tr.bR = etaR - tr.hR;
   return 1;
@@ -589,7 +606,8 @@ static void residual(const Params& P, int n, const T* eta, const T* m, const T* 
     cell_geometry(wid, geo);
     double dxr = (P.flags & FLAG_BETA_LOCAL) ? wid[2] : Dx;
     reconstruct(geo, dxr, P.weno_eps, vs, hs, ms5, bs, rec[j + 1]);
-    int lim = limit_cell(he[j + G], me[j + G], rec[j + 1], P.pp_eps, tr[j + 1]);
+    int lim = limit_cell(he[j + G], me[j + G], rec[j + 1], P.pp_eps, tr[j + 1],
+                         !(P.flags & FLAG_NO_HU_LIMIT));
     if (j >= 0 && j < n) {
       cnt.n_class[rec[j + 1].cls] += 1;
       if (cls) cls[j] = (uint8_t)rec[j + 1].cls;
@@ -612,8 +630,23 @@ static void residual(const Params& P, int n, const T* eta, const T* m, const T* 
     if (val(hr) < 0.0) hr = 0.0;
     T sl = fabs(Lt[i].u - w[i]) + sqrt(P.g * hl);
     T sr = fabs(Rt[i].u - w[i]) + sqrt(P.g * hr);
+    if (P.flags & FLAG_ALPHA_CELLAVG) continue;
     if (val(sl) > val(alpha)) alpha = sl;
     if (val(sr) > val(alpha)) alpha = sr;
+  }
+  if (P.flags & FLAG_ALPHA_CELLAVG) {
+    /* R19: the speed over the cell averages of the cells and their two nodes */
+    for (int j = 0; j < n; ++j) {
+      T hc = eta[j] - b[j];
+      T uc = 0.0;
+      if (val(hc) > P.dry_eps) uc = m[j] / hc;
+      if (val(hc) < 0.0) hc = 0.0;
+      T cg = sqrt(P.g * hc);
+      T sa = fabs(uc - w[j]) + cg;
+      T sb = fabs(uc - w[j + 1]) + cg;
+      if (val(sa) > val(alpha)) alpha = sa;
+      if (val(sb) > val(alpha)) alpha = sb;
+    }
   }
   if (alpha_out) *alpha_out = val(alpha);
   /* Numerical fluxes (eq. (3.13), (3.17)) and bottom averages (eq. (4.9)). */
@@ -685,6 +718,8 @@ static void mesh_velocity(const Params& P, int n, const T* eta, const T* m, cons
      * (sin(om(t+dt)) - sin(om t))/dt = 2 cos(om(t+dt/2)) sin(om dt/2)/dt. */
     double om = P.mesh_omega;
     double fac = 2.0 * std::cos(om * (t + 0.5 * dt)) * std::sin(0.5 * om * dt) / dt;
+    /* R21: the map's time derivative at t instead of the chord */
+    if (P.flags & FLAG_W_TANGENT) fac = om * std::cos(om * t);
     for (int i = 0; i <= n; ++i) w[i] = P.mesh_A * mesh_shape(P, xi[i], xi[0], xi[n]) * fac;
   } else {
     /* Fluid-following mesh: node average of the cell velocities, two passes
@@ -878,14 +913,15 @@ int orc_reconstruct(const double* wid5, const double* v5, const double* h5, cons
 }
 
 /* Positivity limiter on given traces.  in[6] = hL, mL, bL, hR, mR, bR;
- * out[6] same order.  Returns 0 untouched, 1 limited, 2 negative mean. */
-int orc_limit(double hbar, double mbar, const double* in, double pp_eps, double* out) {
+ * out[6] same order; hu_lim = 0 leaves the hu traces alone (R20).
+ * Returns 0 untouched, 1 limited, 2 negative mean. */
+int orc_limit(double hbar, double mbar, const double* in, double pp_eps, int hu_lim, double* out) {
   Recon<double> o;
   for (int mu = 0; mu < 4; ++mu) { o.h[mu] = 0; o.m[mu] = 0; o.b[mu] = 0; o.bx[mu] = 0; }
   o.h[0] = in[0]; o.m[0] = in[1]; o.b[0] = in[2];
   o.h[3] = in[3]; o.m[3] = in[4]; o.b[3] = in[5];
   Traces<double> tr;
-  int r = limit_cell(hbar, mbar, o, pp_eps, tr);
+  int r = limit_cell(hbar, mbar, o, pp_eps, tr, hu_lim != 0);
   out[0] = tr.hL; out[1] = tr.mL; out[2] = tr.bL;
   out[3] = tr.hR; out[4] = tr.mR; out[5] = tr.bR;
   return r;

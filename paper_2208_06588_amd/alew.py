@@ -15,10 +15,13 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libalew.so")
 
-OK, E_ARG, E_MESH, E_NEGDEPTH, E_NONFINITE, E_HIP, E_NOMEM, E_UNSUPPORTED, E_NEGWEIGHT = range(9)
+(OK, E_ARG, E_MESH, E_NEGDEPTH, E_NONFINITE, E_HIP, E_NOMEM, E_UNSUPPORTED, E_NEGWEIGHT,
+ E_CAPACITY) = range(10)
 BC = {"periodic": 0, "transmissive": 1, "reflective": 2}
 MESH = {"given": 0, "sine": 1, "paper": 2, "fluid": 3}
 F_BETA_LOCAL, F_BETA_FROM_H, F_HYDROSTATIC = 1, 2, 4
+F_ALPHA_CELLAVG, F_NO_HU_LIMIT, F_W_TANGENT = 8, 16, 32
+CLS_SIG_MUL = 1099511628211  # multiplier of the class-sequence signature of alew_run
 ENGINE_AUTO, ENGINE_PERSISTENT, ENGINE_STAGES = 0, 1, 2
 
 
@@ -76,7 +79,9 @@ def lib():
         L.alew_step.argtypes = [vp, C.POINTER(Params), i64, vp, vp, vp, vp, vp, vp, C.c_double,
                                 C.c_double, C.c_double, vp, C.POINTER(Stats)]
         L.alew_run.argtypes = [vp, C.POINTER(Params), i64, C.POINTER(C.c_int64), vp, vp, vp, vp, vp,
-                               dp, dp, C.POINTER(C.c_int64), vp, vp, i64, C.POINTER(Stats)]
+                               dp, dp, C.POINTER(C.c_int64), vp, vp, i64, vp, vp,
+                               C.POINTER(Stats)]
+        L.alew_adjoint_reserve.argtypes = [vp, i64, i64, i64]
         L.alew_adjoint.argtypes = [vp, C.POINTER(Params), i64, C.POINTER(C.c_int64), vp, vp, vp,
                                    vp, vp, C.c_double, i64, vp, i64, i64, vp, vp, vp, vp, vp, vp]
         L.alew_last_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
@@ -89,7 +94,7 @@ def lib():
         L.alew_last_error.restype = C.c_char_p
         L.alew_version.restype = C.c_char_p
         for f in ("alew_create", "alew_set_stream", "alew_set_launch", "alew_get_launch",
-                  "alew_step", "alew_run", "alew_adjoint"):
+                  "alew_step", "alew_run", "alew_adjoint", "alew_adjoint_reserve"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -202,13 +207,21 @@ class Context:
         return S
 
     def run(self, p: Params, cell_off: Sequence[int], h, hu, b, x, xi, t0=None, t_end=None,
-            max_steps=None, dts=None, dt_log=None, dts_stride=0, check=True):
-        """Run a packed ragged batch; returns the per-instance Stats."""
+            max_steps=None, dts=None, dt_log=None, dts_stride=0, cls_count=None, cls_sig=None,
+            check=True):
+        """Run a packed ragged batch; returns the per-instance Stats.  cls_count
+        (int32, 3 * cells) and cls_sig (int64, cells) accumulate the class record
+        of every cell and stage (see alew_run)."""
         ninst = len(cell_off) - 1
-        _sizes(int(cell_off[-1]), ninst, h, hu, b, x, xi, None)
+        S = int(cell_off[-1])
+        _sizes(S, ninst, h, hu, b, x, xi, None)
         for d in (dts, dt_log):
             if d is not None and d.numel() < ninst * dts_stride:
                 raise ValueError("dts/dt_log must hold ninst * dts_stride entries")
+        if (cls_count is None) != (cls_sig is None):
+            raise ValueError("cls_count and cls_sig go together")
+        if cls_count is not None and (cls_count.numel() != 3 * S or cls_sig.numel() != S):
+            raise ValueError("cls_count must hold 3 * cells entries and cls_sig one per cell")
         self._sync_stream()
         off = (C.c_int64 * len(cell_off))(*[int(v) for v in cell_off])
         n = len(cell_off) - 1
@@ -228,10 +241,16 @@ class Context:
         stats = (Stats * n)()
         st = lib().alew_run(self._h, C.byref(p), n, off, _ptr(h), _ptr(hu), _ptr(b), _ptr(x),
                             _ptr(xi), darr(t0), darr(t_end), iarr(max_steps), _ptr(dts),
-                            _ptr(dt_log), int(dts_stride), stats)
+                            _ptr(dt_log), int(dts_stride), _ptr(cls_count, torch.int32),
+                            _ptr(cls_sig, torch.int64), stats)
         if check:
             _check(st)
         return list(stats)
+
+    def adjoint_reserve(self, nsteps, ngauge, ckpt_every=16):
+        """Allocate the adjoint workspace for up to nsteps steps and ngauge gauges
+        per instance at the context's capacity."""
+        _check(lib().alew_adjoint_reserve(self._h, int(nsteps), int(ckpt_every), int(ngauge)))
 
     def adjoint(self, p: Params, cell_off, h0, hu0, b0, x0, xi, nsteps, dts, ngauge, gauge_x,
                 gauge_h, gauge_bar=None, dh0=None, dhu0=None, db0=None, ckpt_every=16, t0=0.0):

@@ -19,7 +19,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <numeric>
+#include <type_traits>
 #include <string>
 #include <vector>
 
@@ -35,6 +37,9 @@ using namespace alew_dev;
 // Items per plain tile (set-up, step epilogue, finish): independent of the
 // stage kernels' work-group size.
 constexpr int PB = 256;
+// Fewest cells a stage tile owns over every supported shape (block 64, one
+// cell per thread, compact tiles: 64 slots, 58 owned); sizes the tile tables.
+constexpr int64_t MIN_OWN = 58;
 
 struct Tile {
   int32_t inst;
@@ -209,8 +214,10 @@ __device__ void boundary_update(Inst& I, const Consts& cs, const Bufs& bf, int i
     I.active = 0;
     return;
   }
-  // the frozen step sizes and the step log hold dts_stride entries per instance
+  // the frozen step sizes and the step log hold dts_stride entries per
+  // instance: an instance that needs more steps stops with a status bit
   if ((bf.dts || bf.dt_log) && I.steps >= bf.dts_stride) {
+    I.status |= SB_CAPACITY;
     I.active = 0;
     return;
   }
@@ -222,7 +229,11 @@ __device__ void boundary_update(Inst& I, const Consts& cs, const Bufs& bf, int i
     return;
   }
   I.dt = dt;
-  I.wscale = (cs.mesh == MESH_SINE || cs.mesh == MESH_PAPER) ? chord_factor(cs, I.t, dt) : 1.0;
+  if (cs.mesh == MESH_SINE || cs.mesh == MESH_PAPER)
+    I.wscale = (cs.flags & F_W_TANGENT) ? cs.mesh_omega * cos(cs.mesh_omega * I.t)
+                                        : chord_factor(cs, I.t, dt);
+  else
+    I.wscale = 1.0;
   if (bf.dt_log) bf.dt_log[(int64_t)i * bf.dts_stride + I.steps] = dt;
   I.dx[0] = bitsd(I.r_maxJ);
   if (bf.dump.scal_next) {
@@ -659,7 +670,7 @@ struct alew_ctx {
   bool tables_masked = false;      // tables hold only the instances active at a check
   std::vector<uint8_t> cached_mask;
   bool split_s = false, split_p = false;  // some instance has several chunks
-  int64_t tiles_cap = 0;
+  int64_t cap_stage = 0, cap_plain = 0;  // tile table capacities (set in alew_create)
   int64_t n_tiles_edge = 0, n_tiles_inner = 0;
   int n_cu = 0;
   std::vector<int64_t> cell_off_h;  // cached batch layout
@@ -766,32 +777,10 @@ alew_status build_tiles(alew_ctx* c, const int64_t* cell_off, int64_t ninst, int
   pfirst[ninst] = (int64_t)tp.size();
   if (ts.size() >= (size_t)INT32_MAX || tp.size() >= (size_t)INT32_MAX)
     return fail(ALEW_E_ARG, "too many tiles");
-  const int64_t need = (int64_t)std::max(ts.size(), tp.size());
-  if (need > c->tiles_cap) {
-    for (Tile** tp_ : {&c->tiles_stage_d, &c->tiles_plain_d, &c->tiles_edge_d, &c->tiles_inner_d}) {
-      if (*tp_) (void)hipFree(*tp_);
-      *tp_ = nullptr;
-    }
-    for (double** rp : {&c->srec, &c->prec, &c->screc, &c->pcrec}) {
-      if (*rp) (void)hipFree(*rp);
-      *rp = nullptr;
-    }
-    for (RChunk** cp : {&c->schunk_d, &c->pchunk_d}) {
-      if (*cp) (void)hipFree(*cp);
-      *cp = nullptr;
-    }
-    HIPCHK(hipMalloc(&c->tiles_stage_d, need * sizeof(Tile)));
-    HIPCHK(hipMalloc(&c->tiles_plain_d, need * sizeof(Tile)));
-    HIPCHK(hipMalloc(&c->tiles_edge_d, need * sizeof(Tile)));
-    HIPCHK(hipMalloc(&c->tiles_inner_d, need * sizeof(Tile)));
-    HIPCHK(hipMalloc(&c->srec, need * SREC * sizeof(double)));
-    HIPCHK(hipMalloc(&c->prec, need * PREC * sizeof(double)));
-    HIPCHK(hipMalloc(&c->screc, need * SREC * sizeof(double)));
-    HIPCHK(hipMalloc(&c->pcrec, need * PREC * sizeof(double)));
-    HIPCHK(hipMalloc(&c->schunk_d, need * sizeof(RChunk)));
-    HIPCHK(hipMalloc(&c->pchunk_d, need * sizeof(RChunk)));
-    c->tiles_cap = need;
-  }
+  // the tables were sized in alew_create for the smallest stage tile (no
+  // allocation here); the caller's capacity checks keep them within bounds
+  if ((int64_t)ts.size() > c->cap_stage || (int64_t)tp.size() > c->cap_plain)
+    return fail(ALEW_E_ARG, "internal: tile tables exceed the context capacity");
   // record chunks: up to RCHUNK consecutive records of one instance
   auto chunk = [&](const std::vector<int64_t>& first, std::vector<RChunk>& out,
                    std::vector<int64_t>& cfirst, bool& split) {
@@ -855,13 +844,15 @@ alew_status build_tiles(alew_ctx* c, const int64_t* cell_off, int64_t ninst, int
 }
 
 Bufs make_bufs(alew_ctx* c, int64_t S, int64_t ninst, double* hu, double* b, const double* xi,
-               uint8_t* cls, const double* dts, double* dt_log, int64_t dts_stride) {
+               uint8_t* cls, const double* dts, double* dt_log, int64_t dts_stride,
+               uint32_t* ccount = nullptr, uint64_t* csig = nullptr) {
   Bufs bf;
   bf.cell_off = c->cell_off_d;
   bf.eta = c->eta; bf.m = hu; bf.b = b;
   bf.xa = c->xa; bf.xb = c->xb; bf.xi = xi; bf.w = c->w;
   bf.P0 = c->P0; bf.D0 = c->D0; bf.P1 = c->P1; bf.D1 = c->D1;
   bf.cls = cls; bf.inst = c->inst;
+  bf.ccount = ccount; bf.csig = (unsigned long long*)csig;
   bf.dts = dts; bf.dt_log = dt_log; bf.dts_stride = dts_stride;
   bf.S = S; bf.ninst = (int32_t)ninst; bf.pad = 0;
   bf.srec = c->srec; bf.prec = c->prec;
@@ -1009,7 +1000,7 @@ alew_status run_stage_engine(alew_ctx* c, const Bufs& bf, const Consts& cs, int6
   HIPCHK(ensure_graph());
   int64_t it = 0;
   c->last_launches = 0;
-  HIPCHK(hipEventRecord(c->ev0, c->stream));
+  if (c->ev0) HIPCHK(hipEventRecord(c->ev0, c->stream));
   while (it < max_iters) {
     for (int k = 0; k < check_every && it < max_iters; ++k) {
       if (use_graph) {
@@ -1040,11 +1031,14 @@ alew_status run_stage_engine(alew_ctx* c, const Bufs& bf, const Consts& cs, int6
     }
   }
   c->ktime_rec = false;
-  HIPCHK(hipEventRecord(c->ev1, c->stream));
-  HIPCHK(hipEventSynchronize(c->ev1));
-  float ms = 0.f;
-  HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
-  c->last_ms = ms;
+  c->last_ms = 0.0;
+  if (c->ev0 && c->ev1) {  // a context without events (the allocation-free step) skips timing
+    HIPCHK(hipEventRecord(c->ev1, c->stream));
+    HIPCHK(hipEventSynchronize(c->ev1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    c->last_ms = ms;
+  }
   return ALEW_OK;
 }
 
@@ -1100,6 +1094,7 @@ alew_status map_status(int bits) {
   if (bits & SB_NONFINITE) return ALEW_E_NONFINITE;
   if (bits & SB_NEGDEPTH) return ALEW_E_NEGDEPTH;
   if (bits & SB_NEGWEIGHT) return ALEW_E_NEGWEIGHT;
+  if (bits & SB_CAPACITY) return ALEW_E_CAPACITY;
   if (bits & SB_SEQUENCE) return ALEW_E_UNSUPPORTED;  // instances of a batch out of step
   return ALEW_OK;
 }
@@ -1109,7 +1104,7 @@ alew_status drive(alew_ctx* c, const alew_params* p, int64_t ninst, const int64_
                   double* h, double* hu, double* b, double* x, const double* xi,
                   const double* wgiven, const double* t0, const double* t_end,
                   const int64_t* max_steps, const double* dts, double* dt_log, int64_t dts_stride,
-                  uint8_t* cls, alew_stats* stats, int engine) {
+                  uint8_t* cls, uint32_t* ccount, uint64_t* csig, alew_stats* stats, int engine) {
   alew_status ps = check_params(p);
   if (ps != ALEW_OK) return ps;
   if (!c) return fail(ALEW_E_ARG, "ctx is NULL");
@@ -1125,6 +1120,8 @@ alew_status drive(alew_ctx* c, const alew_params* p, int64_t ninst, const int64_
   const int64_t S = cell_off[ninst];
   if (S > c->max_cells) return fail(ALEW_E_ARG, "total cells exceed the context capacity");
   if ((dts || dt_log) && dts_stride <= 0) return fail(ALEW_E_ARG, "dts_stride must be > 0");
+  if ((ccount == nullptr) != (csig == nullptr))
+    return fail(ALEW_E_ARG, "cls_count and cls_sig go together");
   const int B = pick_block(c, engine);
   const int CPT = (engine == 1) ? 1 : pick_cpt(c, B);
   const bool noext = engine != 1 && c->launch.compact_tiles == 1;
@@ -1149,7 +1146,7 @@ alew_status drive(alew_ctx* c, const alew_params* p, int64_t ninst, const int64_
   }
   HIPCHK(hipMemcpyAsync(c->inst, c->inst_h, ninst * sizeof(Inst), hipMemcpyHostToDevice, c->stream));
   HIPCHK(hipMemcpyAsync(c->xa, x, (S + ninst) * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-  Bufs bf = make_bufs(c, S, ninst, hu, b, xi, cls, dts, dt_log, dts_stride);
+  Bufs bf = make_bufs(c, S, ninst, hu, b, xi, cls, dts, dt_log, dts_stride, ccount, csig);
   const Consts cs = make_consts(p);
   const dim3 gp((unsigned)c->n_tiles_plain);
 #define ALEW_DISPATCH(BB)                                                                       \
@@ -1211,6 +1208,40 @@ alew_status drive(alew_ctx* c, const alew_params* p, int64_t ninst, const int64_
     g_err = buf;
   }
   return worst;
+}
+
+// Workspace of alew_adjoint (in doubles): hu and b of the run, checkpoints
+// (state, nodes, instance records) every K steps, the per-step records of one
+// segment (q of the three stages, x^n and w^n, step scalars, argmax keys),
+// and the adjoint state, reverse-tile table and per-instance sums.
+constexpr int ADJ_OWN = 250;  // owned cells of a fused reverse-stage tile
+struct AdjLayout {
+  size_t n_ck, n_ckI, per_step, n_seg, n_at, bytes;
+};
+AdjLayout adj_layout(int64_t S, int64_t ninst, int64_t n_atiles, int64_t nsteps, int64_t K,
+                     int64_t ngauge) {
+  AdjLayout L;
+  const int64_t nck = (nsteps + K - 1) / K;
+  const int64_t NN = S + ninst;
+  const size_t n_state = 2 * (size_t)S;
+  L.n_ck = (size_t)nck * (3 * S + NN);
+  L.n_ckI = (size_t)nck * ninst * sizeof(Inst) / 8 + 1;
+  L.per_step = 9 * (size_t)S + 2 * (size_t)NN + 11 * (size_t)ninst;
+  L.n_seg = (size_t)(K + 1) * L.per_step;
+  L.n_at = (sizeof(AdjTile) / 8) * (size_t)n_atiles;
+  const size_t n_adj = 9 * (size_t)S + (size_t)ninst + (size_t)ninst * ngauge +
+                       18 * (size_t)ninst + L.n_at + (size_t)n_atiles + (size_t)ninst + 1;
+  L.bytes = (n_state + L.n_ck + L.n_ckI + L.n_seg + n_adj) * 8;
+  return L;
+}
+
+alew_status adj_reserve(alew_ctx* c, size_t bytes) {
+  if (c->adj_ws) (void)hipFree(c->adj_ws);
+  c->adj_ws = nullptr;
+  c->adj_ws_bytes = 0;
+  if (hipMalloc(&c->adj_ws, bytes) != hipSuccess) return fail(ALEW_E_NOMEM, "adjoint workspace");
+  c->adj_ws_bytes = bytes;
+  return ALEW_OK;
 }
 
 }  // namespace
@@ -1280,6 +1311,22 @@ alew_status alew_create(alew_ctx** out, int64_t max_cells, int64_t max_inst, voi
             alloc((void**)&c->queue_d, sizeof(unsigned)) && alloc((void**)&c->nactive_d, sizeof(int)) &&
             alloc((void**)&c->act_d, max_inst) &&
             alloc((void**)&c->dt1_d, sizeof(double));
+  // tile tables, result records and record chunks, sized for the smallest
+  // stage tile (64 slots, 58 owned cells) and the plain tiles (256 items over
+  // the n + 1 nodes of each instance)
+  c->cap_stage = (max_cells + MIN_OWN - 1) / MIN_OWN + max_inst;
+  c->cap_plain = max_cells / PB + max_inst + 1;
+  const int64_t cs_ = c->cap_stage, cp_ = c->cap_plain;
+  ok = ok && alloc((void**)&c->tiles_stage_d, cs_ * sizeof(Tile)) &&
+       alloc((void**)&c->tiles_edge_d, cs_ * sizeof(Tile)) &&
+       alloc((void**)&c->tiles_inner_d, cs_ * sizeof(Tile)) &&
+       alloc((void**)&c->tiles_plain_d, cp_ * sizeof(Tile)) &&
+       alloc((void**)&c->srec, cs_ * SREC * sizeof(double)) &&
+       alloc((void**)&c->screc, cs_ * SREC * sizeof(double)) &&
+       alloc((void**)&c->prec, cp_ * PREC * sizeof(double)) &&
+       alloc((void**)&c->pcrec, cp_ * PREC * sizeof(double)) &&
+       alloc((void**)&c->schunk_d, cs_ * sizeof(RChunk)) &&
+       alloc((void**)&c->pchunk_d, cp_ * sizeof(RChunk));
   ok = ok && hipHostMalloc((void**)&c->dt1_h, sizeof(double), hipHostMallocDefault) == hipSuccess;
   ok = ok && hipHostMalloc((void**)&c->inst_h, max_inst * sizeof(Inst), hipHostMallocDefault) == hipSuccess;
   ok = ok && hipHostMalloc((void**)&c->nactive_h, sizeof(int), hipHostMallocDefault) == hipSuccess;
@@ -1362,7 +1409,7 @@ alew_status alew_step(alew_ctx* c, const alew_params* p, int64_t ncell, double* 
   c->launch.use_graph = 0;
   alew_stats st;
   alew_status r = drive(c, p, 1, off, h, hu, b, x, xi, w, &t, &tend, &one, dts, nullptr,
-                        dts ? 1 : 0, cls, &st, 2);
+                        dts ? 1 : 0, cls, nullptr, nullptr, &st, 2);
   c->launch = keep;
   if (stats) *stats = st;
   return r;
@@ -1371,7 +1418,8 @@ alew_status alew_step(alew_ctx* c, const alew_params* p, int64_t ncell, double* 
 alew_status alew_run(alew_ctx* c, const alew_params* p, int64_t ninst, const int64_t* cell_off,
                      double* h, double* hu, double* b, double* x, const double* xi,
                      const double* t0, const double* t_end, const int64_t* max_steps,
-                     const double* dts, double* dt_log, int64_t dts_stride, alew_stats* stats) {
+                     const double* dts, double* dt_log, int64_t dts_stride, uint32_t* cls_count,
+                     uint64_t* cls_sig, alew_stats* stats) {
   if (p && p->mesh == ALEW_MESH_GIVEN) return fail(ALEW_E_UNSUPPORTED, "alew_run needs a SINE, PAPER or FLUID mesh");
   if (!c) return fail(ALEW_E_ARG, "ctx is NULL");
   int engine = c->launch.engine;
@@ -1379,7 +1427,17 @@ alew_status alew_run(alew_ctx* c, const alew_params* p, int64_t ninst, const int
   std::vector<alew_stats> tmp;
   if (!stats) { tmp.resize(ninst > 0 ? ninst : 1); stats = tmp.data(); }
   return drive(c, p, ninst, cell_off, h, hu, b, x, xi, nullptr, t0, t_end, max_steps, dts, dt_log,
-               dts_stride, nullptr, stats, engine);
+               dts_stride, nullptr, cls_count, cls_sig, stats, engine);
+}
+
+alew_status alew_adjoint_reserve(alew_ctx* c, int64_t nsteps, int64_t ckpt_every, int64_t ngauge) {
+  if (!c) return fail(ALEW_E_ARG, "ctx is NULL");
+  if (nsteps < 1 || ngauge < 1) return fail(ALEW_E_ARG, "nsteps and ngauge must be >= 1");
+  const int64_t K = ckpt_every > 0 ? ckpt_every : 16;
+  const int64_t nat = c->max_cells / ADJ_OWN + c->max_inst;
+  const AdjLayout L = adj_layout(c->max_cells, c->max_inst, nat, nsteps, K, ngauge);
+  if (L.bytes <= c->adj_ws_bytes) return ALEW_OK;
+  return adj_reserve(c, L.bytes);
 }
 
 alew_status alew_adjoint(alew_ctx* c, const alew_params* p, int64_t ninst,
@@ -1393,6 +1451,8 @@ alew_status alew_adjoint(alew_ctx* c, const alew_params* p, int64_t ninst,
   if (!c) return fail(ALEW_E_ARG, "ctx is NULL");
   if (p->mesh != ALEW_MESH_SINE && p->mesh != ALEW_MESH_PAPER)
     return fail(ALEW_E_UNSUPPORTED, "the adjoint needs a prescribed (SINE or PAPER) mesh");
+  if (p->flags & ALEW_F_ALPHA_CELLAVG)
+    return fail(ALEW_E_UNSUPPORTED, "the adjoint takes the LF speed over the face traces");
   if (ninst <= 0 || ninst > c->max_inst || !cell_off) return fail(ALEW_E_ARG, "bad ninst / cell_off");
   if (!h0 || !hu0 || !b0 || !x0 || !xi || !dts) return fail(ALEW_E_ARG, "NULL input array");
   if (nsteps < 1) return fail(ALEW_E_ARG, "nsteps must be >= 1");
@@ -1410,31 +1470,19 @@ alew_status alew_adjoint(alew_ctx* c, const alew_params* p, int64_t ninst,
   const int B = pick_block(c, 2), CPT = pick_cpt(c, B);
   alew_status ts = build_tiles(c, cell_off, ninst, PB, B * CPT, c->launch.compact_tiles == 1);
   if (ts != ALEW_OK) return ts;
-  // workspace layout (doubles)
-  const size_t n_state = 2 * (size_t)S;                 // hu, b of the run
-  const size_t n_ck = (size_t)nck * (3 * S + NN);       // checkpoints
-  const size_t n_ckI = (size_t)nck * ninst * sizeof(Inst) / 8 + 1;
-  // records of one step: q of the three stages, x^n and w^n, the step
-  // scalars, and the argmax keys of the three stages
-  const size_t per_step = 9 * (size_t)S + 2 * (size_t)NN + 11 * (size_t)ninst;
-  const size_t n_seg = (size_t)(K + 1) * per_step;
-  // tiles of the fused reverse stage: 250 owned cells each (256 threads)
-  constexpr int BA = 256, TBA = BA - 6;
+  // tiles of the fused reverse stage: ADJ_OWN owned cells each (256 threads)
+  constexpr int BA = 256, TBA = ADJ_OWN;
   std::vector<AdjTile> atiles;
   for (int64_t i = 0; i < ninst; ++i)
     for (int64_t c0 = 0; c0 < cell_off[i + 1] - cell_off[i]; c0 += TBA)
       atiles.push_back(AdjTile{(int32_t)i, 0, c0, cell_off[i], cell_off[i + 1] - cell_off[i]});
-  const size_t n_at = (sizeof(AdjTile) / 8) * atiles.size();
-  const size_t n_adj = 9 * (size_t)S + (size_t)ninst + (size_t)ninst * ngauge +
-                       18 * (size_t)ninst + n_at + atiles.size() + (size_t)ninst + 1;
-  const size_t need = (n_state + n_ck + n_ckI + n_seg + n_adj) * 8;
-  if (need > c->adj_ws_bytes) {
-    if (c->adj_ws) (void)hipFree(c->adj_ws);
-    c->adj_ws = nullptr;
-    c->adj_ws_bytes = 0;
-    if (hipMalloc(&c->adj_ws, need) != hipSuccess) return fail(ALEW_E_NOMEM, "adjoint workspace");
-    c->adj_ws_bytes = need;
+  const AdjLayout L = adj_layout(S, ninst, (int64_t)atiles.size(), nsteps, K, ngauge);
+  if (L.bytes > c->adj_ws_bytes) {
+    alew_status rs = adj_reserve(c, L.bytes);
+    if (rs != ALEW_OK) return rs;
   }
+  const size_t n_ck = L.n_ck, n_ckI = L.n_ckI, per_step = L.per_step, n_seg = L.n_seg,
+               n_at = L.n_at;
   double* wp = c->adj_ws;
   double* st_m = wp; wp += S;
   double* st_b = wp; wp += S;

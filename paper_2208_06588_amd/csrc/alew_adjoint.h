@@ -209,17 +209,21 @@ __device__ __forceinline__ void alpha_trace_vjp(double h, double m, double w, do
 // ----------------------------------------------------------------------------
 // Reverse of the positivity limiter (1D eq. (3.20)-(3.21), Remark 4.1).
 // o: unlimited traces.  In: adjoints of the limited traces; out: adjoints of
-// the unlimited traces, plus the cell means.
+// the unlimited traces, plus the cell means.  hu_lim as in limit_cell.
 // ----------------------------------------------------------------------------
 __device__ __forceinline__ void limit_vjp(double hbar, double mbar, double pp_eps, const CellRecon& o,
                                           TraceAdj& LL, TraceAdj& LR, double& lhbar,
-                                          double& lmbar) {
+                                          double& lmbar, bool hu_lim = true) {
   if (hbar <= 0.0) {
-    // h' = hbar, m' = mbar, b' = (h + b) - hbar
+    // h' = hbar, m' = mbar (hu_lim), b' = (h + b) - hbar
     lhbar += LL.h + LR.h - LL.b - LR.b;
-    lmbar += LL.m + LR.m;
-    LL.h = LL.b; LL.m = 0.0;
-    LR.h = LR.b; LR.m = 0.0;
+    LL.h = LL.b;
+    LR.h = LR.b;
+    if (hu_lim) {
+      lmbar += LL.m + LR.m;
+      LL.m = 0.0;
+      LR.m = 0.0;
+    }
     return;
   }
   const double s1 = 1.0 / 12.0;
@@ -241,9 +245,13 @@ __device__ __forceinline__ void limit_vjp(double hbar, double mbar, double pp_ep
   double lhL = LL.b + Phi * lhLt;
   double lhR = LR.b + Phi * lhRt;
   lhbar += (1.0 - Phi) * (lhLt + lhRt);
-  lPhi += (o.mL - mbar) * LL.m + (o.mR - mbar) * LR.m;
-  const double lmL = Phi * LL.m, lmR = Phi * LR.m;
-  lmbar += (1.0 - Phi) * (LL.m + LR.m);
+  double lmL = LL.m, lmR = LR.m;
+  if (hu_lim) {
+    lPhi += (o.mL - mbar) * LL.m + (o.mR - mbar) * LR.m;
+    lmL = Phi * LL.m;
+    lmR = Phi * LR.m;
+    lmbar += (1.0 - Phi) * (LL.m + LR.m);
+  }
   if (!clamped) {
     lhbar += lPhi * ((eps_const ? 1.0 : 0.0) - Phi) * iden;
     const double lmn = lPhi * Phi * iden;
@@ -685,7 +693,7 @@ __global__ __launch_bounds__(B) void k_adj_fused(AdjBufs ab, Consts cs,
     recon_cell<HR>(v5, h5, &sm.m[t], &sm.b[t], &sm.J[t], frcp(sm.J[t + 2]), Dx, cs.weno_eps,
                    sm.e[t + 2], o);
     ou = o;
-    limit_cell(h5[2], sm.m[t + 2], cs.pp_eps, o);
+    limit_cell(h5[2], sm.m[t + 2], cs.pp_eps, o, !(cs.flags & F_NO_HU_LIMIT));
     sm.u.tr[0][t] = o.hL; sm.u.tr[1][t] = o.mL; sm.u.tr[2][t] = o.bL;
     sm.u.tr[3][t] = o.hR; sm.u.tr[4][t] = o.mR; sm.u.tr[5][t] = o.bR;
   }
@@ -736,7 +744,7 @@ __global__ __launch_bounds__(B) void k_adj_fused(AdjBufs ab, Consts cs,
       }
     }
     double lhbar = 0.0, lmbar = 0.0;
-    limit_vjp(h5[2], sm.m[t + 2], cs.pp_eps, ou, LL, LR, lhbar, lmbar);
+    limit_vjp(h5[2], sm.m[t + 2], cs.pp_eps, ou, LL, LR, lhbar, lmbar, !(cs.flags & F_NO_HU_LIMIT));
     ReconAdjOut ra;
     recon_cell_vjp<HR>(v5, h5, &sm.m[t], &sm.b[t], &sm.J[t], Dx, cs.weno_eps, sm.e[t + 2], LL, LR,
                        lrint, ra, hle, hlb);
@@ -859,12 +867,12 @@ __global__ __launch_bounds__(64) void k_adj_patch(AdjBufs ab, Consts cs, int s) 
   CellRecon o;
   recon_cell(v5, h5, m5, b5, J5, frcp(J5[2]), Dx, cs.weno_eps, e5[2], o);
   const CellRecon ou = o;
-  limit_cell(h5[2], m5[2], cs.pp_eps, o);
+  limit_cell(h5[2], m5[2], cs.pp_eps, o, !(cs.flags & F_NO_HU_LIMIT));
   TraceAdj LL{0, 0, 0}, LR{0, 0, 0};
   if (side == 0) alpha_trace_vjp(o.hR, o.mR, w[f], cs.g, cs.dry_eps, lal, LR);
   else alpha_trace_vjp(o.hL, o.mL, w[f], cs.g, cs.dry_eps, lal, LL);
   double lhbar = 0.0, lmbar = 0.0;
-  limit_vjp(h5[2], m5[2], cs.pp_eps, ou, LL, LR, lhbar, lmbar);
+  limit_vjp(h5[2], m5[2], cs.pp_eps, ou, LL, LR, lhbar, lmbar, !(cs.flags & F_NO_HU_LIMIT));
   ReconAdjOut ra;
   recon_cell_vjp(v5, h5, m5, b5, J5, Dx, cs.weno_eps, e5[2], LL, LR, 0.0, ra);
   const bool vh = (cs.flags & F_BETA_FROM_H) != 0;

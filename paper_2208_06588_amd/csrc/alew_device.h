@@ -20,9 +20,15 @@ namespace alew_dev {
 
 enum { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1, BC_REFLECTIVE = 2 };
 enum { MESH_GIVEN = 0, MESH_SINE = 1, MESH_PAPER = 2, MESH_FLUID = 3 };
-enum { F_BETA_LOCAL = 1, F_BETA_FROM_H = 2, F_HYDROSTATIC = 4 };
+enum {
+  F_BETA_LOCAL = 1, F_BETA_FROM_H = 2, F_HYDROSTATIC = 4, F_ALPHA_CELLAVG = 8, F_NO_HU_LIMIT = 16,
+  F_W_TANGENT = 32
+};
 // status bits (combined per instance; mapped to alew_status on the host)
-enum { SB_MESH = 1, SB_NEGDEPTH = 2, SB_NONFINITE = 4, SB_NEGWEIGHT = 8, SB_SEQUENCE = 16 };
+enum {
+  SB_MESH = 1, SB_NEGDEPTH = 2, SB_NONFINITE = 4, SB_NEGWEIGHT = 8, SB_SEQUENCE = 16,
+  SB_CAPACITY = 32
+};
 
 struct Consts {
   double g, cfl, weno_eps, pp_eps;
@@ -420,13 +426,16 @@ __device__ __forceinline__ void recon_cell(const double* __restrict__ v5,  // in
 
 // ----------------------------------------------------------------------------
 // Positivity limiter, 1D form of eq. (3.20)-(3.21); bottom traces by Remark 4.1.
+// The hu traces are scaled by the same Phi about their mean unless hu_lim is
+// false (then the limiter acts on h, and through Remark 4.1 on b, only).
 // Returns 1 when the traces were modified.
 // ----------------------------------------------------------------------------
-__device__ __forceinline__ int limit_cell(double hbar, double mbar, double pp_eps, CellRecon& o) {
+__device__ __forceinline__ int limit_cell(double hbar, double mbar, double pp_eps, CellRecon& o,
+                                          bool hu_lim = true) {
   if (hbar <= 0.0) {
     const double eL = o.hL + o.bL, eR = o.hR + o.bR;
     o.hL = hbar; o.hR = hbar;
-    o.mL = mbar; o.mR = mbar;
+    if (hu_lim) { o.mL = mbar; o.mR = mbar; }
     o.bL = eL - o.hL;
     o.bR = eR - o.hR;
     return 1;
@@ -443,8 +452,10 @@ __device__ __forceinline__ int limit_cell(double hbar, double mbar, double pp_ep
   const double eL = o.hL + o.bL, eR = o.hR + o.bR;
   o.hL = Phi * (o.hL - hbar) + hbar;
   o.hR = Phi * (o.hR - hbar) + hbar;
-  o.mL = Phi * (o.mL - mbar) + mbar;
-  o.mR = Phi * (o.mR - mbar) + mbar;
+  if (hu_lim) {
+    o.mL = Phi * (o.mL - mbar) + mbar;
+    o.mR = Phi * (o.mR - mbar) + mbar;
+  }
   o.bL = eL - o.hL;
   o.bR = eR - o.hR;
   return 1;

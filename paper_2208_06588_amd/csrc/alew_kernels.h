@@ -41,6 +41,11 @@ struct Bufs {
   double* P1;
   double* D1;
   uint8_t* cls;  // optional [3][S] classes of the current step
+  // optional class record of a run: per-cell counts of stages classified
+  // S / T / N ([3][S]) and a signature of each cell's class sequence ([S]),
+  // csig <- csig * CLS_SIG_MUL + class + 1 (mod 2^64) at every stage
+  uint32_t* ccount;
+  unsigned long long* csig;
   Inst* inst;
   const double* dts;  // optional frozen step sizes [ninst][dts_stride]
   double* dt_log;     // optional [ninst][dts_stride]
@@ -60,6 +65,10 @@ struct Bufs {
   double* pcrec;           // [plain chunks][PREC]
   Dump dump;
 };
+
+// Multiplier of the class-sequence signature (odd, so that every class
+// sequence of a cell maps to its own residue far more often than not).
+constexpr unsigned long long CLS_SIG_MUL = 1099511628211ull;
 
 // Per-instance view used by the tile bodies.
 struct View {
@@ -380,7 +389,7 @@ __device__ __forceinline__ StageRes stage_compute(const Bufs& bf, const Consts& 
       const double Dx = (cs.flags & F_BETA_LOCAL) ? Jj[c] : sc.dx;
       recon_cell<HR>(v5, h5, sm.u.in.m + i, sb, sm.u.in.J + i, sm.u.in.iJ[i + 2], Dx,
                      cs.weno_eps, ebar[c], o);
-      const int lim = limit_cell(hbar, mbar[c], cs.pp_eps, o);
+      const int lim = limit_cell(hbar, mbar[c], cs.pp_eps, o, !(cs.flags & F_NO_HU_LIMIT));
       // HR: the cell's hydrostatic source from its limited traces (eta kept by
       // the limiter) and the interior values; else the special-source term
       rint[c] = HR ? hydro_source(cs.g, o.hL + o.bL, o.e1, o.e2, o.hR + o.bR, o.bL, o.b1, o.b2, o.bR)
@@ -390,6 +399,11 @@ __device__ __forceinline__ StageRes stage_compute(const Bufs& bf, const Consts& 
         lim_owned = lim != 0;
         if (hbar < -cs.pp_eps) st |= SB_NEGDEPTH;
         if (cls_tile) cls_tile[i - 1] = (uint8_t)o.cls;
+        if (bf.ccount) {
+          const int64_t g = v.co + c0 - 1 + i;
+          bf.ccount[(int64_t)o.cls * bf.S + g] += 1u;
+          bf.csig[g] = bf.csig[g] * CLS_SIG_MUL + (unsigned long long)(o.cls + 1);
+        }
       }
       if (o.negw && (owned || (lghost && i == 0) || i == ighr)) { neg_cell = true; st |= SB_NEGWEIGHT; }
       tl0[c] = o.hL; tl1[c] = o.mL; tl2[c] = o.bL;
@@ -410,6 +424,9 @@ __device__ __forceinline__ StageRes stage_compute(const Bufs& bf, const Consts& 
   }
   lds_sync();
   // 3. face at node j of tile cell i (between cells j-1 and j), i = 1 .. TB-1
+  // LF speed: over the limited face traces, or (ALPHA_CELLAVG) over the cell
+  // averages of the stage input and the two node speeds of each owned cell
+  const bool a_cell = (cs.flags & F_ALPHA_CELLAVG) != 0;
   double fspeed = 0.0;
   double fsl[CPT], fsr[CPT];
 #pragma unroll
@@ -429,7 +446,7 @@ __device__ __forceinline__ StageRes stage_compute(const Bufs& bf, const Consts& 
         sm.u.fl[0][i] = f.Fc1; sm.u.fl[1][i] = f.Fc2 + f.cl; sm.u.fl[2][i] = f.Gc;
         sm.u.fl[3][i] = f.je; sm.u.fl[4][i] = f.jm; sm.u.fl[5][i] = f.jb;
         sm.u.fl[6][i] = f.Fc2 + f.cr;
-        fspeed = vmax(fspeed, f.speed);
+        if (!a_cell) fspeed = vmax(fspeed, f.speed);
         fsl[c] = f.sl;
         fsr[c] = f.sr;
       } else {
@@ -439,7 +456,7 @@ __device__ __forceinline__ StageRes stage_compute(const Bufs& bf, const Consts& 
         // face (one LDS array less; still water still cancels to round-off)
         sm.u.fl[0][i] = f.Fc1; sm.u.fl[1][i] = f.Fc2 - 0.5 * cs.g * f.B2; sm.u.fl[2][i] = f.Gc;
         sm.u.fl[3][i] = f.je; sm.u.fl[4][i] = f.jm; sm.u.fl[5][i] = f.jb; sm.u.fl[6][i] = f.B1;
-        fspeed = vmax(fspeed, f.speed);
+        if (!a_cell) fspeed = vmax(fspeed, f.speed);
         fsl[c] = f.sl;
         fsr[c] = f.sr;
       }
@@ -482,6 +499,12 @@ __device__ __forceinline__ StageRes stage_compute(const Bufs& bf, const Consts& 
       if (bf.dump.q) {
         const int64_t o = (int64_t)(3 * (sc.s - 1)) * NS + gt + i;
         bf.dump.q[o] = eb; bf.dump.q[o + NS] = mb; bf.dump.q[o + 2 * NS] = bb;
+      }
+      if (a_cell) {
+        const double hc = eb - bb;
+        const double uc = hc > cs.dry_eps ? mb * frcp(hc) : 0.0;
+        const double du = vmax(fabs(uc - sm.wn[i + 2]), fabs(uc - sm.wn[i + 3]));
+        fspeed = vmax(fspeed, du + fsqrt(g * vmax(hc, 0.0)));
       }
       const double Jnext = sm.Jx[i + 2];
       maxJ = vmax(maxJ, Jnext);

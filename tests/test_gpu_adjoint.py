@@ -54,9 +54,9 @@ def _params(bc, cfl=0.6, hydro=False):
     return g, o
 
 
-# The wet/dry case divides by trace depths of order 1e-3 (u = hu/h and its
-# derivatives -u/h, 1/h), which multiplies the round-off difference between the
-# two evaluation orders; it gets a 10x looser bound.
+# Errors are measured cell by cell, |g - o| / max(1, |o|), so that cells with a
+# gradient of order one are held to the bar however large the gradient is at a
+# wet/dry front elsewhere.
 # The 560-cell cases span three tiles of the reverse-stage kernel (250 owned
 # cells each), with gauges dense enough that the adjoint is nonzero across the
 # tile seams.
@@ -67,18 +67,19 @@ def _params(bc, cfl=0.6, hydro=False):
 @pytest.mark.parametrize("hydro", [False, True])
 @pytest.mark.parametrize("kind,ckpt,tol,n,nsteps,ng,cfl", [
     ("smooth", 3, 1e-11, 64, 7, 6, 0.3), ("step", 2, 1e-11, 64, 7, 6, 0.3),
-    ("wetdry", 16, 1e-10, 64, 7, 6, 0.3), ("smooth", 3, 1e-11, 560, 8, 40, 0.3),
-    ("step", 4, 1e-11, 560, 8, 40, 0.3), ("wetdry", 5, 1e-10, 560, 8, 40, 0.08)])
+    ("wetdry", 16, 1e-11, 64, 7, 6, 0.3), ("smooth", 3, 1e-11, 560, 8, 40, 0.3),
+    ("step", 4, 1e-11, 560, 8, 40, 0.3), ("wetdry", 5, 1e-11, 560, 8, 40, 0.08)])
 def test_adjoint_matches_oracle(dev, kind, ckpt, tol, n, nsteps, ng, cfl, hydro):
     xi, h, hu, b, bc = _case(kind, n)
     gp, op = _params(bc, cfl=cfl, hydro=hydro)
-    if hydro and kind == "wetdry":
+    if hydro and kind == "wetdry" and n == 560:
         # the hydrostatic form also divides by the starred depths h* = max(0,
         # eta - max(b-, b+)), which at the wet/dry front are far below the trace
-        # depths (bounded only by dry_eps = 1e-8): the gradient reaches ~1e6
-        # there (~1 elsewhere) and the round-off of the two evaluation orders is
-        # amplified accordingly
-        tol = max(tol, 1e-8)
+        # depths (bounded only by dry_eps = 1e-8): the momentum flux carries
+        # hu^2 / h*, whose derivatives hu / h*^2 reach ~1e16 and cancel to
+        # gradients of ~1e8 at the front, so the round-off of the two evaluation
+        # orders is amplified by ~1e8 relative to the result there
+        tol = 1e-8
     # step sizes: those the CFL rule picks in the oracle's own run
     r = O.run(op, h, hu, b, xi, xi, max_steps=1)
     dts = np.full(nsteps, r["stats"].dt_max)
@@ -95,11 +96,19 @@ def test_adjoint_matches_oracle(dev, kind, ckpt, tol, n, nsteps, ng, cfl, hydro)
                 gh, T["gb"], dh, dhu, db, ckpt_every=ckpt)
     torch.cuda.synchronize()
     np.testing.assert_allclose(gh.cpu().numpy(), gh_o, rtol=0, atol=1e-12)
-    for g, o in ((dh, dh_o), (dhu, dhu_o), (db, db_o)):
+    for name, g, o in (("h", dh, dh_o), ("hu", dhu, dhu_o), ("b", db, db_o)):
         g = g.cpu().numpy()
         scale = max(1.0, np.abs(o).max())
         err = np.abs(g - o).max() / scale
+        cell = np.abs(g - o) / np.maximum(1.0, np.abs(o))
+        big = cell > 1e-11
+        print(f"adjoint {kind} n={n} hydro={hydro} d/d{name}: per-cell max {cell.max():.2e} "
+              f"(cells above 1e-11: {int(big.sum())}, their |grad| "
+              f"{np.sort(np.abs(o[big]))[:4]}..{np.abs(o[big]).max() if big.any() else 0:.2e}, "
+              f"median |grad| {np.median(np.abs(o)):.2e}), global-scale {err:.2e}, "
+              f"max |grad| {np.abs(o).max():.2e}", flush=True)
         assert err <= tol, err
+        assert cell.max() <= tol, cell.max()
 
 
 def _accuracy_case(n):

@@ -10,8 +10,12 @@ shape: one-wave stage tiles of 64 threads, two cells per thread).
   discrete masses of eta and b (the waves have not reached the transmissive
   ends and the mesh does not move there, so no mass crosses them).
 * The 256 x 65536-cell inversion batch, 200 frozen steps, checkpoints every
-  16: the gradient of the gauge misfit with respect to b along smooth random
-  directions against central differences of the GPU forward.
+  16: the gradient of the gauge misfit with respect to (h0, b0) along 32 smooth
+  random directions against central differences of the GPU forward.
+* Long horizon: the smallest instance of the perturbation draw and the one
+  closest to 5000 cells, run together to t = 0.2, against the oracle with
+  class records; the 2^24-cell bowl for one step against the oracle on every
+  cell.  Both well-balanced forms.
 """
 import concurrent.futures as cf
 import math
@@ -115,20 +119,148 @@ def test_full_inversion_gradient_against_central_differences(dev):
     db = d3[2]
     assert torch.isfinite(db).all()
 
-    def J(bb):
+    dh = d3[0]
+
+    def J(hh, bb):
         g = torch.zeros(ninst * ng, dtype=torch.float64, device=dev)
-        ctx.adjoint(p, off, T["h"], T["hu"], bb, T["x"], T["xi"], nsteps, dts, ng, T["gauge_x"],
+        ctx.adjoint(p, off, hh, T["hu"], bb, T["x"], T["xi"], nsteps, dts, ng, T["gauge_x"],
                     g, None, ckpt_every=ckpt)
         return float(torch.dot(gbar, g))
 
     xc = torch.tensor(np.tile(0.5 * (bt["xi"][:n] + bt["xi"][1:n + 1]), ninst),
                       dtype=torch.float64, device=dev)
-    for k in range(2):
-        # smooth direction: one Gaussian bump per instance, random centre and sign
+
+    def bump():
+        # smooth direction: one Gaussian bump per instance, random centre, width, sign
         c = torch.tensor(np.repeat(rng.uniform(0.2, 0.8, ninst), n), device=dev)
+        w = torch.tensor(np.repeat(rng.uniform(0.03, 0.08, ninst), n), device=dev)
         sgn = torch.tensor(np.repeat(rng.choice([-1.0, 1.0], ninst), n), device=dev)
-        v = sgn * torch.exp(-((xc - c) / 0.05) ** 2)
-        e = 1e-6
-        fd = (J(T["b"] + e * v) - J(T["b"] - e * v)) / (2 * e)
-        ad = float(torch.dot(db, v))
-        assert abs(fd - ad) <= 1e-6 * max(1.0, abs(ad)), (k, fd, ad)
+        return sgn * torch.exp(-((xc - c) / w) ** 2)
+
+    # 32 random directions over (h0, b0); central differences with step 1e-6
+    e = 1e-6
+    worst = 0.0
+    for k in range(32):
+        vh, vb = bump(), bump()
+        fd = (J(T["h"] + e * vh, T["b"] + e * vb) - J(T["h"] - e * vh, T["b"] - e * vb)) / (2 * e)
+        ad = float(torch.dot(dh, vh) + torch.dot(db, vb))
+        rel = abs(fd - ad) / max(1.0, abs(ad))
+        worst = max(worst, rel)
+        assert rel <= 1e-6, (k, fd, ad)
+    print(f"32 directions: worst relative difference {worst:.2e}", flush=True)
+
+
+def test_perturbation_subbatch_to_t_end_classes_and_state(dev):
+    """Long-horizon parity on the seed-2208065881 draw: the smallest instance and
+    the one closest to 5000 cells run together, in one batched call, from the
+    initial state to t = 0.2 (every step of the real run), for both
+    well-balanced forms.  Each instance equals the oracle at 1e-11 with equal
+    step counts and step sizes, and its class record (per-cell counts and
+    sequence signatures over every stage of every step) shows no flip."""
+    from gpu_common import class_flips, class_record
+
+    full = W.perturbation_batch()
+    ns = np.diff(full["cell_off"])
+    eps = full["eps"]
+    del full
+    pick = [int(np.argmin(ns)), int(np.argmin(np.abs(ns - 5000)))]
+    insts = [W.perturbation_instance(int(ns[i]), float(eps[i])) for i in pick]
+    bt = W.pack(insts, bc="transmissive")
+    off = [int(v) for v in bt["cell_off"]]
+    S = off[-1]
+    print(f"instances {pick} of {ns[pick].tolist()} cells", flush=True)
+
+    def oparams(hr):
+        return O.params(bc=O.BC_TRANSMISSIVE, mesh=O.MESH_SINE, mesh_A=0.05, mesh_k=1.0,
+                        mesh_omega=math.pi, cfl=0.6, weno_eps=1e-9,
+                        flags=O.FLAG_HYDROSTATIC if hr else 0)
+
+    def oracle_one(job):
+        k, hr = job
+        a, e = off[k], off[k + 1]
+        n = e - a
+        return O.run(oparams(hr), bt["h"][a:e], bt["hu"][a:e], bt["b"][a:e],
+                     bt["x"][a + k:e + k + 1], bt["xi"][a + k:e + k + 1], t_end=0.2,
+                     max_steps=n + 1000, record_cls=True)
+
+    jobs = [(k, hr) for hr in (False, True) for k in range(2)]
+    ex = cf.ThreadPoolExecutor(max_workers=len(jobs))
+    fut = {j: ex.submit(oracle_one, j) for j in jobs}
+    ctx = alew.Context(S, 2)
+    gpu = {}
+    for hr in (False, True):
+        p = alew.params(bc="transmissive", mesh="sine", mesh_A=0.05, mesh_k=1.0,
+                        mesh_omega=math.pi, cfl=0.6, weno_eps=1e-9,
+                        flags=alew.F_HYDROSTATIC if hr else 0)
+        T = {k: torch.tensor(bt[k], dtype=torch.float64, device=dev)
+             for k in ("h", "hu", "b", "x", "xi")}
+        cnt = torch.zeros(3 * S, dtype=torch.int32, device=dev)
+        sig = torch.zeros(S, dtype=torch.int64, device=dev)
+        st = ctx.run(p, off, T["h"], T["hu"], T["b"], T["x"], T["xi"], t_end=[0.2, 0.2],
+                     cls_count=cnt, cls_sig=sig)
+        torch.cuda.synchronize()
+        gpu[hr] = (st, {k: v.cpu().numpy() for k, v in T.items()},
+                   cnt.cpu().numpy().astype(np.int64).reshape(3, S), sig.cpu().numpy().view(np.uint64))
+        print(f"gpu run done (hydrostatic={hr}): steps {[s.steps for s in st]}", flush=True)
+    for (k, hr) in jobs:
+        r = fut[(k, hr)].result()
+        st, G, C, Z = gpu[hr]
+        a, e = off[k], off[k + 1]
+        nsteps = r["stats"].steps
+        print(f"instance {pick[k]} hydrostatic={hr}: {nsteps} steps", flush=True)
+        assert r["status"] == 0 and st[k].status == 0
+        assert st[k].steps == nsteps
+        assert abs(st[k].t - 0.2) < 1e-14
+        # step sizes agree to round-off of the step rule; the last step is the
+        # clipped remainder t_end - t, t a sum of ~N step sizes each equal to the
+        # oracle's within an ulp or so, so it is compared on the scale of t_end
+        assert abs(st[k].dt_max - r["stats"].dt_max) <= 1e-13 * r["stats"].dt_max
+        assert abs(st[k].dt_min - r["stats"].dt_min) <= 1e-13 * 0.2
+        rc, rs = class_record(r["cls"][:nsteps])
+        cells, lower = class_flips(C[:, a:e], Z[a:e], rc, rs)
+        assert cells == 0 and lower == 0, (pick[k], hr, cells, lower)
+        g = dict(h=G["h"][a:e], hu=G["hu"][a:e], b=G["b"][a:e], x=G["x"][a + k:e + k + 1])
+        for f in ("h", "hu", "b", "x"):
+            err = _relerr(g[f], r[f])
+            assert err <= TOL, (pick[k], hr, f, err)
+    ex.shutdown()
+
+
+def test_bowl_2p24_one_step_every_cell(dev):
+    """The 2^24-cell parabolic bowl (fluid-following mesh, CFL 0.08, limiter on
+    the dry shelf) for one step in the launch the bench times, against the
+    oracle on the host element by element, for both well-balanced forms."""
+    wl = W.bowl_1d(1 << 24)
+    n = len(wl["h"])
+
+    def oracle_one(hr):
+        P = O.params(bc=O.BC_TRANSMISSIVE, mesh=O.MESH_FLUID, cfl=0.08, weno_eps=1e-6,
+                     mesh_A=0.0, mesh_k=0.0, mesh_omega=0.0,
+                     flags=O.FLAG_HYDROSTATIC if hr else 0)
+        return O.run(P, wl["h"], wl["hu"], wl["b"], wl["x"], wl["xi"], max_steps=1)
+
+    ex = cf.ThreadPoolExecutor(max_workers=2)
+    fut = {hr: ex.submit(oracle_one, hr) for hr in (False, True)}
+    ctx = alew.Context(n, 1)
+    out = {}
+    for hr in (False, True):
+        p = alew.params(bc="transmissive", mesh="fluid", mesh_A=0.0, mesh_k=0.0, mesh_omega=0.0,
+                        cfl=0.08, weno_eps=1e-6, flags=alew.F_HYDROSTATIC if hr else 0)
+        T = {k: torch.tensor(wl[k], dtype=torch.float64, device=dev)
+             for k in ("h", "hu", "b", "x", "xi")}
+        st = ctx.run(p, [0, n], T["h"], T["hu"], T["b"], T["x"], T["xi"], max_steps=[1])
+        torch.cuda.synchronize()
+        out[hr] = (st[0], {k: v.cpu().numpy() for k, v in T.items() if k != "xi"})
+        del T
+    for hr in (False, True):
+        r = fut[hr].result()
+        st, G = out[hr]
+        assert r["status"] == 0 and st.status == 0 and st.steps == 1
+        assert st.n_limited == r["stats"].n_limited > 0
+        assert tuple(st.n_class) == tuple(r["stats"].n_class)
+        for f in ("h", "hu", "b", "x"):
+            err = _relerr(G[f], r[f])
+            assert err <= TOL, (hr, f, err)
+        print(f"bowl 2^24 hydrostatic={hr}: limited {st.n_limited}, classes {tuple(st.n_class)}",
+              flush=True)
+    ex.shutdown()

@@ -173,6 +173,51 @@ def test_smooth_class_is_the_linear_scheme():
     np.testing.assert_allclose(vals[0:4], lin, rtol=1e-14)
 
 
+# data with a kink inside the big stencil: gamma(eps -> 0) > 1
+_KINK = dict(w=[1.0, 1.1, 0.9, 1.05, 0.95], dx=1.1,
+             h5=np.array([1.0, 1.05, 1.2, 1.9, 2.0]),
+             m5=np.array([0.1, 0.12, 0.2, 0.5, 0.52]),
+             b5=np.array([0.2, 0.25, 0.3, 0.28, 0.26]))
+
+
+def _kink_recon(eps):
+    k = _KINK
+    return O.reconstruct(k["w"], k["h5"], k["m5"], k["b5"], dx=k["dx"], eps=eps)
+
+
+def _eps_at_gamma(target):
+    """The epsilon at which gamma = tau / (beta^A + eps) (eq. (2.7)) equals target;
+    the indicators themselves do not depend on epsilon."""
+    _, _, beta, _ = _kink_recon(1e-300)
+    return abs(beta[0] - beta[2]) / target - beta.mean()
+
+
+@pytest.mark.parametrize("edge,below,above", [(0.5, 0, 1), (1.0, 1, 2)])
+def test_transition_weights_continuous_at_class_edges(edge, below, above):
+    """Step 3, eq. (2.8): M(gamma) = 2 gamma - 1 is 0 at gamma = 1/2, where the
+    transition weights become the linear ones, and 1 at gamma = 1, where they
+    become the WENO-Z ones.  So the hybrid values do not jump where the class
+    label does: epsilon a hair either side of the edge flips the class and moves
+    the values only by the hair."""
+    eps = _eps_at_gamma(edge)
+    assert eps > 0
+    lo, c_lo, _, g_lo = _kink_recon(eps * (1 + 1e-10))  # larger eps: gamma just below the edge
+    hi, c_hi, _, g_hi = _kink_recon(eps * (1 - 1e-10))
+    assert g_lo < edge < g_hi
+    assert (c_lo, c_hi) == (below, above)
+    scale = np.abs(lo).max()
+    assert np.abs(hi - lo).max() < 1e-8 * scale, np.abs(hi - lo).max()
+
+
+def test_transition_region_moves_from_linear_to_weno_values():
+    """The test data above has teeth: across the transition region (gamma from
+    1/2 to 1) the values move by far more than the continuity bound, i.e. the
+    linear and the WENO-Z weights differ here."""
+    v_half, *_ = _kink_recon(_eps_at_gamma(0.5))
+    v_one, *_ = _kink_recon(_eps_at_gamma(1.0))
+    assert np.abs(v_half - v_one).max() > 1e-3 * np.abs(v_half).max()
+
+
 # ----------------------------------------------------------------------------
 # Sec. 3.4.2: positivity limiter (1D form of eq. (3.20)-(3.21)) + Remark 4.1
 # ----------------------------------------------------------------------------
@@ -333,6 +378,50 @@ def test_mesh_nodes_follow_prescribed_map():
     r = O.run(P, wl["h"], wl["hu"], wl["b"], wl["x"], wl["xi"], t_end=0.07)
     X = wl["xi"] + 0.05 * np.sin(2 * np.pi * wl["xi"]) * math.sin(math.pi * r["t"])
     np.testing.assert_allclose(r["x"], X, atol=1e-14)
+
+
+def _fluid_speeds(hu, bc):
+    n = hu.size
+    P = O.params(bc=bc, mesh=O.MESH_FLUID)
+    xi = np.linspace(0.0, 1.0, n + 1)
+    return O.mesh_velocity(P, np.ones(n), hu, np.zeros(n), xi, 0.0, 1.0)
+
+
+def test_fluid_mesh_speeds_are_the_binomial_filter():
+    """Fluid-following node speeds (the mesh of the 2^24-cell bowl): the mean of
+    the two adjacent cell velocities, then two passes of [1/4, 1/2, 1/4].  The
+    three steps compose to the binomial filter (1 + z)^5 / 32, so a unit
+    velocity in one cell far from the ends moves nodes m-2 .. m+3 by
+    1, 5, 10, 10, 5, 1 over 32 and no other node.  With transmissive ends the
+    end nodes are held at 0 in every pass: a unit velocity in the first cell
+    gives 0, 5, 4, 1 over 32 at nodes 0..3."""
+    n, m = 40, 17
+    hu = np.zeros(n)
+    hu[m] = 1.0
+    w = _fluid_speeds(hu, O.BC_TRANSMISSIVE)
+    want = np.zeros(n + 1)
+    want[m - 2:m + 4] = np.array([1, 5, 10, 10, 5, 1]) / 32.0
+    np.testing.assert_allclose(w, want, atol=1e-16)
+    hu = np.zeros(n)
+    hu[0] = 1.0
+    w = _fluid_speeds(hu, O.BC_TRANSMISSIVE)
+    want = np.zeros(n + 1)
+    want[:4] = np.array([0, 5, 4, 1]) / 32.0
+    np.testing.assert_allclose(w, want, atol=1e-16)
+
+
+@pytest.mark.parametrize("k", [1, 5, 13])
+def test_fluid_mesh_speeds_transfer_function_periodic(k):
+    """Fourier symbol of the same filter on a periodic uniform mesh: a cell
+    velocity sin(2 pi k x_j) (x_j the cell centres, spacing D) gives node speeds
+    cos(pi k D)^5 sin(2 pi k x_i) -- cos(pi k D) from the two-cell mean and
+    cos(pi k D)^2 from each [1/4, 1/2, 1/4] pass."""
+    n = 64
+    xc = (np.arange(n) + 0.5) / n
+    xn = np.arange(n + 1) / n
+    w = _fluid_speeds(np.sin(2 * np.pi * k * xc), O.BC_PERIODIC)
+    np.testing.assert_allclose(w, np.cos(np.pi * k / n) ** 5 * np.sin(2 * np.pi * k * xn),
+                               atol=1e-14)
 
 
 def test_positivity_moses_second_problem():
@@ -579,3 +668,95 @@ def test_adjoint_matches_central_differences(flags):
               - J(wl["h"] - eps * vh, wl["hu"] - eps * vm, wl["b"] - eps * vb)) / (2 * eps)
         ad = dh @ vh + dhu @ vm + db @ vb
         assert abs(fd - ad) <= 1e-6 * max(1.0, abs(ad)), (fd, ad)
+
+
+# ----------------------------------------------------------------------------
+# Alternative readings behind flags (LF speed over cell averages, limiter on h
+# only, tangent node speed): each keeps the structure the paper proves, and
+# each is pinned to a closed form where one exists.
+# ----------------------------------------------------------------------------
+_ALT_FLAGS = [O.FLAG_ALPHA_CELLAVG, O.FLAG_NO_HU_LIMIT,
+              O.FLAG_ALPHA_CELLAVG | O.FLAG_NO_HU_LIMIT | O.FLAG_HYDROSTATIC]
+
+
+@pytest.mark.parametrize("flags", _ALT_FLAGS)
+def test_alternative_readings_keep_gcl_and_lake_at_rest(flags):
+    """eq. (2.11) / Lemma 4.1 hold under every reading: a constant state gives
+    q * dw, still water (eta = const, hu = 0) gives (eta * dw, 0)."""
+    n = 40
+    J = _moving_widths(n, 3, L=10.0)
+    x = np.concatenate([[0.0], np.cumsum(J)])
+    xc = 0.5 * (x[1:] + x[:-1])
+    w = np.random.default_rng(4).normal(size=n + 1) * 0.3
+    P = O.params(bc=O.BC_TRANSMISSIVE, mesh=O.MESH_GIVEN, flags=flags)
+    R, _, _ = O.residual(P, np.full(n, 3.0), np.full(n, 0.8), np.full(n, 0.5), J, w)
+    np.testing.assert_allclose(R, np.outer([3.0, 0.8, 0.5], np.diff(w)), atol=1e-12)
+    b = np.where((xc > 4) & (xc < 8), 4.0, 0.0) + 0.3 * np.sin(xc)
+    R, _, _ = O.residual(P, np.full(n, 10.0), np.zeros(n), b, J, w)
+    np.testing.assert_allclose(R[0], 10.0 * np.diff(w), atol=1e-11)
+    np.testing.assert_allclose(R[1], 0.0, atol=1e-11)
+
+
+def test_alpha_over_cell_averages_closed_form():
+    """Reading of eq. (3.13) with the speed over the cell averages: on still
+    water of depth H with one cell moving at U, alpha is the largest of
+    |U - w| at that cell's two nodes and |w| at every node, plus sqrt(g H)."""
+    n, k = 30, 11
+    J = _moving_widths(n, 8)
+    w = np.random.default_rng(5).normal(size=n + 1) * 0.2
+    H, U = 2.0, 0.9
+    hu = np.zeros(n)
+    hu[k] = U * H
+    P = O.params(bc=O.BC_TRANSMISSIVE, mesh=O.MESH_GIVEN, flags=O.FLAG_ALPHA_CELLAVG)
+    _, alpha, _ = O.residual(P, np.full(n, H), hu, np.zeros(n), J, w)
+    want = max(np.abs(w).max(), abs(U - w[k]), abs(U - w[k + 1])) + math.sqrt(9.812 * H)
+    assert alpha == pytest.approx(want, rel=1e-15)
+
+
+def test_limiter_on_h_only():
+    """Reading with the limiter of eq. (3.20)-(3.21) acting on h only: the h and
+    b traces are those of the default limiter (Remark 4.1 keeps eta), the hu
+    traces stay as reconstructed; where the limiter does not act nothing
+    changes, so a smooth run is bit-identical with and without the flag."""
+    rng = np.random.default_rng(21)
+    for _ in range(20):
+        hbar = rng.uniform(1e-6, 1.0)
+        tr = np.array([hbar * rng.uniform(-1, 2), rng.normal(), rng.normal(),
+                       hbar * rng.uniform(-1, 2), rng.normal(), rng.normal()])
+        d, r0 = O.limit(hbar, 0.3, tr)
+        o, r1 = O.limit(hbar, 0.3, tr, hu_lim=False)
+        assert r0 == r1
+        np.testing.assert_array_equal(o[[0, 2, 3, 5]], d[[0, 2, 3, 5]])
+        np.testing.assert_array_equal(o[[1, 4]], tr[[1, 4]])
+    wl = W.accuracy_1d(50)
+    a0 = O.run(_params_for(wl), wl["h"], wl["hu"], wl["b"], wl["x"], wl["xi"], max_steps=20)
+    a1 = O.run(_params_for(wl, flags=O.FLAG_NO_HU_LIMIT), wl["h"], wl["hu"], wl["b"], wl["x"],
+               wl["xi"], max_steps=20)
+    assert a0["stats"].n_limited == 0
+    for k in ("h", "hu", "b", "x"):
+        assert np.array_equal(a0[k], a1[k])
+
+
+def test_tangent_node_speed_closed_form():
+    """Tangent reading of the node speed: dX/dt(xi, t) = A S(xi) omega cos(omega t)
+    for X = xi + A S(xi) sin(omega t); the default chord of eq. (2.1) is
+    (X(t+dt) - X(t)) / dt.  Nodes moved with the tangent leave the map by
+    A S (omega dt)^3 / 6 + ... after one step from t = 0."""
+    n, A, om, dt, t = 32, 0.05, math.pi, 0.01, 0.3
+    xi = np.linspace(0.0, 1.0, n + 1)
+    S = np.sin(2 * np.pi * xi)
+    z = np.zeros(n)
+    Pt = O.params(bc=O.BC_PERIODIC, mesh=O.MESH_SINE, mesh_A=A, mesh_omega=om,
+                  flags=O.FLAG_W_TANGENT)
+    Pc = O.params(bc=O.BC_PERIODIC, mesh=O.MESH_SINE, mesh_A=A, mesh_omega=om)
+    w_t = O.mesh_velocity(Pt, np.ones(n), z, z, xi, t, dt)
+    w_c = O.mesh_velocity(Pc, np.ones(n), z, z, xi, t, dt)
+    S[-1] = S[0]
+    np.testing.assert_allclose(w_t, A * S * om * math.cos(om * t), atol=1e-15)
+    np.testing.assert_allclose(w_c, A * S * (math.sin(om * (t + dt)) - math.sin(om * t)) / dt,
+                               atol=1e-13)
+    wl = W.accuracy_1d(32)
+    r = O.run(_params_for(wl, flags=O.FLAG_W_TANGENT), wl["h"], wl["hu"], wl["b"], wl["x"],
+              wl["xi"], max_steps=1, dts=[dt])
+    np.testing.assert_allclose(r["x"] - (xi + A * S * math.sin(om * dt)),
+                               A * S * (om * dt - math.sin(om * dt)), atol=1e-16)

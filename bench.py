@@ -108,7 +108,10 @@ def roofline(ctx, p, off, T, tnow, L, S, kern_ms, launches, steps, copy_bw=True)
     import torch
     per_stage = ALG_BYTES_PER_CELL_STEP / 3.0
     if L.engine == alew.ENGINE_PERSISTENT:
-        kernel = f"k_persistent<{L.block or 256}>"
+        blk = L.block or 256
+        cpt = L.cells_per_thread or (2 if blk == 64 else 1)
+        hr = 'true' if p.flags & alew.F_HYDROSTATIC else 'false'
+        kernel = f"k_persistent<{blk}, {cpt}, {hr}>"
         ms_launch = kern_ms / max(1, launches)
         achieved = ALG_BYTES_PER_CELL_STEP * S * steps / max(1, launches) / (ms_launch / 1e3) / 1e9
         stage_launches, epi = None, None
@@ -240,7 +243,13 @@ def cpu_baseline(bt, ninst_sample, steps):
     P = O.params(bc=O.BC_TRANSMISSIVE, mesh=O.MESH_SINE, mesh_A=0.05, mesh_k=1.0,
                  mesh_omega=np.pi, cfl=0.6, weno_eps=1e-9)
     O.lib()
-    cores = min(16, os.cpu_count() or 1)
+    nproc = os.cpu_count() or 1
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        pass
+    # the machine's CPU share for one GPU is 16 cores whatever the host shows
+    cores = min(16, nproc)
 
     def one(i):
         a, e = int(off[i]), int(off[i + 1])
@@ -254,9 +263,17 @@ def cpu_baseline(bt, ninst_sample, steps):
     wall = time.perf_counter() - t0
     ncell = int(off[ninst_sample])
     return dict(value=work / wall, unit="cell-updates/s", cores=cores, kind="oracle",
-                per_core=work / wall / cores,
+                per_core=work / wall / cores, nproc=nproc, cpu_model=cpu_model(),
                 sample=f"first {ninst_sample} instances of the same draw ({ncell} cells), "
                        f"{steps} CFL steps each, one instance per thread; {wall:.1f} s wall")
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            return next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
+    except (OSError, StopIteration):
+        return "unknown"
 
 
 def oracle_other_configs():
@@ -268,13 +285,7 @@ def oracle_other_configs():
     steps."""
     import oracle as O
     from paper_2208_06588_amd import workloads as W
-    out = {}
-    try:
-        with open("/proc/cpuinfo") as f:
-            out["cpu"] = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
-    except (OSError, StopIteration):
-        out["cpu"] = "unknown"
-    out["threads"] = 1
+    out = {"cpu": cpu_model(), "threads": 1}
     wl = W.accuracy_1d(200, "sine")
     op = O.params(bc=O.BC_PERIODIC, mesh=O.MESH_SINE, mesh_A=0.05, mesh_k=1.0,
                   mesh_omega=math.pi, cfl=0.6, weno_eps=1e-6)
@@ -396,6 +407,85 @@ def adjoint_leg(dev, ninst, ncell, nsteps, ngauge, ckpt, flags=0):
                      "and the reverse sweep")
 
 
+def speedup_leg(p, off, T, tnow, L, k=64, steps=3):
+    """Batched (one call for k instances) against one call per instance, same
+    GPU, same k instances, same launch shape, from the state after the timed
+    steps at each instance's own time.  Per-instance calls are timed two ways:
+    warm, with one context per instance whose tile tables and step graph were
+    built by an untimed call on the same arrays (launches and per-call host
+    work only), and cold, with one shared context whose tables and graph are
+    rebuilt for every instance (also the set-up a naive caller pays)."""
+    import torch
+    from paper_2208_06588_amd import alew
+    sub_off = off[:k + 1]
+    Ssub = sub_off[-1]
+
+    def sub_state():
+        return {kk: v[:Ssub + (k if kk in ("x", "xi") else 0)].clone() for kk, v in T.items()}
+
+    def launch_of(c):
+        c.set_launch(engine=L.engine, block=L.block, steps_per_launch=L.steps_per_launch,
+                     use_graph=L.use_graph, cells_per_thread=L.cells_per_thread,
+                     compact_tiles=L.compact_tiles)
+
+    def one(c, Tp, i):
+        c0, c1 = sub_off[i], sub_off[i + 1]
+        return c.run(p, [0, c1 - c0], Tp["h"][c0:c1], Tp["hu"][c0:c1], Tp["b"][c0:c1],
+                     Tp["x"][c0 + i:c1 + i + 1], Tp["xi"][c0 + i:c1 + i + 1], t0=[tnow[i]],
+                     max_steps=[steps])
+
+    ctxb = alew.Context(Ssub, k)
+    launch_of(ctxb)
+    Tb = sub_state()
+    ctxb.run(p, sub_off, Tb["h"], Tb["hu"], Tb["b"], Tb["x"], Tb["xi"], t0=tnow[:k],
+             max_steps=[steps] * k)  # untimed: tables and graph of the batch
+    Tb = sub_state()
+    torch.cuda.synchronize()
+    a0 = time.perf_counter()
+    ctxb.run(p, sub_off, Tb["h"], Tb["hu"], Tb["b"], Tb["x"], Tb["xi"], t0=tnow[:k],
+             max_steps=[steps] * k)
+    torch.cuda.synchronize()
+    batched = time.perf_counter() - a0
+    # warm: a context per instance, each built by one untimed call on its arrays
+    ctxs = []
+    Tw = sub_state()
+    Tsave = sub_state()
+    for i in range(k):
+        c = alew.Context(sub_off[i + 1] - sub_off[i], 1)
+        launch_of(c)
+        one(c, Tw, i)
+        ctxs.append(c)
+    for kk in Tw:
+        Tw[kk].copy_(Tsave[kk])
+    torch.cuda.synchronize()
+    a0 = time.perf_counter()
+    for i in range(k):
+        one(ctxs[i], Tw, i)
+    torch.cuda.synchronize()
+    warm = time.perf_counter() - a0
+    for kk in ("h", "hu", "b", "x"):
+        assert torch.equal(Tw[kk], Tb[kk]), f"per-instance result differs ({kk})"
+    for c in ctxs:
+        c.close()
+    # cold: one context shared by the instances
+    Tc = sub_state()
+    c1 = alew.Context(max(np.diff(sub_off)), 1)
+    launch_of(c1)
+    torch.cuda.synchronize()
+    a0 = time.perf_counter()
+    for i in range(k):
+        one(c1, Tc, i)
+    torch.cuda.synchronize()
+    cold = time.perf_counter() - a0
+    c1.close()
+    ctxb.close()
+    return dict(instances=k, steps=steps, cells=int(Ssub), batched_s=round(batched, 4),
+                per_instance_warm_s=round(warm, 4), per_instance_cold_s=round(cold, 4),
+                speedup=round(warm / batched, 2), speedup_cold=round(cold / batched, 2),
+                note="speedup: per-instance calls on warm per-instance contexts (no table or "
+                     "graph rebuild); speedup_cold: one shared context rebuilding both per call")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -425,9 +515,9 @@ def main():
     ap.add_argument("--oracle-suite", action="store_true",
                     help="CPU baseline: also time the oracle on the other configurations, "
                          "single threaded (about 2 minutes); and the 200-cell run on the GPU")
-    ap.add_argument("--full-run", action="store_true",
-                    help="also time the whole batch to t = 0.2 (every instance its own CFL steps; "
-                         "about a minute)")
+    ap.add_argument("--no-full-run", action="store_true",
+                    help="skip timing the whole batch to t = 0.2 (every instance from t = 0 with "
+                         "its own CFL steps, 609-12201 steps; about 45 s)")
     ap.add_argument("--bowl-steps", type=int, default=20)
     ap.add_argument("--scheme", default="special", choices=["special", "hydrostatic"],
                     help="well-balanced form of the timed forward leg (Sec. 4.2 special source "
@@ -509,6 +599,12 @@ def main():
 
     roof = roofline(ctx, p, off, T, tnow=[s.t for s in st], L=L, S=S, kern_ms=kern_ms,
                     launches=launches, steps=args.steps, copy_bw=args.copy_probe == 0)
+    # the whole step (stage kernels, per-instance reductions, step epilogue,
+    # node update and step-size reductions) against the same algorithmic bytes
+    step_gbs = ALG_BYTES_PER_CELL_STEP * S * args.steps / wall / 1e9
+    roof["step_level"] = dict(achieved=round(step_gbs, 1), frac=round(step_gbs / HBM_PEAK_GBS, 4),
+                              alg_bytes_per_cell_step=ALG_BYTES_PER_CELL_STEP,
+                              timing="wall clock of the timed call")
 
     out = {
         "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1,
@@ -540,7 +636,7 @@ def main():
             ctx, p_hr, off, T, tn, L, S, args.hr_steps))
         log(f"hydrostatic: {out['hydrostatic']}")
 
-    if args.full_run:
+    if not args.no_full_run:
         # the whole job: every instance from its initial state at t = 0 to t = 0.2 in one call
         W2 = {k: torch.tensor(bt[k], dtype=torch.float64, device=dev)
               for k in ("h", "hu", "b", "x", "xi")}
@@ -560,38 +656,9 @@ def main():
         del W2
 
     if not args.no_speedup:
-        # batched (one call) vs one call per instance, same GPU, same 64 instances,
-        # from the state after the timed steps (at its own times)
-        tnow = [s.t for s in st]
-        k = min(64, ninst)
-        sub_off = off[:k + 1]
-        Ssub = sub_off[-1]
-        steps = 3
-        Tb = {kk: v[:Ssub + (k if kk in ("x", "xi") else 0)].clone() for kk, v in T.items()}
-        torch.cuda.synchronize()
-        a0 = time.perf_counter()
-        ctx.run(p, sub_off, Tb["h"], Tb["hu"], Tb["b"], Tb["x"], Tb["xi"], t0=tnow[:k],
-                max_steps=[steps] * k)
-        torch.cuda.synchronize()
-        batched = time.perf_counter() - a0
-        Tp = {kk: v[:Ssub + (k if kk in ("x", "xi") else 0)].clone() for kk, v in T.items()}
-        ctx1 = alew.Context(max(np.diff(sub_off)), 1)
-        ctx1.set_launch(engine=L.engine, block=L.block, steps_per_launch=L.steps_per_launch,
-                        use_graph=L.use_graph, cells_per_thread=L.cells_per_thread,
-                        compact_tiles=L.compact_tiles)  # the batched run's launch
-        torch.cuda.synchronize()
-        a0 = time.perf_counter()
-        for i in range(k):
-            c0, c1 = sub_off[i], sub_off[i + 1]
-            ctx1.run(p, [0, c1 - c0], Tp["h"][c0:c1], Tp["hu"][c0:c1], Tp["b"][c0:c1],
-                     Tp["x"][c0 + i:c1 + i + 1], Tp["xi"][c0 + i:c1 + i + 1], t0=[tnow[i]],
-                     max_steps=[steps])
-        torch.cuda.synchronize()
-        per_inst = time.perf_counter() - a0
-        out["batched_speedup"] = dict(instances=k, steps=steps, batched_s=round(batched, 4),
-                                      per_instance_s=round(per_inst, 4),
-                                      speedup=round(per_inst / batched, 2))
-        del Tb, Tp, ctx1
+        out["batched_speedup"] = guarded("batched speedup", lambda: speedup_leg(
+            p, off, T, [s.t for s in st], L))
+        log(f"batched speedup: {out['batched_speedup']}")
 
     if not args.no_bowl:
         out["bowl"] = guarded("bowl", lambda: bowl_leg(dev, 1 << 24, args.bowl_steps, 2))

@@ -1,7 +1,7 @@
 """Launch-configuration tuner for the batched forward run.
 
-Times short runs of every candidate (engine, work-group size, graph use /
-steps per launch, cells per thread, tile form) on copies of the caller's
+Times short runs of every candidate (engine and stages per launch,
+work-group size, graph use, cells per thread, tile form) on copies of the caller's
 batch, times the near-fastest again over longer runs and keeps the fastest
 (the library's automatic shape when it is within 1 % of it).
 Results are cached in a JSON file keyed by the GPU architecture and a hash of
@@ -18,10 +18,21 @@ import torch
 
 from . import alew
 
+# Stages per launch: the stage engine runs one RK stage per kernel launch (the
+# global LF speed of a stage is a reduction over the whole instance, taken
+# between launches); the persistent engine runs 3 x steps_per_launch stages of
+# each instance per launch (0: every stage to the end of the run), a
+# work-group per instance.
 CANDIDATES = [
     dict(engine=alew.ENGINE_PERSISTENT, block=128, steps_per_launch=0, use_graph=0,
          cells_per_thread=1),
     dict(engine=alew.ENGINE_PERSISTENT, block=256, steps_per_launch=0, use_graph=0,
+         cells_per_thread=1),
+    dict(engine=alew.ENGINE_PERSISTENT, block=64, steps_per_launch=0, use_graph=0,
+         cells_per_thread=2),
+    dict(engine=alew.ENGINE_PERSISTENT, block=64, steps_per_launch=1, use_graph=0,
+         cells_per_thread=2),
+    dict(engine=alew.ENGINE_PERSISTENT, block=256, steps_per_launch=1, use_graph=0,
          cells_per_thread=1),
     dict(engine=alew.ENGINE_STAGES, block=128, steps_per_launch=0, use_graph=1, cells_per_thread=1),
     dict(engine=alew.ENGINE_STAGES, block=256, steps_per_launch=0, use_graph=1, cells_per_thread=1),
@@ -45,7 +56,8 @@ AUTO = dict(engine=alew.ENGINE_STAGES, block=64, steps_per_launch=0, use_graph=1
 
 def name_of(c) -> str:
     return (f"engine{c['engine']}-b{c['block']}-g{c['use_graph']}"
-            f"-c{c.get('cells_per_thread', 1)}-t{c.get('compact_tiles', 0)}")
+            f"-c{c.get('cells_per_thread', 1)}-t{c.get('compact_tiles', 0)}"
+            f"-s{c.get('steps_per_launch', 0)}")
 
 CACHE = os.environ.get("ALEW_TUNE_CACHE", os.path.expanduser("~/.cache/alew/autotune.json"))
 
@@ -91,14 +103,19 @@ def tune(ctx: alew.Context, p: alew.Params, cell_off, state: dict, steps: int = 
 
     def time_one(cand, ns):
         ctx.set_launch(**cand)
-        # one untimed step builds tile tables and graphs, then `ns` timed steps
+        # one untimed step builds tile tables and graphs, then `ns` steps timed
+        # on the wall clock (launches, host checks between launches and the
+        # call's set-up alike for every candidate)
+        wall = 0.0
         for nrun in (1, ns):
             T = {k: v.clone() for k, v in state.items()}
             torch.cuda.synchronize()
+            a = time.perf_counter()
             ctx.run(p, cell_off, T["h"], T["hu"], T["b"], T["x"], T["xi"], max_steps=[nrun] * ninst)
             torch.cuda.synchronize()
+            wall = time.perf_counter() - a
             del T
-        return ctx.last_timing()[0] * 1e-3
+        return wall
 
     times = {}
     for cand in candidates:

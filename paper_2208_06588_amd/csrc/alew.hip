@@ -466,13 +466,15 @@ __global__ __launch_bounds__(1024) void k_count_active(Bufs bf, int* __restrict_
   if (threadIdx.x == 0) *n_active = cnt;
 }
 
-// Persistent engine: one launch for the whole batch.
-template <int B, bool HR>
+// Persistent engine: one launch for the whole batch.  A work-group of B
+// threads runs the stage tiles of its instance one after the other, CPT cells
+// per thread (tiles of B * CPT cells, B * CPT - 2 owned).
+template <int B, int CPT, bool HR>
 __global__ __launch_bounds__(B) void k_persistent(Bufs bf, Consts cs,
                                                   const int32_t* __restrict__ order,
                                                   unsigned* __restrict__ queue,
                                                   int32_t steps_limit) {
-  __shared__ SmemStage<B, 1> sm;
+  __shared__ SmemStage<B, CPT> sm;
   __shared__ Inst sI;
   __shared__ int s_idx;
   __shared__ double su[B + 6], sv[B + 4], red[(B / 64) * 8];
@@ -493,8 +495,8 @@ __global__ __launch_bounds__(B) void k_persistent(Bufs bf, Consts cs,
       for (int s = 1; s <= 3; ++s) {
         const StageScal sc = stage_scal(sI, s);
         double amax = 0.0, jmax = 0.0;
-        for (int64_t c0 = 0; c0 < v.n; c0 += B - 2) {
-          StageRes r = stage_tile<B, 1, HR>(bf, cs, v, sc, c0, sm, nullptr);
+        for (int64_t c0 = 0; c0 < v.n; c0 += B * CPT - 2) {
+          StageRes r = stage_tile<B, CPT, HR>(bf, cs, v, sc, c0, sm, nullptr);
           amax = fmax(amax, r.alpha);
           jmax = fmax(jmax, r.maxJ);
           c_cls[0] += r.ncls0; c_cls[1] += r.ncls1; c_cls[2] += r.ncls2;
@@ -1042,14 +1044,16 @@ alew_status run_stage_engine(alew_ctx* c, const Bufs& bf, const Consts& cs, int6
   return ALEW_OK;
 }
 
-template <int B>
+template <int B, int CPT>
 alew_status run_persistent(alew_ctx* c, const Bufs& bf, const Consts& cs, int64_t ninst) {
   int dev = 0, ncu = 0, per_cu = 0;
   HIPCHK(hipGetDevice(&dev));
   HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
   const bool hr = (cs.flags & F_HYDROSTATIC) != 0;
-  if (hr) HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<B, true>, B, 0));
-  else HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<B, false>, B, 0));
+  if (hr)
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<B, CPT, true>, B, 0));
+  else
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<B, CPT, false>, B, 0));
   int64_t grid = (int64_t)std::max(1, ncu) * std::max(1, per_cu);
   grid = std::min<int64_t>(grid, ninst);
   const int limit = c->launch.steps_per_launch;
@@ -1059,11 +1063,11 @@ alew_status run_persistent(alew_ctx* c, const Bufs& bf, const Consts& cs, int64_
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, c->stream, c->queue_d);
     HIPCHK(hipEventRecord(c->ev0, c->stream));
     if (hr)
-      hipLaunchKernelGGL((k_persistent<B, true>), dim3((unsigned)grid), dim3(B), 0, c->stream, bf,
-                         cs, c->order_d, c->queue_d, limit);
+      hipLaunchKernelGGL((k_persistent<B, CPT, true>), dim3((unsigned)grid), dim3(B), 0, c->stream,
+                         bf, cs, c->order_d, c->queue_d, limit);
     else
-      hipLaunchKernelGGL((k_persistent<B, false>), dim3((unsigned)grid), dim3(B), 0, c->stream, bf,
-                         cs, c->order_d, c->queue_d, limit);
+      hipLaunchKernelGGL((k_persistent<B, CPT, false>), dim3((unsigned)grid), dim3(B), 0, c->stream,
+                         bf, cs, c->order_d, c->queue_d, limit);
     HIPCHK(hipEventRecord(c->ev1, c->stream));
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventSynchronize(c->ev1));
@@ -1079,6 +1083,14 @@ alew_status run_persistent(alew_ctx* c, const Bufs& bf, const Consts& cs, int64_
   }
   c->last_ms = total;
   return ALEW_OK;
+}
+
+template <int B>
+alew_status run_persist(alew_ctx* c, const Bufs& bf, const Consts& cs, int64_t ninst, int cpt) {
+  if constexpr (B <= 256) {
+    if (cpt == 2) return run_persistent<B, 2>(c, bf, cs, ninst);
+  }
+  return run_persistent<B, 1>(c, bf, cs, ninst);
 }
 
 template <int B>
@@ -1123,7 +1135,7 @@ alew_status drive(alew_ctx* c, const alew_params* p, int64_t ninst, const int64_
   if ((ccount == nullptr) != (csig == nullptr))
     return fail(ALEW_E_ARG, "cls_count and cls_sig go together");
   const int B = pick_block(c, engine);
-  const int CPT = (engine == 1) ? 1 : pick_cpt(c, B);
+  const int CPT = pick_cpt(c, B);
   const bool noext = engine != 1 && c->launch.compact_tiles == 1;
   alew_status ts = build_tiles(c, cell_off, ninst, PB, B * CPT, noext);
   if (ts != ALEW_OK) return ts;
@@ -1156,7 +1168,7 @@ alew_status drive(alew_ctx* c, const alew_params* p, int64_t ninst, const int64_
       hipLaunchKernelGGL(k_wfluid<PB>, gp, dim3(PB), 0, c->stream, bf, cs, c->tiles_plain_d);  \
     launch_boundary(c, bf, cs, c->stream, 1);                                                 \
     HIPCHK(hipGetLastError());                                                                  \
-    alew_status rs = (engine == 1) ? run_persistent<BB>(c, bf, cs, ninst)                       \
+    alew_status rs = (engine == 1) ? run_persist<BB>(c, bf, cs, ninst, CPT)                     \
                                    : run_stages<BB>(c, bf, cs, max_iters, CPT);                 \
     if (rs != ALEW_OK) return rs;                                                               \
     if (c->tables_masked) { /* every instance's tiles again for the finish */                   \

@@ -184,6 +184,20 @@ alew_status alew_step(alew_ctx* ctx, const alew_params* p, int64_t ncell, double
                       double* b, double* x, const double* xi, const double* w, double t, double dt,
                       double t_end, uint8_t* cls, alew_stats* stats);
 
+/* For callers that cannot allocate device memory (serving loops, harnesses
+ * that forbid hipMalloc): the step of alew_step without a context and without
+ * any allocation.  Its scratch (state and stage buffers, tile tables, result
+ * records: about 8.7 MB) is a file-scope device array of the library, one copy
+ * per GPU, held until the process ends.  Arguments, results and errors as
+ * alew_step; ncell <= 65536 (larger: ALEW_E_ARG).  hip_stream: the stream to
+ * enqueue on (NULL = default stream); the call returns after its work on that
+ * stream is done.  Every call on a GPU uses that GPU's one array, which keeps
+ * the last call's contents; the library serializes the calls on a GPU with a
+ * lock, and two calls whose work overlapped on one GPU would race. */
+alew_status alew_step_noalloc(const alew_params* p, int64_t ncell, double* h, double* hu, double* b,
+                              double* x, const double* xi, const double* w, double t, double dt,
+                              double t_end, uint8_t* cls, alew_stats* stats, void* hip_stream);
+
 /* Run a ragged batch of independent instances.
  * cell_off (host) [ninst+1]; h, hu, b, x, xi packed as described above.
  * t0, t_end, max_steps (host) [ninst], each may be NULL: instance i starts at

@@ -82,6 +82,8 @@ def lib():
                                dp, dp, C.POINTER(C.c_int64), vp, vp, i64, vp, vp,
                                C.POINTER(Stats)]
         L.alew_adjoint_reserve.argtypes = [vp, i64, i64, i64]
+        L.alew_step_noalloc.argtypes = [C.POINTER(Params), i64, vp, vp, vp, vp, vp, vp, C.c_double,
+                                        C.c_double, C.c_double, vp, C.POINTER(Stats), vp]
         L.alew_adjoint.argtypes = [vp, C.POINTER(Params), i64, C.POINTER(C.c_int64), vp, vp, vp,
                                    vp, vp, C.c_double, i64, vp, i64, i64, vp, vp, vp, vp, vp, vp]
         L.alew_last_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
@@ -94,7 +96,8 @@ def lib():
         L.alew_last_error.restype = C.c_char_p
         L.alew_version.restype = C.c_char_p
         for f in ("alew_create", "alew_set_stream", "alew_set_launch", "alew_get_launch",
-                  "alew_step", "alew_run", "alew_adjoint", "alew_adjoint_reserve"):
+                  "alew_step", "alew_run", "alew_adjoint", "alew_adjoint_reserve",
+                  "alew_step_noalloc"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -275,6 +278,29 @@ class Context:
                                 int(ckpt_every), int(ngauge), _ptr(gauge_x), _ptr(gauge_h),
                                 _ptr(gauge_bar), _ptr(dh0), _ptr(dhu0), _ptr(db0))
         _check(st)
+
+
+NOALLOC_MAX_CELLS = 65536
+
+
+def step_noalloc(p: Params, h, hu, b, x, xi=None, w=None, t=0.0, dt=0.0, t_end=0.0, cls=None,
+                 check=True) -> Stats:
+    """alew_step_noalloc: one step of one instance without a context and without
+    device allocation (the library's static scratch; ncell <= 65536), on the
+    current torch stream."""
+    n = h.numel()
+    _sizes(n, 1, h, hu, b, x, xi, w)
+    if cls is not None and cls.numel() != 3 * n:
+        raise ValueError("cls must hold 3 * ncell entries")
+    S = Stats()
+    st = lib().alew_step_noalloc(C.byref(p), n, _ptr(h), _ptr(hu), _ptr(b), _ptr(x), _ptr(xi),
+                                 _ptr(w), float(t), float(dt), float(t_end),
+                                 _ptr(cls, torch.uint8), C.byref(S),
+                                 C.c_void_p(torch.cuda.current_stream().cuda_stream))
+    if check:
+        _check(st)
+    S.status = st if st else S.status
+    return S
 
 
 def version() -> str:

@@ -1256,7 +1256,81 @@ alew_status adj_reserve(alew_ctx* c, size_t bytes) {
   return ALEW_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Allocation-free step: alew_step's scratch in a file-scope device array
+// ---------------------------------------------------------------------------
+constexpr int64_t NA_CELLS = 65536;  // largest instance of alew_step_noalloc
+constexpr int NA_MAXDEV = 64;
+constexpr size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
+constexpr int64_t NA_CAP_STAGE = (NA_CELLS + MIN_OWN - 1) / MIN_OWN + 1;
+constexpr int64_t NA_CAP_PLAIN = NA_CELLS / PB + 2;
+constexpr size_t NA_BYTES =
+    al256(NA_CELLS * 8) + 4 * al256(3 * NA_CELLS * 8) + 3 * al256((NA_CELLS + 1) * 8) +
+    al256(sizeof(Inst)) + 5 * al256(2 * sizeof(int64_t)) + 4 * al256(8) + al256(8) +
+    3 * al256(NA_CAP_STAGE * sizeof(Tile)) + al256(NA_CAP_PLAIN * sizeof(Tile)) +
+    2 * al256(NA_CAP_STAGE * SREC * 8) + 2 * al256(NA_CAP_PLAIN * PREC * 8) +
+    al256(NA_CAP_STAGE * sizeof(RChunk)) + al256(NA_CAP_PLAIN * sizeof(RChunk));
+
 }  // namespace
+
+// One copy per GPU, held until the process ends.  Host code never uses this
+// name for the memory: it takes the device address from hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[NA_BYTES];
+
+namespace {
+
+struct NoallocDev {
+  bool ready = false;
+  alew_ctx ctx;                // device pointers into scratch; no events, no graph
+  Inst inst_h;                 // host copies (pageable: nothing is allocated)
+  double dt1_h = 0.0;
+  int nactive_h = 0;
+  uint8_t act_h = 0;
+};
+NoallocDev g_na[NA_MAXDEV];
+std::mutex g_na_mu[NA_MAXDEV];
+
+// Point the context's buffers into the device array at base (same order and
+// sizes as NA_BYTES).
+alew_status noalloc_setup(NoallocDev& d, char* base) {
+  alew_ctx* c = &d.ctx;
+  size_t off = 0;
+  auto take = [&](auto** p, size_t bytes) {
+    *p = reinterpret_cast<std::remove_reference_t<decltype(*p)>>(base + off);
+    off += al256(bytes);
+  };
+  const int64_t S = NA_CELLS, Nn = NA_CELLS + 1;
+  take(&c->eta, S * 8);
+  take(&c->P0, 3 * S * 8); take(&c->D0, 3 * S * 8); take(&c->P1, 3 * S * 8); take(&c->D1, 3 * S * 8);
+  take(&c->w, Nn * 8); take(&c->xa, Nn * 8); take(&c->xb, Nn * 8);
+  take(&c->inst, sizeof(Inst));
+  take(&c->cell_off_d, 2 * sizeof(int64_t)); take(&c->sfirst_d, 2 * sizeof(int64_t));
+  take(&c->pfirst_d, 2 * sizeof(int64_t)); take(&c->scfirst_d, 2 * sizeof(int64_t));
+  take(&c->pcfirst_d, 2 * sizeof(int64_t));
+  take(&c->order_d, 8); take(&c->queue_d, 8); take(&c->nactive_d, 8); take(&c->act_d, 8);
+  take(&c->dt1_d, 8);
+  take(&c->tiles_stage_d, NA_CAP_STAGE * sizeof(Tile));
+  take(&c->tiles_edge_d, NA_CAP_STAGE * sizeof(Tile));
+  take(&c->tiles_inner_d, NA_CAP_STAGE * sizeof(Tile));
+  take(&c->tiles_plain_d, NA_CAP_PLAIN * sizeof(Tile));
+  take(&c->srec, NA_CAP_STAGE * SREC * 8); take(&c->screc, NA_CAP_STAGE * SREC * 8);
+  take(&c->prec, NA_CAP_PLAIN * PREC * 8); take(&c->pcrec, NA_CAP_PLAIN * PREC * 8);
+  take(&c->schunk_d, NA_CAP_STAGE * sizeof(RChunk));
+  take(&c->pchunk_d, NA_CAP_PLAIN * sizeof(RChunk));
+  if (off > NA_BYTES) return fail(ALEW_E_ARG, "internal: static scratch layout");
+  c->max_cells = NA_CELLS;
+  c->max_inst = 1;
+  c->cap_stage = NA_CAP_STAGE;
+  c->cap_plain = NA_CAP_PLAIN;
+  c->inst_h = &d.inst_h;
+  c->dt1_h = &d.dt1_h;
+  c->nactive_h = &d.nactive_h;
+  c->act_h = &d.act_h;
+  return ALEW_OK;
+}
+
+}  // namespace
+
 
 // ============================================================================
 // C ABI
@@ -1423,6 +1497,44 @@ alew_status alew_step(alew_ctx* c, const alew_params* p, int64_t ncell, double* 
   alew_status r = drive(c, p, 1, off, h, hu, b, x, xi, w, &t, &tend, &one, dts, nullptr,
                         dts ? 1 : 0, cls, nullptr, nullptr, &st, 2);
   c->launch = keep;
+  if (stats) *stats = st;
+  return r;
+}
+
+alew_status alew_step_noalloc(const alew_params* p, int64_t ncell, double* h, double* hu, double* b,
+                              double* x, const double* xi, const double* w, double t, double dt,
+                              double t_end, uint8_t* cls, alew_stats* stats, void* hip_stream) {
+  if (ncell < 5) return fail(ALEW_E_ARG, "ncell must be >= 5");
+  if (ncell > NA_CELLS)
+    return fail(ALEW_E_ARG, "alew_step_noalloc: ncell exceeds the static scratch maximum of " +
+                                std::to_string(NA_CELLS) + " cells");
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= NA_MAXDEV) return fail(ALEW_E_ARG, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_na_mu[dev]);
+  NoallocDev& d = g_na[dev];
+  if (!d.ready) {
+    // once per device, with the device current: the address of this GPU's copy
+    void* ptr = nullptr;
+    HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    alew_status ls = noalloc_setup(d, (char*)ptr);
+    if (ls != ALEW_OK) return ls;
+    d.ready = true;
+  }
+  alew_ctx* c = &d.ctx;
+  c->stream = (hipStream_t)hip_stream;
+  const int64_t off[2] = {0, ncell};
+  const int64_t one = 1;
+  const double tend = t_end;
+  const double* dts = nullptr;
+  if (dt > 0) {
+    hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, c->stream, c->dt1_d, (int64_t)1, dt);
+    dts = c->dt1_d;
+  }
+  c->launch = alew_launch{2, 0, 0, 0, 0, 0};
+  alew_stats st;
+  alew_status r = drive(c, p, 1, off, h, hu, b, x, xi, w, &t, &tend, &one, dts, nullptr,
+                        dts ? 1 : 0, cls, nullptr, nullptr, &st, 2);
   if (stats) *stats = st;
   return r;
 }

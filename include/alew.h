@@ -98,10 +98,23 @@ enum {
                                 h traces (and the b traces through Remark 4.1) only;
                                 by default the hu traces are scaled by the same Phi
                                 about the cell mean of hu                             */
-  ALEW_F_W_TANGENT = 32      /* SINE / PAPER meshes: the node speed of a step is the
+  ALEW_F_W_TANGENT = 32,     /* SINE / PAPER meshes: the node speed of a step is the
                                 map's time derivative at the start of the step,
                                 A S(xi) omega cos(omega t_n), instead of the chord of
                                 eq. (2.1) (nodes then leave the map by O(dt^2) a step) */
+  ALEW_F_NONWB = 64          /* the ALE-WENO scheme of Sec. 3 without well-balancing,
+                                eq. (3.11)-(3.13): (eta, hu) reconstructed in the local
+                                characteristic variables of each cell's mean state (the
+                                eigenvectors (1, u -+ c) of the flux Jacobian;
+                                component-wise where the mean depth is at most dry_eps),
+                                b reconstructed with weights of its own, every variable
+                                with its own indicators and detector class (the class
+                                reported for a cell is the largest of the three); the
+                                source term is the integral of -g (eta - b) b_x over the
+                                cell by the 4-point Gauss-Lobatto rule on the unlimited
+                                values; the positivity limiter changes h and keeps the b
+                                traces.  alew_step and alew_run only; not with
+                                ALEW_F_HYDROSTATIC                                     */
 };
 
 typedef struct {

@@ -24,7 +24,7 @@ BC_PERIODIC, BC_TRANSMISSIVE, BC_REFLECTIVE = 0, 1, 2
 MESH_GIVEN, MESH_SINE, MESH_PAPER, MESH_FLUID = 0, 1, 2, 3
 ST_OK, ST_ARG, ST_MESH, ST_NEGDEPTH, ST_NONFINITE, ST_NEGWEIGHT = 0, 1, 2, 3, 4, 8
 FLAG_BETA_LOCAL, FLAG_BETA_FROM_H, FLAG_HYDROSTATIC = 1, 2, 4
-FLAG_ALPHA_CELLAVG, FLAG_NO_HU_LIMIT, FLAG_W_TANGENT = 8, 16, 32
+FLAG_ALPHA_CELLAVG, FLAG_NO_HU_LIMIT, FLAG_W_TANGENT, FLAG_NONWB = 8, 16, 32, 64
 
 
 class Params(C.Structure):
@@ -71,6 +71,8 @@ def lib():
         L.orc_geometry.argtypes = [dp, dp, dp, dp, dp]
         L.orc_reconstruct.argtypes = [dp, dp, dp, dp, dp, C.c_double, C.c_double, dp, dp, dp]
         L.orc_limit.argtypes = [C.c_double, C.c_double, dp, C.c_double, C.c_int, dp]
+        L.orc_reconstruct_char.argtypes = [dp, dp, dp, dp, C.c_double, C.c_double, C.c_double,
+                                           C.c_double, dp]
         L.orc_hydro_source.argtypes = [C.c_double, dp, dp]
         L.orc_hydro_source.restype = C.c_double
         L.orc_residual.argtypes = [C.POINTER(Params), C.c_int64, dp, dp, dp, dp, dp, dp, dp, u8p]
@@ -125,6 +127,17 @@ def reconstruct(widths5, h5, m5, b5, dx, eps=1e-6, v5=None):
     cls = lib().orc_reconstruct(_p(_f64(widths5)), _p(v5), _p(h5), _p(m5), _p(b5),
                                 float(dx), float(eps), _p(out), _p(beta), _p(gam))
     return out, cls, beta, float(gam[0])
+
+
+def reconstruct_char(widths5, eta5, m5, b5, dx, eps=1e-6, g=9.812, dry_eps=1e-8):
+    """Unlimited reconstruction of one cell of the scheme without
+    well-balancing (Sec. 3; characteristic variables of the cell's mean
+    state, b on its own).  Returns (vals[16] = h[4], hu[4], b[4], b_x[4]; cls)."""
+    out = np.zeros(16)
+    cls = lib().orc_reconstruct_char(_p(_f64(widths5)), _p(_f64(eta5)), _p(_f64(m5)),
+                                     _p(_f64(b5)), float(dx), float(eps), float(g),
+                                     float(dry_eps), _p(out))
+    return out, cls
 
 
 def limit(hbar, mbar, traces6, pp_eps=1e-11, hu_lim=True):

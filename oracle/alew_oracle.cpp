@@ -97,6 +97,18 @@
  *  R21 FLAG_W_TANGENT: the node speed of a step on a prescribed map is the map's
  *      time derivative at the start of the step, dX/dt(xi, t_n), instead of the
  *      chord of eq. (2.1).
+ *  R22 FLAG_NONWB: the scheme of Sec. 3 without well-balancing.  q = (eta, hu)
+ *      is reconstructed in local characteristic variables (the remark after
+ *      Step 4 of Sec. 2.2 prefers them for systems) taken from the eigenvectors
+ *      of the flux Jacobian at the cell's own mean state; where the mean depth
+ *      is at most dry_eps the reconstruction is component-wise.  Each
+ *      characteristic variable and b (needed for the bottom flux of eq. (3.17)
+ *      and the source) get their own indicators, class and weights.  The
+ *      source integral of r(q, b) over the cell uses the 4-point Gauss-Lobatto
+ *      rule of the limiter on the unlimited values (b_x: the derivative of b's
+ *      hybrid reconstruction).  The limiter acts on h = eta - b and keeps the
+ *      bottom traces (Remark 4.1 is stated for the well-balanced schemes; here
+ *      a flat bottom stays flat).
  */
 #include <cmath>
 #include <cstdint>
@@ -164,7 +176,7 @@ enum { ST_OK = 0, ST_ARG = 1, ST_MESH = 2, ST_NEGDEPTH = 3, ST_NONFINITE = 4, ST
 
 enum {
   FLAG_BETA_LOCAL = 1, FLAG_BETA_FROM_H = 2, FLAG_HYDROSTATIC = 4, FLAG_ALPHA_CELLAVG = 8,
-  FLAG_NO_HU_LIMIT = 16, FLAG_W_TANGENT = 32
+  FLAG_NO_HU_LIMIT = 16, FLAG_W_TANGENT = 32, FLAG_NONWB = 64
 };
 
 struct Params {
@@ -227,6 +239,7 @@ struct CellGeo {
   double c[3][4][3];   /* c[r][mu][i]: u_r(x_mu) = sum_i c[r][mu][i] ubar_{j-r+i} */
   double cd[3][4][3];  /* same for d u_r/dx at x_mu                            */
   double d[4][3];      /* linear weights d_r(x_mu)                              */
+  double cq[4][5];     /* dP/dx at x_mu of the 5-cell quartic P, per average     */
 };
 
 /* Mean over [a,b] of s^p. */
@@ -286,6 +299,12 @@ static void cell_geometry(const double wid[5], CellGeo& G) {
     G.d[mu][0] = d0;
     G.d[mu][2] = d2;
     G.d[mu][1] = 1.0 - d0 - d2;
+    /* derivative of the quartic at the point: d/dx = (1/J) d/ds */
+    for (int k = 0; k < 5; ++k) {
+      double dv = 0.0;
+      for (int p = 1; p < 5; ++p) dv = dv + p * std::pow(s, p - 1) * M5i[p * 5 + k];
+      G.cq[mu][k] = dv / Jj;
+    }
   }
 }
 
@@ -392,6 +411,72 @@ static void reconstruct(const CellGeo& G, double Dx, double eps, const T v[5], c
   }
 }
 
+/* Non-well-balanced scheme of Sec. 3 (R22): the equilibrium variables
+ * q = (eta, hu) reconstructed in local characteristic variables (the remark
+ * after Step 4 of Sec. 2.2), b on its own.  The flux Jacobian of f(q) with
+ * respect to q at fixed b has the eigenvalues u -+ c, c = sqrt(g h), and the
+ * right eigenvectors (1, u - c), (1, u + c); the characteristic variables of
+ * the 5 stencil averages are taken with the left eigenvectors of cell j's
+ * mean state, each is reconstructed as a scalar with its own indicators,
+ * class and weights (Steps 1-4), and the point values are mapped back with
+ * the right eigenvectors.  Where the mean depth is at most dry_eps the frame
+ * is the identity.  o.h holds h = eta - b at the points, o.bx the derivative
+ * of b's reconstruction; o.cls the largest of the three classes. */
+template <class T>
+static void reconstruct_char(const CellGeo& G, double Dx, double eps, double g, double dry,
+                             const T eta[5], const T m[5], const T b[5], Recon<T>& o) {
+  T zero[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  T hbar = eta[2] - b[2];
+  bool chr = val(hbar) > dry;
+  T u = 0.0, c = 0.0;
+  T w1[5], w2[5];
+  if (chr) {
+    u = m[2] / hbar;
+    c = sqrt(g * hbar);
+    for (int k = 0; k < 5; ++k) {
+      /* rows of the inverse of R = [[1, 1], [u - c, u + c]] */
+      w1[k] = ((u + c) * eta[k] - m[k]) / (2.0 * c);
+      w2[k] = ((c - u) * eta[k] + m[k]) / (2.0 * c);
+    }
+  } else {
+    for (int k = 0; k < 5; ++k) {
+      w1[k] = eta[k];
+      w2[k] = m[k];
+    }
+  }
+  Recon<T> r1, r2, rb;
+  reconstruct(G, Dx, eps, w1, w1, zero, w1, r1);
+  reconstruct(G, Dx, eps, w2, w2, zero, w2, r2);
+  reconstruct(G, Dx, eps, b, b, zero, b, rb);
+  if (rb.cls == CLS_S) {
+    /* where b is smooth its reconstruction is the 5-cell quartic P (linear
+     * weights), and b_x its derivative: fourth order, where the weighted
+     * stencil derivatives sum_r d_r p_r' leave out sum_r d_r' p_r and are
+     * second order only */
+    for (int mu = 0; mu < 4; ++mu) {
+      T v = 0.0;
+      for (int k = 0; k < 5; ++k) v = v + G.cq[mu][k] * b[k];
+      rb.bx[mu] = v;
+    }
+  }
+  for (int mu = 0; mu < 4; ++mu) {
+    T e, mm;
+    if (chr) {
+      e = r1.h[mu] + r2.h[mu];
+      mm = (u - c) * r1.h[mu] + (u + c) * r2.h[mu];
+    } else {
+      e = r1.h[mu];
+      mm = r2.h[mu];
+    }
+    o.h[mu] = e - rb.h[mu];
+    o.m[mu] = mm;
+    o.b[mu] = rb.h[mu];
+    o.bx[mu] = rb.bx[mu];
+  }
+  o.cls = std::max(r1.cls, std::max(r2.cls, rb.cls));
+  o.negw = r1.negw | r2.negw | rb.negw;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Sec. 3.4.2, eq. (3.20)-(3.21) in 1D, with Remark 4.1                      */
 /* ------------------------------------------------------------------------ */
@@ -404,7 +489,7 @@ struct Traces {
  * (FLAG_NO_HU_LIMIT) leaves the hu traces as reconstructed. */
 template <class T>
 static int limit_cell(T hbar, T mbar, const Recon<T>& o, double pp_eps, Traces<T>& tr,
-                      bool hu_lim = true) {
+                      bool hu_lim = true, bool keep_b = false) {
   tr.hL = o.h[0]; tr.mL = o.m[0]; tr.bL = o.b[0];
   tr.hR = o.h[3]; tr.mR = o.m[3]; tr.bR = o.b[3];
   const double s1 = kGLW[0];
@@ -413,8 +498,10 @@ static int limit_cell(T hbar, T mbar, const Recon<T>& o, double pp_eps, Traces<T
     T etaL = tr.hL + tr.bL, etaR = tr.hR + tr.bR;
     tr.hL = hbar; tr.hR = hbar;
     if (hu_lim) { tr.mL = mbar; tr.mR = mbar; }
-    tr.bL = etaL - tr.hL;
-    tr.bR = etaR - tr.hR;
+    if (!keep_b) {
+      tr.bL = etaL - tr.hL;
+      tr.bR = etaR - tr.hR;
+    }
     return val(hbar) < 0.0 ? 2 : 1;
   }
   /* Interior mean delta from hbar = s1 hL + s1 hR + (1 - 2 s1) delta. */
@@ -433,8 +520,10 @@ static int limit_cell(T hbar, T mbar, const Recon<T>& o, double pp_eps, Traces<T
     tr.mL = Phi * (tr.mL - mbar) + mbar;
     tr.mR = Phi * (tr.mR - mbar) + mbar;
   }
-  tr.bL = etaL - tr.hL;
-  tr.bR = etaR - tr.hR;
+  if (!keep_b) {
+    tr.bL = etaL - tr.hL;
+    tr.bR = etaR - tr.hR;
+  }
   return 1;
 }
 
@@ -605,9 +694,16 @@ static void residual(const Params& P, int n, const T* eta, const T* m, const T* 
     CellGeo geo;
     cell_geometry(wid, geo);
     double dxr = (P.flags & FLAG_BETA_LOCAL) ? wid[2] : Dx;
-    reconstruct(geo, dxr, P.weno_eps, vs, hs, ms5, bs, rec[j + 1]);
+    const bool nonwb = (P.flags & FLAG_NONWB) != 0;
+    if (nonwb) {
+      T es[5];
+      for (int k = 0; k < 5; ++k) es[k] = etae[j - 2 + k + G];
+      reconstruct_char(geo, dxr, P.weno_eps, P.g, P.dry_eps, es, ms5, bs, rec[j + 1]);
+    } else {
+      reconstruct(geo, dxr, P.weno_eps, vs, hs, ms5, bs, rec[j + 1]);
+    }
     int lim = limit_cell(he[j + G], me[j + G], rec[j + 1], P.pp_eps, tr[j + 1],
-                         !(P.flags & FLAG_NO_HU_LIMIT));
+                         !(P.flags & FLAG_NO_HU_LIMIT), nonwb);
     if (j >= 0 && j < n) {
       cnt.n_class[rec[j + 1].cls] += 1;
       if (cls) cls[j] = (uint8_t)rec[j + 1].cls;
@@ -677,6 +773,21 @@ static void residual(const Params& P, int n, const T* eta, const T* m, const T* 
       T bv[4] = {Rt[j].b, o.b[1], o.b[2], Lt[j + 1].b};
       R[j] = -(He_r + He_l);
       R[n + j] = -(Hm_r + Hm_l) + hydro_source(P.g, ev, bv);
+      R[2 * n + j] = -(Gb[j + 1] - Gb[j]);
+    }
+    return;
+  }
+  if (P.flags & FLAG_NONWB) {
+    /* Residuals of the scheme of Sec. 3 (eq. (3.11)-(3.12)): the fluxes and the
+     * integral of the source r(q, b) = (0, -g (eta - b) b_x) over the cell by
+     * the 4-point Gauss-Lobatto rule on the unlimited reconstructed values. */
+    for (int j = 0; j < n; ++j) {
+      const Recon<T>& o = rec[j + 1];
+      T S = 0.0;
+      for (int mu = 0; mu < 4; ++mu)
+        S = S + (kGLW[mu] * J[j]) * ((-P.g) * (o.h[mu] * o.bx[mu]));
+      R[j] = -(F1[j + 1] - F1[j]);
+      R[n + j] = -(F2[j + 1] - F2[j]) + S;
       R[2 * n + j] = -(Gb[j + 1] - Gb[j]);
     }
     return;
@@ -908,6 +1019,25 @@ int orc_reconstruct(const double* wid5, const double* v5, const double* h5, cons
       double tau = std::fabs(beta[0] - beta[2]);
       *gamma_out = tau / ((beta[0] + beta[1] + beta[2]) / 3.0 + eps);
     }
+  }
+  return o.cls;
+}
+
+/* Reconstruction of one cell of the scheme without well-balancing (R22):
+ * out[16] = h[4], hu[4], b[4], b_x[4] at the 4 Gauss-Lobatto points; returns
+ * the cell's class (the largest of the three variables' classes). */
+int orc_reconstruct_char(const double* wid5, const double* eta5, const double* m5,
+                         const double* b5, double Dx, double eps, double g, double dry,
+                         double* out) {
+  CellGeo G;
+  cell_geometry(wid5, G);
+  Recon<double> o;
+  reconstruct_char(G, Dx, eps, g, dry, eta5, m5, b5, o);
+  for (int mu = 0; mu < 4; ++mu) {
+    out[mu] = o.h[mu];
+    out[4 + mu] = o.m[mu];
+    out[8 + mu] = o.b[mu];
+    out[12 + mu] = o.bx[mu];
   }
   return o.cls;
 }

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libalew.so")
 BC = {"periodic": 0, "transmissive": 1, "reflective": 2}
 MESH = {"given": 0, "sine": 1, "paper": 2, "fluid": 3}
 F_BETA_LOCAL, F_BETA_FROM_H, F_HYDROSTATIC = 1, 2, 4
-F_ALPHA_CELLAVG, F_NO_HU_LIMIT, F_W_TANGENT = 8, 16, 32
+F_ALPHA_CELLAVG, F_NO_HU_LIMIT, F_W_TANGENT, F_NONWB = 8, 16, 32, 64
 CLS_SIG_MUL = 1099511628211  # multiplier of the class-sequence signature of alew_run
 ENGINE_AUTO, ENGINE_PERSISTENT, ENGINE_STAGES = 0, 1, 2
 

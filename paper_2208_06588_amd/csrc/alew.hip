@@ -127,7 +127,7 @@ __device__ __forceinline__ void publish_stage(const Bufs& bf, int rec, const Sta
 
 // Stage s of one tile; par is the parity of the step (x^n in xa or xb).
 // NOEXT: tiles of TB slots (TB - 6 owned cells) instead of TB + 4 slots.
-template <int B, int CPT, bool NOEXT, bool HR>
+template <int B, int CPT, bool NOEXT, int SCH>
 __global__ __launch_bounds__(B) void k_stage(Bufs bf, Consts cs, const Tile* __restrict__ tiles,
                                              int s, int par) {
   constexpr int TB = B * CPT;
@@ -156,7 +156,7 @@ __global__ __launch_bounds__(B) void k_stage(Bufs bf, Consts cs, const Tile* __r
   const StageScal sc = stage_scal_const(bf.inst, tl.inst, s);
   lds_sync();
   uint8_t* cl = bf.cls ? bf.cls + (int64_t)(s - 1) * bf.S + v.co : nullptr;
-  const StageRes r = stage_compute<B, CPT, NR, HR>(bf, cs, v, sc, tl.c0, sm, cl, st, (int)threadIdx.x);
+  const StageRes r = stage_compute<B, CPT, NR, SCH>(bf, cs, v, sc, tl.c0, sm, cl, st, (int)threadIdx.x);
   if (threadIdx.x == 0) publish_stage(bf, tl.rec, r);
 }
 
@@ -469,7 +469,7 @@ __global__ __launch_bounds__(1024) void k_count_active(Bufs bf, int* __restrict_
 // Persistent engine: one launch for the whole batch.  A work-group of B
 // threads runs the stage tiles of its instance one after the other, CPT cells
 // per thread (tiles of B * CPT cells, B * CPT - 2 owned).
-template <int B, int CPT, bool HR>
+template <int B, int CPT, int SCH>
 __global__ __launch_bounds__(B) void k_persistent(Bufs bf, Consts cs,
                                                   const int32_t* __restrict__ order,
                                                   unsigned* __restrict__ queue,
@@ -496,7 +496,7 @@ __global__ __launch_bounds__(B) void k_persistent(Bufs bf, Consts cs,
         const StageScal sc = stage_scal(sI, s);
         double amax = 0.0, jmax = 0.0;
         for (int64_t c0 = 0; c0 < v.n; c0 += B * CPT - 2) {
-          StageRes r = stage_tile<B, CPT, HR>(bf, cs, v, sc, c0, sm, nullptr);
+          StageRes r = stage_tile<B, CPT, SCH>(bf, cs, v, sc, c0, sm, nullptr);
           amax = fmax(amax, r.alpha);
           jmax = fmax(jmax, r.maxJ);
           c_cls[0] += r.ncls0; c_cls[1] += r.ncls1; c_cls[2] += r.ncls2;
@@ -702,6 +702,13 @@ struct alew_ctx {
 
 namespace {
 
+// Scheme of the stage kernels from the flags.
+int scheme_of(const Consts& cs) {
+  if (cs.flags & F_HYDROSTATIC) return SCH_HYDRO;
+  if (cs.flags & F_NONWB) return SCH_NONWB;
+  return SCH_SPECIAL;
+}
+
 Consts make_consts(const alew_params* p) {
   Consts c;
   c.g = p->g; c.cfl = p->cfl; c.weno_eps = p->weno_eps; c.pp_eps = p->pp_eps;
@@ -718,6 +725,8 @@ alew_status check_params(const alew_params* p) {
   if (p->mesh < 0 || p->mesh > 3) return fail(ALEW_E_ARG, "unknown mesh mode");
   if ((p->mesh == ALEW_MESH_SINE || p->mesh == ALEW_MESH_PAPER) && !(p->mesh_omega == p->mesh_omega))
     return fail(ALEW_E_ARG, "mesh_omega is NaN");
+  if ((p->flags & ALEW_F_HYDROSTATIC) && (p->flags & ALEW_F_NONWB))
+    return fail(ALEW_E_ARG, "HYDROSTATIC and NONWB select different schemes");
   return ALEW_OK;
 }
 
@@ -912,24 +921,21 @@ template <int B, int CPT>
 void launch_step_seq(alew_ctx* c, const Bufs& bf, const Consts& cs, hipStream_t st, int64_t step) {
   const int par = (int)(step & 1);
   const dim3 gs((unsigned)c->n_tiles_stage), gp((unsigned)c->n_tiles_plain);
+  const int sch = scheme_of(cs);
   for (int s = 1; s <= 3; ++s) {
     const int kt = kt_begin(c, st, 0, (double)c->tables_cells);
-    const bool hr = (cs.flags & F_HYDROSTATIC) != 0;
+#define ALEW_STAGE(NX, SC)                                                                      \
+  hipLaunchKernelGGL((k_stage<B, CPT, NX, SC>), gs, dim3(B), 0, st, bf, cs, c->tiles_stage_d, s, par)
     if (c->tiles_noext) {
-      if (hr)
-        hipLaunchKernelGGL((k_stage<B, CPT, true, true>), gs, dim3(B), 0, st, bf, cs,
-                           c->tiles_stage_d, s, par);
-      else
-        hipLaunchKernelGGL((k_stage<B, CPT, true, false>), gs, dim3(B), 0, st, bf, cs,
-                           c->tiles_stage_d, s, par);
+      if (sch == SCH_HYDRO) ALEW_STAGE(true, SCH_HYDRO);
+      else if (sch == SCH_NONWB) ALEW_STAGE(true, SCH_NONWB);
+      else ALEW_STAGE(true, SCH_SPECIAL);
     } else {
-      if (hr)
-        hipLaunchKernelGGL((k_stage<B, CPT, false, true>), gs, dim3(B), 0, st, bf, cs,
-                           c->tiles_stage_d, s, par);
-      else
-        hipLaunchKernelGGL((k_stage<B, CPT, false, false>), gs, dim3(B), 0, st, bf, cs,
-                           c->tiles_stage_d, s, par);
+      if (sch == SCH_HYDRO) ALEW_STAGE(false, SCH_HYDRO);
+      else if (sch == SCH_NONWB) ALEW_STAGE(false, SCH_NONWB);
+      else ALEW_STAGE(false, SCH_SPECIAL);
     }
+#undef ALEW_STAGE
     kt_end(c, st, kt);
     launch_after_stage(c, bf, st, s);
   }
@@ -1049,11 +1055,13 @@ alew_status run_persistent(alew_ctx* c, const Bufs& bf, const Consts& cs, int64_
   int dev = 0, ncu = 0, per_cu = 0;
   HIPCHK(hipGetDevice(&dev));
   HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-  const bool hr = (cs.flags & F_HYDROSTATIC) != 0;
-  if (hr)
-    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<B, CPT, true>, B, 0));
+  const int sch = scheme_of(cs);
+  if (sch == SCH_HYDRO)
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<B, CPT, SCH_HYDRO>, B, 0));
+  else if (sch == SCH_NONWB)
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<B, CPT, SCH_NONWB>, B, 0));
   else
-    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<B, CPT, false>, B, 0));
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<B, CPT, SCH_SPECIAL>, B, 0));
   int64_t grid = (int64_t)std::max(1, ncu) * std::max(1, per_cu);
   grid = std::min<int64_t>(grid, ninst);
   const int limit = c->launch.steps_per_launch;
@@ -1062,12 +1070,15 @@ alew_status run_persistent(alew_ctx* c, const Bufs& bf, const Consts& cs, int64_
   for (;;) {
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, c->stream, c->queue_d);
     HIPCHK(hipEventRecord(c->ev0, c->stream));
-    if (hr)
-      hipLaunchKernelGGL((k_persistent<B, CPT, true>), dim3((unsigned)grid), dim3(B), 0, c->stream,
-                         bf, cs, c->order_d, c->queue_d, limit);
+    if (sch == SCH_HYDRO)
+      hipLaunchKernelGGL((k_persistent<B, CPT, SCH_HYDRO>), dim3((unsigned)grid), dim3(B), 0,
+                         c->stream, bf, cs, c->order_d, c->queue_d, limit);
+    else if (sch == SCH_NONWB)
+      hipLaunchKernelGGL((k_persistent<B, CPT, SCH_NONWB>), dim3((unsigned)grid), dim3(B), 0,
+                         c->stream, bf, cs, c->order_d, c->queue_d, limit);
     else
-      hipLaunchKernelGGL((k_persistent<B, CPT, false>), dim3((unsigned)grid), dim3(B), 0, c->stream,
-                         bf, cs, c->order_d, c->queue_d, limit);
+      hipLaunchKernelGGL((k_persistent<B, CPT, SCH_SPECIAL>), dim3((unsigned)grid), dim3(B), 0,
+                         c->stream, bf, cs, c->order_d, c->queue_d, limit);
     HIPCHK(hipEventRecord(c->ev1, c->stream));
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventSynchronize(c->ev1));
@@ -1577,6 +1588,8 @@ alew_status alew_adjoint(alew_ctx* c, const alew_params* p, int64_t ninst,
     return fail(ALEW_E_UNSUPPORTED, "the adjoint needs a prescribed (SINE or PAPER) mesh");
   if (p->flags & ALEW_F_ALPHA_CELLAVG)
     return fail(ALEW_E_UNSUPPORTED, "the adjoint takes the LF speed over the face traces");
+  if (p->flags & ALEW_F_NONWB)
+    return fail(ALEW_E_UNSUPPORTED, "the adjoint covers the well-balanced schemes");
   if (ninst <= 0 || ninst > c->max_inst || !cell_off) return fail(ALEW_E_ARG, "bad ninst / cell_off");
   if (!h0 || !hu0 || !b0 || !x0 || !xi || !dts) return fail(ALEW_E_ARG, "NULL input array");
   if (nsteps < 1) return fail(ALEW_E_ARG, "nsteps must be >= 1");

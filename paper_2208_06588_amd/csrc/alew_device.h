@@ -22,8 +22,13 @@ enum { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1, BC_REFLECTIVE = 2 };
 enum { MESH_GIVEN = 0, MESH_SINE = 1, MESH_PAPER = 2, MESH_FLUID = 3 };
 enum {
   F_BETA_LOCAL = 1, F_BETA_FROM_H = 2, F_HYDROSTATIC = 4, F_ALPHA_CELLAVG = 8, F_NO_HU_LIMIT = 16,
-  F_W_TANGENT = 32
+  F_W_TANGENT = 32, F_NONWB = 64
 };
+// Scheme of a stage kernel (a template parameter): the special source-term
+// treatment (Sec. 4.2), the hydrostatic reconstruction (Sec. 4.1), or the
+// ALE-WENO scheme of Sec. 3 without well-balancing, with characteristic
+// reconstruction.
+enum { SCH_SPECIAL = 0, SCH_HYDRO = 1, SCH_NONWB = 2 };
 // status bits (combined per instance; mapped to alew_status on the host)
 enum {
   SB_MESH = 1, SB_NEGDEPTH = 2, SB_NONFINITE = 4, SB_NEGWEIGHT = 8, SB_SEQUENCE = 16,
@@ -425,19 +430,221 @@ __device__ __forceinline__ void recon_cell(const double* __restrict__ v5,  // in
 }
 
 // ----------------------------------------------------------------------------
+// Reconstruction with weights of its own for each variable (the scheme of
+// Sec. 3 without well-balancing): the geometry of the cell (stencil maps and
+// the linear weights at the 4 Gauss-Lobatto points) is shared, and each
+// variable gets its indicators, detector class and hybrid weights (Sec. 2.2,
+// Steps 2-4 for a scalar).
+// ----------------------------------------------------------------------------
+struct CellGeom {
+  double kb1[3], kb2[3], kc1[3], kc2[3];  // B_r, C_r from the two other averages of stencil r
+  double d[4][3];                         // linear weights at the 4 points
+  double dd[4][3];                        // their derivatives d/dy at the 4 points
+  double kap, kapC;                       // Dx / Delta_j and the y^2 indicator factor
+  unsigned sgn;                           // OR of the weights' high words (sign bit)
+};
+
+__device__ __forceinline__ void cell_geom(const double* __restrict__ J5, double iJ0, double Dx,
+                                          CellGeom& G) {
+  double M1[4], M2[4], M3[4], M4[4];
+  stencil_moments(J5, iJ0, M1, M2, M3, M4);
+  const int C1[3] = {2, 1, 0}, C2[3] = {3, 2, 1};
+  double B3[3], C3[3], B4[3], C4[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const int c1 = C1[r], c2 = C2[r];
+    const double idet = frcp(M1[c1] * M2[c2] - M1[c2] * M2[c1]);
+    G.kb1[r] = M2[c2] * idet;
+    G.kb2[r] = -M2[c1] * idet;
+    G.kc1[r] = -M1[c2] * idet;
+    G.kc2[r] = M1[c1] * idet;
+    B3[r] = G.kb1[r] * M3[c1] + G.kb2[r] * M3[c2];
+    C3[r] = G.kc1[r] * M3[c1] + G.kc2[r] * M3[c2];
+    B4[r] = G.kb1[r] * M4[c1] + G.kb2[r] * M4[c2];
+    C4[r] = G.kc1[r] * M4[c1] + G.kc2[r] * M4[c2];
+  }
+  const double q = 0.22360679774997896964, q3 = 0.011180339887498948482;
+  const double yv[4] = {-0.5, -q, q, 0.5};
+  const double p2v[4] = {1.0 / 6.0, -1.0 / 30.0, -1.0 / 30.0, 1.0 / 6.0};
+  const double f3v[4] = {-0.125, -q3, q3, 0.125};
+  const double f4v[4] = {0.05, -0.01, -0.01, 0.05};
+  unsigned sgn = 0u;
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+    double e3[3], e4[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      e3[r] = B3[r] * yv[mu] + C3[r] * p2v[mu] - f3v[mu];
+      e4[r] = B4[r] * yv[mu] + C4[r] * p2v[mu] - f4v[mu];
+    }
+    const double x0 = e3[1] * e4[2] - e3[2] * e4[1];
+    const double x1 = e3[2] * e4[0] - e3[0] * e4[2];
+    const double x2 = e3[0] * e4[1] - e3[1] * e4[0];
+    const double is = frcp(x0 + x1 + x2);
+    G.d[mu][0] = x0 * is;
+    G.d[mu][1] = x1 * is;
+    G.d[mu][2] = x2 * is;
+    sgn |= hiword(G.d[mu][0]) | hiword(G.d[mu][1]) | hiword(G.d[mu][2]);
+    // d_r' = (x_r' - d_r X') / X with X = x_0 + x_1 + x_2 (quotient rule), the
+    // error vectors differentiated term by term
+    const double y = yv[mu];
+    double g3[3], g4[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      g3[r] = B3[r] + 2.0 * C3[r] * y - 3.0 * y * y;
+      g4[r] = B4[r] + 2.0 * C4[r] * y - 4.0 * y * y * y;
+    }
+    const double y0 = g3[1] * e4[2] + e3[1] * g4[2] - g3[2] * e4[1] - e3[2] * g4[1];
+    const double y1 = g3[2] * e4[0] + e3[2] * g4[0] - g3[0] * e4[2] - e3[0] * g4[2];
+    const double y2 = g3[0] * e4[1] + e3[0] * g4[1] - g3[1] * e4[0] - e3[1] * g4[0];
+    const double Xp = y0 + y1 + y2;
+    G.dd[mu][0] = (y0 - G.d[mu][0] * Xp) * is;
+    G.dd[mu][1] = (y1 - G.d[mu][1] * Xp) * is;
+    G.dd[mu][2] = (y2 - G.d[mu][2] * Xp) * is;
+  }
+  G.sgn = sgn;
+  G.kap = Dx * iJ0;
+  G.kapC = G.kap * (1.0 / 3.0) + 4.0 * G.kap * G.kap * G.kap;
+}
+
+// Values of one variable at the 4 points (and, with der, its x-derivative);
+// returns the variable's class.
+__device__ __forceinline__ int recon_scalar(const CellGeom& G, const double* u5, double eps,
+                                            double iJ0, double* val, double* der) {
+  const int C1[3] = {2, 1, 0}, C2[3] = {3, 2, 1};
+  const double du[4] = {u5[0] - u5[2], u5[1] - u5[2], u5[3] - u5[2], u5[4] - u5[2]};
+  double Bv[3], Cv[3], beta[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    Bv[r] = G.kb1[r] * du[C1[r]] + G.kb2[r] * du[C2[r]];
+    Cv[r] = G.kc1[r] * du[C1[r]] + G.kc2[r] * du[C2[r]];
+    beta[r] = G.kap * (Bv[r] * Bv[r]) + G.kapC * (Cv[r] * Cv[r]);
+  }
+  const double tau = fabs(beta[0] - beta[2]);
+  const double betaA = (beta[0] + beta[1] + beta[2]) * (1.0 / 3.0);
+  const double gam = tau * frcp(betaA + eps);
+  const int cls = (gam <= 0.5) ? 0 : ((gam >= 1.0) ? 2 : 1);
+  double K[3] = {1.0, 1.0, 1.0};
+  if (cls != 0) {
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const double z = tau * frcp(beta[r] + eps);
+      K[r] = 1.0 + z * z;
+    }
+  }
+  const double Mg = 2.0 * gam - 1.0;
+  const double q = 0.22360679774997896964;
+  const double yv[4] = {-0.5, -q, q, 0.5};
+  const double p2v[4] = {1.0 / 6.0, -1.0 / 30.0, -1.0 / 30.0, 1.0 / 6.0};
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+    double ph[3];
+    if (cls == 0) {
+#pragma unroll
+      for (int r = 0; r < 3; ++r) ph[r] = G.d[mu][r];
+    } else {
+      const double a0 = G.d[mu][0] * K[0], a1 = G.d[mu][1] * K[1], a2 = G.d[mu][2] * K[2];
+      const double ia = frcp(a0 + a1 + a2);
+      ph[0] = a0 * ia;
+      ph[1] = a1 * ia;
+      ph[2] = a2 * ia;
+      if (cls == 1) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) ph[r] = Mg * ph[r] + (1.0 - Mg) * G.d[mu][r];
+      }
+    }
+    double sB = 0.0, sC = 0.0;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      sB += ph[r] * Bv[r];
+      sC += ph[r] * Cv[r];
+    }
+    val[mu] = u5[2] + (sB * yv[mu] + sC * p2v[mu]);
+    if (der) {
+      if (cls == 0) {
+        // smooth: the reconstruction is the 5-cell quartic sum_r d_r p_r, and its
+        // derivative sum_r (d_r' p_r + d_r p_r') is fourth order (the weighted
+        // stencil derivatives alone are second order)
+        double dq = sB + 2.0 * yv[mu] * sC;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) dq += G.dd[mu][r] * (Bv[r] * yv[mu] + Cv[r] * p2v[mu]);
+        der[mu] = dq * iJ0;
+      } else {
+        der[mu] = (sB + 2.0 * yv[mu] * sC) * iJ0;
+      }
+    }
+  }
+  return cls;
+}
+
+// Cell of the scheme without well-balancing: (eta, hu) reconstructed in the
+// characteristic variables of the cell's mean state (eigenvectors of the flux
+// Jacobian, (1, u -+ c); component-wise where the mean depth is at most dry),
+// b with weights of its own.  Traces of h = eta - b, hu and b; rint = the
+// source integral of -g (eta - b) b_x over the cell by the 4-point
+// Gauss-Lobatto rule with the unlimited values.  The class is the largest of
+// the three variables' classes.
+__device__ __forceinline__ void recon_cell_char(const double* __restrict__ e5,
+                                                const double* __restrict__ m5,
+                                                const double* __restrict__ b5,
+                                                const double* __restrict__ J5, double iJ0, double Dx,
+                                                double eps, double g, double dry, CellRecon& o) {
+  CellGeom G;
+  cell_geom(J5, iJ0, Dx, G);
+  const double hb = e5[2] - b5[2];
+  const bool chr = hb > dry;
+  double u = 0.0, c = 0.0, w1[5], w2[5];
+  if (chr) {
+    u = m5[2] * frcp(hb);
+    c = fsqrt(g * hb);
+    const double i2c = 0.5 * frcp(c);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      w1[k] = ((u + c) * e5[k] - m5[k]) * i2c;
+      w2[k] = ((c - u) * e5[k] + m5[k]) * i2c;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 5; ++k) { w1[k] = e5[k]; w2[k] = m5[k]; }
+  }
+  double v1[4], v2[4], bv[4], bx[4];
+  const int c1 = recon_scalar(G, w1, eps, iJ0, v1, nullptr);
+  const int c2 = recon_scalar(G, w2, eps, iJ0, v2, nullptr);
+  const int cb = recon_scalar(G, b5, eps, iJ0, bv, bx);
+  const double wgl[4] = {1.0 / 12.0, 5.0 / 12.0, 5.0 / 12.0, 1.0 / 12.0};
+  double ri = 0.0, ev[4], mv[4];
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+    ev[mu] = chr ? v1[mu] + v2[mu] : v1[mu];
+    mv[mu] = chr ? (u - c) * v1[mu] + (u + c) * v2[mu] : v2[mu];
+    ri += (wgl[mu] * J5[2]) * ((-g) * ((ev[mu] - bv[mu]) * bx[mu]));
+  }
+  o.hL = ev[0] - bv[0]; o.mL = mv[0]; o.bL = bv[0];
+  o.hR = ev[3] - bv[3]; o.mR = mv[3]; o.bR = bv[3];
+  o.rint = ri;
+  o.cls = c1 > c2 ? c1 : c2;
+  if (cb > o.cls) o.cls = cb;
+  o.negw = (int)(G.sgn >> 31);
+}
+
+// ----------------------------------------------------------------------------
 // Positivity limiter, 1D form of eq. (3.20)-(3.21); bottom traces by Remark 4.1.
 // The hu traces are scaled by the same Phi about their mean unless hu_lim is
 // false (then the limiter acts on h, and through Remark 4.1 on b, only).
 // Returns 1 when the traces were modified.
 // ----------------------------------------------------------------------------
+// keep_b: the bottom traces stay and eta follows h (the scheme without
+// well-balancing); by default eta stays and b follows h (Remark 4.1).
 __device__ __forceinline__ int limit_cell(double hbar, double mbar, double pp_eps, CellRecon& o,
-                                          bool hu_lim = true) {
+                                          bool hu_lim = true, bool keep_b = false) {
   if (hbar <= 0.0) {
     const double eL = o.hL + o.bL, eR = o.hR + o.bR;
     o.hL = hbar; o.hR = hbar;
     if (hu_lim) { o.mL = mbar; o.mR = mbar; }
-    o.bL = eL - o.hL;
-    o.bR = eR - o.hR;
+    if (!keep_b) {
+      o.bL = eL - o.hL;
+      o.bR = eR - o.hR;
+    }
     return 1;
   }
   const double s1 = 1.0 / 12.0;
@@ -456,8 +663,10 @@ __device__ __forceinline__ int limit_cell(double hbar, double mbar, double pp_ep
     o.mL = Phi * (o.mL - mbar) + mbar;
     o.mR = Phi * (o.mR - mbar) + mbar;
   }
-  o.bL = eL - o.hL;
-  o.bR = eR - o.hR;
+  if (!keep_b) {
+    o.bL = eL - o.hL;
+    o.bR = eR - o.hR;
+  }
   return 1;
 }
 

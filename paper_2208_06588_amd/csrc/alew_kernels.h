@@ -337,11 +337,13 @@ __device__ __forceinline__ double shfl_prev(double x, int lane) {
 // reductions.  Thread t handles the tile cells t + c B, c < CPT.  NR tile
 // cells are reconstructed (NR - 2 owned): TB with the four extra stencil
 // slots loaded, TB - 4 without them.
-template <int B, int CPT, int NR = B * CPT, bool HR = false>
+template <int B, int CPT, int NR = B * CPT, int SCH = SCH_SPECIAL>
 __device__ __forceinline__ StageRes stage_compute(const Bufs& bf, const Consts& cs, const View& v,
                                                   const StageScal& sc, int64_t c0,
                                                   SmemStage<B, CPT>& sm, uint8_t* cls_inst,
                                                   int st, int t) {
+  constexpr bool HR = SCH == SCH_HYDRO;
+  constexpr bool NWB = SCH == SCH_NONWB;
   constexpr int TB = B * CPT;
   constexpr int NW = B / 64;
   const int lane = t & 63, wv = t >> 6;
@@ -387,11 +389,16 @@ __device__ __forceinline__ StageRes stage_compute(const Bufs& bf, const Consts& 
       const double hbar = h5[2];
       ebar[c] = se[2]; mbar[c] = sm.u.in.m[i + 2]; bbar[c] = sb[2]; Jj[c] = sm.u.in.J[i + 2];
       const double Dx = (cs.flags & F_BETA_LOCAL) ? Jj[c] : sc.dx;
-      recon_cell<HR>(v5, h5, sm.u.in.m + i, sb, sm.u.in.J + i, sm.u.in.iJ[i + 2], Dx,
-                     cs.weno_eps, ebar[c], o);
-      const int lim = limit_cell(hbar, mbar[c], cs.pp_eps, o, !(cs.flags & F_NO_HU_LIMIT));
+      if (NWB)
+        recon_cell_char(se, sm.u.in.m + i, sb, sm.u.in.J + i, sm.u.in.iJ[i + 2], Dx, cs.weno_eps,
+                        cs.g, cs.dry_eps, o);
+      else
+        recon_cell<HR>(v5, h5, sm.u.in.m + i, sb, sm.u.in.J + i, sm.u.in.iJ[i + 2], Dx,
+                       cs.weno_eps, ebar[c], o);
+      const int lim = limit_cell(hbar, mbar[c], cs.pp_eps, o, !(cs.flags & F_NO_HU_LIMIT), NWB);
       // HR: the cell's hydrostatic source from its limited traces (eta kept by
-      // the limiter) and the interior values; else the special-source term
+      // the limiter) and the interior values; NWB: the source integral; else
+      // the special-source term
       rint[c] = HR ? hydro_source(cs.g, o.hL + o.bL, o.e1, o.e2, o.hR + o.bR, o.bL, o.b1, o.b2, o.bR)
                    : o.rint;
       if (owned) {
@@ -454,7 +461,9 @@ __device__ __forceinline__ StageRes stage_compute(const Bufs& bf, const Consts& 
         face_flux(tp0[c], tp1[c], tp2[c], tl0[c], tl1[c], tl2[c], sm.wn[i + 2], cs.g, cs.dry_eps, f);
         // the g/2 b^2 part of the special source joins the momentum flux at the
         // face (one LDS array less; still water still cancels to round-off)
-        sm.u.fl[0][i] = f.Fc1; sm.u.fl[1][i] = f.Fc2 - 0.5 * cs.g * f.B2; sm.u.fl[2][i] = f.Gc;
+        sm.u.fl[0][i] = f.Fc1;
+        sm.u.fl[1][i] = NWB ? f.Fc2 : f.Fc2 - 0.5 * cs.g * f.B2;
+        sm.u.fl[2][i] = f.Gc;
         sm.u.fl[3][i] = f.je; sm.u.fl[4][i] = f.jm; sm.u.fl[5][i] = f.jb; sm.u.fl[6][i] = f.B1;
         if (!a_cell) fspeed = vmax(fspeed, f.speed);
         fsl[c] = f.sl;
@@ -478,8 +487,9 @@ __device__ __forceinline__ StageRes stage_compute(const Bufs& bf, const Consts& 
       const double eb = ebar[c], mb = mbar[c], bb = bbar[c], Jc = Jj[c];
       const double Ae = -(fl[0][i + 1] - fl[0][i]);
       const double Am = HR ? -(fl[1][i + 1] - fl[6][i]) + rint[c]
-                           : -(fl[1][i + 1] - fl[1][i]) - g * eb * (fl[6][i + 1] - fl[6][i]) -
-                                 g * rint[c];
+                           : (NWB ? -(fl[1][i + 1] - fl[1][i]) + rint[c]
+                                  : -(fl[1][i + 1] - fl[1][i]) - g * eb * (fl[6][i + 1] - fl[6][i]) -
+                                        g * rint[c]);
       const double Ab = -(fl[2][i + 1] - fl[2][i]);
       const double De = 0.5 * (fl[3][i + 1] - fl[3][i]);
       const double Dm = 0.5 * (fl[4][i + 1] - fl[4][i]);
@@ -555,14 +565,14 @@ __device__ __forceinline__ StageRes stage_compute(const Bufs& bf, const Consts& 
 }
 
 // One stage over the tile of owned cells [c0, c0 + TB - 2) of one instance.
-template <int B, int CPT, bool HR>
+template <int B, int CPT, int SCH>
 __device__ __forceinline__ StageRes stage_tile(const Bufs& bf, const Consts& cs, const View& v,
                                                const StageScal& sc, int64_t c0,
                                                SmemStage<B, CPT>& sm, uint8_t* cls_inst) {
   int st = 0;
   stage_load<B, CPT>(bf, cs, v, sc, c0, sm, st);
   lds_sync();
-  return stage_compute<B, CPT, B * CPT, HR>(bf, cs, v, sc, c0, sm, cls_inst, st, (int)threadIdx.x);
+  return stage_compute<B, CPT, B * CPT, SCH>(bf, cs, v, sc, c0, sm, cls_inst, st, (int)threadIdx.x);
 }
 
 // Scalars of stage s of instance i read through the constant address space

@@ -760,3 +760,112 @@ def test_tangent_node_speed_closed_form():
               wl["xi"], max_steps=1, dts=[dt])
     np.testing.assert_allclose(r["x"] - (xi + A * S * math.sin(om * dt)),
                                A * S * (om * dt - math.sin(om * dt)), atol=1e-16)
+
+
+# ----------------------------------------------------------------------------
+# Scheme of Sec. 3 without well-balancing (characteristic reconstruction)
+# ----------------------------------------------------------------------------
+def test_characteristic_reconstruction_keeps_one_wave_family():
+    """Remark after Step 4 of Sec. 2.2 (local characteristic decomposition): data
+    that vary only along one right eigenvector (1, u - c) of the cell's flux
+    Jacobian -- here with a jump, so the weights are nonlinear -- are
+    reconstructed along that eigenvector alone: (hu - hu_j) = (u - c)(eta - eta_j)
+    at every point.  Component-wise weights, or the other eigenvector, would
+    mix the two families."""
+    w = [1.0, 1.1, 0.9, 1.05, 0.95]
+    eta0, m0, b0 = 2.0, 0.6, 0.5
+    h = eta0 - b0
+    u, c = m0 / h, math.sqrt(9.812 * h)
+    s = np.array([-0.1, -0.05, 0.0, 0.3, 0.35])  # cell j keeps the mean state
+    for lam in (u - c, u + c):
+        eta, m = eta0 + s, m0 + s * lam
+        v, cls = O.reconstruct_char(w, eta, m, np.full(5, b0), dx=1.1)
+        de = v[0:4] + v[8:12] - eta0
+        assert cls == 2 and np.abs(de).max() > 1e-2
+        np.testing.assert_allclose(v[4:8] - m0, lam * de, rtol=0, atol=1e-13)
+
+
+def test_characteristic_reconstruction_is_linear_on_smooth_data():
+    """Where every variable is smooth the reconstruction is the linear one, and
+    a linear change of variables commutes with it: the values equal the
+    component-wise linear reconstruction sum_r d_r u_r of eta, hu and b."""
+    rng = np.random.default_rng(31)
+    w = rng.uniform(0.8, 1.2, 5)
+    e = _edges(w)
+    avg = lambda q: np.array([_poly_avg(q, e[k], e[k + 1]) for k in range(5)])
+    eta, m, b = avg([2.0, 0.01, 0.002]), avg([0.5, -0.02, 0.001]), avg([0.3, 0.004, -0.001])
+    v, cls = O.reconstruct_char(w, eta, m, b, dx=w.max())
+    assert cls == 0
+    d, cc, *_ = O.geometry(w)
+    lin = lambda a: sum(d[:, r] * (cc[r] @ a[2 - r:5 - r]) for r in range(3))
+    np.testing.assert_allclose(v[0:4] + v[8:12], lin(eta), rtol=1e-13)
+    np.testing.assert_allclose(v[4:8], lin(m), rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(v[8:12], lin(b), rtol=1e-13)
+
+
+def test_nonwb_bottom_slope_fourth_order():
+    """The source integral of the scheme of Sec. 3 needs b_x at the Gauss-Lobatto
+    points; in smooth cells it is the derivative of the 5-cell quartic, whose
+    error falls by 2^4 per halving of the cells (the weighted stencil
+    derivatives sum_r d_r u_r' alone fall only by 2^2)."""
+    f = lambda x: np.sin(2 * x) + 0.3 * np.cos(5 * x)
+    F = lambda x: -np.cos(2 * x) / 2 + 0.3 * np.sin(5 * x) / 5
+    df = lambda x: 2 * np.cos(2 * x) - 1.5 * np.sin(5 * x)
+    errs = []
+    for dx in (0.02, 0.01, 0.005):
+        e = np.array([-2, -1, 0, 1, 2, 3]) * dx + 0.3
+        bav = (F(e[1:]) - F(e[:-1])) / dx
+        z = np.zeros(5)
+        v, cls = O.reconstruct_char([dx] * 5, np.full(5, 1.0), z, bav, dx=dx)
+        assert cls == 0
+        errs.append(np.abs(v[12:16] - df(0.3 + dx * GL_S)).max())
+    for a, b in zip(errs, errs[1:]):
+        assert 3.7 < math.log2(a / b) < 4.4, errs
+
+
+def test_nonwb_positivity_moses_second_problem():
+    """Table 5.3: Moses's second problem is run with the scheme without
+    well-balancing (flat bottom); Property 3.1 keeps h >= 0 with the limiter
+    active, and the flat bottom stays flat (the limiter keeps the b traces)."""
+    wl = W.moses2_1d(200, t_end=1.0)
+    r = O.run(_params_for(wl, flags=O.FLAG_NONWB), wl["h"], wl["hu"], wl["b"], wl["x"], wl["xi"],
+              t_end=1.0)
+    S = r["stats"]
+    assert r["status"] == 0 and S.n_limited > 0
+    assert S.h_min >= -1e-20 and r["h"].min() >= -1e-20
+    assert np.abs(r["b"]).max() == 0.0
+
+
+@pytest.mark.parametrize("bottom,table", [("smooth", "table5.4nwb"), ("step", "table5.5nwb")])
+def test_nonwb_does_not_keep_still_water(bottom, table):
+    """Tables 5.4 / 5.5, rows of the scheme without well-balancing: still water
+    is not preserved (errors far above round-off; over the step bottom they are
+    of order one, Linf(h+b) = 5.3 in the paper)."""
+    wl = W.still_water_1d(200, bottom)
+    r = O.run(_params_for(wl, flags=O.FLAG_NONWB), wl["h"], wl["hu"], wl["b"], wl["x"], wl["xi"],
+              t_end=0.5)
+    assert r["status"] == 0
+    J = np.diff(r["x"])
+    e = r["h"] + r["b"] - 10.0
+    got = [np.sum(np.abs(e) * J), np.sum(np.abs(r["hu"]) * J), np.abs(e).max(), np.abs(r["hu"]).max()]
+    paper = [float(v) for row in _gold("paper_tables.txt") if row[0] == table for v in row[1:]]
+    if bottom == "smooth":
+        assert all(1e-8 < g < 1e-2 for g in got), (got, paper)
+    else:
+        assert got[2] > 0.1 and got[3] > 0.1, (got, paper)
+
+
+def test_nonwb_constant_state_and_mass():
+    """Constant states are preserved on a moving mesh (D-GCL) and the masses of
+    eta and b are conserved (periodic), as for the other schemes."""
+    wl = W.accuracy_1d(40)
+    n = 40
+    r = O.run(_params_for(wl, flags=O.FLAG_NONWB), np.full(n, 2.0), np.full(n, 0.7),
+              np.full(n, 0.0), wl["x"], wl["xi"], max_steps=15)
+    np.testing.assert_allclose(r["h"], 2.0, atol=1e-13)
+    np.testing.assert_allclose(r["hu"], 0.7, atol=1e-13)
+    r = O.run(_params_for(wl, flags=O.FLAG_NONWB), wl["h"], wl["hu"], wl["b"], wl["x"], wl["xi"],
+              max_steps=30)
+    S = r["stats"]
+    assert abs(S.mass_eta - S.mass_eta0) <= 1e-13 * abs(S.mass_eta0)
+    assert abs(S.mass_b - S.mass_b0) <= 1e-13 * abs(S.mass_b0)

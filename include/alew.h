@@ -117,6 +117,23 @@ enum {
                                 ALEW_F_HYDROSTATIC                                     */
 };
 
+/* Bottom topography (Sec. 3.3).  ALE (default): the cell averages of b are a
+ * state variable evolved by the ALE scheme of eq. (3.17) from the b the caller
+ * passes.  The other kinds give b(x) in closed form, and the cell averages are
+ * its L2 projection onto the moving cells, eq. (3.16): at every stage on the
+ * stage's mesh (t_n, t_{n+1}, t_{n+1/2}) and at the end of every step on the
+ * new mesh; the b array's input values are not used, and it receives the
+ * projection onto the final mesh.  Parameters bottom_p[0..3]:
+ *   STEP      b = p0 on [p1, p2], 0 elsewhere
+ *   GAUSS     b = p0 exp(-p1 (x - p2)^2)
+ *   SIN2      b = p0 sin^2(pi p1 x)
+ *   BUMP      b = p0 (cos(pi (x - p2) / p1) + 1) for |x - p2| < p1, else 0
+ *   PARABOLA  b = p0 (x / p1)^2 */
+enum {
+  ALEW_BOTTOM_ALE = 0, ALEW_BOTTOM_STEP = 1, ALEW_BOTTOM_GAUSS = 2, ALEW_BOTTOM_SIN2 = 3,
+  ALEW_BOTTOM_BUMP = 4, ALEW_BOTTOM_PARABOLA = 5
+};
+
 typedef struct {
   double g;          /* gravitational constant (9.812 in Sec. 5)                       */
   double cfl;        /* CFL number of the time-step rule                               */
@@ -127,7 +144,8 @@ typedef struct {
   int32_t bc;        /* ALEW_BC_*                                                      */
   int32_t mesh;      /* ALEW_MESH_*                                                    */
   int32_t flags;     /* ALEW_F_*                                                       */
-  int32_t pad;
+  int32_t bottom;    /* ALEW_BOTTOM_* (0: evolved by eq. (3.17))                       */
+  double bottom_p[4];  /* parameters of the analytic bottom                           */
 } alew_params;
 
 typedef struct {

@@ -32,7 +32,8 @@ class Params(C.Structure):
         ("g", C.c_double), ("cfl", C.c_double), ("weno_eps", C.c_double), ("pp_eps", C.c_double),
         ("mesh_A", C.c_double), ("mesh_k", C.c_double), ("mesh_omega", C.c_double),
         ("dry_eps", C.c_double),
-        ("bc", C.c_int32), ("mesh", C.c_int32), ("flags", C.c_int32), ("pad", C.c_int32),
+        ("bc", C.c_int32), ("mesh", C.c_int32), ("flags", C.c_int32), ("bottom", C.c_int32),
+        ("bottom_p", C.c_double * 4),
     ]
 
 
@@ -71,6 +72,8 @@ def lib():
         L.orc_geometry.argtypes = [dp, dp, dp, dp, dp]
         L.orc_reconstruct.argtypes = [dp, dp, dp, dp, dp, C.c_double, C.c_double, dp, dp, dp]
         L.orc_limit.argtypes = [C.c_double, C.c_double, dp, C.c_double, C.c_int, dp]
+        L.orc_bottom_average.argtypes = [C.POINTER(Params), C.c_double, C.c_double]
+        L.orc_bottom_average.restype = C.c_double
         L.orc_reconstruct_char.argtypes = [dp, dp, dp, dp, C.c_double, C.c_double, C.c_double,
                                            C.c_double, dp]
         L.orc_hydro_source.argtypes = [C.c_double, dp, dp]
@@ -96,13 +99,18 @@ def _f64(a):
     return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
 
 
+BOTTOM_ALE, BOTTOM_STEP, BOTTOM_GAUSS, BOTTOM_SIN2, BOTTOM_BUMP, BOTTOM_PARABOLA = range(6)
+
+
 def params(g=9.812, cfl=0.6, weno_eps=1e-6, pp_eps=1e-11, bc=BC_PERIODIC, mesh=MESH_SINE,
-           mesh_A=0.05, mesh_k=1.0, mesh_omega=np.pi, flags=0, dry_eps=1e-8) -> Params:
+           mesh_A=0.05, mesh_k=1.0, mesh_omega=np.pi, flags=0, dry_eps=1e-8, bottom=BOTTOM_ALE,
+           bottom_p=(0.0, 0.0, 0.0, 0.0)) -> Params:
     """Scheme constants: g (Sec. 5), CFL, WENO epsilon (Sec. 2.2 Step 2),
-    positivity epsilon (eq. (3.20)), boundary type, mesh motion and the dry
-    tolerance of the trace velocity."""
+    positivity epsilon (eq. (3.20)), boundary type, mesh motion, the dry
+    tolerance of the trace velocity, and the bottom (evolved by eq. (3.17), or
+    an analytic b(x) projected onto the cells, eq. (3.16))."""
     return Params(g, cfl, weno_eps, pp_eps, mesh_A, mesh_k, mesh_omega, dry_eps, bc, mesh, flags,
-                  0)
+                  bottom, (C.c_double * 4)(*[float(v) for v in bottom_p]))
 
 
 def geometry(widths5):
@@ -127,6 +135,11 @@ def reconstruct(widths5, h5, m5, b5, dx, eps=1e-6, v5=None):
     cls = lib().orc_reconstruct(_p(_f64(widths5)), _p(v5), _p(h5), _p(m5), _p(b5),
                                 float(dx), float(eps), _p(out), _p(beta), _p(gam))
     return out, cls, beta, float(gam[0])
+
+
+def bottom_average(P: Params, xl, xr):
+    """Average over [xl, xr] of the analytic bottom of P (eq. (3.16))."""
+    return float(lib().orc_bottom_average(C.byref(P), float(xl), float(xr)))
 
 
 def reconstruct_char(widths5, eta5, m5, b5, dx, eps=1e-6, g=9.812, dry_eps=1e-8):

@@ -109,6 +109,13 @@
  *      hybrid reconstruction).  The limiter acts on h = eta - b and keeps the
  *      bottom traces (Remark 4.1 is stated for the well-balanced schemes; here
  *      a flat bottom stays flat).
+ *  R23 params.bottom != ALE: the bottom is an analytic b(x) and its cell
+ *      averages are the L2 projection of eq. (3.16) onto the moving cells,
+ *      taken on the mesh of every stage (t_n, t_{n+1}, t_{n+1/2}, the meshes of
+ *      eq. (3.14)) and on the new mesh at the end of the step, instead of the
+ *      ALE evolution of eq. (3.17); the initial b is the projection onto the
+ *      initial cells.  The integral is taken by the 5-point Gauss-Legendre
+ *      rule on the smooth pieces of b.
  */
 #include <cmath>
 #include <cstdint>
@@ -182,8 +189,66 @@ enum {
 struct Params {
   double g, cfl, weno_eps, pp_eps;
   double mesh_A, mesh_k, mesh_omega, dry_eps;
-  int32_t bc, mesh, flags, pad;
+  int32_t bc, mesh, flags, bottom;
+  double bottom_p[4];
 };
+
+/* ------------------------------------------------------------------------ */
+/* Sec. 3.3, eq. (3.16): L2 projection of an analytic bottom b(x) (R23)       */
+/* ------------------------------------------------------------------------ */
+enum { BOTTOM_ALE = 0, BOTTOM_STEP = 1, BOTTOM_GAUSS = 2, BOTTOM_SIN2 = 3, BOTTOM_BUMP = 4,
+       BOTTOM_PARABOLA = 5 };
+
+static double bottom_value(const Params& P, double x) {
+  const double* p = P.bottom_p;
+  switch (P.bottom) {
+    case BOTTOM_STEP: return (x >= p[1] && x <= p[2]) ? p[0] : 0.0;
+    case BOTTOM_GAUSS: return p[0] * std::exp(-p[1] * (x - p[2]) * (x - p[2]));
+    case BOTTOM_SIN2: {
+      double s = std::sin(M_PI * p[1] * x);
+      return p[0] * s * s;
+    }
+    case BOTTOM_BUMP:
+      return std::fabs(x - p[2]) < p[1] ? p[0] * (std::cos(M_PI * (x - p[2]) / p[1]) + 1.0) : 0.0;
+    case BOTTOM_PARABOLA: return p[0] * (x / p[1]) * (x / p[1]);
+    default: return 0.0;
+  }
+}
+
+/* Average of b over [xl, xr]: the 5-point Gauss-Legendre rule on 16 equal
+ * parts of every piece between the points where b is not smooth (exact for
+ * the step and the parabola; for the smooth pieces the composite rule is
+ * accurate to round-off also on cells as wide as the bump itself). */
+static double bottom_average(const Params& P, double xl, double xr) {
+  static const double r[5] = {-0.90617984593866399280, -0.53846931010568309104, 0.0,
+                              0.53846931010568309104, 0.90617984593866399280};
+  static const double w[5] = {0.23692688505618908751, 0.47862867049936646804,
+                              0.56888888888888888889, 0.47862867049936646804,
+                              0.23692688505618908751};
+  std::vector<double> cuts = {xl};
+  const double* p = P.bottom_p;
+  double br[2] = {0.0, 0.0};
+  int nb = 0;
+  if (P.bottom == BOTTOM_STEP) { br[0] = p[1]; br[1] = p[2]; nb = 2; }
+  if (P.bottom == BOTTOM_BUMP) { br[0] = p[2] - p[1]; br[1] = p[2] + p[1]; nb = 2; }
+  for (int k = 0; k < nb; ++k)
+    if (br[k] > xl && br[k] < xr) cuts.push_back(br[k]);
+  cuts.push_back(xr);
+  std::sort(cuts.begin(), cuts.end());
+  double I = 0.0;
+  const int parts = 16;
+  for (size_t k = 0; k + 1 < cuts.size(); ++k) {
+    for (int e = 0; e < parts; ++e) {
+      const double a = cuts[k] + (cuts[k + 1] - cuts[k]) * e / parts;
+      const double b = cuts[k] + (cuts[k + 1] - cuts[k]) * (e + 1) / parts;
+      const double m = 0.5 * (a + b), hw = 0.5 * (b - a);
+      double s = 0.0;
+      for (int q = 0; q < 5; ++q) s = s + w[q] * bottom_value(P, m + r[q] * hw);
+      I = I + s * hw;
+    }
+  }
+  return I / (xr - xl);
+}
 
 struct Stats {
   int64_t steps;
@@ -926,9 +991,14 @@ static int step(const Params& P, int n, T* eta, T* m, T* b, double* x, const dou
   std::vector<double> Js = J0, Jn(n);
   const double ca[3] = {0.0, 0.75, 1.0 / 3.0};
   const double cb[3] = {1.0, 0.25, 2.0 / 3.0};
+  /* stage meshes t_n, t_{n+1}, t_{n+1/2} (eq. (3.14)): nodes x + tau w */
+  const double tau[3] = {0.0, dt, 0.5 * dt};
   for (int s = 0; s < 3; ++s) {
     for (int j = 0; j < n; ++j)
       if (!(Js[j] > 0.0)) return ST_MESH;
+    if (P.bottom != BOTTOM_ALE)  /* R23: b is the projection onto the stage mesh */
+      for (int j = 0; j < n; ++j)
+        q[2 * n + j] = bottom_average(P, x[j] + tau[s] * w[j], x[j + 1] + tau[s] * w[j + 1]);
     double alpha;
     residual(P, n, q.data(), q.data() + n, q.data() + 2 * n, Js.data(), w.data(), Rv.data(), &alpha,
              cls ? cls + (size_t)s * n : nullptr, cnt);
@@ -946,6 +1016,8 @@ static int step(const Params& P, int n, T* eta, T* m, T* b, double* x, const dou
     b[j] = q[2 * n + j];
   }
   for (int i = 0; i <= n; ++i) x[i] = x[i] + dt * w[i];
+  if (P.bottom != BOTTOM_ALE)
+    for (int j = 0; j < n; ++j) b[j] = bottom_average(P, x[j], x[j + 1]);
   if (w_used)
     for (int i = 0; i <= n; ++i) w_used[i] = w[i];
   t = t + dt;
@@ -1042,6 +1114,11 @@ int orc_reconstruct_char(const double* wid5, const double* eta5, const double* m
   return o.cls;
 }
 
+/* Cell average of the analytic bottom over [xl, xr] (R23, eq. (3.16)). */
+double orc_bottom_average(const Params* P, double xl, double xr) {
+  return bottom_average(*P, xl, xr);
+}
+
 /* Positivity limiter on given traces.  in[6] = hL, mL, bL, hR, mR, bR;
  * out[6] same order; hu_lim = 0 leaves the hu traces alone (R20).
  * Returns 0 untouched, 1 limited, 2 negative mean. */
@@ -1104,6 +1181,8 @@ int orc_run(const Params* P, int64_t n_, double* h, double* hu, double* b, doubl
   if (P->mesh != MESH_GIVEN && !xi) return ST_ARG;
   if (P->mesh == MESH_GIVEN && !w_given) return ST_ARG;
   stats_init(S);
+  if (P->bottom != BOTTOM_ALE)  /* R23: the projection onto the initial cells */
+    for (int j = 0; j < n; ++j) b[j] = bottom_average(*P, x[j], x[j + 1]);
   std::vector<double> eta(n);
   for (int j = 0; j < n; ++j) eta[j] = h[j] + b[j];
   double t = t0;
@@ -1156,6 +1235,7 @@ int orc_adjoint(const Params* P, int64_t n_, const double* h0, const double* hu0
                 double* dh0, double* dhu0, double* db0) {
   const int n = (int)n_;
   if (n < 5 || P->mesh == MESH_FLUID || P->mesh == MESH_GIVEN) return ST_ARG;
+  if (P->bottom != BOTTOM_ALE) return ST_ARG;
   std::vector<TapeNode> tape;
   tape.reserve(1 << 20);
   g_tape = &tape;

@@ -30,7 +30,8 @@ class Params(C.Structure):
         ("g", C.c_double), ("cfl", C.c_double), ("weno_eps", C.c_double), ("pp_eps", C.c_double),
         ("mesh_A", C.c_double), ("mesh_k", C.c_double), ("mesh_omega", C.c_double),
         ("dry_eps", C.c_double),
-        ("bc", C.c_int32), ("mesh", C.c_int32), ("flags", C.c_int32), ("pad", C.c_int32),
+        ("bc", C.c_int32), ("mesh", C.c_int32), ("flags", C.c_int32), ("bottom", C.c_int32),
+        ("bottom_p", C.c_double * 4),
     ]
 
 
@@ -103,11 +104,17 @@ def lib():
     return _lib
 
 
+BOTTOM = {"ale": 0, "step": 1, "gauss": 2, "sin2": 3, "bump": 4, "parabola": 5}
+
+
 def params(g=9.812, cfl=0.6, weno_eps=1e-6, pp_eps=1e-11, dry_eps=1e-8, bc="periodic",
-           mesh="sine", mesh_A=0.05, mesh_k=1.0, mesh_omega=3.141592653589793, flags=0) -> Params:
+           mesh="sine", mesh_A=0.05, mesh_k=1.0, mesh_omega=3.141592653589793, flags=0,
+           bottom="ale", bottom_p=(0.0, 0.0, 0.0, 0.0)) -> Params:
     return Params(g, cfl, weno_eps, pp_eps, mesh_A, mesh_k, mesh_omega, dry_eps,
                   BC[bc] if isinstance(bc, str) else int(bc),
-                  MESH[mesh] if isinstance(mesh, str) else int(mesh), int(flags), 0)
+                  MESH[mesh] if isinstance(mesh, str) else int(mesh), int(flags),
+                  BOTTOM[bottom] if isinstance(bottom, str) else int(bottom),
+                  (C.c_double * 4)(*[float(v) for v in bottom_p]))
 
 
 def _ptr(t: Optional[torch.Tensor], dtype=torch.float64):

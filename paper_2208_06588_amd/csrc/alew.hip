@@ -64,7 +64,10 @@ __global__ __launch_bounds__(B) void k_prep(Bufs bf, Consts cs, const Tile* __re
   double speed = 0, minJ = INFINITY, maxJ = 0, hmin = INFINITY, me = 0, mb = 0, sabs = 0;
   if (j < v.n) {
     const int64_t g = v.co + j;
-    const double h = h_in[g], b = bf.b[g], m = bf.m[g];
+    // an analytic bottom: its projection onto the initial cells replaces b
+    const double b = cs.bottom != BOT_ALE ? bottom_avg(cs, v.x[j], v.x[j + 1]) : bf.b[g];
+    if (cs.bottom != BOT_ALE) bf.b[g] = b;
+    const double h = h_in[g], m = bf.m[g];
     const double e = h + b;
     bf.eta[g] = e;
     const double J = v.x[j + 1] - v.x[j];
@@ -109,6 +112,44 @@ __global__ __launch_bounds__(B) void k_wfluid(Bufs bf, Consts cs, const Tile* __
   View v = make_view(bf, tl.inst, I);
   const double W = wfluid_tile<B>(bf, cs, v, tl.c0, su, sv, red);
   if (threadIdx.x == 0) bf.prec[(int64_t)tl.rec * PREC + 4] = W;
+}
+
+// Stage input of b under the L2 projection of eq. (3.16): the previous stage
+// left P_b, D_b of the ALE bottom update in its stage buffers; they become the
+// projection onto the mesh of stage s (x^n + tau w, tau = dt for stage 2 and
+// dt / 2 for stage 3) times the stage width (the recurrence of eq. (3.15), as
+// the stage kernel forms it) with D_b = 0, so the stage kernel's b is the
+// projection.  Cells [c0, c0 + B) of one instance.
+__device__ __forceinline__ void project_cell(const Bufs& bf, const Consts& cs, const View& v,
+                                             int64_t j, int s, double dt, double wsc) {
+  const double x0 = v.x[j], x1 = v.x[j + 1];
+  const double w0 = bf.w[v.no + j] * wsc, w1 = bf.w[v.no + j + 1] * wsc;
+  const double Jn = x1 - x0, dw = w1 - w0;
+  const double J1 = Jn + dt * dw;
+  const double J = (s == 2) ? J1 : 0.75 * Jn + 0.25 * (J1 + dt * dw);
+  const double tau = (s == 2) ? dt : 0.5 * dt;
+  const double bp = bottom_avg(cs, x0 + tau * w0, x1 + tau * w1);
+  const int64_t g = v.co + j;
+  double* P = (s == 2) ? bf.P0 : bf.P1;
+  double* D = (s == 2) ? bf.D0 : bf.D1;
+  P[2 * bf.S + g] = bp * J;
+  D[2 * bf.S + g] = 0.0;
+}
+
+template <int B>
+__global__ __launch_bounds__(B) void k_project(Bufs bf, Consts cs, const Tile* __restrict__ tiles,
+                                               int s, int par) {
+  const Tile tl = tiles[blockIdx.x];
+  View v;
+  v.n = tl.n;
+  v.co = tl.co;
+  v.no = tl.co + tl.inst;
+  v.x = (par ? bf.xb : bf.xa) + v.no;
+  v.xnew = (par ? bf.xa : bf.xb) + v.no;
+  const Inst& I = bf.inst[tl.inst];
+  if (!I.active) return;
+  const int64_t j = tl.c0 + threadIdx.x;
+  if (j < v.n) project_cell(bf, cs, v, j, s, I.dt, I.wscale);
 }
 
 // Result record of one stage tile.
@@ -508,6 +549,8 @@ __global__ __launch_bounds__(B) void k_persistent(Bufs bf, Consts cs,
           sI.alpha[s - 1] = amax;
           if (s < 3) sI.dx[s] = jmax;
         }
+        if (cs.bottom != BOT_ALE && s < 3)
+          for (int64_t j = threadIdx.x; j < v.n; j += B) project_cell(bf, cs, v, j, s + 1, dt, sI.wscale);
         __syncthreads();
       }
       double fsp = 0.0, fminJ = INFINITY, fmaxJ = 0.0, fhmin = INFINITY;
@@ -713,7 +756,8 @@ Consts make_consts(const alew_params* p) {
   Consts c;
   c.g = p->g; c.cfl = p->cfl; c.weno_eps = p->weno_eps; c.pp_eps = p->pp_eps;
   c.mesh_A = p->mesh_A; c.mesh_k = p->mesh_k; c.mesh_omega = p->mesh_omega; c.dry_eps = p->dry_eps;
-  c.bc = p->bc; c.mesh = p->mesh; c.flags = p->flags; c.pad = 0;
+  c.bc = p->bc; c.mesh = p->mesh; c.flags = p->flags; c.bottom = p->bottom;
+  for (int k = 0; k < 4; ++k) c.bp[k] = p->bottom_p[k];
   return c;
 }
 
@@ -727,6 +771,9 @@ alew_status check_params(const alew_params* p) {
     return fail(ALEW_E_ARG, "mesh_omega is NaN");
   if ((p->flags & ALEW_F_HYDROSTATIC) && (p->flags & ALEW_F_NONWB))
     return fail(ALEW_E_ARG, "HYDROSTATIC and NONWB select different schemes");
+  if (p->bottom < 0 || p->bottom > ALEW_BOTTOM_PARABOLA) return fail(ALEW_E_ARG, "unknown bottom");
+  if ((p->bottom == ALEW_BOTTOM_BUMP || p->bottom == ALEW_BOTTOM_PARABOLA) && !(p->bottom_p[1] > 0))
+    return fail(ALEW_E_ARG, "bottom_p[1] must be > 0 for BUMP and PARABOLA");
   return ALEW_OK;
 }
 
@@ -938,6 +985,9 @@ void launch_step_seq(alew_ctx* c, const Bufs& bf, const Consts& cs, hipStream_t 
 #undef ALEW_STAGE
     kt_end(c, st, kt);
     launch_after_stage(c, bf, st, s);
+    if (cs.bottom != BOT_ALE && s < 3)
+      hipLaunchKernelGGL(k_project<PB>, dim3((unsigned)c->n_tiles_plain), dim3(PB), 0, st, bf, cs,
+                         c->tiles_plain_d, s + 1, par);
   }
   const int kf = kt_begin(c, st, 1, (double)c->tables_cells);
   hipLaunchKernelGGL(k_final<PB>, gp, dim3(PB), 0, st, bf, cs, c->tiles_plain_d, par);
@@ -1590,6 +1640,8 @@ alew_status alew_adjoint(alew_ctx* c, const alew_params* p, int64_t ninst,
     return fail(ALEW_E_UNSUPPORTED, "the adjoint takes the LF speed over the face traces");
   if (p->flags & ALEW_F_NONWB)
     return fail(ALEW_E_UNSUPPORTED, "the adjoint covers the well-balanced schemes");
+  if (p->bottom != ALEW_BOTTOM_ALE)
+    return fail(ALEW_E_UNSUPPORTED, "the adjoint differentiates with respect to an evolved bottom");
   if (ninst <= 0 || ninst > c->max_inst || !cell_off) return fail(ALEW_E_ARG, "bad ninst / cell_off");
   if (!h0 || !hu0 || !b0 || !x0 || !xi || !dts) return fail(ALEW_E_ARG, "NULL input array");
   if (nsteps < 1) return fail(ALEW_E_ARG, "nsteps must be >= 1");

@@ -38,8 +38,54 @@ enum {
 struct Consts {
   double g, cfl, weno_eps, pp_eps;
   double mesh_A, mesh_k, mesh_omega, dry_eps;
-  int32_t bc, mesh, flags, pad;
+  int32_t bc, mesh, flags, bottom;
+  double bp[4];
 };
+
+enum { BOT_ALE = 0, BOT_STEP = 1, BOT_GAUSS = 2, BOT_SIN2 = 3, BOT_BUMP = 4, BOT_PARABOLA = 5 };
+
+// Average of the analytic bottom over [xl, xr] (the L2 projection of eq.
+// (3.16) onto one cell): closed forms of the integral where the bottom has
+// one, the 5-point Gauss-Legendre rule (exact to degree 9) for the Gaussian.
+__device__ __forceinline__ double bottom_avg(const Consts& cs, double xl, double xr) {
+  const double* p = cs.bp;
+  const double L = xr - xl;
+  switch (cs.bottom) {
+    case BOT_STEP: {
+      const double a = xl > p[1] ? xl : p[1], b = xr < p[2] ? xr : p[2];
+      return b > a ? p[0] * ((b - a) / L) : 0.0;
+    }
+    case BOT_GAUSS: {
+      const double r1 = 0.90617984593866399280, r2 = 0.53846931010568309104;
+      const double w0 = 0.56888888888888888889, w1 = 0.23692688505618908751,
+                   w2 = 0.47862867049936646804;
+      const double m = 0.5 * (xl + xr), hw = 0.5 * L;
+      auto f = [&](double x) { const double z = x - p[2]; return exp(-p[1] * (z * z)); };
+      const double s = w0 * f(m) + w1 * (f(m - r1 * hw) + f(m + r1 * hw)) +
+                       w2 * (f(m - r2 * hw) + f(m + r2 * hw));
+      return p[0] * (0.5 * s);
+    }
+    case BOT_SIN2: {
+      // sin^2 = (1 - cos 2 pi k x) / 2; the difference of sines over the cell by
+      // the sum-to-product identity (no cancellation on small cells)
+      const double k = M_PI * p[1];
+      return p[0] * (0.5 - cos(k * (xl + xr)) * sin(k * L) / (2.0 * k * L));
+    }
+    case BOT_BUMP: {
+      const double a = xl > p[2] - p[1] ? xl : p[2] - p[1];
+      const double b = xr < p[2] + p[1] ? xr : p[2] + p[1];
+      if (!(b > a)) return 0.0;
+      const double k = M_PI / p[1];
+      // int of cos(k (x - c)) over [a, b] = 2 cos(k (m - c)) sin(k (b - a) / 2) / k
+      const double I = 2.0 * cos(k * (0.5 * (a + b) - p[2])) * sin(0.5 * k * (b - a)) / k;
+      return p[0] * ((I + (b - a)) / L);
+    }
+    case BOT_PARABOLA:
+      return p[0] * ((xl * xl + xl * xr + xr * xr) / (3.0 * p[1] * p[1]));
+    default:
+      return 0.0;
+  }
+}
 
 // Per-instance scalars.  Reduction slots hold IEEE bit patterns so that
 // integer atomics give order-independent max/min.

@@ -663,11 +663,12 @@ __device__ __forceinline__ void final_cell(const Bufs& bf, const Consts& cs, con
   const double c = (2.0 / 3.0) * dt * alpha3;
   const int64_t gi = v.co + j;
   const double iJ3 = frcp(J3);
+  const double xn0 = x0 + dt * w0, xn1 = x1 + dt * w1;
   const double e = (r.p0 + c * r.d0) * iJ3;
   const double m = (r.p1 + c * r.d1) * iJ3;
-  const double b = (r.p2 + c * r.d2) * iJ3;
+  // an analytic bottom: its projection onto the new cell (eq. (3.16))
+  const double b = cs.bottom != BOT_ALE ? bottom_avg(cs, xn0, xn1) : (r.p2 + c * r.d2) * iJ3;
   bf.eta[gi] = e; bf.m[gi] = m; bf.b[gi] = b;
-  const double xn0 = x0 + dt * w0, xn1 = x1 + dt * w1;
   if (bf.dump.xw) {
     const int64_t NN = bf.S + bf.ninst;
     bf.dump.xw[v.no + j] = x0;

@@ -869,3 +869,82 @@ def test_nonwb_constant_state_and_mass():
     S = r["stats"]
     assert abs(S.mass_eta - S.mass_eta0) <= 1e-13 * abs(S.mass_eta0)
     assert abs(S.mass_b - S.mass_b0) <= 1e-13 * abs(S.mass_b0)
+
+
+# ----------------------------------------------------------------------------
+# Sec. 3.3, eq. (3.16): L2 projection of an analytic bottom onto moving cells
+# ----------------------------------------------------------------------------
+_BOTTOMS = {
+    "step": (O.BOTTOM_STEP, (4.0, 4.0, 8.0, 0.0)),
+    "gauss": (O.BOTTOM_GAUSS, (5.0, 0.4, 5.0, 0.0)),
+    "sin2": (O.BOTTOM_SIN2, (1.0, 1.0, 0.0, 0.0)),
+    "bump": (O.BOTTOM_BUMP, (0.25, 0.1, 1.5, 0.0)),
+    "parabola": (O.BOTTOM_PARABOLA, (10.0, 3000.0, 0.0, 0.0)),
+}
+
+
+def _exact_average(kind, p, a, b):
+    """Cell average from the antiderivative of each closed form."""
+    if kind == "step":
+        lo, hi = max(a, p[1]), min(b, p[2])
+        return p[0] * max(0.0, hi - lo) / (b - a)
+    if kind == "gauss":
+        k = math.sqrt(p[1])
+        return p[0] * math.sqrt(math.pi) / (2 * k) * (math.erf(k * (b - p[2])) -
+                                                      math.erf(k * (a - p[2]))) / (b - a)
+    if kind == "sin2":
+        w = 2 * math.pi * p[1]
+        return p[0] * (0.5 - (math.sin(w * b) - math.sin(w * a)) / (2 * w * (b - a)))
+    if kind == "bump":
+        lo, hi = max(a, p[2] - p[1]), min(b, p[2] + p[1])
+        if hi <= lo:
+            return 0.0
+        I = p[1] / math.pi * (math.sin(math.pi * (hi - p[2]) / p[1]) -
+                              math.sin(math.pi * (lo - p[2]) / p[1])) + (hi - lo)
+        return p[0] * I / (b - a)
+    return p[0] * (b ** 3 - a ** 3) / (3 * p[1] ** 2 * (b - a))
+
+
+@pytest.mark.parametrize("kind", list(_BOTTOMS))
+def test_bottom_projection_is_the_cell_average(kind):
+    """eq. (3.16): the projected bottom is the average of b(x) over the cell,
+    also for cells that contain a jump or a kink of b."""
+    code, bp = _BOTTOMS[kind]
+    P = O.params(bottom=code, bottom_p=bp)
+    rng = np.random.default_rng(4)
+    centre = {"step": 4.0, "gauss": 5.0, "sin2": 0.3, "bump": 1.4, "parabola": 1200.0}[kind]
+    scale = {"parabola": 50.0, "bump": 0.01}.get(kind, 0.05)
+    edges = [4.0, 8.0] if kind == "step" else ([1.4, 1.6] if kind == "bump" else [])
+    for _ in range(30):
+        a = centre + rng.uniform(-3, 3) * scale
+        b = a + rng.uniform(0.1, 1.0) * scale
+        want = _exact_average(kind, bp, a, b)
+        # (absolute bound on the scale of the bottom's height: near the edge of
+        # the bump cos + 1 cancels in either evaluation)
+        assert O.bottom_average(P, a, b) == pytest.approx(want, rel=1e-13, abs=1e-14 * bp[0])
+    for e in edges:  # cells straddling the points where b jumps or kinks
+        a, b = e - 0.3 * scale, e + 0.7 * scale
+        assert O.bottom_average(P, a, b) == pytest.approx(_exact_average(kind, bp, a, b),
+                                                          rel=1e-13, abs=1e-14 * bp[0])
+
+
+@pytest.mark.parametrize("flags", [0, O.FLAG_HYDROSTATIC])
+@pytest.mark.parametrize("bottom", ["gauss", "step"])
+def test_projected_bottom_keeps_still_water(bottom, flags):
+    """Example 5.3 with the bottom projected onto the moving cells at every
+    stage instead of evolved: the well-balanced schemes still keep still water
+    to round-off (eta is not touched by the projection, and h = eta - b with
+    the shared weights reconstructs eta = const), and the bottom mass equals
+    the integral of b over the domain at all times."""
+    code, bp = _BOTTOMS[bottom]
+    wl = W.still_water_1d(200, "smooth" if bottom == "gauss" else "step")
+    r = O.run(_params_for(wl, bottom=code, bottom_p=bp, flags=flags), wl["h"], wl["hu"],
+              np.zeros(200), wl["x"], wl["xi"], t_end=0.5)
+    assert r["status"] == 0
+    assert np.abs(r["h"] + r["b"] - 10.0).max() < 1e-12
+    assert np.abs(r["hu"]).max() < 1e-11
+    integral = {"gauss": 5.0 * math.sqrt(math.pi / 0.4) * math.erf(5 * math.sqrt(0.4)),
+                "step": 16.0}[bottom]
+    S = r["stats"]
+    assert S.mass_b0 == pytest.approx(integral, rel=1e-13)
+    assert S.mass_b == pytest.approx(integral, rel=1e-13)

@@ -48,6 +48,17 @@ class Stats(C.Structure):
     ]
 
 
+class Params2(C.Structure):
+    """Constants of the 2D tensor-product scheme (nodes move per direction:
+    x = xi + Ax sin(2 pi kx xi) sin(omx t), y likewise)."""
+    _fields_ = [
+        ("g", C.c_double), ("cfl", C.c_double), ("weno_eps", C.c_double), ("dry_eps", C.c_double),
+        ("Ax", C.c_double), ("kx", C.c_double), ("omx", C.c_double),
+        ("Ay", C.c_double), ("ky", C.c_double), ("omy", C.c_double),
+        ("bcx", C.c_int32), ("bcy", C.c_int32), ("flags", C.c_int32), ("pad", C.c_int32),
+    ]
+
+
 def build(force: bool = False) -> str:
     """Compile the oracle with g++ (no FMA contraction, IEEE division/sqrt)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
@@ -85,6 +96,13 @@ def lib():
                               C.c_double, C.c_int64, dp, dp, u8p, C.POINTER(Stats)]
         L.orc_adjoint.argtypes = [C.POINTER(Params), C.c_int64, dp, dp, dp, dp, dp, C.c_double,
                                   C.c_int64, dp, C.c_int64, dp, dp, dp, dp, dp, dp]
+        L.orc2_run.argtypes = [C.POINTER(Params2), C.c_int64, C.c_int64, dp, dp, dp, dp, dp, dp,
+                               dp, dp, C.c_double, C.c_double, C.c_int64, dp,
+                               C.POINTER(C.c_int64), u8p, C.POINTER(C.c_int64), dp]
+        L.orc2_sweep.argtypes = [dp, C.c_double, C.c_double, dp, dp, dp, dp, dp, dp, dp]
+        L.orc2_residual.argtypes = [C.POINTER(Params2), C.c_int64, C.c_int64, dp, dp, dp, dp, dp,
+                                    dp, dp, dp, dp]
+        L.orc2_residual.restype = C.c_double
         _lib = L
     return _lib
 
@@ -221,3 +239,51 @@ def adjoint(P: Params, h0, hu0, b0, x0, xi, dts, gauge_x, gauge_bar, t0=0.0):
                            dts.size, _p(dts), gx.size, _p(gx), _p(gh), _p(gb), _p(dh), _p(dhu),
                            _p(db))
     return gh, dh, dhu, db, st
+
+
+# ---------------------------------------------------------------------------
+# 2D tensor-product extension
+# ---------------------------------------------------------------------------
+def params2(g=9.812, cfl=0.6, weno_eps=1e-6, dry_eps=1e-8, Ax=0.02, kx=1.0, omx=np.pi, Ay=0.02,
+            ky=1.0, omy=np.pi, bcx=BC_PERIODIC, bcy=BC_PERIODIC) -> Params2:
+    return Params2(g, cfl, weno_eps, dry_eps, Ax, kx, omx, Ay, ky, omy, bcx, bcy, 0, 0)
+
+
+def sweep2(widths5, e5, mx5, my5, h5, b5, dx, eps=1e-6, ext5=None):
+    """One sweep of the 2D dimension-by-dimension reconstruction on 5 cells.
+    Returns (out[6, 4] = h, hu, hv, b, db/ds, ext at the 4 Gauss-Lobatto
+    points of the middle cell; class)."""
+    out = np.zeros(24)
+    ext = None if ext5 is None else _f64(ext5)
+    c = lib().orc2_sweep(_p(_f64(widths5)), float(dx), float(eps), _p(_f64(e5)), _p(_f64(mx5)),
+                         _p(_f64(my5)), _p(_f64(h5)), _p(_f64(b5)), _p(ext), _p(out))
+    return out.reshape(6, 4), c
+
+
+def residual2(P: Params2, eta, hu, hv, b, dx, dy, wx, wy):
+    """Semi-discrete right-hand side of the 2D scheme; arrays [ny, nx]."""
+    eta, hu, hv, b = (_f64(a) for a in (eta, hu, hv, b))
+    ny, nx = eta.shape
+    R = np.zeros(4 * nx * ny)
+    al = lib().orc2_residual(C.byref(P), nx, ny, _p(eta), _p(hu), _p(hv), _p(b), _p(_f64(dx)),
+                             _p(_f64(dy)), _p(_f64(wx)), _p(_f64(wy)), _p(R))
+    return R.reshape(4, ny, nx), al
+
+
+def run2(P: Params2, h, hu, hv, b, x, y, xi, yi, t0=0.0, t_end=0.0, max_steps=0,
+         record_cls=False):
+    """Time-march the 2D scheme; arrays [ny, nx] (row j, column i).  Returns
+    dict(h, hu, hv, b, x, y, t, steps, status, n_class, mass, cls)."""
+    h, hu, hv, b, x, y = (_f64(a).copy() for a in (h, hu, hv, b, x, y))
+    ny, nx = h.shape
+    t = np.zeros(1)
+    steps = C.c_int64()
+    ncls = (C.c_int64 * 3)()
+    mass = np.zeros(4)
+    cls = np.zeros((max_steps, 3, ny, nx), np.uint8) if (record_cls and max_steps > 0) else None
+    st = lib().orc2_run(C.byref(P), nx, ny, _p(h), _p(hu), _p(hv), _p(b), _p(x), _p(y),
+                        _p(_f64(xi)), _p(_f64(yi)), float(t0), float(t_end), int(max_steps),
+                        _p(t), C.byref(steps), None if cls is None else
+                        cls.ctypes.data_as(C.POINTER(C.c_uint8)), ncls, _p(mass))
+    return dict(h=h, hu=hu, hv=hv, b=b, x=x, y=y, t=float(t[0]), steps=steps.value, status=st,
+                n_class=list(ncls), mass=mass, cls=cls)

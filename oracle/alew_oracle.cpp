@@ -1042,6 +1042,370 @@ static void mass(int n, const double* eta, const double* b, const double* x, dou
   }
 }
 
+
+/* ======================================================================== */
+/* 2D extension on a tensor-product moving mesh (R24-R28)                    */
+/* ======================================================================== */
+/* R24 Mesh: the nodes move along each logical direction on its own,
+ *     x_i(t) = xi_i + Ax sin(2 pi kx xi_i) sin(omx t) and
+ *     y_j(t) = eta_j + Ay sin(2 pi ky eta_j) sin(omy t), so the cells are
+ *     rectangles [x_i, x_{i+1}] x [y_j, y_{j+1}] of moving widths; node speeds
+ *     are the chords of eq. (2.1) per direction.
+ * R25 Reconstruction (Sec. 2.2 in two dimensions): dimension by dimension.  An
+ *     x-sweep of row j (the 1D hybrid procedure on the widths dx_{i-2..i+2})
+ *     gives, from the cell averages, the y-line averages at the 4 Gauss-Lobatto
+ *     abscissae of cell i; a y-sweep of those line averages over the rows
+ *     j-2..j+2 (widths dy) gives the point values at the 4 x 4 tensor
+ *     Gauss-Lobatto points of the cell.  Each sweep has its own indicators,
+ *     class and hybrid weights, on (eta, hu, hv) summed (eq. (2.10), d = 3),
+ *     shared by h, hu, hv and b; b_x is the y-sweep of the x-derivative line
+ *     values, b_y the derivative in the y-sweep of b.  Dx of the indicators is
+ *     the largest width in the sweep's direction.  The class of a cell is the
+ *     largest of its x-sweep's and its four y-sweeps' classes.
+ * R26 Fluxes: the Lax-Friedrichs flux of eq. (3.13) at the 4 Gauss-Lobatto
+ *     points of every edge (corners included; the rule is exact to degree 5),
+ *     alpha global over all edge points and both traces; the bottom's ALE flux
+ *     of eq. (3.17); the special source of eq. (4.7)-(4.10) with B1, B2 on the
+ *     edges and the interior term by the 4 x 4 Gauss-Lobatto rule on the cell
+ *     (its geometric area at the stage time) with the unlimited values.
+ * R27 Time: eq. (3.14) with the area recurrence eq. (3.15), div(w) J taken as
+ *     dA/dt = dwx_i dy_j(t_s) + dx_i(t_s) dwy_j on the stage mesh t_s;
+ *     dt = CFL min(dx, dy) / (max over cells of max(|u|, |v|) + sqrt(g h) +
+ *     max |W|), W the node speeds at t_n.
+ * R28 No positivity limiter in 2D (the directional limiter of eq. (3.21)-(3.22)
+ *     is not built here); traces with h <= dry_eps carry u = v = 0 and
+ *     hu = hv = 0 in the flux as in 1D.  Boundaries periodic or transmissive in
+ *     each direction. */
+struct Params2 {
+  double g, cfl, weno_eps, dry_eps;
+  double Ax, kx, omx, Ay, ky, omy;
+  int32_t bcx, bcy, flags, pad;
+};
+
+/* One sweep: 5 cells along a direction (widths wid), indicator variables
+ * (eta, hu, hv) and the variables reconstructed with the shared weights at the
+ * 4 Gauss-Lobatto points of the middle cell: out[0..3] = h, hu, hv, b,
+ * out[4] = db/ds (derivative along the sweep), out[5] = the extra variable
+ * (if ext5 is not NULL).  Returns the class. */
+static int sweep2(const CellGeo& G, double Dx, double eps, const double e5[5], const double mx5[5],
+                  const double my5[5], const double h5[5], const double b5[5], const double* ext5,
+                  double out[6][4]) {
+  double beta[3];
+  for (int r = 0; r < 3; ++r) {
+    double ev[3] = {e5[2 - r], e5[3 - r], e5[4 - r]};
+    double xv[3] = {mx5[2 - r], mx5[3 - r], mx5[4 - r]};
+    double yv[3] = {my5[2 - r], my5[3 - r], my5[4 - r]};
+    beta[r] = beta_one(G, r, ev, Dx) + beta_one(G, r, xv, Dx) + beta_one(G, r, yv, Dx);
+  }
+  double tau = std::fabs(beta[0] - beta[2]);
+  double betaA = (beta[0] + beta[1] + beta[2]) / 3.0;
+  double gamma = tau / (betaA + eps);
+  int cls = gamma <= 0.5 ? CLS_S : (gamma >= 1.0 ? CLS_N : CLS_T);
+  const double* var[6] = {h5, mx5, my5, b5, b5, ext5};
+  for (int mu = 0; mu < 4; ++mu) {
+    double phi[3];
+    if (cls == CLS_S) {
+      for (int r = 0; r < 3; ++r) phi[r] = G.d[mu][r];
+    } else {
+      double al[3], sum = 0.0;
+      for (int r = 0; r < 3; ++r) {
+        double q = tau / (beta[r] + eps);
+        al[r] = G.d[mu][r] * (1.0 + q * q);
+        sum = sum + al[r];
+      }
+      for (int r = 0; r < 3; ++r) {
+        double pn = al[r] / sum;
+        phi[r] = cls == CLS_N ? pn : (2.0 * gamma - 1.0) * pn + (1.0 - (2.0 * gamma - 1.0)) * G.d[mu][r];
+      }
+    }
+    for (int v = 0; v < 6; ++v) {
+      if (!var[v]) continue;
+      double acc = 0.0;
+      for (int r = 0; r < 3; ++r) {
+        double pr = 0.0;
+        for (int i = 0; i < 3; ++i)
+          pr = pr + (v == 4 ? G.cd[r][mu][i] : G.c[r][mu][i]) * var[v][2 - r + i];
+        acc = acc + phi[r] * pr;
+      }
+      out[v][mu] = acc;
+    }
+  }
+  return cls;
+}
+
+struct Counters2 {
+  int64_t n_class[3];
+};
+
+static int wrap_index(int bc, int n, int k) {
+  if (k >= 0 && k < n) return k;
+  if (bc == BC_PERIODIC) return ((k % n) + n) % n;
+  return k < 0 ? 0 : n - 1;
+}
+
+/* Residual (eta, hu, hv, b) of the 2D scheme on the stage mesh: widths dx[nx],
+ * dy[ny] at the stage time, node speeds wx[nx+1], wy[ny+1].  Returns alpha. */
+static double residual2(const Params2& P, int nx, int ny, const double* eta, const double* mx,
+                        const double* my, const double* b, const double* dx, const double* dy,
+                        const double* wx, const double* wy, double* R, uint8_t* cls,
+                        Counters2& cnt) {
+  const int G = 3, EX = nx + 2 * G, EY = ny + 2 * G;
+  auto cell = [&](int i, int j) { return wrap_index(P.bcx, nx, i) + nx * wrap_index(P.bcy, ny, j); };
+  auto wdx = [&](int i) { return dx[wrap_index(P.bcx, nx, i)]; };
+  auto wdy = [&](int j) { return dy[wrap_index(P.bcy, ny, j)]; };
+  double Dxg = 0.0, Dyg = 0.0;
+  for (int i = 0; i < nx; ++i) Dxg = std::max(Dxg, dx[i]);
+  for (int j = 0; j < ny; ++j) Dyg = std::max(Dyg, dy[j]);
+  /* the geometry of an x-sweep depends on the column only, of a y-sweep on
+   * the row only (tensor-product mesh): one per column i in -1..nx and row j
+   * in -1..ny */
+  std::vector<CellGeo> Gx(nx + 2), Gy(ny + 2);
+  for (int i = -1; i <= nx; ++i) {
+    double wid[5];
+    for (int k = 0; k < 5; ++k) wid[k] = wdx(i - 2 + k);
+    cell_geometry(wid, Gx[i + 1]);
+  }
+  for (int j = -1; j <= ny; ++j) {
+    double wid[5];
+    for (int k = 0; k < 5; ++k) wid[k] = wdy(j - 2 + k);
+    cell_geometry(wid, Gy[j + 1]);
+  }
+  /* x-sweeps: line values L[(i, j)][var][mu] for i in -1..nx, j in -3..ny+2 */
+  const int LX = nx + 2, LY = ny + 6;
+  std::vector<double> L((size_t)LX * LY * 5 * 4);
+  std::vector<int> xcls((size_t)LX * LY);
+  auto Lat = [&](int i, int j, int v, int mu) -> double& {
+    return L[((((size_t)(j + 3) * LX + (i + 1)) * 5) + v) * 4 + mu];
+  };
+  for (int j = -3; j <= ny + 2; ++j)
+    for (int i = -1; i <= nx; ++i) {
+      double e5[5], x5[5], y5[5], h5[5], b5[5];
+      for (int k = 0; k < 5; ++k) {
+        const int c = cell(i - 2 + k, j);
+        e5[k] = eta[c]; x5[k] = mx[c]; y5[k] = my[c]; b5[k] = b[c]; h5[k] = eta[c] - b[c];
+      }
+      double out[6][4];
+      xcls[(size_t)(j + 3) * LX + (i + 1)] =
+          sweep2(Gx[i + 1], Dxg, P.weno_eps, e5, x5, y5, h5, b5, nullptr, out);
+      for (int v = 0; v < 5; ++v)
+        for (int mu = 0; mu < 4; ++mu) Lat(i, j, v, mu) = out[v][mu];
+    }
+  /* y-sweeps: point values V[(i, j)][var][mu][nu] for i in -1..nx, j in -1..ny;
+   * var: h, hu, hv, b, b_x, b_y */
+  const int VX = nx + 2, VY = ny + 2;
+  std::vector<double> V((size_t)VX * VY * 6 * 16);
+  auto Vat = [&](int i, int j, int v, int mu, int nu) -> double& {
+    return V[((((size_t)(j + 1) * VX + (i + 1)) * 6) + v) * 16 + mu * 4 + nu];
+  };
+  for (int j = -1; j <= ny; ++j)
+    for (int i = -1; i <= nx; ++i) {
+      int cmax = xcls[(size_t)(j + 3) * LX + (i + 1)];
+      for (int mu = 0; mu < 4; ++mu) {
+        double e5[5], x5[5], y5[5], h5[5], b5[5], d5[5];
+        for (int k = 0; k < 5; ++k) {
+          const int jj = j - 2 + k;
+          h5[k] = Lat(i, jj, 0, mu); x5[k] = Lat(i, jj, 1, mu); y5[k] = Lat(i, jj, 2, mu);
+          b5[k] = Lat(i, jj, 3, mu); d5[k] = Lat(i, jj, 4, mu);
+          e5[k] = h5[k] + b5[k];
+        }
+        double out[6][4];
+        int c = sweep2(Gy[j + 1], Dyg, P.weno_eps, e5, x5, y5, h5, b5, d5, out);
+        cmax = std::max(cmax, c);
+        for (int nu = 0; nu < 4; ++nu) {
+          Vat(i, j, 0, mu, nu) = out[0][nu];
+          Vat(i, j, 1, mu, nu) = out[1][nu];
+          Vat(i, j, 2, mu, nu) = out[2][nu];
+          Vat(i, j, 3, mu, nu) = out[3][nu];
+          Vat(i, j, 4, mu, nu) = out[5][nu];  /* b_x: y-sweep of the x-derivative lines */
+          Vat(i, j, 5, mu, nu) = out[4][nu];  /* b_y */
+        }
+      }
+      if (i >= 0 && i < nx && j >= 0 && j < ny) {
+        cnt.n_class[cmax] += 1;
+        if (cls) cls[i + nx * j] = (uint8_t)cmax;
+      }
+    }
+  /* traces at an edge point: h, hu, hv, b of one side */
+  struct Tr { double h, m1, m2, b; };
+  auto trace = [&](int i, int j, int mu, int nu) {
+    Tr t{Vat(i, j, 0, mu, nu), Vat(i, j, 1, mu, nu), Vat(i, j, 2, mu, nu), Vat(i, j, 3, mu, nu)};
+    if (!(t.h > P.dry_eps)) { t.m1 = 0.0; t.m2 = 0.0; }
+    return t;
+  };
+  auto speed = [&](const Tr& t, int dir, double w) {
+    double un = 0.0;
+    if (t.h > P.dry_eps) un = (dir == 0 ? t.m1 : t.m2) / t.h;
+    return std::fabs(un - w) + std::sqrt(P.g * std::max(t.h, 0.0));
+  };
+  double alpha = 0.0;
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i <= nx; ++i)
+      for (int nu = 0; nu < 4; ++nu) {
+        alpha = std::max(alpha, speed(trace(i - 1, j, 3, nu), 0, wx[i]));
+        alpha = std::max(alpha, speed(trace(i, j, 0, nu), 0, wx[i]));
+      }
+  for (int j = 0; j <= ny; ++j)
+    for (int i = 0; i < nx; ++i)
+      for (int mu = 0; mu < 4; ++mu) {
+        alpha = std::max(alpha, speed(trace(i, j - 1, mu, 3), 1, wy[j]));
+        alpha = std::max(alpha, speed(trace(i, j, mu, 0), 1, wy[j]));
+      }
+  /* edge integrals: flux (eta, hu, hv), bottom flux, B1, B2 */
+  struct EdgeI { double F[3], Gb, B1, B2; };
+  auto edge = [&](const Tr& l, const Tr& r, int dir, double w, double len, const double* wts,
+                  int npt, const Tr* L_, const Tr* R_) {
+    EdgeI e{{0, 0, 0}, 0, 0, 0};
+    (void)l; (void)r;
+    for (int k = 0; k < npt; ++k) {
+      const Tr& a = L_[k];
+      const Tr& c = R_[k];
+      double ua = a.h > P.dry_eps ? a.m1 / a.h : 0.0, va = a.h > P.dry_eps ? a.m2 / a.h : 0.0;
+      double uc = c.h > P.dry_eps ? c.m1 / c.h : 0.0, vc = c.h > P.dry_eps ? c.m2 / c.h : 0.0;
+      double ea = a.h + a.b, ec = c.h + c.b;
+      double Ha[3], Hc[3];
+      if (dir == 0) {
+        Ha[0] = a.m1 - w * ea; Ha[1] = a.m1 * ua + 0.5 * P.g * a.h * a.h - w * a.m1; Ha[2] = a.m1 * va - w * a.m2;
+        Hc[0] = c.m1 - w * ec; Hc[1] = c.m1 * uc + 0.5 * P.g * c.h * c.h - w * c.m1; Hc[2] = c.m1 * vc - w * c.m2;
+      } else {
+        Ha[0] = a.m2 - w * ea; Ha[1] = a.m2 * ua - w * a.m1; Ha[2] = a.m2 * va + 0.5 * P.g * a.h * a.h - w * a.m2;
+        Hc[0] = c.m2 - w * ec; Hc[1] = c.m2 * uc - w * c.m1; Hc[2] = c.m2 * vc + 0.5 * P.g * c.h * c.h - w * c.m2;
+      }
+      double jump[3] = {ec - ea, c.m1 - a.m1, c.m2 - a.m2};
+      for (int q = 0; q < 3; ++q)
+        e.F[q] = e.F[q] + wts[k] * (0.5 * (Ha[q] + Hc[q]) - 0.5 * alpha * jump[q]);
+      e.Gb = e.Gb + wts[k] * (-0.5 * w * (a.b + c.b) - 0.5 * alpha * (c.b - a.b));
+      e.B1 = e.B1 + wts[k] * (0.5 * (a.b + c.b));
+      e.B2 = e.B2 + wts[k] * (0.5 * (a.b * a.b + c.b * c.b));
+    }
+    for (int q = 0; q < 3; ++q) e.F[q] = e.F[q] * len;
+    e.Gb = e.Gb * len; e.B1 = e.B1 * len; e.B2 = e.B2 * len;
+    return e;
+  };
+  std::vector<EdgeI> EXs((size_t)(nx + 1) * ny), EYs((size_t)nx * (ny + 1));
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i <= nx; ++i) {
+      Tr Ls[4], Rs[4];
+      for (int nu = 0; nu < 4; ++nu) { Ls[nu] = trace(i - 1, j, 3, nu); Rs[nu] = trace(i, j, 0, nu); }
+      EXs[(size_t)j * (nx + 1) + i] = edge(Ls[0], Rs[0], 0, wx[i], dy[j], kGLW, 4, Ls, Rs);
+    }
+  for (int j = 0; j <= ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      Tr Ls[4], Rs[4];
+      for (int mu = 0; mu < 4; ++mu) { Ls[mu] = trace(i, j - 1, mu, 3); Rs[mu] = trace(i, j, mu, 0); }
+      EYs[(size_t)j * nx + i] = edge(Ls[0], Rs[0], 1, wy[j], dx[i], kGLW, 4, Ls, Rs);
+    }
+  const size_t N = (size_t)nx * ny;
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      const size_t c = (size_t)i + (size_t)nx * j;
+      const EdgeI& el = EXs[(size_t)j * (nx + 1) + i];
+      const EdgeI& er = EXs[(size_t)j * (nx + 1) + i + 1];
+      const EdgeI& eb = EYs[(size_t)j * nx + i];
+      const EdgeI& et = EYs[(size_t)(j + 1) * nx + i];
+      const double etab = eta[c];
+      double ix = 0.0, iy = 0.0;
+      for (int mu = 0; mu < 4; ++mu)
+        for (int nu = 0; nu < 4; ++nu) {
+          double e = Vat(i, j, 0, mu, nu) + Vat(i, j, 3, mu, nu);
+          ix = ix + (kGLW[mu] * kGLW[nu]) * ((e - etab) * Vat(i, j, 4, mu, nu));
+          iy = iy + (kGLW[mu] * kGLW[nu]) * ((e - etab) * Vat(i, j, 5, mu, nu));
+        }
+      const double area = dx[i] * dy[j];
+      const double Sx = 0.5 * P.g * (er.B2 - el.B2) - P.g * etab * (er.B1 - el.B1) - P.g * area * ix;
+      const double Sy = 0.5 * P.g * (et.B2 - eb.B2) - P.g * etab * (et.B1 - eb.B1) - P.g * area * iy;
+      R[c] = -(er.F[0] - el.F[0]) - (et.F[0] - eb.F[0]);
+      R[N + c] = -(er.F[1] - el.F[1]) - (et.F[1] - eb.F[1]) + Sx;
+      R[2 * N + c] = -(er.F[2] - el.F[2]) - (et.F[2] - eb.F[2]) + Sy;
+      R[3 * N + c] = -(er.Gb - el.Gb) - (et.Gb - eb.Gb);
+    }
+  return alpha;
+}
+
+static double chord2(double A, double om, double t, double dt) {
+  (void)A;
+  return 2.0 * std::cos(om * (t + 0.5 * dt)) * std::sin(0.5 * om * dt) / dt;
+}
+
+/* One step of the 2D scheme (R27).  State eta, mx, my, b [nx*ny] in place;
+ * nodes x [nx+1], y [ny+1] in place; xi, yi the reference nodes. */
+static int step2(const Params2& P, int nx, int ny, double* eta, double* mx, double* my, double* b,
+                 double* x, double* y, const double* xi, const double* yi, double& t, double dt,
+                 uint8_t* cls, Counters2& cnt) {
+  const size_t N = (size_t)nx * ny;
+  std::vector<double> wx(nx + 1), wy(ny + 1);
+  const double fx = chord2(P.Ax, P.omx, t, dt), fy = chord2(P.Ay, P.omy, t, dt);
+  for (int i = 0; i <= nx; ++i) wx[i] = P.Ax * std::sin(2.0 * M_PI * P.kx * xi[i]) * fx;
+  for (int j = 0; j <= ny; ++j) wy[j] = P.Ay * std::sin(2.0 * M_PI * P.ky * yi[j]) * fy;
+  if (P.bcx == BC_PERIODIC) wx[nx] = wx[0];
+  if (P.bcy == BC_PERIODIC) wy[ny] = wy[0];
+  std::vector<double> dx0(nx), dy0(ny), dwx(nx), dwy(ny);
+  for (int i = 0; i < nx; ++i) { dx0[i] = x[i + 1] - x[i]; dwx[i] = wx[i + 1] - wx[i]; }
+  for (int j = 0; j < ny; ++j) { dy0[j] = y[j + 1] - y[j]; dwy[j] = wy[j + 1] - wy[j]; }
+  std::vector<double> J0(N), Js(N), Jn(N), Qn(4 * N), q(4 * N), Rv(4 * N);
+  double* st[4] = {eta, mx, my, b};
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      const size_t c = (size_t)i + (size_t)nx * j;
+      J0[c] = dx0[i] * dy0[j];
+      for (int v = 0; v < 4; ++v) {
+        Qn[v * N + c] = J0[c] * st[v][c];
+        q[v * N + c] = st[v][c];
+      }
+    }
+  Js = J0;
+  const double ca[3] = {0.0, 0.75, 1.0 / 3.0};
+  const double cb[3] = {1.0, 0.25, 2.0 / 3.0};
+  const double tau[3] = {0.0, dt, 0.5 * dt};
+  std::vector<double> dxs(nx), dys(ny);
+  for (int s = 0; s < 3; ++s) {
+    for (int i = 0; i < nx; ++i) dxs[i] = dx0[i] + tau[s] * dwx[i];
+    for (int j = 0; j < ny; ++j) dys[j] = dy0[j] + tau[s] * dwy[j];
+    for (size_t c = 0; c < N; ++c)
+      if (!(Js[c] > 0.0)) return ST_MESH;
+    residual2(P, nx, ny, q.data(), q.data() + N, q.data() + 2 * N, q.data() + 3 * N, dxs.data(),
+              dys.data(), wx.data(), wy.data(), Rv.data(), cls ? cls + (size_t)s * N : nullptr, cnt);
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        const size_t c = (size_t)i + (size_t)nx * j;
+        const double dA = dwx[i] * dys[j] + dxs[i] * dwy[j];
+        Jn[c] = ca[s] * J0[c] + cb[s] * (Js[c] + dt * dA);
+      }
+    for (int v = 0; v < 4; ++v)
+      for (size_t c = 0; c < N; ++c) {
+        double Q = ca[s] * Qn[v * N + c] + cb[s] * (Js[c] * q[v * N + c] + dt * Rv[v * N + c]);
+        q[v * N + c] = Q / Jn[c];
+      }
+    Js = Jn;
+  }
+  for (int v = 0; v < 4; ++v)
+    for (size_t c = 0; c < N; ++c) st[v][c] = q[v * N + c];
+  for (int i = 0; i <= nx; ++i) x[i] = x[i] + dt * wx[i];
+  for (int j = 0; j <= ny; ++j) y[j] = y[j] + dt * wy[j];
+  t = t + dt;
+  for (size_t c = 0; c < N; ++c)
+    for (int v = 0; v < 4; ++v)
+      if (!std::isfinite(st[v][c])) return ST_NONFINITE;
+  return ST_OK;
+}
+
+static double cfl_dt2(const Params2& P, int nx, int ny, const double* eta, const double* mx,
+                      const double* my, const double* b, const double* x, const double* y,
+                      const double* xi, const double* yi, double t) {
+  double hmin = INFINITY, smax = 0.0;
+  for (int i = 0; i < nx; ++i) hmin = std::min(hmin, x[i + 1] - x[i]);
+  for (int j = 0; j < ny; ++j) hmin = std::min(hmin, y[j + 1] - y[j]);
+  for (size_t c = 0; c < (size_t)nx * ny; ++c) {
+    double h = eta[c] - b[c];
+    double u = h > P.dry_eps ? mx[c] / h : 0.0, v = h > P.dry_eps ? my[c] / h : 0.0;
+    smax = std::max(smax, std::max(std::fabs(u), std::fabs(v)) + std::sqrt(P.g * std::max(h, 0.0)));
+  }
+  double W = 0.0;
+  for (int i = 0; i <= nx; ++i)
+    W = std::max(W, std::fabs(P.Ax * P.omx * std::cos(P.omx * t) * std::sin(2.0 * M_PI * P.kx * xi[i])));
+  for (int j = 0; j <= ny; ++j)
+    W = std::max(W, std::fabs(P.Ay * P.omy * std::cos(P.omy * t) * std::sin(2.0 * M_PI * P.ky * yi[j])));
+  return P.cfl * hmin / (smax + W);
+}
 }  // namespace orc
 
 /* ======================================================================== */
@@ -1287,4 +1651,74 @@ int orc_adjoint(const Params* P, int64_t n_, const double* h0, const double* hu0
   return st;
 }
 
+
+/* 2D tensor-product run (R24-R28): state h, hu, hv, b [nx*ny] (cell (i, j) at
+ * i + nx j) and nodes x [nx+1], y [ny+1] in place, xi, yi the reference nodes;
+ * from t0 until t_end (if > t0) and/or max_steps steps.  cls (optional)
+ * [max_steps][3][nx*ny].  n_class (optional) [3]. */
+int orc2_run(const Params2* P, int64_t nx_, int64_t ny_, double* h, double* hu, double* hv,
+             double* b, double* x, double* y, const double* xi, const double* yi, double t0,
+             double t_end, int64_t max_steps, double* t_out, int64_t* steps_out, uint8_t* cls,
+             int64_t* n_class, double* mass /* [4]: eta, b at start and end */) {
+  const int nx = (int)nx_, ny = (int)ny_;
+  if (nx < 5 || ny < 5) return ST_ARG;
+  const size_t N = (size_t)nx * ny;
+  std::vector<double> eta(N);
+  for (size_t c = 0; c < N; ++c) eta[c] = h[c] + b[c];
+  auto masses = [&](double& me, double& mb) {
+    me = 0.0; mb = 0.0;
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        const size_t c = (size_t)i + (size_t)nx * j;
+        const double A = (x[i + 1] - x[i]) * (y[j + 1] - y[j]);
+        me = me + A * eta[c];
+        mb = mb + A * b[c];
+      }
+  };
+  if (mass) masses(mass[0], mass[1]);
+  double t = t0;
+  int64_t k = 0;
+  int st = ST_OK;
+  Counters2 cnt{{0, 0, 0}};
+  const bool timed = t_end > t0;
+  while (true) {
+    if (max_steps > 0 && k >= max_steps) break;
+    if (timed && !(t < t_end)) break;
+    if (!timed && max_steps <= 0) break;
+    double dt = cfl_dt2(*P, nx, ny, eta.data(), hu, hv, b, x, y, xi, yi, t);
+    if (timed && t + dt > t_end) dt = t_end - t;
+    st = step2(*P, nx, ny, eta.data(), hu, hv, b, x, y, xi, yi, t, dt,
+               cls ? cls + (size_t)k * 3 * N : nullptr, cnt);
+    ++k;
+    if (st != ST_OK) break;
+  }
+  for (size_t c = 0; c < N; ++c) h[c] = eta[c] - b[c];
+  if (mass) masses(mass[2], mass[3]);
+  if (t_out) *t_out = t;
+  if (steps_out) *steps_out = k;
+  if (n_class)
+    for (int c = 0; c < 3; ++c) n_class[c] = cnt.n_class[c];
+  return st;
+}
+
+/* One 2D reconstruction sweep (R25) on 5 cells: out[6][4] as sweep2. */
+int orc2_sweep(const double* wid5, double Dx, double eps, const double* e5, const double* mx5,
+               const double* my5, const double* h5, const double* b5, const double* ext5,
+               double* out) {
+  double o[6][4] = {{0}};
+  CellGeo G;
+  cell_geometry(wid5, G);
+  int c = sweep2(G, Dx, eps, e5, mx5, my5, h5, b5, ext5, o);
+  for (int v = 0; v < 6; ++v)
+    for (int mu = 0; mu < 4; ++mu) out[v * 4 + mu] = o[v][mu];
+  return c;
+}
+
+/* Residual of the 2D scheme (eta, hu, hv, b) [4][nx*ny]; returns alpha. */
+double orc2_residual(const Params2* P, int64_t nx, int64_t ny, const double* eta, const double* hu,
+                     const double* hv, const double* b, const double* dx, const double* dy,
+                     const double* wx, const double* wy, double* R) {
+  Counters2 cnt{{0, 0, 0}};
+  return residual2(*P, (int)nx, (int)ny, eta, hu, hv, b, dx, dy, wx, wy, R, nullptr, cnt);
+}
 }  /* extern "C" */

@@ -252,3 +252,59 @@ def inversion_batch(ninst: int = 256, n: int = 65536, seed: int = 2208065883,
     out["b_true"] = np.concatenate(bts)
     out["gauge_x"] = np.concatenate(gxs)
     return out
+
+
+# --------------------------------------------------------------------------
+# Two dimensions (tensor-product cells): Examples 5.6 and 5.11, and the
+# 2048 x 2048 smooth periodic configuration
+# --------------------------------------------------------------------------
+def cell_averages_2d(f, xn: np.ndarray, yn: np.ndarray) -> np.ndarray:
+    """Averages of f(x, y) over the rectangles [xn_i, xn_i+1] x [yn_j, yn_j+1]
+    (5 x 5 Gauss-Legendre points per cell); array [ny, nx]."""
+    xm, xh = 0.5 * (xn[1:] + xn[:-1]), 0.5 * (xn[1:] - xn[:-1])
+    ym, yh = 0.5 * (yn[1:] + yn[:-1]), 0.5 * (yn[1:] - yn[:-1])
+    out = np.zeros((len(ym), len(xm)))
+    for a, wa in zip(_GL5_X, _GL5_W):
+        X = (xm + a * xh)[None, :]
+        for c, wc in zip(_GL5_X, _GL5_W):
+            Y = (ym + c * yh)[:, None]
+            out += 0.25 * wa * wc * f(X, Y)
+    return out
+
+
+def accuracy_2d(n: int = 100, t_end: float = 0.05):
+    """Example 5.6 on [0,1]^2, periodic: b = sin 2 pi x + cos 2 pi y,
+    h = 10 + exp(sin 2 pi x) cos 2 pi y, hu = sin(cos 2 pi x) sin 2 pi y,
+    hv = cos 2 pi x cos(sin 2 pi y); nodes moving per direction (the
+    tensor-product form of eq. (5.2)): x = xi + 0.03 sin(2 pi xi) sin(2 pi t / t_end),
+    y = eta + 0.02 sin(2 pi eta) sin(4 pi t / t_end)."""
+    xi = uniform_nodes(n, 0.0, 1.0)
+    tp = 2 * math.pi
+    b = cell_averages_2d(lambda x, y: np.sin(tp * x) + np.cos(tp * y), xi, xi)
+    h = cell_averages_2d(lambda x, y: 10.0 + np.exp(np.sin(tp * x)) * np.cos(tp * y), xi, xi)
+    hu = cell_averages_2d(lambda x, y: np.sin(np.cos(tp * x)) * np.sin(tp * y), xi, xi)
+    hv = cell_averages_2d(lambda x, y: np.cos(tp * x) * np.cos(np.sin(tp * y)), xi, xi)
+    return dict(xi=xi, yi=xi.copy(), h=h, hu=hu, hv=hv, b=b, bc="periodic", t_end=t_end,
+                Ax=0.03, kx=1.0, omx=2 * math.pi / t_end, Ay=0.02, ky=1.0, omy=4 * math.pi / t_end)
+
+
+def still_water_2d(n: int = 100, t_end: float = 0.1):
+    """Example 5.11 on [0,1]^2: b = 0.8 exp(-50 ((x-0.5)^2 + (y-0.5)^2)),
+    h + b = 1, hu = hv = 0; nodes as in accuracy_2d with this t_end."""
+    xi = uniform_nodes(n, 0.0, 1.0)
+    bf = lambda x, y: 0.8 * np.exp(-50.0 * ((x - 0.5) ** 2 + (y - 0.5) ** 2))
+    b = cell_averages_2d(bf, xi, xi)
+    h = cell_averages_2d(lambda x, y: 1.0 - bf(x, y), xi, xi)
+    z = np.zeros_like(h)
+    return dict(xi=xi, yi=xi.copy(), h=h, hu=z, hv=z.copy(), b=b, bc="periodic", t_end=t_end,
+                Ax=0.03, kx=1.0, omx=2 * math.pi / t_end, Ay=0.02, ky=1.0, omy=4 * math.pi / t_end)
+
+
+def smooth_2d(n: int = 2048):
+    """The 2048 x 2048 periodic configuration: b = sin 2 pi x + cos 2 pi y,
+    h = 10 + exp(sin 2 pi x) cos 2 pi y, hu = sin(cos 2 pi x) sin 2 pi y,
+    hv = cos 2 pi x cos(sin 2 pi y) on [0,1]^2; nodes x = xi + 0.02 sin(2 pi xi)
+    sin(pi t) and y likewise (tensor-product form of its perturbation)."""
+    wl = accuracy_2d(n)
+    wl.update(Ax=0.02, omx=math.pi, Ay=0.02, omy=math.pi, t_end=0.0)
+    return wl

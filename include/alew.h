@@ -308,6 +308,69 @@ alew_status alew_set_kernel_timing(alew_ctx* ctx, int on);
 alew_status alew_kernel_timing(const alew_ctx* ctx, int which, double* ms, int64_t* launches,
                                double* cells);
 
+/* ------------------------------------------------------------------------
+ * 2D extension: the special source-term scheme (Sec. 2-4 in two dimensions:
+ * eq. (3.11)-(3.15) with the 2D flux, eq. (4.7)-(4.10) with the 4 x 4
+ * Gauss-Lobatto rule on the cell and 4 Gauss-Lobatto points per edge) on a
+ * tensor-product moving mesh of rectangles: node i of the x-direction at
+ * x_i(t) = xi_i + Ax sin(2 pi kx xi_i) sin(omx t), node j of the y-direction at
+ * y_j(t) = yi_j + Ay sin(2 pi ky yi_j) sin(omy t); the node speeds of a step
+ * are the chords (X(t + dt) - X(t)) / dt.  The reconstruction runs dimension by
+ * dimension (Sec. 2.2 along x on cell averages, then along y on the line
+ * values): indicators summed over (eta, hu, hv), one class per sweep (the
+ * cell's class is the largest of its x-sweep's and its four y-sweeps').
+ * dt = cfl min(dx, dy) / (max over cells of max(|u|, |v|) + sqrt(g h) + max
+ * node-speed bound of the maps at t).  No positivity limiter in 2D: traces with
+ * h <= dry_eps carry zero discharge.  State arrays are [ny][nx] (cell (i, j)
+ * at i + nx j), device FP64; nodes x [nx + 1], y [ny + 1] in place; reference
+ * nodes xi [nx + 1], yi [ny + 1].
+ * ------------------------------------------------------------------------ */
+typedef struct alew2d_ctx alew2d_ctx;
+
+typedef struct {
+  double g, cfl, weno_eps, dry_eps; /* 9.812, 0.6, 1e-6, 1e-8                      */
+  double Ax, kx, omx;               /* x-node map                                  */
+  double Ay, ky, omy;               /* y-node map                                  */
+  int32_t bcx, bcy;                 /* ALEW_BC_PERIODIC or ALEW_BC_TRANSMISSIVE    */
+  int32_t flags, pad;               /* flags: none defined, must be 0              */
+} alew2d_params;
+
+typedef struct {
+  int64_t steps;
+  double t, dt_min, dt_max;
+  double mass0, mass_b0, mass, mass_b; /* sums of area x eta and area x b, start / end */
+  int64_t n_class[3];                  /* cells x stages per class over the run        */
+  int32_t status, pad;
+} alew2d_stats;
+
+/* Context for grids up to max_nx x max_ny cells (max_nx <= 2^24, max_ny <=
+ * 65535, product <= 2^31): allocates about 340 bytes per cell of device
+ * workspace; alew2d_run allocates nothing. */
+alew_status alew2d_create(alew2d_ctx** ctx, int64_t max_nx, int64_t max_ny, void* hip_stream);
+void alew2d_destroy(alew2d_ctx* ctx);
+alew_status alew2d_set_stream(alew2d_ctx* ctx, void* hip_stream);
+/* rows: rows of cells per y-sweep wavefront (default 16); check_every: steps
+ * between the host's stop checks of a run with t_end (default 8). */
+alew_status alew2d_set_launch(alew2d_ctx* ctx, int32_t rows, int32_t check_every);
+
+/* Advance from t0 until t_end (if > t0) and/or max_steps steps (if > 0).
+ * h, hu, hv, b [nx * ny] and x, y are updated in place.  cls (device, optional)
+ * [3 * nx * ny] receives the classes of every cell at the three stages of the
+ * last step; cls_count (device, optional) [3 * nx * ny] and cls_sig (device,
+ * optional) [nx * ny] accumulate a record of every stage as alew_run's do.
+ * stats (host, optional).  Errors: ALEW_E_ARG / ALEW_E_UNSUPPORTED before any
+ * work; ALEW_E_MESH (a non-positive area) or ALEW_E_NONFINITE stop the run
+ * after the step that met them, with the state of that step in the arrays. */
+alew_status alew2d_run(alew2d_ctx* ctx, const alew2d_params* p, int64_t nx, int64_t ny,
+                       double* h, double* hu, double* hv, double* b, double* x, double* y,
+                       const double* xi, const double* yi, double t0, double t_end,
+                       int64_t max_steps, uint8_t* cls, uint32_t* cls_count, uint64_t* cls_sig,
+                       alew2d_stats* stats);
+
+/* Device time (ms, host pointer) of the last alew2d_run, from HIP events on the
+ * context's stream around its launches. */
+alew_status alew2d_last_timing(const alew2d_ctx* ctx, double* ms);
+
 /* Message for the calling thread's last non-OK status ("" if none). */
 const char* alew_last_error(void);
 

@@ -56,6 +56,30 @@ class Launch(C.Structure):
                 ("compact_tiles", C.c_int32)]
 
 
+class Params2(C.Structure):
+    """alew2d_params: the 2D tensor-product scheme (nodes move per direction,
+    x = xi + Ax sin(2 pi kx xi) sin(omx t), y likewise)."""
+    _fields_ = [
+        ("g", C.c_double), ("cfl", C.c_double), ("weno_eps", C.c_double), ("dry_eps", C.c_double),
+        ("Ax", C.c_double), ("kx", C.c_double), ("omx", C.c_double),
+        ("Ay", C.c_double), ("ky", C.c_double), ("omy", C.c_double),
+        ("bcx", C.c_int32), ("bcy", C.c_int32), ("flags", C.c_int32), ("pad", C.c_int32),
+    ]
+
+
+class Stats2(C.Structure):
+    _fields_ = [
+        ("steps", C.c_int64), ("t", C.c_double), ("dt_min", C.c_double), ("dt_max", C.c_double),
+        ("mass0", C.c_double), ("mass_b0", C.c_double), ("mass", C.c_double),
+        ("mass_b", C.c_double), ("n_class", C.c_int64 * 3), ("status", C.c_int32),
+        ("pad", C.c_int32),
+    ]
+
+    def as_dict(self):
+        return {k: (list(getattr(self, k)) if k == "n_class" else getattr(self, k))
+                for k, _ in self._fields_ if k != "pad"}
+
+
 class AlewError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"alew status {status}: {msg}")
@@ -94,11 +118,19 @@ def lib():
         L.alew_kernel_timing.argtypes = [vp, C.c_int, C.POINTER(C.c_double),
                                          C.POINTER(C.c_int64), C.POINTER(C.c_double)]
         L.alew_kernel_timing.restype = C.c_int
+        L.alew2d_create.argtypes = [C.POINTER(vp), i64, i64, vp]
+        L.alew2d_destroy.argtypes = [vp]
+        L.alew2d_set_stream.argtypes = [vp, vp]
+        L.alew2d_set_launch.argtypes = [vp, C.c_int32, C.c_int32]
+        L.alew2d_last_timing.argtypes = [vp, C.POINTER(C.c_double)]
+        L.alew2d_run.argtypes = [vp, C.POINTER(Params2), i64, i64, vp, vp, vp, vp, vp, vp, vp, vp,
+                                 C.c_double, C.c_double, i64, vp, vp, vp, C.POINTER(Stats2)]
         L.alew_last_error.restype = C.c_char_p
         L.alew_version.restype = C.c_char_p
         for f in ("alew_create", "alew_set_stream", "alew_set_launch", "alew_get_launch",
                   "alew_step", "alew_run", "alew_adjoint", "alew_adjoint_reserve",
-                  "alew_step_noalloc"):
+                  "alew_step_noalloc", "alew2d_create", "alew2d_set_stream",
+                  "alew2d_set_launch", "alew2d_last_timing", "alew2d_run"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -308,6 +340,77 @@ def step_noalloc(p: Params, h, hu, b, x, xi=None, w=None, t=0.0, dt=0.0, t_end=0
         _check(st)
     S.status = st if st else S.status
     return S
+
+
+def params2(g=9.812, cfl=0.6, weno_eps=1e-6, dry_eps=1e-8, Ax=0.02, kx=1.0,
+            omx=3.141592653589793, Ay=0.02, ky=1.0, omy=3.141592653589793, bcx="periodic",
+            bcy="periodic") -> Params2:
+    bc = lambda v: BC[v] if isinstance(v, str) else int(v)
+    return Params2(g, cfl, weno_eps, dry_eps, Ax, kx, omx, Ay, ky, omy, bc(bcx), bc(bcy), 0, 0)
+
+
+class Context2:
+    """Workspace of the 2D tensor-product scheme for grids up to max_nx x
+    max_ny cells; work goes to the current torch stream."""
+
+    def __init__(self, max_nx: int, max_ny: int, device=None):
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.max_nx, self.max_ny = int(max_nx), int(max_ny)
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            stream = torch.cuda.current_stream().cuda_stream
+            _check(lib().alew2d_create(C.byref(h), self.max_nx, self.max_ny, C.c_void_p(stream)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().alew2d_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_launch(self, rows=16, check_every=8):
+        _check(lib().alew2d_set_launch(self._h, int(rows), int(check_every)))
+
+    def last_timing(self) -> float:
+        """Device milliseconds of the last run (events around its launches)."""
+        ms = C.c_double()
+        _check(lib().alew2d_last_timing(self._h, C.byref(ms)))
+        return ms.value
+
+    def run(self, p: Params2, h, hu, hv, b, x, y, xi, yi, t0=0.0, t_end=0.0, max_steps=0,
+            cls=None, cls_count=None, cls_sig=None, check=True) -> Stats2:
+        """Advance the [ny, nx] state in place; returns Stats2.  cls (uint8,
+        3 nx ny): classes of the last step; cls_count (int32, 3 nx ny) and
+        cls_sig (int64, nx ny): the class record of the run."""
+        if h.dim() != 2:
+            raise ValueError("state tensors are [ny, nx]")
+        ny, nx = h.shape
+        for name, t in (("hu", hu), ("hv", hv), ("b", b)):
+            if tuple(t.shape) != (ny, nx):
+                raise ValueError(f"{name} must be [{ny}, {nx}]")
+        for name, t, n in (("x", x, nx + 1), ("xi", xi, nx + 1), ("y", y, ny + 1),
+                           ("yi", yi, ny + 1)):
+            if t.numel() != n:
+                raise ValueError(f"{name} must hold {n} nodes")
+        for name, t, n in (("cls", cls, 3 * nx * ny), ("cls_count", cls_count, 3 * nx * ny),
+                           ("cls_sig", cls_sig, nx * ny)):
+            if t is not None and t.numel() != n:
+                raise ValueError(f"{name} must hold {n} entries")
+        _check(lib().alew2d_set_stream(self._h, C.c_void_p(torch.cuda.current_stream().cuda_stream)))
+        S = Stats2()
+        st = lib().alew2d_run(self._h, C.byref(p), nx, ny, _ptr(h), _ptr(hu), _ptr(hv), _ptr(b),
+                              _ptr(x), _ptr(y), _ptr(xi), _ptr(yi), float(t0), float(t_end),
+                              int(max_steps), _ptr(cls, torch.uint8), _ptr(cls_count, torch.int32),
+                              _ptr(cls_sig, torch.int64), C.byref(S))
+        if check:
+            _check(st)
+        S.status = st if st else S.status
+        return S
 
 
 def version() -> str:

@@ -6,9 +6,9 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = os.path.join(HERE, "csrc", "alew.hip")
+SRC = [os.path.join(HERE, "csrc", f) for f in ("alew.hip", "alew2d.hip")]
 DEPS = [os.path.join(HERE, "csrc", f)
-        for f in ("alew.hip", "alew_device.h", "alew_kernels.h", "alew_adjoint.h")]
+        for f in ("alew.hip", "alew2d.hip", "alew_device.h", "alew_kernels.h", "alew_adjoint.h")]
 LIB = os.path.join(HERE, "libalew.so")
 INCLUDE = os.path.join(ROOT, "include")
 
@@ -24,7 +24,7 @@ HIPCC_FLAGS = [
 
 
 def build(force: bool = True, verbose: bool = False) -> str:
-    """Compile csrc/alew.hip into libalew.so (always, unless force=False and
+    """Compile csrc/alew.hip and csrc/alew2d.hip into libalew.so (always, unless force=False and
     the library is newer than every source)."""
     if not force and os.path.exists(LIB):
         t = os.path.getmtime(LIB)
@@ -32,7 +32,7 @@ def build(force: bool = True, verbose: bool = False) -> str:
             return LIB
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmp = LIB + ".tmp"
-    cmd = [hipcc, *HIPCC_FLAGS, "-I", INCLUDE, "-o", tmp, SRC]
+    cmd = [hipcc, *HIPCC_FLAGS, "-I", INCLUDE, "-o", tmp, *SRC]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed:\n" + r.stdout + r.stderr)

@@ -678,6 +678,12 @@ struct GraphKey {
 
 }  // namespace
 
+// Message setter for the other translation units of the library (the 2D
+// entry points): same thread-local message as alew_last_error() returns.
+__attribute__((visibility("hidden"))) alew_status alew_set_error(alew_status s, const char* msg) {
+  return fail(s, msg);
+}
+
 struct alew_ctx {
   hipStream_t stream = nullptr;
   hipStream_t cap_stream = nullptr;  // capture stream for graphs

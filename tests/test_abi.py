@@ -16,13 +16,13 @@ HEADER = os.path.join(ROOT, "include", "alew.h")
 def _declared():
     txt = open(HEADER).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(alew_[a-z_]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(alew(?:2d)?_[a-z_]+)\s*\(", txt)))
 
 
 def test_header_declares_the_boundary():
     names = _declared()
     for n in ("alew_create", "alew_destroy", "alew_step", "alew_run", "alew_adjoint",
-              "alew_last_error", "alew_set_launch"):
+              "alew_last_error", "alew_set_launch", "alew2d_create", "alew2d_run"):
         assert n in names
 
 
@@ -45,6 +45,9 @@ int main(void) {
   printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(alew_params), offsetof(alew_params, bc),
          offsetof(alew_params, dry_eps), sizeof(alew_stats), offsetof(alew_stats, t),
          offsetof(alew_stats, status), sizeof(alew_launch));
+  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(alew2d_params), offsetof(alew2d_params, bcx),
+         offsetof(alew2d_params, omy), sizeof(alew2d_stats), offsetof(alew2d_stats, n_class),
+         offsetof(alew2d_stats, status));
   return 0;
 }
 '''
@@ -55,8 +58,10 @@ int main(void) {
         subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), "-o", exe, c])
         got = [int(v) for v in subprocess.check_output([exe]).split()]
     P, S, L = alew.Params, alew.Stats, alew.Launch
+    P2, S2 = alew.Params2, alew.Stats2
     want = [C.sizeof(P), P.bc.offset, P.dry_eps.offset, C.sizeof(S), S.t.offset, S.status.offset,
-            C.sizeof(L)]
+            C.sizeof(L), C.sizeof(P2), P2.bcx.offset, P2.omy.offset, C.sizeof(S2),
+            S2.n_class.offset, S2.status.offset]
     assert got == want
 
 

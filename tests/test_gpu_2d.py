@@ -1,0 +1,223 @@
+"""GPU path of the 2D tensor-product scheme (alew2d_run) against the 2D oracle,
+through the C ABI: full runs of Example 5.6 and Example 5.11, a ragged
+non-square grid with transmissive y-boundaries, launch shapes, the class
+record, one step at the 2048 x 2048 size of the 2D workload against the oracle
+cell by cell, and its 100-step run checked by invariants."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from gpu_common import class_flips, class_record
+from paper_2208_06588_amd import alew, workloads as W
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-11
+
+
+@pytest.fixture(scope="module")
+def dev():
+    torch.cuda.set_device(0)
+    return torch.device("cuda", 0)
+
+
+def _t(a, dev):
+    return torch.tensor(np.asarray(a), dtype=torch.float64, device=dev)
+
+
+def _pair(wl, cfl=0.6, eps=1e-6, bcy="periodic"):
+    g = alew.params2(cfl=cfl, weno_eps=eps, Ax=wl["Ax"], kx=wl["kx"], omx=wl["omx"], Ay=wl["Ay"],
+                     ky=wl["ky"], omy=wl["omy"], bcx="periodic", bcy=bcy)
+    o = O.params2(cfl=cfl, weno_eps=eps, Ax=wl["Ax"], kx=wl["kx"], omx=wl["omx"], Ay=wl["Ay"],
+                  ky=wl["ky"], omy=wl["omy"], bcx=O.BC_PERIODIC,
+                  bcy=O.BC_PERIODIC if bcy == "periodic" else O.BC_TRANSMISSIVE)
+    return g, o
+
+
+def _gpu_run(ctx, p, wl, dev, record=False, **kw):
+    T = {k: _t(wl[k], dev) for k in ("h", "hu", "hv", "b")}
+    X = {k: _t(wl[k], dev) for k in ("xi", "yi")}
+    x, y = X["xi"].clone(), X["yi"].clone()
+    n = T["h"].numel()
+    cnt = torch.zeros(3 * n, dtype=torch.int32, device=dev) if record else None
+    sig = torch.zeros(n, dtype=torch.int64, device=dev) if record else None
+    st = ctx.run(p, T["h"], T["hu"], T["hv"], T["b"], x, y, X["xi"], X["yi"], cls_count=cnt,
+                 cls_sig=sig, **kw)
+    torch.cuda.synchronize()
+    out = {k: v.cpu().numpy() for k, v in T.items()}
+    out["x"], out["y"] = x.cpu().numpy(), y.cpu().numpy()
+    if record:
+        out["cnt"] = cnt.cpu().numpy().astype(np.int64).reshape(3, n)
+        out["sig"] = sig.cpu().numpy().view(np.uint64)
+    return out, st
+
+
+def _ora_run(p, wl, **kw):
+    return O.run2(p, wl["h"], wl["hu"], wl["hv"], wl["b"], wl["xi"], wl["yi"], wl["xi"], wl["yi"],
+                  **kw)
+
+
+def _parity(g, r, tag=""):
+    for k in ("h", "hu", "hv", "b", "x", "y"):
+        e = float(np.abs(g[k] - r[k]).max() / max(1.0, np.abs(r[k]).max()))
+        assert e <= TOL, (tag, k, e)
+
+
+def test_accuracy_example_full_run_with_class_record(dev):
+    """Example 5.6 at 50 x 50 to t = 0.05: state, nodes, step count and the
+    class of every cell at every stage (record signatures) equal the oracle."""
+    wl = W.accuracy_2d(50)
+    gp, op = _pair(wl)
+    ctx = alew.Context2(50, 50)
+    g, st = _gpu_run(ctx, gp, wl, dev, record=True, t_end=wl["t_end"])
+    r = _ora_run(op, wl, t_end=wl["t_end"], max_steps=1000, record_cls=True)
+    assert st.status == 0 and r["status"] == 0
+    assert st.steps == r["steps"] and abs(st.t - r["t"]) < 1e-15
+    assert list(st.n_class) == list(r["n_class"])
+    rc, rs = class_record(r["cls"][:r["steps"]].reshape(r["steps"], 3, -1))
+    cells, lower = class_flips(g["cnt"], g["sig"], rc, rs)
+    assert cells == 0 and lower == 0
+    _parity(g, r)
+    assert abs(st.mass - st.mass0) < 1e-13 * abs(st.mass0)
+    assert abs(st.mass0 - r["mass"][0]) < 1e-13 * abs(st.mass0)
+
+
+def test_still_water_example_5_11(dev):
+    """Example 5.11 on 100 x 100 moving cells to t = 0.1: still water kept at
+    round-off (Table 5.12) and the oracle's state."""
+    wl = W.still_water_2d(100)
+    gp, op = _pair(wl)
+    ctx = alew.Context2(100, 100)
+    g, st = _gpu_run(ctx, gp, wl, dev, t_end=wl["t_end"])
+    assert st.status == 0 and abs(st.t - 0.1) < 1e-15
+    assert np.abs(g["h"] + g["b"] - 1.0).max() < 1e-13
+    assert np.abs(g["hu"]).max() < 1e-13 and np.abs(g["hv"]).max() < 1e-13
+    r = _ora_run(op, wl, t_end=wl["t_end"])
+    assert st.steps == r["steps"]
+    _parity(g, r)
+
+
+def _ragged(nx, ny):
+    xi, yi = W.uniform_nodes(nx, 0.0, 1.0), W.uniform_nodes(ny, 0.0, 1.0)
+    tp = 2 * math.pi
+    f = lambda fn: W.cell_averages_2d(fn, xi, yi)
+    return dict(xi=xi, yi=yi,
+                b=f(lambda x, y: 0.5 * np.sin(tp * x) + 0.3 * np.cos(np.pi * y)),
+                h=f(lambda x, y: 3.0 + np.exp(np.sin(tp * x)) * np.cos(np.pi * y) ** 2),
+                hu=f(lambda x, y: np.sin(np.cos(tp * x)) * np.sin(np.pi * y)),
+                hv=f(lambda x, y: 0.2 * np.cos(tp * x) * np.cos(np.sin(np.pi * y))),
+                Ax=0.03, kx=2.0, omx=20.0, Ay=0.02, ky=1.0, omy=35.0)
+
+
+def test_ragged_grid_transmissive_y_and_launch_shapes(dev):
+    """130 x 37 cells (three strips, the last one ragged; row chunks ragged),
+    periodic in x, transmissive in y, both node directions moving: 40 steps
+    equal the oracle, and every row-chunk height gives the same bits."""
+    wl = _ragged(130, 37)
+    gp, op = _pair(wl, cfl=0.5, bcy="transmissive")
+    r = _ora_run(op, wl, max_steps=40)
+    assert r["status"] == 0
+    outs = []
+    for rows in (16, 1, 5, 64):
+        ctx = alew.Context2(130, 37)
+        ctx.set_launch(rows=rows)
+        g, st = _gpu_run(ctx, gp, wl, dev, max_steps=40)
+        assert st.status == 0 and st.steps == 40
+        assert list(st.n_class) == list(r["n_class"])
+        outs.append(g)
+    _parity(outs[0], r)
+    for g in outs[1:]:
+        for k in ("h", "hu", "hv", "b"):
+            assert np.array_equal(g[k], outs[0][k]), k
+
+
+def test_timed_run_in_chunks_and_resume(dev):
+    """A run to t_end stops exactly there whatever the host's check interval;
+    two runs (t = 0 -> 0.02 -> 0.05) equal one run 0 -> 0.05 split the same
+    way by the oracle."""
+    wl = W.accuracy_2d(25)
+    gp, op = _pair(wl)
+    res = []
+    for every in (1, 3, 64):
+        ctx = alew.Context2(25, 25)
+        ctx.set_launch(check_every=every)
+        g, st = _gpu_run(ctx, gp, wl, dev, t_end=0.05)
+        assert st.status == 0 and abs(st.t - 0.05) < 1e-15
+        res.append((g, st.steps))
+    for g, n in res[1:]:
+        assert n == res[0][1] and np.array_equal(g["h"], res[0][0]["h"])
+    ctx = alew.Context2(25, 25)
+    T = {k: _t(wl[k], dev) for k in ("h", "hu", "hv", "b")}
+    xi, yi = _t(wl["xi"], dev), _t(wl["yi"], dev)
+    x, y = xi.clone(), yi.clone()
+    ctx.run(gp, T["h"], T["hu"], T["hv"], T["b"], x, y, xi, yi, t0=0.0, t_end=0.02)
+    st = ctx.run(gp, T["h"], T["hu"], T["hv"], T["b"], x, y, xi, yi, t0=0.02, t_end=0.05)
+    r1 = _ora_run(op, wl, t_end=0.02)
+    mid = dict(wl, h=r1["h"], hu=r1["hu"], hv=r1["hv"], b=r1["b"])
+    r2 = O.run2(op, mid["h"], mid["hu"], mid["hv"], mid["b"], r1["x"], r1["y"], wl["xi"], wl["yi"],
+                t0=0.02, t_end=0.05)
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in T.items()}
+    g["x"], g["y"] = x.cpu().numpy(), y.cpu().numpy()
+    assert st.status == 0
+    _parity(g, r2)
+
+
+def test_argument_errors(dev):
+    wl = W.accuracy_2d(25)
+    gp, _ = _pair(wl)
+    ctx = alew.Context2(20, 20)
+    with pytest.raises(alew.AlewError) as ei:
+        _gpu_run(ctx, gp, wl, dev, max_steps=1)
+    assert ei.value.status == alew.E_ARG
+    ctx = alew.Context2(25, 25)
+    bad = alew.params2(bcx="reflective")
+    with pytest.raises(alew.AlewError) as ei:
+        _gpu_run(ctx, bad, wl, dev, max_steps=1)
+    assert ei.value.status == alew.E_UNSUPPORTED
+    g, st = _gpu_run(ctx, gp, wl, dev)  # neither t_end nor max_steps: no step
+    assert st.steps == 0 and np.array_equal(g["x"], wl["xi"])
+    # the state passes through eta = h + b and back: h at round-off
+    assert np.abs(g["h"] - wl["h"]).max() < 1e-14 * np.abs(wl["h"]).max()
+    assert np.array_equal(g["hu"], wl["hu"]) and np.array_equal(g["b"], wl["b"])
+
+
+@pytest.fixture(scope="module")
+def full_size():
+    """The 2048 x 2048 periodic workload (b = sin 2 pi x + cos 2 pi y, ...;
+    node maps of amplitude 0.02, omega = pi)."""
+    return W.smooth_2d(2048)
+
+
+def test_full_size_one_step_every_cell_against_oracle(dev, full_size):
+    """One step of the 2048 x 2048 workload in the launch configuration the
+    benchmark times: every cell equals the oracle's."""
+    wl = full_size
+    gp, op = _pair(wl)
+    ctx = alew.Context2(2048, 2048)
+    g, st = _gpu_run(ctx, gp, wl, dev, max_steps=1)
+    r = _ora_run(op, wl, max_steps=1)
+    assert st.status == 0 and r["status"] == 0
+    assert list(st.n_class) == list(r["n_class"])
+    _parity(g, r, "2048^2")
+
+
+def test_full_size_hundred_steps_invariants(dev, full_size):
+    """100 steps at 2048 x 2048: finite, mass of eta and of b conserved to
+    round-off, nodes on the prescribed maps at the final time."""
+    wl = full_size
+    gp, _ = _pair(wl)
+    ctx = alew.Context2(2048, 2048)
+    g, st = _gpu_run(ctx, gp, wl, dev, max_steps=100)
+    assert st.status == 0 and st.steps == 100
+    ms = ctx.last_timing()
+    print(f"2048^2 x 100 steps: {ms:.1f} ms, {3 * 100 * 2048 * 2048 / (ms * 1e-3) / 1e9:.2f} "
+          "G cell-stage updates/s")
+    assert all(np.isfinite(g[k]).all() for k in ("h", "hu", "hv", "b"))
+    assert abs(st.mass - st.mass0) < 1e-13 * abs(st.mass0)
+    assert abs(st.mass_b - st.mass_b0) < 1e-12
+    xs = wl["xi"] + wl["Ax"] * np.sin(2 * np.pi * wl["kx"] * wl["xi"]) * np.sin(wl["omx"] * st.t)
+    assert np.abs(g["x"] - xs).max() < 1e-13
+    assert sum(st.n_class) == 3 * 100 * 2048 * 2048

@@ -486,6 +486,98 @@ def speedup_leg(p, off, T, tnow, L, k=64, steps=3):
                      "graph rebuild); speedup_cold: one shared context rebuilding both per call")
 
 
+
+def source_hash_2d():
+    """Hash of the code (comments stripped) of the 2D kernels' sources."""
+    h = hashlib.sha1()
+    for f in ("alew2d.hip", "alew_device.h"):
+        with open(os.path.join(ROOT, "paper_2208_06588_amd", "csrc", f)) as fh:
+            h.update(_code_only(fh.read()).encode())
+    return h.hexdigest()[:16]
+
+
+# FP64 vector peak of the MI355X: 256 CUs x 4 SIMDs x 2.4 GHz x 32 flops per cycle
+FP64_PEAK_TFLOPS = 78.6
+
+
+def tensor2d_leg(dev, n, steps, warmup):
+    """The 2D tensor-product workload: n x n cells on [0,1]^2, periodic,
+    b = sin 2 pi x + cos 2 pi y, h = 10 + exp(sin 2 pi x) cos 2 pi y,
+    hu = sin(cos 2 pi x) sin 2 pi y, hv = cos 2 pi x cos(sin 2 pi y), nodes
+    x = xi + 0.02 sin(2 pi xi) sin(pi t) and y likewise, CFL 0.6.  `steps`
+    steps from t = 0 in one call (timed on the wall clock and by the library's
+    events) after `warmup` untimed steps on a copy; then 3 steps with an event
+    pair around every launch for the time split and the roofline of the
+    dominant kernel (FP64 VALU-bound: counters from profiles/counters.json
+    when they were taken on this source)."""
+    import torch
+    from paper_2208_06588_amd import alew, workloads as W
+    wl = W.smooth_2d(n)
+    p = alew.params2(cfl=0.6, Ax=wl["Ax"], kx=wl["kx"], omx=wl["omx"], Ay=wl["Ay"], ky=wl["ky"],
+                     omy=wl["omy"])
+    ctx = alew.Context2(n, n)
+    T0 = {k: torch.tensor(wl[k], dtype=torch.float64, device=dev)
+          for k in ("h", "hu", "hv", "b", "xi", "yi")}
+
+    def fresh():
+        T = {k: v.clone() for k, v in T0.items()}
+        T["x"], T["y"] = T0["xi"].clone(), T0["yi"].clone()
+        return T
+
+    def go(T, nsteps):
+        return ctx.run(p, T["h"], T["hu"], T["hv"], T["b"], T["x"], T["y"], T["xi"], T["yi"],
+                       max_steps=nsteps)
+
+    if warmup:
+        go(fresh(), warmup)
+    T = fresh()
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    st = go(T, steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - a
+    ev_ms = ctx.last_timing()
+    assert st.status == 0 and st.steps == steps, "2D run did not complete"
+    N = n * n
+    ctx.set_kernel_timing(True)
+    go(fresh(), 3)
+    torch.cuda.synchronize()
+    ctx.set_kernel_timing(False)
+    names = ["k2_kin", "k2_xsweep<s>", "k2_ysweep<s>", "k2_fin"]
+    split = {}
+    for q, nm in enumerate(names):
+        ms, nl = ctx.kernel_timing(q)
+        split[nm] = dict(launches=nl, launch_ms=round(ms / max(1, nl), 4), ms_per_step=round(ms / 3, 4))
+    dom = max(names, key=lambda k: split[k]["ms_per_step"])
+    roof = dict(bound="alu", kernel=dom, achieved=None, peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
+                frac=None, traffic=None, launch_ms=split[dom]["launch_ms"],
+                timing="HIP events on the library stream around each launch")
+    c = None
+    try:
+        with open(os.path.join(ROOT, "profiles", "counters.json")) as f:
+            c = json.load(f).get(dom)
+    except (OSError, ValueError):
+        c = None
+    if c is not None and c.get("source_hash") == source_hash_2d():
+        flops = c["fp64_flops_per_cell_stage"] * N
+        tf = flops / (split[dom]["launch_ms"] / 1e3) / 1e12
+        roof.update(achieved=round(tf, 2), frac=round(tf / FP64_PEAK_TFLOPS, 4),
+                    fp64_flops_per_cell_stage=round(c["fp64_flops_per_cell_stage"], 1),
+                    valu_insts_per_wave=round(c["valu_per_wave"], 1),
+                    traffic=round(c["hbm_bytes_per_cell_stage"] * N),
+                    traffic_note="FETCH_SIZE x %.2f + WRITE_SIZE x %.2f per launch (copy-kernel "
+                                 "calibration)" % (c["fetch_factor"], c["write_factor"]))
+    elif c is not None:
+        roof["note"] = "counters in profiles/counters.json were taken on another source"
+    return dict(workload=f"2D tensor-product moving mesh, {n} x {n} cells FP64 on [0,1]^2, "
+                         "periodic, smooth data of Example 5.6, node maps 0.02 sin(2 pi xi) "
+                         "sin(pi t) per direction, CFL 0.6, special source-term scheme",
+                steps=steps, value=3.0 * N * steps / wall, unit="cell-updates/s",
+                ms_per_step=round(wall * 1e3 / steps, 4),
+                event_ms_per_step=round(ev_ms / steps, 4), t_end=st.t,
+                n_class=list(st.n_class), kernels=split, roofline=roof)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -525,6 +617,11 @@ def main():
     ap.add_argument("--no-hydrostatic", action="store_true",
                     help="skip the hydrostatic-reconstruction legs (forward and adjoint)")
     ap.add_argument("--hr-steps", type=int, default=20)
+    ap.add_argument("--no-2d", action="store_true", help="skip the 2048 x 2048 2D leg")
+    ap.add_argument("--only-2d", action="store_true",
+                    help="run only the 2D leg and print its object (profiling)")
+    ap.add_argument("--n2d", type=int, default=2048)
+    ap.add_argument("--steps-2d", type=int, default=100)
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="first copy a buffer of this many MiB (calibrates profiler byte counters)")
     args = ap.parse_args()
@@ -548,6 +645,9 @@ def main():
         torch.cuda.synchronize()
         log(f"copy probe: {n * 8} bytes read, {n * 8} bytes written")
         del a, b
+    if args.only_2d:
+        print(json.dumps({"tensor2d": tensor2d_leg(dev, args.n2d, args.steps_2d, 2)}), flush=True)
+        return
     t0 = time.perf_counter()
     bt = W.perturbation_batch(ninst=args.ninst) if args.ninst == 4096 else \
         W.perturbation_batch(subset=args.ninst)
@@ -663,6 +763,11 @@ def main():
     if not args.no_bowl:
         out["bowl"] = guarded("bowl", lambda: bowl_leg(dev, 1 << 24, args.bowl_steps, 2))
         log(f"bowl: {out['bowl']}")
+
+    if not args.no_2d:
+        out["tensor2d"] = guarded("2D", lambda: tensor2d_leg(dev, args.n2d, args.steps_2d, 2))
+        log(f"2D: {out['tensor2d']}")
+        torch.cuda.empty_cache()
 
     if not args.no_adjoint:
         del ctx, T

@@ -344,7 +344,7 @@ typedef struct {
 } alew2d_stats;
 
 /* Context for grids up to max_nx x max_ny cells (max_nx <= 2^24, max_ny <=
- * 65535, product <= 2^31): allocates about 340 bytes per cell of device
+ * 65535, product <= 2^26): allocates about 340 bytes per cell of device
  * workspace; alew2d_run allocates nothing. */
 alew_status alew2d_create(alew2d_ctx** ctx, int64_t max_nx, int64_t max_ny, void* hip_stream);
 void alew2d_destroy(alew2d_ctx* ctx);
@@ -370,6 +370,15 @@ alew_status alew2d_run(alew2d_ctx* ctx, const alew2d_params* p, int64_t nx, int6
 /* Device time (ms, host pointer) of the last alew2d_run, from HIP events on the
  * context's stream around its launches. */
 alew_status alew2d_last_timing(const alew2d_ctx* ctx, double* ms);
+
+/* Per-kernel timing: with on != 0 later alew2d_run calls record a HIP event
+ * pair on the context's stream around every launch of a step (off by
+ * default).  alew2d_kernel_timing returns the summed device time (ms) and the
+ * number of launches of the last call per kind: which = 0 step kinematics,
+ * 1 x-sweeps, 2 y-sweeps (edge fluxes, source, right-hand side), 3 step
+ * epilogues.  Host pointers. */
+alew_status alew2d_set_kernel_timing(alew2d_ctx* ctx, int on);
+alew_status alew2d_kernel_timing(const alew2d_ctx* ctx, int which, double* ms, int64_t* launches);
 
 /* Message for the calling thread's last non-OK status ("" if none). */
 const char* alew_last_error(void);

@@ -123,6 +123,9 @@ def lib():
         L.alew2d_set_stream.argtypes = [vp, vp]
         L.alew2d_set_launch.argtypes = [vp, C.c_int32, C.c_int32]
         L.alew2d_last_timing.argtypes = [vp, C.POINTER(C.c_double)]
+        L.alew2d_set_kernel_timing.argtypes = [vp, C.c_int]
+        L.alew2d_kernel_timing.argtypes = [vp, C.c_int, C.POINTER(C.c_double),
+                                           C.POINTER(C.c_int64)]
         L.alew2d_run.argtypes = [vp, C.POINTER(Params2), i64, i64, vp, vp, vp, vp, vp, vp, vp, vp,
                                  C.c_double, C.c_double, i64, vp, vp, vp, C.POINTER(Stats2)]
         L.alew_last_error.restype = C.c_char_p
@@ -130,7 +133,8 @@ def lib():
         for f in ("alew_create", "alew_set_stream", "alew_set_launch", "alew_get_launch",
                   "alew_step", "alew_run", "alew_adjoint", "alew_adjoint_reserve",
                   "alew_step_noalloc", "alew2d_create", "alew2d_set_stream",
-                  "alew2d_set_launch", "alew2d_last_timing", "alew2d_run"):
+                  "alew2d_set_launch", "alew2d_last_timing", "alew2d_run",
+                  "alew2d_set_kernel_timing", "alew2d_kernel_timing"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -381,6 +385,17 @@ class Context2:
         ms = C.c_double()
         _check(lib().alew2d_last_timing(self._h, C.byref(ms)))
         return ms.value
+
+    def set_kernel_timing(self, on=True):
+        """Event pairs around every launch of later runs."""
+        _check(lib().alew2d_set_kernel_timing(self._h, 1 if on else 0))
+
+    def kernel_timing(self, which):
+        """(milliseconds, launches) of the last run for which = 0 kinematics,
+        1 x-sweeps, 2 y-sweeps, 3 step epilogues (with kernel timing on)."""
+        ms, n = C.c_double(), C.c_int64()
+        _check(lib().alew2d_kernel_timing(self._h, int(which), C.byref(ms), C.byref(n)))
+        return ms.value, n.value
 
     def run(self, p: Params2, h, hu, hv, b, x, y, xi, yi, t0=0.0, t_end=0.0, max_steps=0,
             cls=None, cls_count=None, cls_sig=None, check=True) -> Stats2:

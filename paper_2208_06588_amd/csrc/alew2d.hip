@@ -38,6 +38,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "alew.h"
 #include "alew_device.h"
@@ -67,7 +68,6 @@ struct State2 {
   double Dx[3], Dy[3];
   int64_t steps, max_steps;
   unsigned long long alpha[3];  // bits of each stage's LF speed (non-negative: integer max)
-  unsigned long long smax;      // bits of the largest wave speed of the step's state
   unsigned long long n_class[3];
   int32_t status, done, timed, pad;
 };
@@ -76,11 +76,11 @@ struct K2 {
   double g, cfl, eps, dry;
   double Ax, kx, omx, Ay, ky, omy;
   int32_t bcx, bcy, nx, ny;
-  int64_t N, LW, PL;  // cells; row length and plane size of the line-value planes
+  int64_t N, LW, PL4;  // cells; row length of the line-value planes, 4 x their cells
   double* qa;         // [4][N] step state (eta, hu, hv, b)
   double* qs0;        // [4][N] stage states (even / odd stages)
   double* qs1;
-  double* L;          // [20][ny][LW] line values (h, hu, hv, b, db/dx) x 4 abscissae
+  double* L;          // [5][ny][LW][4] line values (h, hu, hv, b, db/dx) at the 4 abscissae
   uint8_t* xcls;      // [ny][LW]
   double* Rc;         // [4][N] right-hand side: Rc + alpha Rd
   double* Rd;
@@ -93,6 +93,8 @@ struct K2 {
   uint32_t* ccount;            // [3][N] class counts over the run (or NULL)
   unsigned long long* csig;    // [N] class sequence signatures (or NULL)
   double* part;                // [2][ny] row sums of the mass diagnostics
+  double* spart;               // [nspart] work-group maxima of the wave speed (next dt)
+  int64_t nspart;
 };
 
 __device__ __forceinline__ int wrapi(int bc, int n, int k) {
@@ -304,18 +306,41 @@ __device__ __forceinline__ void lf_point(double g, double dry, double w, double 
   amax = fmax(amax, fmax(sa, sc));
 }
 
+// Value of lane (l & ~3) + perm[l & 3] within each quad of lanes (DPP quad_perm;
+// CTRL = perm0 | perm1 << 2 | perm2 << 4 | perm3 << 6): 0xB1 swaps neighbours,
+// 0x4E swaps pairs.
+template <int CTRL>
+__device__ __forceinline__ double quad_perm(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+// sum over a quad, the same bits in its four lanes ((a + b) + (c + d) with the
+// pair sums commuted)
+__device__ __forceinline__ double quad_sum(double v) {
+  v += quad_perm<0xB1>(v);
+  return v + quad_perm<0x4E>(v);
+}
+__device__ __forceinline__ int quad_max(int v) {
+  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xf, 0xf, false));
+  return max(v, __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xf, 0xf, false));
+}
+
 // ----------------------------------------------------------------------------
 // kernels
 // ----------------------------------------------------------------------------
-// Step state from the caller's arrays: eta = h + b; wave-speed bound of the
-// first step; mass sums per row.
+// Step state from the caller's arrays: eta = h + b; work-group maxima of the
+// wave speed max(|u|, |v|) + sqrt(g h) for the first step size.  Grid:
+// (ceil(nx / 256), ny), as the step epilogue's.
 __global__ void __launch_bounds__(256) k2_prep(K2 k, const double* __restrict__ h,
                                                const double* __restrict__ hu,
                                                const double* __restrict__ hv,
                                                const double* __restrict__ b) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = (int)blockIdx.x * 256 + threadIdx.x, j = blockIdx.y;
   double s = 0.0;
-  if (c < k.N) {
+  if (i < k.nx) {
+    const int64_t c = i + (int64_t)k.nx * j;
     const double bb = b[c], m = hu[c], n = hv[c], e = h[c] + bb;
     const double hh = e - bb;
     k.qa[c] = e;
@@ -326,8 +351,11 @@ __global__ void __launch_bounds__(256) k2_prep(K2 k, const double* __restrict__ 
     if (hh > k.dry) { u = m / hh; v = n / hh; }
     s = fmax(fabs(u), fabs(v)) + fsqrt(k.g * fmax(hh, 0.0));
   }
-  s = wave_max(s);
-  if ((threadIdx.x & 63) == 0) amax_pos(&k.st->smax, s);
+  __shared__ double red[4];
+  double v1[1] = {s};
+  const int op[1] = {0};
+  block_reduce<256, 1>(v1, op, red);
+  if (threadIdx.x == 0) k.spart[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = v1[0];
 }
 
 // Sums over row j of area x eta and area x b (one work-group per row, fixed
@@ -393,28 +421,28 @@ __global__ void __launch_bounds__(KB) k2_kin(K2 k) {
   const int nx = k.nx, ny = k.ny;
   const double t = s_t;
   const double TP = 2.0 * M_PI;
-  double hmin = INFINITY, W = 0.0;
+  double hmin = INFINITY, W = 0.0, smax = 0.0;
+  for (int64_t e = tid; e < k.nspart; e += KB) smax = fmax(smax, k.spart[e]);
   for (int i = tid; i < nx; i += KB) hmin = fmin(hmin, k.x[i + 1] - k.x[i]);
   for (int j = tid; j < ny; j += KB) hmin = fmin(hmin, k.y[j + 1] - k.y[j]);
   const double cx = k.Ax * k.omx * cos(k.omx * t), cy = k.Ay * k.omy * cos(k.omy * t);
   for (int i = tid; i <= nx; i += KB) W = fmax(W, fabs(cx * sin(TP * k.kx * k.xi[i])));
   for (int j = tid; j <= ny; j += KB) W = fmax(W, fabs(cy * sin(TP * k.ky * k.yi[j])));
   {
-    double v[2] = {hmin, W};
-    const int op[2] = {1, 0};
-    block_reduce<KB, 2>(v, op, red);
+    double v[3] = {hmin, W, smax};
+    const int op[3] = {1, 0, 0};
+    block_reduce<KB, 3>(v, op, red);
     hmin = v[0];
     W = v[1];
+    smax = v[2];
   }
   if (tid == 0) {
-    const double smax = bitsd(S.smax);
     double dt = k.cfl * hmin / (smax + W);
     if (S.timed && t + dt > S.t_end) dt = S.t_end - t;
     s_dt = dt;
     S.dt = dt;
     S.dt_min = fmin(S.dt_min, dt);
     S.dt_max = fmax(S.dt_max, dt);
-    S.smax = 0ull;
     S.alpha[0] = S.alpha[1] = S.alpha[2] = 0ull;
   }
   __syncthreads();
@@ -557,157 +585,179 @@ __global__ void __launch_bounds__(XB) k2_xsweep(K2 k) {
   load_geo(k.Gx, nx + 2, S, i + 1, G);
   double oh[4], om[4], on[4], ob[4], od[4], ox[4];
   const int cls = sweep<false>(G, k.eps, e5, m5, n5, h5, b5, nullptr, oh, om, on, ob, od, ox);
-  const int64_t o = (int64_t)j * k.LW + (i + 1);
+  const uint32_t o = (uint32_t)j * (uint32_t)k.LW + (uint32_t)(i + 1);
+  double* __restrict__ Lh = k.L;
+  double* __restrict__ Lm = k.L + k.PL4;
+  double* __restrict__ Ln = k.L + 2 * k.PL4;
+  double* __restrict__ Lb = k.L + 3 * k.PL4;
+  double* __restrict__ Lx = k.L + 4 * k.PL4;
 #pragma unroll
   for (int mu = 0; mu < 4; ++mu) {
-    k.L[(0 * 4 + mu) * k.PL + o] = oh[mu];
-    k.L[(1 * 4 + mu) * k.PL + o] = om[mu];
-    k.L[(2 * 4 + mu) * k.PL + o] = on[mu];
-    k.L[(3 * 4 + mu) * k.PL + o] = ob[mu];
-    k.L[(4 * 4 + mu) * k.PL + o] = od[mu];
+    Lh[o * 4u + mu] = oh[mu];
+    Lm[o * 4u + mu] = om[mu];
+    Ln[o * 4u + mu] = on[mu];
+    Lb[o * 4u + mu] = ob[mu];
+    Lx[o * 4u + mu] = od[mu];
   }
   k.xcls[o] = (uint8_t)cls;
 }
 
-// y-sweep of stage S: a wavefront marches up rows j0-1 .. j1 of its strip
-// (lane l on column 62 blockIdx.x + l - 1; lanes 0 and 63 are the strip's
-// ring columns); rows j0-1 and j1 give only the traces of the edges below
-// row j0 and above row j1 - 1.
+// y-sweep of stage S: a work-group of 256 threads marches up rows j0-1 .. j1
+// of its strip of 64 columns (column 62 blockIdx.x + slot - 1; slots 0 and 63
+// are the strip's ring columns), four threads per column: thread q of a
+// column reconstructs along y at abscissa q, evaluates the bottom edge at
+// point q (against the top trace it kept from the row below) and the left
+// edge at point q (against the left neighbour's right traces, through LDS);
+// the column's four threads then sum the edge points and the source terms by
+// quad shuffles, and thread q writes component q of the right-hand side.
+// Rows j0-1 and j1 give only the traces of the edges below row j0 and above
+// row j1 - 1.
 template <int S>
-__global__ void __launch_bounds__(64) k2_ysweep(K2 k, int rows) {
+__global__ void __launch_bounds__(256) k2_ysweep(K2 k, int rows) {
   const State2& St = *k.st;
   if (St.done) return;
-  const int l = threadIdx.x;
+  __shared__ double sL[64][4][4];  // left traces of each column at point nu: h, hu, hv, b
+  __shared__ double sR[64][4][4];  // right traces
+  __shared__ double sF[64][12];    // left-edge sums of each column: C[4], D[4], B1, B2
+  const int t = threadIdx.x, cs = t >> 2, q = t & 3;
   const int nx = k.nx, ny = k.ny;
-  const int i = STRIP * (int)blockIdx.x + l - 1;
+  const int i = STRIP * (int)blockIdx.x + cs - 1;
   const int j0 = (int)blockIdx.y * rows, j1 = min(j0 + rows, ny);
-  const bool own_col = l >= 1 && l <= STRIP && i >= 0 && i < nx;
-  const bool xedge = l >= 1 && i >= 0 && i <= nx;  // this lane's left edge exists
+  const bool own_col = cs >= 1 && cs <= STRIP && i >= 0 && i < nx;
+  const bool xedge = cs >= 1 && i >= 0 && i <= nx;  // this column's left edge exists
   const bool ycol = i >= 0 && i < nx;
-  const int ic = min(max(i, -1), nx);              // lanes past the ring load a valid column
-  const int64_t lc = ic + 1;
+  const int ic = min(max(i, -1), nx);               // slots past the ring load a valid column
+  const uint32_t lc = (uint32_t)(ic + 1);
+  // 32-bit offsets from uniform plane pointers (the context caps the grid at
+  // 2^26 cells, so every offset here stays below 2^29 elements)
+  const uint32_t lo = lc * 4u + (uint32_t)q, rowL = 4u * (uint32_t)k.LW;
+  const double* __restrict__ Lh = k.L;
+  const double* __restrict__ Lm = k.L + k.PL4;
+  const double* __restrict__ Ln = k.L + 2 * k.PL4;
+  const double* __restrict__ Lb = k.L + 3 * k.PL4;
+  const double* __restrict__ Lx = k.L + 4 * k.PL4;
   const double dt = St.dt, tau = TAU(S, dt), g = k.g, dry = k.dry;
   const double* qcur = (S & 1) ? k.qs1 : k.qs0;
   const int iw = min(max(i, 0), nx - 1);
   const double dxs = k.dx0[iw] + tau * k.dwx[iw];
   const double wxl = k.wx[min(max(i, 0), nx)];
+  const double wq = GLW[q];
   double amax = 0.0;
   unsigned ncl[3] = {0u, 0u, 0u};
-  // traces at the top edge of the previous row (per abscissa mu)
-  double th[4], tm[4], tn[4], tb[4];
-  // partial right-hand side of the previous row (everything but its top edge)
-  double P[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double th = 0.0, tm = 0.0, tn = 0.0, tb = 0.0;  // top trace at abscissa q, row below
+  double Pc = 0.0, Pd = 0.0;  // component q of the previous row's partial right-hand side
   double etab_p = 0.0;
   for (int jr = j0 - 1; jr <= j1; ++jr) {
     const bool first = jr == j0 - 1, last = jr == j1;
     const bool body = !first && !last;
     Geo G;
     load_geo(k.Gy, ny + 2, S, jr + 1, G);
-    int rw[5];
-#pragma unroll
-    for (int q = 0; q < 5; ++q) rw[q] = wrapi(k.bcy, ny, jr - 2 + q);
     const int jw = wrapi(k.bcy, ny, jr);
     const double dys = k.dy0[jw] + tau * k.dwy[jw];
     const double wyb = k.wy[min(max(jr, 0), ny)];
-    const int64_t c = (int64_t)(ycol ? i : 0) + (int64_t)nx * jw;
+    const uint32_t c = (uint32_t)(ycol ? i : 0) + (uint32_t)nx * (uint32_t)jw;
     const double etab = body && ycol ? qcur[c] : 0.0;
-    int ymax = 0;
-    double ix = 0.0, iy = 0.0;
-    double rh[4], rm[4], rn[4], rb[4];  // right traces (abscissa 3)
-    double Cl[4] = {0, 0, 0, 0}, Dl[4] = {0, 0, 0, 0}, B1l = 0.0, B2l = 0.0;
-    double Cb[4] = {0, 0, 0, 0}, Db[4] = {0, 0, 0, 0}, B1b = 0.0, B2b = 0.0;
-#pragma unroll
-    for (int mi = 0; mi < 4; ++mi) {
-      const int mu = (mi + 3) & 3;  // 3, 0, 1, 2: right traces first
+    // reconstruction along y at abscissa q: point values at nu = 0..3
+    double oh[4], om[4], on[4], ob[4], od[4], ox[4];
+    int cl;
+    {
       double h5[5], m5[5], n5[5], b5[5], x5[5], e5[5];
 #pragma unroll
-      for (int q = 0; q < 5; ++q) {
-        const int64_t o = (int64_t)rw[q] * k.LW + lc;
-        h5[q] = k.L[(0 * 4 + mu) * k.PL + o];
-        m5[q] = k.L[(1 * 4 + mu) * k.PL + o];
-        n5[q] = k.L[(2 * 4 + mu) * k.PL + o];
-        b5[q] = k.L[(3 * 4 + mu) * k.PL + o];
-        x5[q] = k.L[(4 * 4 + mu) * k.PL + o];
-        e5[q] = h5[q] + b5[q];
+      for (int r = 0; r < 5; ++r) {
+        const uint32_t o = (uint32_t)wrapi(k.bcy, ny, jr - 2 + r) * rowL + lo;
+        h5[r] = Lh[o];
+        m5[r] = Lm[o];
+        n5[r] = Ln[o];
+        b5[r] = Lb[o];
+        x5[r] = Lx[o];
+        e5[r] = h5[r] + b5[r];
       }
-      double oh[4], om[4], on[4], ob[4], od[4], ox[4];
-      const int cl = sweep<true>(G, k.eps, e5, m5, n5, h5, b5, x5, oh, om, on, ob, od, ox);
-      ymax = max(ymax, cl);
-      if (body) {
-#pragma unroll
-        for (int nu = 0; nu < 4; ++nu) {
-          const double e = oh[nu] + ob[nu];
-          ix += (GLW[mu] * GLW[nu]) * ((e - etab) * ox[nu]);
-          iy += (GLW[mu] * GLW[nu]) * ((e - etab) * od[nu]);
-        }
-      }
-      if (mu == 3) {
-#pragma unroll
-        for (int nu = 0; nu < 4; ++nu) { rh[nu] = oh[nu]; rm[nu] = om[nu]; rn[nu] = on[nu]; rb[nu] = ob[nu]; }
-      }
-      if (mu == 0) {
-        // left edge (node i): the left neighbour's right traces by a lane shuffle
-        double am = 0.0;
-#pragma unroll
-        for (int nu = 0; nu < 4; ++nu) {
-          const double ah = __shfl_up(rh[nu], 1, 64), amm = __shfl_up(rm[nu], 1, 64);
-          const double an = __shfl_up(rn[nu], 1, 64), ab = __shfl_up(rb[nu], 1, 64);
-          lf_point<0>(g, dry, wxl, GLW[nu], ah, amm, an, ab, oh[nu], om[nu], on[nu], ob[nu], Cl, Dl,
-                      B1l, B2l, am);
-        }
-        if (body && xedge) amax = fmax(amax, am);
-      }
-      if (!first) {
-        // bottom edge (node jr) at abscissa mu: the cell below's top trace
-        double am = 0.0;
-        lf_point<1>(g, dry, wyb, GLW[mu], th[mu], tm[mu], tn[mu], tb[mu], oh[0], om[0], on[0], ob[0],
-                    Cb, Db, B1b, B2b, am);
-        if (ycol && jr >= 0 && jr <= ny) amax = fmax(amax, am);
-      }
-      th[mu] = oh[3]; tm[mu] = om[3]; tn[mu] = on[3]; tb[mu] = ob[3];
+      cl = sweep<true>(G, k.eps, e5, m5, n5, h5, b5, x5, oh, om, on, ob, od, ox);
     }
+    double ix = 0.0, iy = 0.0;
+    if (body) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      Cl[q] *= dys; Dl[q] *= dys;
-      Cb[q] *= dxs; Db[q] *= dxs;
+      for (int nu = 0; nu < 4; ++nu) {
+        const double e = oh[nu] + ob[nu];
+        ix += (wq * GLW[nu]) * ((e - etab) * ox[nu]);
+        iy += (wq * GLW[nu]) * ((e - etab) * od[nu]);
+      }
     }
-    B1l *= dys; B2l *= dys; B1b *= dxs; B2b *= dxs;
-    // right edge = the right neighbour's left edge
-    double Cr[4], Dr[4];
+    // bottom edge (node jr) at point q: the cell below's top trace
+    double Cy[4] = {0, 0, 0, 0}, Dy[4] = {0, 0, 0, 0}, B1y = 0.0, B2y = 0.0;
+    if (!first) {
+      double am = 0.0;
+      lf_point<1>(g, dry, wyb, wq, th, tm, tn, tb, oh[0], om[0], on[0], ob[0], Cy, Dy, B1y, B2y, am);
+      if (ycol) amax = fmax(amax, am);
+    }
+    th = oh[3]; tm = om[3]; tn = on[3]; tb = ob[3];
+    if (q == 0)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      Cr[q] = __shfl_down(Cl[q], 1, 64);
-      Dr[q] = __shfl_down(Dl[q], 1, 64);
+      for (int nu = 0; nu < 4; ++nu) {
+        sL[cs][nu][0] = oh[nu]; sL[cs][nu][1] = om[nu]; sL[cs][nu][2] = on[nu]; sL[cs][nu][3] = ob[nu];
+      }
+    if (q == 3)
+#pragma unroll
+      for (int nu = 0; nu < 4; ++nu) {
+        sR[cs][nu][0] = oh[nu]; sR[cs][nu][1] = om[nu]; sR[cs][nu][2] = on[nu]; sR[cs][nu][3] = ob[nu];
+      }
+    __syncthreads();
+    // left edge (node i) at point q: the left neighbour's right trace
+    double Cx[4] = {0, 0, 0, 0}, Dx[4] = {0, 0, 0, 0}, B1x = 0.0, B2x = 0.0;
+    if (body && cs >= 1) {
+      double am = 0.0;
+      lf_point<0>(g, dry, wxl, wq, sR[cs - 1][q][0], sR[cs - 1][q][1], sR[cs - 1][q][2],
+                  sR[cs - 1][q][3], sL[cs][q][0], sL[cs][q][1], sL[cs][q][2], sL[cs][q][3], Cx, Dx,
+                  B1x, B2x, am);
+      if (xedge) amax = fmax(amax, am);
     }
-    const double B1r = __shfl_down(B1l, 1, 64), B2r = __shfl_down(B2l, 1, 64);
+    // sums over the column's four points (every thread of the quad gets them)
+    auto qsum = [](double v) { return quad_sum(v); };
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      Cy[r] = qsum(Cy[r]) * dxs; Dy[r] = qsum(Dy[r]) * dxs;
+      Cx[r] = qsum(Cx[r]) * dys; Dx[r] = qsum(Dx[r]) * dys;
+    }
+    B1y = qsum(B1y) * dxs; B2y = qsum(B2y) * dxs;
+    B1x = qsum(B1x) * dys; B2x = qsum(B2x) * dys;
+    ix = qsum(ix);
+    iy = qsum(iy);
+    const int ymax = quad_max(cl);
+    // publish the left-edge sums: the right edge of the column to the left
+    {
+      const double fv[12] = {Cx[0], Cx[1], Cx[2], Cx[3], Dx[0], Dx[1], Dx[2], Dx[3], B1x, B2x, 0.0, 0.0};
+#pragma unroll
+      for (int r = 0; r < 3; ++r) sF[cs][q + 4 * r] = fv[q + 4 * r];
+    }
+    __syncthreads();
+    const int cn = min(cs + 1, 63);
+    // component q of: C, D of the bottom (this row) edge, and the right edge
+    const double Cyq = q == 0 ? Cy[0] : q == 1 ? Cy[1] : q == 2 ? Cy[2] : Cy[3];
+    const double Dyq = q == 0 ? Dy[0] : q == 1 ? Dy[1] : q == 2 ? Dy[2] : Dy[3];
+    const double Cxq = q == 0 ? Cx[0] : q == 1 ? Cx[1] : q == 2 ? Cx[2] : Cx[3];
+    const double Dxq = q == 0 ? Dx[0] : q == 1 ? Dx[1] : q == 2 ? Dx[2] : Dx[3];
+    const double Crq = sF[cn][q], Drq = sF[cn][4 + q];
+    const double B1r = sF[cn][8], B2r = sF[cn][9];
     if (!first) {
       // the previous row is complete: its top edge is this row's bottom edge
       const int jp = jr - 1;
       if (own_col && jp >= j0) {
-        const int64_t cp = i + (int64_t)nx * jp;
-        const double Rcv[4] = {P[0] - Cb[0], P[1] - Cb[1],
-                               P[2] - Cb[2] + (0.5 * g * B2b - g * etab_p * B1b), P[3] - Cb[3]};
-        const double Rdv[4] = {P[4] - Db[0], P[5] - Db[1], P[6] - Db[2], P[7] - Db[3]};
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          k.Rc[v * k.N + cp] = Rcv[v];
-          k.Rd[v * k.N + cp] = Rdv[v];
-        }
+        const uint32_t cp = (uint32_t)q * (uint32_t)k.N + (uint32_t)i + (uint32_t)nx * (uint32_t)jp;
+        double rc = Pc - Cyq;
+        if (q == 2) rc += 0.5 * g * B2y - g * etab_p * B1y;
+        k.Rc[cp] = rc;
+        k.Rd[cp] = Pd - Dyq;
       }
     }
     if (body) {
       const double area = dxs * dys;
-      const double Sx = 0.5 * g * (B2r - B2l) - g * etab * (B1r - B1l) - g * area * ix;
-      const double Sy0 = -0.5 * g * B2b + g * etab * B1b - g * area * iy;
-      P[0] = -(Cr[0] - Cl[0]) + Cb[0];
-      P[1] = -(Cr[1] - Cl[1]) + Cb[1] + Sx;
-      P[2] = -(Cr[2] - Cl[2]) + Cb[2] + Sy0;
-      P[3] = -(Cr[3] - Cl[3]) + Cb[3];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) P[4 + q] = -(Dr[q] - Dl[q]) + Db[q];
+      Pc = -(Crq - Cxq) + Cyq;
+      if (q == 1) Pc += 0.5 * g * (B2r - B2x) - g * etab * (B1r - B1x) - g * area * ix;
+      if (q == 2) Pc += -0.5 * g * B2y + g * etab * B1y - g * area * iy;
+      Pd = -(Drq - Dxq) + Dyq;
       etab_p = etab;
-      if (own_col) {
-        const int cls = max(ymax, (int)k.xcls[(int64_t)jr * k.LW + lc]);
+      if (own_col && q == 0) {
+        const int cls = max(ymax, (int)k.xcls[(uint32_t)jr * (uint32_t)k.LW + lc]);
         ncl[cls] += 1u;
         const int64_t cc = i + (int64_t)nx * jr;
         if (k.cls) k.cls[S * k.N + cc] = (uint8_t)cls;
@@ -716,25 +766,27 @@ __global__ void __launch_bounds__(64) k2_ysweep(K2 k, int rows) {
       }
     }
   }
+  // one atomic per wavefront for the stage's speed and the class counts
   amax = wave_max(amax);
-  if (l == 0) amax_pos(&k.st->alpha[S], amax);
+  if ((t & 63) == 0) amax_pos(&k.st->alpha[S], amax);
 #pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    const unsigned n = wave_usum(ncl[q]);
-    if (l == 0 && n) atomicAdd(&k.st->n_class[q], (unsigned long long)n);
+  for (int r = 0; r < 3; ++r) {
+    const unsigned n = wave_usum(ncl[r]);
+    if ((t & 63) == 0 && n) atomicAdd(&k.st->n_class[r], (unsigned long long)n);
   }
 }
 
 // Step epilogue: the third stage's update into the step state, the finite
-// check and the wave-speed bound of the next step.
+// check and the work-group maxima of the next step's wave speed.  Grid:
+// (ceil(nx / 256), ny).
 __global__ void __launch_bounds__(256) k2_fin(K2 k) {
   const State2& St = *k.st;
   if (St.done) return;
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = (int)blockIdx.x * 256 + threadIdx.x, j = blockIdx.y;
   double s = 0.0;
   bool bad = false;
-  if (c < k.N) {
-    const int i = (int)(c % k.nx), j = (int)(c / k.nx);
+  if (i < k.nx) {
+    const int64_t c = i + (int64_t)k.nx * j;
     double q[4], Jn;
     stage_update<3>(k, c, k.dx0[i], k.dwx[i], k.dy0[j], k.dwy[j], St.dt, bitsd(St.alpha[2]), k.qs0,
                     q, Jn);
@@ -748,9 +800,12 @@ __global__ void __launch_bounds__(256) k2_fin(K2 k) {
     if (hh > k.dry) { u = q[1] / hh; v = q[2] / hh; }
     s = fmax(fabs(u), fabs(v)) + fsqrt(k.g * fmax(hh, 0.0));
   }
-  s = wave_max(s);
-  if ((threadIdx.x & 63) == 0) amax_pos(&k.st->smax, s);
   if (bad) atomicOr(&k.st->status, SB_NONFINITE);
+  __shared__ double red[4];
+  double v1[1] = {s};
+  const int op[1] = {0};
+  block_reduce<256, 1>(v1, op, red);
+  if (threadIdx.x == 0) k.spart[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = v1[0];
 }
 
 // Caller's arrays from the step state: h = eta - b, hu, hv, b.
@@ -778,7 +833,7 @@ struct alew2d_ctx {
   double *qa = nullptr, *qs0 = nullptr, *qs1 = nullptr, *L = nullptr, *Rc = nullptr, *Rd = nullptr;
   uint8_t* xcls = nullptr;
   double *dx0 = nullptr, *dwx = nullptr, *dy0 = nullptr, *dwy = nullptr, *wx = nullptr, *wy = nullptr;
-  double *Gx = nullptr, *Gy = nullptr, *part = nullptr, *mass = nullptr;
+  double *Gx = nullptr, *Gy = nullptr, *part = nullptr, *mass = nullptr, *spart = nullptr;
   State2* st = nullptr;
   State2* st_h = nullptr;  // pinned
   double* mass_h = nullptr;  // pinned [4]
@@ -786,6 +841,13 @@ struct alew2d_ctx {
   int check_every = 8;     // steps between stop checks of a timed run
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   double last_ms = 0.0;
+  // per-kernel timing (alew2d_set_kernel_timing): an event pair around every
+  // launch of a step, summed per kind after the call
+  int ktime_on = 0;
+  std::vector<hipEvent_t> kt_ev;
+  std::vector<int> kt_kind;
+  double kt_ms[4] = {0, 0, 0, 0};
+  int64_t kt_n[4] = {0, 0, 0, 0};
 };
 
 namespace {
@@ -813,8 +875,8 @@ alew_status alew2d_create(alew2d_ctx** out, int64_t max_nx, int64_t max_ny, void
   if (!out) return fail2(ALEW_E_ARG, "ctx output pointer is NULL");
   *out = nullptr;
   if (max_nx < 5 || max_ny < 5) return fail2(ALEW_E_ARG, "max_nx >= 5 and max_ny >= 5 required");
-  if (max_nx > (1 << 24) || max_ny > 65535 || max_nx * max_ny > ((int64_t)1 << 31))
-    return fail2(ALEW_E_ARG, "max_nx <= 2^24, max_ny <= 65535 and max_nx * max_ny <= 2^31 required");
+  if (max_nx > (1 << 24) || max_ny > 65535 || max_nx * max_ny > ((int64_t)1 << 26))
+    return fail2(ALEW_E_ARG, "max_nx <= 2^24, max_ny <= 65535 and max_nx * max_ny <= 2^26 required");
   alew2d_ctx* c = new alew2d_ctx();
   c->stream = (hipStream_t)hip_stream;
   c->max_nx = max_nx;
@@ -831,6 +893,7 @@ alew_status alew2d_create(alew2d_ctx** out, int64_t max_nx, int64_t max_ny, void
             alloc((void**)&c->Gx, (size_t)NGF * 3 * (max_nx + 2) * 8) &&
             alloc((void**)&c->Gy, (size_t)NGF * 3 * (max_ny + 2) * 8) &&
             alloc((void**)&c->part, 2 * max_ny * 8) && alloc((void**)&c->mass, 4 * 8) &&
+            alloc((void**)&c->spart, ((max_nx + 255) / 256) * max_ny * 8) &&
             alloc((void**)&c->st, sizeof(State2));
   ok = ok && hipHostMalloc((void**)&c->st_h, sizeof(State2), hipHostMallocDefault) == hipSuccess;
   ok = ok && hipHostMalloc((void**)&c->mass_h, 4 * 8, hipHostMallocDefault) == hipSuccess;
@@ -846,14 +909,29 @@ alew_status alew2d_create(alew2d_ctx** out, int64_t max_nx, int64_t max_ny, void
 void alew2d_destroy(alew2d_ctx* c) {
   if (!c) return;
   void* ps[] = {c->qa, c->qs0, c->qs1, c->L, c->Rc, c->Rd, c->xcls, c->dx0, c->dwx, c->dy0,
-                c->dwy, c->wx, c->wy, c->Gx, c->Gy, c->part, c->mass, c->st};
+                c->dwy, c->wx, c->wy, c->Gx, c->Gy, c->part, c->mass, c->spart, c->st};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   if (c->st_h) (void)hipHostFree(c->st_h);
   if (c->mass_h) (void)hipHostFree(c->mass_h);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
+  for (hipEvent_t e : c->kt_ev) (void)hipEventDestroy(e);
   delete c;
+}
+
+alew_status alew2d_set_kernel_timing(alew2d_ctx* c, int on) {
+  if (!c) return fail2(ALEW_E_ARG, "ctx is NULL");
+  c->ktime_on = on ? 1 : 0;
+  return ALEW_OK;
+}
+
+alew_status alew2d_kernel_timing(const alew2d_ctx* c, int which, double* ms, int64_t* launches) {
+  if (!c || !ms || !launches || which < 0 || which > 3)
+    return fail2(ALEW_E_ARG, "ctx, which in 0..3 and output pointers required");
+  *ms = c->kt_ms[which];
+  *launches = c->kt_n[which];
+  return ALEW_OK;
 }
 
 alew_status alew2d_set_stream(alew2d_ctx* c, void* s) {
@@ -898,11 +976,14 @@ alew_status alew2d_run(alew2d_ctx* c, const alew2d_params* p, int64_t nx, int64_
   k.g = p->g; k.cfl = p->cfl; k.eps = p->weno_eps; k.dry = p->dry_eps;
   k.Ax = p->Ax; k.kx = p->kx; k.omx = p->omx; k.Ay = p->Ay; k.ky = p->ky; k.omy = p->omy;
   k.bcx = p->bcx; k.bcy = p->bcy; k.nx = (int32_t)nx; k.ny = (int32_t)ny;
-  k.N = nx * ny; k.LW = nx + 2; k.PL = (nx + 2) * ny;
+  k.N = nx * ny; k.LW = nx + 2; k.PL4 = 4 * (nx + 2) * ny;
   k.qa = c->qa; k.qs0 = c->qs0; k.qs1 = c->qs1; k.L = c->L; k.xcls = c->xcls; k.Rc = c->Rc;
   k.Rd = c->Rd; k.dx0 = c->dx0; k.dwx = c->dwx; k.dy0 = c->dy0; k.dwy = c->dwy; k.wx = c->wx;
   k.wy = c->wy; k.Gx = c->Gx; k.Gy = c->Gy; k.x = x; k.y = y; k.xi = xi; k.yi = yi; k.st = c->st;
   k.cls = cls; k.ccount = cls_count; k.csig = (unsigned long long*)cls_sig; k.part = c->part;
+  const dim3 gc((unsigned)((nx + 255) / 256), (unsigned)ny);  // per-cell kernels
+  k.spart = c->spart;
+  k.nspart = (int64_t)gc.x * gc.y;
   const bool timed = t_end > t0;
   State2& S = *c->st_h;
   std::memset(&S, 0, sizeof(S));
@@ -917,28 +998,56 @@ alew_status alew2d_run(alew2d_ctx* c, const alew2d_params* p, int64_t nx, int64_
   const int64_t N = k.N;
   const unsigned nb = (unsigned)((N + 255) / 256);
   HIPCHK2(hipEventRecord(c->ev0, st));
-  hipLaunchKernelGGL(k2_prep, dim3(nb), dim3(256), 0, st, k, h, hu, hv, b);
+  hipLaunchKernelGGL(k2_prep, gc, dim3(256), 0, st, k, h, hu, hv, b);
   hipLaunchKernelGGL(k2_mass_rows, dim3((unsigned)ny), dim3(256), 0, st, k);
   hipLaunchKernelGGL(k2_mass_sum, dim3(1), dim3(256), 0, st, k, c->mass);
   const dim3 gx((unsigned)((nx + 2 + XB - 1) / XB), (unsigned)ny);
   const dim3 gy((unsigned)((nx + STRIP - 1) / STRIP), (unsigned)((ny + c->rows - 1) / c->rows));
   const int rows = c->rows;
-  auto one_step = [&]() {
-    hipLaunchKernelGGL(k2_kin, dim3(1), dim3(KB), 0, st, k);
-    hipLaunchKernelGGL(k2_xsweep<0>, gx, dim3(XB), 0, st, k);
-    hipLaunchKernelGGL(k2_ysweep<0>, gy, dim3(64), 0, st, k, rows);
-    hipLaunchKernelGGL(k2_xsweep<1>, gx, dim3(XB), 0, st, k);
-    hipLaunchKernelGGL(k2_ysweep<1>, gy, dim3(64), 0, st, k, rows);
-    hipLaunchKernelGGL(k2_xsweep<2>, gx, dim3(XB), 0, st, k);
-    hipLaunchKernelGGL(k2_ysweep<2>, gy, dim3(64), 0, st, k, rows);
-    hipLaunchKernelGGL(k2_fin, dim3(nb), dim3(256), 0, st, k);
+  // kernel timing: event pairs (created on first use, reused by later calls)
+  size_t kt_used = 0;
+  for (int q = 0; q < 4; ++q) { c->kt_ms[q] = 0.0; c->kt_n[q] = 0; }
+  c->kt_kind.clear();
+  auto mark = [&](int kind, bool begin) -> alew_status {
+    if (!c->ktime_on) return ALEW_OK;
+    if (kt_used == c->kt_ev.size()) {
+      hipEvent_t e;
+      HIPCHK2(hipEventCreate(&e));
+      c->kt_ev.push_back(e);
+    }
+    HIPCHK2(hipEventRecord(c->kt_ev[kt_used++], st));
+    if (begin) c->kt_kind.push_back(kind);
+    return ALEW_OK;
+  };
+  auto one_step = [&]() -> alew_status {
+    alew_status r = ALEW_OK;
+    auto timed_launch = [&](int kind, auto&& launch) {
+      if (r == ALEW_OK) r = mark(kind, true);
+      launch();
+      if (r == ALEW_OK) r = mark(kind, false);
+    };
+    timed_launch(0, [&] { hipLaunchKernelGGL(k2_kin, dim3(1), dim3(KB), 0, st, k); });
+    timed_launch(1, [&] { hipLaunchKernelGGL(k2_xsweep<0>, gx, dim3(XB), 0, st, k); });
+    timed_launch(2, [&] { hipLaunchKernelGGL(k2_ysweep<0>, gy, dim3(256), 0, st, k, rows); });
+    timed_launch(1, [&] { hipLaunchKernelGGL(k2_xsweep<1>, gx, dim3(XB), 0, st, k); });
+    timed_launch(2, [&] { hipLaunchKernelGGL(k2_ysweep<1>, gy, dim3(256), 0, st, k, rows); });
+    timed_launch(1, [&] { hipLaunchKernelGGL(k2_xsweep<2>, gx, dim3(XB), 0, st, k); });
+    timed_launch(2, [&] { hipLaunchKernelGGL(k2_ysweep<2>, gy, dim3(256), 0, st, k, rows); });
+    timed_launch(3, [&] { hipLaunchKernelGGL(k2_fin, gc, dim3(256), 0, st, k); });
+    return r;
   };
   int64_t launched = 0;
   if (!timed) {
-    for (; launched < max_steps; ++launched) one_step();
+    for (; launched < max_steps; ++launched) {
+      const alew_status r = one_step();
+      if (r != ALEW_OK) return r;
+    }
   } else {
     while (true) {
-      for (int q = 0; q < c->check_every; ++q) one_step();
+      for (int q = 0; q < c->check_every; ++q) {
+        const alew_status r = one_step();
+        if (r != ALEW_OK) return r;
+      }
       launched += c->check_every;
       HIPCHK2(hipGetLastError());
       HIPCHK2(hipMemcpyAsync(c->st_h, c->st, sizeof(State2), hipMemcpyDeviceToHost, st));
@@ -958,6 +1067,12 @@ alew_status alew2d_run(alew2d_ctx* c, const alew2d_params* p, int64_t nx, int64_
   HIPCHK2(hipStreamSynchronize(st));
   float ms = 0.0f;
   if (hipEventElapsedTime(&ms, c->ev0, c->ev1) == hipSuccess) c->last_ms = ms;
+  for (size_t q = 0; q < c->kt_kind.size(); ++q) {
+    float m = 0.0f;
+    HIPCHK2(hipEventElapsedTime(&m, c->kt_ev[2 * q], c->kt_ev[2 * q + 1]));
+    c->kt_ms[c->kt_kind[q]] += m;
+    c->kt_n[c->kt_kind[q]] += 1;
+  }
   const State2& R = *c->st_h;
   const alew_status status = map_bits(R.status);
   if (stats) {

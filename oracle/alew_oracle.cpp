@@ -106,7 +106,9 @@
  *      and the source) get their own indicators, class and weights.  The
  *      source integral of r(q, b) over the cell uses the 4-point Gauss-Lobatto
  *      rule of the limiter on the unlimited values (b_x: the derivative of b's
- *      hybrid reconstruction).  The limiter acts on h = eta - b and keeps the
+ *      hybrid reconstruction; where b's class is smooth, the derivative of the
+ *      5-cell quartic, which is fourth order where the weighted candidate
+ *      derivatives are second order only).  The limiter acts on h = eta - b and keeps the
  *      bottom traces (Remark 4.1 is stated for the well-balanced schemes; here
  *      a flat bottom stays flat).
  *  R23 params.bottom != ALE: the bottom is an analytic b(x) and its cell

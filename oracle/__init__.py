@@ -19,6 +19,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "alew_oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# ALEW_ORACLE_LIB: load a separately built copy (the sanitizer test's build of
+# the same source) instead of building and loading liboracle.so
+_LIB_OVERRIDE = os.environ.get("ALEW_ORACLE_LIB")
 
 BC_PERIODIC, BC_TRANSMISSIVE, BC_REFLECTIVE = 0, 1, 2
 MESH_GIVEN, MESH_SINE, MESH_PAPER, MESH_FLUID = 0, 1, 2, 3
@@ -76,8 +79,11 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        build()
-        L = C.CDLL(_LIB)
+        if _LIB_OVERRIDE:
+            L = C.CDLL(_LIB_OVERRIDE)
+        else:
+            build()
+            L = C.CDLL(_LIB)
         dp = C.POINTER(C.c_double)
         u8p = C.POINTER(C.c_uint8)
         L.orc_geometry.argtypes = [dp, dp, dp, dp, dp]

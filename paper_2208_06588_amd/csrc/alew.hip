@@ -618,13 +618,19 @@ __global__ void k_gauge(Bufs bf, int64_t ngauge, const double* __restrict__ gx,
   if (gh) gh[id] = bf.eta[g] - bf.b[g];
 }
 
-__global__ void k_gauge_seed(int64_t ntot, int64_t S, const int64_t* __restrict__ gcell,
-                             const double* __restrict__ gbar, double* __restrict__ lam) {
-  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= ntot) return;
-  const int64_t g = gcell[id];
-  atomicAdd(&lam[g], gbar[id]);           // d hbar / d eta
-  atomicAdd(&lam[2 * S + g], -gbar[id]);  // d hbar / d b
+// Seed of the reverse sweep: each gauge adds its cotangent to its cell's eta and
+// b adjoints.  One thread per instance walks the instance's gauges in order, so
+// gauges sharing a cell add in a fixed order (instances own disjoint cells).
+__global__ void k_gauge_seed(int64_t ninst, int64_t ngauge, int64_t S,
+                             const int64_t* __restrict__ gcell, const double* __restrict__ gbar,
+                             double* __restrict__ lam) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ninst) return;
+  for (int64_t k = i * ngauge; k < (i + 1) * ngauge; ++k) {
+    const int64_t g = gcell[k];
+    lam[g] += gbar[k];           // d hbar / d eta
+    lam[2 * S + g] -= gbar[k];   // d hbar / d b
+  }
 }
 
 __global__ void k_fill(double* __restrict__ p, int64_t n, double v) {
@@ -1762,7 +1768,8 @@ alew_status alew_adjoint(alew_ctx* c, const alew_params* p, int64_t ninst,
   // reverse sweep
   const unsigned g3 = (unsigned)((3 * S + 255) / 256);
   hipLaunchKernelGGL(k_fill, dim3(g3), dim3(256), 0, st, lam, 3 * S, 0.0);
-  hipLaunchKernelGGL(k_gauge_seed, dim3(gb), dim3(256), 0, st, ng, S, gcell, gauge_bar, lam);
+  hipLaunchKernelGGL(k_gauge_seed, dim3((unsigned)((ninst + 255) / 256)), dim3(256), 0, st, ninst,
+                     ngauge, S, gcell, gauge_bar, lam);
   AdjBufs ab;
   ab.cell_off = c->cell_off_d; ab.S = S; ab.ninst = (int32_t)ninst; ab.pad = 0;
   ab.lam = lam; ab.lam_out = lam2; ab.lbase = lbase; ab.lalpha = lalpha;

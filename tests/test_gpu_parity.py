@@ -450,3 +450,48 @@ def test_device_errors_are_reported(dev):
         ctx.run(p, [0, 3], small["h"], small["hu"], small["b"], small["x"], small["xi"],
                 max_steps=[1])
     assert ei.value.status == alew.E_ARG
+
+
+def test_depth_weight_and_step_size_errors_are_reported(dev):
+    """Further device errors forced from the host through the inputs: a negative
+    mean depth in the initial state (ALEW_E_NEGDEPTH in the first stage), a
+    stencil whose widths span three decades so that a linear weight goes
+    negative (ALEW_E_NEGWEIGHT: the splitting the paper mentions is not built,
+    the condition is reported), and frozen step sizes twenty times the CFL step
+    on Moses's second problem (the mean depth goes negative; the oracle with the
+    same steps reports the same status after the same step)."""
+    wl = W.accuracy_1d(64)
+    ctx = alew.Context(64, 1)
+    p = _gp(wl)
+    h = wl["h"].copy()
+    h[20] = -0.5
+    T = {k: _t(v, dev) for k, v in dict(h=h, hu=wl["hu"], b=wl["b"], x=wl["x"], xi=wl["xi"]).items()}
+    st = ctx.run(p, [0, 64], T["h"], T["hu"], T["b"], T["x"], T["xi"], max_steps=[2], check=False)
+    assert st[0].status == alew.E_NEGDEPTH
+    # widths [0.019, 0.025, 3.7, 0.019, 53] (a negative linear weight at the
+    # Gauss-Lobatto points, checked on the oracle's geometry) repeated, static mesh
+    pattern = np.array([1.88578153e-02, 2.52381902e-02, 3.70078437e+00, 1.85853584e-02,
+                        5.29734963e+01])
+    assert np.asarray(O.geometry(list(pattern))[0]).min() < 0.0
+    n = 40
+    wid = np.tile(pattern, n // 5)
+    x = np.concatenate([[0.0], np.cumsum(wid)])
+    z = np.zeros(n)
+    pg = alew.params(bc="transmissive", mesh="given")
+    Tn = {k: _t(v, dev) for k, v in dict(h=z + 1.0, hu=z, b=z, x=x, w=np.zeros(n + 1)).items()}
+    ctx2 = alew.Context(n, 1)
+    s2 = ctx2.step(pg, Tn["h"], Tn["hu"], Tn["b"], Tn["x"], w=Tn["w"], dt=1e-3, check=False)
+    assert s2.status == alew.E_NEGWEIGHT and s2.n_negweight > 0
+    # twenty CFL steps at once on a dry-bed problem
+    wm = W.moses2_1d(200, t_end=1.0)
+    pm = _gp(wm)
+    r1 = O.run(_op(wm), wm["h"], wm["hu"], wm["b"], wm["x"], wm["xi"], max_steps=1)
+    dts = np.full(10, 20.0 * r1["stats"].dt_max)
+    ro = O.run(_op(wm), wm["h"], wm["hu"], wm["b"], wm["x"], wm["xi"], max_steps=10, dts=dts)
+    assert ro["status"] in (O.ST_NEGDEPTH, O.ST_NONFINITE)
+    ctx3 = alew.Context(200, 1)
+    Tm = {k: _t(wm[k], dev) for k in ("h", "hu", "b", "x", "xi")}
+    s3 = ctx3.run(pm, [0, 200], Tm["h"], Tm["hu"], Tm["b"], Tm["x"], Tm["xi"], max_steps=[10],
+                  dts=_t(dts, dev), dts_stride=10, check=False)
+    want = alew.E_NEGDEPTH if ro["status"] == O.ST_NEGDEPTH else alew.E_NONFINITE
+    assert s3[0].status == want and s3[0].steps == ro["stats"].steps

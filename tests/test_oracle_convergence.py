@@ -67,25 +67,35 @@ def errors():
 @pytest.mark.slow
 @pytest.mark.parametrize("scheme", list(SCHEMES))
 def test_errors_match_the_paper_tables(errors, scheme):
-    """L1 errors of h + b and hu within a factor 2 of Table 5.2 (special source
-    term, hydrostatic reconstruction) or Table 5.1 (without well-balancing) at
-    every N; the projected bottom against the special source-term column."""
+    """L1 errors of h + b and hu against Table 5.2 (special source term,
+    hydrostatic reconstruction) or Table 5.1 (without well-balancing); the
+    projected bottom against the special source-term column.  From N = 200 on
+    the errors agree with the printed three digits to 2 % (measured: 1.720e-5,
+    6.798e-7, 2.231e-8 for h + b against 1.72e-5, 6.80e-7, 2.23e-8), at 50 and
+    100 cells to 12 % (the printed reference is another scheme's 12800-cell
+    run, here the oracle's own 6400-cell run)."""
     table = SCHEMES[scheme][1]
     paper = {int(r[1]): (float(r[2]), float(r[3])) for r in _gold("paper_tables.txt")
              if r[0] == table}
     for n in NS:
         for k in range(2):
             e, p = errors[scheme, n][k], paper[n][k]
-            assert p / 2 < e < 2 * p, (scheme, n, k, e, p)
+            assert abs(e / p - 1.0) < (0.02 if n >= 200 else 0.12), (scheme, n, k, e, p)
 
 
 @pytest.mark.slow
 @pytest.mark.parametrize("scheme", list(SCHEMES))
 def test_fifth_order_from_400_to_800(errors, scheme):
     """The observed order reaches the scheme's fifth order: above 4.5 from 400
-    to 800 cells and above 4.2 from 200 to 400, for h + b and hu (the paper
-    prints 4.66 and 4.93)."""
+    to 800 cells and above 4.2 from 200 to 400, for h + b and hu, and within
+    0.05 of the orders of the printed table (4.66 and 4.93)."""
+    table = SCHEMES[scheme][1]
+    paper = {int(r[1]): (float(r[2]), float(r[3])) for r in _gold("paper_tables.txt")
+             if r[0] == table}
     for k in range(2):
         o1 = math.log2(errors[scheme, 200][k] / errors[scheme, 400][k])
         o2 = math.log2(errors[scheme, 400][k] / errors[scheme, 800][k])
+        p1 = math.log2(paper[200][k] / paper[400][k])
+        p2 = math.log2(paper[400][k] / paper[800][k])
         assert o1 > 4.2 and o2 > 4.5, (scheme, k, o1, o2)
+        assert abs(o1 - p1) < 0.05 and abs(o2 - p2) < 0.05, (scheme, k, o1, o2, p1, p2)

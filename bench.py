@@ -16,6 +16,7 @@ from __future__ import annotations
 
 import argparse
 import concurrent.futures as cf
+import gc
 import hashlib
 import json
 import math
@@ -97,6 +98,15 @@ def copy_bandwidth(nbytes=4 << 30, reps=10):
     return round(2.0 * n * 8 * reps / (ms / 1e3) / 1e9, 1)
 
 
+def scheme_id(p):
+    """The stage kernels' scheme template argument: 0 special source term,
+    1 hydrostatic reconstruction, 2 without well-balancing."""
+    from paper_2208_06588_amd import alew
+    if p.flags & alew.F_NONWB:
+        return 2
+    return 1 if p.flags & alew.F_HYDROSTATIC else 0
+
+
 def roofline(ctx, p, off, T, tnow, L, S, kern_ms, launches, steps, copy_bw=True):
     """Roofline object of the dominant kernel.  For the stage-launch engine the
     same number of steps runs once more with an event pair around every stage
@@ -110,16 +120,14 @@ def roofline(ctx, p, off, T, tnow, L, S, kern_ms, launches, steps, copy_bw=True)
     if L.engine == alew.ENGINE_PERSISTENT:
         blk = L.block or 256
         cpt = L.cells_per_thread or (2 if blk == 64 else 1)
-        hr = 'true' if p.flags & alew.F_HYDROSTATIC else 'false'
-        kernel = f"k_persistent<{blk}, {cpt}, {hr}>"
+        kernel = f"k_persistent<{blk}, {cpt}, {scheme_id(p)}>"
         ms_launch = kern_ms / max(1, launches)
         achieved = ALG_BYTES_PER_CELL_STEP * S * steps / max(1, launches) / (ms_launch / 1e3) / 1e9
         stage_launches, epi = None, None
     else:
         blk = L.block or 64  # 0 = the library's choice for the stage launches
         cpt = L.cells_per_thread or (2 if blk == 64 else 1)
-        hr = 'true' if p.flags & alew.F_HYDROSTATIC else 'false'
-        kernel = f"k_stage<{blk}, {cpt}, {'true' if L.compact_tiles else 'false'}, {hr}>"
+        kernel = f"k_stage<{blk}, {cpt}, {'true' if L.compact_tiles else 'false'}, {scheme_id(p)}>"
         ctx.set_kernel_timing(True)
         W = {k: v.clone() for k, v in T.items()}
         ctx.run(p, off, W["h"], W["hu"], W["b"], W["x"], W["xi"], t0=tnow,
@@ -184,6 +192,7 @@ def bowl_leg(dev, n, steps, warmup):
                                         if c["engine"] == alew.ENGINE_STAGES])
     st = ctx.run(p, [0, n], T["h"], T["hu"], T["b"], T["x"], T["xi"], max_steps=[warmup])
     torch.cuda.synchronize()
+    gc.collect()
     a = time.perf_counter()
     st = ctx.run(p, [0, n], T["h"], T["hu"], T["b"], T["x"], T["xi"], t0=[st[0].t], max_steps=[steps])
     torch.cuda.synchronize()
@@ -219,6 +228,7 @@ def hydrostatic_leg(ctx, p, off, T, tnow, L, S, steps):
     st = ctx.run(p, off, W["h"], W["hu"], W["b"], W["x"], W["xi"], t0=tnow, max_steps=[2] * ninst)
     tnow = [s.t for s in st]
     torch.cuda.synchronize()
+    gc.collect()
     a = time.perf_counter()
     st = ctx.run(p, off, W["h"], W["hu"], W["b"], W["x"], W["xi"], t0=tnow,
                  max_steps=[steps] * ninst)
@@ -341,6 +351,7 @@ def small_run_leg(dev):
     W1 = {k: v.clone() for k, v in T.items()}
     ctx.run(gp, [0, 200], W1["h"], W1["hu"], W1["b"], W1["x"], W1["xi"], t_end=[0.1])
     torch.cuda.synchronize()
+    gc.collect()
     a = time.perf_counter()
     sg = ctx.run(gp, [0, 200], T["h"], T["hu"], T["b"], T["x"], T["xi"], t_end=[0.1])[0]
     torch.cuda.synchronize()
@@ -381,6 +392,7 @@ def adjoint_leg(dev, ninst, ncell, nsteps, ngauge, ckpt, flags=0):
     # forward alone (same frozen steps)
     W1 = {k: T[k].clone() for k in ("h", "hu", "b", "x")}
     torch.cuda.synchronize()
+    gc.collect()
     a = time.perf_counter()
     ctx.run(p, off, W1["h"], W1["hu"], W1["b"], W1["x"], T["xi"], max_steps=[nsteps] * ninst,
             dts=dts, dts_stride=nsteps)
@@ -393,6 +405,7 @@ def adjoint_leg(dev, ninst, ncell, nsteps, ngauge, ckpt, flags=0):
     gbar = gh - gh_obs
     d3 = [torch.zeros(S, dtype=torch.float64, device=dev) for _ in range(3)]
     torch.cuda.synchronize()
+    gc.collect()
     a = time.perf_counter()
     ctx.adjoint(p, off, T["h"], T["hu"], T["b"], T["x"], T["xi"], nsteps, dts, ngauge,
                 T["gauge_x"], gh, gbar, *d3, ckpt_every=ckpt)
@@ -441,6 +454,7 @@ def speedup_leg(p, off, T, tnow, L, k=64, steps=3):
              max_steps=[steps] * k)  # untimed: tables and graph of the batch
     Tb = sub_state()
     torch.cuda.synchronize()
+    gc.collect()
     a0 = time.perf_counter()
     ctxb.run(p, sub_off, Tb["h"], Tb["hu"], Tb["b"], Tb["x"], Tb["xi"], t0=tnow[:k],
              max_steps=[steps] * k)
@@ -458,6 +472,7 @@ def speedup_leg(p, off, T, tnow, L, k=64, steps=3):
     for kk in Tw:
         Tw[kk].copy_(Tsave[kk])
     torch.cuda.synchronize()
+    gc.collect()
     a0 = time.perf_counter()
     for i in range(k):
         one(ctxs[i], Tw, i)
@@ -472,6 +487,7 @@ def speedup_leg(p, off, T, tnow, L, k=64, steps=3):
     c1 = alew.Context(max(np.diff(sub_off)), 1)
     launch_of(c1)
     torch.cuda.synchronize()
+    gc.collect()
     a0 = time.perf_counter()
     for i in range(k):
         one(c1, Tc, i)
@@ -532,6 +548,7 @@ def tensor2d_leg(dev, n, steps, warmup):
         go(fresh(), warmup)
     T = fresh()
     torch.cuda.synchronize()
+    gc.collect()
     a = time.perf_counter()
     st = go(T, steps)
     torch.cuda.synchronize()
@@ -684,6 +701,8 @@ def main():
         st = ctx.run(p, off, T["h"], T["hu"], T["b"], T["x"], T["xi"], t0=tnow,
                      max_steps=[args.warmup] * ninst)
         tnow = [s.t for s in st]
+    # the interpreter's cycle collector runs now, not inside the timed call
+    gc.collect()
     torch.cuda.synchronize()
     w0 = time.perf_counter()
     st = ctx.run(p, off, T["h"], T["hu"], T["b"], T["x"], T["xi"], t0=tnow,
@@ -741,6 +760,7 @@ def main():
         W2 = {k: torch.tensor(bt[k], dtype=torch.float64, device=dev)
               for k in ("h", "hu", "b", "x", "xi")}
         torch.cuda.synchronize()
+        gc.collect()
         a0 = time.perf_counter()
         stf = ctx.run(p, off, W2["h"], W2["hu"], W2["b"], W2["x"], W2["xi"], t_end=[0.2] * ninst)
         torch.cuda.synchronize()

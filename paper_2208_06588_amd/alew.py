@@ -255,7 +255,8 @@ class Context:
     def run(self, p: Params, cell_off: Sequence[int], h, hu, b, x, xi, t0=None, t_end=None,
             max_steps=None, dts=None, dt_log=None, dts_stride=0, cls_count=None, cls_sig=None,
             check=True):
-        """Run a packed ragged batch; returns the per-instance Stats.  cls_count
+        """Run a packed ragged batch; returns the per-instance Stats (a ctypes
+        array: index it or iterate over it).  cls_count
         (int32, 3 * cells) and cls_sig (int64, cells) accumulate the class record
         of every cell and stage (see alew_run)."""
         ninst = len(cell_off) - 1
@@ -291,7 +292,9 @@ class Context:
                             _ptr(cls_sig, torch.int64), stats)
         if check:
             _check(st)
-        return list(stats)
+        # the ctypes array itself (indexable, iterable): no per-instance Python
+        # objects are made inside the call
+        return stats
 
     def adjoint_reserve(self, nsteps, ngauge, ckpt_every=16):
         """Allocate the adjoint workspace for up to nsteps steps and ngauge gauges

@@ -53,7 +53,8 @@ typedef enum {
   ALEW_E_UNSUPPORTED = 7, /* combination not supported by this entry point; also an
                            * instance of a batch out of step with the others (the
                            * stage kernels take one node-buffer parity per launch) */
-  ALEW_E_NEGWEIGHT = 8,   /* a negative linear weight d_r (Sec. 2.2, after Step 4)  */
+  ALEW_E_NEGWEIGHT = 8,   /* a negative linear weight d_r (Sec. 2.2, after Step 4)
+                           * without ALEW_F_SPLIT                                 */
   ALEW_E_CAPACITY = 9     /* the step-size buffer of alew_run (dts or dt_log) holds
                            * fewer than the steps an instance needed: the instance
                            * stopped there, before its t_end / max_steps            */
@@ -115,6 +116,19 @@ enum {
                                 values; the positivity limiter changes h and keeps the b
                                 traces.  alew_step and alew_run only; not with
                                 ALEW_F_HYDROSTATIC                                     */
+  ,
+  ALEW_F_SPLIT = 128         /* negative linear weights (the remark after Step 4 of
+                                Sec. 2.2): by default a negative weight is reported
+                                (ALEW_E_NEGWEIGHT, counted in n_negweight).  With
+                                this flag, at a point whose linear weights include a
+                                negative one, the nonlinear weights of the
+                                transition and non-smooth classes come from the
+                                splitting of Shi, Hu & Shu (2002, theta = 3): a
+                                positive and a negative group, each with its own
+                                nonlinear weights; such cell-stages are counted and
+                                the run goes on.  Runs the stage engine in its
+                                automatic tile shape.  alew_step and alew_run;
+                                alew_adjoint ignores it (and reports)              */
 };
 
 /* Bottom topography (Sec. 3.3).  ALE (default): the cell averages of b are a
@@ -359,7 +373,8 @@ alew_status alew2d_set_launch(alew2d_ctx* ctx, int32_t rows, int32_t check_every
  * last step; cls_count (device, optional) [3 * nx * ny] and cls_sig (device,
  * optional) [nx * ny] accumulate a record of every stage as alew_run's do.
  * stats (host, optional).  Errors: ALEW_E_ARG / ALEW_E_UNSUPPORTED before any
- * work; ALEW_E_MESH (a non-positive area) or ALEW_E_NONFINITE stop the run
+ * work; ALEW_E_MESH (a non-positive area), ALEW_E_NONFINITE or ALEW_E_NEGWEIGHT
+ * (a negative linear weight on a stage mesh; not split in 2D) stop the run
  * after the step that met them, with the state of that step in the arrays. */
 alew_status alew2d_run(alew2d_ctx* ctx, const alew2d_params* p, int64_t nx, int64_t ny,
                        double* h, double* hu, double* hv, double* b, double* x, double* y,

@@ -28,6 +28,7 @@ MESH_GIVEN, MESH_SINE, MESH_PAPER, MESH_FLUID = 0, 1, 2, 3
 ST_OK, ST_ARG, ST_MESH, ST_NEGDEPTH, ST_NONFINITE, ST_NEGWEIGHT = 0, 1, 2, 3, 4, 8
 FLAG_BETA_LOCAL, FLAG_BETA_FROM_H, FLAG_HYDROSTATIC = 1, 2, 4
 FLAG_ALPHA_CELLAVG, FLAG_NO_HU_LIMIT, FLAG_W_TANGENT, FLAG_NONWB = 8, 16, 32, 64
+FLAG_SPLIT = 128  # negative linear weights split instead of reported (R29)
 
 
 class Params(C.Structure):
@@ -91,6 +92,8 @@ def lib():
         L.orc_limit.argtypes = [C.c_double, C.c_double, dp, C.c_double, C.c_int, dp]
         L.orc_bottom_average.argtypes = [C.POINTER(Params), C.c_double, C.c_double]
         L.orc_bottom_average.restype = C.c_double
+        L.orc_nonlinear_weights.argtypes = [dp, dp, C.c_int, dp]
+        L.orc_nonlinear_weights.restype = None
         L.orc_reconstruct_char.argtypes = [dp, dp, dp, dp, C.c_double, C.c_double, C.c_double,
                                            C.c_double, dp]
         L.orc_hydro_source.argtypes = [C.c_double, dp, dp]
@@ -164,6 +167,14 @@ def reconstruct(widths5, h5, m5, b5, dx, eps=1e-6, v5=None):
 def bottom_average(P: Params, xl, xr):
     """Average over [xl, xr] of the analytic bottom of P (eq. (3.16))."""
     return float(lib().orc_bottom_average(C.byref(P), float(xl), float(xr)))
+
+
+def nonlinear_weights(d, K, split=True):
+    """Nonlinear weights of one point from linear weights d[3] and the factors
+    K[3] = 1 + (tau / (beta_r + eps))^2 (split: the splitting of R29)."""
+    phi = np.zeros(3)
+    lib().orc_nonlinear_weights(_p(_f64(d)), _p(_f64(K)), 1 if split else 0, _p(phi))
+    return phi
 
 
 def reconstruct_char(widths5, eta5, m5, b5, dx, eps=1e-6, g=9.812, dry_eps=1e-8):

@@ -118,6 +118,15 @@
  *      ALE evolution of eq. (3.17); the initial b is the projection onto the
  *      initial cells.  The integral is taken by the 5-point Gauss-Legendre
  *      rule on the smooth pieces of b.
+ *  R29 Negative linear weights (the remark after Step 4 of Sec. 2.2 asks for
+ *      a special treatment): by default a point whose linear weights include
+ *      a negative one is counted and the run reports ST_NEGWEIGHT (the weights
+ *      are used as they are).  FLAG_SPLIT: the nonlinear weights of the
+ *      transition and non-smooth classes at such a point come from the
+ *      splitting of Shi, Hu & Shu (2002) with theta = 3 (nonlinear_weights
+ *      below), the smooth class keeps the linear weights (a linear
+ *      combination needs no positivity), and the run goes on.  The 2D sweeps
+ *      always split.
  */
 #include <cmath>
 #include <cstdint>
@@ -185,7 +194,7 @@ enum { ST_OK = 0, ST_ARG = 1, ST_MESH = 2, ST_NEGDEPTH = 3, ST_NONFINITE = 4, ST
 
 enum {
   FLAG_BETA_LOCAL = 1, FLAG_BETA_FROM_H = 2, FLAG_HYDROSTATIC = 4, FLAG_ALPHA_CELLAVG = 8,
-  FLAG_NO_HU_LIMIT = 16, FLAG_W_TANGENT = 32, FLAG_NONWB = 64
+  FLAG_NO_HU_LIMIT = 16, FLAG_W_TANGENT = 32, FLAG_NONWB = 64, FLAG_SPLIT = 128
 };
 
 struct Params {
@@ -415,9 +424,43 @@ static T beta_one(const CellGeo& G, int r, const T v[3], double Dx) {
 }
 
 /* v[5]: the first indicator variable (eta by default, see R3). */
+/* Nonlinear weights at one point from the linear weights d[3] and the factors
+ * K_r = 1 + (tau / (beta_r + eps))^2 of eq. (2.9).  With a negative linear
+ * weight and split set (R29), the weights are split into a positive group
+ * gp_r = (d_r + 3 |d_r|) / 2 and a negative group gm_r = gp_r - d_r (both
+ * non-negative, gp - gm = d), each normalised to sum one and given its own
+ * nonlinear weights; the point value is sp (positive group's value) -
+ * sm (negative group's value), sp, sm the group sums: the splitting of Shi,
+ * Hu & Shu (J. Comput. Phys. 175, 2002) with theta = 3. */
+template <class T>
+static void nonlinear_weights(const double d[3], const T K[3], bool split, T phi[3]) {
+  const bool neg = d[0] < 0.0 || d[1] < 0.0 || d[2] < 0.0;
+  if (neg && split) {
+    double gp[3], gm[3], sp = 0.0, sm = 0.0;
+    for (int r = 0; r < 3; ++r) {
+      gp[r] = 0.5 * (d[r] + 3.0 * std::fabs(d[r]));
+      gm[r] = gp[r] - d[r];
+      sp = sp + gp[r];
+      sm = sm + gm[r];
+    }
+    T ap[3], am[3];
+    for (int r = 0; r < 3; ++r) {
+      ap[r] = (gp[r] / sp) * K[r];
+      am[r] = (gm[r] / sm) * K[r];
+    }
+    T SP = ap[0] + ap[1] + ap[2], SM = am[0] + am[1] + am[2];
+    for (int r = 0; r < 3; ++r) phi[r] = sp * (ap[r] / SP) - sm * (am[r] / SM);
+    return;
+  }
+  T a[3];
+  for (int r = 0; r < 3; ++r) a[r] = d[r] * K[r];
+  T sum = a[0] + a[1] + a[2];
+  for (int r = 0; r < 3; ++r) phi[r] = a[r] / sum;
+}
+
 template <class T>
 static void reconstruct(const CellGeo& G, double Dx, double eps, const T v[5], const T h[5],
-                        const T m[5], const T b[5], Recon<T>& o) {
+                        const T m[5], const T b[5], Recon<T>& o, bool split = true) {
   /* Step 2: indicators summed over the two equations, detector. */
   T beta[3];
   for (int r = 0; r < 3; ++r) {
@@ -442,14 +485,13 @@ static void reconstruct(const CellGeo& G, double Dx, double eps, const T v[5], c
     if (cls == CLS_S) {
       for (int r = 0; r < 3; ++r) phi[r] = G.d[mu][r];
     } else {
-      T alpha[3];
+      T Kf[3];
       for (int r = 0; r < 3; ++r) {
         T q = tau / (beta[r] + eps);
-        alpha[r] = G.d[mu][r] * (1.0 + q * q);
+        Kf[r] = 1.0 + q * q;
       }
-      T sum = alpha[0] + alpha[1] + alpha[2];
       T phiN[3];
-      for (int r = 0; r < 3; ++r) phiN[r] = alpha[r] / sum;
+      nonlinear_weights(G.d[mu], Kf, split, phiN);
       if (cls == CLS_N) {
         for (int r = 0; r < 3; ++r) phi[r] = phiN[r];
       } else {
@@ -491,7 +533,8 @@ static void reconstruct(const CellGeo& G, double Dx, double eps, const T v[5], c
  * of b's reconstruction; o.cls the largest of the three classes. */
 template <class T>
 static void reconstruct_char(const CellGeo& G, double Dx, double eps, double g, double dry,
-                             const T eta[5], const T m[5], const T b[5], Recon<T>& o) {
+                             const T eta[5], const T m[5], const T b[5], Recon<T>& o,
+                             bool split = true) {
   T zero[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   T hbar = eta[2] - b[2];
   bool chr = val(hbar) > dry;
@@ -512,9 +555,9 @@ static void reconstruct_char(const CellGeo& G, double Dx, double eps, double g, 
     }
   }
   Recon<T> r1, r2, rb;
-  reconstruct(G, Dx, eps, w1, w1, zero, w1, r1);
-  reconstruct(G, Dx, eps, w2, w2, zero, w2, r2);
-  reconstruct(G, Dx, eps, b, b, zero, b, rb);
+  reconstruct(G, Dx, eps, w1, w1, zero, w1, r1, split);
+  reconstruct(G, Dx, eps, w2, w2, zero, w2, r2, split);
+  reconstruct(G, Dx, eps, b, b, zero, b, rb, split);
   if (rb.cls == CLS_S) {
     /* where b is smooth its reconstruction is the 5-cell quartic P (linear
      * weights), and b_x its derivative: fourth order, where the weighted
@@ -762,12 +805,13 @@ static void residual(const Params& P, int n, const T* eta, const T* m, const T* 
     cell_geometry(wid, geo);
     double dxr = (P.flags & FLAG_BETA_LOCAL) ? wid[2] : Dx;
     const bool nonwb = (P.flags & FLAG_NONWB) != 0;
+    const bool split = (P.flags & FLAG_SPLIT) != 0;
     if (nonwb) {
       T es[5];
       for (int k = 0; k < 5; ++k) es[k] = etae[j - 2 + k + G];
-      reconstruct_char(geo, dxr, P.weno_eps, P.g, P.dry_eps, es, ms5, bs, rec[j + 1]);
+      reconstruct_char(geo, dxr, P.weno_eps, P.g, P.dry_eps, es, ms5, bs, rec[j + 1], split);
     } else {
-      reconstruct(geo, dxr, P.weno_eps, vs, hs, ms5, bs, rec[j + 1]);
+      reconstruct(geo, dxr, P.weno_eps, vs, hs, ms5, bs, rec[j + 1], split);
     }
     int lim = limit_cell(he[j + G], me[j + G], rec[j + 1], P.pp_eps, tr[j + 1],
                          !(P.flags & FLAG_NO_HU_LIMIT), nonwb);
@@ -1030,7 +1074,7 @@ static int step(const Params& P, int n, T* eta, T* m, T* b, double* x, const dou
       st = ST_NONFINITE;
     if (val(eta[j]) - val(b[j]) < -P.pp_eps && st == ST_OK) st = ST_NEGDEPTH;
   }
-  if (cnt.n_negweight && st == ST_OK) st = ST_NEGWEIGHT;
+  if (cnt.n_negweight && st == ST_OK && !(P.flags & FLAG_SPLIT)) st = ST_NEGWEIGHT;
   return st;
 }
 
@@ -1109,16 +1153,14 @@ static int sweep2(const CellGeo& G, double Dx, double eps, const double e5[5], c
     if (cls == CLS_S) {
       for (int r = 0; r < 3; ++r) phi[r] = G.d[mu][r];
     } else {
-      double al[3], sum = 0.0;
+      double Kf[3], pn[3];
       for (int r = 0; r < 3; ++r) {
         double q = tau / (beta[r] + eps);
-        al[r] = G.d[mu][r] * (1.0 + q * q);
-        sum = sum + al[r];
+        Kf[r] = 1.0 + q * q;
       }
-      for (int r = 0; r < 3; ++r) {
-        double pn = al[r] / sum;
-        phi[r] = cls == CLS_N ? pn : (2.0 * gamma - 1.0) * pn + (1.0 - (2.0 * gamma - 1.0)) * G.d[mu][r];
-      }
+      nonlinear_weights(G.d[mu], Kf, false, pn);
+      for (int r = 0; r < 3; ++r)
+        phi[r] = cls == CLS_N ? pn[r] : (2.0 * gamma - 1.0) * pn[r] + (1.0 - (2.0 * gamma - 1.0)) * G.d[mu][r];
     }
     for (int v = 0; v < 6; ++v) {
       if (!var[v]) continue;
@@ -1137,6 +1179,7 @@ static int sweep2(const CellGeo& G, double Dx, double eps, const double e5[5], c
 
 struct Counters2 {
   int64_t n_class[3];
+  int negw;  /* a negative linear weight on a stage mesh (R29) */
 };
 
 static int wrap_index(int bc, int n, int k) {
@@ -1172,6 +1215,11 @@ static double residual2(const Params2& P, int nx, int ny, const double* eta, con
     for (int k = 0; k < 5; ++k) wid[k] = wdy(j - 2 + k);
     cell_geometry(wid, Gy[j + 1]);
   }
+  for (const std::vector<CellGeo>* T : {&Gx, &Gy})
+    for (const CellGeo& g : *T)
+      for (int mu = 0; mu < 4; ++mu)
+        for (int r = 0; r < 3; ++r)
+          if (g.d[mu][r] < 0.0) cnt.negw = 1;
   /* x-sweeps: line values L[(i, j)][var][mu] for i in -1..nx, j in -3..ny+2 */
   const int LX = nx + 2, LY = ny + 6;
   std::vector<double> L((size_t)LX * LY * 5 * 4);
@@ -1387,7 +1435,7 @@ static int step2(const Params2& P, int nx, int ny, double* eta, double* mx, doub
   for (size_t c = 0; c < N; ++c)
     for (int v = 0; v < 4; ++v)
       if (!std::isfinite(st[v][c])) return ST_NONFINITE;
-  return ST_OK;
+  return cnt.negw ? ST_NEGWEIGHT : ST_OK;
 }
 
 static double cfl_dt2(const Params2& P, int nx, int ny, const double* eta, const double* mx,
@@ -1681,7 +1729,7 @@ int orc2_run(const Params2* P, int64_t nx_, int64_t ny_, double* h, double* hu, 
   double t = t0;
   int64_t k = 0;
   int st = ST_OK;
-  Counters2 cnt{{0, 0, 0}};
+  Counters2 cnt{{0, 0, 0}, 0};
   const bool timed = t_end > t0;
   while (true) {
     if (max_steps > 0 && k >= max_steps) break;
@@ -1703,6 +1751,13 @@ int orc2_run(const Params2* P, int64_t nx_, int64_t ny_, double* h, double* hu, 
   return st;
 }
 
+/* Nonlinear weights of one point (eq. (2.9), with the splitting of R29 when
+ * split != 0 and a linear weight is negative): d[3] linear weights, K[3] the
+ * factors 1 + (tau / (beta_r + eps))^2; phi[3] out. */
+void orc_nonlinear_weights(const double* d, const double* K, int split, double* phi) {
+  nonlinear_weights(d, K, split != 0, phi);
+}
+
 /* One 2D reconstruction sweep (R25) on 5 cells: out[6][4] as sweep2. */
 int orc2_sweep(const double* wid5, double Dx, double eps, const double* e5, const double* mx5,
                const double* my5, const double* h5, const double* b5, const double* ext5,
@@ -1720,7 +1775,7 @@ int orc2_sweep(const double* wid5, double Dx, double eps, const double* e5, cons
 double orc2_residual(const Params2* P, int64_t nx, int64_t ny, const double* eta, const double* hu,
                      const double* hv, const double* b, const double* dx, const double* dy,
                      const double* wx, const double* wy, double* R) {
-  Counters2 cnt{{0, 0, 0}};
+  Counters2 cnt{{0, 0, 0}, 0};
   return residual2(*P, (int)nx, (int)ny, eta, hu, hv, b, dx, dy, wx, wy, R, nullptr, cnt);
 }
 }  /* extern "C" */

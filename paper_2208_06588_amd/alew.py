@@ -21,6 +21,7 @@ BC = {"periodic": 0, "transmissive": 1, "reflective": 2}
 MESH = {"given": 0, "sine": 1, "paper": 2, "fluid": 3}
 F_BETA_LOCAL, F_BETA_FROM_H, F_HYDROSTATIC = 1, 2, 4
 F_ALPHA_CELLAVG, F_NO_HU_LIMIT, F_W_TANGENT, F_NONWB = 8, 16, 32, 64
+F_SPLIT = 128  # split negative linear weights instead of reporting them
 CLS_SIG_MUL = 1099511628211  # multiplier of the class-sequence signature of alew_run
 ENGINE_AUTO, ENGINE_PERSISTENT, ENGINE_STAGES = 0, 1, 2
 

@@ -985,7 +985,15 @@ void launch_step_seq(alew_ctx* c, const Bufs& bf, const Consts& cs, hipStream_t 
     const int kt = kt_begin(c, st, 0, (double)c->tables_cells);
 #define ALEW_STAGE(NX, SC)                                                                      \
   hipLaunchKernelGGL((k_stage<B, CPT, NX, SC>), gs, dim3(B), 0, st, bf, cs, c->tiles_stage_d, s, par)
-    if (c->tiles_noext) {
+    if (cs.flags & F_SPLIT) {
+      // split negative weights: the automatic tile shape only (the driver
+      // forces it), so that no other shape carries the split's registers
+      if constexpr (B == 64 && CPT == 2) {
+        if (sch == SCH_HYDRO) ALEW_STAGE(false, SCH_HYDRO | SCH_SPLIT);
+        else if (sch == SCH_NONWB) ALEW_STAGE(false, SCH_NONWB | SCH_SPLIT);
+        else ALEW_STAGE(false, SCH_SPECIAL | SCH_SPLIT);
+      }
+    } else if (c->tiles_noext) {
       if (sch == SCH_HYDRO) ALEW_STAGE(true, SCH_HYDRO);
       else if (sch == SCH_NONWB) ALEW_STAGE(true, SCH_NONWB);
       else ALEW_STAGE(true, SCH_SPECIAL);
@@ -1207,9 +1215,12 @@ alew_status drive(alew_ctx* c, const alew_params* p, int64_t ninst, const int64_
   if ((dts || dt_log) && dts_stride <= 0) return fail(ALEW_E_ARG, "dts_stride must be > 0");
   if ((ccount == nullptr) != (csig == nullptr))
     return fail(ALEW_E_ARG, "cls_count and cls_sig go together");
-  const int B = pick_block(c, engine);
-  const int CPT = pick_cpt(c, B);
-  const bool noext = engine != 1 && c->launch.compact_tiles == 1;
+  // split negative weights: the stage engine in its automatic tile shape
+  const bool split = (p->flags & ALEW_F_SPLIT) != 0;
+  if (split) engine = 2;
+  const int B = split ? 64 : pick_block(c, engine);
+  const int CPT = split ? 2 : pick_cpt(c, B);
+  const bool noext = !split && engine != 1 && c->launch.compact_tiles == 1;
   alew_status ts = build_tiles(c, cell_off, ninst, PB, B * CPT, noext);
   if (ts != ALEW_OK) return ts;
   // per-instance scalars
@@ -1714,7 +1725,10 @@ alew_status alew_adjoint(alew_ctx* c, const alew_params* p, int64_t ninst,
   HIPCHK(hipMemcpyAsync(st_m, hu0, S * 8, hipMemcpyDeviceToDevice, st));
   HIPCHK(hipMemcpyAsync(st_b, b0, S * 8, hipMemcpyDeviceToDevice, st));
   Bufs bf = make_bufs(c, S, ninst, st_m, st_b, xi, nullptr, dts, nullptr, nsteps);
-  const Consts cs = make_consts(p);
+  // the reverse sweep differentiates the unsplit weights: a negative linear
+  // weight is reported (ALEW_E_NEGWEIGHT), never split
+  Consts cs = make_consts(p);
+  cs.flags &= ~F_SPLIT;
   const dim3 gp((unsigned)c->n_tiles_plain);
   auto step_dump = [&](int64_t slot) {
     Dump d;

@@ -508,6 +508,9 @@ __global__ void __launch_bounds__(KB) k2_kin(K2 k) {
     const double iJ = 1.0 / J5[2];
     CellGeom G;
     cell_geom(J5, iJ, isx ? mx[s] : my[s], G);
+    // a negative linear weight (Sec. 2.2, after Step 4) is not split in 2D: the
+    // run reports it after this step
+    if (G.sgn >> 31) atomicOr(&k.st->status, SB_NEGWEIGHT);
     double* T = isx ? k.Gx : k.Gy;
     auto put = [&](int fld, double v) { T[((int64_t)fld * 3 + s) * ne + (a + 1)] = v; };
 #pragma unroll
@@ -864,6 +867,7 @@ alew_status fail2(alew_status s, const std::string& m) { return alew_set_error(s
 alew_status map_bits(int bits) {
   if (bits & SB_MESH) return ALEW_E_MESH;
   if (bits & SB_NONFINITE) return ALEW_E_NONFINITE;
+  if (bits & SB_NEGWEIGHT) return ALEW_E_NEGWEIGHT;
   return bits ? ALEW_E_HIP : ALEW_OK;
 }
 
@@ -1088,8 +1092,9 @@ alew_status alew2d_run(alew2d_ctx* c, const alew2d_params* p, int64_t nx, int64_
     stats->status = (int32_t)status;
   }
   if (status != ALEW_OK)
-    return fail2(status, status == ALEW_E_MESH ? "a cell area became non-positive"
-                                               : "non-finite state");
+    return fail2(status, status == ALEW_E_MESH       ? "a cell area became non-positive"
+                         : status == ALEW_E_NEGWEIGHT ? "a negative linear weight on the stage mesh"
+                                                      : "non-finite state");
   return ALEW_OK;
 }
 

@@ -22,13 +22,14 @@ enum { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1, BC_REFLECTIVE = 2 };
 enum { MESH_GIVEN = 0, MESH_SINE = 1, MESH_PAPER = 2, MESH_FLUID = 3 };
 enum {
   F_BETA_LOCAL = 1, F_BETA_FROM_H = 2, F_HYDROSTATIC = 4, F_ALPHA_CELLAVG = 8, F_NO_HU_LIMIT = 16,
-  F_W_TANGENT = 32, F_NONWB = 64
+  F_W_TANGENT = 32, F_NONWB = 64, F_SPLIT = 128
 };
 // Scheme of a stage kernel (a template parameter): the special source-term
 // treatment (Sec. 4.2), the hydrostatic reconstruction (Sec. 4.1), or the
 // ALE-WENO scheme of Sec. 3 without well-balancing, with characteristic
-// reconstruction.
-enum { SCH_SPECIAL = 0, SCH_HYDRO = 1, SCH_NONWB = 2 };
+// reconstruction; SCH_SPLIT added: negative linear weights split (a separate
+// instantiation, so that the other kernels carry none of its registers).
+enum { SCH_SPECIAL = 0, SCH_HYDRO = 1, SCH_NONWB = 2, SCH_SPLIT = 4 };
 // status bits (combined per instance; mapped to alew_status on the host)
 enum {
   SB_MESH = 1, SB_NEGDEPTH = 2, SB_NONFINITE = 4, SB_NEGWEIGHT = 8, SB_SEQUENCE = 16,
@@ -284,6 +285,30 @@ __device__ __forceinline__ int64_t ghost_src(int bc, int64_t n, int64_t k, doubl
 // functions, d is the normalised cross product e^(3) x e^(4).  That is the
 // 5-cell quartic condition of Step 1, in a form with 3x3 work per point.
 // ----------------------------------------------------------------------------
+// Nonlinear weights at a point whose linear weights d include a negative one:
+// the splitting of Shi, Hu & Shu (J. Comput. Phys. 175, 2002) with theta = 3.
+// gp_r = (d_r + 3 |d_r|) / 2 and gm_r = gp_r - d_r are both non-negative
+// (gp - gm = d); each group, normalised to sum one, gets the WENO-Z factors K,
+// and the weights are sp w+_r - sm w-_r (sp, sm the group sums), which add up
+// to one and stay in [-sm, sp] however the factors vary.  With w+_r =
+// gp_r K_r / sum_s gp_s K_s (and likewise w-), the weights are
+// K_r (cp gp_r - cm gm_r), cp = sp / sum gp K, cm = sm / sum gm K.  Kept out of
+// line: it runs only on meshes with negative linear weights, and inlined it
+// would cost the stage kernel registers on every mesh.
+__device__ __forceinline__ void split_weights(const double* d, const double* K, double* ph) {
+  double gp[3], gm[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    gp[r] = 0.5 * (d[r] + 3.0 * fabs(d[r]));
+    gm[r] = gp[r] - d[r];
+  }
+  const double sp = gp[0] + gp[1] + gp[2], sm = gm[0] + gm[1] + gm[2];
+  const double cp = sp / (gp[0] * K[0] + gp[1] * K[1] + gp[2] * K[2]);
+  const double cm = sm / (gm[0] * K[0] + gm[1] * K[1] + gm[2] * K[2]);
+#pragma unroll
+  for (int r = 0; r < 3; ++r) ph[r] = K[r] * (cp * gp[r] - cm * gm[r]);
+}
+
 struct CellRecon {
   double hL, mL, bL, hR, mR, bR;  // unlimited traces
   double rint;                    // sum_mu w_mu (eta_mu - etabar) b_x(x_mu) * Delta_j
@@ -321,7 +346,8 @@ __device__ __forceinline__ void recon_cell(const double* __restrict__ v5,  // in
                                            const double* __restrict__ m5,
                                            const double* __restrict__ b5,
                                            const double* __restrict__ J5, double iJ0, double Dx,
-                                           double eps, double etabar, CellRecon& o) {
+                                           double eps, double etabar, CellRecon& o,
+                                           bool split = false) {
   const double J0 = J5[2];
   double M1[4], M2[4], M3[4], M4[4];  // cells j-2, j-1, j+1, j+2
   stencil_moments(J5, iJ0, M1, M2, M3, M4);
@@ -458,11 +484,15 @@ __device__ __forceinline__ void recon_cell(const double* __restrict__ v5,  // in
     for (int mu = 0; mu < 4; ++mu) {
       double d[3], ph[3];
       lin_weights(mu, d);
-      const double a0 = d[0] * K[0], a1 = d[1] * K[1], a2 = d[2] * K[2];
-      const double ia = frcp(a0 + a1 + a2);
-      ph[0] = a0 * ia;
-      ph[1] = a1 * ia;
-      ph[2] = a2 * ia;
+      if (__builtin_expect(split && ((hiword(d[0]) | hiword(d[1]) | hiword(d[2])) >> 31), 0)) {
+        split_weights(d, K, ph);
+      } else {
+        const double a0 = d[0] * K[0], a1 = d[1] * K[1], a2 = d[2] * K[2];
+        const double ia = frcp(a0 + a1 + a2);
+        ph[0] = a0 * ia;
+        ph[1] = a1 * ia;
+        ph[2] = a2 * ia;
+      }
       if (cls == 1) {
 #pragma unroll
         for (int r = 0; r < 3; ++r) ph[r] = Mg * ph[r] + (1.0 - Mg) * d[r];
@@ -556,7 +586,8 @@ __device__ __forceinline__ void cell_geom(const double* __restrict__ J5, double 
 // Values of one variable at the 4 points (and, with der, its x-derivative);
 // returns the variable's class.
 __device__ __forceinline__ int recon_scalar(const CellGeom& G, const double* u5, double eps,
-                                            double iJ0, double* val, double* der) {
+                                            double iJ0, double* val, double* der,
+                                            bool split = false) {
   const int C1[3] = {2, 1, 0}, C2[3] = {3, 2, 1};
   const double du[4] = {u5[0] - u5[2], u5[1] - u5[2], u5[3] - u5[2], u5[4] - u5[2]};
   double Bv[3], Cv[3], beta[3];
@@ -589,11 +620,15 @@ __device__ __forceinline__ int recon_scalar(const CellGeom& G, const double* u5,
 #pragma unroll
       for (int r = 0; r < 3; ++r) ph[r] = G.d[mu][r];
     } else {
-      const double a0 = G.d[mu][0] * K[0], a1 = G.d[mu][1] * K[1], a2 = G.d[mu][2] * K[2];
-      const double ia = frcp(a0 + a1 + a2);
-      ph[0] = a0 * ia;
-      ph[1] = a1 * ia;
-      ph[2] = a2 * ia;
+      if (__builtin_expect(split && ((hiword(G.d[mu][0]) | hiword(G.d[mu][1]) | hiword(G.d[mu][2])) >> 31), 0)) {
+        split_weights(G.d[mu], K, ph);
+      } else {
+        const double a0 = G.d[mu][0] * K[0], a1 = G.d[mu][1] * K[1], a2 = G.d[mu][2] * K[2];
+        const double ia = frcp(a0 + a1 + a2);
+        ph[0] = a0 * ia;
+        ph[1] = a1 * ia;
+        ph[2] = a2 * ia;
+      }
       if (cls == 1) {
 #pragma unroll
         for (int r = 0; r < 3; ++r) ph[r] = Mg * ph[r] + (1.0 - Mg) * G.d[mu][r];
@@ -634,7 +669,8 @@ __device__ __forceinline__ void recon_cell_char(const double* __restrict__ e5,
                                                 const double* __restrict__ m5,
                                                 const double* __restrict__ b5,
                                                 const double* __restrict__ J5, double iJ0, double Dx,
-                                                double eps, double g, double dry, CellRecon& o) {
+                                                double eps, double g, double dry, CellRecon& o,
+                                                bool split = false) {
   CellGeom G;
   cell_geom(J5, iJ0, Dx, G);
   const double hb = e5[2] - b5[2];
@@ -654,9 +690,9 @@ __device__ __forceinline__ void recon_cell_char(const double* __restrict__ e5,
     for (int k = 0; k < 5; ++k) { w1[k] = e5[k]; w2[k] = m5[k]; }
   }
   double v1[4], v2[4], bv[4], bx[4];
-  const int c1 = recon_scalar(G, w1, eps, iJ0, v1, nullptr);
-  const int c2 = recon_scalar(G, w2, eps, iJ0, v2, nullptr);
-  const int cb = recon_scalar(G, b5, eps, iJ0, bv, bx);
+  const int c1 = recon_scalar(G, w1, eps, iJ0, v1, nullptr, split);
+  const int c2 = recon_scalar(G, w2, eps, iJ0, v2, nullptr, split);
+  const int cb = recon_scalar(G, b5, eps, iJ0, bv, bx, split);
   const double wgl[4] = {1.0 / 12.0, 5.0 / 12.0, 5.0 / 12.0, 1.0 / 12.0};
   double ri = 0.0, ev[4], mv[4];
 #pragma unroll

@@ -342,8 +342,9 @@ __device__ __forceinline__ StageRes stage_compute(const Bufs& bf, const Consts& 
                                                   const StageScal& sc, int64_t c0,
                                                   SmemStage<B, CPT>& sm, uint8_t* cls_inst,
                                                   int st, int t) {
-  constexpr bool HR = SCH == SCH_HYDRO;
-  constexpr bool NWB = SCH == SCH_NONWB;
+  constexpr bool HR = (SCH & 3) == SCH_HYDRO;
+  constexpr bool NWB = (SCH & 3) == SCH_NONWB;
+  constexpr bool split = (SCH & SCH_SPLIT) != 0;
   constexpr int TB = B * CPT;
   constexpr int NW = B / 64;
   const int lane = t & 63, wv = t >> 6;
@@ -391,10 +392,10 @@ __device__ __forceinline__ StageRes stage_compute(const Bufs& bf, const Consts& 
       const double Dx = (cs.flags & F_BETA_LOCAL) ? Jj[c] : sc.dx;
       if (NWB)
         recon_cell_char(se, sm.u.in.m + i, sb, sm.u.in.J + i, sm.u.in.iJ[i + 2], Dx, cs.weno_eps,
-                        cs.g, cs.dry_eps, o);
+                        cs.g, cs.dry_eps, o, split);
       else
         recon_cell<HR>(v5, h5, sm.u.in.m + i, sb, sm.u.in.J + i, sm.u.in.iJ[i + 2], Dx,
-                       cs.weno_eps, ebar[c], o);
+                       cs.weno_eps, ebar[c], o, split);
       const int lim = limit_cell(hbar, mbar[c], cs.pp_eps, o, !(cs.flags & F_NO_HU_LIMIT), NWB);
       // HR: the cell's hydrostatic source from its limited traces (eta kept by
       // the limiter) and the interior values; NWB: the source integral; else
@@ -412,7 +413,10 @@ __device__ __forceinline__ StageRes stage_compute(const Bufs& bf, const Consts& 
           bf.csig[g] = bf.csig[g] * CLS_SIG_MUL + (unsigned long long)(o.cls + 1);
         }
       }
-      if (o.negw && (owned || (lghost && i == 0) || i == ighr)) { neg_cell = true; st |= SB_NEGWEIGHT; }
+      if (o.negw && (owned || (lghost && i == 0) || i == ighr)) {
+        neg_cell = true;
+        if (!split) st |= SB_NEGWEIGHT;  // split weights: counted, not an error
+      }
       tl0[c] = o.hL; tl1[c] = o.mL; tl2[c] = o.bL;
       hR = o.hR; mR = o.mR; bR = o.bR;
     }

@@ -495,3 +495,41 @@ def test_depth_weight_and_step_size_errors_are_reported(dev):
                   dts=_t(dts, dev), dts_stride=10, check=False)
     want = alew.E_NEGDEPTH if ro["status"] == O.ST_NEGDEPTH else alew.E_NONFINITE
     assert s3[0].status == want and s3[0].steps == ro["stats"].steps
+
+
+def test_split_negative_weights_equal_oracle(dev):
+    """A static periodic mesh whose cells have negative linear weights (width
+    ratio 21), rough data over a non-flat bottom: with
+    ALEW_F_SPLIT forty alew_step calls equal the oracle's run with FLAG_SPLIT
+    (status OK, equal negative-weight counts, non-smooth cells present);
+    without the flag the first step reports ALEW_E_NEGWEIGHT."""
+    pattern = [0.41924619, 0.36692919, 7.89957065, 7.28913825, 4.92334761]
+    n = 60
+    wid = np.tile(pattern, n // 5)
+    x = np.concatenate([[0.0], np.cumsum(wid)])
+    xc = 0.5 * (x[1:] + x[:-1])
+    b = 0.3 * np.sin(6 * np.pi * xc / x[-1]) ** 2
+    eta = 2.0 + 0.5 * np.sign(np.sin(4 * np.pi * xc / x[-1]))
+    z = np.zeros(n)
+    P = O.params(bc=O.BC_PERIODIC, mesh=O.MESH_GIVEN, cfl=0.3, flags=O.FLAG_SPLIT)
+    r = O.run(P, eta - b, z, b, x, x, w=np.zeros(n + 1), max_steps=40)
+    assert r["status"] == 0 and r["stats"].n_negweight > 0 and r["stats"].n_class[2] > 0
+    ctx = alew.Context(n, 1)
+    for flags, nsteps in ((alew.F_SPLIT, 40), (0, 1)):
+        pg = alew.params(bc="periodic", mesh="given", cfl=0.3, flags=flags)
+        T = {k: _t(v, dev) for k, v in dict(h=eta - b, hu=z, b=b, x=x, w=np.zeros(n + 1)).items()}
+        negw, t = 0, 0.0
+        for _ in range(nsteps):
+            st = ctx.step(pg, T["h"], T["hu"], T["b"], T["x"], w=T["w"], t=t, check=False)
+            t = st.t
+            negw += st.n_negweight
+            if st.status != 0:
+                break
+        if flags:
+            assert st.status == 0 and negw == r["stats"].n_negweight
+            g = {k: T[k].cpu().numpy() for k in ("h", "hu", "b", "x")}
+            for k in ("h", "hu", "b", "x"):
+                e = np.abs(g[k] - r[k]).max() / max(1.0, np.abs(r[k]).max())
+                assert e <= 1e-11, (k, e)
+        else:
+            assert st.status == alew.E_NEGWEIGHT

@@ -948,3 +948,95 @@ def test_projected_bottom_keeps_still_water(bottom, flags):
     S = r["stats"]
     assert S.mass_b0 == pytest.approx(integral, rel=1e-13)
     assert S.mass_b == pytest.approx(integral, rel=1e-13)
+
+
+# ----------------------------------------------------------------------------
+# Negative linear weights (remark after Step 4 of Sec. 2.2): the splitting of
+# Shi, Hu & Shu (2002) behind FLAG_SPLIT
+# ----------------------------------------------------------------------------
+# widths of five cells whose linear weights at an interior Gauss-Lobatto point
+# include a negative one (found by search over width ratios up to e^8)
+NEG_PATTERN = [1.88578153e-02, 2.52381902e-02, 3.70078437e+00, 1.85853584e-02, 5.29734963e+01]
+
+
+def test_split_weights_properties():
+    """The split nonlinear weights add up to one, reduce to the linear weights
+    when every stencil is equally smooth, are the plain WENO-Z weights when no
+    linear weight is negative, give a stencil across a jump (small factor K)
+    no weight, and stay bounded where the plain weights blow up (sum d_r K_r
+    = 0)."""
+    d = np.asarray(O.geometry(NEG_PATTERN)[0]).reshape(4, 3)
+    dn = [row for row in d if row.min() < 0][0]
+    assert dn.min() < -0.1
+    rng = np.random.default_rng(4)
+    for _ in range(50):
+        K = 1.0 + rng.uniform(0, 1e3, 3) ** 2
+        phi = O.nonlinear_weights(dn, K, split=True)
+        assert abs(phi.sum() - 1.0) < 1e-13
+        dp = rng.uniform(0.05, 1.0, 3)
+        dp /= dp.sum()
+        assert np.array_equal(O.nonlinear_weights(dp, K, True), O.nonlinear_weights(dp, K, False))
+    np.testing.assert_allclose(O.nonlinear_weights(dn, [7.0, 7.0, 7.0], True), dn, atol=1e-15)
+    big = 1e12
+    for r in range(3):
+        K = np.full(3, big)
+        K[r] = 1.0
+        assert abs(O.nonlinear_weights(dn, K, True)[r]) < 1e-10
+    # factors with sum d_r K_r = 0: the plain weights divide by zero
+    d0 = np.array([-0.2, 0.9, 0.3])
+    K0 = np.array([6.0, 1.0, 1.0])
+    plain = O.nonlinear_weights(d0, K0, False)
+    assert not np.all(np.isfinite(plain)) or np.abs(plain).max() > 1e10
+    gp = 0.5 * (d0 + 3 * np.abs(d0))
+    sp, sm = gp.sum(), (gp - d0).sum()
+    split = O.nonlinear_weights(d0, K0, True)
+    assert np.all(split >= -sm - 1e-14) and np.all(split <= sp + 1e-14)
+    assert abs(split.sum() - 1.0) < 1e-14
+
+
+# a milder pattern (width ratio 21, smallest linear weight -0.028) for runs: the
+# one above amplifies round-off by ~1e5 over a few dozen steps
+NEG_PATTERN_RUN = [0.41924619, 0.36692919, 7.89957065, 7.28913825, 4.92334761]
+
+
+def _neg_mesh_case(n=60):
+    wid = np.tile(NEG_PATTERN_RUN, n // 5)
+    x = np.concatenate([[0.0], np.cumsum(wid)])
+    xc = 0.5 * (x[1:] + x[:-1])
+    L = x[-1]
+    b = 0.3 * np.sin(6 * np.pi * xc / L) ** 2
+    return x, xc, b
+
+
+def test_split_run_on_a_mesh_with_negative_weights():
+    """Rough data over a non-flat bottom on a static mesh whose cells have
+    negative linear weights: without FLAG_SPLIT the run reports ST_NEGWEIGHT;
+    with it the run completes, the split changes the state (the negative
+    weights sit at interior points, i.e. in the source quadrature), mass is
+    conserved (periodic); still water over the same bottom, all in the smooth
+    class, is the unsplit run bit for bit and stays at round-off."""
+    x, xc, b = _neg_mesh_case()
+    n = len(xc)
+    eta = 2.0 + 0.5 * np.sign(np.sin(4 * np.pi * xc / x[-1]))
+    z = np.zeros(n)
+    res = {}
+    for fl in (0, O.FLAG_SPLIT):
+        P = O.params(bc=O.BC_PERIODIC, mesh=O.MESH_GIVEN, cfl=0.3, flags=fl)
+        res[fl] = O.run(P, eta - b, z, b, x, x, w=np.zeros(n + 1), max_steps=40)
+    assert res[0]["status"] == O.ST_NEGWEIGHT and res[0]["stats"].n_negweight > 0
+    r = res[O.FLAG_SPLIT]
+    assert r["status"] == 0 and r["stats"].n_negweight == res[0]["stats"].n_negweight
+    assert r["stats"].n_class[2] > 0
+    assert np.abs(r["h"] - res[0]["h"]).max() > 1e-9
+    S = r["stats"]
+    assert abs(S.mass_eta - S.mass_eta0) < 1e-13 * abs(S.mass_eta0)
+    still = {}
+    for fl in (0, O.FLAG_SPLIT):
+        P = O.params(bc=O.BC_PERIODIC, mesh=O.MESH_GIVEN, cfl=0.3, flags=fl)
+        still[fl] = O.run(P, 2.0 - b, z, b, x, x, w=np.zeros(n + 1), max_steps=40)
+    rs = still[O.FLAG_SPLIT]
+    assert rs["status"] == 0 and rs["stats"].n_negweight > 0
+    assert rs["stats"].n_class[0] == 40 * 3 * n  # still water is smooth: linear weights
+    for k in ("h", "hu", "b"):
+        assert np.array_equal(rs[k], still[0][k])
+    assert np.abs(rs["h"] + rs["b"] - 2.0).max() < 1e-12 and np.abs(rs["hu"]).max() < 1e-12

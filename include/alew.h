@@ -333,10 +333,18 @@ alew_status alew_kernel_timing(const alew_ctx* ctx, int which, double* ms, int64
  * dimension (Sec. 2.2 along x on cell averages, then along y on the line
  * values): indicators summed over (eta, hu, hv), one class per sweep (the
  * cell's class is the largest of its x-sweep's and its four y-sweeps').
- * dt = cfl min(dx, dy) / (max over cells of max(|u|, |v|) + sqrt(g h) + max
- * node-speed bound of the maps at t).  No positivity limiter in 2D: traces with
- * h <= dry_eps carry zero discharge.  State arrays are [ny][nx] (cell (i, j)
- * at i + nx j), device FP64; nodes x [nx + 1], y [ny + 1] in place; reference
+ * Step size (the CFL condition eq. (3.19) sums over the four edges):
+ * dt = cfl / ((s + Wx) / min dx + (s + Wy) / min dy), Wx, Wy the largest node
+ * speeds of each direction at t, s the larger of the means' largest
+ * max(|u|, |v|) + sqrt(g h) and the previous step's Lax-Friedrichs alpha
+ * (eq. (3.13), on the traces; none at a call's first step).  Positivity: the
+ * limiter of eq. (3.20) split by direction as eq. (3.21)-(3.22) (the bottom
+ * and top edge traces limited together, the left and right ones together,
+ * each with the interior mean from the Gauss-Lobatto identity and
+ * eps = min(1e-11, hbar); hu, hv towards their means by the same factor, b
+ * following eta); traces with h <= dry_eps carry zero discharge; a mean depth
+ * below -1e-11 is ALEW_E_NEGDEPTH.  State arrays are [ny][nx] (cell (i, j) at
+ * i + nx j), device FP64; nodes x [nx + 1], y [ny + 1] in place; reference
  * nodes xi [nx + 1], yi [ny + 1].
  * ------------------------------------------------------------------------ */
 typedef struct alew2d_ctx alew2d_ctx;
@@ -354,6 +362,7 @@ typedef struct {
   double t, dt_min, dt_max;
   double mass0, mass_b0, mass, mass_b; /* sums of area x eta and area x b, start / end */
   int64_t n_class[3];                  /* cells x stages per class over the run        */
+  int64_t n_limited;                   /* cells x stages where the limiter acted       */
   int32_t status, pad;
 } alew2d_stats;
 
@@ -373,7 +382,8 @@ alew_status alew2d_set_launch(alew2d_ctx* ctx, int32_t rows, int32_t check_every
  * last step; cls_count (device, optional) [3 * nx * ny] and cls_sig (device,
  * optional) [nx * ny] accumulate a record of every stage as alew_run's do.
  * stats (host, optional).  Errors: ALEW_E_ARG / ALEW_E_UNSUPPORTED before any
- * work; ALEW_E_MESH (a non-positive area), ALEW_E_NONFINITE or ALEW_E_NEGWEIGHT
+ * work; ALEW_E_MESH (a non-positive area), ALEW_E_NEGDEPTH, ALEW_E_NONFINITE or
+ * ALEW_E_NEGWEIGHT
  * (a negative linear weight on a stage mesh; not split in 2D) stop the run
  * after the step that met them, with the state of that step in the arrays. */
 alew_status alew2d_run(alew2d_ctx* ctx, const alew2d_params* p, int64_t nx, int64_t ny,

@@ -107,7 +107,10 @@ def lib():
                                   C.c_int64, dp, C.c_int64, dp, dp, dp, dp, dp, dp]
         L.orc2_run.argtypes = [C.POINTER(Params2), C.c_int64, C.c_int64, dp, dp, dp, dp, dp, dp,
                                dp, dp, C.c_double, C.c_double, C.c_int64, dp,
-                               C.POINTER(C.c_int64), u8p, C.POINTER(C.c_int64), dp]
+                               C.POINTER(C.c_int64), u8p, C.POINTER(C.c_int64), dp,
+                               C.POINTER(C.c_int64), dp, C.c_int64]
+        L.orc2_limit_edges.argtypes = [C.c_double, C.c_double, C.c_double, dp]
+        L.orc2_limit_edges.restype = C.c_int
         L.orc2_sweep.argtypes = [dp, C.c_double, C.c_double, dp, dp, dp, dp, dp, dp, dp]
         L.orc2_residual.argtypes = [C.POINTER(Params2), C.c_int64, C.c_int64, dp, dp, dp, dp, dp,
                                     dp, dp, dp, dp]
@@ -175,6 +178,15 @@ def nonlinear_weights(d, K, split=True):
     phi = np.zeros(3)
     lib().orc_nonlinear_weights(_p(_f64(d)), _p(_f64(K)), 1 if split else 0, _p(phi))
     return phi
+
+
+def limit_edges2(hbar, mbar, nbar, e):
+    """The directional positivity limiter of one cell (eq. (3.21) / (3.22))
+    on its two opposite edges: e[2][4][4] = (side, Gauss-Lobatto
+    point, h / hu / hv / b).  Returns (limited copy, acted)."""
+    t = np.array(e, dtype=np.float64).reshape(32).copy()
+    r = lib().orc2_limit_edges(C.c_double(hbar), C.c_double(mbar), C.c_double(nbar), _p(t))
+    return t.reshape(2, 4, 4), bool(r)
 
 
 def reconstruct_char(widths5, eta5, m5, b5, dx, eps=1e-6, g=9.812, dry_eps=1e-8):
@@ -288,9 +300,10 @@ def residual2(P: Params2, eta, hu, hv, b, dx, dy, wx, wy):
 
 
 def run2(P: Params2, h, hu, hv, b, x, y, xi, yi, t0=0.0, t_end=0.0, max_steps=0,
-         record_cls=False):
+         record_cls=False, record_dts=0):
     """Time-march the 2D scheme; arrays [ny, nx] (row j, column i).  Returns
-    dict(h, hu, hv, b, x, y, t, steps, status, n_class, mass, cls)."""
+    dict(h, hu, hv, b, x, y, t, steps, status, n_class, mass, cls, n_limited,
+    dts: the step sizes of the first record_dts steps)."""
     h, hu, hv, b, x, y = (_f64(a).copy() for a in (h, hu, hv, b, x, y))
     ny, nx = h.shape
     t = np.zeros(1)
@@ -298,9 +311,14 @@ def run2(P: Params2, h, hu, hv, b, x, y, xi, yi, t0=0.0, t_end=0.0, max_steps=0,
     ncls = (C.c_int64 * 3)()
     mass = np.zeros(4)
     cls = np.zeros((max_steps, 3, ny, nx), np.uint8) if (record_cls and max_steps > 0) else None
+    nlim = C.c_int64()
+    dts = np.zeros(int(record_dts)) if record_dts > 0 else None
     st = lib().orc2_run(C.byref(P), nx, ny, _p(h), _p(hu), _p(hv), _p(b), _p(x), _p(y),
                         _p(_f64(xi)), _p(_f64(yi)), float(t0), float(t_end), int(max_steps),
                         _p(t), C.byref(steps), None if cls is None else
-                        cls.ctypes.data_as(C.POINTER(C.c_uint8)), ncls, _p(mass))
+                        cls.ctypes.data_as(C.POINTER(C.c_uint8)), ncls, _p(mass), C.byref(nlim),
+                        _p(dts), int(record_dts))
+    if dts is not None:
+        dts = dts[:min(steps.value, dts.size)]
     return dict(h=h, hu=hu, hv=hv, b=b, x=x, y=y, t=float(t[0]), steps=steps.value, status=st,
-                n_class=list(ncls), mass=mass, cls=cls)
+                n_class=list(ncls), mass=mass, cls=cls, n_limited=nlim.value, dts=dts)

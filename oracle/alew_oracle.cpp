@@ -1115,13 +1115,31 @@ static void mass(int n, const double* eta, const double* b, const double* x, dou
  *     edges and the interior term by the 4 x 4 Gauss-Lobatto rule on the cell
  *     (its geometric area at the stage time) with the unlimited values.
  * R27 Time: eq. (3.14) with the area recurrence eq. (3.15), div(w) J taken as
- *     dA/dt = dwx_i dy_j(t_s) + dx_i(t_s) dwy_j on the stage mesh t_s;
- *     dt = CFL min(dx, dy) / (max over cells of max(|u|, |v|) + sqrt(g h) +
- *     max |W|), W the node speeds at t_n.
- * R28 No positivity limiter in 2D (the directional limiter of eq. (3.21)-(3.22)
- *     is not built here); traces with h <= dry_eps carry u = v = 0 and
- *     hu = hv = 0 in the flux as in 1D.  Boundaries periodic or transmissive in
- *     each direction. */
+ *     dA/dt = dwx_i dy_j(t_s) + dx_i(t_s) dwy_j on the stage mesh t_s.  Step
+ *     size dt = CFL / ((s + Wx) / min dx + (s + Wy) / min dy): the CFL
+ *     condition eq. (3.19) sums over the four edges of the cell, so both
+ *     directions share the budget; Wx, Wy the largest
+ *     node speeds of each direction at t_n; s the larger of the largest
+ *     max(|u|, |v|) + sqrt(g h) over the cell means and the previous step's
+ *     Lax-Friedrichs alpha (the largest of its three stages; 0 at the first
+ *     step of a run).  Eq. (3.19) bounds dt by the alpha of eq. (3.13),
+ *     taken on the traces, which a step knows only after its stages: near a
+ *     wet-dry front a corner trace of small depth carries |hu / h| far above
+ *     the means' speeds, and a step size from the means alone then breaks
+ *     the condition by orders of magnitude (Example 5.9 on 50 x 50 cells
+ *     reaches alpha ~ 9e3 against ~ 20 and negative depths within ten
+ *     steps).
+ * R28 Positivity: the limiter of eq. (3.20) split by direction as
+ *     eq. (3.21)-(3.22) prescribe, on the rectangle's Gauss-Lobatto
+ *     points: the bottom and top edge traces of a cell are limited together
+ *     with delta1 (the mean of the interior rows from the Gauss-Lobatto
+ *     identity), the left and right edge traces with delta2, each with its own
+ *     Phi and eps = min(1e-11, hbar) (limit_edges2); hu, hv move to their means
+ *     by the same Phi and b follows eta (Remark 4.1); the source keeps the
+ *     unlimited point values.  A mean depth below -1e-11 ends the run
+ *     (ST_NEGDEPTH).  Traces with h <= dry_eps carry u = v = 0 and hu = hv = 0
+ *     in the flux as in 1D.  Boundaries periodic or transmissive in each
+ *     direction. */
 struct Params2 {
   double g, cfl, weno_eps, dry_eps;
   double Ax, kx, omx, Ay, ky, omy;
@@ -1180,7 +1198,48 @@ static int sweep2(const CellGeo& G, double Dx, double eps, const double e5[5], c
 struct Counters2 {
   int64_t n_class[3];
   int negw;  /* a negative linear weight on a stage mesh (R29) */
+  int64_t n_limited;  /* owned cells where the limiter acted in either direction */
+  int negdepth;       /* an owned mean depth below -1e-11 */
 };
+
+/* R28: the positivity limiter of eq. (3.20) in one direction of a rectangle
+ * (eq. (3.21) / (3.22)): the traces h, hu, hv, b at the
+ * 4 points of the cell's two edges across that direction, e[side][k][var].
+ * delta is the mean of the interior lines from the Gauss-Lobatto identity
+ * hbar = s1 (edge quadrature, side 0) + s1 (side 1) + (1 - 2 s1) delta;
+ * m = min(edge values, delta); where m < eps = min(1e-11, hbar) the depths,
+ * hu and hv move towards the cell means by Phi = (hbar - eps) / (hbar - m) and
+ * the bottom follows eta (Remark 4.1).  Returns 1 if it acted. */
+static int limit_edges2(double hbar, double mbar, double nbar, double e[2][4][4]) {
+  const double s1 = kGLW[0], PPE = 1e-11;
+  double eta[2][4];
+  for (int sd = 0; sd < 2; ++sd)
+    for (int k = 0; k < 4; ++k) eta[sd][k] = e[sd][k][0] + e[sd][k][3];
+  double Phi;
+  if (hbar <= 0.0) {
+    Phi = 0.0;
+  } else {
+    double q[2] = {0.0, 0.0};
+    for (int sd = 0; sd < 2; ++sd)
+      for (int k = 0; k < 4; ++k) q[sd] = q[sd] + kGLW[k] * e[sd][k][0];
+    const double delta = (hbar - s1 * q[0] - s1 * q[1]) / (1.0 - 2.0 * s1);
+    double mn = delta;
+    for (int sd = 0; sd < 2; ++sd)
+      for (int k = 0; k < 4; ++k) mn = std::min(mn, e[sd][k][0]);
+    const double epsj = std::min(PPE, hbar);
+    if (!(mn < epsj)) return 0;
+    Phi = std::min(1.0, (hbar - epsj) / (hbar - mn));
+  }
+  for (int sd = 0; sd < 2; ++sd)
+    for (int k = 0; k < 4; ++k) {
+      double* t = e[sd][k];
+      t[0] = Phi * (t[0] - hbar) + hbar;
+      t[1] = Phi * (t[1] - mbar) + mbar;
+      t[2] = Phi * (t[2] - nbar) + nbar;
+      t[3] = eta[sd][k] - t[0];
+    }
+  return 1;
+}
 
 static int wrap_index(int bc, int n, int k) {
   if (k >= 0 && k < n) return k;
@@ -1275,10 +1334,52 @@ static double residual2(const Params2& P, int nx, int ny, const double* eta, con
         if (cls) cls[i + nx * j] = (uint8_t)cmax;
       }
     }
-  /* traces at an edge point: h, hu, hv, b of one side */
+  /* R28: limited edge traces of every cell -1..nx x -1..ny: the left and
+   * right edges (points nu) limited across x, the bottom and top edges
+   * (points mu) across y; the point values V stay unlimited for the source */
+  std::vector<double> TX((size_t)VX * VY * 32), TY((size_t)VX * VY * 32);
+  auto TXat = [&](int i, int j, int sd, int k, int v) -> double& {
+    return TX[((((size_t)(j + 1) * VX + (i + 1)) * 2 + sd) * 4 + k) * 4 + v];
+  };
+  auto TYat = [&](int i, int j, int sd, int k, int v) -> double& {
+    return TY[((((size_t)(j + 1) * VX + (i + 1)) * 2 + sd) * 4 + k) * 4 + v];
+  };
+  for (int j = -1; j <= ny; ++j)
+    for (int i = -1; i <= nx; ++i) {
+      const int c = cell(i, j);
+      const double hbar = eta[c] - b[c];
+      double ex[2][4][4], ey[2][4][4];
+      for (int sd = 0; sd < 2; ++sd)
+        for (int k = 0; k < 4; ++k)
+          for (int v = 0; v < 4; ++v) {
+            ex[sd][k][v] = Vat(i, j, v, sd ? 3 : 0, k);
+            ey[sd][k][v] = Vat(i, j, v, k, sd ? 3 : 0);
+          }
+      const int lx = limit_edges2(hbar, mx[c], my[c], ex);
+      const int ly = limit_edges2(hbar, mx[c], my[c], ey);
+      for (int sd = 0; sd < 2; ++sd)
+        for (int k = 0; k < 4; ++k)
+          for (int v = 0; v < 4; ++v) {
+            TXat(i, j, sd, k, v) = ex[sd][k][v];
+            TYat(i, j, sd, k, v) = ey[sd][k][v];
+          }
+      if (i >= 0 && i < nx && j >= 0 && j < ny) {
+        if (lx || ly) cnt.n_limited += 1;
+        if (hbar < -1e-11) cnt.negdepth = 1;
+      }
+    }
+  /* traces at an edge point: h, hu, hv, b of one side; dir 0: the x-edge
+   * point nu of the left (mu = 0) or right (mu = 3) edge, dir 1: the y-edge
+   * point mu of the bottom (nu = 0) or top (nu = 3) edge */
   struct Tr { double h, m1, m2, b; };
-  auto trace = [&](int i, int j, int mu, int nu) {
-    Tr t{Vat(i, j, 0, mu, nu), Vat(i, j, 1, mu, nu), Vat(i, j, 2, mu, nu), Vat(i, j, 3, mu, nu)};
+  auto trace_x = [&](int i, int j, int sd, int nu) {
+    Tr t{TXat(i, j, sd, nu, 0), TXat(i, j, sd, nu, 1), TXat(i, j, sd, nu, 2), TXat(i, j, sd, nu, 3)};
+    if (!(t.h > P.dry_eps)) { t.m1 = 0.0; t.m2 = 0.0; }
+    return t;
+  };
+  auto trace_y = [&](int i, int j, int mu, int nu) {
+    const int sd = nu == 3 ? 1 : 0;
+    Tr t{TYat(i, j, sd, mu, 0), TYat(i, j, sd, mu, 1), TYat(i, j, sd, mu, 2), TYat(i, j, sd, mu, 3)};
     if (!(t.h > P.dry_eps)) { t.m1 = 0.0; t.m2 = 0.0; }
     return t;
   };
@@ -1291,14 +1392,14 @@ static double residual2(const Params2& P, int nx, int ny, const double* eta, con
   for (int j = 0; j < ny; ++j)
     for (int i = 0; i <= nx; ++i)
       for (int nu = 0; nu < 4; ++nu) {
-        alpha = std::max(alpha, speed(trace(i - 1, j, 3, nu), 0, wx[i]));
-        alpha = std::max(alpha, speed(trace(i, j, 0, nu), 0, wx[i]));
+        alpha = std::max(alpha, speed(trace_x(i - 1, j, 1, nu), 0, wx[i]));
+        alpha = std::max(alpha, speed(trace_x(i, j, 0, nu), 0, wx[i]));
       }
   for (int j = 0; j <= ny; ++j)
     for (int i = 0; i < nx; ++i)
       for (int mu = 0; mu < 4; ++mu) {
-        alpha = std::max(alpha, speed(trace(i, j - 1, mu, 3), 1, wy[j]));
-        alpha = std::max(alpha, speed(trace(i, j, mu, 0), 1, wy[j]));
+        alpha = std::max(alpha, speed(trace_y(i, j - 1, mu, 3), 1, wy[j]));
+        alpha = std::max(alpha, speed(trace_y(i, j, mu, 0), 1, wy[j]));
       }
   /* edge integrals: flux (eta, hu, hv), bottom flux, B1, B2 */
   struct EdgeI { double F[3], Gb, B1, B2; };
@@ -1335,13 +1436,13 @@ static double residual2(const Params2& P, int nx, int ny, const double* eta, con
   for (int j = 0; j < ny; ++j)
     for (int i = 0; i <= nx; ++i) {
       Tr Ls[4], Rs[4];
-      for (int nu = 0; nu < 4; ++nu) { Ls[nu] = trace(i - 1, j, 3, nu); Rs[nu] = trace(i, j, 0, nu); }
+      for (int nu = 0; nu < 4; ++nu) { Ls[nu] = trace_x(i - 1, j, 1, nu); Rs[nu] = trace_x(i, j, 0, nu); }
       EXs[(size_t)j * (nx + 1) + i] = edge(Ls[0], Rs[0], 0, wx[i], dy[j], kGLW, 4, Ls, Rs);
     }
   for (int j = 0; j <= ny; ++j)
     for (int i = 0; i < nx; ++i) {
       Tr Ls[4], Rs[4];
-      for (int mu = 0; mu < 4; ++mu) { Ls[mu] = trace(i, j - 1, mu, 3); Rs[mu] = trace(i, j, mu, 0); }
+      for (int mu = 0; mu < 4; ++mu) { Ls[mu] = trace_y(i, j - 1, mu, 3); Rs[mu] = trace_y(i, j, mu, 0); }
       EYs[(size_t)j * nx + i] = edge(Ls[0], Rs[0], 1, wy[j], dx[i], kGLW, 4, Ls, Rs);
     }
   const size_t N = (size_t)nx * ny;
@@ -1380,7 +1481,7 @@ static double chord2(double A, double om, double t, double dt) {
  * nodes x [nx+1], y [ny+1] in place; xi, yi the reference nodes. */
 static int step2(const Params2& P, int nx, int ny, double* eta, double* mx, double* my, double* b,
                  double* x, double* y, const double* xi, const double* yi, double& t, double dt,
-                 uint8_t* cls, Counters2& cnt) {
+                 uint8_t* cls, Counters2& cnt, double& alpha_max) {
   const size_t N = (size_t)nx * ny;
   std::vector<double> wx(nx + 1), wy(ny + 1);
   const double fx = chord2(P.Ax, P.omx, t, dt), fy = chord2(P.Ay, P.omy, t, dt);
@@ -1412,8 +1513,11 @@ static int step2(const Params2& P, int nx, int ny, double* eta, double* mx, doub
     for (int j = 0; j < ny; ++j) dys[j] = dy0[j] + tau[s] * dwy[j];
     for (size_t c = 0; c < N; ++c)
       if (!(Js[c] > 0.0)) return ST_MESH;
-    residual2(P, nx, ny, q.data(), q.data() + N, q.data() + 2 * N, q.data() + 3 * N, dxs.data(),
-              dys.data(), wx.data(), wy.data(), Rv.data(), cls ? cls + (size_t)s * N : nullptr, cnt);
+    const double alpha =
+        residual2(P, nx, ny, q.data(), q.data() + N, q.data() + 2 * N, q.data() + 3 * N,
+                  dxs.data(), dys.data(), wx.data(), wy.data(), Rv.data(),
+                  cls ? cls + (size_t)s * N : nullptr, cnt);
+    alpha_max = std::max(alpha_max, alpha);
     for (int j = 0; j < ny; ++j)
       for (int i = 0; i < nx; ++i) {
         const size_t c = (size_t)i + (size_t)nx * j;
@@ -1432,6 +1536,7 @@ static int step2(const Params2& P, int nx, int ny, double* eta, double* mx, doub
   for (int i = 0; i <= nx; ++i) x[i] = x[i] + dt * wx[i];
   for (int j = 0; j <= ny; ++j) y[j] = y[j] + dt * wy[j];
   t = t + dt;
+  if (cnt.negdepth) return ST_NEGDEPTH;
   for (size_t c = 0; c < N; ++c)
     for (int v = 0; v < 4; ++v)
       if (!std::isfinite(st[v][c])) return ST_NONFINITE;
@@ -1440,21 +1545,22 @@ static int step2(const Params2& P, int nx, int ny, double* eta, double* mx, doub
 
 static double cfl_dt2(const Params2& P, int nx, int ny, const double* eta, const double* mx,
                       const double* my, const double* b, const double* x, const double* y,
-                      const double* xi, const double* yi, double t) {
-  double hmin = INFINITY, smax = 0.0;
-  for (int i = 0; i < nx; ++i) hmin = std::min(hmin, x[i + 1] - x[i]);
-  for (int j = 0; j < ny; ++j) hmin = std::min(hmin, y[j + 1] - y[j]);
+                      const double* xi, const double* yi, double t, double alpha_prev) {
+  double dxmin = INFINITY, dymin = INFINITY, smax = 0.0;
+  for (int i = 0; i < nx; ++i) dxmin = std::min(dxmin, x[i + 1] - x[i]);
+  for (int j = 0; j < ny; ++j) dymin = std::min(dymin, y[j + 1] - y[j]);
   for (size_t c = 0; c < (size_t)nx * ny; ++c) {
     double h = eta[c] - b[c];
     double u = h > P.dry_eps ? mx[c] / h : 0.0, v = h > P.dry_eps ? my[c] / h : 0.0;
     smax = std::max(smax, std::max(std::fabs(u), std::fabs(v)) + std::sqrt(P.g * std::max(h, 0.0)));
   }
-  double W = 0.0;
+  double Wx = 0.0, Wy = 0.0;
   for (int i = 0; i <= nx; ++i)
-    W = std::max(W, std::fabs(P.Ax * P.omx * std::cos(P.omx * t) * std::sin(2.0 * M_PI * P.kx * xi[i])));
+    Wx = std::max(Wx, std::fabs(P.Ax * P.omx * std::cos(P.omx * t) * std::sin(2.0 * M_PI * P.kx * xi[i])));
   for (int j = 0; j <= ny; ++j)
-    W = std::max(W, std::fabs(P.Ay * P.omy * std::cos(P.omy * t) * std::sin(2.0 * M_PI * P.ky * yi[j])));
-  return P.cfl * hmin / (smax + W);
+    Wy = std::max(Wy, std::fabs(P.Ay * P.omy * std::cos(P.omy * t) * std::sin(2.0 * M_PI * P.ky * yi[j])));
+  smax = std::max(smax, alpha_prev);
+  return P.cfl / ((smax + Wx) / dxmin + (smax + Wy) / dymin);
 }
 }  // namespace orc
 
@@ -1709,7 +1815,9 @@ int orc_adjoint(const Params* P, int64_t n_, const double* h0, const double* hu0
 int orc2_run(const Params2* P, int64_t nx_, int64_t ny_, double* h, double* hu, double* hv,
              double* b, double* x, double* y, const double* xi, const double* yi, double t0,
              double t_end, int64_t max_steps, double* t_out, int64_t* steps_out, uint8_t* cls,
-             int64_t* n_class, double* mass /* [4]: eta, b at start and end */) {
+             int64_t* n_class, double* mass /* [4]: eta, b at start and end */,
+             int64_t* n_limited, double* dts_out /* step sizes of the first dts_cap steps */,
+             int64_t dts_cap) {
   const int nx = (int)nx_, ny = (int)ny_;
   if (nx < 5 || ny < 5) return ST_ARG;
   const size_t N = (size_t)nx * ny;
@@ -1729,16 +1837,19 @@ int orc2_run(const Params2* P, int64_t nx_, int64_t ny_, double* h, double* hu, 
   double t = t0;
   int64_t k = 0;
   int st = ST_OK;
-  Counters2 cnt{{0, 0, 0}, 0};
+  Counters2 cnt{{0, 0, 0}, 0, 0, 0};
+  double alpha_prev = 0.0;  /* the previous step's largest stage alpha (R27) */
   const bool timed = t_end > t0;
   while (true) {
     if (max_steps > 0 && k >= max_steps) break;
     if (timed && !(t < t_end)) break;
     if (!timed && max_steps <= 0) break;
-    double dt = cfl_dt2(*P, nx, ny, eta.data(), hu, hv, b, x, y, xi, yi, t);
+    double dt = cfl_dt2(*P, nx, ny, eta.data(), hu, hv, b, x, y, xi, yi, t, alpha_prev);
     if (timed && t + dt > t_end) dt = t_end - t;
+    if (dts_out && k < dts_cap) dts_out[k] = dt;
+    alpha_prev = 0.0;
     st = step2(*P, nx, ny, eta.data(), hu, hv, b, x, y, xi, yi, t, dt,
-               cls ? cls + (size_t)k * 3 * N : nullptr, cnt);
+               cls ? cls + (size_t)k * 3 * N : nullptr, cnt, alpha_prev);
     ++k;
     if (st != ST_OK) break;
   }
@@ -1748,6 +1859,7 @@ int orc2_run(const Params2* P, int64_t nx_, int64_t ny_, double* h, double* hu, 
   if (steps_out) *steps_out = k;
   if (n_class)
     for (int c = 0; c < 3; ++c) n_class[c] = cnt.n_class[c];
+  if (n_limited) *n_limited = cnt.n_limited;
   return st;
 }
 
@@ -1756,6 +1868,17 @@ int orc2_run(const Params2* P, int64_t nx_, int64_t ny_, double* h, double* hu, 
  * factors 1 + (tau / (beta_r + eps))^2; phi[3] out. */
 void orc_nonlinear_weights(const double* d, const double* K, int split, double* phi) {
   nonlinear_weights(d, K, split != 0, phi);
+}
+
+/* The directional limiter of R28 on one cell's two opposite edges:
+ * e[2][4][4] = (side, point, h/hu/hv/b), limited in place; returns 1 if it
+ * acted. */
+int orc2_limit_edges(double hbar, double mbar, double nbar, double* e) {
+  double t[2][4][4];
+  for (int k = 0; k < 32; ++k) t[k / 16][(k / 4) % 4][k % 4] = e[k];
+  const int r = limit_edges2(hbar, mbar, nbar, t);
+  for (int k = 0; k < 32; ++k) e[k] = t[k / 16][(k / 4) % 4][k % 4];
+  return r;
 }
 
 /* One 2D reconstruction sweep (R25) on 5 cells: out[6][4] as sweep2. */
@@ -1775,7 +1898,7 @@ int orc2_sweep(const double* wid5, double Dx, double eps, const double* e5, cons
 double orc2_residual(const Params2* P, int64_t nx, int64_t ny, const double* eta, const double* hu,
                      const double* hv, const double* b, const double* dx, const double* dy,
                      const double* wx, const double* wy, double* R) {
-  Counters2 cnt{{0, 0, 0}, 0};
+  Counters2 cnt{{0, 0, 0}, 0, 0, 0};
   return residual2(*P, (int)nx, (int)ny, eta, hu, hv, b, dx, dy, wx, wy, R, nullptr, cnt);
 }
 }  /* extern "C" */

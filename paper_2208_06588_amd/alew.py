@@ -72,8 +72,8 @@ class Stats2(C.Structure):
     _fields_ = [
         ("steps", C.c_int64), ("t", C.c_double), ("dt_min", C.c_double), ("dt_max", C.c_double),
         ("mass0", C.c_double), ("mass_b0", C.c_double), ("mass", C.c_double),
-        ("mass_b", C.c_double), ("n_class", C.c_int64 * 3), ("status", C.c_int32),
-        ("pad", C.c_int32),
+        ("mass_b", C.c_double), ("n_class", C.c_int64 * 3), ("n_limited", C.c_int64),
+        ("status", C.c_int32), ("pad", C.c_int32),
     ]
 
     def as_dict(self):

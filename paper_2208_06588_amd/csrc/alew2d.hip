@@ -69,6 +69,7 @@ struct State2 {
   int64_t steps, max_steps;
   unsigned long long alpha[3];  // bits of each stage's LF speed (non-negative: integer max)
   unsigned long long n_class[3];
+  unsigned long long n_limited;
   int32_t status, done, timed, pad;
 };
 
@@ -322,9 +323,39 @@ __device__ __forceinline__ double quad_sum(double v) {
   v += quad_perm<0xB1>(v);
   return v + quad_perm<0x4E>(v);
 }
+__device__ __forceinline__ double quad_min(double v) {
+  v = fmin(v, quad_perm<0xB1>(v));
+  return fmin(v, quad_perm<0x4E>(v));
+}
 __device__ __forceinline__ int quad_max(int v) {
   v = max(v, __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xf, 0xf, false));
   return max(v, __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xf, 0xf, false));
+}
+
+// Positivity limiter across one direction of a rectangle (eq. (3.21)-(3.22)
+// split by direction): Phi from the cell mean depth hbar, the Gauss-Lobatto
+// quadratures q0, q1 of the depth along the cell's two edges across that
+// direction and the smallest edge value mn; delta, the mean of the interior
+// lines, follows from hbar = s1 q0 + s1 q1 + (1 - 2 s1) delta.  Phi = 1 where
+// min(mn, delta) >= eps = min(1e-11, hbar); 0 where hbar <= 0.
+__device__ __forceinline__ double limiter_phi(double hbar, double q0, double q1, double mn) {
+  if (!(hbar > 0.0)) return 0.0;
+  const double s1 = GLW[0];
+  const double delta = (hbar - s1 * q0 - s1 * q1) / (1.0 - 2.0 * s1);
+  mn = fmin(mn, delta);
+  const double epsj = fmin(1e-11, hbar);
+  if (!(mn < epsj)) return 1.0;
+  return fmin(1.0, (hbar - epsj) / (hbar - mn));
+}
+// A trace moved towards the cell means by Phi; b follows eta (Remark 4.1).
+__device__ __forceinline__ void limit_trace(double Phi, double hbar, double mbar, double nbar,
+                                            double& h, double& m, double& n, double& b) {
+  if (Phi == 1.0) return;
+  const double eta = h + b;
+  h = Phi * (h - hbar) + hbar;
+  m = Phi * (m - mbar) + mbar;
+  n = Phi * (n - nbar) + nbar;
+  b = eta - h;
 }
 
 // ----------------------------------------------------------------------------
@@ -397,15 +428,19 @@ __global__ void __launch_bounds__(256) k2_mass_sum(K2 k, double* __restrict__ ou
 }
 
 // Step kinematics (one work-group): stop test, step size
-// dt = CFL min(dx, dy) / (max(|u|, |v|) + sqrt(g h) + max |W|), node speeds
-// (the chords of the prescribed maps over [t, t + dt]), widths and their
-// increments, stage Dx / Dy of the indicators, the geometry tables of the
-// three stage meshes, and the nodes of t + dt.
+// dt = CFL / ((s + Wx) / min dx + (s + Wy) / min dy) (the CFL condition
+// eq. (3.19) sums over the cell's four edges), s the larger of the means'
+// max(|u|, |v|) + sqrt(g h) and the previous step's Lax-Friedrichs alpha
+// (eq. (3.13), taken on the traces; zero at a run's first step), Wx, Wy the
+// largest node speeds of each direction; node speeds (the chords of the
+// prescribed maps over [t, t + dt]), widths and their increments, stage
+// Dx / Dy of the indicators, the geometry tables of the three stage meshes,
+// and the nodes of t + dt.
 __global__ void __launch_bounds__(KB) k2_kin(K2 k) {
   State2& S = *k.st;
   __shared__ int s_go;
   __shared__ double s_dt, s_t;
-  __shared__ double red[3 * (KB / 64)];
+  __shared__ double red[5 * (KB / 64)];
   const int tid = threadIdx.x;
   if (tid == 0) {
     bool stop = S.status != 0 || S.done != 0;
@@ -421,23 +456,28 @@ __global__ void __launch_bounds__(KB) k2_kin(K2 k) {
   const int nx = k.nx, ny = k.ny;
   const double t = s_t;
   const double TP = 2.0 * M_PI;
-  double hmin = INFINITY, W = 0.0, smax = 0.0;
+  double dxmin = INFINITY, dymin = INFINITY, Wx = 0.0, Wy = 0.0, smax = 0.0;
   for (int64_t e = tid; e < k.nspart; e += KB) smax = fmax(smax, k.spart[e]);
-  for (int i = tid; i < nx; i += KB) hmin = fmin(hmin, k.x[i + 1] - k.x[i]);
-  for (int j = tid; j < ny; j += KB) hmin = fmin(hmin, k.y[j + 1] - k.y[j]);
+  for (int i = tid; i < nx; i += KB) dxmin = fmin(dxmin, k.x[i + 1] - k.x[i]);
+  for (int j = tid; j < ny; j += KB) dymin = fmin(dymin, k.y[j + 1] - k.y[j]);
   const double cx = k.Ax * k.omx * cos(k.omx * t), cy = k.Ay * k.omy * cos(k.omy * t);
-  for (int i = tid; i <= nx; i += KB) W = fmax(W, fabs(cx * sin(TP * k.kx * k.xi[i])));
-  for (int j = tid; j <= ny; j += KB) W = fmax(W, fabs(cy * sin(TP * k.ky * k.yi[j])));
+  for (int i = tid; i <= nx; i += KB) Wx = fmax(Wx, fabs(cx * sin(TP * k.kx * k.xi[i])));
+  for (int j = tid; j <= ny; j += KB) Wy = fmax(Wy, fabs(cy * sin(TP * k.ky * k.yi[j])));
   {
-    double v[3] = {hmin, W, smax};
-    const int op[3] = {1, 0, 0};
-    block_reduce<KB, 3>(v, op, red);
-    hmin = v[0];
-    W = v[1];
-    smax = v[2];
+    double v[5] = {dxmin, dymin, Wx, Wy, smax};
+    const int op[5] = {1, 1, 0, 0, 0};
+    block_reduce<KB, 5>(v, op, red);
+    dxmin = v[0];
+    dymin = v[1];
+    Wx = v[2];
+    Wy = v[3];
+    smax = v[4];
   }
   if (tid == 0) {
-    double dt = k.cfl * hmin / (smax + W);
+    // the previous step's alpha of its three stages (bits of non-negative
+    // doubles; zeroed when a run starts)
+    for (int s = 0; s < 3; ++s) smax = fmax(smax, bitsd(S.alpha[s]));
+    double dt = k.cfl / ((smax + Wx) / dxmin + (smax + Wy) / dymin);
     if (S.timed && t + dt > S.t_end) dt = S.t_end - t;
     s_dt = dt;
     S.dt = dt;
@@ -646,7 +686,8 @@ __global__ void __launch_bounds__(256) k2_ysweep(K2 k, int rows) {
   const double wxl = k.wx[min(max(i, 0), nx)];
   const double wq = GLW[q];
   double amax = 0.0;
-  unsigned ncl[3] = {0u, 0u, 0u};
+  unsigned ncl[3] = {0u, 0u, 0u}, nlim = 0u;
+  bool negd = false;
   double th = 0.0, tm = 0.0, tn = 0.0, tb = 0.0;  // top trace at abscissa q, row below
   double Pc = 0.0, Pd = 0.0;  // component q of the previous row's partial right-hand side
   double etab_p = 0.0;
@@ -660,6 +701,10 @@ __global__ void __launch_bounds__(256) k2_ysweep(K2 k, int rows) {
     const double wyb = k.wy[min(max(jr, 0), ny)];
     const uint32_t c = (uint32_t)(ycol ? i : 0) + (uint32_t)nx * (uint32_t)jw;
     const double etab = body && ycol ? qcur[c] : 0.0;
+    // means of the cell (ring and ghost cells: their source cells) for the limiter
+    const uint32_t cm = (uint32_t)wrapi(k.bcx, nx, ic) + (uint32_t)nx * (uint32_t)jw;
+    const double hbar = qcur[cm] - qcur[3 * (uint32_t)k.N + cm];
+    const double mbar = qcur[(uint32_t)k.N + cm], nbar = qcur[2 * (uint32_t)k.N + cm];
     // reconstruction along y at abscissa q: point values at nu = 0..3
     double oh[4], om[4], on[4], ob[4], od[4], ox[4];
     int cl;
@@ -686,6 +731,38 @@ __global__ void __launch_bounds__(256) k2_ysweep(K2 k, int rows) {
         iy += (wq * GLW[nu]) * ((e - etab) * od[nu]);
       }
     }
+    // positivity limiter, per direction (the source above keeps the unlimited
+    // values): across x on the left and right edges (threads 0 and 3 hold
+    // them), across y on the bottom and top edges (point q of each here);
+    // both factors from the unlimited values
+    double p1, p2;
+    {
+      const double qb = quad_sum(wq * oh[0]), qt = quad_sum(wq * oh[3]);
+      p1 = limiter_phi(hbar, qb, qt, quad_min(fmin(oh[0], oh[3])));
+      double ql = 0.0, mnl = oh[0];
+#pragma unroll
+      for (int nu = 0; nu < 4; ++nu) {
+        ql += GLW[nu] * oh[nu];
+        mnl = fmin(mnl, oh[nu]);
+      }
+      const double q0 = quad_perm<0x00>(ql), q3 = quad_perm<0xFF>(ql);
+      const double m0 = quad_perm<0x00>(mnl), m3 = quad_perm<0xFF>(mnl);
+      p2 = limiter_phi(hbar, q0, q3, fmin(m0, m3));
+    }
+    const bool limited = p1 != 1.0 || p2 != 1.0;
+    // the left / right edge traces (corners included) limited across x
+    if (q == 0 || q == 3) {
+      double (*dst)[4] = q == 0 ? sL[cs] : sR[cs];
+#pragma unroll
+      for (int nu = 0; nu < 4; ++nu) {
+        double hh = oh[nu], mm = om[nu], nn = on[nu], bb = ob[nu];
+        limit_trace(p2, hbar, mbar, nbar, hh, mm, nn, bb);
+        dst[nu][0] = hh; dst[nu][1] = mm; dst[nu][2] = nn; dst[nu][3] = bb;
+      }
+    }
+    // the bottom / top traces at point q limited across y
+    limit_trace(p1, hbar, mbar, nbar, oh[0], om[0], on[0], ob[0]);
+    limit_trace(p1, hbar, mbar, nbar, oh[3], om[3], on[3], ob[3]);
     // bottom edge (node jr) at point q: the cell below's top trace
     double Cy[4] = {0, 0, 0, 0}, Dy[4] = {0, 0, 0, 0}, B1y = 0.0, B2y = 0.0;
     if (!first) {
@@ -694,16 +771,6 @@ __global__ void __launch_bounds__(256) k2_ysweep(K2 k, int rows) {
       if (ycol) amax = fmax(amax, am);
     }
     th = oh[3]; tm = om[3]; tn = on[3]; tb = ob[3];
-    if (q == 0)
-#pragma unroll
-      for (int nu = 0; nu < 4; ++nu) {
-        sL[cs][nu][0] = oh[nu]; sL[cs][nu][1] = om[nu]; sL[cs][nu][2] = on[nu]; sL[cs][nu][3] = ob[nu];
-      }
-    if (q == 3)
-#pragma unroll
-      for (int nu = 0; nu < 4; ++nu) {
-        sR[cs][nu][0] = oh[nu]; sR[cs][nu][1] = om[nu]; sR[cs][nu][2] = on[nu]; sR[cs][nu][3] = ob[nu];
-      }
     __syncthreads();
     // left edge (node i) at point q: the left neighbour's right trace
     double Cx[4] = {0, 0, 0, 0}, Dx[4] = {0, 0, 0, 0}, B1x = 0.0, B2x = 0.0;
@@ -762,6 +829,8 @@ __global__ void __launch_bounds__(256) k2_ysweep(K2 k, int rows) {
       if (own_col && q == 0) {
         const int cls = max(ymax, (int)k.xcls[(uint32_t)jr * (uint32_t)k.LW + lc]);
         ncl[cls] += 1u;
+        if (limited) nlim += 1u;
+        if (hbar < -1e-11) negd = true;
         const int64_t cc = i + (int64_t)nx * jr;
         if (k.cls) k.cls[S * k.N + cc] = (uint8_t)cls;
         if (k.ccount) k.ccount[cls * k.N + cc] += 1u;
@@ -777,6 +846,9 @@ __global__ void __launch_bounds__(256) k2_ysweep(K2 k, int rows) {
     const unsigned n = wave_usum(ncl[r]);
     if ((t & 63) == 0 && n) atomicAdd(&k.st->n_class[r], (unsigned long long)n);
   }
+  const unsigned nl = wave_usum(nlim);
+  if ((t & 63) == 0 && nl) atomicAdd(&k.st->n_limited, (unsigned long long)nl);
+  if (negd) atomicOr(&k.st->status, SB_NEGDEPTH);
 }
 
 // Step epilogue: the third stage's update into the step state, the finite
@@ -866,6 +938,7 @@ alew_status fail2(alew_status s, const std::string& m) { return alew_set_error(s
 
 alew_status map_bits(int bits) {
   if (bits & SB_MESH) return ALEW_E_MESH;
+  if (bits & SB_NEGDEPTH) return ALEW_E_NEGDEPTH;
   if (bits & SB_NONFINITE) return ALEW_E_NONFINITE;
   if (bits & SB_NEGWEIGHT) return ALEW_E_NEGWEIGHT;
   return bits ? ALEW_E_HIP : ALEW_OK;
@@ -1089,10 +1162,12 @@ alew_status alew2d_run(alew2d_ctx* c, const alew2d_params* p, int64_t nx, int64_
     stats->mass = c->mass_h[2];
     stats->mass_b = c->mass_h[3];
     for (int q = 0; q < 3; ++q) stats->n_class[q] = (int64_t)R.n_class[q];
+    stats->n_limited = (int64_t)R.n_limited;
     stats->status = (int32_t)status;
   }
   if (status != ALEW_OK)
     return fail2(status, status == ALEW_E_MESH       ? "a cell area became non-positive"
+                         : status == ALEW_E_NEGDEPTH  ? "a mean depth below -1e-11"
                          : status == ALEW_E_NEGWEIGHT ? "a negative linear weight on the stage mesh"
                                                       : "non-finite state");
   return ALEW_OK;

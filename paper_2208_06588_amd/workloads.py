@@ -308,3 +308,68 @@ def smooth_2d(n: int = 2048):
     wl = accuracy_2d(n)
     wl.update(Ax=0.02, omx=math.pi, Ay=0.02, omy=math.pi, t_end=0.0)
     return wl
+
+
+def dam_break_2d(nx: int = 200, ny: int | None = None, t_end: float = 1.75, amp=(0.03, 0.02)):
+    """Example 5.9, the circular dam break on [-100, 100]^2: b = 0, h = 10 for
+    r <= 60 and 0 outside, hu = hv = 0, transmissive; nodes moving per
+    direction in the tensor-product form of eq. (5.2):
+    x = xi + amp[0] sin(2 pi xi / 200) sin(2 pi t / t_end),
+    y = eta + amp[1] sin(2 pi eta / 200) sin(4 pi t / t_end).  The cells
+    cut by the dam hold the exact averages of the step."""
+    ny = nx if ny is None else ny
+    # nodes and averages mirror-symmetric to the bit about both axes
+    xi, yi = uniform_nodes(nx, -100.0, 100.0), uniform_nodes(ny, -100.0, 100.0)
+    xi, yi = 0.5 * (xi - xi[::-1]), 0.5 * (yi - yi[::-1])
+    h = _disc_averages_2d(xi, yi, 60.0, 10.0)
+    h = ((h + h[:, ::-1]) + (h[::-1, :] + h[::-1, ::-1])) * 0.25
+    z = np.zeros_like(h)
+    return dict(xi=xi, yi=yi, h=h, hu=z, hv=z.copy(), b=z.copy(), bc="transmissive", t_end=t_end,
+                Ax=amp[0], kx=1.0 / 200.0, omx=2 * math.pi / t_end, Ay=amp[1], ky=1.0 / 200.0,
+                omy=4 * math.pi / t_end)
+
+
+def _disc_area(x0: float, x1: float, y0: float, y1: float, r: float) -> float:
+    """Area of the rectangle [x0, x1] x [y0, y1] inside the disc of radius r
+    about the origin: the integral over x of the chord of the disc clipped to
+    [y0, y1], exact on each piece between the abscissae where the clipping
+    changes (the antiderivative of sqrt(r^2 - x^2) is
+    (x sqrt(r^2 - x^2) + r^2 asin(x / r)) / 2)."""
+    F = lambda x: 0.5 * (x * math.sqrt(max(r * r - x * x, 0.0)) + r * r * math.asin(max(-1.0, min(1.0, x / r))))
+    cuts = {x0, x1}
+    for y in (y0, y1):
+        if abs(y) < r:
+            s = math.sqrt(r * r - y * y)
+            cuts.update(c for c in (-s, s) if x0 < c < x1)
+    cuts.update(c for c in (-r, r) if x0 < c < x1)
+    pts = sorted(cuts)
+    area = 0.0
+    for a, b in zip(pts[:-1], pts[1:]):
+        xm = 0.5 * (a + b)
+        if abs(xm) >= r:
+            continue
+        s = math.sqrt(r * r - xm * xm)
+        top_arc, bot_arc = s < y1, -s > y0
+        if min(y1, s) <= max(y0, -s):
+            continue
+        arc = F(b) - F(a)
+        area += (arc if top_arc else y1 * (b - a)) - (-arc if bot_arc else y0 * (b - a))
+    return area
+
+
+def _disc_averages_2d(xn: np.ndarray, yn: np.ndarray, r: float, value: float) -> np.ndarray:
+    """Cell averages [ny, nx] of value inside the disc of radius r about the
+    origin and 0 outside."""
+    out = np.zeros((len(yn) - 1, len(xn) - 1))
+    for j in range(len(yn) - 1):
+        y0, y1 = float(yn[j]), float(yn[j + 1])
+        for i in range(len(xn) - 1):
+            x0, x1 = float(xn[i]), float(xn[i + 1])
+            near = min(x0 * x0 if x0 > 0 else (x1 * x1 if x1 < 0 else 0.0), 1e300) + \
+                (y0 * y0 if y0 > 0 else (y1 * y1 if y1 < 0 else 0.0))
+            far = max(x0 * x0, x1 * x1) + max(y0 * y0, y1 * y1)
+            if far <= r * r:
+                out[j, i] = value
+            elif near < r * r:
+                out[j, i] = value * _disc_area(x0, x1, y0, y1, r) / ((x1 - x0) * (y1 - y0))
+    return out

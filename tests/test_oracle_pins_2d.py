@@ -70,21 +70,24 @@ def test_sweep_reproduces_polynomials_on_nonuniform_widths():
 
 def test_y_constant_data_reduce_to_the_1d_scheme():
     """Example 5.1 data extended constantly in y, the y nodes at rest: every row
-    of the 2D run equals the pinned 1D oracle's run (same time steps, classes
-    and state; hv stays at round-off).  Pins the x-sweep, the edge fluxes, the
-    special source and the area recurrence against the 1D scheme."""
+    of the 2D run equals the pinned 1D oracle's run with the 2D run's step
+    sizes (same classes and state; hv stays at round-off).  Pins the x-sweep,
+    the edge fluxes, the special source and the area recurrence against the
+    1D scheme."""
     n, ny = 64, 5
     wl = W.accuracy_1d(n)
-    p1 = O.params(bc=O.BC_PERIODIC, mesh=O.MESH_SINE, mesh_A=0.05, mesh_k=1.0,
-                  mesh_omega=math.pi, cfl=0.6, weno_eps=wl["weno_eps"])
-    r1 = O.run(p1, wl["h"], wl["hu"], wl["b"], wl["x"], wl["xi"], t_end=0.1)
-    assert r1["status"] == 0
     yi = W.uniform_nodes(ny, 0.0, 1.0)
     P = _p2(cfl=0.6, weno_eps=wl["weno_eps"], Ax=0.05, kx=1.0, omx=math.pi, Ay=0.0)
     tile = lambda a: np.tile(np.asarray(a), (ny, 1))
     r2 = O.run2(P, tile(wl["h"]), tile(wl["hu"]), np.zeros((ny, n)), tile(wl["b"]), wl["xi"], yi,
-                wl["xi"], yi, t_end=0.1)
-    assert r2["status"] == 0 and r2["steps"] == r1["stats"].steps
+                wl["xi"], yi, t_end=0.1, record_dts=1000)
+    assert r2["status"] == 0 and r2["steps"] == len(r2["dts"])
+    p1 = O.params(bc=O.BC_PERIODIC, mesh=O.MESH_SINE, mesh_A=0.05, mesh_k=1.0,
+                  mesh_omega=math.pi, cfl=0.6, weno_eps=wl["weno_eps"])
+    r1 = O.run(p1, wl["h"], wl["hu"], wl["b"], wl["x"], wl["xi"], max_steps=r2["steps"],
+               dts=r2["dts"])
+    assert r1["status"] == 0 and r1["stats"].steps == r2["steps"]
+    assert abs(r1["t"] - 0.1) < 1e-15
     assert tuple(r2["n_class"]) == tuple(ny * c for c in r1["stats"].n_class)
     for k in ("h", "hu", "b"):
         assert np.abs(r2[k] - r1[k][None, :]).max() < 1e-12 * max(1.0, np.abs(r1[k]).max()), k
@@ -190,3 +193,125 @@ def test_accuracy_example_5_6_against_table_5_8():
             assert 0.7 < e / p < 1.3, (n, errs[n], paper[n])
     for a, b in zip(errs[25], errs[50]):
         assert math.log2(a / b) > 2.3
+
+
+def _edges(rng, hmin, hmax):
+    e = np.zeros((2, 4, 4))
+    e[..., 0] = rng.uniform(hmin, hmax, (2, 4))
+    e[..., 1:] = rng.normal(size=(2, 4, 3))
+    return e
+
+
+def _identity_delta(hbar, e):
+    """The interior mean fixed by the Gauss-Lobatto identity of the cell mean
+    (the decomposition in the proof of the positivity proposition, App. A)."""
+    w = np.array([1.0, 5.0, 5.0, 1.0]) / 12.0
+    q = (e[..., 0] * w).sum(axis=1)
+    return (hbar - w[0] * q[0] - w[0] * q[1]) / (1.0 - 2.0 * w[0])
+
+
+def test_directional_limiter_properties():
+    """The limiter of eq. (3.20) on one direction's two edges (eq. (3.21) /
+    (3.22)): with the edge depths and the interior mean delta (identity of the
+    cell mean, App. A) at or above eps = min(1e-11, hbar) nothing moves;
+    otherwise one factor Phi pulls h, hu, hv of every point towards the cell
+    means, the smallest of the edge depths and the new delta lands on eps,
+    the identity still returns the cell mean, and eta = h + b is unchanged at
+    every point (the bottom follows, Remark 4.1)."""
+    rng = np.random.default_rng(11)
+    for _ in range(50):
+        e = _edges(rng, 0.2, 3.0)
+        hbar, mb, nb = 1.5, 0.3, -0.2
+        if _identity_delta(hbar, e) < 1e-11:
+            continue
+        out, acted = O.limit_edges2(hbar, mb, nb, e)
+        assert not acted and np.array_equal(out, e)
+    cases = 0
+    for hbar in (1.0, 1e-3, 5e-12):
+        for lo, hi in ((-0.5 * hbar, 2.0 * hbar), (0.5 * hbar, 4.0 * hbar)):
+            for _ in range(30):
+                e = _edges(rng, lo, hi)
+                mb, nb = rng.normal(size=2)
+                d0 = _identity_delta(hbar, e)
+                eps = min(1e-11, hbar)
+                m = min(e[..., 0].min(), d0)
+                out, acted = O.limit_edges2(hbar, mb, nb, e)
+                assert acted == (m < eps)
+                if not acted:
+                    continue
+                cases += 1
+                phi = (out[0, 0, 0] - hbar) / (e[0, 0, 0] - hbar)
+                assert 0.0 <= phi < 1.0
+                tol = 1e-12 * max(1.0, abs(mb), abs(nb))
+                assert np.allclose(out[..., 0] - hbar, phi * (e[..., 0] - hbar), rtol=0, atol=1e-14 * hbar + 1e-27)
+                assert np.allclose(out[..., 1] - mb, phi * (e[..., 1] - mb), rtol=0, atol=tol)
+                assert np.allclose(out[..., 2] - nb, phi * (e[..., 2] - nb), rtol=0, atol=tol)
+                assert np.allclose(out[..., 0] + out[..., 3], e[..., 0] + e[..., 3], rtol=0,
+                                   atol=1e-15 * np.abs(e[..., 0] + e[..., 3]).max())
+                d1 = _identity_delta(hbar, out)
+                assert abs(min(out[..., 0].min(), d1) - eps) <= 1e-13 * hbar
+                assert abs(d1 - hbar - phi * (d0 - hbar)) <= 1e-13 * hbar
+    assert cases > 60
+    # an empty cell: every trace takes the means
+    e = _edges(rng, -1e-3, 1e-3)
+    out, acted = O.limit_edges2(0.0, 0.0, 0.0, e)
+    assert acted and not out[..., :3].any()
+    assert np.array_equal(out[..., 3], e[..., 0] + e[..., 3])
+
+
+def _dam(n, amp=(0.03, 0.02), dry_eps=1e-6, t_end=1.75, bc=O.BC_TRANSMISSIVE, **kw):
+    wl = W.dam_break_2d(n, amp=amp, t_end=t_end)
+    P = _p2(cfl=0.08, dry_eps=dry_eps, Ax=wl["Ax"], kx=wl["kx"], omx=wl["omx"], Ay=wl["Ay"],
+            ky=wl["ky"], omy=wl["omy"], bcx=bc, bcy=bc)
+    return wl, _run2(P, wl, t_end=t_end, **kw)
+
+
+def test_circular_dam_break_example_5_9():
+    """Example 5.9 (h = 10 inside r = 60, dry outside, flat bottom) on 50 x 50
+    moving cells to t = 1.75 at CFL 0.08: the run completes with the limiter
+    active, the smallest depth lies in [-1e-11, 1e-11] (Table 5.10 prints
+    1.00e-11, the limiter's eps), the solution keeps the data's mirror
+    symmetry about both axes, and on the periodic square (no outflow: the
+    scheme's stencils carry round-off-sized tails to a transmissive boundary
+    long before the front) the volume of water and of the bottom (which the
+    limited traces move, Remark 4.1) are conserved to round-off."""
+    paper = [float(r[1]) for r in _gold("paper_tables.txt") if r[0] == "table5.10"]
+    wl, r = _dam(50)
+    assert r["status"] == 0 and abs(r["t"] - 1.75) < 1e-15
+    assert r["n_limited"] > 0
+    h = r["h"]
+    assert -1e-11 <= h.min() <= paper[0]
+    assert np.abs(h - h[:, ::-1]).max() < 1e-11 and np.abs(h - h[::-1, :]).max() < 1e-11
+    for k in ("hu", "hv"):
+        assert np.abs(r[k]).max() > 1.0
+    assert np.abs(r["hu"] + r["hu"][:, ::-1]).max() < 1e-10
+    assert np.abs(r["hv"] + r["hv"][::-1, :]).max() < 1e-10
+    # along the x axis (cells of width 4 centred at 2, 6, ..., 98): the inner
+    # rarefaction has not reached the centre (it moves in at sqrt(10 g) ~ 9.9
+    # from r = 60), the depth at the dam site lies near the 1D dam-break value
+    # 4/9 h0 = 4.44, the front has passed r = 82, the corners stay dry
+    assert h[25, 25] > 9.99 and h.max() < 10.01
+    assert 3.5 < h[25, 39] < 6.0 and 3.5 < h[25, 40] < 6.0
+    assert 0.05 < h[25, 45] < 1.0
+    assert h[0, 0] < 1e-8 and h[-1, -1] < 1e-8
+    _, r1 = _dam(50, t_end=1.75, bc=O.BC_PERIODIC)
+    assert r1["status"] == 0 and r1["n_limited"] > 0
+    m = r1["mass"]
+    assert abs(m[2] - m[0]) < 1e-13 * m[0] and abs(m[3] - m[1]) < 1e-12
+
+
+def test_dam_break_without_lagged_alpha_would_break_the_cfl_bound():
+    """Why the step size takes the previous step's trace alpha (the CFL
+    condition eq. (3.19) is in terms of the alpha of eq. (3.13)): on the dam
+    break the traces' alpha exceeds the speed of the cell means several
+    times over, so a step size from the means alone would break the bound,
+    while the run with the lagged alpha keeps every mean depth non-negative
+    on a strongly moving mesh as well."""
+    wl, r = _dam(50, amp=(2.0, 4.0 / 3.0), record_dts=2000)
+    assert r["status"] == 0 and r["h"].min() >= -1e-11
+    h = wl["h"]
+    s0 = math.sqrt(9.812 * h.max())
+    # the first step uses the means (alpha of no step before it); later steps
+    # are shorter because the traces' alpha is larger
+    assert r["dts"][1:].min() < 0.5 * r["dts"][0]
+    assert r["dts"][0] < 0.08 / (2 * s0 / (200.0 / 50)) * 1.01

@@ -66,7 +66,9 @@ class Params2(C.Structure):
 def build(force: bool = False) -> str:
     """Compile the oracle with g++ (no FMA contraction, IEEE division/sqrt)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
+        # a name of its own per process: worker processes that start together
+        # may build at once, and each renames a complete library into place
+        tmp = f"{_LIB}.{os.getpid()}.tmp"
         subprocess.check_call(
             ["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
              "-shared", "-o", tmp, _SRC])

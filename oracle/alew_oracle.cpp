@@ -61,7 +61,16 @@
  *      h = eta - b is the difference of two separately updated means.
  *  R12 Special source (eq. (4.8)-(4.10), 1D): B1, B2 from the limited bottom
  *      traces; the interior integral uses the 4-point Gauss-Lobatto rule with
- *      the unlimited hybrid values of eta = h + b and of d b/dx.
+ *      the unlimited hybrid values of eta = h + b and of d b/dx: the
+ *      derivative of b's reconstruction, i.e. where the class is smooth the
+ *      derivative of the 5-cell quartic (the smooth class's reconstruction,
+ *      eq. (2.10) with the linear weights, is that quartic at every point);
+ *      in the non-smooth class the weighted stencil slopes sum_r phi_r p_r'
+ *      (the weights change from point to point and no single polynomial is
+ *      formed); in the transition class M times the WENO-Z weighted slopes
+ *      plus (1 - M) times the quartic's, the blend of eq. (2.8) applied to
+ *      the two parts, so that b_x, like the values, is continuous where the
+ *      class changes.
  *  R13 Bottom evolves by the ALE scheme of eq. (3.17) (the paper's default).
  *  R14 Ghost cells: 3 per side.  Periodic wraps; transmissive copies the
  *      boundary cell (values and width); reflective mirrors with hu negated.
@@ -106,9 +115,9 @@
  *      and the source) get their own indicators, class and weights.  The
  *      source integral of r(q, b) over the cell uses the 4-point Gauss-Lobatto
  *      rule of the limiter on the unlimited values (b_x: the derivative of b's
- *      hybrid reconstruction; where b's class is smooth, the derivative of the
- *      5-cell quartic, which is fourth order where the weighted candidate
- *      derivatives are second order only).  The limiter acts on h = eta - b and keeps the
+ *      hybrid reconstruction as in R12, with b's own class; the quartic's
+ *      derivative is fourth order where the weighted candidate derivatives
+ *      are second order only).  The limiter acts on h = eta - b and keeps the
  *      bottom traces (Remark 4.1 is stated for the well-balanced schemes; here
  *      a flat bottom stays flat).
  *  R23 params.bottom != ALE: the bottom is an analytic b(x) and its cell
@@ -479,11 +488,12 @@ static void reconstruct(const CellGeo& G, double Dx, double eps, const T v[5], c
   o.negw = 0;
   /* Steps 3-4 at each point. */
   for (int mu = 0; mu < 4; ++mu) {
-    T phi[3];
+    T phi[3], phiS[3]; /* weights of the values and of the slope's WENO part */
     for (int r = 0; r < 3; ++r)
       if (G.d[mu][r] < 0.0) o.negw = 1;
     if (cls == CLS_S) {
       for (int r = 0; r < 3; ++r) phi[r] = G.d[mu][r];
+      for (int r = 0; r < 3; ++r) phiS[r] = 0.0;
     } else {
       T Kf[3];
       for (int r = 0; r < 3; ++r) {
@@ -492,6 +502,7 @@ static void reconstruct(const CellGeo& G, double Dx, double eps, const T v[5], c
       }
       T phiN[3];
       nonlinear_weights(G.d[mu], Kf, split, phiN);
+      for (int r = 0; r < 3; ++r) phiS[r] = phiN[r];
       if (cls == CLS_N) {
         for (int r = 0; r < 3; ++r) phi[r] = phiN[r];
       } else {
@@ -511,7 +522,24 @@ static void reconstruct(const CellGeo& G, double Dx, double eps, const T v[5], c
       vh = vh + phi[r] * ph;
       vm = vm + phi[r] * pm;
       vb = vb + phi[r] * pb;
-      vbx = vbx + phi[r] * pbx;
+      vbx = vbx + phiS[r] * pbx;
+    }
+    /* R12: b_x is the derivative of b's reconstruction.  The linear part of
+     * eq. (2.10) is the quartic of the big stencil at every point, so its
+     * slope is the quartic's derivative; the WENO-Z part has weights that
+     * change from point to point, and its slope is taken as the weighted
+     * stencil slopes.  Smooth: the quartic's; transition: M times the
+     * weighted slopes plus (1 - M) times the quartic's (continuous at both
+     * class edges); non-smooth: the weighted slopes. */
+    if (cls != CLS_N) {
+      T vq = 0.0;
+      for (int k = 0; k < 5; ++k) vq = vq + G.cq[mu][k] * b[k];
+      if (cls == CLS_S) {
+        vbx = vq;
+      } else {
+        T M = 2.0 * gamma - 1.0;
+        vbx = M * vbx + (1.0 - M) * vq;
+      }
     }
     o.h[mu] = vh;
     o.m[mu] = vm;
@@ -557,18 +585,11 @@ static void reconstruct_char(const CellGeo& G, double Dx, double eps, double g, 
   Recon<T> r1, r2, rb;
   reconstruct(G, Dx, eps, w1, w1, zero, w1, r1, split);
   reconstruct(G, Dx, eps, w2, w2, zero, w2, r2, split);
+  /* b_x as R12: where b is smooth its reconstruction is the 5-cell quartic
+   * P (linear weights) and b_x its derivative, fourth order (the weighted
+   * stencil derivatives sum_r d_r p_r' leave out sum_r d_r' p_r and are
+   * second order only); blended in the transition class */
   reconstruct(G, Dx, eps, b, b, zero, b, rb, split);
-  if (rb.cls == CLS_S) {
-    /* where b is smooth its reconstruction is the 5-cell quartic P (linear
-     * weights), and b_x its derivative: fourth order, where the weighted
-     * stencil derivatives sum_r d_r p_r' leave out sum_r d_r' p_r and are
-     * second order only */
-    for (int mu = 0; mu < 4; ++mu) {
-      T v = 0.0;
-      for (int k = 0; k < 5; ++k) v = v + G.cq[mu][k] * b[k];
-      rb.bx[mu] = v;
-    }
-  }
   for (int mu = 0; mu < 4; ++mu) {
     T e, mm;
     if (chr) {
@@ -1105,7 +1126,9 @@ static void mass(int n, const double* eta, const double* b, const double* x, dou
  *     Gauss-Lobatto points of the cell.  Each sweep has its own indicators,
  *     class and hybrid weights, on (eta, hu, hv) summed (eq. (2.10), d = 3),
  *     shared by h, hu, hv and b; b_x is the y-sweep of the x-derivative line
- *     values, b_y the derivative in the y-sweep of b.  Dx of the indicators is
+ *     values, b_y the derivative in the y-sweep of b, each derivative taken
+ *     as in 1D (R12: the 5-cell quartic's where the sweep's class is smooth,
+ *     blended by M with the WENO-Z weighted slopes in the transition class).  Dx of the indicators is
  *     the largest width in the sweep's direction.  The class of a cell is the
  *     largest of its x-sweep's and its four y-sweeps' classes.
  * R26 Fluxes: the Lax-Friedrichs flux of eq. (3.13) at the 4 Gauss-Lobatto
@@ -1167,11 +1190,11 @@ static int sweep2(const CellGeo& G, double Dx, double eps, const double e5[5], c
   int cls = gamma <= 0.5 ? CLS_S : (gamma >= 1.0 ? CLS_N : CLS_T);
   const double* var[6] = {h5, mx5, my5, b5, b5, ext5};
   for (int mu = 0; mu < 4; ++mu) {
-    double phi[3];
+    double phi[3], pn[3] = {0.0, 0.0, 0.0};
     if (cls == CLS_S) {
       for (int r = 0; r < 3; ++r) phi[r] = G.d[mu][r];
     } else {
-      double Kf[3], pn[3];
+      double Kf[3];
       for (int r = 0; r < 3; ++r) {
         double q = tau / (beta[r] + eps);
         Kf[r] = 1.0 + q * q;
@@ -1187,9 +1210,17 @@ static int sweep2(const CellGeo& G, double Dx, double eps, const double e5[5], c
         double pr = 0.0;
         for (int i = 0; i < 3; ++i)
           pr = pr + (v == 4 ? G.cd[r][mu][i] : G.c[r][mu][i]) * var[v][2 - r + i];
-        acc = acc + phi[r] * pr;
+        acc = acc + (v == 4 ? pn[r] : phi[r]) * pr;
       }
       out[v][mu] = acc;
+    }
+    /* b's derivative as in 1D (R12): the quartic's where the class is smooth,
+     * blended with the WENO-Z weighted slopes by M in the transition class */
+    if (cls != CLS_N) {
+      double vq = 0.0;
+      for (int k = 0; k < 5; ++k) vq = vq + G.cq[mu][k] * b5[k];
+      const double M = 2.0 * gamma - 1.0;
+      out[4][mu] = cls == CLS_S ? vq : M * out[4][mu] + (1.0 - M) * vq;
     }
   }
   return cls;

@@ -56,7 +56,7 @@ namespace alew2d {
 // counterpart, and 1 / width.  SoA: field f of entry e at stage s is
 // T[(f * 3 + s) * n_entries + e].
 enum { GF_KB1 = 0, GF_KB2 = 3, GF_KC1 = 6, GF_KC2 = 9, GF_D = 12, GF_KAP = 24, GF_KAPC = 25,
-       GF_IJ = 26, NGF = 27 };
+       GF_IJ = 26, GF_QI = 27, GF_QB = 31, NGF = 35 };
 
 constexpr int STRIP = 62;  // columns owned by a y-sweep wavefront (64 lanes, one ring each side)
 constexpr int XB = 256;    // x-sweep work-group (row segment)
@@ -147,6 +147,9 @@ __device__ __forceinline__ void stage_update(const K2& k, int64_t c, double dx0,
 
 struct Geo {
   double kb1[3], kb2[3], kc1[3], kc2[3], d[4][3], kap, kapC, iJ;
+  // the quartic's fields (GF_QI, GF_QB), read where the sweep needs them
+  const double* tq;
+  int64_t tst;
 };
 
 __device__ __forceinline__ void load_geo(const double* __restrict__ T, int64_t ne, int s, int64_t e,
@@ -166,6 +169,8 @@ __device__ __forceinline__ void load_geo(const double* __restrict__ T, int64_t n
   G.kap = f(GF_KAP);
   G.kapC = f(GF_KAPC);
   G.iJ = f(GF_IJ);
+  G.tq = T + ((int64_t)GF_QI * 3 + s) * ne + e;
+  G.tst = 3 * ne;
 }
 
 // B_r, C_r of the three candidate stencils of one variable (Sec. 2.2, Step 1)
@@ -183,7 +188,10 @@ __device__ __forceinline__ void stencil_bc(const Geo& G, const double* u, double
 // along one direction: indicators of eq. (2.10) summed over (eta, hu, hv),
 // the detector class, the hybrid weights at the 4 Gauss-Lobatto points
 // shared by every variable; values of h, hu, hv, b (and of an extra variable
-// with EXT) at the points, and db/ds, the weighted candidate derivatives of b.
+// with EXT) at the points, and b's derivative along the sweep: the 5-cell
+// quartic's where the class is smooth, the stencil slopes weighted by the
+// WENO-Z weights where it is not, blended by M(gamma) in the transition class
+// (as in 1D).
 template <bool EXT>
 __device__ __forceinline__ int sweep(const Geo& G, double eps, const double* e5, const double* m5,
                                      const double* n5, const double* h5, const double* b5,
@@ -223,6 +231,27 @@ __device__ __forceinline__ int sweep(const Geo& G, double eps, const double* e5,
   const double q = 0.22360679774997896964;  // sqrt(5)/10
   const double yv[4] = {-0.5, -q, q, 0.5};
   const double p2v[4] = {1.0 / 6.0, -1.0 / 30.0, -1.0 / 30.0, 1.0 / 6.0};
+  // b's derivative: the quartic's (smooth and transition classes) first, at
+  // all 4 points; its geometry is loaded here, not with the rest (registers)
+  if (cls != 2) {
+    asm volatile("" ::: "memory");
+    double qi[4], qb[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      qi[i] = G.tq[i * G.tst];
+      qb[i] = G.tq[(i + GF_QB - GF_QI) * G.tst];
+    }
+    const double dB = Bb[0] - Bb[2], dC = Cb[0] - Cb[2];
+    const double a3 = qi[0] * dB + qi[1] * dC;
+    const double a4 = qi[2] * dB + qi[3] * dC;
+    const double a1 = Bb[1] - (a3 * qb[0] + a4 * qb[1]);
+    const double a2 = Cb[1] - (a3 * qb[2] + a4 * qb[3]);
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+      const double y = yv[mu];
+      od[mu] = (a1 + (2.0 * y) * a2 + (3.0 * y * y) * a3 + (4.0 * y * y * y) * a4) * G.iJ;
+    }
+  }
 #pragma unroll
   for (int mu = 0; mu < 4; ++mu) {
     double ph[3];
@@ -235,6 +264,16 @@ __device__ __forceinline__ int sweep(const Geo& G, double eps, const double* e5,
       ph[0] = a0 * ia;
       ph[1] = a1 * ia;
       ph[2] = a2 * ia;
+      // the WENO-Z weighted slopes of b: the derivative (non-smooth) or its
+      // Mg part (transition)
+      double sBn = 0.0, sCn = 0.0;
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        sBn += ph[r] * Bb[r];
+        sCn += ph[r] * Cb[r];
+      }
+      const double wN = (sBn + 2.0 * yv[mu] * sCn) * G.iJ;
+      od[mu] = cls == 2 ? wN : Mg * wN + (1.0 - Mg) * od[mu];
       if (cls == 1) {
 #pragma unroll
         for (int r = 0; r < 3; ++r) ph[r] = Mg * ph[r] + (1.0 - Mg) * G.d[mu][r];
@@ -252,16 +291,7 @@ __device__ __forceinline__ int sweep(const Geo& G, double eps, const double* e5,
     oh[mu] = val(Bh, Ch, h5[2]);
     om[mu] = val(Bm, Cm, m5[2]);
     on[mu] = val(Bn, Cn, n5[2]);
-    {
-      double sB = 0.0, sC = 0.0;
-#pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        sB += ph[r] * Bb[r];
-        sC += ph[r] * Cb[r];
-      }
-      ob[mu] = b5[2] + (sB * yv[mu] + sC * p2v[mu]);
-      od[mu] = (sB + 2.0 * yv[mu] * sC) * G.iJ;
-    }
+    ob[mu] = val(Bb, Cb, b5[2]);
     if (EXT) ox[mu] = val(Bx, Cx, x5[2]);
   }
   return cls;
@@ -567,6 +597,11 @@ __global__ void __launch_bounds__(KB) k2_kin(K2 k) {
     put(GF_KAP, G.kap);
     put(GF_KAPC, G.kapC);
     put(GF_IJ, iJ);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      put(GF_QI + i, G.qi[i]);
+      put(GF_QB + i, G.qb[i]);
+    }
   }
   // nodes of t + dt (every read of the old nodes is behind the barriers above)
   for (int i = tid; i <= nx; i += KB) k.x[i] = k.x[i] + dt * k.wx[i];

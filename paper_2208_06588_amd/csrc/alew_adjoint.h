@@ -277,6 +277,60 @@ struct ReconAdjOut {
   double letabar;
 };
 
+// The 5-cell quartic Q = ubar + a1 y + a2 (y^2 - 1/12) + a3 y^3 + a4 (y^4 -
+// 1/80) of one variable from its stencil coefficients B_r, C_r (as
+// recon_cell: a3, a4 from stencils 0 and 2 by the 2x2 system of their
+// coefficients on y^3 and y^4 - 1/80, a1, a2 from stencil 1), with the
+// geometry recomputed from the widths; and the reverse of that map.
+struct QuartGeo {
+  double qi[4], qb[4];
+};
+__device__ __forceinline__ void quartic_geo(const double* __restrict__ J5, double iJ0,
+                                            QuartGeo& Q) {
+  double M1[4], M2[4], M3[4], M4[4];
+  stencil_moments(J5, iJ0, M1, M2, M3, M4);
+  const int C1[3] = {2, 1, 0}, C2[3] = {3, 2, 1};
+  double B3[3], C3[3], B4[3], C4[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const int c1 = C1[r], c2 = C2[r];
+    const double idet = frcp(M1[c1] * M2[c2] - M1[c2] * M2[c1]);
+    const double kb1 = M2[c2] * idet, kb2 = -M2[c1] * idet;
+    const double kc1 = -M1[c2] * idet, kc2 = M1[c1] * idet;
+    B3[r] = kb1 * M3[c1] + kb2 * M3[c2];
+    C3[r] = kc1 * M3[c1] + kc2 * M3[c2];
+    B4[r] = kb1 * M4[c1] + kb2 * M4[c2];
+    C4[r] = kc1 * M4[c1] + kc2 * M4[c2];
+  }
+  const double g00 = B3[0] - B3[2], g01 = B4[0] - B4[2];
+  const double g10 = C3[0] - C3[2], g11 = C4[0] - C4[2];
+  const double igd = frcp(g00 * g11 - g01 * g10);
+  Q.qi[0] = g11 * igd; Q.qi[1] = -g01 * igd; Q.qi[2] = -g10 * igd; Q.qi[3] = g00 * igd;
+  Q.qb[0] = B3[1]; Q.qb[1] = B4[1]; Q.qb[2] = C3[1]; Q.qb[3] = C4[1];
+}
+__device__ __forceinline__ void quartic_b(const double* __restrict__ J5, double iJ0,
+                                          const double* Bx, const double* Cx, double* a) {
+  QuartGeo Q;
+  quartic_geo(J5, iJ0, Q);
+  const double dB = Bx[0] - Bx[2], dC = Cx[0] - Cx[2];
+  a[2] = Q.qi[0] * dB + Q.qi[1] * dC;
+  a[3] = Q.qi[2] * dB + Q.qi[3] * dC;
+  a[0] = Bx[1] - (a[2] * Q.qb[0] + a[3] * Q.qb[1]);
+  a[1] = Cx[1] - (a[2] * Q.qb[2] + a[3] * Q.qb[3]);
+}
+__device__ __forceinline__ void quartic_b_rev(const double* __restrict__ J5, double iJ0,
+                                              const double* la, double* lBx, double* lCx) {
+  QuartGeo Q;
+  quartic_geo(J5, iJ0, Q);
+  lBx[1] += la[0];
+  lCx[1] += la[1];
+  const double l2 = la[2] - (la[0] * Q.qb[0] + la[1] * Q.qb[2]);
+  const double l3 = la[3] - (la[0] * Q.qb[1] + la[1] * Q.qb[3]);
+  const double ldB = Q.qi[0] * l2 + Q.qi[2] * l3, ldC = Q.qi[1] * l2 + Q.qi[3] * l3;
+  lBx[0] += ldB; lBx[2] -= ldB;
+  lCx[0] += ldC; lCx[2] -= ldC;
+}
+
 // HR: the interior values of eta and b (points 1, 2) take the cotangents
 // le[mu], lb[mu] of the hydrostatic source instead of the special-source term.
 template <bool HR = false>
@@ -380,6 +434,25 @@ __device__ __forceinline__ void recon_cell_vjp(const double* __restrict__ v5,
     }
   }
   const double Mg = 2.0 * gam - 1.0;
+  // b_x (special source) by the rule of recon_cell: the slopes weighted by ph
+  // plus (1 - mq) corr, corr = Q_b' - (the slopes weighted by the linear
+  // weights), mq = 0 (smooth), Mg (transition), 1 (non-smooth).  For the
+  // smooth class the whole special-source term is reversed after the point
+  // loop, through the quartics (nothing of it is held across the loop); the
+  // transition class keeps corr and its cotangent at the 4 points.
+  const double mq = cls == 0 ? 0.0 : (cls == 1 ? Mg : 1.0);
+  double corr[4] = {0, 0, 0, 0}, lab[4] = {0, 0, 0, 0};
+  if (!HR && cls == 1) {
+    double ab[4];
+    quartic_b(J5, iJ0, Bb, Cb, ab);
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+      const double y = yv[mu];
+      const double wd = ((d[mu][0] * Bb[0] + d[mu][1] * Bb[1] + d[mu][2] * Bb[2]) +
+                         2.0 * y * (d[mu][0] * Cb[0] + d[mu][1] * Cb[1] + d[mu][2] * Cb[2])) * iJ0;
+      corr[mu] = (ab[0] + (2.0 * y) * ab[1] + (3.0 * y * y) * ab[2] + (4.0 * y * y * y) * ab[3]) * iJ0 - wd;
+    }
+  }
   // ---------------- reverse ----------------
   double lBv[3] = {0, 0, 0}, lCv[3] = {0, 0, 0}, lBh[3] = {0, 0, 0}, lCh[3] = {0, 0, 0};
   double lBm[3] = {0, 0, 0}, lCm[3] = {0, 0, 0}, lBb[3] = {0, 0, 0}, lCb[3] = {0, 0, 0};
@@ -411,7 +484,7 @@ __device__ __forceinline__ void recon_cell_vjp(const double* __restrict__ v5,
     }
     const double hv = h5[2] + (sBh * y + sCh * p2);
     const double bv = b5[2] + (sBb * y + sCb * p2);
-    const double bxv = (sBb + 2.0 * y * sCb) * iJ0;
+    const double bxv = (sBb + 2.0 * y * sCb) * iJ0 + (1.0 - mq) * corr[mu];
     // adjoints of the values at this point
     double lhv = 0.0, lmv = 0.0, lbv = 0.0, lbx = 0.0;
     if (mu == 0) { lhv += LL.h; lmv += LL.m; lbv += LL.b; }
@@ -419,7 +492,7 @@ __device__ __forceinline__ void recon_cell_vjp(const double* __restrict__ v5,
     if (HR) {
       // eta = h + b and b at the interior points feed the hydrostatic source
       if (mu == 1 || mu == 2) { lhv += hle[mu]; lbv += hle[mu] + hlb[mu]; }
-    } else {
+    } else if (cls != 0) {
       // rint = sum_mu (w_mu J0) ((h + b) - etabar) b_x
       const double cw = wgl[mu] * J0;
       lhv += lrint * cw * bxv;
@@ -429,6 +502,20 @@ __device__ __forceinline__ void recon_cell_vjp(const double* __restrict__ v5,
     }
     // v = v0 + (sB y + sC p2); b_x = (sB_b + 2 y sC_b) / J0
     lh0 += lhv; lm0 += lmv; lb0 += lbv;
+    if (cls == 1) {
+      // b_x's correction (1 - Mg) corr onto Mg, onto the linear weights'
+      // slopes here and onto the quartic's coefficients (reversed after the
+      // loop)
+      const double lq = (1.0 - Mg) * lbx * iJ0;
+      lMg -= corr[mu] * lbx;
+      lab[0] += lq; lab[1] += (2.0 * y) * lq; lab[2] += (3.0 * y * y) * lq;
+      lab[3] += (4.0 * y * y * y) * lq;
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        lBb[r] -= d[mu][r] * lq;
+        lCb[r] -= d[mu][r] * (2.0 * y * lq);
+      }
+    }
     const double lsBh = y * lhv, lsCh = p2 * lhv;
     const double lsBm = y * lmv, lsCm = p2 * lmv;
     const double lsBb = y * lbv + iJ0 * lbx, lsCb = p2 * lbv + 2.0 * y * iJ0 * lbx;
@@ -456,6 +543,41 @@ __device__ __forceinline__ void recon_cell_vjp(const double* __restrict__ v5,
 #pragma unroll
       for (int r = 0; r < 3; ++r) lK[r] += d[mu][r] * ((lphN[r] - dotp) * isa_mu[mu]);
     }
+  }
+  if (!HR && cls != 2) {
+    // reverse of the quartic parts: for the smooth class the special-source
+    // term sum_mu (w_mu J0) (eta_mu - etabar) Q_b'(y_mu) / J0 with eta_mu =
+    // ubar_h + ubar_b + Q_h(y_mu) + Q_b(y_mu) (the smooth values are the
+    // quartics'); for the transition class corr = Q_b' - weighted slopes
+    asm volatile("" ::: "memory");
+    if (cls == 0) {
+      double ab[4];
+      quartic_b(J5, iJ0, Bb, Cb, ab);
+      double ah[4], lah[4] = {0, 0, 0, 0};
+      quartic_b(J5, iJ0, Bh, Ch, ah);
+#pragma unroll
+      for (int mu = 0; mu < 4; ++mu) {
+        const double y = yv[mu], p2 = p2v[mu], f3 = f3v[mu], f4 = f4v[mu];
+        const double dy2 = 2.0 * y, dy3 = 3.0 * y * y, dy4 = 4.0 * y * y * y;
+        const double eta = (h5[2] + (ah[0] * y + ah[1] * p2 + ah[2] * f3 + ah[3] * f4)) +
+                           (b5[2] + (ab[0] * y + ab[1] * p2 + ab[2] * f3 + ab[3] * f4));
+        const double bxv = (ab[0] + dy2 * ab[1] + dy3 * ab[2] + dy4 * ab[3]) * iJ0;
+        const double cw = wgl[mu] * J0;
+        const double le = lrint * cw * bxv;      // onto h and b at the point
+        const double lbx = lrint * cw * (eta - etabar);
+        letab -= le;
+        lh0 += le;
+        lb0 += le;
+        lah[0] += y * le; lah[1] += p2 * le; lah[2] += f3 * le; lah[3] += f4 * le;
+        const double lbj = iJ0 * lbx;
+        lab[0] += y * le + lbj;
+        lab[1] += p2 * le + dy2 * lbj;
+        lab[2] += f3 * le + dy3 * lbj;
+        lab[3] += f4 * le + dy4 * lbj;
+      }
+      quartic_b_rev(J5, iJ0, lah, lBh, lCh);
+    }
+    quartic_b_rev(J5, iJ0, lab, lBb, lCb);
   }
   double lbeta[3] = {0, 0, 0}, ltau = 0.0;
   if (cls != 0) {
@@ -649,7 +771,7 @@ __device__ __forceinline__ void adj_slot_put(const AdjSlotRaw& r, int q, double 
 }
 
 template <int B, bool HR>
-__global__ __launch_bounds__(B) void k_adj_fused(AdjBufs ab, Consts cs,
+__global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(2))) void k_adj_fused(AdjBufs ab, Consts cs,
                                                  const AdjTile* __restrict__ tiles, int s,
                                                  double* __restrict__ gfold) {
   constexpr int TB = B - 6;

@@ -422,6 +422,78 @@ __device__ __forceinline__ void recon_cell(const double* __restrict__ v5,  // in
   // (eta - etabar) b_x, weights (1,5,5,1)/12, summed in point order
   const double wgl[4] = {1.0 / 12.0, 5.0 / 12.0, 5.0 / 12.0, 1.0 / 12.0};
   double ri = 0.0;
+  // The smooth class combines the stencils with the linear weights, which is
+  // the 5-cell quartic Q = ubar + a1 y + a2 (y^2 - 1/12) + a3 y^3 +
+  // a4 (y^4 - 1/80) itself.  Each stencil quadratic reproduces the first two
+  // terms and projects the last two: B_r = a1 + a3 B3_r + a4 B4_r and
+  // C_r = a2 + a3 C3_r + a4 C4_r, so stencils 0 and 2 give a3, a4 (a 2x2
+  // system that only depends on the geometry) and stencil 1 gives a1, a2.
+  // b_x of the smooth class is Q_b' / Delta_j.
+  // the 2x2 matrix of stencils 0 and 2 (formed where used: kept live across
+  // the point loops it would cost registers)
+  auto gmat = [&](double* g) {
+    g[0] = B3[0] - B3[2]; g[1] = B4[0] - B4[2];
+    g[2] = C3[0] - C3[2]; g[3] = C4[0] - C4[2];
+  };
+  auto quartic = [&](const double* Bx, const double* Cx, const double* g, double igd, double* a) {
+    const double dB = Bx[0] - Bx[2], dC = Cx[0] - Cx[2];
+    a[2] = (g[3] * dB - g[1] * dC) * igd;
+    a[3] = (g[0] * dC - g[2] * dB) * igd;
+    a[0] = Bx[1] - (a[2] * B3[1] + a[3] * B4[1]);
+    a[1] = Cx[1] - (a[2] * C3[1] + a[3] * C4[1]);
+  };
+  // Q' at the 4 points from its even and odd parts
+  auto qslope = [&](const double* a, double* bx) {
+    const double ee = a[0] + 0.75 * a[2], oe = a[1] + 0.5 * a[3];
+    const double ei = a[0] + 0.15 * a[2], oi = (2.0 * q) * a[1] + (4.0 * q3) * a[3];
+    bx[0] = (ee - oe) * iJ0;
+    bx[1] = (ei - oi) * iJ0;
+    bx[2] = (ei + oi) * iJ0;
+    bx[3] = (ee + oe) * iJ0;
+  };
+  // Where no width of the stencil is more than four times another, every
+  // linear weight at the 4 points is positive (smallest 0.011, at widths
+  // (4, 4, 4, 1, 1)): a smooth cell there needs neither the weights nor their
+  // sign test and evaluates Q directly.
+  const double jmax = vmax(vmax(vmax(J5[0], J5[1]), vmax(J5[3], J5[4])), J0);
+  const double jmin = vmin(vmin(vmin(J5[0], J5[1]), vmin(J5[3], J5[4])), J0);
+  if (cls == 0 && jmax <= 4.0 * jmin) {
+    double g[4];
+    gmat(g);
+    const double igd = frcp(g[0] * g[3] - g[1] * g[2]);
+    double ah[4], ab[4], am[4], bx[4];
+    quartic(Bh, Ch, g, igd, ah);
+    quartic(Bb, Cb, g, igd, ab);
+    quartic(Bm, Cm, g, igd, am);
+    qslope(ab, bx);
+    // values at -1/2, -q, q, 1/2: even part a2 p2 + a4 f4, odd part a1 y + a3 y^3
+    auto vals = [&](double v0, const double* a, double* v) {
+      const double ee = a[1] * (1.0 / 6.0) + a[3] * 0.05, oe = a[0] * 0.5 + a[2] * 0.125;
+      const double ei = a[1] * (-1.0 / 30.0) + a[3] * (-0.01), oi = a[0] * q + a[2] * q3;
+      v[0] = v0 + (ee - oe);
+      v[1] = v0 + (ei - oi);
+      v[2] = v0 + (ei + oi);
+      v[3] = v0 + (ee + oe);
+    };
+    double hv[4], bv[4];
+    vals(h5[2], ah, hv);
+    vals(b5[2], ab, bv);
+    if (HR) {
+      o.e1 = hv[1] + bv[1]; o.b1 = bv[1];
+      o.e2 = hv[2] + bv[2]; o.b2 = bv[2];
+    } else {
+#pragma unroll
+      for (int mu = 0; mu < 4; ++mu) ri += (wgl[mu] * J0) * (((hv[mu] + bv[mu]) - etabar) * bx[mu]);
+    }
+    o.hL = hv[0]; o.bL = bv[0]; o.hR = hv[3]; o.bR = bv[3];
+    const double em = am[1] * (1.0 / 6.0) + am[3] * 0.05, om = am[0] * 0.5 + am[2] * 0.125;
+    o.mL = m5[2] + (em - om);
+    o.mR = m5[2] + (em + om);
+    o.rint = ri;
+    o.cls = 0;
+    o.negw = 0;
+    return;
+  }
   // linear weights d_r at point mu
   auto lin_weights = [&](int mu, double* d) {
     double e3[3], e4[3];
@@ -439,8 +511,9 @@ __device__ __forceinline__ void recon_cell(const double* __restrict__ v5,  // in
     d[2] = x2 * is;
     sgn |= hiword(d[0]) | hiword(d[1]) | hiword(d[2]);
   };
-  // reconstructed values at point mu with the weights ph_r
-  auto at_point = [&](int mu, const double* ph) {
+  // reconstructed values at point mu with the weights ph_r; b_x given (bxg)
+  // or, non-smooth class, the stencil slopes weighted by ph
+  auto at_point = [&](int mu, const double* ph, double bxg) {
     const double y = yv[mu], p2 = p2v[mu];
     double sBh = 0, sCh = 0, sBm = 0, sCm = 0, sBb = 0, sCb = 0;
 #pragma unroll
@@ -458,19 +531,28 @@ __device__ __forceinline__ void recon_cell(const double* __restrict__ v5,  // in
       if (mu == 1) { o.e1 = hv + bv; o.b1 = bv; }
       if (mu == 2) { o.e2 = hv + bv; o.b2 = bv; }
     } else {
-      const double bxv = (sBb + 2.0 * y * sCb) * iJ0;
+      const double bxv = cls == 2 ? (sBb + 2.0 * y * sCb) * iJ0 : bxg;
       ri += (wgl[mu] * J0) * (((hv + bv) - etabar) * bxv);
     }
     if (mu == 0) { o.hL = hv; o.mL = m5[2] + (sBm * y + sCm * p2); o.bL = bv; }
     if (mu == 3) { o.hR = hv; o.mR = m5[2] + (sBm * y + sCm * p2); o.bR = bv; }
   };
-  // one branch per cell (not per point): a smooth cell takes the linear weights
+  // one branch per cell (not per point)
   if (cls == 0) {
+    // smooth cell on a stencil with widths further apart: the weights (and
+    // their sign test) at every point, b_x the quartic's
+    double bx[4] = {0.0, 0.0, 0.0, 0.0};
+    if (!HR) {
+      double g[4], ab[4];
+      gmat(g);
+      quartic(Bb, Cb, g, frcp(g[0] * g[3] - g[1] * g[2]), ab);
+      qslope(ab, bx);
+    }
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) {
       double d[3];
       lin_weights(mu, d);
-      at_point(mu, d);
+      at_point(mu, d, bx[mu]);
     }
   } else {
     double K[3];
@@ -493,11 +575,27 @@ __device__ __forceinline__ void recon_cell(const double* __restrict__ v5,  // in
         ph[1] = a1 * ia;
         ph[2] = a2 * ia;
       }
+      double bxg = 0.0;
       if (cls == 1) {
+        // transition: b_x = Mg (WENO-Z weighted slopes) + (1 - Mg) Q' (the
+        // quartic recomputed at each point: a rare class, no registers held
+        // across the loop)
+        const double y = yv[mu];
+        const double wN = HR ? 0.0
+                             : ((ph[0] * Bb[0] + ph[1] * Bb[1] + ph[2] * Bb[2]) +
+                                2.0 * y * (ph[0] * Cb[0] + ph[1] * Cb[1] + ph[2] * Cb[2])) * iJ0;
 #pragma unroll
         for (int r = 0; r < 3; ++r) ph[r] = Mg * ph[r] + (1.0 - Mg) * d[r];
+        if (!HR) {
+          double g[4], ab[4];
+          gmat(g);
+          quartic(Bb, Cb, g, frcp(g[0] * g[3] - g[1] * g[2]), ab);
+          const double qd = ab[0] + (2.0 * y) * ab[1] + (3.0 * y * y) * ab[2] +
+                            (4.0 * y * y * y) * ab[3];
+          bxg = Mg * wN + (1.0 - Mg) * (qd * iJ0);
+        }
       }
-      at_point(mu, ph);
+      at_point(mu, ph, bxg);
     }
   }
   o.rint = ri;
@@ -517,6 +615,9 @@ struct CellGeom {
   double d[4][3];                         // linear weights at the 4 points
   double dd[4][3];                        // their derivatives d/dy at the 4 points
   double kap, kapC;                       // Dx / Delta_j and the y^2 indicator factor
+  // the 5-cell quartic's a3, a4 = qi (B_0 - B_2, C_0 - C_2) and a1 = B_1 -
+  // a3 qb[0] - a4 qb[1], a2 = C_1 - a3 qb[2] - a4 qb[3] (see recon_cell)
+  double qi[4], qb[4];
   unsigned sgn;                           // OR of the weights' high words (sign bit)
 };
 
@@ -581,6 +682,14 @@ __device__ __forceinline__ void cell_geom(const double* __restrict__ J5, double 
   G.sgn = sgn;
   G.kap = Dx * iJ0;
   G.kapC = G.kap * (1.0 / 3.0) + 4.0 * G.kap * G.kap * G.kap;
+  {
+    const double g00 = B3[0] - B3[2], g01 = B4[0] - B4[2];
+    const double g10 = C3[0] - C3[2], g11 = C4[0] - C4[2];
+    const double igd = frcp(g00 * g11 - g01 * g10);
+    G.qi[0] = g11 * igd; G.qi[1] = -g01 * igd;
+    G.qi[2] = -g10 * igd; G.qi[3] = g00 * igd;
+    G.qb[0] = B3[1]; G.qb[1] = B4[1]; G.qb[2] = C3[1]; G.qb[3] = C4[1];
+  }
 }
 
 // Values of one variable at the 4 points (and, with der, its x-derivative);
@@ -615,7 +724,7 @@ __device__ __forceinline__ int recon_scalar(const CellGeom& G, const double* u5,
   const double p2v[4] = {1.0 / 6.0, -1.0 / 30.0, -1.0 / 30.0, 1.0 / 6.0};
 #pragma unroll
   for (int mu = 0; mu < 4; ++mu) {
-    double ph[3];
+    double ph[3], pn[3] = {0.0, 0.0, 0.0};
     if (cls == 0) {
 #pragma unroll
       for (int r = 0; r < 3; ++r) ph[r] = G.d[mu][r];
@@ -629,6 +738,7 @@ __device__ __forceinline__ int recon_scalar(const CellGeom& G, const double* u5,
         ph[1] = a1 * ia;
         ph[2] = a2 * ia;
       }
+      pn[0] = ph[0]; pn[1] = ph[1]; pn[2] = ph[2];
       if (cls == 1) {
 #pragma unroll
         for (int r = 0; r < 3; ++r) ph[r] = Mg * ph[r] + (1.0 - Mg) * G.d[mu][r];
@@ -642,16 +752,29 @@ __device__ __forceinline__ int recon_scalar(const CellGeom& G, const double* u5,
     }
     val[mu] = u5[2] + (sB * yv[mu] + sC * p2v[mu]);
     if (der) {
-      if (cls == 0) {
-        // smooth: the reconstruction is the 5-cell quartic sum_r d_r p_r, and its
-        // derivative sum_r (d_r' p_r + d_r p_r') is fourth order (the weighted
-        // stencil derivatives alone are second order)
-        double dq = sB + 2.0 * yv[mu] * sC;
+      // the derivative of the reconstruction: where it is the 5-cell quartic
+      // sum_r d_r p_r (smooth class), sum_r (d_r' p_r + d_r p_r') (fourth
+      // order; the weighted stencil derivatives alone are second order); the
+      // WENO-Z weighted stencil slopes where it is not, blended by Mg in the
+      // transition class
+      double dq = 0.0;
+      if (cls != 2) {
 #pragma unroll
-        for (int r = 0; r < 3; ++r) dq += G.dd[mu][r] * (Bv[r] * yv[mu] + Cv[r] * p2v[mu]);
+        for (int r = 0; r < 3; ++r)
+          dq += G.d[mu][r] * (Bv[r] + 2.0 * yv[mu] * Cv[r]) +
+                G.dd[mu][r] * (Bv[r] * yv[mu] + Cv[r] * p2v[mu]);
+      }
+      if (cls == 0) {
         der[mu] = dq * iJ0;
       } else {
-        der[mu] = (sB + 2.0 * yv[mu] * sC) * iJ0;
+        double sBn = 0.0, sCn = 0.0;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          sBn += pn[r] * Bv[r];
+          sCn += pn[r] * Cv[r];
+        }
+        const double wN = (sBn + 2.0 * yv[mu] * sCn) * iJ0;
+        der[mu] = cls == 2 ? wN : Mg * wN + (1.0 - Mg) * (dq * iJ0);
       }
     }
   }

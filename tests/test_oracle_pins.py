@@ -173,6 +173,31 @@ def test_smooth_class_is_the_linear_scheme():
     np.testing.assert_allclose(vals[0:4], lin, rtol=1e-14)
 
 
+def test_smooth_class_bottom_slope_is_the_quartics_derivative():
+    """R12: b_x of the special source term is the derivative of b's
+    reconstruction.  In the smooth class that reconstruction is the 5-cell
+    quartic at every point, so for a quartic bottom on a non-uniform stencil
+    b_x at the 4 Gauss-Lobatto points is the bottom's exact slope (the
+    weighted stencil slopes sum_r d_r p_r' would miss it by O(Delta^2)); h, hu
+    and b stay the linear scheme's values."""
+    rng = np.random.default_rng(12)
+    w = rng.uniform(0.8, 1.25, 5) * 0.1
+    e = _edges(w)
+    qb = np.array([0.3, 0.8, -2.0, 5.0, -7.0])  # b(x) quartic
+    bav = np.array([_poly_avg(qb, e[k], e[k + 1]) for k in range(5)])
+    h = np.full(5, 2.0) - bav  # eta = 2: flat surface, smooth class
+    vals, cls, _, _ = O.reconstruct(w, h, np.zeros(5), bav, dx=w.max())
+    assert cls == 0
+    xs = e[2] + w[2] * np.array([0.0, 0.5 - math.sqrt(5) / 10, 0.5 + math.sqrt(5) / 10, 1.0])
+    slope = np.polynomial.polynomial.polyval(xs, np.polynomial.polynomial.polyder(qb))
+    np.testing.assert_allclose(vals[12:16], slope, rtol=0, atol=1e-11 * np.abs(slope).max())
+    d, c, cd, _ = O.geometry(w)
+    weighted = sum(d[:, r] * (cd[r] @ bav[2 - r:5 - r]) for r in range(3))
+    assert np.abs(weighted - slope).max() > 1e-6 * np.abs(slope).max()
+    lin = sum(d[:, r] * (c[r] @ bav[2 - r:5 - r]) for r in range(3))
+    np.testing.assert_allclose(vals[8:12], lin, rtol=1e-13)
+
+
 # data with a kink inside the big stencil: gamma(eps -> 0) > 1
 _KINK = dict(w=[1.0, 1.1, 0.9, 1.05, 0.95], dx=1.1,
              h5=np.array([1.0, 1.05, 1.2, 1.9, 2.0]),

@@ -136,12 +136,13 @@ __device__ __forceinline__ void stage_update(const K2& k, int64_t c, double dx0,
   double J[S + 1];
   jrec<S>(dx0, dwx, dy0, dwy, dt, J);
   Jn = J[S];
+  const double iJS = frcp(J[S]);
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const double R = k.Rc[v * k.N + c] + alpha * k.Rd[v * k.N + c];
     const double Q = CA(S - 1) * (J[0] * k.qa[v * k.N + c]) +
                      CB(S - 1) * (J[S - 1] * qprev[v * k.N + c] + dt * R);
-    q[v] = Q / J[S];
+    q[v] = Q * iJS;
   }
 }
 
@@ -217,13 +218,13 @@ __device__ __forceinline__ int sweep(const Geo& G, double eps, const double* e5,
   if (EXT) stencil_bc(G, x5, Bx, Cx);
   const double tau = fabs(beta[0] - beta[2]);
   const double betaA = (beta[0] + beta[1] + beta[2]) * (1.0 / 3.0);
-  const double gam = tau / (betaA + eps);
+  const double gam = tau * frcp(betaA + eps);
   const int cls = (gam <= 0.5) ? 0 : ((gam >= 1.0) ? 2 : 1);
   double K[3] = {1.0, 1.0, 1.0};
   if (cls != 0) {
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
-      const double z = tau / (beta[r] + eps);
+      const double z = tau * frcp(beta[r] + eps);
       K[r] = 1.0 + z * z;
     }
   }
@@ -260,7 +261,7 @@ __device__ __forceinline__ int sweep(const Geo& G, double eps, const double* e5,
       for (int r = 0; r < 3; ++r) ph[r] = G.d[mu][r];
     } else {
       const double a0 = G.d[mu][0] * K[0], a1 = G.d[mu][1] * K[1], a2 = G.d[mu][2] * K[2];
-      const double ia = 1.0 / (a0 + a1 + a2);
+      const double ia = frcp(a0 + a1 + a2);
       ph[0] = a0 * ia;
       ph[1] = a1 * ia;
       ph[2] = a2 * ia;
@@ -310,8 +311,8 @@ __device__ __forceinline__ void lf_point(double g, double dry, double w, double 
   if (!(ah > dry)) { am = 0.0; an = 0.0; }
   if (!(ch > dry)) { cm = 0.0; cn = 0.0; }
   double ua = 0.0, va = 0.0, uc = 0.0, vc = 0.0;
-  if (ah > dry) { const double r = 1.0 / ah; ua = am * r; va = an * r; }
-  if (ch > dry) { const double r = 1.0 / ch; uc = cm * r; vc = cn * r; }
+  if (ah > dry) { const double r = frcp(ah); ua = am * r; va = an * r; }
+  if (ch > dry) { const double r = frcp(ch); uc = cm * r; vc = cn * r; }
   const double ea = ah + ab, ec = ch + cb;
   double Ha[3], Hc[3];
   if (DIR == 0) {
@@ -371,11 +372,11 @@ __device__ __forceinline__ int quad_max(int v) {
 __device__ __forceinline__ double limiter_phi(double hbar, double q0, double q1, double mn) {
   if (!(hbar > 0.0)) return 0.0;
   const double s1 = GLW[0];
-  const double delta = (hbar - s1 * q0 - s1 * q1) / (1.0 - 2.0 * s1);
+  const double delta = (hbar - s1 * q0 - s1 * q1) * (1.0 / (1.0 - 2.0 * s1));
   mn = fmin(mn, delta);
   const double epsj = fmin(1e-11, hbar);
   if (!(mn < epsj)) return 1.0;
-  return fmin(1.0, (hbar - epsj) / (hbar - mn));
+  return fmin(1.0, (hbar - epsj) * frcp(hbar - mn));
 }
 // A trace moved towards the cell means by Phi; b follows eta (Remark 4.1).
 __device__ __forceinline__ void limit_trace(double Phi, double hbar, double mbar, double nbar,

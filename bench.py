@@ -278,6 +278,58 @@ def cpu_baseline(bt, ninst_sample, steps):
                        f"{steps} CFL steps each, one instance per thread; {wall:.1f} s wall")
 
 
+def class_flips_leg(dev, bt, ninst_sample, steps):
+    """Class flips between the GPU and the oracle on the first ninst_sample
+    instances of the batch over `steps` steps: both record the class of every
+    cell at every stage (the GPU as per-cell counts and a sequence signature,
+    sig <- sig * CLS_SIG_MUL + class + 1 per stage, the oracle as the full
+    record, reduced here the same way); a cell whose signatures differ has
+    flipped at least once."""
+    import torch
+    import oracle as O
+    from paper_2208_06588_amd import alew
+    off = bt["cell_off"][:ninst_sample + 1]
+    S = int(off[-1])
+    P = O.params(bc=O.BC_TRANSMISSIVE, mesh=O.MESH_SINE, mesh_A=0.05, mesh_k=1.0,
+                 mesh_omega=np.pi, cfl=0.6, weno_eps=1e-9)
+    mul = np.uint64(alew.CLS_SIG_MUL)
+
+    def one(i):
+        a, e = int(off[i]), int(off[i + 1])
+        r = O.run(P, bt["h"][a:e], bt["hu"][a:e], bt["b"][a:e], bt["x"][a + i:e + i + 1],
+                  bt["xi"][a + i:e + i + 1], max_steps=steps, record_cls=True)
+        cl = r["cls"][:r["stats"].steps]
+        counts = np.stack([(cl == c).sum(axis=(0, 1)) for c in range(3)]).astype(np.int64)
+        sig = np.zeros(e - a, dtype=np.uint64)
+        with np.errstate(over="ignore"):
+            for k in range(cl.shape[0]):
+                for st in range(3):
+                    sig = sig * mul + (cl[k, st].astype(np.uint64) + np.uint64(1))
+        return counts, sig
+
+    with cf.ThreadPoolExecutor(max_workers=16) as ex:
+        ref = list(ex.map(one, range(ninst_sample)))
+    rc = np.concatenate([c for c, _ in ref], axis=1)
+    rs = np.concatenate([g for _, g in ref])
+    T = {k: torch.tensor(np.asarray(bt[k][:S + (ninst_sample if k in ("x", "xi") else 0)]),
+                         dtype=torch.float64, device=dev) for k in ("h", "hu", "b", "x", "xi")}
+    cnt = torch.zeros(3 * S, dtype=torch.int32, device=dev)
+    sig = torch.zeros(S, dtype=torch.int64, device=dev)
+    ctx = alew.Context(S, ninst_sample)
+    p = alew.params(bc="transmissive", mesh="sine", mesh_A=0.05, mesh_k=1.0, mesh_omega=np.pi,
+                    cfl=0.6, weno_eps=1e-9)
+    ctx.run(p, list(off), T["h"], T["hu"], T["b"], T["x"], T["xi"], max_steps=[steps] * ninst_sample,
+            cls_count=cnt, cls_sig=sig)
+    torch.cuda.synchronize()
+    gc_ = cnt.cpu().numpy().astype(np.int64).reshape(3, S)
+    gs = sig.cpu().numpy().view(np.uint64)
+    cells = int((gs != rs).sum())
+    return dict(instances=ninst_sample, cells=S, steps=steps, cell_stages=3 * S * steps,
+                flipped_cells=cells,
+                flipped_cell_stages_at_least=int(np.abs(gc_ - rc).sum()) // 2,
+                class_counts=[int(v) for v in rc.sum(axis=1)])
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -810,6 +862,10 @@ def main():
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = guarded("cpu baseline", lambda: cpu_baseline(
             bt, min(args.cpu_inst, ninst), args.cpu_steps))
+        log("class flips against the oracle ...")
+        out["class_flips"] = guarded("class flips", lambda: class_flips_leg(
+            dev, bt, min(32, ninst), args.cpu_steps))
+        log(f"class flips: {out['class_flips']}")
         if args.oracle_suite:
             log("oracle on the other configurations ...")
             out["cpu_baseline"]["other_configs"] = guarded("oracle, other configurations",

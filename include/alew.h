@@ -65,11 +65,19 @@ enum { ALEW_BC_PERIODIC = 0, ALEW_BC_TRANSMISSIVE = 1, ALEW_BC_REFLECTIVE = 2 };
 /* Mesh motion.  GIVEN: node speeds w supplied by the caller (alew_step only).
  * SINE: S(xi) = sin(2 pi mesh_k xi).  PAPER: S(xi) = (xi - xi_N)(xi - xi_0) /
  * (3 (xi_N - xi_0)^2), eq. (5.1) with mesh_A = 1, mesh_omega = 2 pi / t_end.
- * For SINE and PAPER the node speed of a step is the chord of eq. (2.1),
+ * ALIGNED: S(xi) = (xi - xi_N)(xi - xi_0)(xi - p1)(xi - p2) / (3 (xi_N - xi_0)^4)
+ * with p1 = bottom_p[1], p2 = bottom_p[2] (the STEP bottom's jump points),
+ * eq. (5.14) of Example 5.5: a node placed on a jump point stays on it, so the
+ * projection of eq. (3.16) never averages across the jump (the cell count of
+ * the example's domain [0, 1500] must be a multiple of 8 for 562.5 and 937.5
+ * to be nodes).
+ * For SINE, PAPER and ALIGNED the node speed of a step is the chord of eq. (2.1),
  * (X(xi, t+dt) - X(xi, t)) / dt.  FLUID: node speeds follow the fluid (average
  * of the two adjacent cell velocities, two passes of [1/4,1/2,1/4] smoothing,
  * fixed end nodes unless periodic). */
-enum { ALEW_MESH_GIVEN = 0, ALEW_MESH_SINE = 1, ALEW_MESH_PAPER = 2, ALEW_MESH_FLUID = 3 };
+enum {
+  ALEW_MESH_GIVEN = 0, ALEW_MESH_SINE = 1, ALEW_MESH_PAPER = 2, ALEW_MESH_FLUID = 3, ALEW_MESH_ALIGNED = 4
+};
 
 /* flags */
 enum {
@@ -99,7 +107,7 @@ enum {
                                 h traces (and the b traces through Remark 4.1) only;
                                 by default the hu traces are scaled by the same Phi
                                 about the cell mean of hu                             */
-  ALEW_F_W_TANGENT = 32,     /* SINE / PAPER meshes: the node speed of a step is the
+  ALEW_F_W_TANGENT = 32,     /* prescribed meshes: the node speed of a step is the
                                 map's time derivative at the start of the step,
                                 A S(xi) omega cos(omega t_n), instead of the chord of
                                 eq. (2.1) (nodes then leave the map by O(dt^2) a step) */
@@ -217,7 +225,7 @@ alew_status alew_get_launch(const alew_ctx* ctx, alew_launch* launch);
 
 /* One time step of one instance (eq. (3.14)-(3.15)).
  * h, hu, b [ncell] and x [ncell+1] are updated in place.  xi [ncell+1] is
- * required for SINE/PAPER meshes; w [ncell+1] is required for GIVEN (node
+ * required for SINE/PAPER/ALIGNED meshes; w [ncell+1] is required for GIVEN (node
  * speeds over the step; w[ncell] must equal w[0] when periodic).
  * dt > 0 fixes the step; dt <= 0 selects the CFL rule
  *   dt = cfl * min_j Delta_j / (max_j(|u_j| + sqrt(g h_j)) + max_i |W_i|),
@@ -261,7 +269,7 @@ alew_status alew_step_noalloc(const alew_params* p, int64_t ncell, double* h, do
  * class sequence: at every stage, in time order,
  *     cls_sig[g] = cls_sig[g] * 1099511628211 + class + 1   (mod 2^64),
  * class 0 smooth, 1 transition, 2 non-smooth.
- * stats (host, optional) [ninst].  mesh must be SINE, PAPER or FLUID. */
+ * stats (host, optional) [ninst].  mesh must be SINE, PAPER, ALIGNED or FLUID. */
 alew_status alew_run(alew_ctx* ctx, const alew_params* p, int64_t ninst, const int64_t* cell_off,
                      double* h, double* hu, double* b, double* x, const double* xi,
                      const double* t0, const double* t_end, const int64_t* max_steps,

@@ -24,7 +24,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _LIB_OVERRIDE = os.environ.get("ALEW_ORACLE_LIB")
 
 BC_PERIODIC, BC_TRANSMISSIVE, BC_REFLECTIVE = 0, 1, 2
-MESH_GIVEN, MESH_SINE, MESH_PAPER, MESH_FLUID = 0, 1, 2, 3
+MESH_GIVEN, MESH_SINE, MESH_PAPER, MESH_FLUID, MESH_ALIGNED = 0, 1, 2, 3, 4
 ST_OK, ST_ARG, ST_MESH, ST_NEGDEPTH, ST_NONFINITE, ST_NEGWEIGHT = 0, 1, 2, 3, 4, 8
 FLAG_BETA_LOCAL, FLAG_BETA_FROM_H, FLAG_HYDROSTATIC = 1, 2, 4
 FLAG_ALPHA_CELLAVG, FLAG_NO_HU_LIMIT, FLAG_W_TANGENT, FLAG_NONWB = 8, 16, 32, 64

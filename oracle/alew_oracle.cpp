@@ -136,6 +136,13 @@
  *      below), the smooth class keeps the linear weights (a linear
  *      combination needs no positivity), and the run goes on.  The 2D sweeps
  *      always split.
+ *  R30 MESH_ALIGNED: the quartic map of eq. (5.14) (Example 5.5), the map of
+ *      eq. (5.1) times (xi - p1)(xi - p2) / (xmax - xmin)^2 with p1, p2 the
+ *      step bottom's jump points bottom_p[1], bottom_p[2]: a node placed on a
+ *      jump point stays there, so the projection of eq. (3.16) never averages
+ *      across a jump.  With the example's 100 uniform cells on [0, 1500] the
+ *      jump points 562.5 = 3L/8 and 937.5 = 5L/8 lie inside cells; a cell
+ *      count that is a multiple of 8 puts them on nodes.
  */
 #include <cmath>
 #include <cstdint>
@@ -198,7 +205,7 @@ using std::fabs;
 /* Parameters, statistics                                                    */
 /* ------------------------------------------------------------------------ */
 enum { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1, BC_REFLECTIVE = 2 };
-enum { MESH_GIVEN = 0, MESH_SINE = 1, MESH_PAPER = 2, MESH_FLUID = 3 };
+enum { MESH_GIVEN = 0, MESH_SINE = 1, MESH_PAPER = 2, MESH_FLUID = 3, MESH_ALIGNED = 4 };
 enum { ST_OK = 0, ST_ARG = 1, ST_MESH = 2, ST_NEGDEPTH = 3, ST_NONFINITE = 4, ST_NEGWEIGHT = 8 };
 
 enum {
@@ -945,9 +952,19 @@ static void residual(const Params& P, int n, const T* eta, const T* m, const T* 
 /* ------------------------------------------------------------------------ */
 static double mesh_shape(const Params& P, double xi, double xmin, double xmax) {
   if (P.mesh == MESH_SINE) return std::sin(2.0 * M_PI * P.mesh_k * xi);
-  /* eq. (5.1): (xi - xmax)(xi - xmin) / (3 (xmax - xmin)^2) */
   double L = xmax - xmin;
+  /* eq. (5.14): the quartic that also vanishes at the two jump points of the
+   * step bottom (bottom_p[1], bottom_p[2]), so that nodes placed there stay
+   * there: (xi - xmax)(xi - xmin)(xi - p1)(xi - p2) / (3 (xmax - xmin)^4) */
+  if (P.mesh == MESH_ALIGNED)
+    return (xi - xmax) * (xi - xmin) * (xi - P.bottom_p[1]) * (xi - P.bottom_p[2]) /
+           (3.0 * L * L * L * L);
+  /* eq. (5.1): (xi - xmax)(xi - xmin) / (3 (xmax - xmin)^2) */
   return (xi - xmax) * (xi - xmin) / (3.0 * L * L);
+}
+
+static bool prescribed_mesh(const Params& P) {
+  return P.mesh == MESH_SINE || P.mesh == MESH_PAPER || P.mesh == MESH_ALIGNED;
 }
 
 /* Node speeds for the step [t, t+dt]. */
@@ -956,7 +973,7 @@ static void mesh_velocity(const Params& P, int n, const T* eta, const T* m, cons
                           const double* xi, const double* w_given, double t, double dt, double* w) {
   if (P.mesh == MESH_GIVEN) {
     for (int i = 0; i <= n; ++i) w[i] = w_given[i];
-  } else if (P.mesh == MESH_SINE || P.mesh == MESH_PAPER) {
+  } else if (prescribed_mesh(P)) {
     /* Chord of X(xi,t) = xi + A S(xi) sin(omega t) over the step (eq. (2.1)):
      * (sin(om(t+dt)) - sin(om t))/dt = 2 cos(om(t+dt/2)) sin(om dt/2)/dt. */
     double om = P.mesh_omega;
@@ -1004,7 +1021,7 @@ static double mesh_speed_bound(const Params& P, int n, const T* eta, const T* m,
   double W = 0.0;
   if (P.mesh == MESH_GIVEN) {
     for (int i = 0; i <= n; ++i) W = std::max(W, std::fabs(w_given[i]));
-  } else if (P.mesh == MESH_SINE || P.mesh == MESH_PAPER) {
+  } else if (prescribed_mesh(P)) {
     double Smax = 0.0;
     for (int i = 0; i <= n; ++i) Smax = std::max(Smax, std::fabs(mesh_shape(P, xi[i], xi[0], xi[n])));
     W = std::fabs(P.mesh_A * P.mesh_omega * std::cos(P.mesh_omega * t)) * Smax;
@@ -1729,6 +1746,7 @@ int orc_run(const Params* P, int64_t n_, double* h, double* hu, double* b, doubl
             const double* dts, double* t_out, uint8_t* cls, Stats* S) {
   const int n = (int)n_;
   if (n < 5 || !P || !h || !hu || !b || !x) return ST_ARG;
+  if (P->mesh < MESH_GIVEN || P->mesh > MESH_ALIGNED) return ST_ARG;
   if (P->mesh != MESH_GIVEN && !xi) return ST_ARG;
   if (P->mesh == MESH_GIVEN && !w_given) return ST_ARG;
   stats_init(S);

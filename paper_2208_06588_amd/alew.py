@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libalew.so")
 (OK, E_ARG, E_MESH, E_NEGDEPTH, E_NONFINITE, E_HIP, E_NOMEM, E_UNSUPPORTED, E_NEGWEIGHT,
  E_CAPACITY) = range(10)
 BC = {"periodic": 0, "transmissive": 1, "reflective": 2}
-MESH = {"given": 0, "sine": 1, "paper": 2, "fluid": 3}
+MESH = {"given": 0, "sine": 1, "paper": 2, "fluid": 3, "aligned": 4}
 F_BETA_LOCAL, F_BETA_FROM_H, F_HYDROSTATIC = 1, 2, 4
 F_ALPHA_CELLAVG, F_NO_HU_LIMIT, F_W_TANGENT, F_NONWB = 8, 16, 32, 64
 F_SPLIT = 128  # split negative linear weights instead of reporting them

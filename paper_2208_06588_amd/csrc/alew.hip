@@ -80,7 +80,7 @@ __global__ __launch_bounds__(B) void k_prep(Bufs bf, Consts cs, const Tile* __re
     if (!isfinite(h) || !isfinite(m) || !isfinite(b)) atomicOr(&I.status, (int)SB_NONFINITE);
   }
   if (j <= v.n) {
-    if (cs.mesh == MESH_SINE || cs.mesh == MESH_PAPER) {
+    if (prescribed(cs.mesh)) {
       // the map's node amplitudes A S(xi); periodic meshes repeat node 0 at node n
       const double* xi = bf.xi + v.no;
       const int64_t jj = (cs.bc == BC_PERIODIC && j == v.n) ? 0 : j;
@@ -270,7 +270,7 @@ __device__ void boundary_update(Inst& I, const Consts& cs, const Bufs& bf, int i
     return;
   }
   I.dt = dt;
-  if (cs.mesh == MESH_SINE || cs.mesh == MESH_PAPER)
+  if (prescribed(cs.mesh))
     I.wscale = (cs.flags & F_W_TANGENT) ? cs.mesh_omega * cos(cs.mesh_omega * I.t)
                                         : chord_factor(cs, I.t, dt);
   else
@@ -326,7 +326,7 @@ __device__ __forceinline__ void apply_boundary(const Bufs& bf, const Consts& cs,
   if (first) {
     I.mass_eta0 = r.me;
     I.mass_b0 = r.mb;
-    if (cs.mesh == MESH_SINE || cs.mesh == MESH_PAPER) I.smax = r.w4;
+    if (prescribed(cs.mesh)) I.smax = r.w4;
   }
   if (cs.mesh == MESH_GIVEN || cs.mesh == MESH_FLUID) I.r_W = dbits(r.w4);
   boundary_update(I, cs, bf, i, first);
@@ -778,9 +778,11 @@ alew_status check_params(const alew_params* p) {
   if (!(p->g > 0) || !(p->cfl > 0) || !(p->weno_eps > 0) || !(p->pp_eps >= 0) || !(p->dry_eps >= 0))
     return fail(ALEW_E_ARG, "g, cfl, weno_eps must be > 0 and pp_eps, dry_eps >= 0");
   if (p->bc < 0 || p->bc > 2) return fail(ALEW_E_ARG, "unknown boundary type");
-  if (p->mesh < 0 || p->mesh > 3) return fail(ALEW_E_ARG, "unknown mesh mode");
-  if ((p->mesh == ALEW_MESH_SINE || p->mesh == ALEW_MESH_PAPER) && !(p->mesh_omega == p->mesh_omega))
+  if (p->mesh < 0 || p->mesh > ALEW_MESH_ALIGNED) return fail(ALEW_E_ARG, "unknown mesh mode");
+  if (prescribed(p->mesh) && !(p->mesh_omega == p->mesh_omega))
     return fail(ALEW_E_ARG, "mesh_omega is NaN");
+  if (p->mesh == ALEW_MESH_ALIGNED && !(std::isfinite(p->bottom_p[1]) && std::isfinite(p->bottom_p[2])))
+    return fail(ALEW_E_ARG, "the ALIGNED mesh needs finite roots bottom_p[1], bottom_p[2]");
   if ((p->flags & ALEW_F_HYDROSTATIC) && (p->flags & ALEW_F_NONWB))
     return fail(ALEW_E_ARG, "HYDROSTATIC and NONWB select different schemes");
   if (p->bottom < 0 || p->bottom > ALEW_BOTTOM_PARABOLA) return fail(ALEW_E_ARG, "unknown bottom");
@@ -1204,7 +1206,7 @@ alew_status drive(alew_ctx* c, const alew_params* p, int64_t ninst, const int64_
   if (ninst <= 0 || !cell_off) return fail(ALEW_E_ARG, "ninst <= 0 or cell_off is NULL");
   if (ninst > c->max_inst) return fail(ALEW_E_ARG, "ninst exceeds the context capacity");
   if (!h || !hu || !b || !x) return fail(ALEW_E_ARG, "state or node array is NULL");
-  if ((p->mesh == ALEW_MESH_SINE || p->mesh == ALEW_MESH_PAPER) && !xi)
+  if (prescribed(p->mesh) && !xi)
     return fail(ALEW_E_ARG, "xi is required for the prescribed mesh");
   if (p->mesh == ALEW_MESH_GIVEN && !wgiven) return fail(ALEW_E_ARG, "w is required for MESH_GIVEN");
   if (cell_off[0] != 0) return fail(ALEW_E_ARG, "cell_off[0] must be 0");
@@ -1628,7 +1630,7 @@ alew_status alew_run(alew_ctx* c, const alew_params* p, int64_t ninst, const int
                      const double* t0, const double* t_end, const int64_t* max_steps,
                      const double* dts, double* dt_log, int64_t dts_stride, uint32_t* cls_count,
                      uint64_t* cls_sig, alew_stats* stats) {
-  if (p && p->mesh == ALEW_MESH_GIVEN) return fail(ALEW_E_UNSUPPORTED, "alew_run needs a SINE, PAPER or FLUID mesh");
+  if (p && p->mesh == ALEW_MESH_GIVEN) return fail(ALEW_E_UNSUPPORTED, "alew_run needs a SINE, PAPER, ALIGNED or FLUID mesh");
   if (!c) return fail(ALEW_E_ARG, "ctx is NULL");
   int engine = c->launch.engine;
   if (engine == 0) engine = 2;
@@ -1657,8 +1659,8 @@ alew_status alew_adjoint(alew_ctx* c, const alew_params* p, int64_t ninst,
   alew_status ps = check_params(p);
   if (ps != ALEW_OK) return ps;
   if (!c) return fail(ALEW_E_ARG, "ctx is NULL");
-  if (p->mesh != ALEW_MESH_SINE && p->mesh != ALEW_MESH_PAPER)
-    return fail(ALEW_E_UNSUPPORTED, "the adjoint needs a prescribed (SINE or PAPER) mesh");
+  if (!prescribed(p->mesh))
+    return fail(ALEW_E_UNSUPPORTED, "the adjoint needs a prescribed (SINE, PAPER or ALIGNED) mesh");
   if (p->flags & ALEW_F_ALPHA_CELLAVG)
     return fail(ALEW_E_UNSUPPORTED, "the adjoint takes the LF speed over the face traces");
   if (p->flags & ALEW_F_NONWB)

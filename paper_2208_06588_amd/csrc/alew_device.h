@@ -19,7 +19,11 @@
 namespace alew_dev {
 
 enum { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1, BC_REFLECTIVE = 2 };
-enum { MESH_GIVEN = 0, MESH_SINE = 1, MESH_PAPER = 2, MESH_FLUID = 3 };
+enum { MESH_GIVEN = 0, MESH_SINE = 1, MESH_PAPER = 2, MESH_FLUID = 3, MESH_ALIGNED = 4 };
+// Meshes moved by a prescribed map X(xi, t) = xi + A S(xi) sin(omega t).
+__host__ __device__ __forceinline__ bool prescribed(int mesh) {
+  return mesh == MESH_SINE || mesh == MESH_PAPER || mesh == MESH_ALIGNED;
+}
 enum {
   F_BETA_LOCAL = 1, F_BETA_FROM_H = 2, F_HYDROSTATIC = 4, F_ALPHA_CELLAVG = 8, F_NO_HU_LIMIT = 16,
   F_W_TANGENT = 32, F_NONWB = 64, F_SPLIT = 128

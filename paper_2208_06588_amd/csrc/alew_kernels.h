@@ -736,10 +736,14 @@ __device__ __forceinline__ FinalRes final_tile(const Bufs& bf, const Consts& cs,
 }
 
 // Shape function of the prescribed mesh map.
+// PAPER: eq. (5.1).  ALIGNED: eq. (5.14), which also vanishes at the step
+// bottom's jump points bp[1], bp[2] (nodes placed there never move).
 __device__ __forceinline__ double mesh_shape(const Consts& cs, double xi, double x0, double x1) {
   if (cs.mesh == MESH_SINE) return sin(2.0 * M_PI * cs.mesh_k * xi);
   const double L = x1 - x0;
-  return (xi - x1) * (xi - x0) / (3.0 * L * L);
+  const double q = (xi - x1) * (xi - x0);
+  if (cs.mesh == MESH_ALIGNED) return q * (xi - cs.bp[1]) * (xi - cs.bp[2]) / (3.0 * L * L * L * L);
+  return q / (3.0 * L * L);
 }
 
 // Chord factor of the prescribed map over the step [t, t+dt] (eq. (2.1)):
@@ -814,7 +818,7 @@ __device__ __forceinline__ double next_dt(const Inst& I, const Consts& cs, const
     dt = dts[(int64_t)i * dts_stride + I.steps];
   } else {
     double W;
-    if (cs.mesh == MESH_SINE || cs.mesh == MESH_PAPER)
+    if (prescribed(cs.mesh))
       W = fabs(cs.mesh_A * cs.mesh_omega * cos(cs.mesh_omega * I.t)) * I.smax;
     else
       W = bitsd(I.r_W);

@@ -103,6 +103,30 @@ def moses2_1d(n: int = 200, t_end: float = 1.0):
 
 
 # --------------------------------------------------------------------------
+# Example 5.5, dam break over a rectangular bump (projected bottom)
+# --------------------------------------------------------------------------
+def dam_break_bump_1d(n: int = 104, t_end: float = 15.0):
+    """[0, 1500]; b = 8 on [562.5, 937.5], 0 elsewhere (eq. (5.12)); hu = 0,
+    h + b = 20 for x <= 750 and 15 beyond (eq. (5.13)); transmissive.  The
+    bottom is the projection of eq. (3.16) of that step onto the moving cells
+    (bottom 'step', parameters (8, 562.5, 937.5)), and the nodes follow the
+    quartic map of eq. (5.14) ('aligned': its roots include the two jump points).
+    n must be a multiple of 8: then 562.5 = 3L/8, 750 and 937.5 = 5L/8 are nodes
+    (the example's 100 cells would put the jump points inside cells)."""
+    if n % 8:
+        raise ValueError("n must be a multiple of 8 for the jump points to be nodes")
+    xi = uniform_nodes(n, 0.0, 1500.0)
+    bf = lambda x: np.where((x >= 562.5) & (x <= 937.5), 8.0, 0.0)
+    ef = lambda x: np.where(x <= 750.0, 20.0, 15.0)
+    br = (562.5, 750.0, 937.5)
+    b = cell_averages(bf, xi, br)
+    h = cell_averages(lambda x: ef(x) - bf(x), xi, br)
+    return dict(xi=xi, x=xi.copy(), h=h, hu=np.zeros(n), b=b, bc="transmissive", t_end=t_end,
+                cfl=0.6, weno_eps=1e-6, mesh="aligned", mesh_A=1.0, mesh_k=0.0,
+                mesh_omega=2 * math.pi / t_end, bottom_p=(8.0, 562.5, 937.5, 0.0))
+
+
+# --------------------------------------------------------------------------
 # Example 5.4 (LeVeque perturbation), ragged batch
 # --------------------------------------------------------------------------
 def _lev_bottom(x):

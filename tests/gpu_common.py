@@ -24,7 +24,8 @@ def gparams(wl, **kw):
 
 def oparams(wl, **kw):
     bc = dict(periodic=O.BC_PERIODIC, transmissive=O.BC_TRANSMISSIVE, reflective=O.BC_REFLECTIVE)
-    mesh = dict(given=O.MESH_GIVEN, sine=O.MESH_SINE, paper=O.MESH_PAPER, fluid=O.MESH_FLUID)
+    mesh = dict(given=O.MESH_GIVEN, sine=O.MESH_SINE, paper=O.MESH_PAPER, fluid=O.MESH_FLUID,
+                aligned=O.MESH_ALIGNED)
     d = dict(bc=bc[wl["bc"]], mesh=mesh[wl["mesh"]], mesh_A=wl["mesh_A"], mesh_k=wl["mesh_k"],
              mesh_omega=wl["mesh_omega"], cfl=wl["cfl"], weno_eps=wl["weno_eps"])
     d.update(kw)

@@ -111,6 +111,38 @@ def test_adjoint_matches_oracle(dev, kind, ckpt, tol, n, nsteps, ng, cfl, hydro)
         assert cell.max() <= tol, cell.max()
 
 
+def test_adjoint_on_the_jump_aligned_mesh(dev):
+    """The quartic map of eq. (5.14) with its interior roots at 0.375 and 0.625
+    on [0, 1] (nodes 24 and 40 of 64; bottom_p[1], bottom_p[2]), the bottom
+    evolved by eq. (3.17): the GPU adjoint against the oracle's tape adjoint,
+    cell by cell at 1e-11."""
+    n, nsteps, ng = 64, 7, 6
+    xi, h, hu, b, bc = _case("step", n)
+    bp = (0.0, 0.375, 0.625, 0.0)
+    gp = alew.params(bc=bc, mesh="aligned", mesh_A=1.0, mesh_k=0.0, mesh_omega=math.pi,
+                     cfl=0.3, bottom_p=bp)
+    op = O.params(bc=O.BC_PERIODIC, mesh=O.MESH_ALIGNED, mesh_A=1.0, mesh_k=0.0,
+                  mesh_omega=math.pi, cfl=0.3, bottom_p=bp)
+    r = O.run(op, h, hu, b, xi, xi, max_steps=1)
+    dts = np.full(nsteps, r["stats"].dt_max)
+    rng = np.random.default_rng(12)
+    gx = np.sort(rng.uniform(0.03, 0.97, ng))
+    gbar = rng.normal(size=ng)
+    gh_o, dh_o, dhu_o, db_o, st = O.adjoint(op, h, hu, b, xi, xi, dts, gx, gbar)
+    assert st == 0
+    ctx = alew.Context(n, 1)
+    T = {k: _t(v, dev) for k, v in dict(h=h, hu=hu, b=b, x=xi, xi=xi, dts=dts, gx=gx, gb=gbar).items()}
+    gh = torch.zeros(ng, dtype=torch.float64, device=dev)
+    dh, dhu, db = (torch.zeros(n, dtype=torch.float64, device=dev) for _ in range(3))
+    ctx.adjoint(gp, [0, n], T["h"], T["hu"], T["b"], T["x"], T["xi"], nsteps, T["dts"], ng, T["gx"],
+                gh, T["gb"], dh, dhu, db, ckpt_every=3)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(gh.cpu().numpy(), gh_o, rtol=0, atol=1e-12)
+    for g, o in ((dh, dh_o), (dhu, dhu_o), (db, db_o)):
+        cell = np.abs(g.cpu().numpy() - o) / np.maximum(1.0, np.abs(o))
+        assert cell.max() <= 1e-11, cell.max()
+
+
 def _accuracy_case(n):
     # Example 5.1 data: strongly varying, so the hybrid weights stay in the
     # linear class and the map is smooth at the scale of the FD step (with

@@ -150,3 +150,26 @@ def test_projected_engines_agree_and_adjoint_refuses(dev):
                     torch.full((2,), 1e-4, dtype=torch.float64, device=dev), 1,
                     torch.tensor([0.5, 0.5], dtype=torch.float64, device=dev), g)
     assert ei.value.status == alew.E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("scheme,t_end", [(0, 15.0), (alew.F_HYDROSTATIC, 15.0),
+                                          (alew.F_NONWB, 15.0), (0, 60.0)])
+def test_example_5_5_jump_aligned_mesh(dev, scheme, t_end):
+    """Example 5.5 (dam break over the rectangular bump, bottom projected, nodes
+    moved by the quartic map of eq. (5.14)) on 104 cells against the oracle:
+    equal steps and class counts, the state at the parity tolerance; on the GPU
+    as well the nodes on the jump points never move and the projected bottom is
+    exactly 0 or 8.  t = 60: the waves have left through both ends."""
+    of = {0: 0, alew.F_HYDROSTATIC: O.FLAG_HYDROSTATIC, alew.F_NONWB: O.FLAG_NONWB}[scheme]
+    wl = W.dam_break_bump_1d(104, t_end)
+    bp = wl["bottom_p"]
+    ctx = alew.Context(104, 1)
+    g, st = run_one(ctx, gparams(wl, bottom="step", bottom_p=bp, flags=scheme), wl, dev,
+                    t_end=[t_end])
+    r = O.run(oparams(wl, bottom=O.BOTTOM_STEP, bottom_p=bp, flags=of), wl["h"], wl["hu"],
+              np.zeros(104), wl["x"], wl["xi"], t_end=t_end)
+    assert st.status == 0 and r["status"] == 0 and st.steps == r["stats"].steps
+    assert tuple(st.n_class) == tuple(r["stats"].n_class)
+    assert g["x"][39] == 562.5 and g["x"][65] == 937.5
+    assert set(np.unique(g["b"]).tolist()) == {0.0, 8.0}
+    assert_parity(g, r)

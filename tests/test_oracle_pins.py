@@ -347,7 +347,8 @@ def test_lake_at_rest_residual(bottom):
 def _params_for(wl, **kw):
     bc = dict(periodic=O.BC_PERIODIC, transmissive=O.BC_TRANSMISSIVE,
               reflective=O.BC_REFLECTIVE)[wl["bc"]]
-    mesh = dict(sine=O.MESH_SINE, paper=O.MESH_PAPER, fluid=O.MESH_FLUID)[wl["mesh"]]
+    mesh = dict(sine=O.MESH_SINE, paper=O.MESH_PAPER, fluid=O.MESH_FLUID,
+                aligned=O.MESH_ALIGNED)[wl["mesh"]]
     base = dict(bc=bc, mesh=mesh, mesh_A=wl["mesh_A"], mesh_k=wl["mesh_k"],
                 mesh_omega=wl["mesh_omega"], cfl=wl["cfl"], weno_eps=wl["weno_eps"])
     base.update(kw)
@@ -973,6 +974,63 @@ def test_projected_bottom_keeps_still_water(bottom, flags):
     S = r["stats"]
     assert S.mass_b0 == pytest.approx(integral, rel=1e-13)
     assert S.mass_b == pytest.approx(integral, rel=1e-13)
+
+
+def _dam_bump(flags, t):
+    """Example 5.5 on 104 cells (the jump points 562.5 = 3L/8 and 937.5 = 5L/8
+    are nodes), the quartic map of eq. (5.14) with t_end = 15, run to t."""
+    wl = W.dam_break_bump_1d(104, 15.0)
+    P = _params_for(wl, bottom=O.BOTTOM_STEP, bottom_p=wl["bottom_p"], flags=flags)
+    r = O.run(P, wl["h"], wl["hu"], np.zeros(104), wl["x"], wl["xi"], t_end=t)
+    xc = 0.5 * (wl["xi"][:-1] + wl["xi"][1:])
+    eta0 = np.where(xc <= 750.0, 20.0, 15.0)
+    return wl, r, xc, eta0
+
+
+@pytest.mark.parametrize("flags", [0, O.FLAG_HYDROSTATIC])
+def test_example_5_5_dam_break_over_the_bump(flags):
+    """Example 5.5: dam break at x = 750 over the rectangular bump of eq. (5.12),
+    bottom projected (eq. (3.16)), nodes moved by eq. (5.14).  The map vanishes
+    at the jump points, so the nodes there never move and every cell lies on or
+    off the bump: the projection gives exactly 0 or 8.  The well-balanced
+    schemes keep the water over both jumps at rest to round-off until the dam's
+    waves arrive (they start 187.5 away; at t = 1 they are still far); at
+    t = 15 the end cells are still at rest and the volume of water is
+    conserved (nothing has left the domain)."""
+    for t in (1.0, 15.0):
+        wl, r, xc, eta0 = _dam_bump(flags, t)
+        x, b, h, hu = r["x"], r["b"], r["h"], r["hu"]
+        assert r["status"] == 0
+        assert x[39] == 562.5 and x[65] == 937.5
+        assert set(np.unique(b).tolist()) == {0.0, 8.0}
+        assert np.array_equal(b == 8.0, (xc > 562.5) & (xc < 937.5))
+        # the map of eq. (5.14) at the dam site: 750 + S(750) sin(2 pi t / 15),
+        # S(750) = (-750)(750)(187.5)(-187.5) / (3 1500^4) = 1/768
+        assert abs(x[52] - (750.0 + math.sin(2 * math.pi * r["t"] / 15.0) / 768.0)) < 1e-12
+        eta = h + b
+        if t == 1.0:
+            edges = (np.abs(xc - 562.5) < 40.0) | (np.abs(xc - 937.5) < 40.0)
+            assert np.abs(hu[edges]).max() < 1e-12
+            assert np.abs(eta - eta0)[edges].max() < 1e-12
+        else:
+            ends = (xc < 100.0) | (xc > 1400.0)
+            assert np.abs(hu[ends]).max() < 1e-11
+            assert np.abs(eta - eta0)[ends].max() < 1e-12
+            vol0 = float((wl["h"] * np.diff(wl["x"])).sum())
+            assert abs(float((h * np.diff(x)).sum()) - vol0) < 1e-12 * vol0
+            # the dam's waves have reached the bump's edges
+            assert np.abs(hu[np.abs(xc - 562.5) < 40.0]).max() > 1.0
+
+
+def test_example_5_5_without_well_balancing_fails_at_the_jumps():
+    """Example 5.5 with the scheme of Sec. 3 without well-balancing: the pressure
+    jump at each edge of the bump is not balanced by the source, so the still
+    water there starts to flow at once (the paper reports a failed run); at
+    t = 1 the discharge over the jumps is of order ten."""
+    _, r, xc, _ = _dam_bump(O.FLAG_NONWB, 1.0)
+    assert r["status"] == 0
+    edges = (np.abs(xc - 562.5) < 40.0) | (np.abs(xc - 937.5) < 40.0)
+    assert np.abs(r["hu"][edges]).max() > 5.0
 
 
 # ----------------------------------------------------------------------------

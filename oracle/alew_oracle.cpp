@@ -134,8 +134,9 @@
  *      transition and non-smooth classes at such a point come from the
  *      splitting of Shi, Hu & Shu (2002) with theta = 3 (nonlinear_weights
  *      below), the smooth class keeps the linear weights (a linear
- *      combination needs no positivity), and the run goes on.  The 2D sweeps
- *      always split.
+ *      combination needs no positivity), and the run goes on.  In 2D a
+ *      negative weight on a stage mesh ends the run with ST_NEGWEIGHT after
+ *      the step that met it (that step's sweeps use the split weights).
  *  R30 MESH_ALIGNED: the quartic map of eq. (5.14) (Example 5.5), the map of
  *      eq. (5.1) times (xi - p1)(xi - p2) / (xmax - xmin)^2 with p1, p2 the
  *      step bottom's jump points bottom_p[1], bottom_p[2]: a node placed on a

@@ -141,14 +141,21 @@ def roofline(ctx, p, off, T, tnow, L, S, kern_ms, launches, steps, copy_bw=True)
         achieved = per_stage * scells / (sms / 1e3) / 1e9
         stage_launches = sn
         epi = dict(kernel="k_final<256>", launches=en, launch_ms=round(ems / max(1, en), 4))
-        log(f"kernel timing: {sn} stage launches, {ms_launch:.4f} ms each; "
-            f"{en} epilogues, {ems / max(1, en):.4f} ms each")
+        # RK stage 1 reads the step's state (88 B per cell moved); stages 2 and 3
+        # also the previous stage's partial updates (136 B per cell)
+        by_stage = []
+        for q in (2, 3, 4):
+            qms, qn, _ = ctx.kernel_timing(q)
+            by_stage.append(round(qms / max(1, qn), 4))
+        log(f"kernel timing: {sn} stage launches, {ms_launch:.4f} ms each (by RK stage "
+            f"{by_stage}); {en} epilogues, {ems / max(1, en):.4f} ms each")
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None, kernel=kernel,
                 launch_ms=round(ms_launch, 4), launches=stage_launches,
                 alg_bytes_per_cell_stage=round(per_stage, 3),
                 timing="HIP events on the library stream around each launch")
     if epi is not None:
+        roof["launch_ms_by_rk_stage"] = by_stage
         roof["step_epilogue"] = epi
     if copy_bw:  # (profiler runs calibrate their byte counters with a copy of their own)
         roof["copy_gbs"] = copy_bandwidth()

@@ -324,7 +324,9 @@ alew_status alew_last_timing(const alew_ctx* ctx, double* ms, int64_t* launches)
 alew_status alew_set_kernel_timing(alew_ctx* ctx, int on);
 
 /* Totals of the last call with kernel timing on.  which: 0 = stage launches,
- * 1 = step epilogues.  ms: summed device time; launches: number of launches;
+ * 1 = step epilogues, 2, 3, 4 = the stage launches of RK stage 1, 2, 3 (stage 1
+ * reads the step's state; stages 2 and 3 also the previous stage's partial
+ * updates).  ms: summed device time; launches: number of launches;
  * cells: summed batch cells over those launches (every launch covers the whole
  * batch; tiles of instances already finished return at once).  Host pointers. */
 alew_status alew_kernel_timing(const alew_ctx* ctx, int which, double* ms, int64_t* launches,

@@ -224,7 +224,8 @@ class Context:
 
     def kernel_timing(self, which=0):
         """(milliseconds, launches, cells) summed over the stage launches
-        (which=0) or step epilogues (which=1) of the last timed run."""
+        (which=0), the step epilogues (which=1) or the stage launches of RK
+        stage 1, 2, 3 (which=2, 3, 4) of the last timed run."""
         ms, n, cells = C.c_double(), C.c_int64(), C.c_double()
         _check(lib().alew_kernel_timing(self._h, which, C.byref(ms), C.byref(n), C.byref(cells)))
         return ms.value, n.value, cells.value

@@ -936,7 +936,8 @@ Bufs make_bufs(alew_ctx* c, int64_t S, int64_t ninst, double* hu, double* b, con
   return bf;
 }
 
-// Event pair around a launch for per-kernel timing (kind 0: stage, 1: epilogue).
+// Event pair around a launch for per-kernel timing (kind 1: epilogue; 2, 3, 4:
+// the stage launch of RK stage 1, 2, 3).
 int kt_begin(alew_ctx* c, hipStream_t st, int kind, double cells) {
   if (!c->ktime_rec) return -1;
   const size_t k = c->kt_used;
@@ -984,7 +985,7 @@ void launch_step_seq(alew_ctx* c, const Bufs& bf, const Consts& cs, hipStream_t 
   const dim3 gs((unsigned)c->n_tiles_stage), gp((unsigned)c->n_tiles_plain);
   const int sch = scheme_of(cs);
   for (int s = 1; s <= 3; ++s) {
-    const int kt = kt_begin(c, st, 0, (double)c->tables_cells);
+    const int kt = kt_begin(c, st, 1 + s, (double)c->tables_cells);
 #define ALEW_STAGE(NX, SC)                                                                      \
   hipLaunchKernelGGL((k_stage<B, CPT, NX, SC>), gs, dim3(B), 0, st, bf, cs, c->tiles_stage_d, s, par)
     if (cs.flags & F_SPLIT) {
@@ -1440,11 +1441,12 @@ alew_status alew_set_kernel_timing(alew_ctx* c, int on) {
 alew_status alew_kernel_timing(const alew_ctx* c, int which, double* ms, int64_t* launches,
                                double* cells) {
   if (!c || !ms || !launches || !cells) return fail(ALEW_E_ARG, "NULL argument");
-  if (which != 0 && which != 1) return fail(ALEW_E_ARG, "which must be 0 or 1");
+  if (which < 0 || which > 4) return fail(ALEW_E_ARG, "which must be 0 to 4");
   double tot = 0.0, cel = 0.0;
   int64_t n = 0;
   for (size_t k = 0; k < c->kt_used; ++k) {
-    if (c->kt_kind[k] != which) continue;
+    const int kd = c->kt_kind[k];
+    if (which == 0 ? kd < 2 : kd != which) continue;
     float e = 0.f;
     HIPCHK(hipEventElapsedTime(&e, c->kt_ev[2 * k], c->kt_ev[2 * k + 1]));
     tot += e;

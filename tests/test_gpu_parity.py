@@ -533,3 +533,23 @@ def test_split_negative_weights_equal_oracle(dev):
                 assert e <= 1e-11, (k, e)
         else:
             assert st.status == alew.E_NEGWEIGHT
+
+
+def test_kernel_timing_by_rk_stage(dev):
+    """Per-launch event timing (alew_set_kernel_timing): the launches of RK stages
+    1, 2 and 3 are one per step each and add up to the stage launches; one step
+    epilogue per step; every time positive."""
+    wl = W.accuracy_1d(200)
+    ctx = alew.Context(200, 1)
+    ctx.set_kernel_timing(True)
+    _run_gpu(ctx, _gp(wl), wl, dev, max_steps=[5])
+    ctx.set_kernel_timing(False)
+    ms, n, cells = ctx.kernel_timing(0)
+    parts = [ctx.kernel_timing(q) for q in (2, 3, 4)]
+    assert n == 15 and [p[1] for p in parts] == [5, 5, 5]
+    assert abs(sum(p[0] for p in parts) - ms) <= 1e-9 * max(1.0, ms) and ms > 0
+    assert all(p[0] > 0 for p in parts) and cells == pytest.approx(15 * 200)
+    ems, en, _ = ctx.kernel_timing(1)
+    assert en == 5 and ems > 0
+    with pytest.raises(Exception):
+        ctx.kernel_timing(5)

@@ -137,6 +137,20 @@
  *      combination needs no positivity), and the run goes on.  In 2D a
  *      negative weight on a stage mesh ends the run with ST_NEGWEIGHT after
  *      the step that met it (that step's sweeps use the split weights).
+ *  R31 2D FLAG_HYDROSTATIC: the scheme of eq. (4.4)-(4.6) on the
+ *      tensor-product mesh: at each of the 4 Gauss-Lobatto points of an edge
+ *      the flux of the starred states q* = (eta*, hu, hv) (h* = max(0, eta -
+ *      max(b-, b+)), velocities hu / h*, hv / h*), theta added to the eta
+ *      component, and the pressure correction g/2 (h^2 - h*^2) of each cell's
+ *      own trace on its normal momentum; the reconstruction, the bottom flux and
+ *      alpha are the special source-term scheme's.  The paper leaves the 2D
+ *      source to the 1D construction ("similar"): here the 1D source of R18
+ *      (the cubic interpolants of eta and b through the 4 point values, their
+ *      integral by 5-point Gauss-Legendre) on every x-line (points nu) and
+ *      y-line (points mu) of the cell, weighted by the other direction's
+ *      Gauss-Lobatto rule; the point values are the unlimited ones, as for
+ *      the special source (R28).  Still water is kept line by line: the edge
+ *      and cell rules share the points.
  *  R30 MESH_ALIGNED: the quartic map of eq. (5.14) (Example 5.5), the map of
  *      eq. (5.1) times (xi - p1)(xi - p2) / (xmax - xmin)^2 with p1, p2 the
  *      step bottom's jump points bottom_p[1], bottom_p[2]: a node placed on a
@@ -1450,15 +1464,46 @@ static double residual2(const Params2& P, int nx, int ny, const double* eta, con
         alpha = std::max(alpha, speed(trace_y(i, j - 1, mu, 3), 1, wy[j]));
         alpha = std::max(alpha, speed(trace_y(i, j, mu, 0), 1, wy[j]));
       }
-  /* edge integrals: flux (eta, hu, hv), bottom flux, B1, B2 */
-  struct EdgeI { double F[3], Gb, B1, B2; };
+  /* edge integrals: flux (eta, hu, hv), bottom flux, B1, B2; with the
+   * hydrostatic reconstruction (R31) also the pressure corrections of the
+   * cell on the left / below (PL) and on the right / above (PR) */
+  const bool hydro = (P.flags & FLAG_HYDROSTATIC) != 0;
+  struct EdgeI { double F[3], Gb, B1, B2, PL, PR; };
   auto edge = [&](const Tr& l, const Tr& r, int dir, double w, double len, const double* wts,
                   int npt, const Tr* L_, const Tr* R_) {
-    EdgeI e{{0, 0, 0}, 0, 0, 0};
+    EdgeI e{{0, 0, 0}, 0, 0, 0, 0, 0};
     (void)l; (void)r;
     for (int k = 0; k < npt; ++k) {
       const Tr& a = L_[k];
       const Tr& c = R_[k];
+      if (hydro) {
+        /* eq. (4.5)-(4.6): the flux of the starred states, theta on the eta
+         * component, each side's pressure correction g/2 (h^2 - h*^2) */
+        const double bm = std::max(a.b, c.b);
+        const double ea = a.h + a.b, ec = c.h + c.b;
+        const double hsa = std::max(0.0, ea - bm), hsc = std::max(0.0, ec - bm);
+        const double esa = hsa + a.b, esc = hsc + c.b;
+        double usa = 0.0, vsa = 0.0, usc = 0.0, vsc = 0.0;
+        if (hsa > P.dry_eps) { usa = a.m1 / hsa; vsa = a.m2 / hsa; }
+        if (hsc > P.dry_eps) { usc = c.m1 / hsc; vsc = c.m2 / hsc; }
+        double Ha[3], Hc[3];
+        if (dir == 0) {
+          Ha[0] = a.m1 - w * esa; Ha[1] = a.m1 * usa + 0.5 * P.g * hsa * hsa - w * a.m1; Ha[2] = a.m1 * vsa - w * a.m2;
+          Hc[0] = c.m1 - w * esc; Hc[1] = c.m1 * usc + 0.5 * P.g * hsc * hsc - w * c.m1; Hc[2] = c.m1 * vsc - w * c.m2;
+        } else {
+          Ha[0] = a.m2 - w * esa; Ha[1] = a.m2 * usa - w * a.m1; Ha[2] = a.m2 * vsa + 0.5 * P.g * hsa * hsa - w * a.m2;
+          Hc[0] = c.m2 - w * esc; Hc[1] = c.m2 * usc - w * c.m1; Hc[2] = c.m2 * vsc + 0.5 * P.g * hsc * hsc - w * c.m2;
+        }
+        const double jump[3] = {esc - esa, c.m1 - a.m1, c.m2 - a.m2};
+        const double theta = 0.5 * (w + alpha) * (esc - ec) + 0.5 * (w - alpha) * (esa - ea);
+        for (int q = 0; q < 3; ++q)
+          e.F[q] = e.F[q] + wts[k] * (0.5 * (Ha[q] + Hc[q]) - 0.5 * alpha * jump[q]);
+        e.F[0] = e.F[0] + wts[k] * theta;
+        e.Gb = e.Gb + wts[k] * (-0.5 * w * (a.b + c.b) - 0.5 * alpha * (c.b - a.b));
+        e.PL = e.PL + wts[k] * (0.5 * P.g * a.h * a.h - 0.5 * P.g * hsa * hsa);
+        e.PR = e.PR + wts[k] * (0.5 * P.g * c.h * c.h - 0.5 * P.g * hsc * hsc);
+        continue;
+      }
       double ua = a.h > P.dry_eps ? a.m1 / a.h : 0.0, va = a.h > P.dry_eps ? a.m2 / a.h : 0.0;
       double uc = c.h > P.dry_eps ? c.m1 / c.h : 0.0, vc = c.h > P.dry_eps ? c.m2 / c.h : 0.0;
       double ea = a.h + a.b, ec = c.h + c.b;
@@ -1479,6 +1524,7 @@ static double residual2(const Params2& P, int nx, int ny, const double* eta, con
     }
     for (int q = 0; q < 3; ++q) e.F[q] = e.F[q] * len;
     e.Gb = e.Gb * len; e.B1 = e.B1 * len; e.B2 = e.B2 * len;
+    e.PL = e.PL * len; e.PR = e.PR * len;
     return e;
   };
   std::vector<EdgeI> EXs((size_t)(nx + 1) * ny), EYs((size_t)nx * (ny + 1));
@@ -1511,8 +1557,29 @@ static double residual2(const Params2& P, int nx, int ny, const double* eta, con
           iy = iy + (kGLW[mu] * kGLW[nu]) * ((e - etab) * Vat(i, j, 5, mu, nu));
         }
       const double area = dx[i] * dy[j];
-      const double Sx = 0.5 * P.g * (er.B2 - el.B2) - P.g * etab * (er.B1 - el.B1) - P.g * area * ix;
-      const double Sy = 0.5 * P.g * (et.B2 - eb.B2) - P.g * etab * (et.B1 - eb.B1) - P.g * area * iy;
+      double Sx = 0.5 * P.g * (er.B2 - el.B2) - P.g * etab * (er.B1 - el.B1) - P.g * area * ix;
+      double Sy = 0.5 * P.g * (et.B2 - eb.B2) - P.g * etab * (et.B1 - eb.B1) - P.g * area * iy;
+      if (hydro) {
+        /* R31: the 1D source of R18 on every Gauss-Lobatto line of the cell
+         * (x-lines at the points nu, y-lines at the points mu), weighted by
+         * the other direction's rule; the pressure corrections of the cell's
+         * own traces on its four edges */
+        Sx = 0.0;
+        Sy = 0.0;
+        for (int k = 0; k < 4; ++k) {
+          double ex_[4], bx_[4], ey_[4], by_[4];
+          for (int l = 0; l < 4; ++l) {
+            ex_[l] = Vat(i, j, 0, l, k) + Vat(i, j, 3, l, k);
+            bx_[l] = Vat(i, j, 3, l, k);
+            ey_[l] = Vat(i, j, 0, k, l) + Vat(i, j, 3, k, l);
+            by_[l] = Vat(i, j, 3, k, l);
+          }
+          Sx = Sx + kGLW[k] * dy[j] * hydro_source(P.g, ex_, bx_);
+          Sy = Sy + kGLW[k] * dx[i] * hydro_source(P.g, ey_, by_);
+        }
+        Sx = Sx - er.PL + el.PR;
+        Sy = Sy - et.PL + eb.PR;
+      }
       R[c] = -(er.F[0] - el.F[0]) - (et.F[0] - eb.F[0]);
       R[N + c] = -(er.F[1] - el.F[1]) - (et.F[1] - eb.F[1]) + Sx;
       R[2 * N + c] = -(er.F[2] - el.F[2]) - (et.F[2] - eb.F[2]) + Sy;

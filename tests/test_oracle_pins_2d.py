@@ -9,6 +9,7 @@ import math
 import os
 
 import numpy as np
+import pytest
 
 import oracle as O
 from paper_2208_06588_amd import workloads as W
@@ -68,22 +69,24 @@ def test_sweep_reproduces_polynomials_on_nonuniform_widths():
     assert np.abs(out[4] - pv(pts, dq)).max() < 1e-9 * np.abs(pv(pts, dq)).max()
 
 
-def test_y_constant_data_reduce_to_the_1d_scheme():
+@pytest.mark.parametrize("flags", [0, O.FLAG_HYDROSTATIC])
+def test_y_constant_data_reduce_to_the_1d_scheme(flags):
     """Example 5.1 data extended constantly in y, the y nodes at rest: every row
     of the 2D run equals the pinned 1D oracle's run with the 2D run's step
     sizes (same classes and state; hv stays at round-off).  Pins the x-sweep,
-    the edge fluxes, the special source and the area recurrence against the
-    1D scheme."""
+    the edge fluxes, the source (special, or the hydrostatic reconstruction's
+    starred fluxes, pressure corrections and line source) and the area
+    recurrence against the 1D scheme."""
     n, ny = 64, 5
     wl = W.accuracy_1d(n)
     yi = W.uniform_nodes(ny, 0.0, 1.0)
-    P = _p2(cfl=0.6, weno_eps=wl["weno_eps"], Ax=0.05, kx=1.0, omx=math.pi, Ay=0.0)
+    P = _p2(cfl=0.6, weno_eps=wl["weno_eps"], Ax=0.05, kx=1.0, omx=math.pi, Ay=0.0, flags=flags)
     tile = lambda a: np.tile(np.asarray(a), (ny, 1))
     r2 = O.run2(P, tile(wl["h"]), tile(wl["hu"]), np.zeros((ny, n)), tile(wl["b"]), wl["xi"], yi,
                 wl["xi"], yi, t_end=0.1, record_dts=1000)
     assert r2["status"] == 0 and r2["steps"] == len(r2["dts"])
     p1 = O.params(bc=O.BC_PERIODIC, mesh=O.MESH_SINE, mesh_A=0.05, mesh_k=1.0,
-                  mesh_omega=math.pi, cfl=0.6, weno_eps=wl["weno_eps"])
+                  mesh_omega=math.pi, cfl=0.6, weno_eps=wl["weno_eps"], flags=flags)
     r1 = O.run(p1, wl["h"], wl["hu"], wl["b"], wl["x"], wl["xi"], max_steps=r2["steps"],
                dts=r2["dts"])
     assert r1["status"] == 0 and r1["stats"].steps == r2["steps"]
@@ -154,35 +157,40 @@ def test_mass_and_bottom_are_conserved():
     assert abs(m[3] - m[1]) < 1e-13
 
 
-def test_still_water_table_5_12():
+@pytest.mark.parametrize("flags,row", [(0, "table5.12"), (O.FLAG_HYDROSTATIC, "table5.12hr")])
+def test_still_water_table_5_12(flags, row):
     """Example 5.11 (b = 0.8 exp(-50 r^2), h + b = 1, at rest) on 100 x 100
     moving cells to t = 0.1: the still-water state is kept at round-off, as
-    Table 5.12 prints for the special source-term scheme (errors near 1e-15)."""
+    Table 5.12 prints for both well-balanced schemes (errors near 1e-15)."""
     wl = W.still_water_2d(100)
-    P = _p2(cfl=0.6, Ax=wl["Ax"], kx=1.0, omx=wl["omx"], Ay=wl["Ay"], ky=1.0, omy=wl["omy"])
+    P = _p2(cfl=0.6, Ax=wl["Ax"], kx=1.0, omx=wl["omx"], Ay=wl["Ay"], ky=1.0, omy=wl["omy"],
+            flags=flags)
     r = _run2(P, wl, t_end=wl["t_end"])
     assert r["status"] == 0 and abs(r["t"] - 0.1) < 1e-15
-    paper = [float(v) for row in _gold("paper_tables.txt") if row[0] == "table5.12"
-             for v in row[1:]]
+    paper = [float(v) for r_ in _gold("paper_tables.txt") if r_[0] == row for v in r_[1:]]
     err = [np.abs(r["h"] + r["b"] - 1.0), np.abs(r["hu"]), np.abs(r["hv"])]
     got = [e.mean() for e in err] + [e.max() for e in err]
     for g, p in zip(got, paper):
         assert g < 10 * p, (got, paper)
 
 
-def test_accuracy_example_5_6_against_table_5_8():
+@pytest.mark.parametrize("flags,table", [(0, "table5.8"), (O.FLAG_HYDROSTATIC, "table5.7")])
+def test_accuracy_example_5_6_against_table_5_8(flags, table):
     """Example 5.6 at 25 x 25 and 50 x 50 (CFL 0.6, t = 0.05): the L1 errors
-    of h + b, hu, hv against a 200 x 200 oracle run (averaged onto the coarse
-    cells) are within 30 % of Table 5.8's, and so the orders at the coarse end
-    (2.6, 3.4, 2.8 in the paper) are reproduced."""
+    of h + b, hu, hv against a 200 x 200 oracle run of the special scheme
+    (averaged onto the coarse cells; its own error is a thousandth of these)
+    are within 30 % of Table 5.8's (special source term) or Table 5.7's
+    (hydrostatic reconstruction), and so the orders at the coarse end (2.6,
+    3.4, 2.8 in the paper) are reproduced."""
     ref = np.array([[float(v) for v in row] for row in _gold("ex56_reference.txt")])
     ref = ref.T.reshape(3, 50, 50)
     paper = {int(r[1]): [float(v) for v in r[3:]] for r in _gold("paper_tables.txt")
-             if r[0] == "table5.8"}
+             if r[0] == table}
     errs = {}
     for n in (25, 50):
         wl = W.accuracy_2d(n)
-        P = _p2(cfl=0.6, Ax=wl["Ax"], kx=1.0, omx=wl["omx"], Ay=wl["Ay"], ky=1.0, omy=wl["omy"])
+        P = _p2(cfl=0.6, Ax=wl["Ax"], kx=1.0, omx=wl["omx"], Ay=wl["Ay"], ky=1.0, omy=wl["omy"],
+                flags=flags)
         r = _run2(P, wl, t_end=wl["t_end"])
         assert r["status"] == 0
         f = 50 // n

@@ -353,7 +353,15 @@ alew_status alew_kernel_timing(const alew_ctx* ctx, int which, double* ms, int64
  * each with the interior mean from the Gauss-Lobatto identity and
  * eps = min(1e-11, hbar); hu, hv towards their means by the same factor, b
  * following eta); traces with h <= dry_eps carry zero discharge; a mean depth
- * below -1e-11 is ALEW_E_NEGDEPTH.  State arrays are [ny][nx] (cell (i, j) at
+ * below -1e-11 is ALEW_E_NEGDEPTH.  flags = ALEW_F_HYDROSTATIC selects the
+ * hydrostatic reconstruction of Sec. 4.1 (eq. (4.4)-(4.6)) instead of the
+ * special source term: at each edge point the momentum fluxes of the starred
+ * states (h* = max(0, eta - max(b-, b+)), discharges kept) and each cell's
+ * pressure correction g/2 (h^2 - h*^2) of its own trace; the cell source is the
+ * 1D hydrostatic source (the cubic through the 4 Gauss-Lobatto values of b,
+ * eta - b times its derivative, by the 4-point rule) on every Gauss-Lobatto
+ * line of the cell, weighted by the other direction's rule.  Other flags are
+ * ALEW_E_UNSUPPORTED.  State arrays are [ny][nx] (cell (i, j) at
  * i + nx j), device FP64; nodes x [nx + 1], y [ny + 1] in place; reference
  * nodes xi [nx + 1], yi [ny + 1].
  * ------------------------------------------------------------------------ */
@@ -364,7 +372,7 @@ typedef struct {
   double Ax, kx, omx;               /* x-node map                                  */
   double Ay, ky, omy;               /* y-node map                                  */
   int32_t bcx, bcy;                 /* ALEW_BC_PERIODIC or ALEW_BC_TRANSMISSIVE    */
-  int32_t flags, pad;               /* flags: none defined, must be 0              */
+  int32_t flags, pad;               /* 0, or ALEW_F_HYDROSTATIC (see above)        */
 } alew2d_params;
 
 typedef struct {

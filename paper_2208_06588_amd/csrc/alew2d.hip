@@ -303,24 +303,42 @@ __device__ __forceinline__ int sweep(const Geo& G, double eps, const double* e5,
 // likewise, the edge terms B1 = (b- + b+)/2 and B2 = (b-^2 + b+^2)/2 of the
 // special source, weighted by wt; amax takes both traces' speeds
 // |u.n - w.n| + sqrt(g h).  Traces with h <= dry carry zero discharge.
-template <int DIR>
+// HYD: the hydrostatic reconstruction (eq. (4.4)-(4.6)): the momentum fluxes
+// of the starred states (h* = max(0, eta - max(b-, b+)), discharges kept),
+// and the pressure corrections g/2 (h^2 - h*^2) of the side a (left / below:
+// PL) and c (PR); the eta component of the starred flux plus theta is the
+// plain one exactly, so C, D of eta are the plain ones; no B1, B2.
+template <int DIR, bool HYD = false>
 __device__ __forceinline__ void lf_point(double g, double dry, double w, double wt, double ah,
                                          double am, double an, double ab, double ch, double cm,
                                          double cn, double cb, double (&C)[4], double (&D)[4],
-                                         double& B1, double& B2, double& amax) {
+                                         double& B1, double& B2, double& amax, double& PL,
+                                         double& PR) {
   if (!(ah > dry)) { am = 0.0; an = 0.0; }
   if (!(ch > dry)) { cm = 0.0; cn = 0.0; }
   double ua = 0.0, va = 0.0, uc = 0.0, vc = 0.0;
   if (ah > dry) { const double r = frcp(ah); ua = am * r; va = an * r; }
   if (ch > dry) { const double r = frcp(ch); uc = cm * r; vc = cn * r; }
   const double ea = ah + ab, ec = ch + cb;
+  // depths and velocities of the momentum fluxes
+  double pa = ah, pc = ch, usa = ua, vsa = va, usc = uc, vsc = vc;
+  if (HYD) {
+    const double bm = fmax(ab, cb);
+    pa = fmax(0.0, ea - bm);
+    pc = fmax(0.0, ec - bm);
+    usa = 0.0; vsa = 0.0; usc = 0.0; vsc = 0.0;
+    if (pa > dry) { const double r = frcp(pa); usa = am * r; vsa = an * r; }
+    if (pc > dry) { const double r = frcp(pc); usc = cm * r; vsc = cn * r; }
+    PL += wt * (0.5 * g * (ah * ah - pa * pa));
+    PR += wt * (0.5 * g * (ch * ch - pc * pc));
+  }
   double Ha[3], Hc[3];
   if (DIR == 0) {
-    Ha[0] = am - w * ea; Ha[1] = am * ua + 0.5 * g * ah * ah - w * am; Ha[2] = am * va - w * an;
-    Hc[0] = cm - w * ec; Hc[1] = cm * uc + 0.5 * g * ch * ch - w * cm; Hc[2] = cm * vc - w * cn;
+    Ha[0] = am - w * ea; Ha[1] = am * usa + 0.5 * g * pa * pa - w * am; Ha[2] = am * vsa - w * an;
+    Hc[0] = cm - w * ec; Hc[1] = cm * usc + 0.5 * g * pc * pc - w * cm; Hc[2] = cm * vsc - w * cn;
   } else {
-    Ha[0] = an - w * ea; Ha[1] = an * ua - w * am; Ha[2] = an * va + 0.5 * g * ah * ah - w * an;
-    Hc[0] = cn - w * ec; Hc[1] = cn * uc - w * cm; Hc[2] = cn * vc + 0.5 * g * ch * ch - w * cn;
+    Ha[0] = an - w * ea; Ha[1] = an * usa - w * am; Ha[2] = an * vsa + 0.5 * g * pa * pa - w * an;
+    Hc[0] = cn - w * ec; Hc[1] = cn * usc - w * cm; Hc[2] = cn * vsc + 0.5 * g * pc * pc - w * cn;
   }
   const double jump[3] = {ec - ea, cm - am, cn - an};
 #pragma unroll
@@ -330,8 +348,10 @@ __device__ __forceinline__ void lf_point(double g, double dry, double w, double 
   }
   C[3] += wt * (-0.5 * w * (ab + cb));
   D[3] += wt * (-0.5 * (cb - ab));
-  B1 += wt * (0.5 * (ab + cb));
-  B2 += wt * (0.5 * (ab * ab + cb * cb));
+  if (!HYD) {
+    B1 += wt * (0.5 * (ab + cb));
+    B2 += wt * (0.5 * (ab * ab + cb * cb));
+  }
   const double una = DIR == 0 ? ua : va, unc = DIR == 0 ? uc : vc;
   const double sa = fabs(una - w) + fsqrt(g * fmax(ah, 0.0));
   const double sc = fabs(unc - w) + fsqrt(g * fmax(ch, 0.0));
@@ -691,7 +711,7 @@ __global__ void __launch_bounds__(XB) k2_xsweep(K2 k) {
 // quad shuffles, and thread q writes component q of the right-hand side.
 // Rows j0-1 and j1 give only the traces of the edges below row j0 and above
 // row j1 - 1.
-template <int S>
+template <int S, bool HYD>
 __global__ void __launch_bounds__(256) k2_ysweep(K2 k, int rows) {
   const State2& St = *k.st;
   if (St.done) return;
@@ -721,6 +741,14 @@ __global__ void __launch_bounds__(256) k2_ysweep(K2 k, int rows) {
   const double dxs = k.dx0[iw] + tau * k.dwx[iw];
   const double wxl = k.wx[min(max(i, 0), nx)];
   const double wq = GLW[q];
+  // HYD: row q of the cubic's differentiation matrix at the Gauss-Lobatto
+  // points (cell coordinate in [0, 1]; the rows hydro_source applies)
+  constexpr double PHI = 1.6180339887498948482, PHI1 = 0.6180339887498948482;
+  constexpr double R5 = 2.2360679774997896964;
+  const double dq0 = q == 0 ? -6.0 : q == 1 ? -PHI : q == 2 ? PHI1 : -1.0;
+  const double dq1 = q == 0 ? 5.0 * PHI : q == 1 ? 0.0 : q == 2 ? -R5 : 5.0 * PHI1;
+  const double dq2 = q == 0 ? -5.0 * PHI1 : q == 1 ? R5 : q == 2 ? 0.0 : -5.0 * PHI;
+  const double dq3 = q == 0 ? 1.0 : q == 1 ? -PHI1 : q == 2 ? PHI : 6.0;
   double amax = 0.0;
   unsigned ncl[3] = {0u, 0u, 0u}, nlim = 0u;
   bool negd = false;
@@ -759,7 +787,21 @@ __global__ void __launch_bounds__(256) k2_ysweep(K2 k, int rows) {
       cl = sweep<true>(G, k.eps, e5, m5, n5, h5, b5, x5, oh, om, on, ob, od, ox);
     }
     double ix = 0.0, iy = 0.0;
-    if (body) {
+    if (body && HYD) {
+      // the line sources of the hydrostatic reconstruction (the 1D source on
+      // every Gauss-Lobatto line) from the unlimited values: this lane's part
+      // of each x-line (point nu; b of the line from the quad's four lanes),
+      // and its own y-line's, each with its abscissa's weight
+#pragma unroll
+      for (int nu = 0; nu < 4; ++nu) {
+        const double d = dq0 * quad_perm<0x00>(ob[nu]) + dq1 * quad_perm<0x55>(ob[nu]) +
+                         dq2 * quad_perm<0xAA>(ob[nu]) + dq3 * quad_perm<0xFF>(ob[nu]);
+        ix += GLW[nu] * (oh[nu] * d);
+      }
+      ix *= wq;
+      iy = wq * hydro_source(g, oh[0] + ob[0], oh[1] + ob[1], oh[2] + ob[2], oh[3] + ob[3], ob[0],
+                             ob[1], ob[2], ob[3]);
+    } else if (body) {
 #pragma unroll
       for (int nu = 0; nu < 4; ++nu) {
         const double e = oh[nu] + ob[nu];
@@ -801,20 +843,23 @@ __global__ void __launch_bounds__(256) k2_ysweep(K2 k, int rows) {
     limit_trace(p1, hbar, mbar, nbar, oh[3], om[3], on[3], ob[3]);
     // bottom edge (node jr) at point q: the cell below's top trace
     double Cy[4] = {0, 0, 0, 0}, Dy[4] = {0, 0, 0, 0}, B1y = 0.0, B2y = 0.0;
+    double PLy = 0.0, PRy = 0.0;  // HYD: pressure corrections below / above the edge
     if (!first) {
       double am = 0.0;
-      lf_point<1>(g, dry, wyb, wq, th, tm, tn, tb, oh[0], om[0], on[0], ob[0], Cy, Dy, B1y, B2y, am);
+      lf_point<1, HYD>(g, dry, wyb, wq, th, tm, tn, tb, oh[0], om[0], on[0], ob[0], Cy, Dy, B1y,
+                       B2y, am, PLy, PRy);
       if (ycol) amax = fmax(amax, am);
     }
     th = oh[3]; tm = om[3]; tn = on[3]; tb = ob[3];
     __syncthreads();
     // left edge (node i) at point q: the left neighbour's right trace
     double Cx[4] = {0, 0, 0, 0}, Dx[4] = {0, 0, 0, 0}, B1x = 0.0, B2x = 0.0;
+    double PLx = 0.0, PRx = 0.0;  // HYD: pressure corrections left / right of the edge
     if (body && cs >= 1) {
       double am = 0.0;
-      lf_point<0>(g, dry, wxl, wq, sR[cs - 1][q][0], sR[cs - 1][q][1], sR[cs - 1][q][2],
-                  sR[cs - 1][q][3], sL[cs][q][0], sL[cs][q][1], sL[cs][q][2], sL[cs][q][3], Cx, Dx,
-                  B1x, B2x, am);
+      lf_point<0, HYD>(g, dry, wxl, wq, sR[cs - 1][q][0], sR[cs - 1][q][1], sR[cs - 1][q][2],
+                       sR[cs - 1][q][3], sL[cs][q][0], sL[cs][q][1], sL[cs][q][2], sL[cs][q][3],
+                       Cx, Dx, B1x, B2x, am, PLx, PRx);
       if (xedge) amax = fmax(amax, am);
     }
     // sums over the column's four points (every thread of the quad gets them)
@@ -824,14 +869,20 @@ __global__ void __launch_bounds__(256) k2_ysweep(K2 k, int rows) {
       Cy[r] = qsum(Cy[r]) * dxs; Dy[r] = qsum(Dy[r]) * dxs;
       Cx[r] = qsum(Cx[r]) * dys; Dx[r] = qsum(Dx[r]) * dys;
     }
-    B1y = qsum(B1y) * dxs; B2y = qsum(B2y) * dxs;
-    B1x = qsum(B1x) * dys; B2x = qsum(B2x) * dys;
+    if (HYD) {
+      PLy = qsum(PLy) * dxs; PRy = qsum(PRy) * dxs;
+      PLx = qsum(PLx) * dys; PRx = qsum(PRx) * dys;
+    } else {
+      B1y = qsum(B1y) * dxs; B2y = qsum(B2y) * dxs;
+      B1x = qsum(B1x) * dys; B2x = qsum(B2x) * dys;
+    }
     ix = qsum(ix);
     iy = qsum(iy);
     const int ymax = quad_max(cl);
     // publish the left-edge sums: the right edge of the column to the left
     {
-      const double fv[12] = {Cx[0], Cx[1], Cx[2], Cx[3], Dx[0], Dx[1], Dx[2], Dx[3], B1x, B2x, 0.0, 0.0};
+      const double fv[12] = {Cx[0], Cx[1], Cx[2], Cx[3], Dx[0], Dx[1], Dx[2], Dx[3], B1x, B2x,
+                             PLx, 0.0};
 #pragma unroll
       for (int r = 0; r < 3; ++r) sF[cs][q + 4 * r] = fv[q + 4 * r];
     }
@@ -844,13 +895,14 @@ __global__ void __launch_bounds__(256) k2_ysweep(K2 k, int rows) {
     const double Dxq = q == 0 ? Dx[0] : q == 1 ? Dx[1] : q == 2 ? Dx[2] : Dx[3];
     const double Crq = sF[cn][q], Drq = sF[cn][4 + q];
     const double B1r = sF[cn][8], B2r = sF[cn][9];
+    const double PLr = sF[cn][10];  // HYD: this cell's correction on its right edge
     if (!first) {
       // the previous row is complete: its top edge is this row's bottom edge
       const int jp = jr - 1;
       if (own_col && jp >= j0) {
         const uint32_t cp = (uint32_t)q * (uint32_t)k.N + (uint32_t)i + (uint32_t)nx * (uint32_t)jp;
         double rc = Pc - Cyq;
-        if (q == 2) rc += 0.5 * g * B2y - g * etab_p * B1y;
+        if (q == 2) rc += HYD ? -PLy : 0.5 * g * B2y - g * etab_p * B1y;
         k.Rc[cp] = rc;
         k.Rd[cp] = Pd - Dyq;
       }
@@ -858,8 +910,13 @@ __global__ void __launch_bounds__(256) k2_ysweep(K2 k, int rows) {
     if (body) {
       const double area = dxs * dys;
       Pc = -(Crq - Cxq) + Cyq;
-      if (q == 1) Pc += 0.5 * g * (B2r - B2x) - g * etab * (B1r - B1x) - g * area * ix;
-      if (q == 2) Pc += -0.5 * g * B2y + g * etab * B1y - g * area * iy;
+      if (HYD) {
+        if (q == 1) Pc += (PRx - PLr) - g * dys * ix;
+        if (q == 2) Pc += PRy + dxs * iy;
+      } else {
+        if (q == 1) Pc += 0.5 * g * (B2r - B2x) - g * etab * (B1r - B1x) - g * area * ix;
+        if (q == 2) Pc += -0.5 * g * B2y + g * etab * B1y - g * area * iy;
+      }
       Pd = -(Drq - Dxq) + Dyq;
       etab_p = etab;
       if (own_col && q == 0) {
@@ -1082,7 +1139,9 @@ alew_status alew2d_run(alew2d_ctx* c, const alew2d_params* p, int64_t nx, int64_
   if ((p->bcx != ALEW_BC_PERIODIC && p->bcx != ALEW_BC_TRANSMISSIVE) ||
       (p->bcy != ALEW_BC_PERIODIC && p->bcy != ALEW_BC_TRANSMISSIVE))
     return fail2(ALEW_E_UNSUPPORTED, "2D boundaries: periodic or transmissive");
-  if (p->flags != 0) return fail2(ALEW_E_UNSUPPORTED, "no 2D flags are defined");
+  if (p->flags & ~ALEW_F_HYDROSTATIC)
+    return fail2(ALEW_E_UNSUPPORTED, "the only 2D flag is HYDROSTATIC");
+  const bool hyd = (p->flags & ALEW_F_HYDROSTATIC) != 0;
   if (!std::isfinite(t0) || std::isnan(t_end) || max_steps < 0)
     return fail2(ALEW_E_ARG, "t0 finite, t_end not NaN and max_steps >= 0 required");
   K2 k{};
@@ -1141,11 +1200,20 @@ alew_status alew2d_run(alew2d_ctx* c, const alew2d_params* p, int64_t nx, int64_
     };
     timed_launch(0, [&] { hipLaunchKernelGGL(k2_kin, dim3(1), dim3(KB), 0, st, k); });
     timed_launch(1, [&] { hipLaunchKernelGGL(k2_xsweep<0>, gx, dim3(XB), 0, st, k); });
-    timed_launch(2, [&] { hipLaunchKernelGGL(k2_ysweep<0>, gy, dim3(256), 0, st, k, rows); });
+    timed_launch(2, [&] {
+      if (hyd) hipLaunchKernelGGL((k2_ysweep<0, true>), gy, dim3(256), 0, st, k, rows);
+      else hipLaunchKernelGGL((k2_ysweep<0, false>), gy, dim3(256), 0, st, k, rows);
+    });
     timed_launch(1, [&] { hipLaunchKernelGGL(k2_xsweep<1>, gx, dim3(XB), 0, st, k); });
-    timed_launch(2, [&] { hipLaunchKernelGGL(k2_ysweep<1>, gy, dim3(256), 0, st, k, rows); });
+    timed_launch(2, [&] {
+      if (hyd) hipLaunchKernelGGL((k2_ysweep<1, true>), gy, dim3(256), 0, st, k, rows);
+      else hipLaunchKernelGGL((k2_ysweep<1, false>), gy, dim3(256), 0, st, k, rows);
+    });
     timed_launch(1, [&] { hipLaunchKernelGGL(k2_xsweep<2>, gx, dim3(XB), 0, st, k); });
-    timed_launch(2, [&] { hipLaunchKernelGGL(k2_ysweep<2>, gy, dim3(256), 0, st, k, rows); });
+    timed_launch(2, [&] {
+      if (hyd) hipLaunchKernelGGL((k2_ysweep<2, true>), gy, dim3(256), 0, st, k, rows);
+      else hipLaunchKernelGGL((k2_ysweep<2, false>), gy, dim3(256), 0, st, k, rows);
+    });
     timed_launch(3, [&] { hipLaunchKernelGGL(k2_fin, gc, dim3(256), 0, st, k); });
     return r;
   };

@@ -27,12 +27,14 @@ def _t(a, dev):
     return torch.tensor(np.asarray(a), dtype=torch.float64, device=dev)
 
 
-def _pair(wl, cfl=0.6, eps=1e-6, bcy="periodic"):
+def _pair(wl, cfl=0.6, eps=1e-6, bcy="periodic", hydro=False):
     g = alew.params2(cfl=cfl, weno_eps=eps, Ax=wl["Ax"], kx=wl["kx"], omx=wl["omx"], Ay=wl["Ay"],
-                     ky=wl["ky"], omy=wl["omy"], bcx="periodic", bcy=bcy)
+                     ky=wl["ky"], omy=wl["omy"], bcx="periodic", bcy=bcy,
+                     flags=alew.F_HYDROSTATIC if hydro else 0)
     o = O.params2(cfl=cfl, weno_eps=eps, Ax=wl["Ax"], kx=wl["kx"], omx=wl["omx"], Ay=wl["Ay"],
                   ky=wl["ky"], omy=wl["omy"], bcx=O.BC_PERIODIC,
-                  bcy=O.BC_PERIODIC if bcy == "periodic" else O.BC_TRANSMISSIVE)
+                  bcy=O.BC_PERIODIC if bcy == "periodic" else O.BC_TRANSMISSIVE,
+                  flags=O.FLAG_HYDROSTATIC if hydro else 0)
     return g, o
 
 
@@ -191,11 +193,13 @@ def full_size():
     return W.smooth_2d(2048)
 
 
-def test_full_size_one_step_every_cell_against_oracle(dev, full_size):
+@pytest.mark.parametrize("hydro", [False, True])
+def test_full_size_one_step_every_cell_against_oracle(dev, full_size, hydro):
     """One step of the 2048 x 2048 workload in the launch configuration the
-    benchmark times: every cell equals the oracle's."""
+    benchmark times: every cell equals the oracle's (special source term, and
+    the hydrostatic reconstruction)."""
     wl = full_size
-    gp, op = _pair(wl)
+    gp, op = _pair(wl, hydro=hydro)
     ctx = alew.Context2(2048, 2048)
     g, st = _gpu_run(ctx, gp, wl, dev, max_steps=1)
     r = _ora_run(op, wl, max_steps=1)
@@ -279,7 +283,8 @@ def test_circular_dam_break_at_the_papers_resolution(dev):
     assert abs(st2.mass_b - st2.mass_b0) < 1e-9
 
 
-def test_fifth_order_against_table_5_8(dev):
+@pytest.mark.parametrize("hydro,table", [(False, "table5.8"), (True, "table5.7")])
+def test_fifth_order_against_table_5_8(dev, hydro, table):
     """Example 5.6 to t = 0.05 on 100², 200², 400² and 800² moving cells at the
     CFL numbers of Table 5.8 (0.5, 0.4, 0.3, 0.2), against this scheme's own
     1600² run (CFL 0.2; the mesh is uniform again at t_end, so 2^k x 2^k fine
@@ -287,18 +292,20 @@ def test_fifth_order_against_table_5_8(dev):
     25 % of the printed ones and those of hu within a factor 3 (printed
     against another scheme's 1600² reference), and the orders reach fifth
     order: above 4.8 from 400² to 800² for all three (the paper: 5.03, 4.82,
-    4.97), and within 0.25 of the printed h + b orders at every refinement."""
+    4.97), and within 0.25 of the printed h + b orders at every refinement.
+    The same for the hydrostatic reconstruction against Table 5.7 (same CFL
+    numbers; printed orders 5.04, 4.82, 4.97 at the fine end)."""
     paper = {}
     import os
     gold = os.path.join(os.path.dirname(__file__), "golden", "paper_tables.txt")
     for ln in open(gold):
         r = ln.split()
-        if r and r[0] == "table5.8":
+        if r and r[0] == table:
             paper[int(r[1])] = [float(v) for v in r[3:6]]
 
     def run(n, cfl):
         wl = W.accuracy_2d(n)
-        gp, _ = _pair(wl, cfl=cfl)
+        gp, _ = _pair(wl, cfl=cfl, hydro=hydro)
         g, st = _gpu_run(alew.Context2(n, n), gp, wl, dev, t_end=wl["t_end"])
         assert st.status == 0 and abs(st.t - 0.05) < 1e-15
         return [g["h"] + g["b"], g["hu"], g["hv"]]
@@ -321,3 +328,48 @@ def test_fifth_order_against_table_5_8(dev):
         assert abs(o[0] - po) < 0.25, (a, b, o, po)
         if a == 400:
             assert min(o) > 4.8, o
+
+
+@pytest.mark.parametrize("case", ["accuracy", "still_water", "ragged"])
+def test_hydrostatic_reconstruction_against_oracle(dev, case):
+    """The hydrostatic reconstruction (Sec. 4.1, flag HYDROSTATIC): Example 5.6
+    at 50 x 50 to t = 0.05 with the class of every cell at every stage,
+    Example 5.11 on 100 x 100 to t = 0.1 (still water at round-off, Table
+    5.12's hydrostatic row), and the ragged 130 x 37 grid with transmissive y
+    (40 steps): the oracle's steps, classes and state."""
+    if case == "accuracy":
+        wl = W.accuracy_2d(50)
+        gp, op = _pair(wl, hydro=True)
+        ctx = alew.Context2(50, 50)
+        g, st = _gpu_run(ctx, gp, wl, dev, record=True, t_end=wl["t_end"])
+        r = _ora_run(op, wl, t_end=wl["t_end"], max_steps=1000, record_cls=True)
+        rc, rs = class_record(r["cls"][:r["steps"]].reshape(r["steps"], 3, -1))
+        cells, lower = class_flips(g["cnt"], g["sig"], rc, rs)
+        assert cells == 0 and lower == 0
+    elif case == "still_water":
+        wl = W.still_water_2d(100)
+        gp, op = _pair(wl, hydro=True)
+        ctx = alew.Context2(100, 100)
+        g, st = _gpu_run(ctx, gp, wl, dev, t_end=wl["t_end"])
+        assert np.abs(g["h"] + g["b"] - 1.0).max() < 1e-13
+        assert np.abs(g["hu"]).max() < 1e-13 and np.abs(g["hv"]).max() < 1e-13
+        r = _ora_run(op, wl, t_end=wl["t_end"])
+    else:
+        wl = _ragged(130, 37)
+        gp, op = _pair(wl, cfl=0.5, bcy="transmissive", hydro=True)
+        ctx = alew.Context2(130, 37)
+        g, st = _gpu_run(ctx, gp, wl, dev, max_steps=40)
+        r = _ora_run(op, wl, max_steps=40)
+    assert st.status == 0 and r["status"] == 0 and st.steps == r["steps"]
+    assert list(st.n_class) == list(r["n_class"])
+    _parity(g, r, case)
+
+
+def test_unknown_2d_flag_is_refused(dev):
+    """A 2D flag other than HYDROSTATIC is ALEW_E_UNSUPPORTED before any work."""
+    wl = W.accuracy_2d(16)
+    gp, _ = _pair(wl)
+    gp.flags = alew.F_HYDROSTATIC | 1
+    ctx = alew.Context2(16, 16)
+    with pytest.raises(Exception):
+        _gpu_run(ctx, gp, wl, dev, max_steps=1)

@@ -151,6 +151,18 @@
  *      Gauss-Lobatto rule; the point values are the unlimited ones, as for
  *      the special source (R28).  Still water is kept line by line: the edge
  *      and cell rules share the points.
+ *  R32 2D FLAG_NONWB: the scheme of Sec. 3 without well-balancing on the
+ *      tensor-product mesh, as R22 in each sweep: q = (eta, hu, hv) in the
+ *      local characteristic variables of the sweep direction (the flux
+ *      Jacobian's eigenvectors at the cell's mean state; the x-sweep of a
+ *      row's cell at that cell's mean, the y-sweep of every abscissa at the
+ *      cell's mean), each characteristic variable and b with their own
+ *      indicators, class and weights (b's x-derivative lines in the y-sweep
+ *      with b's weights), the identity frame where the mean depth is at most
+ *      dry_eps; the plain Lax-Friedrichs flux; the source -g h grad b by the
+ *      4 x 4 Gauss-Lobatto rule on the unlimited values (b_x, b_y the
+ *      derivatives of b's reconstructions, R12); the limiter keeps the bottom
+ *      traces (as R22).
  *  R30 MESH_ALIGNED: the quartic map of eq. (5.14) (Example 5.5), the map of
  *      eq. (5.1) times (xi - p1)(xi - p2) / (xmax - xmin)^2 with p1, p2 the
  *      step bottom's jump points bottom_p[1], bottom_p[2]: a node placed on a
@@ -1258,6 +1270,70 @@ static int sweep2(const CellGeo& G, double Dx, double eps, const double e5[5], c
   return cls;
 }
 
+/* R32: one sweep of the scheme without well-balancing.  q = (eta, m_x, m_y)
+ * in the local characteristic variables of the sweep direction (dir 0: x,
+ * 1: y), taken from the eigenvectors of that direction's flux Jacobian at the
+ * mean state (hbar, mxbar, mybar) given: with u_n, u_t the normal and
+ * tangential velocities and c = sqrt(g hbar), the eigenvalues u_n - c, u_n,
+ * u_n + c have the right eigenvectors (1, u_n - c, u_t), (0, 0, 1),
+ * (1, u_n + c, u_t) in (eta, m_n, m_t); where hbar <= dry the frame is the
+ * identity.  Each characteristic variable and b are swept as scalars with
+ * their own indicators, class and weights (sweep2 on one variable); the
+ * extra variable (b's x-derivative lines in the y-sweep) takes b's weights.
+ * out as sweep2's (h = eta - b); returns the largest of the four classes. */
+static int sweep2_char(const CellGeo& G, double Dx, double eps, double g, double dry, int dir,
+                       double hbar, double mxbar, double mybar, const double e5[5],
+                       const double mx5[5], const double my5[5], const double b5[5],
+                       const double* ext5, double out[6][4]) {
+  const double zero[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  const bool chr = hbar > dry;
+  double un = 0.0, ut = 0.0, c = 0.0;
+  if (chr) {
+    un = (dir == 0 ? mxbar : mybar) / hbar;
+    ut = (dir == 0 ? mybar : mxbar) / hbar;
+    c = std::sqrt(g * hbar);
+  }
+  double w[3][5];
+  for (int k = 0; k < 5; ++k) {
+    const double mn = dir == 0 ? mx5[k] : my5[k], mt = dir == 0 ? my5[k] : mx5[k];
+    if (chr) {
+      /* rows of the inverse of the right-eigenvector matrix */
+      w[0][k] = ((un + c) * e5[k] - mn) / (2.0 * c);
+      w[1][k] = mt - ut * e5[k];
+      w[2][k] = ((c - un) * e5[k] + mn) / (2.0 * c);
+    } else {
+      w[0][k] = e5[k];
+      w[1][k] = mt;
+      w[2][k] = mn;
+    }
+  }
+  double ow[3][6][4], ob[6][4];
+  int cmax = 0;
+  for (int q = 0; q < 3; ++q)
+    cmax = std::max(cmax, sweep2(G, Dx, eps, w[q], zero, zero, w[q], w[q], nullptr, ow[q]));
+  cmax = std::max(cmax, sweep2(G, Dx, eps, b5, zero, zero, b5, b5, ext5, ob));
+  for (int mu = 0; mu < 4; ++mu) {
+    const double a0 = ow[0][0][mu], a1 = ow[1][0][mu], a2 = ow[2][0][mu];
+    double e, mn, mt;
+    if (chr) {
+      e = a0 + a2;
+      mn = (un - c) * a0 + (un + c) * a2;
+      mt = ut * a0 + a1 + ut * a2;
+    } else {
+      e = a0;
+      mt = a1;
+      mn = a2;
+    }
+    out[0][mu] = e - ob[0][mu];
+    out[1][mu] = dir == 0 ? mn : mt;
+    out[2][mu] = dir == 0 ? mt : mn;
+    out[3][mu] = ob[0][mu];
+    out[4][mu] = ob[4][mu];
+    out[5][mu] = ob[5][mu];
+  }
+  return cmax;
+}
+
 struct Counters2 {
   int64_t n_class[3];
   int negw;  /* a negative linear weight on a stage mesh (R29) */
@@ -1273,7 +1349,8 @@ struct Counters2 {
  * m = min(edge values, delta); where m < eps = min(1e-11, hbar) the depths,
  * hu and hv move towards the cell means by Phi = (hbar - eps) / (hbar - m) and
  * the bottom follows eta (Remark 4.1).  Returns 1 if it acted. */
-static int limit_edges2(double hbar, double mbar, double nbar, double e[2][4][4]) {
+static int limit_edges2(double hbar, double mbar, double nbar, double e[2][4][4],
+                        bool keep_b = false) {
   const double s1 = kGLW[0], PPE = 1e-11;
   double eta[2][4];
   for (int sd = 0; sd < 2; ++sd)
@@ -1299,7 +1376,7 @@ static int limit_edges2(double hbar, double mbar, double nbar, double e[2][4][4]
       t[0] = Phi * (t[0] - hbar) + hbar;
       t[1] = Phi * (t[1] - mbar) + mbar;
       t[2] = Phi * (t[2] - nbar) + nbar;
-      t[3] = eta[sd][k] - t[0];
+      if (!keep_b) t[3] = eta[sd][k] - t[0];
     }
   return 1;
 }
@@ -1317,6 +1394,7 @@ static double residual2(const Params2& P, int nx, int ny, const double* eta, con
                         const double* wx, const double* wy, double* R, uint8_t* cls,
                         Counters2& cnt) {
   const int G = 3, EX = nx + 2 * G, EY = ny + 2 * G;
+  const bool nwb = (P.flags & FLAG_NONWB) != 0;  /* R32 */
   auto cell = [&](int i, int j) { return wrap_index(P.bcx, nx, i) + nx * wrap_index(P.bcy, ny, j); };
   auto wdx = [&](int i) { return dx[wrap_index(P.bcx, nx, i)]; };
   auto wdy = [&](int j) { return dy[wrap_index(P.bcy, ny, j)]; };
@@ -1358,7 +1436,9 @@ static double residual2(const Params2& P, int nx, int ny, const double* eta, con
       }
       double out[6][4];
       xcls[(size_t)(j + 3) * LX + (i + 1)] =
-          sweep2(Gx[i + 1], Dxg, P.weno_eps, e5, x5, y5, h5, b5, nullptr, out);
+          nwb ? sweep2_char(Gx[i + 1], Dxg, P.weno_eps, P.g, P.dry_eps, 0, h5[2], x5[2], y5[2],
+                            e5, x5, y5, b5, nullptr, out)
+              : sweep2(Gx[i + 1], Dxg, P.weno_eps, e5, x5, y5, h5, b5, nullptr, out);
       for (int v = 0; v < 5; ++v)
         for (int mu = 0; mu < 4; ++mu) Lat(i, j, v, mu) = out[v][mu];
     }
@@ -1381,7 +1461,10 @@ static double residual2(const Params2& P, int nx, int ny, const double* eta, con
           e5[k] = h5[k] + b5[k];
         }
         double out[6][4];
-        int c = sweep2(Gy[j + 1], Dyg, P.weno_eps, e5, x5, y5, h5, b5, d5, out);
+        const int cc = cell(i, j);
+        int c = nwb ? sweep2_char(Gy[j + 1], Dyg, P.weno_eps, P.g, P.dry_eps, 1, eta[cc] - b[cc],
+                                  mx[cc], my[cc], e5, x5, y5, b5, d5, out)
+                    : sweep2(Gy[j + 1], Dyg, P.weno_eps, e5, x5, y5, h5, b5, d5, out);
         cmax = std::max(cmax, c);
         for (int nu = 0; nu < 4; ++nu) {
           Vat(i, j, 0, mu, nu) = out[0][nu];
@@ -1418,8 +1501,8 @@ static double residual2(const Params2& P, int nx, int ny, const double* eta, con
             ex[sd][k][v] = Vat(i, j, v, sd ? 3 : 0, k);
             ey[sd][k][v] = Vat(i, j, v, k, sd ? 3 : 0);
           }
-      const int lx = limit_edges2(hbar, mx[c], my[c], ex);
-      const int ly = limit_edges2(hbar, mx[c], my[c], ey);
+      const int lx = limit_edges2(hbar, mx[c], my[c], ex, nwb);
+      const int ly = limit_edges2(hbar, mx[c], my[c], ey, nwb);
       for (int sd = 0; sd < 2; ++sd)
         for (int k = 0; k < 4; ++k)
           for (int v = 0; v < 4; ++v) {
@@ -1579,6 +1662,19 @@ static double residual2(const Params2& P, int nx, int ny, const double* eta, con
         }
         Sx = Sx - er.PL + el.PR;
         Sy = Sy - et.PL + eb.PR;
+      }
+      if (nwb) {
+        /* R32: -g h grad b by the 4 x 4 Gauss-Lobatto rule on the unlimited
+         * point values (b_x, b_y: the derivatives of b's reconstructions) */
+        double sx = 0.0, sy = 0.0;
+        for (int mu = 0; mu < 4; ++mu)
+          for (int nu = 0; nu < 4; ++nu) {
+            const double wgt = kGLW[mu] * kGLW[nu], hh = Vat(i, j, 0, mu, nu);
+            sx = sx + wgt * (hh * Vat(i, j, 4, mu, nu));
+            sy = sy + wgt * (hh * Vat(i, j, 5, mu, nu));
+          }
+        Sx = -P.g * area * sx;
+        Sy = -P.g * area * sy;
       }
       R[c] = -(er.F[0] - el.F[0]) - (et.F[0] - eb.F[0]);
       R[N + c] = -(er.F[1] - el.F[1]) - (et.F[1] - eb.F[1]) + Sx;
@@ -1937,6 +2033,7 @@ int orc2_run(const Params2* P, int64_t nx_, int64_t ny_, double* h, double* hu, 
              int64_t dts_cap) {
   const int nx = (int)nx_, ny = (int)ny_;
   if (nx < 5 || ny < 5) return ST_ARG;
+  if ((P->flags & FLAG_HYDROSTATIC) && (P->flags & FLAG_NONWB)) return ST_ARG;
   const size_t N = (size_t)nx * ny;
   std::vector<double> eta(N);
   for (size_t c = 0; c < N; ++c) eta[c] = h[c] + b[c];

@@ -69,14 +69,15 @@ def test_sweep_reproduces_polynomials_on_nonuniform_widths():
     assert np.abs(out[4] - pv(pts, dq)).max() < 1e-9 * np.abs(pv(pts, dq)).max()
 
 
-@pytest.mark.parametrize("flags", [0, O.FLAG_HYDROSTATIC])
+@pytest.mark.parametrize("flags", [0, O.FLAG_HYDROSTATIC, O.FLAG_NONWB])
 def test_y_constant_data_reduce_to_the_1d_scheme(flags):
     """Example 5.1 data extended constantly in y, the y nodes at rest: every row
     of the 2D run equals the pinned 1D oracle's run with the 2D run's step
     sizes (same classes and state; hv stays at round-off).  Pins the x-sweep,
     the edge fluxes, the source (special, or the hydrostatic reconstruction's
-    starred fluxes, pressure corrections and line source) and the area
-    recurrence against the 1D scheme."""
+    starred fluxes, pressure corrections and line source; or the scheme without
+    well-balancing, whose x-direction characteristic frame reduces to the 1D
+    one) and the area recurrence against the 1D scheme."""
     n, ny = 64, 5
     wl = W.accuracy_1d(n)
     yi = W.uniform_nodes(ny, 0.0, 1.0)
@@ -157,11 +158,14 @@ def test_mass_and_bottom_are_conserved():
     assert abs(m[3] - m[1]) < 1e-13
 
 
-@pytest.mark.parametrize("flags,row", [(0, "table5.12"), (O.FLAG_HYDROSTATIC, "table5.12hr")])
+@pytest.mark.parametrize("flags,row", [(0, "table5.12"), (O.FLAG_HYDROSTATIC, "table5.12hr"),
+                                       (O.FLAG_NONWB, "table5.12nwb")])
 def test_still_water_table_5_12(flags, row):
     """Example 5.11 (b = 0.8 exp(-50 r^2), h + b = 1, at rest) on 100 x 100
     moving cells to t = 0.1: the still-water state is kept at round-off, as
-    Table 5.12 prints for both well-balanced schemes (errors near 1e-15)."""
+    Table 5.12 prints for both well-balanced schemes (errors near 1e-15); the
+    scheme without well-balancing leaves it by its truncation error, and the
+    six errors equal the printed ones (1.27e-6 ... 2.30e-5) within 5 %."""
     wl = W.still_water_2d(100)
     P = _p2(cfl=0.6, Ax=wl["Ax"], kx=1.0, omx=wl["omx"], Ay=wl["Ay"], ky=1.0, omy=wl["omy"],
             flags=flags)
@@ -171,17 +175,22 @@ def test_still_water_table_5_12(flags, row):
     err = [np.abs(r["h"] + r["b"] - 1.0), np.abs(r["hu"]), np.abs(r["hv"])]
     got = [e.mean() for e in err] + [e.max() for e in err]
     for g, p in zip(got, paper):
-        assert g < 10 * p, (got, paper)
+        if flags == O.FLAG_NONWB:
+            assert abs(g / p - 1.0) < 0.05, (got, paper)
+        else:
+            assert g < 10 * p, (got, paper)
 
 
-@pytest.mark.parametrize("flags,table", [(0, "table5.8"), (O.FLAG_HYDROSTATIC, "table5.7")])
+@pytest.mark.parametrize("flags,table", [(0, "table5.8"), (O.FLAG_HYDROSTATIC, "table5.7"),
+                                         (O.FLAG_NONWB, "table5.6")])
 def test_accuracy_example_5_6_against_table_5_8(flags, table):
     """Example 5.6 at 25 x 25 and 50 x 50 (CFL 0.6, t = 0.05): the L1 errors
     of h + b, hu, hv against a 200 x 200 oracle run of the special scheme
     (averaged onto the coarse cells; its own error is a thousandth of these)
-    are within 30 % of Table 5.8's (special source term) or Table 5.7's
-    (hydrostatic reconstruction), and so the orders at the coarse end (2.6,
-    3.4, 2.8 in the paper) are reproduced."""
+    are within 30 % of Table 5.8's (special source term), Table 5.7's
+    (hydrostatic reconstruction) or Table 5.6's (without well-balancing), and
+    so the orders at the coarse end (2.6, 3.4, 2.8 in the paper) are
+    reproduced."""
     ref = np.array([[float(v) for v in row] for row in _gold("ex56_reference.txt")])
     ref = ref.T.reshape(3, 50, 50)
     paper = {int(r[1]): [float(v) for v in r[3:]] for r in _gold("paper_tables.txt")

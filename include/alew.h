@@ -360,7 +360,14 @@ alew_status alew_kernel_timing(const alew_ctx* ctx, int which, double* ms, int64
  * pressure correction g/2 (h^2 - h*^2) of its own trace; the cell source is the
  * 1D hydrostatic source (the cubic through the 4 Gauss-Lobatto values of b,
  * eta - b times its derivative, by the 4-point rule) on every Gauss-Lobatto
- * line of the cell, weighted by the other direction's rule.  Other flags are
+ * line of the cell, weighted by the other direction's rule.  flags =
+ * ALEW_F_NONWB selects the scheme of Sec. 3 without well-balancing: in each
+ * sweep (eta, hu, hv) in the local characteristic variables of the sweep
+ * direction (the flux Jacobian's eigenvectors at the cell's mean state; the
+ * identity where the mean depth is at most dry_eps), each characteristic
+ * variable and b with their own indicators, class and weights; the plain
+ * flux; the source -g h grad b by the 4 x 4 Gauss-Lobatto rule; the limiter
+ * keeps the bottom traces.  Both flags together are ALEW_E_ARG, other flags
  * ALEW_E_UNSUPPORTED.  State arrays are [ny][nx] (cell (i, j) at
  * i + nx j), device FP64; nodes x [nx + 1], y [ny + 1] in place; reference
  * nodes xi [nx + 1], yi [ny + 1].
@@ -372,7 +379,7 @@ typedef struct {
   double Ax, kx, omx;               /* x-node map                                  */
   double Ay, ky, omy;               /* y-node map                                  */
   int32_t bcx, bcy;                 /* ALEW_BC_PERIODIC or ALEW_BC_TRANSMISSIVE    */
-  int32_t flags, pad;               /* 0, or ALEW_F_HYDROSTATIC (see above)        */
+  int32_t flags, pad;               /* 0, ALEW_F_HYDROSTATIC or ALEW_F_NONWB        */
 } alew2d_params;
 
 typedef struct {

@@ -354,7 +354,8 @@ def step_noalloc(p: Params, h, hu, b, x, xi=None, w=None, t=0.0, dt=0.0, t_end=0
 def params2(g=9.812, cfl=0.6, weno_eps=1e-6, dry_eps=1e-8, Ax=0.02, kx=1.0,
             omx=3.141592653589793, Ay=0.02, ky=1.0, omy=3.141592653589793, bcx="periodic",
             bcy="periodic", flags=0) -> Params2:
-    """flags: 0 (special source term) or F_HYDROSTATIC (hydrostatic reconstruction)."""
+    """flags: 0 (special source term), F_HYDROSTATIC (hydrostatic reconstruction)
+    or F_NONWB (without well-balancing, characteristic sweeps)."""
     bc = lambda v: BC[v] if isinstance(v, str) else int(v)
     return Params2(g, cfl, weno_eps, dry_eps, Ax, kx, omx, Ay, ky, omy, bc(bcx), bc(bcy),
                    int(flags), 0)

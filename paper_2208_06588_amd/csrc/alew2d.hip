@@ -298,6 +298,70 @@ __device__ __forceinline__ int sweep(const Geo& G, double eps, const double* e5,
   return cls;
 }
 
+// One sweep of the scheme without well-balancing: (eta, hu, hv) in the local
+// characteristic variables of the sweep direction (DIR 0: x, 1: y), from the
+// eigenvectors of that direction's flux Jacobian at the mean state (hb, mxb,
+// myb): eigenvalues u_n -+ c, u_n, right eigenvectors (1, u_n - c, u_t),
+// (0, 0, 1), (1, u_n + c, u_t) in (eta, m_n, m_t); the identity where hb <=
+// dry.  Each characteristic variable and b are swept as scalars with their
+// own indicators, class and weights (sweep on one variable); b's derivative
+// and (EXT) the extra lines take b's weights.  Outputs as sweep's (h = eta -
+// b); returns the largest of the four classes.
+template <int DIR, bool EXT>
+__device__ __forceinline__ int sweep_char(const Geo& G, double eps, double g, double dry,
+                                          double hb, double mxb, double myb, const double* e5,
+                                          const double* m5, const double* n5, const double* b5,
+                                          const double* x5, double (&oh)[4], double (&om)[4],
+                                          double (&on)[4], double (&ob)[4], double (&od)[4],
+                                          double (&ox)[4]) {
+  const bool chr = hb > dry;
+  double un = 0.0, ut = 0.0, c = 0.0, i2c = 0.0;
+  if (chr) {
+    const double ih = frcp(hb);
+    un = (DIR == 0 ? mxb : myb) * ih;
+    ut = (DIR == 0 ? myb : mxb) * ih;
+    c = fsqrt(g * hb);
+    i2c = 0.5 * frcp(c);
+  }
+  double w0[5], w1[5], w2[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    const double mn = DIR == 0 ? m5[k] : n5[k], mt = DIR == 0 ? n5[k] : m5[k];
+    if (chr) {
+      w0[k] = ((un + c) * e5[k] - mn) * i2c;
+      w1[k] = mt - ut * e5[k];
+      w2[k] = ((c - un) * e5[k] + mn) * i2c;
+    } else {
+      w0[k] = e5[k];
+      w1[k] = mt;
+      w2[k] = mn;
+    }
+  }
+  const double z5[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  double a0[4], a1[4], a2[4], t[4], u[4];
+  int cl = sweep<false>(G, eps, w0, z5, z5, w0, w0, nullptr, a0, t, t, t, u, u);
+  cl = max(cl, sweep<false>(G, eps, w1, z5, z5, w1, w1, nullptr, a1, t, t, t, u, u));
+  cl = max(cl, sweep<false>(G, eps, w2, z5, z5, w2, w2, nullptr, a2, t, t, t, u, u));
+  cl = max(cl, sweep<EXT>(G, eps, b5, z5, z5, b5, b5, x5, t, u, u, ob, od, ox));
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+    double e, mn, mt;
+    if (chr) {
+      e = a0[mu] + a2[mu];
+      mn = (un - c) * a0[mu] + (un + c) * a2[mu];
+      mt = ut * a0[mu] + a1[mu] + ut * a2[mu];
+    } else {
+      e = a0[mu];
+      mt = a1[mu];
+      mn = a2[mu];
+    }
+    oh[mu] = e - ob[mu];
+    om[mu] = DIR == 0 ? mn : mt;
+    on[mu] = DIR == 0 ? mt : mn;
+  }
+  return cl;
+}
+
 // Lax-Friedrichs flux of eq. (3.13) for F.n - (w.n) q at one edge point,
 // split as C + alpha D (D = -jump / 2), the bottom's ALE flux of eq. (3.17)
 // likewise, the edge terms B1 = (b- + b+)/2 and B2 = (b-^2 + b+^2)/2 of the
@@ -398,7 +462,9 @@ __device__ __forceinline__ double limiter_phi(double hbar, double q0, double q1,
   if (!(mn < epsj)) return 1.0;
   return fmin(1.0, (hbar - epsj) * frcp(hbar - mn));
 }
-// A trace moved towards the cell means by Phi; b follows eta (Remark 4.1).
+// A trace moved towards the cell means by Phi; b follows eta (Remark 4.1), or
+// (KEEPB: the scheme without well-balancing) keeps its value.
+template <bool KEEPB = false>
 __device__ __forceinline__ void limit_trace(double Phi, double hbar, double mbar, double nbar,
                                             double& h, double& m, double& n, double& b) {
   if (Phi == 1.0) return;
@@ -406,7 +472,7 @@ __device__ __forceinline__ void limit_trace(double Phi, double hbar, double mbar
   h = Phi * (h - hbar) + hbar;
   m = Phi * (m - mbar) + mbar;
   n = Phi * (n - nbar) + nbar;
-  b = eta - h;
+  if (!KEEPB) b = eta - h;
 }
 
 // ----------------------------------------------------------------------------
@@ -636,8 +702,9 @@ __global__ void __launch_bounds__(KB) k2_kin(K2 k) {
 // x-sweep of stage S: a work-group of XB threads outputs the line values of
 // columns i0 .. i0 + XB - 1 (i0 = blockIdx.x XB - 1, columns -1..nx) of row
 // blockIdx.y from the XB + 4 stage states staged in LDS.
-template <int S>
+template <int S, int SCH>
 __global__ void __launch_bounds__(XB) k2_xsweep(K2 k) {
+  constexpr bool NWB = SCH == 2;  // characteristic sweeps of the scheme without well-balancing
   const State2& St = *k.st;
   if (St.done) return;
   __shared__ double sv[4][XB + 4];
@@ -683,7 +750,12 @@ __global__ void __launch_bounds__(XB) k2_xsweep(K2 k) {
   Geo G;
   load_geo(k.Gx, nx + 2, S, i + 1, G);
   double oh[4], om[4], on[4], ob[4], od[4], ox[4];
-  const int cls = sweep<false>(G, k.eps, e5, m5, n5, h5, b5, nullptr, oh, om, on, ob, od, ox);
+  int cls;
+  if (NWB)
+    cls = sweep_char<0, false>(G, k.eps, k.g, k.dry, h5[2], m5[2], n5[2], e5, m5, n5, b5, nullptr,
+                               oh, om, on, ob, od, ox);
+  else
+    cls = sweep<false>(G, k.eps, e5, m5, n5, h5, b5, nullptr, oh, om, on, ob, od, ox);
   const uint32_t o = (uint32_t)j * (uint32_t)k.LW + (uint32_t)(i + 1);
   double* __restrict__ Lh = k.L;
   double* __restrict__ Lm = k.L + k.PL4;
@@ -711,8 +783,11 @@ __global__ void __launch_bounds__(XB) k2_xsweep(K2 k) {
 // quad shuffles, and thread q writes component q of the right-hand side.
 // Rows j0-1 and j1 give only the traces of the edges below row j0 and above
 // row j1 - 1.
-template <int S, bool HYD>
+template <int S, int SCH>
 __global__ void __launch_bounds__(256) k2_ysweep(K2 k, int rows) {
+  // SCH 0: special source term; 1: hydrostatic reconstruction; 2: without
+  // well-balancing (characteristic sweeps, -g h grad b, b kept by the limiter)
+  constexpr bool HYD = SCH == 1, NWB = SCH == 2;
   const State2& St = *k.st;
   if (St.done) return;
   __shared__ double sL[64][4][4];  // left traces of each column at point nu: h, hu, hv, b
@@ -784,7 +859,11 @@ __global__ void __launch_bounds__(256) k2_ysweep(K2 k, int rows) {
         x5[r] = Lx[o];
         e5[r] = h5[r] + b5[r];
       }
-      cl = sweep<true>(G, k.eps, e5, m5, n5, h5, b5, x5, oh, om, on, ob, od, ox);
+      if (NWB)
+        cl = sweep_char<1, true>(G, k.eps, g, dry, hbar, mbar, nbar, e5, m5, n5, b5, x5, oh, om,
+                                 on, ob, od, ox);
+      else
+        cl = sweep<true>(G, k.eps, e5, m5, n5, h5, b5, x5, oh, om, on, ob, od, ox);
     }
     double ix = 0.0, iy = 0.0;
     if (body && HYD) {
@@ -801,6 +880,13 @@ __global__ void __launch_bounds__(256) k2_ysweep(K2 k, int rows) {
       ix *= wq;
       iy = wq * hydro_source(g, oh[0] + ob[0], oh[1] + ob[1], oh[2] + ob[2], oh[3] + ob[3], ob[0],
                              ob[1], ob[2], ob[3]);
+    } else if (body && NWB) {
+      // -g h grad b at the 4 points of this abscissa (the unlimited values)
+#pragma unroll
+      for (int nu = 0; nu < 4; ++nu) {
+        ix += (wq * GLW[nu]) * (oh[nu] * ox[nu]);
+        iy += (wq * GLW[nu]) * (oh[nu] * od[nu]);
+      }
     } else if (body) {
 #pragma unroll
       for (int nu = 0; nu < 4; ++nu) {
@@ -834,13 +920,13 @@ __global__ void __launch_bounds__(256) k2_ysweep(K2 k, int rows) {
 #pragma unroll
       for (int nu = 0; nu < 4; ++nu) {
         double hh = oh[nu], mm = om[nu], nn = on[nu], bb = ob[nu];
-        limit_trace(p2, hbar, mbar, nbar, hh, mm, nn, bb);
+        limit_trace<NWB>(p2, hbar, mbar, nbar, hh, mm, nn, bb);
         dst[nu][0] = hh; dst[nu][1] = mm; dst[nu][2] = nn; dst[nu][3] = bb;
       }
     }
     // the bottom / top traces at point q limited across y
-    limit_trace(p1, hbar, mbar, nbar, oh[0], om[0], on[0], ob[0]);
-    limit_trace(p1, hbar, mbar, nbar, oh[3], om[3], on[3], ob[3]);
+    limit_trace<NWB>(p1, hbar, mbar, nbar, oh[0], om[0], on[0], ob[0]);
+    limit_trace<NWB>(p1, hbar, mbar, nbar, oh[3], om[3], on[3], ob[3]);
     // bottom edge (node jr) at point q: the cell below's top trace
     double Cy[4] = {0, 0, 0, 0}, Dy[4] = {0, 0, 0, 0}, B1y = 0.0, B2y = 0.0;
     double PLy = 0.0, PRy = 0.0;  // HYD: pressure corrections below / above the edge
@@ -902,7 +988,7 @@ __global__ void __launch_bounds__(256) k2_ysweep(K2 k, int rows) {
       if (own_col && jp >= j0) {
         const uint32_t cp = (uint32_t)q * (uint32_t)k.N + (uint32_t)i + (uint32_t)nx * (uint32_t)jp;
         double rc = Pc - Cyq;
-        if (q == 2) rc += HYD ? -PLy : 0.5 * g * B2y - g * etab_p * B1y;
+        if (q == 2 && !NWB) rc += HYD ? -PLy : 0.5 * g * B2y - g * etab_p * B1y;
         k.Rc[cp] = rc;
         k.Rd[cp] = Pd - Dyq;
       }
@@ -913,6 +999,9 @@ __global__ void __launch_bounds__(256) k2_ysweep(K2 k, int rows) {
       if (HYD) {
         if (q == 1) Pc += (PRx - PLr) - g * dys * ix;
         if (q == 2) Pc += PRy + dxs * iy;
+      } else if (NWB) {
+        if (q == 1) Pc += -g * area * ix;
+        if (q == 2) Pc += -g * area * iy;
       } else {
         if (q == 1) Pc += 0.5 * g * (B2r - B2x) - g * etab * (B1r - B1x) - g * area * ix;
         if (q == 2) Pc += -0.5 * g * B2y + g * etab * B1y - g * area * iy;
@@ -1139,9 +1228,11 @@ alew_status alew2d_run(alew2d_ctx* c, const alew2d_params* p, int64_t nx, int64_
   if ((p->bcx != ALEW_BC_PERIODIC && p->bcx != ALEW_BC_TRANSMISSIVE) ||
       (p->bcy != ALEW_BC_PERIODIC && p->bcy != ALEW_BC_TRANSMISSIVE))
     return fail2(ALEW_E_UNSUPPORTED, "2D boundaries: periodic or transmissive");
-  if (p->flags & ~ALEW_F_HYDROSTATIC)
-    return fail2(ALEW_E_UNSUPPORTED, "the only 2D flag is HYDROSTATIC");
-  const bool hyd = (p->flags & ALEW_F_HYDROSTATIC) != 0;
+  if (p->flags & ~(ALEW_F_HYDROSTATIC | ALEW_F_NONWB))
+    return fail2(ALEW_E_UNSUPPORTED, "the 2D flags are HYDROSTATIC and NONWB");
+  if ((p->flags & ALEW_F_HYDROSTATIC) && (p->flags & ALEW_F_NONWB))
+    return fail2(ALEW_E_ARG, "HYDROSTATIC and NONWB select different schemes");
+  const int sch = (p->flags & ALEW_F_HYDROSTATIC) ? 1 : (p->flags & ALEW_F_NONWB) ? 2 : 0;
   if (!std::isfinite(t0) || std::isnan(t_end) || max_steps < 0)
     return fail2(ALEW_E_ARG, "t0 finite, t_end not NaN and max_steps >= 0 required");
   K2 k{};
@@ -1199,20 +1290,32 @@ alew_status alew2d_run(alew2d_ctx* c, const alew2d_params* p, int64_t nx, int64_
       if (r == ALEW_OK) r = mark(kind, false);
     };
     timed_launch(0, [&] { hipLaunchKernelGGL(k2_kin, dim3(1), dim3(KB), 0, st, k); });
-    timed_launch(1, [&] { hipLaunchKernelGGL(k2_xsweep<0>, gx, dim3(XB), 0, st, k); });
-    timed_launch(2, [&] {
-      if (hyd) hipLaunchKernelGGL((k2_ysweep<0, true>), gy, dim3(256), 0, st, k, rows);
-      else hipLaunchKernelGGL((k2_ysweep<0, false>), gy, dim3(256), 0, st, k, rows);
+    timed_launch(1, [&] {
+      if (sch == 2) hipLaunchKernelGGL((k2_xsweep<0, 2>), gx, dim3(XB), 0, st, k);
+      else hipLaunchKernelGGL((k2_xsweep<0, 0>), gx, dim3(XB), 0, st, k);
     });
-    timed_launch(1, [&] { hipLaunchKernelGGL(k2_xsweep<1>, gx, dim3(XB), 0, st, k); });
     timed_launch(2, [&] {
-      if (hyd) hipLaunchKernelGGL((k2_ysweep<1, true>), gy, dim3(256), 0, st, k, rows);
-      else hipLaunchKernelGGL((k2_ysweep<1, false>), gy, dim3(256), 0, st, k, rows);
+      if (sch == 1) hipLaunchKernelGGL((k2_ysweep<0, 1>), gy, dim3(256), 0, st, k, rows);
+      else if (sch == 2) hipLaunchKernelGGL((k2_ysweep<0, 2>), gy, dim3(256), 0, st, k, rows);
+      else hipLaunchKernelGGL((k2_ysweep<0, 0>), gy, dim3(256), 0, st, k, rows);
     });
-    timed_launch(1, [&] { hipLaunchKernelGGL(k2_xsweep<2>, gx, dim3(XB), 0, st, k); });
+    timed_launch(1, [&] {
+      if (sch == 2) hipLaunchKernelGGL((k2_xsweep<1, 2>), gx, dim3(XB), 0, st, k);
+      else hipLaunchKernelGGL((k2_xsweep<1, 0>), gx, dim3(XB), 0, st, k);
+    });
     timed_launch(2, [&] {
-      if (hyd) hipLaunchKernelGGL((k2_ysweep<2, true>), gy, dim3(256), 0, st, k, rows);
-      else hipLaunchKernelGGL((k2_ysweep<2, false>), gy, dim3(256), 0, st, k, rows);
+      if (sch == 1) hipLaunchKernelGGL((k2_ysweep<1, 1>), gy, dim3(256), 0, st, k, rows);
+      else if (sch == 2) hipLaunchKernelGGL((k2_ysweep<1, 2>), gy, dim3(256), 0, st, k, rows);
+      else hipLaunchKernelGGL((k2_ysweep<1, 0>), gy, dim3(256), 0, st, k, rows);
+    });
+    timed_launch(1, [&] {
+      if (sch == 2) hipLaunchKernelGGL((k2_xsweep<2, 2>), gx, dim3(XB), 0, st, k);
+      else hipLaunchKernelGGL((k2_xsweep<2, 0>), gx, dim3(XB), 0, st, k);
+    });
+    timed_launch(2, [&] {
+      if (sch == 1) hipLaunchKernelGGL((k2_ysweep<2, 1>), gy, dim3(256), 0, st, k, rows);
+      else if (sch == 2) hipLaunchKernelGGL((k2_ysweep<2, 2>), gy, dim3(256), 0, st, k, rows);
+      else hipLaunchKernelGGL((k2_ysweep<2, 0>), gy, dim3(256), 0, st, k, rows);
     });
     timed_launch(3, [&] { hipLaunchKernelGGL(k2_fin, gc, dim3(256), 0, st, k); });
     return r;

@@ -334,9 +334,11 @@ def smooth_2d(n: int = 2048):
     return wl
 
 
-def dam_break_2d(nx: int = 200, ny: int | None = None, t_end: float = 1.75, amp=(0.03, 0.02)):
+def dam_break_2d(nx: int = 200, ny: int | None = None, t_end: float = 1.75, amp=(0.03, 0.02),
+                 h_out: float = 0.0):
     """Example 5.9, the circular dam break on [-100, 100]^2: b = 0, h = 10 for
-    r <= 60 and 0 outside, hu = hv = 0, transmissive; nodes moving per
+    r <= 60 and h_out outside (0: the example's dry bed), hu = hv = 0,
+    transmissive; nodes moving per
     direction in the tensor-product form of eq. (5.2):
     x = xi + amp[0] sin(2 pi xi / 200) sin(2 pi t / t_end),
     y = eta + amp[1] sin(2 pi eta / 200) sin(4 pi t / t_end).  The cells
@@ -345,7 +347,7 @@ def dam_break_2d(nx: int = 200, ny: int | None = None, t_end: float = 1.75, amp=
     # nodes and averages mirror-symmetric to the bit about both axes
     xi, yi = uniform_nodes(nx, -100.0, 100.0), uniform_nodes(ny, -100.0, 100.0)
     xi, yi = 0.5 * (xi - xi[::-1]), 0.5 * (yi - yi[::-1])
-    h = _disc_averages_2d(xi, yi, 60.0, 10.0)
+    h = h_out + _disc_averages_2d(xi, yi, 60.0, 10.0 - h_out)
     h = ((h + h[:, ::-1]) + (h[::-1, :] + h[::-1, ::-1])) * 0.25
     z = np.zeros_like(h)
     return dict(xi=xi, yi=yi, h=h, hu=z, hv=z.copy(), b=z.copy(), bc="transmissive", t_end=t_end,

@@ -27,14 +27,14 @@ def _t(a, dev):
     return torch.tensor(np.asarray(a), dtype=torch.float64, device=dev)
 
 
-def _pair(wl, cfl=0.6, eps=1e-6, bcy="periodic", hydro=False):
+def _pair(wl, cfl=0.6, eps=1e-6, bcy="periodic", hydro=False, nonwb=False):
     g = alew.params2(cfl=cfl, weno_eps=eps, Ax=wl["Ax"], kx=wl["kx"], omx=wl["omx"], Ay=wl["Ay"],
                      ky=wl["ky"], omy=wl["omy"], bcx="periodic", bcy=bcy,
-                     flags=alew.F_HYDROSTATIC if hydro else 0)
+                     flags=(alew.F_HYDROSTATIC if hydro else 0) | (alew.F_NONWB if nonwb else 0))
     o = O.params2(cfl=cfl, weno_eps=eps, Ax=wl["Ax"], kx=wl["kx"], omx=wl["omx"], Ay=wl["Ay"],
                   ky=wl["ky"], omy=wl["omy"], bcx=O.BC_PERIODIC,
                   bcy=O.BC_PERIODIC if bcy == "periodic" else O.BC_TRANSMISSIVE,
-                  flags=O.FLAG_HYDROSTATIC if hydro else 0)
+                  flags=(O.FLAG_HYDROSTATIC if hydro else 0) | (O.FLAG_NONWB if nonwb else 0))
     return g, o
 
 
@@ -193,13 +193,13 @@ def full_size():
     return W.smooth_2d(2048)
 
 
-@pytest.mark.parametrize("hydro", [False, True])
-def test_full_size_one_step_every_cell_against_oracle(dev, full_size, hydro):
+@pytest.mark.parametrize("scheme", ["special", "hydrostatic", "nonwb"])
+def test_full_size_one_step_every_cell_against_oracle(dev, full_size, scheme):
     """One step of the 2048 x 2048 workload in the launch configuration the
-    benchmark times: every cell equals the oracle's (special source term, and
-    the hydrostatic reconstruction)."""
+    benchmark times: every cell equals the oracle's (special source term, the
+    hydrostatic reconstruction, the scheme without well-balancing)."""
     wl = full_size
-    gp, op = _pair(wl, hydro=hydro)
+    gp, op = _pair(wl, hydro=scheme == "hydrostatic", nonwb=scheme == "nonwb")
     ctx = alew.Context2(2048, 2048)
     g, st = _gpu_run(ctx, gp, wl, dev, max_steps=1)
     r = _ora_run(op, wl, max_steps=1)
@@ -227,12 +227,13 @@ def test_full_size_hundred_steps_invariants(dev, full_size):
     assert sum(st.n_class) == 3 * 100 * 2048 * 2048
 
 
-def _dam_pair(wl, dry_eps=1e-6):
+def _dam_pair(wl, dry_eps=1e-6, nonwb=False):
     g = alew.params2(cfl=0.08, dry_eps=dry_eps, Ax=wl["Ax"], kx=wl["kx"], omx=wl["omx"],
                      Ay=wl["Ay"], ky=wl["ky"], omy=wl["omy"], bcx="transmissive",
-                     bcy="transmissive")
+                     bcy="transmissive", flags=alew.F_NONWB if nonwb else 0)
     o = O.params2(cfl=0.08, dry_eps=dry_eps, Ax=wl["Ax"], kx=wl["kx"], omx=wl["omx"], Ay=wl["Ay"],
-                  ky=wl["ky"], omy=wl["omy"], bcx=O.BC_TRANSMISSIVE, bcy=O.BC_TRANSMISSIVE)
+                  ky=wl["ky"], omy=wl["omy"], bcx=O.BC_TRANSMISSIVE, bcy=O.BC_TRANSMISSIVE,
+                  flags=O.FLAG_NONWB if nonwb else 0)
     return g, o
 
 
@@ -256,6 +257,41 @@ def test_circular_dam_break_with_the_limiter(dev, nx, ny, amp, t_end):
     assert list(st.n_class) == list(r["n_class"])
     _parity(g, r, f"dam {nx}x{ny}")
     assert -1e-11 <= g["h"].min() <= 1e-11
+
+
+def test_circular_dam_break_without_well_balancing(dev):
+    """Example 5.9 with the scheme the paper shows for it, without
+    well-balancing (characteristic sweeps, the limiter keeping the flat
+    bottom at zero), 64 x 64 to t = 1.75.  At the dry front the frame of a
+    cell whose mean depth is just above dry_eps has c = sqrt(g h) ~ 3e-3, so
+    its characteristic variables are ~ |u| eta / c, thousands of times the
+    values: the GPU's and the oracle's roundings (fused multiply-adds,
+    refined reciprocals) agree to 5e-15 after the first step and separate
+    to 3e-10 by the third, and the lagged step sizes then differ.  So: the
+    first step against the oracle cell by cell, then the run by properties
+    (min h within [-1e-11, 1e-11] as Table 5.10, b exactly zero, the limiter
+    acting, the step count within 5 % of the oracle's run).  The same scheme
+    on a wet bed (depth 1 outside the disc: c >= 3) equals the oracle over
+    the whole run."""
+    wl = W.dam_break_2d(64, 64, t_end=1.75)
+    gp, op = _dam_pair(wl, nonwb=True)
+    g1, st1 = _gpu_run(alew.Context2(64, 64), gp, wl, dev, max_steps=1)
+    r1 = _ora_run(op, wl, max_steps=1)
+    assert st1.status == 0 and r1["status"] == 0 and st1.n_limited == r1["n_limited"]
+    _parity(g1, r1, "dam nonwb, 1 step")
+    g, st = _gpu_run(alew.Context2(64, 64), gp, wl, dev, t_end=1.75)
+    r = _ora_run(op, wl, t_end=1.75)
+    assert st.status == 0 and r["status"] == 0 and abs(st.t - 1.75) < 1e-15
+    assert abs(st.steps - r["steps"]) <= 0.05 * r["steps"], (st.steps, r["steps"])
+    assert -1e-11 <= g["h"].min() <= 1e-11 and st.n_limited > 0
+    assert np.abs(g["b"]).max() == 0.0
+    wet = W.dam_break_2d(64, 64, t_end=1.75, h_out=1.0)
+    gp, op = _dam_pair(wet, nonwb=True)
+    g, st = _gpu_run(alew.Context2(64, 64), gp, wet, dev, t_end=1.75)
+    r = _ora_run(op, wet, t_end=1.75)
+    assert st.status == 0 and r["status"] == 0 and st.steps == r["steps"]
+    assert list(st.n_class) == list(r["n_class"])
+    _parity(g, r, "dam nonwb on a wet bed")
 
 
 def test_circular_dam_break_at_the_papers_resolution(dev):
@@ -283,8 +319,9 @@ def test_circular_dam_break_at_the_papers_resolution(dev):
     assert abs(st2.mass_b - st2.mass_b0) < 1e-9
 
 
-@pytest.mark.parametrize("hydro,table", [(False, "table5.8"), (True, "table5.7")])
-def test_fifth_order_against_table_5_8(dev, hydro, table):
+@pytest.mark.parametrize("hydro,nonwb,table", [(False, False, "table5.8"), (True, False, "table5.7"),
+                                               (False, True, "table5.6")])
+def test_fifth_order_against_table_5_8(dev, hydro, nonwb, table):
     """Example 5.6 to t = 0.05 on 100², 200², 400² and 800² moving cells at the
     CFL numbers of Table 5.8 (0.5, 0.4, 0.3, 0.2), against this scheme's own
     1600² run (CFL 0.2; the mesh is uniform again at t_end, so 2^k x 2^k fine
@@ -293,8 +330,10 @@ def test_fifth_order_against_table_5_8(dev, hydro, table):
     against another scheme's 1600² reference), and the orders reach fifth
     order: above 4.8 from 400² to 800² for all three (the paper: 5.03, 4.82,
     4.97), and within 0.25 of the printed h + b orders at every refinement.
-    The same for the hydrostatic reconstruction against Table 5.7 (same CFL
-    numbers; printed orders 5.04, 4.82, 4.97 at the fine end)."""
+    The same for the hydrostatic reconstruction against Table 5.7 and the
+    scheme without well-balancing against Table 5.6 on 100² ... 400² against
+    their own 800² runs (the suite's time: the printed orders from 200² to
+    400² are 4.72, 4.53, 4.72 and 4.71, 4.53, 4.72; above 4.4 is asked)."""
     paper = {}
     import os
     gold = os.path.join(os.path.dirname(__file__), "golden", "paper_tables.txt")
@@ -305,22 +344,26 @@ def test_fifth_order_against_table_5_8(dev, hydro, table):
 
     def run(n, cfl):
         wl = W.accuracy_2d(n)
-        gp, _ = _pair(wl, cfl=cfl, hydro=hydro)
+        gp, _ = _pair(wl, cfl=cfl, hydro=hydro, nonwb=nonwb)
         g, st = _gpu_run(alew.Context2(n, n), gp, wl, dev, t_end=wl["t_end"])
         assert st.status == 0 and abs(st.t - 0.05) < 1e-15
         return [g["h"] + g["b"], g["hu"], g["hv"]]
 
-    ref = run(1600, 0.2)
+    full = table == "table5.8"
+    nref = 1600 if full else 800
+    ladder = ((100, 0.5), (200, 0.4), (400, 0.3), (800, 0.2)) if full else \
+        ((100, 0.5), (200, 0.4), (400, 0.3))
+    ref = run(nref, 0.2)
     errs = {}
-    for n, cfl in ((100, 0.5), (200, 0.4), (400, 0.3), (800, 0.2)):
+    for n, cfl in ladder:
         got = run(n, cfl)
-        f = 1600 // n
+        f = nref // n
         errs[n] = [float(np.abs(a - r.reshape(n, f, n, f).mean(axis=(1, 3))).mean())
                    for a, r in zip(got, ref)]
         print(f"{n}^2: L1 errors {errs[n]} (printed {paper[n]})", flush=True)
         for k, (e, p) in enumerate(zip(errs[n], paper[n])):
             assert (0.75 < e / p < 1.25) if k != 1 else (1 / 3 < e / p < 3), (n, k, e, p)
-    ns = (100, 200, 400, 800)
+    ns = tuple(n for n, _ in ladder)
     for a, b in zip(ns[:-1], ns[1:]):
         o = [math.log2(x / y) for x, y in zip(errs[a], errs[b])]
         po = math.log2(paper[a][0] / paper[b][0])
@@ -328,18 +371,24 @@ def test_fifth_order_against_table_5_8(dev, hydro, table):
         assert abs(o[0] - po) < 0.25, (a, b, o, po)
         if a == 400:
             assert min(o) > 4.8, o
+        if a == 200 and not full:
+            assert min(o) > 4.4, o
 
 
+@pytest.mark.parametrize("scheme", ["hydrostatic", "nonwb"])
 @pytest.mark.parametrize("case", ["accuracy", "still_water", "ragged"])
-def test_hydrostatic_reconstruction_against_oracle(dev, case):
-    """The hydrostatic reconstruction (Sec. 4.1, flag HYDROSTATIC): Example 5.6
-    at 50 x 50 to t = 0.05 with the class of every cell at every stage,
-    Example 5.11 on 100 x 100 to t = 0.1 (still water at round-off, Table
-    5.12's hydrostatic row), and the ragged 130 x 37 grid with transmissive y
-    (40 steps): the oracle's steps, classes and state."""
+def test_hydrostatic_reconstruction_against_oracle(dev, case, scheme):
+    """The hydrostatic reconstruction (Sec. 4.1, flag HYDROSTATIC) and the
+    scheme without well-balancing (Sec. 3, flag NONWB): Example 5.6 at 50 x 50
+    to t = 0.05 with the class of every cell at every stage, Example 5.11 on
+    100 x 100 to t = 0.1 (still water at round-off with the hydrostatic
+    reconstruction, Table 5.12's hydrostatic row; Table 5.12's errors within
+    5 % without well-balancing), and the ragged 130 x 37 grid with transmissive
+    y (40 steps): the oracle's steps, classes and state."""
+    hyd, nwb = scheme == "hydrostatic", scheme == "nonwb"
     if case == "accuracy":
         wl = W.accuracy_2d(50)
-        gp, op = _pair(wl, hydro=True)
+        gp, op = _pair(wl, hydro=hyd, nonwb=nwb)
         ctx = alew.Context2(50, 50)
         g, st = _gpu_run(ctx, gp, wl, dev, record=True, t_end=wl["t_end"])
         r = _ora_run(op, wl, t_end=wl["t_end"], max_steps=1000, record_cls=True)
@@ -348,15 +397,20 @@ def test_hydrostatic_reconstruction_against_oracle(dev, case):
         assert cells == 0 and lower == 0
     elif case == "still_water":
         wl = W.still_water_2d(100)
-        gp, op = _pair(wl, hydro=True)
+        gp, op = _pair(wl, hydro=hyd, nonwb=nwb)
         ctx = alew.Context2(100, 100)
         g, st = _gpu_run(ctx, gp, wl, dev, t_end=wl["t_end"])
-        assert np.abs(g["h"] + g["b"] - 1.0).max() < 1e-13
-        assert np.abs(g["hu"]).max() < 1e-13 and np.abs(g["hv"]).max() < 1e-13
+        err = [np.abs(g["h"] + g["b"] - 1.0), np.abs(g["hu"]), np.abs(g["hv"])]
+        if hyd:
+            assert max(e.max() for e in err) < 1e-13
+        else:
+            printed = (1.27e-6, 3.63e-6, 3.52e-6, 2.01e-5, 2.40e-5, 2.30e-5)
+            got = [e.mean() for e in err] + [e.max() for e in err]
+            assert all(abs(a / b - 1.0) < 0.05 for a, b in zip(got, printed)), got
         r = _ora_run(op, wl, t_end=wl["t_end"])
     else:
         wl = _ragged(130, 37)
-        gp, op = _pair(wl, cfl=0.5, bcy="transmissive", hydro=True)
+        gp, op = _pair(wl, cfl=0.5, bcy="transmissive", hydro=hyd, nonwb=nwb)
         ctx = alew.Context2(130, 37)
         g, st = _gpu_run(ctx, gp, wl, dev, max_steps=40)
         r = _ora_run(op, wl, max_steps=40)
@@ -366,10 +420,12 @@ def test_hydrostatic_reconstruction_against_oracle(dev, case):
 
 
 def test_unknown_2d_flag_is_refused(dev):
-    """A 2D flag other than HYDROSTATIC is ALEW_E_UNSUPPORTED before any work."""
+    """A 2D flag other than HYDROSTATIC and NONWB is ALEW_E_UNSUPPORTED, and the
+    two together ALEW_E_ARG, before any work."""
     wl = W.accuracy_2d(16)
-    gp, _ = _pair(wl)
-    gp.flags = alew.F_HYDROSTATIC | 1
-    ctx = alew.Context2(16, 16)
-    with pytest.raises(Exception):
-        _gpu_run(ctx, gp, wl, dev, max_steps=1)
+    for fl in (alew.F_HYDROSTATIC | 1, alew.F_HYDROSTATIC | alew.F_NONWB):
+        gp, _ = _pair(wl)
+        gp.flags = fl
+        ctx = alew.Context2(16, 16)
+        with pytest.raises(Exception):
+            _gpu_run(ctx, gp, wl, dev, max_steps=1)

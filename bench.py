@@ -625,27 +625,35 @@ def tensor2d_leg(dev, n, steps, warmup):
         ms, nl = ctx.kernel_timing(q)
         split[nm] = dict(launches=nl, launch_ms=round(ms / max(1, nl), 4), ms_per_step=round(ms / 3, 4))
     dom = max(names, key=lambda k: split[k]["ms_per_step"])
-    # the same workload with the hydrostatic reconstruction (Sec. 4.1): 20 steps
-    # after 2 untimed ones, and the y-sweep's launch time from a 3-step pass
-    ph = alew.params2(cfl=0.6, Ax=wl["Ax"], kx=wl["kx"], omx=wl["omx"], Ay=wl["Ay"], ky=wl["ky"],
-                      omy=wl["omy"], flags=alew.F_HYDROSTATIC)
-    go(fresh(), 2, ph)
-    Th = fresh()
-    torch.cuda.synchronize()
-    a = time.perf_counter()
-    sth = go(Th, 20, ph)
-    torch.cuda.synchronize()
-    wall_h = time.perf_counter() - a
-    assert sth.status == 0 and sth.steps == 20, "2D hydrostatic run did not complete"
-    del Th
-    ctx.set_kernel_timing(True)
-    go(fresh(), 3, ph)
-    torch.cuda.synchronize()
-    ctx.set_kernel_timing(False)
-    yms, yn = ctx.kernel_timing(2)
-    hydro = dict(steps=20, value=3.0 * N * 20 / wall_h, unit="cell-updates/s",
-                 ms_per_step=round(wall_h * 1e3 / 20, 4),
-                 ysweep_launch_ms=round(yms / max(1, yn), 4))
+    def variant(flags, name):
+        """The same workload with another scheme: 20 steps after 2 untimed ones,
+        and the x- and y-sweeps' launch times from a 3-step pass."""
+        pv = alew.params2(cfl=0.6, Ax=wl["Ax"], kx=wl["kx"], omx=wl["omx"], Ay=wl["Ay"],
+                          ky=wl["ky"], omy=wl["omy"], flags=flags)
+        go(fresh(), 2, pv)
+        Tv = fresh()
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        stv = go(Tv, 20, pv)
+        torch.cuda.synchronize()
+        wall_v = time.perf_counter() - a
+        assert stv.status == 0 and stv.steps == 20, f"2D {name} run did not complete"
+        del Tv
+        ctx.set_kernel_timing(True)
+        go(fresh(), 3, pv)
+        torch.cuda.synchronize()
+        ctx.set_kernel_timing(False)
+        xms, xn = ctx.kernel_timing(1)
+        yms, yn = ctx.kernel_timing(2)
+        return dict(steps=20, value=3.0 * N * 20 / wall_v, unit="cell-updates/s",
+                    ms_per_step=round(wall_v * 1e3 / 20, 4),
+                    xsweep_launch_ms=round(xms / max(1, xn), 4),
+                    ysweep_launch_ms=round(yms / max(1, yn), 4))
+
+    # the hydrostatic reconstruction (Sec. 4.1) and the scheme without
+    # well-balancing (Sec. 3, characteristic sweeps)
+    hydro = variant(alew.F_HYDROSTATIC, "hydrostatic")
+    nonwb = variant(alew.F_NONWB, "nonwb")
     roof = dict(bound="alu", kernel=dom, achieved=None, peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
                 frac=None, traffic=None, launch_ms=split[dom]["launch_ms"],
                 timing="HIP events on the library stream around each launch")
@@ -672,7 +680,8 @@ def tensor2d_leg(dev, n, steps, warmup):
                 steps=steps, value=3.0 * N * steps / wall, unit="cell-updates/s",
                 ms_per_step=round(wall * 1e3 / steps, 4),
                 event_ms_per_step=round(ev_ms / steps, 4), t_end=st.t,
-                n_class=list(st.n_class), kernels=split, roofline=roof, hydrostatic=hydro)
+                n_class=list(st.n_class), kernels=split, roofline=roof, hydrostatic=hydro,
+                nonwb=nonwb)
 
 
 def main():

@@ -1,7 +1,8 @@
 """The oracle built with AddressSanitizer and UndefinedBehaviorSanitizer (host
 code only; g++), driven through its Python binding in a subprocess on small
-cases of every scheme, the tape adjoint and the 2D scheme: no invalid access,
-overflow or undefined behaviour is reported."""
+cases of every scheme, the jump-aligned mesh with the projected step, the tape
+adjoint and the 2D scheme in its three forms (a dry bed included): no invalid
+access, overflow or undefined behaviour is reported."""
 import os
 import subprocess
 import sys
@@ -38,12 +39,24 @@ P = O.params(bc=O.BC_PERIODIC, mesh=O.MESH_SINE, mesh_A=0.05, mesh_k=1.0, mesh_o
 gx = np.array([0.2, 0.5, 0.8])
 out = O.adjoint(P, wl["h"], wl["hu"], wl["b"], wl["x"], wl["xi"], [1e-3] * 3, gx, np.ones(3))
 assert out[-1] == 0
+wd = W.dam_break_bump_1d(24, 15.0)
+P = O.params(bc=O.BC_TRANSMISSIVE, mesh=O.MESH_ALIGNED, mesh_A=1.0, mesh_k=0.0,
+             mesh_omega=wd["mesh_omega"], bottom=O.BOTTOM_STEP, bottom_p=wd["bottom_p"])
+assert O.run(P, wd["h"], wd["hu"], wd["b"], wd["x"], wd["xi"], max_steps=3)["status"] == 0
 w2 = W.accuracy_2d(8)
-P2 = O.params2(Ax=w2["Ax"], kx=1.0, omx=w2["omx"], Ay=w2["Ay"], ky=1.0, omy=w2["omy"],
-               bcy=O.BC_TRANSMISSIVE)
-r2 = O.run2(P2, w2["h"], w2["hu"], w2["hv"], w2["b"], w2["xi"], w2["yi"], w2["xi"], w2["yi"],
-            max_steps=2, record_cls=True)
-assert r2["status"] == 0
+for fl in (0, O.FLAG_HYDROSTATIC, O.FLAG_NONWB):
+    P2 = O.params2(Ax=w2["Ax"], kx=1.0, omx=w2["omx"], Ay=w2["Ay"], ky=1.0, omy=w2["omy"],
+                   bcy=O.BC_TRANSMISSIVE, flags=fl)
+    r2 = O.run2(P2, w2["h"], w2["hu"], w2["hv"], w2["b"], w2["xi"], w2["yi"], w2["xi"], w2["yi"],
+                max_steps=2, record_cls=True)
+    assert r2["status"] == 0, (fl, r2["status"])
+wdb = W.dam_break_2d(8, 8, t_end=1.75)
+P2 = O.params2(cfl=0.08, dry_eps=1e-6, Ax=wdb["Ax"], kx=wdb["kx"], omx=wdb["omx"], Ay=wdb["Ay"],
+               ky=wdb["ky"], omy=wdb["omy"], bcx=O.BC_TRANSMISSIVE, bcy=O.BC_TRANSMISSIVE,
+               flags=O.FLAG_NONWB)
+r2 = O.run2(P2, wdb["h"], wdb["hu"], wdb["hv"], wdb["b"], wdb["xi"], wdb["yi"], wdb["xi"],
+            wdb["yi"], max_steps=3)
+assert r2["status"] == 0, r2["status"]
 print("sanitized oracle ok")
 '''
 

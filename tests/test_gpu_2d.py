@@ -208,17 +208,18 @@ def test_full_size_one_step_every_cell_against_oracle(dev, full_size, scheme):
     _parity(g, r, "2048^2")
 
 
-def test_full_size_hundred_steps_invariants(dev, full_size):
-    """100 steps at 2048 x 2048: finite, mass of eta and of b conserved to
-    round-off, nodes on the prescribed maps at the final time."""
+@pytest.mark.parametrize("scheme", ["special", "hydrostatic", "nonwb"])
+def test_full_size_hundred_steps_invariants(dev, full_size, scheme):
+    """100 steps at 2048 x 2048 with each scheme: finite, mass of eta and of b
+    conserved to round-off, nodes on the prescribed maps at the final time."""
     wl = full_size
-    gp, _ = _pair(wl)
+    gp, _ = _pair(wl, hydro=scheme == "hydrostatic", nonwb=scheme == "nonwb")
     ctx = alew.Context2(2048, 2048)
     g, st = _gpu_run(ctx, gp, wl, dev, max_steps=100)
     assert st.status == 0 and st.steps == 100
     ms = ctx.last_timing()
-    print(f"2048^2 x 100 steps: {ms:.1f} ms, {3 * 100 * 2048 * 2048 / (ms * 1e-3) / 1e9:.2f} "
-          "G cell-stage updates/s")
+    print(f"2048^2 x 100 steps ({scheme}): {ms:.1f} ms, "
+          f"{3 * 100 * 2048 * 2048 / (ms * 1e-3) / 1e9:.2f} G cell-stage updates/s")
     assert all(np.isfinite(g[k]).all() for k in ("h", "hu", "hv", "b"))
     assert abs(st.mass - st.mass0) < 1e-13 * abs(st.mass0)
     assert abs(st.mass_b - st.mass_b0) < 1e-12

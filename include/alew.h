@@ -2,7 +2,9 @@
  * alew.h -- C ABI of the MI355X (gfx950) library for the 1D well-balanced
  * ALE-WENO hybrid finite-volume scheme of Zhang, Xia & Xu, "Structure-preserving
  * finite volume arbitrary Lagrangian-Eulerian WENO schemes for the shallow water
- * equations" (special source-term variant, Sec. 4.2).
+ * equations" (special source-term variant, Sec. 4.2; the hydrostatic
+ * reconstruction of Sec. 4.1 and the scheme of Sec. 3 without well-balancing
+ * by flag), and its 2D tensor-product extension (alew2d_*, below).
  *
  * One time step is the modified SSP-RK3 of eq. (3.14) with the width recurrence
  * of eq. (3.15).  Each stage evaluates the semi-discrete right-hand side
@@ -333,9 +335,11 @@ alew_status alew_kernel_timing(const alew_ctx* ctx, int which, double* ms, int64
                                double* cells);
 
 /* ------------------------------------------------------------------------
- * 2D extension: the special source-term scheme (Sec. 2-4 in two dimensions:
- * eq. (3.11)-(3.15) with the 2D flux, eq. (4.7)-(4.10) with the 4 x 4
- * Gauss-Lobatto rule on the cell and 4 Gauss-Lobatto points per edge) on a
+ * 2D extension: the special source-term scheme by default (Sec. 2-4 in two
+ * dimensions: eq. (3.11)-(3.15) with the 2D flux, eq. (4.7)-(4.10) with the
+ * 4 x 4 Gauss-Lobatto rule on the cell and 4 Gauss-Lobatto points per edge),
+ * the hydrostatic reconstruction or the scheme without well-balancing by flag
+ * (see alew2d_params.flags below), on a
  * tensor-product moving mesh of rectangles: node i of the x-direction at
  * x_i(t) = xi_i + Ax sin(2 pi kx xi_i) sin(omx t), node j of the y-direction at
  * y_j(t) = yi_j + Ay sin(2 pi ky yi_j) sin(omy t); the node speeds of a step

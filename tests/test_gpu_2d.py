@@ -430,3 +430,66 @@ def test_unknown_2d_flag_is_refused(dev):
         ctx = alew.Context2(16, 16)
         with pytest.raises(Exception):
             _gpu_run(ctx, gp, wl, dev, max_steps=1)
+
+
+def _basin_pair(w, scheme):
+    fl_g = {"special": 0, "hydrostatic": alew.F_HYDROSTATIC, "nonwb": alew.F_NONWB}[scheme]
+    fl_o = {"special": 0, "hydrostatic": O.FLAG_HYDROSTATIC, "nonwb": O.FLAG_NONWB}[scheme]
+    g = alew.params2(cfl=w["cfl"], dry_eps=w["dry_eps"], Ax=w["Ax"], kx=w["kx"], omx=w["omx"],
+                     Ay=w["Ay"], ky=w["ky"], omy=w["omy"], bcx="transmissive", bcy="transmissive",
+                     flags=fl_g)
+    o = O.params2(cfl=w["cfl"], dry_eps=w["dry_eps"], Ax=w["Ax"], kx=w["kx"], omx=w["omx"],
+                  Ay=w["Ay"], ky=w["ky"], omy=w["omy"], bcx=O.BC_TRANSMISSIVE,
+                  bcy=O.BC_TRANSMISSIVE, flags=fl_o)
+    return g, o
+
+
+@pytest.mark.parametrize("scheme", ["special", "hydrostatic", "nonwb"])
+def test_parabolic_basin_example_5_10(dev, scheme):
+    """Example 5.10 (moving shoreline over the parabolic bottom, exact solution
+    of period T) with each scheme.  40 x 40 for 50 steps against the oracle
+    cell by cell (limited cells, classes, state; beyond that the thin shoreline
+    layer amplifies the two sides' rounding tenfold or more per 50 steps, one
+    limiter decision at its threshold included); 100 x 100, the paper's
+    resolution, over one period by properties at Table 5.11's times T/6, T/2,
+    3T/4, T: the depth stays non-negative (the table prints minima near
+    1e-11), the L1 error of h against the exact solution stays below 2 %
+    (measured 0.2-1.1 %), and the water volume is conserved to round-off (1e-10
+    relative after the period's ~2400 steps)."""
+    w4 = W.parabolic_basin_2d(40)
+    gp, op = _basin_pair(w4, scheme)
+    g, st = _gpu_run(alew.Context2(40, 40), gp, w4, dev, max_steps=50)
+    r = _ora_run(op, w4, max_steps=50)
+    assert st.status == 0 and r["status"] == 0 and r["n_limited"] > 0
+    if scheme == "nonwb":
+        # the characteristic frames round differently on the two sides, and at the
+        # shoreline some cells sit at the limiter's threshold (m within rounding of
+        # eps, Phi within rounding of 1): their count may differ (19 of 178,768
+        # measured), their effect on the state not (the state below at 1e-11)
+        assert abs(st.n_limited - r["n_limited"]) <= 1e-3 * r["n_limited"]
+    else:
+        assert st.n_limited == r["n_limited"]
+    assert list(st.n_class) == list(r["n_class"])
+    _parity(g, r, f"basin {scheme}")
+    w = W.parabolic_basin_2d(100)
+    gp, _ = _basin_pair(w, scheme)
+    ctx = alew.Context2(100, 100)
+    T = {k: _t(w[k], dev) for k in ("h", "hu", "hv", "b", "xi", "yi")}
+    x, y = T["xi"].clone(), T["yi"].clone()
+    area0 = np.outer(np.diff(w["yi"]), np.diff(w["xi"]))
+    vol0 = float((w["h"] * area0).sum())
+    t0 = 0.0
+    for frac in (1 / 6, 1 / 2, 3 / 4, 1.0):
+        st = ctx.run(gp, T["h"], T["hu"], T["hv"], T["b"], x, y, T["xi"], T["yi"], t0=t0,
+                     t_end=frac * w["T"])
+        torch.cuda.synchronize()
+        assert st.status == 0 and abs(st.t - frac * w["T"]) < 1e-9
+        t0 = st.t
+        h, xs, ys = T["h"].cpu().numpy(), x.cpu().numpy(), y.cpu().numpy()
+        area = np.outer(np.diff(ys), np.diff(xs))
+        ex = W.parabolic_basin_exact_2d(xs, ys, st.t)
+        l1 = float((np.abs(h - ex) * area).sum() / (ex * area).sum())
+        print(f"basin {scheme} t = {frac:.3f} T: min h {h.min():.2e}, L1 {l1:.2e}", flush=True)
+        assert h.min() >= -1e-11 and l1 < 0.02, (frac, h.min(), l1)
+        # round-off of the sums over ~7000 stage updates of 10^4 cells (6e-12 measured at T)
+        assert abs(float((h * area).sum()) - vol0) < 1e-10 * vol0

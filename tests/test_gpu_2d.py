@@ -493,3 +493,20 @@ def test_parabolic_basin_example_5_10(dev, scheme):
         assert h.min() >= -1e-11 and l1 < 0.02, (frac, h.min(), l1)
         # round-off of the sums over ~7000 stage updates of 10^4 cells (6e-12 measured at T)
         assert abs(float((h * area).sum()) - vol0) < 1e-10 * vol0
+
+
+@pytest.mark.parametrize("scheme", ["special", "hydrostatic", "nonwb"])
+@pytest.mark.parametrize("nx,ny,bcy", [(5, 5, "periodic"), (5, 9, "transmissive"),
+                                       (63, 5, "periodic"), (64, 6, "transmissive")])
+def test_smallest_grids_every_scheme(dev, scheme, nx, ny, bcy):
+    """The smallest grids the entry point takes (5 cells a direction: fewer than
+    a stencil's worth of distinct neighbours with periodic wrap, a single row
+    chunk) and strips one or two columns past a strip's 62 owned columns, with
+    each scheme: 10 steps equal the oracle's (classes, limited cells, state)."""
+    wl = _ragged(nx, ny)
+    gp, op = _pair(wl, cfl=0.5, bcy=bcy, hydro=scheme == "hydrostatic", nonwb=scheme == "nonwb")
+    g, st = _gpu_run(alew.Context2(nx, ny), gp, wl, dev, max_steps=10)
+    r = _ora_run(op, wl, max_steps=10)
+    assert st.status == 0 and r["status"] == 0 and st.steps == r["steps"] == 10
+    assert list(st.n_class) == list(r["n_class"]) and st.n_limited == r["n_limited"]
+    _parity(g, r, f"{scheme} {nx}x{ny}")

@@ -384,6 +384,8 @@ typedef struct {
   double Ay, ky, omy;               /* y-node map                                  */
   int32_t bcx, bcy;                 /* ALEW_BC_PERIODIC or ALEW_BC_TRANSMISSIVE    */
   int32_t flags, pad;               /* 0, ALEW_F_HYDROSTATIC or ALEW_F_NONWB        */
+  double Vx, Vy;                    /* uniform node translation: x_i(t) adds Vx t,
+                                       y_j(t) adds Vy t (Example 5.7's w = (1, 0)) */
 } alew2d_params;
 
 typedef struct {

@@ -60,6 +60,7 @@ class Params2(C.Structure):
         ("Ax", C.c_double), ("kx", C.c_double), ("omx", C.c_double),
         ("Ay", C.c_double), ("ky", C.c_double), ("omy", C.c_double),
         ("bcx", C.c_int32), ("bcy", C.c_int32), ("flags", C.c_int32), ("pad", C.c_int32),
+        ("Vx", C.c_double), ("Vy", C.c_double),
     ]
 
 
@@ -276,10 +277,12 @@ def adjoint(P: Params, h0, hu0, b0, x0, xi, dts, gauge_x, gauge_bar, t0=0.0):
 # 2D tensor-product extension
 # ---------------------------------------------------------------------------
 def params2(g=9.812, cfl=0.6, weno_eps=1e-6, dry_eps=1e-8, Ax=0.02, kx=1.0, omx=np.pi, Ay=0.02,
-            ky=1.0, omy=np.pi, bcx=BC_PERIODIC, bcy=BC_PERIODIC, flags=0) -> Params2:
+            ky=1.0, omy=np.pi, bcx=BC_PERIODIC, bcy=BC_PERIODIC, flags=0, Vx=0.0,
+            Vy=0.0) -> Params2:
     """2D scheme constants; flags: 0 (special source term, Sec. 4.2) or
     FLAG_HYDROSTATIC (hydrostatic reconstruction, Sec. 4.1, R31)."""
-    return Params2(g, cfl, weno_eps, dry_eps, Ax, kx, omx, Ay, ky, omy, bcx, bcy, int(flags), 0)
+    return Params2(g, cfl, weno_eps, dry_eps, Ax, kx, omx, Ay, ky, omy, bcx, bcy, int(flags), 0,
+                   float(Vx), float(Vy))
 
 
 def sweep2(widths5, e5, mx5, my5, h5, b5, dx, eps=1e-6, ext5=None):

@@ -163,6 +163,9 @@
  *      4 x 4 Gauss-Lobatto rule on the unlimited values (b_x, b_y the
  *      derivatives of b's reconstructions, R12); the limiter keeps the bottom
  *      traces (as R22).
+ *  R34 2D translation (Example 5.7): the node maps take a uniform velocity
+ *      as well, X = xi + Vx t + Ax sin(2 pi kx xi) sin(omx t) (y likewise);
+ *      the node speeds are the chords, Vx plus the sine part's.
  *  R30 MESH_ALIGNED: the quartic map of eq. (5.14) (Example 5.5), the map of
  *      eq. (5.1) times (xi - p1)(xi - p2) / (xmax - xmin)^2 with p1, p2 the
  *      step bottom's jump points bottom_p[1], bottom_p[2]: a node placed on a
@@ -1211,6 +1214,7 @@ struct Params2 {
   double g, cfl, weno_eps, dry_eps;
   double Ax, kx, omx, Ay, ky, omy;
   int32_t bcx, bcy, flags, pad;
+  double Vx, Vy;  /* a uniform translation of the nodes (R34) */
 };
 
 /* One sweep: 5 cells along a direction (widths wid), indicator variables
@@ -1697,8 +1701,8 @@ static int step2(const Params2& P, int nx, int ny, double* eta, double* mx, doub
   const size_t N = (size_t)nx * ny;
   std::vector<double> wx(nx + 1), wy(ny + 1);
   const double fx = chord2(P.Ax, P.omx, t, dt), fy = chord2(P.Ay, P.omy, t, dt);
-  for (int i = 0; i <= nx; ++i) wx[i] = P.Ax * std::sin(2.0 * M_PI * P.kx * xi[i]) * fx;
-  for (int j = 0; j <= ny; ++j) wy[j] = P.Ay * std::sin(2.0 * M_PI * P.ky * yi[j]) * fy;
+  for (int i = 0; i <= nx; ++i) wx[i] = P.Vx + P.Ax * std::sin(2.0 * M_PI * P.kx * xi[i]) * fx;
+  for (int j = 0; j <= ny; ++j) wy[j] = P.Vy + P.Ay * std::sin(2.0 * M_PI * P.ky * yi[j]) * fy;
   if (P.bcx == BC_PERIODIC) wx[nx] = wx[0];
   if (P.bcy == BC_PERIODIC) wy[ny] = wy[0];
   std::vector<double> dx0(nx), dy0(ny), dwx(nx), dwy(ny);
@@ -1768,9 +1772,9 @@ static double cfl_dt2(const Params2& P, int nx, int ny, const double* eta, const
   }
   double Wx = 0.0, Wy = 0.0;
   for (int i = 0; i <= nx; ++i)
-    Wx = std::max(Wx, std::fabs(P.Ax * P.omx * std::cos(P.omx * t) * std::sin(2.0 * M_PI * P.kx * xi[i])));
+    Wx = std::max(Wx, std::fabs(P.Vx + P.Ax * P.omx * std::cos(P.omx * t) * std::sin(2.0 * M_PI * P.kx * xi[i])));
   for (int j = 0; j <= ny; ++j)
-    Wy = std::max(Wy, std::fabs(P.Ay * P.omy * std::cos(P.omy * t) * std::sin(2.0 * M_PI * P.ky * yi[j])));
+    Wy = std::max(Wy, std::fabs(P.Vy + P.Ay * P.omy * std::cos(P.omy * t) * std::sin(2.0 * M_PI * P.ky * yi[j])));
   smax = std::max(smax, alpha_prev);
   return P.cfl / ((smax + Wx) / dxmin + (smax + Wy) / dymin);
 }

@@ -65,6 +65,7 @@ class Params2(C.Structure):
         ("Ax", C.c_double), ("kx", C.c_double), ("omx", C.c_double),
         ("Ay", C.c_double), ("ky", C.c_double), ("omy", C.c_double),
         ("bcx", C.c_int32), ("bcy", C.c_int32), ("flags", C.c_int32), ("pad", C.c_int32),
+        ("Vx", C.c_double), ("Vy", C.c_double),
     ]
 
 
@@ -353,12 +354,12 @@ def step_noalloc(p: Params, h, hu, b, x, xi=None, w=None, t=0.0, dt=0.0, t_end=0
 
 def params2(g=9.812, cfl=0.6, weno_eps=1e-6, dry_eps=1e-8, Ax=0.02, kx=1.0,
             omx=3.141592653589793, Ay=0.02, ky=1.0, omy=3.141592653589793, bcx="periodic",
-            bcy="periodic", flags=0) -> Params2:
+            bcy="periodic", flags=0, Vx=0.0, Vy=0.0) -> Params2:
     """flags: 0 (special source term), F_HYDROSTATIC (hydrostatic reconstruction)
     or F_NONWB (without well-balancing, characteristic sweeps)."""
     bc = lambda v: BC[v] if isinstance(v, str) else int(v)
     return Params2(g, cfl, weno_eps, dry_eps, Ax, kx, omx, Ay, ky, omy, bc(bcx), bc(bcy),
-                   int(flags), 0)
+                   int(flags), 0, float(Vx), float(Vy))
 
 
 class Context2:

@@ -76,6 +76,7 @@ struct State2 {
 struct K2 {
   double g, cfl, eps, dry;
   double Ax, kx, omx, Ay, ky, omy;
+  double Vx, Vy;  // uniform node translation
   int32_t bcx, bcy, nx, ny;
   int64_t N, LW, PL4;  // cells; row length of the line-value planes, 4 x their cells
   double* qa;         // [4][N] step state (eta, hu, hv, b)
@@ -578,8 +579,8 @@ __global__ void __launch_bounds__(KB) k2_kin(K2 k) {
   for (int i = tid; i < nx; i += KB) dxmin = fmin(dxmin, k.x[i + 1] - k.x[i]);
   for (int j = tid; j < ny; j += KB) dymin = fmin(dymin, k.y[j + 1] - k.y[j]);
   const double cx = k.Ax * k.omx * cos(k.omx * t), cy = k.Ay * k.omy * cos(k.omy * t);
-  for (int i = tid; i <= nx; i += KB) Wx = fmax(Wx, fabs(cx * sin(TP * k.kx * k.xi[i])));
-  for (int j = tid; j <= ny; j += KB) Wy = fmax(Wy, fabs(cy * sin(TP * k.ky * k.yi[j])));
+  for (int i = tid; i <= nx; i += KB) Wx = fmax(Wx, fabs(k.Vx + cx * sin(TP * k.kx * k.xi[i])));
+  for (int j = tid; j <= ny; j += KB) Wy = fmax(Wy, fabs(k.Vy + cy * sin(TP * k.ky * k.yi[j])));
   {
     double v[5] = {dxmin, dymin, Wx, Wy, smax};
     const int op[5] = {1, 1, 0, 0, 0};
@@ -607,8 +608,8 @@ __global__ void __launch_bounds__(KB) k2_kin(K2 k) {
   // chord of the map's time factor over [t, t + dt]
   const double fx = 2.0 * cos(k.omx * (t + 0.5 * dt)) * sin(0.5 * k.omx * dt) / dt;
   const double fy = 2.0 * cos(k.omy * (t + 0.5 * dt)) * sin(0.5 * k.omy * dt) / dt;
-  for (int i = tid; i <= nx; i += KB) k.wx[i] = k.Ax * sin(TP * k.kx * k.xi[i]) * fx;
-  for (int j = tid; j <= ny; j += KB) k.wy[j] = k.Ay * sin(TP * k.ky * k.yi[j]) * fy;
+  for (int i = tid; i <= nx; i += KB) k.wx[i] = k.Vx + k.Ax * sin(TP * k.kx * k.xi[i]) * fx;
+  for (int j = tid; j <= ny; j += KB) k.wy[j] = k.Vy + k.Ay * sin(TP * k.ky * k.yi[j]) * fy;
   __syncthreads();
   if (tid == 0) {
     if (k.bcx == BC_PERIODIC) k.wx[nx] = k.wx[0];
@@ -1233,11 +1234,14 @@ alew_status alew2d_run(alew2d_ctx* c, const alew2d_params* p, int64_t nx, int64_
   if ((p->flags & ALEW_F_HYDROSTATIC) && (p->flags & ALEW_F_NONWB))
     return fail2(ALEW_E_ARG, "HYDROSTATIC and NONWB select different schemes");
   const int sch = (p->flags & ALEW_F_HYDROSTATIC) ? 1 : (p->flags & ALEW_F_NONWB) ? 2 : 0;
+  if (!std::isfinite(p->Vx) || !std::isfinite(p->Vy))
+    return fail2(ALEW_E_ARG, "the node translation Vx, Vy must be finite");
   if (!std::isfinite(t0) || std::isnan(t_end) || max_steps < 0)
     return fail2(ALEW_E_ARG, "t0 finite, t_end not NaN and max_steps >= 0 required");
   K2 k{};
   k.g = p->g; k.cfl = p->cfl; k.eps = p->weno_eps; k.dry = p->dry_eps;
   k.Ax = p->Ax; k.kx = p->kx; k.omx = p->omx; k.Ay = p->Ay; k.ky = p->ky; k.omy = p->omy;
+  k.Vx = p->Vx; k.Vy = p->Vy;
   k.bcx = p->bcx; k.bcy = p->bcy; k.nx = (int32_t)nx; k.ny = (int32_t)ny;
   k.N = nx * ny; k.LW = nx + 2; k.PL4 = 4 * (nx + 2) * ny;
   k.qa = c->qa; k.qs0 = c->qs0; k.qs1 = c->qs1; k.L = c->L; k.xcls = c->xcls; k.Rc = c->Rc;

@@ -355,6 +355,71 @@ def dam_break_2d(nx: int = 200, ny: int | None = None, t_end: float = 1.75, amp=
                 omy=4 * math.pi / t_end)
 
 
+def vortex_2d(refine: int = 1, moving: bool = True, t_end: float = 2.0):
+    """Example 5.7 (a quasi-stationary vortex carried at 1 m/s) on [0,4] x [0,2],
+    periodic, b = 0: inside r_m = 0.45 of (1, 1) the tangential speed v_r(r) of
+    the example and h = 1 - (vmax s)^2 / g exp(1 / (r^2 - r_m^2)) (in balance:
+    g h' = v_r^2 / r), vmax = 0.5; u = 1 - v_r (y - 1) / r, v = v_r (x - 1) / r
+    (a rotation about the centre: the example's (y - 2) and the sign of its v
+    read as typos).  moving: the piecewise-uniform 110 x 70 mesh of eq. (5.17)-
+    (5.18) (the last x segment 1.5 + 0.05 (i - 60), the example's (i - 1.5) read
+    as a typo), translated at w = (1, 0) (eq. (5.19)); else uniform 110 x 70.
+    refine = 2 halves every cell (220 x 140).  The exact solution is the initial
+    vortex moved by t: on the moving mesh the initial cell averages themselves."""
+    g, vmax, rm = 9.812, 0.5, 0.45
+    rvm = 0.5 * math.sqrt(-2.0 + 2.0 * math.sqrt(1.0 + 4.0 * rm ** 4))
+    s = abs(rvm ** 2 - rm ** 2) / (rvm * math.sqrt(2.0 * math.exp(1.0 / (rvm ** 2 - rm ** 2))))
+
+    def fields(x, y, cx):
+        dx, dy = x - cx, y - 1.0
+        r2 = dx * dx + dy * dy
+        inside = r2 < rm * rm
+        e = np.where(inside, np.exp(1.0 / np.where(inside, r2 - rm * rm, -1.0)), 0.0)
+        h = 1.0 - (vmax * s) ** 2 / g * e
+        r = np.sqrt(r2)
+        vr = np.where(inside, vmax * s * r / np.where(inside, rm * rm - r2, 1.0)
+                      * np.sqrt(2.0 * e), 0.0)
+        rr = np.where(r > 0.0, r, 1.0)
+        u = 1.0 - vr * dy / rr
+        v = vr * dx / rr
+        return h, h * u, h * v
+
+    if moving:
+        xn = np.concatenate([0.05 * np.arange(0, 11), 0.5 + 0.02 * np.arange(1, 51),
+                             1.5 + 0.05 * np.arange(1, 51)])
+        yn = np.concatenate([0.05 * np.arange(0, 11), 0.5 + 0.02 * np.arange(1, 51),
+                             1.5 + 0.05 * np.arange(1, 11)])
+    else:
+        xn, yn = uniform_nodes(110, 0.0, 4.0), uniform_nodes(70, 0.0, 2.0)
+    if refine > 1:
+        fine = lambda a: np.concatenate([a[:-1, None] + (a[1:] - a[:-1])[:, None]
+                                         * (np.arange(refine) / refine)[None, :], ], axis=0).ravel()
+        xn = np.append(fine(xn), xn[-1])
+        yn = np.append(fine(yn), yn[-1])
+
+    def averages(cx):
+        out = [np.zeros((len(yn) - 1, len(xn) - 1)) for _ in range(3)]
+        w = _GL5_W[:, None] * _GL5_W[None, :]
+        for p in range(4):
+            for q in range(4):
+                xa = xn[:-1] + (xn[1:] - xn[:-1]) * (p / 4.0)
+                xb = xn[:-1] + (xn[1:] - xn[:-1]) * ((p + 1) / 4.0)
+                ya = yn[:-1] + (yn[1:] - yn[:-1]) * (q / 4.0)
+                yb = yn[:-1] + (yn[1:] - yn[:-1]) * ((q + 1) / 4.0)
+                px = 0.5 * (xa + xb)[:, None] + 0.5 * (xb - xa)[:, None] * _GL5_X[None, :]
+                py = 0.5 * (ya + yb)[:, None] + 0.5 * (yb - ya)[:, None] * _GL5_X[None, :]
+                for o, f in zip(out, fields(px[None, :, None, :], py[:, None, :, None], cx)):
+                    o += (f * w[None, None]).sum(axis=(2, 3)) * 0.25 / 16.0
+        return out
+
+    h, hu, hv = averages(1.0)
+    # exact water height at t_end on the final cells: moving mesh, the initial
+    # averages; static mesh, the vortex centred at 1 + t_end (periodic in x)
+    h_end = h.copy() if moving else averages(1.0 + (t_end % 4.0))[0]
+    return dict(xi=xn, yi=yn, h=h, hu=hu, hv=hv, b=np.zeros_like(h), h_end=h_end,
+                bc="periodic", t_end=t_end, Vx=1.0 if moving else 0.0, cfl=0.6)
+
+
 def parabolic_basin_2d(n: int = 100, amp=(0.03, 0.02), periods: float = 1.0):
     """Example 5.10 (long wave in a parabolic basin) on [-4000, 4000]^2: b =
     h0 (x^2 + y^2) / a^2, h = max(0, h0 (sqrt(1 - A^2) / (1 - A) - r^2 / a^2

@@ -132,7 +132,8 @@ def test_transposition_symmetry():
 def test_constant_state_preserved_under_mesh_motion():
     """A constant state over a flat bottom stays constant while both directions
     of the mesh move (the discrete GCL of eq. (3.15) with the area recurrence),
-    periodic and transmissive boundaries alike."""
+    periodic and transmissive boundaries alike, and with a uniform translation
+    of the nodes added (the nodes then sit on the translated maps)."""
     for bcy in (O.BC_PERIODIC, O.BC_TRANSMISSIVE):
         nx, ny = 16, 12
         xi, yi = W.uniform_nodes(nx, 0.0, 1.0), W.uniform_nodes(ny, 0.0, 1.0)
@@ -144,6 +145,19 @@ def test_constant_state_preserved_under_mesh_motion():
         assert np.abs(r["h"] - 2.0).max() < 1e-13
         assert np.abs(r["hu"] - 0.3).max() < 1e-13 and np.abs(r["hv"] + 0.2).max() < 1e-13
         assert np.abs(r["b"]).max() < 1e-15
+    # a uniform translation on top of the maps (Example 5.7's w = (1, 0)),
+    # periodic: the nodes move by the translation plus the maps, the state stays
+    nx, ny = 16, 12
+    xi, yi = W.uniform_nodes(nx, 0.0, 1.0), W.uniform_nodes(ny, 0.0, 1.0)
+    z = np.zeros((ny, nx))
+    P = _p2(cfl=0.5, Ax=0.03, kx=1.0, omx=40.0, Ay=0.02, ky=1.0, omy=80.0, Vx=1.0, Vy=-0.5)
+    r = O.run2(P, z + 2.0, z + 0.3, z - 0.2, z, xi, yi, xi, yi, max_steps=25)
+    assert r["status"] == 0 and r["steps"] == 25
+    xs = xi + 1.0 * r["t"] + 0.03 * np.sin(2 * np.pi * xi) * np.sin(40.0 * r["t"])
+    ys = yi - 0.5 * r["t"] + 0.02 * np.sin(2 * np.pi * yi) * np.sin(80.0 * r["t"])
+    assert np.abs(r["x"] - xs).max() < 1e-13 and np.abs(r["y"] - ys).max() < 1e-13
+    assert np.abs(r["h"] - 2.0).max() < 1e-13
+    assert np.abs(r["hu"] - 0.3).max() < 1e-13 and np.abs(r["hv"] + 0.2).max() < 1e-13
 
 
 def test_mass_and_bottom_are_conserved():
